@@ -1,0 +1,188 @@
+"""ctypes front end of the FP64 oracle in ``rom_oracle.c`` (test infrastructure).
+
+All matrices are numpy float64 arrays in column-major (Fortran) order:
+operators ``Avs`` (Kv x Ks) and ``Asv`` (Ks x Kv), states ``V`` (Kv x M) and
+``S`` (Ks x M), one sample per column.  The functions copy what they must and
+never touch the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rom_oracle.c")
+_LIB = os.path.join(_HERE, "liborom.so")
+_lock = threading.Lock()
+_lib = None
+
+_d = C.c_double
+_i = C.c_int
+_i64 = C.c_int64
+_pd = C.POINTER(C.c_double)
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            lib = C.CDLL(_LIB)
+            lib.orc_ricker.restype = _d
+            lib.orc_ricker.argtypes = [_d, _d]
+            lib.orc_ricker_dmu.restype = _d
+            lib.orc_ricker_dmu.argtypes = [_d, _d]
+            lib.orc_step_rank1.restype = None
+            lib.orc_step_rank1.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i64, _d, _pd, _pd]
+            lib.orc_run_rank2.restype = _i
+            lib.orc_run_rank2.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i, _pd, _i64, _i64,
+                                          _pd, _pd, _pd, _pd, _pd]
+            lib.orc_energy.restype = None
+            lib.orc_energy.argtypes = [_i, _i, _pd, _d, _i, _pd, _pd, _pd]
+            lib.orc_adjoint.restype = _i
+            lib.orc_adjoint.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i, _pd, _i64, _pd,
+                                        _pd, _pd, _pd, _pd, _pd, _pd, _i64]
+            lib.orc_num_threads.restype = _i
+            lib.orc_num_threads.argtypes = []
+            lib.orc_round_bf16.restype = _d
+            lib.orc_round_bf16.argtypes = [_d]
+            lib.orc_quantize_e4m3.restype = _d
+            lib.orc_quantize_e4m3.argtypes = [_i64, _pd, _pd, _d]
+            _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    """Column-major float64 copy/view of ``a`` (Fortran order)."""
+    x = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and x.shape != tuple(shape):
+        x = x.reshape(shape, order="F")
+    return x
+
+
+def _p(x):
+    return None if x is None else x.ctypes.data_as(_pd)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def ricker(t, mu):
+    lib = _load()
+    return np.vectorize(lambda tt, mm: lib.orc_ricker(float(tt), float(mm)))(t, mu)
+
+
+def ricker_dmu(t, mu):
+    lib = _load()
+    return np.vectorize(lambda tt, mm: lib.orc_ricker_dmu(float(tt), float(mm)))(t, mu)
+
+
+def step_rank1(Avs, Asv, b, dt, n, mu, v, s):
+    """One rank-1 leapfrog step of one sample; returns new (v, s)."""
+    Avs = _f64(Avs); Asv = _f64(Asv)
+    kv, ks = Avs.shape
+    assert Asv.shape == (ks, kv)
+    b = _f64(b).reshape(kv)
+    v = np.array(v, dtype=np.float64).reshape(kv).copy()
+    s = np.array(s, dtype=np.float64).reshape(ks).copy()
+    _load().orc_step_rank1(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), int(n), float(mu),
+                           _p(v), _p(s))
+    return v, s
+
+
+def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=False):
+    """Integrate ``nsteps`` steps from step index ``n0``.
+
+    Returns a dict with V, S (Kv x M / Ks x M, Fortran order) and, when a probe
+    ``c`` is given, J (M, accumulated from zero) and optionally the trace y
+    (nsteps x M).
+    """
+    Avs = _f64(Avs); Asv = _f64(Asv)
+    kv, ks = Avs.shape
+    assert Asv.shape == (ks, kv)
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    M = mu.size
+    b = _f64(b).reshape(kv)
+    V = np.zeros((kv, M), order="F") if V is None else np.array(V, dtype=np.float64, order="F", copy=True)
+    S = np.zeros((ks, M), order="F") if S is None else np.array(S, dtype=np.float64, order="F", copy=True)
+    assert V.shape == (kv, M) and S.shape == (ks, M)
+    cc = None if c is None else np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(kv))
+    J = np.zeros(M) if cc is not None else None
+    y = np.zeros((int(nsteps), M)) if (cc is not None and trace) else None
+    rc = _load().orc_run_rank2(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), M, _p(mu), int(n0),
+                               int(nsteps), _p(V), _p(S), _p(cc), _p(J), _p(y))
+    if rc != 0:
+        raise MemoryError("oracle run failed")
+    out = {"V": V, "S": S}
+    if cc is not None:
+        out["J"] = J
+        if trace:
+            out["y"] = y
+    return out
+
+
+def energy(Avs, dt, V, S):
+    """Modified discrete energy |v|^2 + |s|^2 + dt v^T Avs s per column."""
+    Avs = _f64(Avs)
+    kv, ks = Avs.shape
+    V = _f64(V); S = _f64(S)
+    M = V.shape[1]
+    E = np.zeros(M)
+    _load().orc_energy(kv, ks, _p(Avs), float(dt), M, _p(V), _p(S), _p(E))
+    return E
+
+
+def adjoint(Avs, Asv, b, dt, mu, nsteps, c, V0=None, S0=None, stride=0):
+    """J and its partial gradients w.r.t. Avs, Asv and mu (discrete adjoint)."""
+    Avs = _f64(Avs); Asv = _f64(Asv)
+    kv, ks = Avs.shape
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    M = mu.size
+    b = _f64(b).reshape(kv)
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(kv))
+    V0 = None if V0 is None else _f64(V0, (kv, M))
+    S0 = None if S0 is None else _f64(S0, (ks, M))
+    J = np.zeros(M); dmu = np.zeros(M)
+    dAvs = np.zeros((kv, ks), order="F"); dAsv = np.zeros((ks, kv), order="F")
+    rc = _load().orc_adjoint(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), M, _p(mu), int(nsteps),
+                             _p(c), _p(V0), _p(S0), _p(J), _p(dAvs), _p(dAsv), _p(dmu), int(stride))
+    if rc != 0:
+        raise MemoryError("oracle adjoint failed")
+    return {"J": J, "dAvs": dAvs, "dAsv": dAsv, "dmu": dmu}
+
+
+def round_bf16(x):
+    """Elementwise x -> FP32 -> bfloat16 (RNE), as float64."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.float64)
+    return np.vectorize(lambda v: lib.orc_round_bf16(float(v)))(x).astype(np.float64)
+
+
+def quantize_e4m3(x, amax=0.0):
+    """Per-tensor scaled FP8 E4M3 quantisation; returns (dequantised, scale)."""
+    x = np.asarray(x, dtype=np.float64)
+    flat = np.ascontiguousarray(x.reshape(-1, order="F"))
+    out = np.zeros_like(flat)
+    scale = _load().orc_quantize_e4m3(flat.size, _p(flat), _p(out), float(amax))
+    return out.reshape(x.shape, order="F"), scale

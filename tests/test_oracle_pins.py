@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test fixes one part of the computation independently:
+  * Ricker wavelet: closed-form special points (peak, zeros, minima) and the
+    mu-derivative against finite differences;
+  * leapfrog form: the 1x1-block ("2x2 harmonic oscillator") discrete closed
+    form, and second-order convergence to the continuous solution;
+  * operators + forcing + time sampling together: the SVD-modal closed form
+    of any skew instance (independent 2x2 oscillators driven by a discrete
+    convolution), also with Kv != Ks;
+  * the discrete energy identity of the skew-coupled leapfrog;
+  * rank-1 == rank-2 column by column (bitwise), linearity, run splitting,
+    time reversibility, and brute force on tiny sizes against a separate
+    numpy loop, including non-skew operators;
+  * adjoint: central finite differences, checkpoint-stride invariance.
+The discrete form being pinned is the leapfrog of Sec. 3.1 (velocity first,
+then stress, eq. (3.3)) with forcing sampled at t_n = n dt.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+PI = math.pi
+
+
+# --------------------------------------------------------------------------
+# Ricker wavelet (Sec. 3.2 names it; unit-peak form with delay 1.5/mu)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mu", [0.5, 0.73, 1.0])
+def test_ricker_special_points(mu):
+    t0 = 1.5 / mu
+    assert oracle.ricker(t0, mu) == pytest.approx(1.0, abs=1e-15)
+    # zeros where (mu t - 1.5) = +-1/(sqrt(2) pi)
+    for sgn in (-1, 1):
+        tz = (1.5 + sgn / (math.sqrt(2.0) * PI)) / mu
+        assert abs(oracle.ricker(tz, mu)) < 1e-14
+    # minima -2 e^{-3/2} where (mu t - 1.5) = +-sqrt(1.5)/pi
+    for sgn in (-1, 1):
+        tm = (1.5 + sgn * math.sqrt(1.5) / PI) / mu
+        assert oracle.ricker(tm, mu) == pytest.approx(-2.0 * math.exp(-1.5), rel=1e-13)
+        h = 1e-5
+        slope = (oracle.ricker(tm + h, mu) - oracle.ricker(tm - h, mu)) / (2 * h)
+        assert abs(slope) < 1e-8
+    # even symmetry about the peak and decay far from it
+    for d in (0.1, 0.37, 1.2):
+        assert oracle.ricker(t0 + d, mu) == pytest.approx(oracle.ricker(t0 - d, mu), rel=1e-12, abs=1e-15)
+    assert abs(oracle.ricker(t0 + 8.0 / mu, mu)) < 1e-200
+
+
+@pytest.mark.parametrize("t", [0.0, 0.8, 1.9, 2.5, 3.3, 7.0])
+@pytest.mark.parametrize("mu", [0.55, 0.8, 0.97])
+def test_ricker_dmu_matches_fd(t, mu):
+    h = 1e-6
+    fd = (oracle.ricker(t, mu + h) - oracle.ricker(t, mu - h)) / (2 * h)
+    an = oracle.ricker_dmu(t, mu)
+    assert an == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Leapfrog form: 1x1 blocks (Avs = a, Asv = -a) = discrete harmonic oscillator
+# --------------------------------------------------------------------------
+
+def _osc_closed_form(a, dt, n, v0, s0):
+    """G^n x0 with G = [[1, a dt], [-a dt, 1 - a^2 dt^2]] (det G = 1) via
+    Cayley-Hamilton: G^n = (sin(n th) G - sin((n-1) th) I) / sin th,
+    th = 2 asin(a dt / 2)."""
+    th = 2.0 * math.asin(a * dt / 2.0)
+    G = np.array([[1.0, a * dt], [-a * dt, 1.0 - (a * dt) ** 2]])
+    Gn = (math.sin(n * th) * G - math.sin((n - 1) * th) * np.eye(2)) / math.sin(th)
+    return Gn @ np.array([v0, s0])
+
+
+@pytest.mark.parametrize("a,dt,n", [(1.0, 0.1, 2000), (2.3, 0.05, 777), (0.7, 0.5, 1500)])
+def test_oscillator_closed_form(a, dt, n):
+    Avs = np.array([[a]]); Asv = np.array([[-a]]); b = np.zeros(1)
+    out = oracle.run_rank2(Avs, Asv, b, dt, [0.7], n, V=[[1.0]], S=[[0.0]])
+    ref = _osc_closed_form(a, dt, n, 1.0, 0.0)
+    got = np.array([out["V"][0, 0], out["S"][0, 0]])
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_oscillator_second_order_convergence():
+    """Staggered reading: v^n ~ v(t_n - dt/2), s^n ~ s(t_n).  With exact
+    staggered start values the error at fixed T falls ~4x per halving of dt."""
+    a, T = 1.3, 5.0
+    errs = []
+    for k in range(4):
+        dt = 0.1 / 2 ** k
+        n = int(round(T / dt))
+        v0 = math.cos(-a * dt / 2.0)   # v = cos(a t), s = -sin(a t)
+        out = oracle.run_rank2([[a]], [[-a]], [0.0], dt, [0.7], n, V=[[v0]], S=[[0.0]])
+        ev = out["V"][0, 0] - math.cos(a * (n * dt - dt / 2.0))
+        es = out["S"][0, 0] + math.sin(a * n * dt)
+        errs.append(math.hypot(ev, es))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    for r in ratios:
+        assert 3.6 < r < 4.4, (errs, ratios)
+
+
+# --------------------------------------------------------------------------
+# SVD-modal closed form of any skew instance (Asv = -Avs^T), with forcing
+# --------------------------------------------------------------------------
+
+def _modal_solution(inst, nsteps, V0=None, S0=None):
+    """Exact discrete solution through the SVD Avs = U Sigma W^T.
+
+    alpha = U^T v, beta = W^T s decouple into 2x2 oscillators with step matrix
+    G_i = [[1, s dt], [-s dt, 1 - s^2 dt^2]] (s = sigma_i) and kick
+    [dt bt_i u_n, -s dt^2 bt_i u_n] (bt = U^T b); modes of alpha beyond the
+    rank only accumulate dt bt_i u_n, modes of beta beyond it stay constant.
+    x^N = G^N x^0 + sum_n G^(N-1-n) k^n with the closed-form powers
+    G^k = P_k G - P_{k-1} I, P_k = sin(k th)/sin(th), th = 2 asin(s dt/2).
+    The Ricker values come from the oracle's pinned wavelet."""
+    Avs, b, dt, mu = inst["Avs"], inst["b"], inst["dt"], inst["mu"]
+    kv, ks = Avs.shape
+    M = len(mu)
+    U, sig, Wt = np.linalg.svd(Avs)          # U kv x kv, Wt ks x ks
+    W = Wt.T
+    r = len(sig)
+    N = nsteps
+    tn = np.arange(N) * dt
+    u = np.stack([oracle.ricker(tn, m) for m in mu], axis=1)  # N x M
+    bt = U.T @ b                                              # kv
+    V0 = np.zeros((kv, M)) if V0 is None else np.asarray(V0)
+    S0 = np.zeros((ks, M)) if S0 is None else np.asarray(S0)
+    al0 = U.T @ V0
+    be0 = W.T @ S0
+    alpha = np.zeros((kv, M)); beta = np.zeros((ks, M))
+    k = np.arange(-1, N + 1)                                   # P_{-1} .. P_N
+    for i in range(r):
+        s = sig[i]
+        th = 2.0 * math.asin(s * dt / 2.0)
+        P = np.sin(k * th) / math.sin(th)                      # P[j] = P_{j-1}
+        Pk = lambda kk: P[kk + 1]
+        G = np.array([[1.0, s * dt], [-s * dt, 1.0 - (s * dt) ** 2]])
+        # homogeneous part
+        GN = Pk(N) * G - Pk(N - 1) * np.eye(2)
+        x = GN @ np.vstack([al0[i], be0[i]])
+        # forced part: sum_n G^(N-1-n) [dt bt u_n ; -s dt^2 bt u_n]
+        e = N - 1 - np.arange(N)
+        c1 = Pk(e)[:, None]            # coefficient of G
+        c0 = Pk(e - 1)[:, None]        # coefficient of I
+        k0 = dt * bt[i] * u            # N x M (first component)
+        k1 = -s * dt * dt * bt[i] * u  # N x M (second component)
+        xa = np.sum(c1 * (G[0, 0] * k0 + G[0, 1] * k1) - c0 * k0, axis=0)
+        xb = np.sum(c1 * (G[1, 0] * k0 + G[1, 1] * k1) - c0 * k1, axis=0)
+        alpha[i] = x[0] + xa
+        beta[i] = x[1] + xb
+    for i in range(r, kv):
+        alpha[i] = al0[i] + dt * bt[i] * u.sum(axis=0)
+    for i in range(r, ks):
+        beta[i] = be0[i]
+    return U @ alpha, W @ beta
+
+
+def _relcol(X, R):
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)))
+
+
+@pytest.mark.parametrize("kv,ks,M,N", [(64, 64, 8, 2000), (24, 17, 3, 900), (13, 29, 4, 1100), (5, 5, 2, 300)])
+def test_modal_closed_form(kv, ks, M, N):
+    inst = synth.make_instance(kv, ks, M, seed=3)
+    out = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
+    Vr, Sr = _modal_solution(inst, N)
+    assert _relcol(out["V"], Vr) < 1e-11
+    assert _relcol(out["S"], Sr) < 1e-11
+
+
+def test_modal_closed_form_nonzero_start():
+    inst = synth.make_instance(11, 11, 3, seed=9)
+    rng = np.random.default_rng(1)
+    V0 = rng.standard_normal((11, 3)); S0 = rng.standard_normal((11, 3))
+    out = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 400, V=V0, S=S0)
+    Vr, Sr = _modal_solution(inst, 400, V0, S0)
+    assert _relcol(out["V"], Vr) < 1e-11
+    assert _relcol(out["S"], Sr) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# Discrete energy of the skew-coupled leapfrog
+# --------------------------------------------------------------------------
+
+def test_energy_identity_per_step():
+    """E = |v|^2 + |s|^2 + dt v^T Avs s;  E^{n+1} - E^n = dt (b u_n)^T (v^n + v^{n+1})."""
+    inst = synth.make_instance(20, 14, 3, seed=5)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    V = np.zeros((20, 3), order="F"); S = np.zeros((14, 3), order="F")
+    E = oracle.energy(A, dt, V, S)
+    worst = 0.0
+    for n in range(60):
+        out = oracle.run_rank2(A, B, b, dt, mu, 1, V=V, S=S, n0=n)
+        En = oracle.energy(A, dt, out["V"], out["S"])
+        u = np.array([oracle.ricker(n * dt, m) for m in mu])
+        rhs = dt * np.einsum("i,im->m", b, V + out["V"]) * u
+        scale = max(1.0, float(np.max(np.abs(En))))
+        worst = max(worst, float(np.max(np.abs((En - E) - rhs))) / scale)
+        V, S, E = out["V"], out["S"], En
+    assert worst < 1e-13
+
+
+def test_energy_conserved_after_source():
+    inst = synth.make_instance(64, 64, 8, seed=0)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    first = oracle.run_rank2(A, B, b, dt, mu, 200)          # t = 200 dt >> 1.5/mu + decay
+    E1 = oracle.energy(A, dt, first["V"], first["S"])
+    second = oracle.run_rank2(A, B, b, dt, mu, 1800, V=first["V"], S=first["S"], n0=200)
+    E2 = oracle.energy(A, dt, second["V"], second["S"])
+    assert np.all(E1 > 0)
+    assert np.max(np.abs(E2 - E1) / E1) < 1e-12
+    # boundedness: E >= (1 - dt sigma_max / 2) |x|^2  => states bounded
+    x2 = np.sum(second["V"] ** 2, axis=0) + np.sum(second["S"] ** 2, axis=0)
+    smax = np.linalg.svd(A, compute_uv=False)[0]
+    assert np.all(E2 >= (1 - dt * smax / 2) * x2 * (1 - 1e-12))
+
+
+# --------------------------------------------------------------------------
+# Structural identities
+# --------------------------------------------------------------------------
+
+def test_rank1_equals_rank2_columns_bitwise():
+    inst = synth.make_instance(23, 31, 5, seed=2, skew=False)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    N = 150
+    out = oracle.run_rank2(A, B, b, dt, mu, N)
+    for m in range(5):
+        v = np.zeros(23); s = np.zeros(31)
+        for n in range(N):
+            v, s = oracle.step_rank1(A, B, b, dt, n, mu[m], v, s)
+        assert np.array_equal(v, out["V"][:, m])
+        assert np.array_equal(s, out["S"][:, m])
+
+
+def test_linearity_bitwise():
+    inst = synth.make_instance(16, 16, 3, seed=4)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    rng = np.random.default_rng(7)
+    V0 = rng.standard_normal((16, 3)); S0 = rng.standard_normal((16, 3))
+    o1 = oracle.run_rank2(A, B, b, dt, mu, 300, V=V0, S=S0)
+    o2 = oracle.run_rank2(A, B, 2 * b, dt, mu, 300, V=2 * V0, S=2 * S0)
+    assert np.array_equal(2 * o1["V"], o2["V"]) and np.array_equal(2 * o1["S"], o2["S"])
+
+
+def test_run_split_bitwise():
+    inst = synth.make_instance(12, 9, 4, seed=6)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    c = inst["c"]
+    whole = oracle.run_rank2(A, B, b, dt, mu, 500, c=c)
+    p1 = oracle.run_rank2(A, B, b, dt, mu, 173, c=c)
+    p2 = oracle.run_rank2(A, B, b, dt, mu, 327, V=p1["V"], S=p1["S"], n0=173, c=c)
+    assert np.array_equal(whole["V"], p2["V"]) and np.array_equal(whole["S"], p2["S"])
+    # J accumulates in step order; the split sum equals the whole one up to one rounding
+    assert np.allclose(p1["J"] + p2["J"], whole["J"], rtol=1e-14, atol=0)
+
+
+def test_mu_permutation_bitwise():
+    inst = synth.make_instance(10, 10, 6, seed=8)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    o = oracle.run_rank2(A, B, b, dt, mu, 200)
+    op = oracle.run_rank2(A, B, b, dt, mu[perm], 200)
+    assert np.array_equal(o["V"][:, perm], op["V"])
+
+
+def test_time_reversibility():
+    """Run forward, then undo each step exactly as the leapfrog allows
+    (s^n = s^{n+1} - dt Asv v^{n+1}; v^n = v^{n+1} - dt (Avs s^n + b u_n))."""
+    inst = synth.make_instance(18, 18, 2, seed=10)
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    rng = np.random.default_rng(3)
+    V0 = rng.standard_normal((18, 2)); S0 = rng.standard_normal((18, 2))
+    N = 400
+    out = oracle.run_rank2(A, B, b, dt, mu, N, V=V0, S=S0)
+    V, S = out["V"].copy(), out["S"].copy()
+    for n in range(N - 1, -1, -1):
+        u = np.array([oracle.ricker(n * dt, m) for m in mu])
+        S = S - dt * (B @ V)
+        V = V - dt * (A @ S + np.outer(b, u))
+    assert _relcol(V, V0) < 1e-12 and _relcol(S, S0) < 1e-12
+
+
+def _numpy_loop(inst, N, c=None):
+    A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
+    kv, ks = A.shape
+    M = len(mu)
+    V = np.zeros((kv, M)); S = np.zeros((ks, M)); J = np.zeros(M)
+    for n in range(N):
+        for m in range(M):
+            x = math.pi * (mu[m] * n * dt - 1.5)
+            u = (1 - 2 * x * x) * math.exp(-x * x)
+            V[:, m] = V[:, m] + dt * (A @ S[:, m] + b * u)
+        S = S + dt * (B @ V)
+        if c is not None:
+            J += dt * (c @ V) ** 2
+    return V, S, J
+
+
+@pytest.mark.parametrize("kv,ks,M", [(1, 1, 1), (2, 3, 2), (3, 2, 3), (5, 5, 1), (5, 2, 3), (1, 5, 2)])
+@pytest.mark.parametrize("skew", [True, False])
+def test_bruteforce_tiny(kv, ks, M, skew):
+    inst = synth.make_instance(kv, ks, M, seed=kv * 10 + ks, skew=skew)
+    c = inst["c"]
+    out = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 60, c=c)
+    V, S, J = _numpy_loop(inst, 60, c)
+    assert np.allclose(out["V"], V, rtol=1e-12, atol=1e-13)
+    assert np.allclose(out["S"], S, rtol=1e-12, atol=1e-13)
+    assert np.allclose(out["J"], J, rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Adjoint
+# --------------------------------------------------------------------------
+
+def _J(inst, N, Avs=None, Asv=None, mu=None):
+    o = oracle.run_rank2(inst["Avs"] if Avs is None else Avs, inst["Asv"] if Asv is None else Asv,
+                         inst["b"], inst["dt"], inst["mu"] if mu is None else mu, N, c=inst["c"])
+    return float(np.sum(o["J"])), o["J"]
+
+
+@pytest.mark.parametrize("kv,ks,M,N,skew", [(12, 12, 3, 200, True), (9, 14, 2, 150, False), (6, 4, 4, 90, True)])
+def test_adjoint_vs_central_fd(kv, ks, M, N, skew):
+    inst = synth.make_instance(kv, ks, M, seed=21, skew=skew)
+    adj = oracle.adjoint(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, inst["c"])
+    J0, Jm = _J(inst, N)
+    assert np.sum(adj["J"]) == pytest.approx(J0, rel=1e-14)
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    for which in ("Avs", "Asv"):
+        for _ in range(2):
+            D = rng.standard_normal(inst[which].shape)
+            D /= np.linalg.norm(D)
+            kw_p = {which: inst[which] + h * D}
+            kw_m = {which: inst[which] - h * D}
+            fd = (_J(inst, N, **kw_p)[0] - _J(inst, N, **kw_m)[0]) / (2 * h)
+            an = float(np.sum(adj["d" + which] * D))
+            assert an == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(J0))
+        # one single entry
+        i, j = 1 % inst[which].shape[0], 2 % inst[which].shape[1]
+        E = np.zeros(inst[which].shape); E[i, j] = 1.0
+        fd = (_J(inst, N, **{which: inst[which] + h * E})[0] - _J(inst, N, **{which: inst[which] - h * E})[0]) / (2 * h)
+        assert adj["d" + which][i, j] == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(J0))
+    # all mu at once: J_m depends on mu_m only, so 2 runs give every partial
+    Jp = _J(inst, N, mu=inst["mu"] + h)[1]
+    Jmn = _J(inst, N, mu=inst["mu"] - h)[1]
+    fd = (Jp - Jmn) / (2 * h)
+    assert np.allclose(adj["dmu"], fd, rtol=1e-6, atol=1e-9 * abs(J0))
+
+
+def test_adjoint_checkpoint_stride_invariance():
+    inst = synth.make_instance(10, 10, 3, seed=12)
+    args = (inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 97, inst["c"])
+    ref = oracle.adjoint(*args, stride=1)
+    for stride in (0, 7, 10, 96, 97, 500):
+        got = oracle.adjoint(*args, stride=stride)
+        for k in ("J", "dAvs", "dAsv", "dmu"):
+            assert np.array_equal(ref[k], got[k]), (stride, k)
+
+
+def test_adjoint_nonzero_start_fd():
+    inst = synth.make_instance(7, 7, 2, seed=30)
+    rng = np.random.default_rng(2)
+    V0 = rng.standard_normal((7, 2)); S0 = rng.standard_normal((7, 2))
+    adj = oracle.adjoint(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 80, inst["c"], V0, S0)
+    h = 1e-6
+    D = rng.standard_normal((7, 7)); D /= np.linalg.norm(D)
+
+    def J(A):
+        return float(np.sum(oracle.run_rank2(A, inst["Asv"], inst["b"], inst["dt"], inst["mu"], 80,
+                                             V=V0, S=S0, c=inst["c"])["J"]))
+    fd = (J(inst["Avs"] + h * D) - J(inst["Avs"] - h * D)) / (2 * h)
+    assert float(np.sum(adj["dAvs"] * D)) == pytest.approx(fd, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Operator roundings for the low-precision runs vs torch's CPU casts
+# --------------------------------------------------------------------------
+
+def test_round_bf16_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.uniform(-30, 30, 4000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.005859375, 3.0e-39, -7.1e-41]])
+    ours = oracle.round_bf16(x)
+    ref = torch.from_numpy(x).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_quantize_e4m3_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((37, 41)) / 7.0
+    x[3, 4] = 0.0
+    deq, scale = oracle.quantize_e4m3(x)
+    x32 = torch.from_numpy(x).to(torch.float32)
+    sc = (x32.abs().max() / 448.0)
+    assert float(sc) == scale
+    q = torch.clamp(x32 / sc, -448.0, 448.0).to(torch.float8_e4m3fn).to(torch.float64)
+    ref = (q * float(sc)).numpy()
+    assert np.array_equal(deq, ref)
+    # ties-to-even and subnormals on crafted values (scale 1 via amax = 448)
+    y = np.array([448.0, 460.0, 500.0, -1e9, 1.0625, 1.1875, 0.0029296875, 0.001953125, 0.0009765625, 0.00146484375])
+    deq2, s2 = oracle.quantize_e4m3(y, amax=448.0)
+    assert s2 == 1.0
+    ref2 = torch.clamp(torch.from_numpy(y).to(torch.float32), -448, 448).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(deq2, ref2)
