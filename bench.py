@@ -1,0 +1,165 @@
+"""Benchmark: rank-2 vs rank-1 Galerkin ROM stepping on one MI355X.
+
+Workload (one bench "step"): integrate M = 256 forcing samples of a synthetic
+staggered LTI ROM with Kv = Ks = 256 (random N(0, 1/K) operators, skew coupled,
+Ricker sources with mu ~ U[0.5, 1]) over 10^4 leapfrog steps in FP32, i.e.
+one full rank-2 run.  Inputs are resident on the GPU before timing starts.
+
+Prints ONE JSON line: sample-steps/s of the rank-2 path (whole job), the
+rank-1 path's rate on the same GPU, the roofline of the rank-2 kernel, the
+error against the FP64 oracle on sampled columns, and the oracle's own rate
+on the host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+KV = KS = 256
+M = 256
+NSTEPS = 10000
+SEED = 0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def _err_cols(Xg, Xr):
+    return float(np.max(np.linalg.norm(Xg - Xr, axis=0) / np.linalg.norm(Xr, axis=0)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(samples would shard across GPUs with no communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2009_11742_amd import Rom
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    inst = synth.round_to(synth.make_instance(KV, KS, M, seed=SEED), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device=dev)
+    J = torch.zeros(M, dtype=torch.float64, device=dev)
+    V, S = rom.zeros(M, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        V.zero_(); S.zero_(); J.zero_()
+        rom.run_rank2(mu, V, S, NSTEPS, c=c, J=J, stream=stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    # kernel-only timing: events around each run on the launching stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        V.zero_(); S.zero_(); J.zero_()
+        ev[k][0].record(stream)
+        rom.run_rank2(mu, V, S, NSTEPS, c=c, J=J, stream=stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    value = M * NSTEPS * args.steps / wall
+    kavg_s = float(np.mean(kern_ms)) * 1e-3
+    flops_per_launch = 4.0 * KV * KS * M * NSTEPS
+    achieved = flops_per_launch / kavg_s / 1e12
+
+    Vg = V.cpu().numpy().astype(np.float64).T
+    Sg = S.cpu().numpy().astype(np.float64).T
+    Jg = J.cpu().numpy()
+
+    # ---- rank-1 path on the same GPU: one sample per stream, 2 launches per step
+    rank1 = None
+    if not args.no_rank1:
+        r1_steps = 500
+        best = None
+        for nstreams in (1, 8):
+            streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+            vs = [torch.zeros(KV, dtype=torch.float32, device=dev) for _ in range(nstreams)]
+            ss = [torch.zeros(KS, dtype=torch.float32, device=dev) for _ in range(nstreams)]
+            rom.run_rank1(vs[0], ss[0], float(inst["mu"][0]), 20, stream=streams[0])  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i in range(nstreams):
+                rom.run_rank1(vs[i], ss[i], float(inst["mu"][i]), r1_steps, stream=streams[i])
+            torch.cuda.synchronize()
+            dt1 = time.perf_counter() - t1
+            rate = nstreams * r1_steps / dt1
+            if best is None or rate > best[0]:
+                best = (rate, nstreams)
+        rank1 = {"value": best[0], "unit": "sample-steps/s", "streams": best[1],
+                 "sample": "%d samples x %d steps, %d launches per step" % (best[1], r1_steps, 2)}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded column sample
+    cpu = None
+    errs = None
+    if not args.no_cpu:
+        import oracle
+        nthr = oracle.num_threads()
+        ncol = max(16, nthr)
+        cols = np.linspace(0, M - 1, ncol).round().astype(int)
+        t2 = time.perf_counter()
+        ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][cols], NSTEPS,
+                               c=inst["c"])
+        tcpu = time.perf_counter() - t2
+        cpu = {"value": len(cols) * NSTEPS / tcpu, "unit": "sample-steps/s", "cores": nthr, "kind": "oracle",
+               "sample": "%d of %d columns x %d steps (K=%d, FP64 plain loops), %.1f s" % (len(cols), M, NSTEPS, KV, tcpu)}
+        errs = {"max_rel_state_err": max(_err_cols(Vg[:, cols], ref["V"]), _err_cols(Sg[:, cols], ref["S"])),
+                "max_rel_qoi_err": float(np.max(np.abs(Jg[cols] - ref["J"]) / ref["J"])),
+                "cols_checked": int(len(cols))}
+
+    out = {
+        "metric": "sample-steps/s & MFMA util: rank-2 vs rank-1 on 1 MI355X at stated rel. error",
+        "value": value,
+        "unit": "sample-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rank-2 FP32 leapfrog, Kv=Ks=256, M=256 samples, 10000 steps per run",
+                   "kv": KV, "ks": KS, "M": M, "nsteps": NSTEPS, "seed": SEED},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "rank2_f32_mfma_kernel", "kernel_ms": float(np.mean(kern_ms)),
+                     "flops_per_launch": flops_per_launch},
+        "cpu_baseline": cpu,
+        "rank1": rank1,
+        "rank2_over_rank1": (value / rank1["value"]) if rank1 else None,
+        "accuracy": errs,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * rom.h - C ABI of the MI355X (gfx950) rank-2 Galerkin ROM library.
+ *
+ * The library integrates M forcing samples of one Galerkin-projected,
+ * staggered (velocity/stress) linear time-invariant system together.  The
+ * reduced states of all samples are stacked as matrices (one sample per
+ * column), so every leapfrog half-step is one dense operator x state-matrix
+ * product plus a per-sample forcing update (the "rank-2" form of the paper,
+ * Sec. 2.4 eq. (2.5), written for the two-field shear-wave system of
+ * Sec. 3.1 eq. (3.3)).  The "rank-1" form (Sec. 2.2 eq. (2.3)) advances one
+ * sample with two matrix-vector products per step.
+ *
+ * Problem (eq. (3.3); forcing-only parameters batched as in Sec. 2):
+ *
+ *   dV/dt = Avs S + b u(t; mu_m)        V: Kv x M (velocity coordinates)
+ *   dS/dt = Asv V                       S: Ks x M (stress coordinates)
+ *
+ *   Avs  (Kv x Ks)  reduced velocity operator  (Phi_v^T A_v Phi_s)
+ *   Asv  (Ks x Kv)  reduced stress operator    (Phi_s^T A_s Phi_v)
+ *   b    (Kv)       reduced point source (sparse forcing, Sec. 2.2)
+ *   u    Ricker wavelet (Sec. 3.2), per-sample centre frequency mu_m:
+ *        u(t; mu) = (1 - 2a) exp(-a),  a = pi^2 (mu t - 1.5)^2
+ *
+ * Time integration: leapfrog, velocity first then stress (Sec. 3.1, the
+ * paragraph after eq. (3.3)); the discrete form is
+ *
+ *   for n = n0 .. n0 + nsteps - 1,  t_n = n dt:
+ *     V <- V + dt (Avs S + b u(t_n; mu)^T)
+ *     S <- S + dt (Asv V)                 (uses the updated V)
+ *
+ * and, with a probe row c (a receiver, i.e. one row of Phi_v, Sec. 4.5):
+ *     y_m = c^T V[:, m],   J_m += dt y_m^2
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a rom_status.  On ROM_E_ARG nothing was enqueued
+ *    and no output was written.  rom_last_error() returns a thread-local
+ *    text for the last non-OK status of the calling thread.
+ *  - Matrices are column-major: element (i, j) of an R x C matrix is at
+ *    [i + j*R].  In particular a state matrix stores sample m contiguously
+ *    at [m*K, (m+1)*K) (as the paper's BLAS layout, Sec. 4.2).
+ *  - "dev" pointers are HIP device pointers owned by the caller; "host"
+ *    pointers are ordinary host memory.  The library never frees caller
+ *    memory.  Device buffers of state type hold `double` for ROM_F64 and
+ *    `float` for ROM_F32 states.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *    enqueue work on it; results are ready when the stream is synchronised.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef ROM_H
+#define ROM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROM_OK = 0,
+    ROM_E_ARG = 1,          /* invalid argument (nothing enqueued)            */
+    ROM_E_NOMEM = 2,        /* device or host allocation failed               */
+    ROM_E_DEVICE = 3,       /* HIP runtime error (launch, copy, fault)         */
+    ROM_E_UNSTABLE = 4,     /* skew pair with dt * sigma_max(Avs) >= 2         */
+    ROM_E_UNSUPPORTED = 5,  /* valid but unsupported combination               */
+    ROM_E_NONFINITE = 6,    /* non-finite input values                         */
+    ROM_E_TIMEOUT = 7       /* an in-kernel wait exceeded its time limit       */
+} rom_status;
+
+typedef enum {
+    ROM_F64 = 0,
+    ROM_F32 = 1,
+    ROM_BF16 = 2,           /* operators only                                  */
+    ROM_F8E4M3 = 3          /* operators only: OCP e4m3fn, per-tensor scale    */
+} rom_dtype;
+
+/* rom_config.flags */
+enum {
+    ROM_SKEW_CHECK = 1u     /* if Asv == -Avs^T exactly, require
+                               dt * sigma_max(Avs) < 2 (positivity of the
+                               leapfrog's discrete energy); ROM_E_UNSTABLE
+                               otherwise.  Non-skew pairs are not checked.   */
+};
+
+typedef struct {
+    int32_t kv;             /* velocity reduced size Kv >= 1                   */
+    int32_t ks;             /* stress reduced size Ks >= 1                     */
+    double dt;              /* time step > 0 (the value used, as given)        */
+    rom_dtype op_type;      /* operator precision in the products             */
+    rom_dtype state_type;   /* ROM_F64 or ROM_F32: state and I/O precision    */
+    uint32_t flags;         /* ROM_SKEW_CHECK | ...                            */
+} rom_config;
+
+typedef struct rom_ctx rom_ctx;
+
+/*
+ * Create a context on the current HIP device: validate the configuration,
+ * copy the operators and source to the device, and prepare them for the
+ * products (rounding to op_type, packing).  Operators are the time-
+ * independent reduced matrices computed offline (Sec. 2.2, Sec. 4.2).
+ *
+ *   cfg   host, configuration (copied)
+ *   Avs   host, Kv x Ks column-major FP64
+ *   Asv   host, Ks x Kv column-major FP64
+ *   b     host, Kv FP64
+ *   stream  stream for the uploads (the call synchronises it before return)
+ *   out   receives the context; set to NULL on failure
+ *
+ * The host arrays may be freed on return.  Errors: ROM_E_ARG (NULL pointer,
+ * Kv or Ks < 1, dt <= 0 or not finite, state_type not F64/F32, op_type
+ * narrower than... see rom_run_rank2), ROM_E_NONFINITE (NaN/Inf in inputs),
+ * ROM_E_UNSTABLE (see ROM_SKEW_CHECK), ROM_E_UNSUPPORTED, ROM_E_NOMEM,
+ * ROM_E_DEVICE.
+ */
+rom_status rom_create(const rom_config *cfg, const double *Avs, const double *Asv,
+                      const double *b, void *stream, rom_ctx **out);
+
+/* Release every device buffer owned by the context.  NULL is accepted. */
+rom_status rom_destroy(rom_ctx *ctx);
+
+/*
+ * Rank-1 step (Sec. 2.2 eq. (2.3); Sec. 2.3): advance ONE sample by one
+ * leapfrog step at t_n = n dt, as two matrix-vector products that re-read
+ * the operators from device memory.
+ *
+ *   v   dev, Kv values of state type (in/out)
+ *   s   dev, Ks values of state type (in/out)
+ *   n   step index (forcing sampled at n*dt)
+ *   mu  Ricker centre frequency of this sample
+ *
+ * Requires op_type == state_type.  Repeated calls reproduce column m of a
+ * rank-2 run to the accuracy of the state type.
+ */
+rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu,
+                          void *stream);
+
+/*
+ * Rank-1 run: nsteps calls of rom_step_rank1 for one sample, step indices
+ * n0 .. n0+nsteps-1, enqueued back to back on `stream` (2 launches per step).
+ * The baseline formulation the rank-2 run is compared with.
+ */
+rom_status rom_run_rank1(rom_ctx *ctx, void *v, void *s, double mu, int64_t n0, int64_t nsteps,
+                         void *stream);
+
+/*
+ * Rank-2 run (Sec. 2.4 eq. (2.5) in the staggered form (3.3)): advance all M
+ * samples by `nsteps` leapfrog steps, step indices n0 .. n0+nsteps-1.
+ *
+ *   M       number of samples (columns), >= 1
+ *   mu      dev, M FP64 centre frequencies
+ *   V       dev, Kv x M state type, ld = Kv (in/out)
+ *   S       dev, Ks x M state type, ld = Ks (in/out)
+ *   c       dev, Kv state type probe row, or NULL
+ *   J       dev, M FP64, accumulated (+= dt y_m^2 per step), or NULL
+ *   y       dev, nsteps x M FP64 probe trace (row k = step n0+k), or NULL
+ *
+ * J and y require c.  nsteps == 0 is a no-op.  With ROM_F32 states the
+ * kernel keeps a compensation term per entry during the run (two-term
+ * state) and rounds once when writing back, so splitting a run in two
+ * differs from the whole run by at most a rounding of the state.
+ * Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_DEVICE, ROM_E_TIMEOUT.
+ */
+rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
+                         int64_t nsteps, void *V, void *S, const void *c, double *J,
+                         double *y, void *stream);
+
+/*
+ * Discrete adjoint of a rank-2 run from step 0 for the probe QoI
+ *   J = sum_m sum_{n=0}^{N-1} dt (c^T V_m^(n+1))^2
+ * (differentiation of the leapfrog, the sensitivity use named in Sec. 5).
+ * Reverse sweep with the transposed operators; forward states are rebuilt
+ * from checkpoints every `ckpt_stride` steps (0 = ceil(sqrt(nsteps))).
+ *
+ *   M, mu, c      as rom_run_rank2 (c required)
+ *   nsteps        N >= 1
+ *   V0, S0        dev initial states (state type), NULL = zero
+ *   J             dev, M FP64 (set, not accumulated)
+ *   dAvs          dev, Kv x Ks state type: dJ/dAvs with Asv fixed (set)
+ *   dAsv          dev, Ks x Kv state type: dJ/dAsv with Avs fixed (set)
+ *   dmu           dev, M FP64: dJ/dmu_m (set)
+ * Any of dAvs, dAsv, dmu may be NULL.  dt is held fixed.
+ */
+rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps,
+                       const void *c, const void *V0, const void *S0, double *J,
+                       void *dAvs, void *dAsv, double *dmu, int32_t ckpt_stride,
+                       void *stream);
+
+/*
+ * Grouped run: G independent ROM instances (each its own context, sizes and
+ * samples) advanced `nsteps` steps from step 0 in ONE persistent launch
+ * (batched products, the rank-3 direction of Sec. 5).  All contexts must
+ * have F32 states and F32 operators.  Per instance i: M[i] samples, mu[i]
+ * dev FP64, V[i] / S[i] dev states as in rom_run_rank2.
+ */
+rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M,
+                           const double *const *mu, int64_t nsteps, void *const *V,
+                           void *const *S, void *stream);
+
+/* Thread-local text describing the last non-OK status of this thread. */
+const char *rom_last_error(void);
+
+/* Library version string. */
+const char *rom_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROM_H */

@@ -1,0 +1,86 @@
+"""ctypes loader for ``librom.so`` (the HIP library).  Argument marshalling only.
+
+The library is built in-tree by :mod:`paper_2009_11742_amd.build`.  Loading
+fails loudly when it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librom.so")
+
+ROM_OK, ROM_E_ARG, ROM_E_NOMEM, ROM_E_DEVICE, ROM_E_UNSTABLE, ROM_E_UNSUPPORTED, \
+    ROM_E_NONFINITE, ROM_E_TIMEOUT = range(8)
+STATUS_NAMES = ["ROM_OK", "ROM_E_ARG", "ROM_E_NOMEM", "ROM_E_DEVICE", "ROM_E_UNSTABLE",
+                "ROM_E_UNSUPPORTED", "ROM_E_NONFINITE", "ROM_E_TIMEOUT"]
+ROM_F64, ROM_F32, ROM_BF16, ROM_F8E4M3 = range(4)
+ROM_SKEW_CHECK = 1
+
+# Every symbol include/rom.h declares.
+EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
+           "rom_adjoint", "rom_run_grouped", "rom_last_error", "rom_version"]
+
+
+class RomConfig(C.Structure):
+    _fields_ = [("kv", C.c_int32), ("ks", C.c_int32), ("dt", C.c_double),
+                ("op_type", C.c_int), ("state_type", C.c_int), ("flags", C.c_uint32)]
+
+
+class RomError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__("%s: %s" % (name, msg))
+
+
+_lock = threading.Lock()
+_lib = None
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_d = C.c_double
+_pd = C.POINTER(C.c_double)
+
+
+def load():
+    """Load librom.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librom.so is not built (run paper_2009_11742_amd.build.build() "
+                               "or __graft_entry__.build()); there is no fallback path")
+        lib = C.CDLL(LIB_PATH)
+        lib.rom_create.restype = C.c_int
+        lib.rom_create.argtypes = [C.POINTER(RomConfig), _pd, _pd, _pd, _vp, C.POINTER(_vp)]
+        lib.rom_destroy.restype = C.c_int
+        lib.rom_destroy.argtypes = [_vp]
+        lib.rom_step_rank1.restype = C.c_int
+        lib.rom_step_rank1.argtypes = [_vp, _vp, _vp, _i64, _d, _vp]
+        lib.rom_run_rank1.restype = C.c_int
+        lib.rom_run_rank1.argtypes = [_vp, _vp, _vp, _d, _i64, _i64, _vp]
+        lib.rom_run_rank2.restype = C.c_int
+        lib.rom_run_rank2.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+        lib.rom_adjoint.restype = C.c_int
+        lib.rom_adjoint.argtypes = [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _i32, _vp]
+        lib.rom_run_grouped.restype = C.c_int
+        lib.rom_run_grouped.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_i32), C.POINTER(_vp),
+                                        _i64, C.POINTER(_vp), C.POINTER(_vp), _vp]
+        lib.rom_last_error.restype = C.c_char_p
+        lib.rom_last_error.argtypes = []
+        lib.rom_version.restype = C.c_char_p
+        lib.rom_version.argtypes = []
+        _lib = lib
+        return lib
+
+
+def check(status: int):
+    if status != ROM_OK:
+        msg = load().rom_last_error().decode(errors="replace")
+        raise RomError(status, msg)

@@ -1,0 +1,158 @@
+// Rank-2 leapfrog stepper on the vector ALUs, any state type (used for FP64
+// states: on MI355X FP64 vector FMA runs at the FP64 matrix rate).
+//
+// Same decomposition as the FP32 MFMA kernel: a workgroup owns 4 sample
+// columns for the whole run, its states live in LDS, no cross-workgroup
+// communication.  Thread (wave w, lane) computes rows 64 t + lane for row
+// tiles t = w, w + 4, ... and all 4 columns, summing the reduction in
+// increasing k with fused multiply-adds.  When both operators fit in LDS next
+// to the states they are staged there once; otherwise they are read from L2.
+#include "k_common.h"
+#include "rom_internal.h"
+
+namespace rom {
+namespace {
+
+constexpr int NB = kColBlock;
+constexpr size_t kLdsBudget = 150 * 1024;
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c);
+template <>
+__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return fma(a, b, c); }
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in_lds) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int kv = a.kv, ks = a.ks, kvp = a.kvp, ksp = a.ksp;
+    T *V = reinterpret_cast<T *>(smem);                // [NB][kvp]
+    T *S = V + NB * kvp;                                // [NB][ksp]
+    double *ur = reinterpret_cast<double *>(S + NB * ksp);   // [NB] forcing of this step
+    T *opA = reinterpret_cast<T *>(ur + NB);            // Avs (kv x ks) if staged
+    T *opB = opA + (size_t)kv * ks;                     // Asv (ks x kv) if staged
+    const T *gA = static_cast<const T *>(a.avs);
+    const T *gB = static_cast<const T *>(a.asv);
+    const T *A = gA, *B = gB;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int col0 = blockIdx.x * NB;
+    const T *Vin = static_cast<const T *>(a.V);
+    const T *Sin = static_cast<const T *>(a.S);
+    const T *bv = static_cast<const T *>(a.b);
+    const T *cv = static_cast<const T *>(a.c);
+
+    for (int idx = tid; idx < NB * kvp; idx += 256) {
+        int j = idx / kvp, i = idx - j * kvp, m = col0 + j;
+        V[idx] = (m < a.M && i < kv) ? Vin[(size_t)m * kv + i] : T(0);
+    }
+    for (int idx = tid; idx < NB * ksp; idx += 256) {
+        int j = idx / ksp, i = idx - j * ksp, m = col0 + j;
+        S[idx] = (m < a.M && i < ks) ? Sin[(size_t)m * ks + i] : T(0);
+    }
+    if (ops_in_lds) {
+        for (int idx = tid; idx < kv * ks; idx += 256) {
+            opA[idx] = gA[idx];
+            opB[idx] = gB[idx];
+        }
+        A = opA;
+        B = opB;
+    }
+    double Jacc = 0.0;
+    const T dt = (T)a.dt;
+    __syncthreads();
+
+    for (int64_t k = 0; k < a.nsteps; ++k) {
+        const double t = (double)(a.n0 + k) * a.dt;
+        if (tid < NB) ur[tid] = (col0 + tid < a.M) ? dev::ricker(t, a.mu[col0 + tid]) : 0.0;
+        __syncthreads();
+        // ---- velocity half-step
+        for (int i = w * 64 + lane; i < kv; i += 256) {
+            T acc[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = T(0);
+            for (int q = 0; q < ks; ++q) {
+                T aq = A[i + (size_t)q * kv];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = fma_t<T>(aq, S[j * ksp + q], acc[j]);
+            }
+            const T bi = bv[i];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                T f = bi * (T)ur[j];
+                V[j * kvp + i] = V[j * kvp + i] + dt * (acc[j] + f);
+            }
+        }
+        __syncthreads();
+        if (cv != nullptr && tid < NB) {
+            double yv = 0.0;
+            for (int i = 0; i < kv; ++i) yv = fma((double)cv[i], (double)V[tid * kvp + i], yv);
+            Jacc += a.dt * (yv * yv);
+            if (a.y && col0 + tid < a.M) a.y[(size_t)k * a.M + col0 + tid] = yv;
+        }
+        // ---- stress half-step
+        for (int i = w * 64 + lane; i < ks; i += 256) {
+            T acc[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = T(0);
+            for (int q = 0; q < kv; ++q) {
+                T bq = B[i + (size_t)q * ks];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = fma_t<T>(bq, V[j * kvp + q], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) S[j * ksp + i] = S[j * ksp + i] + dt * acc[j];
+        }
+        __syncthreads();
+    }
+
+    T *Vout = static_cast<T *>(a.V);
+    T *Sout = static_cast<T *>(a.S);
+    for (int idx = tid; idx < NB * kvp; idx += 256) {
+        int j = idx / kvp, i = idx - j * kvp, m = col0 + j;
+        if (m < a.M && i < kv) Vout[(size_t)m * kv + i] = V[idx];
+    }
+    for (int idx = tid; idx < NB * ksp; idx += 256) {
+        int j = idx / ksp, i = idx - j * ksp, m = col0 + j;
+        if (m < a.M && i < ks) Sout[(size_t)m * ks + i] = S[idx];
+    }
+    if (cv != nullptr && a.J && tid < NB && col0 + tid < a.M) a.J[col0 + tid] += Jacc;
+}
+
+template <typename T>
+size_t valu_lds(int kv, int ks, int kvp, int ksp, bool ops) {
+    size_t base = sizeof(T) * (size_t)NB * (kvp + ksp) + sizeof(double) * NB;
+    base = (base + 15) / 16 * 16;
+    return ops ? base + 2 * sizeof(T) * (size_t)kv * ks : base;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_rank2_valu(const Rank2Args &a, hipStream_t st) {
+    const int blocks = (a.M + NB - 1) / NB;
+    bool ops = valu_lds<T>(a.kv, a.ks, a.kvp, a.ksp, true) <= kLdsBudget;
+    size_t lds = valu_lds<T>(a.kv, a.ks, a.kvp, a.ksp, ops);
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rank2_valu_kernel<T>, dim3(blocks), dim3(256), lds, st, a, ops ? 1 : 0);
+    return hipGetLastError();
+}
+
+template hipError_t launch_rank2_valu<double>(const Rank2Args &, hipStream_t);
+template hipError_t launch_rank2_valu<float>(const Rank2Args &, hipStream_t);
+
+size_t rank2_valu_lds_bytes(rom_dtype st, int kv, int ks, int kvp, int ksp) {
+    return st == ROM_F64 ? valu_lds<double>(kv, ks, kvp, ksp, false)
+                         : valu_lds<float>(kv, ks, kvp, ksp, false);
+}
+
+hipError_t rank2_valu_configure() {
+    hipError_t e = hipFuncSetAttribute((const void *)rank2_valu_kernel<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)rank2_valu_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+}  // namespace rom

@@ -1,0 +1,256 @@
+// C-ABI of the rank-2 Galerkin ROM library: argument validation, context
+// lifetime, uploads and kernel dispatch.  Every entry point validates
+// synchronously before enqueueing anything, so ROM_E_ARG means nothing was
+// written.  No exception crosses the ABI.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rom_internal.h"
+
+namespace rom {
+size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp);
+size_t rank2_valu_lds_bytes(rom_dtype st, int kv, int ks, int kvp, int ksp);
+hipError_t rank2_f32_mfma_configure();
+hipError_t rank2_valu_configure();
+}  // namespace rom
+
+namespace {
+
+thread_local std::string g_err;
+
+rom_status fail(rom_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+rom_status hip_fail(hipError_t e, const char *where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return ROM_E_DEVICE;
+}
+
+bool all_finite(const double *x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(x[i])) return false;
+    return true;
+}
+
+size_t tsize(rom_dtype t) { return t == ROM_F64 ? 8 : 4; }
+
+// Largest singular value of A (rows x cols, column-major) by power iteration
+// on A^T A in FP64, run to a relative change below 1e-13.
+double sigma_max(const double *A, int rows, int cols) {
+    std::vector<double> x(cols, 1.0), y(rows), z(cols);
+    double nrm = sqrt((double)cols);
+    for (double &v : x) v /= nrm;
+    double lam = 0.0;
+    for (int it = 0; it < 5000; ++it) {
+        for (int i = 0; i < rows; ++i) y[i] = 0.0;
+        for (int j = 0; j < cols; ++j)
+            for (int i = 0; i < rows; ++i) y[i] += A[i + (size_t)j * rows] * x[j];
+        for (int j = 0; j < cols; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < rows; ++i) s += A[i + (size_t)j * rows] * y[i];
+            z[j] = s;
+        }
+        double n2 = 0.0;
+        for (double v : z) n2 += v * v;
+        n2 = sqrt(n2);
+        if (n2 == 0.0) return 0.0;
+        for (int j = 0; j < cols; ++j) x[j] = z[j] / n2;
+        double prev = lam;
+        lam = n2;  // Rayleigh estimate of sigma^2 (x normalised)
+        if (it > 10 && fabs(lam - prev) <= 1e-13 * lam) break;
+    }
+    return sqrt(lam);
+}
+
+void hfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+void free_ctx(rom_ctx *c) {
+    if (!c) return;
+    hfree(c->avs_cm);
+    hfree(c->asv_cm);
+    hfree(c->avs_pk);
+    hfree(c->asv_pk);
+    hfree(c->b);
+    hfree(c->avs_t);
+    hfree(c->asv_t);
+    hfree(c->status);
+    delete c;
+}
+
+bool g_configured = false;
+
+}  // namespace
+
+extern "C" {
+
+const char *rom_last_error(void) { return g_err.c_str(); }
+
+const char *rom_version(void) { return "rank2rom-mi355x 0.1 (gfx950)"; }
+
+rom_status rom_create(const rom_config *cfg, const double *Avs, const double *Asv,
+                      const double *b, void *stream, rom_ctx **out) {
+    if (out) *out = nullptr;
+    if (!cfg || !Avs || !Asv || !b || !out) return fail(ROM_E_ARG, "rom_create: NULL argument");
+    const int kv = cfg->kv, ks = cfg->ks;
+    if (kv < 1 || ks < 1) return fail(ROM_E_ARG, "rom_create: kv and ks must be >= 1");
+    if (kv > 65536 || ks > 65536) return fail(ROM_E_UNSUPPORTED, "rom_create: kv/ks above 65536");
+    if (!(cfg->dt > 0.0) || !isfinite(cfg->dt)) return fail(ROM_E_ARG, "rom_create: dt must be finite and > 0");
+    if (cfg->state_type != ROM_F64 && cfg->state_type != ROM_F32)
+        return fail(ROM_E_ARG, "rom_create: state_type must be ROM_F64 or ROM_F32");
+    if (cfg->op_type != ROM_F64 && cfg->op_type != ROM_F32 && cfg->op_type != ROM_BF16 &&
+        cfg->op_type != ROM_F8E4M3)
+        return fail(ROM_E_ARG, "rom_create: unknown op_type");
+    if (cfg->op_type != cfg->state_type)
+        return fail(ROM_E_UNSUPPORTED, "rom_create: op_type must equal state_type in this version");
+    if (cfg->flags & ~(uint32_t)ROM_SKEW_CHECK) return fail(ROM_E_ARG, "rom_create: unknown flag bits");
+    const size_t nA = (size_t)kv * ks;
+    if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
+        return fail(ROM_E_NONFINITE, "rom_create: non-finite value in Avs, Asv or b");
+
+    bool skew = true;
+    for (int i = 0; i < ks && skew; ++i)
+        for (int j = 0; j < kv; ++j)
+            if (Asv[i + (size_t)j * ks] != -Avs[j + (size_t)i * kv]) { skew = false; break; }
+    if ((cfg->flags & ROM_SKEW_CHECK) && skew) {
+        double smax = sigma_max(Avs, kv, ks);
+        if (cfg->dt * smax * (1.0 + 1e-9) >= 2.0)
+            return fail(ROM_E_UNSTABLE, "rom_create: dt * sigma_max(Avs) >= 2 for a skew pair "
+                                        "(leapfrog energy not positive)");
+    }
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rom_ctx *c = new (std::nothrow) rom_ctx();
+    if (!c) return fail(ROM_E_NOMEM, "rom_create: host allocation failed");
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: hipGetDevice"); }
+    if (!g_configured) {
+        e = rom::rank2_f32_mfma_configure();
+        if (e == hipSuccess) e = rom::rank2_valu_configure();
+        if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: kernel attributes"); }
+        g_configured = true;
+    }
+    c->kv = kv; c->ks = ks;
+    c->kvp = rom::round_up(kv, 64); c->ksp = rom::round_up(ks, 64);
+    c->dt = cfg->dt; c->op_type = cfg->op_type; c->state_type = cfg->state_type;
+    c->flags = cfg->flags; c->skew = skew;
+    const size_t ts = tsize(c->state_type);
+
+    double *stage = nullptr;
+    const size_t stage_n = 2 * nA + (size_t)c->kvp;
+    e = hipMalloc(&stage, stage_n * sizeof(double));
+    if (e != hipSuccess) { free_ctx(c); return fail(ROM_E_NOMEM, "rom_create: device allocation failed"); }
+    double *sA = stage, *sB = stage + nA, *sb = stage + 2 * nA;
+    std::vector<double> bpad(c->kvp, 0.0);
+    memcpy(bpad.data(), b, sizeof(double) * kv);
+#define CHK(call, what)                                                           \
+    do {                                                                          \
+        e = (call);                                                               \
+        if (e != hipSuccess) { hfree(stage); free_ctx(c);                      \
+            return e == hipErrorOutOfMemory ? fail(ROM_E_NOMEM, what) : hip_fail(e, what); } \
+    } while (0)
+    CHK(hipMemcpyAsync(sA, Avs, nA * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
+    CHK(hipMemcpyAsync(sB, Asv, nA * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
+    CHK(hipMemcpyAsync(sb, bpad.data(), c->kvp * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
+    CHK(hipMalloc(&c->avs_cm, nA * ts), "rom_create: device allocation");
+    CHK(hipMalloc(&c->asv_cm, nA * ts), "rom_create: device allocation");
+    CHK(hipMalloc(&c->b, (size_t)c->kvp * ts), "rom_create: device allocation");
+    CHK(hipMalloc(&c->status, sizeof(int) * 4), "rom_create: device allocation");
+    CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
+    CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), "rom_create: convert");
+    CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), "rom_create: convert");
+    CHK(rom::launch_convert(sb, c->b, c->kvp, c->state_type, st), "rom_create: convert");
+    if (c->state_type == ROM_F32) {
+        CHK(hipMalloc(&c->avs_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
+        CHK(hipMalloc(&c->asv_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
+        CHK(rom::launch_pack_f32(sA, kv, ks, c->kvp, c->ksp, c->avs_pk, st), "rom_create: pack");
+        CHK(rom::launch_pack_f32(sB, ks, kv, c->ksp, c->kvp, c->asv_pk, st), "rom_create: pack");
+    }
+    CHK(hipStreamSynchronize(st), "rom_create: synchronize");
+#undef CHK
+    hfree(stage);
+    *out = c;
+    return ROM_OK;
+}
+
+rom_status rom_destroy(rom_ctx *ctx) {
+    if (!ctx) return ROM_OK;
+    free_ctx(ctx);
+    return ROM_OK;
+}
+
+rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu, void *stream) {
+    if (!ctx || !v || !s) return fail(ROM_E_ARG, "rom_step_rank1: NULL argument");
+    if (n < 0) return fail(ROM_E_ARG, "rom_step_rank1: n must be >= 0");
+    if (!isfinite(mu)) return fail(ROM_E_NONFINITE, "rom_step_rank1: mu not finite");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = ctx->state_type == ROM_F64
+        ? rom::launch_rank1_step<double>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu, v, s, st)
+        : rom::launch_rank1_step<float>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu, v, s, st);
+    if (e != hipSuccess) return hip_fail(e, "rom_step_rank1: launch");
+    return ROM_OK;
+}
+
+rom_status rom_run_rank1(rom_ctx *ctx, void *v, void *s, double mu, int64_t n0, int64_t nsteps,
+                         void *stream) {
+    if (!ctx || !v || !s) return fail(ROM_E_ARG, "rom_run_rank1: NULL argument");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_run_rank1: n0 and nsteps must be >= 0");
+    if (!isfinite(mu)) return fail(ROM_E_NONFINITE, "rom_run_rank1: mu not finite");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        rom_status r = rom_step_rank1(ctx, v, s, n0 + k, mu, stream);
+        if (r != ROM_OK) return r;
+    }
+    return ROM_OK;
+}
+
+rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
+                         void *V, void *S, const void *c, double *J, double *y, void *stream) {
+    if (!ctx) return fail(ROM_E_ARG, "rom_run_rank2: NULL context");
+    if (M < 1) return fail(ROM_E_ARG, "rom_run_rank2: M must be >= 1");
+    if (!mu || !V || !S) return fail(ROM_E_ARG, "rom_run_rank2: NULL mu, V or S");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_run_rank2: n0 and nsteps must be >= 0");
+    if ((J || y) && !c) return fail(ROM_E_ARG, "rom_run_rank2: J and y require the probe c");
+    if (nsteps == 0) return ROM_OK;
+    rom::Rank2Args a;
+    a.b = ctx->b; a.c = c; a.mu = mu; a.V = V; a.S = S; a.J = J; a.y = y;
+    a.kv = ctx->kv; a.ks = ctx->ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M;
+    a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (ctx->state_type == ROM_F32) {
+        if (ctx->kvp + ctx->ksp > rom::kMaxPadSum)
+            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
+        a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
+        e = rom::launch_rank2_f32_mfma(a, st);
+    } else {
+        if (rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) > 150 * 1024)
+            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: FP64 states above the LDS-resident limit");
+        a.avs = ctx->avs_cm; a.asv = ctx->asv_cm;
+        e = rom::launch_rank2_valu<double>(a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: launch");
+    return ROM_OK;
+}
+
+rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps, const void *c,
+                       const void *V0, const void *S0, double *J, void *dAvs, void *dAsv,
+                       double *dmu, int32_t ckpt_stride, void *stream) {
+    (void)ctx; (void)M; (void)mu; (void)nsteps; (void)c; (void)V0; (void)S0; (void)J;
+    (void)dAvs; (void)dAsv; (void)dmu; (void)ckpt_stride; (void)stream;
+    return fail(ROM_E_UNSUPPORTED, "rom_adjoint: not available in this version");
+}
+
+rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
+                           int64_t nsteps, void *const *V, void *const *S, void *stream) {
+    (void)ctx; (void)G; (void)M; (void)mu; (void)nsteps; (void)V; (void)S; (void)stream;
+    return fail(ROM_E_UNSUPPORTED, "rom_run_grouped: not available in this version");
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""Python front end of the HIP library (argument marshalling only).
+
+Every computation runs in the library's kernels; torch provides device memory
+and streams.  State layout: a state matrix of K rows and M samples is a torch
+tensor of shape (M, K), contiguous, i.e. K x M column-major with one sample per
+contiguous row of the tensor (the library's column-major convention).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RomConfig, check
+
+_DT = {"f64": (_lib.ROM_F64, torch.float64), "f32": (_lib.ROM_F32, torch.float32)}
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _host_f64(a, shape):
+    x = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    if x.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (shape, x.shape))
+    return x
+
+
+class Rom:
+    """One ROM instance on the current device.
+
+    Avs (Kv x Ks), Asv (Ks x Kv) and b (Kv) are host arrays (copied).  ``state``
+    is 'f64' or 'f32'; the operators are used in the same precision.
+    """
+
+    def __init__(self, Avs, Asv, b, dt, state="f32", skew_check=False, stream=None):
+        Avs = np.asarray(Avs)
+        kv, ks = Avs.shape
+        self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
+        code, self.torch_dtype = _DT[state]
+        A = _host_f64(Avs, (kv, ks))
+        B = _host_f64(Asv, (ks, kv))
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
+        cfg = RomConfig(kv, ks, float(dt), code, code, _lib.ROM_SKEW_CHECK if skew_check else 0)
+        ctx = C.c_void_p()
+        lib = _lib.load()
+        pd = C.POINTER(C.c_double)
+        check(lib.rom_create(C.byref(cfg), A.ctypes.data_as(pd), B.ctypes.data_as(pd),
+                             bb.ctypes.data_as(pd), _stream_handle(stream), C.byref(ctx)))
+        self._ctx = ctx
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _lib.load().rom_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state helpers -------------------------------------------------
+    def zeros(self, M, device="cuda"):
+        """Zero (V, S) of shapes (M, Kv), (M, Ks) in the state dtype."""
+        V = torch.zeros((M, self.kv), dtype=self.torch_dtype, device=device)
+        S = torch.zeros((M, self.ks), dtype=self.torch_dtype, device=device)
+        return V, S
+
+    def _chk_state(self, X, K, M, name):
+        if X.dtype != self.torch_dtype or not X.is_cuda or not X.is_contiguous() or tuple(X.shape) != (M, K):
+            raise ValueError("%s must be a contiguous CUDA tensor of shape (%d, %d) and dtype %s"
+                             % (name, M, K, self.torch_dtype))
+
+    # ---- entry points --------------------------------------------------
+    def step_rank1(self, v, s, n, mu, stream=None):
+        """One rank-1 step of one sample (v: (Kv,), s: (Ks,) device tensors)."""
+        self._chk_state(v.view(1, -1), self.kv, 1, "v")
+        self._chk_state(s.view(1, -1), self.ks, 1, "s")
+        check(_lib.load().rom_step_rank1(self._ctx, _ptr(v), _ptr(s), int(n), float(mu),
+                                         _stream_handle(stream)))
+
+    def run_rank1(self, v, s, mu, nsteps, n0=0, stream=None):
+        self._chk_state(v.view(1, -1), self.kv, 1, "v")
+        self._chk_state(s.view(1, -1), self.ks, 1, "s")
+        check(_lib.load().rom_run_rank1(self._ctx, _ptr(v), _ptr(s), float(mu), int(n0), int(nsteps),
+                                        _stream_handle(stream)))
+
+    def run_rank2(self, mu, V, S, nsteps, n0=0, c=None, J=None, y=None, stream=None):
+        """Advance all samples ``nsteps`` steps in place.
+
+        mu: (M,) float64 CUDA tensor; V: (M, Kv), S: (M, Ks) state tensors;
+        c: (Kv,) state-dtype probe or None; J: (M,) float64 (accumulated);
+        y: (nsteps, M) float64 probe trace.
+        """
+        M = int(mu.numel())
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        if c is not None:
+            self._chk_state(c.view(1, -1), self.kv, 1, "c")
+        if J is not None and (J.dtype != torch.float64 or J.numel() != M or not J.is_contiguous()):
+            raise ValueError("J must be a contiguous float64 tensor of M entries")
+        if y is not None and (y.dtype != torch.float64 or tuple(y.shape) != (int(nsteps), M) or not y.is_contiguous()):
+            raise ValueError("y must be a contiguous float64 tensor of shape (nsteps, M)")
+        check(_lib.load().rom_run_rank2(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
+                                        _ptr(c), _ptr(J), _ptr(y), _stream_handle(stream)))

@@ -1,0 +1,201 @@
+"""GPU parity of the rank-2 and rank-1 paths against the FP64 oracle.
+
+Error metric (following the relative l2 error of Sec. 4.4 eq. (4.3), taken per
+sample): max over samples m and fields X in {V, S} of
+||X_gpu[:, m] - X_ref[:, m]|| / ||X_ref[:, m]||.  Bars: 1e-12 for FP64
+states, 1e-5 for FP32 states.  Inputs are rounded to the run precision before
+the oracle sees them, so both sides integrate the same numbers.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _rom(inst, state):
+    from paper_2009_11742_amd import Rom
+    return Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state)
+
+
+def _relcol(X, R):
+    nr = np.linalg.norm(R, axis=0)
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.where(nr > 0, nr, 1.0)))
+
+
+def _gpu_run(inst, state, nsteps, cols=None, probe=False, trace=False, n0=0, V0=None, S0=None):
+    rom = _rom(inst, state)
+    mu_np = inst["mu"] if cols is None else inst["mu"][cols]
+    M = len(mu_np)
+    dt_t = rom.torch_dtype
+    mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
+    if V0 is None:
+        V, S = rom.zeros(M)
+    else:
+        V = torch.tensor(np.ascontiguousarray(V0.T), dtype=dt_t, device="cuda")
+        S = torch.tensor(np.ascontiguousarray(S0.T), dtype=dt_t, device="cuda")
+    c = J = y = None
+    if probe:
+        c = torch.tensor(inst["c"], dtype=dt_t, device="cuda")
+        J = torch.zeros(M, dtype=torch.float64, device="cuda")
+        if trace:
+            y = torch.zeros((nsteps, M), dtype=torch.float64, device="cuda")
+    rom.run_rank2(mu, V, S, nsteps, n0=n0, c=c, J=J, y=y)
+    torch.cuda.synchronize()
+    out = {"V": V.cpu().numpy().astype(np.float64).T, "S": S.cpu().numpy().astype(np.float64).T}
+    if probe:
+        out["J"] = J.cpu().numpy()
+        if trace:
+            out["y"] = y.cpu().numpy()
+    rom.close()
+    return out
+
+
+def _ref(inst, nsteps, cols=None, probe=False, trace=False, n0=0, V0=None, S0=None):
+    mu = inst["mu"] if cols is None else inst["mu"][cols]
+    return oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], mu, nsteps, V=V0, S=S0,
+                            n0=n0, c=inst["c"] if probe else None, trace=trace)
+
+
+# ---------------------------------------------------------------------------
+# FP64: the plain-method workload (K = 64, M in {1, 8}, 2000 steps)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M", [1, 8])
+def test_fp64_plain_workload(M):
+    inst = synth.round_to(synth.make_instance(64, 64, M, seed=0), "f64")
+    g = _gpu_run(inst, "f64", 2000, probe=True, trace=True)
+    r = _ref(inst, 2000, probe=True, trace=True)
+    assert _relcol(g["V"], r["V"]) <= TOL["f64"]
+    assert _relcol(g["S"], r["S"]) <= TOL["f64"]
+    assert np.max(np.abs(g["J"] - r["J"]) / np.abs(r["J"])) <= TOL["f64"]
+    assert np.max(np.abs(g["y"] - r["y"])) <= TOL["f64"] * np.max(np.abs(r["y"]))
+
+
+@pytest.mark.parametrize("kv,ks,M,skew", [(70, 45, 5, False), (1, 1, 1, True), (130, 129, 9, True), (3, 200, 2, False)])
+def test_fp64_ragged(kv, ks, M, skew):
+    inst = synth.make_instance(kv, ks, M, seed=kv + ks, skew=skew)
+    g = _gpu_run(inst, "f64", 300, probe=True)
+    r = _ref(inst, 300, probe=True)
+    assert _relcol(g["V"], r["V"]) <= TOL["f64"]
+    assert _relcol(g["S"], r["S"]) <= TOL["f64"]
+    assert np.allclose(g["J"], r["J"], rtol=TOL["f64"], atol=0)
+
+
+def test_fp64_rank1_matches_oracle():
+    from paper_2009_11742_amd import Rom
+    inst = synth.make_instance(64, 64, 2, seed=0)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64")
+    for m in range(2):
+        v = torch.zeros(64, dtype=torch.float64, device="cuda")
+        s = torch.zeros(64, dtype=torch.float64, device="cuda")
+        rom.run_rank1(v, s, inst["mu"][m], 2000)
+        torch.cuda.synchronize()
+        r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][m:m + 1], 2000)
+        assert _relcol(v.cpu().numpy()[:, None], r["V"]) <= TOL["f64"]
+        assert _relcol(s.cpu().numpy()[:, None], r["S"]) <= TOL["f64"]
+
+
+def test_fp64_nonzero_start_and_offset():
+    inst = synth.make_instance(40, 33, 6, seed=4, skew=False)
+    rng = np.random.default_rng(0)
+    V0 = rng.standard_normal((40, 6)); S0 = rng.standard_normal((33, 6))
+    g = _gpu_run(inst, "f64", 150, n0=17, V0=V0, S0=S0, probe=True)
+    r = _ref(inst, 150, n0=17, V0=V0, S0=S0, probe=True)
+    assert _relcol(g["V"], r["V"]) <= TOL["f64"] and _relcol(g["S"], r["S"]) <= TOL["f64"]
+
+
+def test_fp64_run_split_bitwise():
+    inst = synth.make_instance(48, 48, 5, seed=2)
+    whole = _gpu_run(inst, "f64", 400)
+    p1 = _gpu_run(inst, "f64", 150)
+    p2 = _gpu_run(inst, "f64", 250, n0=150, V0=p1["V"], S0=p1["S"])
+    assert np.array_equal(whole["V"], p2["V"]) and np.array_equal(whole["S"], p2["S"])
+
+
+# ---------------------------------------------------------------------------
+# FP32: the rank-2 workload (K = 256, M = 256, 10^4 steps) at full size,
+# checked on sampled columns the oracle computes one by one
+# ---------------------------------------------------------------------------
+
+def test_fp32_rank2_full_size_sampled_columns():
+    inst = synth.round_to(synth.make_instance(256, 256, 256, seed=0), "f32")
+    g = _gpu_run(inst, "f32", 10000, probe=True)
+    cols = np.array([0, 1, 2, 3, 77, 128, 201, 255])
+    r = _ref(inst, 10000, cols=cols, probe=True)
+    err_v = _relcol(g["V"][:, cols], r["V"])
+    err_s = _relcol(g["S"][:, cols], r["S"])
+    print("fp32 K=256 M=256 N=10000 sampled cols: errV=%.3e errS=%.3e" % (err_v, err_s))
+    assert err_v <= TOL["f32"] and err_s <= TOL["f32"]
+    assert np.max(np.abs(g["J"][cols] - r["J"]) / r["J"]) <= TOL["f32"]
+    assert np.all(np.isfinite(g["V"])) and np.all(np.isfinite(g["S"]))
+
+
+@pytest.mark.parametrize("kv,ks,M,skew,N", [(100, 130, 7, False, 1500), (64, 64, 4, True, 3000),
+                                            (200, 77, 13, True, 2000), (1, 2, 3, False, 500)])
+def test_fp32_ragged(kv, ks, M, skew, N):
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=7 * kv + ks, skew=skew), "f32")
+    g = _gpu_run(inst, "f32", N, probe=True, trace=True)
+    r = _ref(inst, N, probe=True, trace=True)
+    assert _relcol(g["V"], r["V"]) <= TOL["f32"]
+    assert _relcol(g["S"], r["S"]) <= TOL["f32"]
+    assert np.max(np.abs(g["J"] - r["J"]) / r["J"]) <= TOL["f32"]
+    assert np.max(np.abs(g["y"] - r["y"])) <= TOL["f32"] * np.max(np.abs(r["y"]))
+
+
+def test_fp32_rank1_full_size_two_samples():
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(256, 256, 256, seed=0), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    for m in (0, 201):
+        v = torch.zeros(256, dtype=torch.float32, device="cuda")
+        s = torch.zeros(256, dtype=torch.float32, device="cuda")
+        rom.run_rank1(v, s, inst["mu"][m], 10000)
+        torch.cuda.synchronize()
+        r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][m:m + 1], 10000)
+        ev = _relcol(v.cpu().numpy().astype(np.float64)[:, None], r["V"])
+        es = _relcol(s.cpu().numpy().astype(np.float64)[:, None], r["S"])
+        print("fp32 rank-1 K=256 N=10000 sample %d: errV=%.3e errS=%.3e" % (m, ev, es))
+        assert ev <= TOL["f32"] and es <= TOL["f32"]
+
+
+def test_fp32_mu_permutation_bitwise():
+    inst = synth.round_to(synth.make_instance(128, 128, 11, seed=5), "f32")
+    perm = np.array([3, 10, 0, 7, 1, 9, 2, 8, 4, 6, 5])
+    a = _gpu_run(inst, "f32", 700, probe=True)
+    b = _gpu_run(inst, "f32", 700, cols=perm, probe=True)
+    assert np.array_equal(a["V"][:, perm], b["V"])
+    assert np.array_equal(a["S"][:, perm], b["S"])
+    assert np.array_equal(a["J"][perm], b["J"])
+
+
+def test_fp32_deterministic_and_split():
+    inst = synth.round_to(synth.make_instance(96, 96, 6, seed=8), "f32")
+    w1 = _gpu_run(inst, "f32", 900)
+    w2 = _gpu_run(inst, "f32", 900)
+    assert np.array_equal(w1["V"], w2["V"]) and np.array_equal(w1["S"], w2["S"])
+    p1 = _gpu_run(inst, "f32", 400)
+    p2 = _gpu_run(inst, "f32", 500, n0=400, V0=p1["V"], S0=p1["S"])
+    # the split drops the compensation word once: within a few FP32 roundings
+    assert _relcol(p2["V"], w1["V"]) <= 1e-6 and _relcol(p2["S"], w1["S"]) <= 1e-6
+
+
+def test_zero_steps_is_noop_and_energy():
+    inst = synth.round_to(synth.make_instance(64, 64, 4, seed=1), "f32")
+    rng = np.random.default_rng(3)
+    V0 = rng.standard_normal((64, 4)).astype(np.float32).astype(np.float64)
+    S0 = rng.standard_normal((64, 4)).astype(np.float32).astype(np.float64)
+    g = _gpu_run(inst, "f32", 0, V0=V0, S0=S0)
+    assert np.array_equal(g["V"], V0) and np.array_equal(g["S"], S0)
+    # after the source has decayed the discrete energy is conserved
+    first = _gpu_run(inst, "f64", 300)
+    second = _gpu_run(inst, "f64", 3000, n0=300, V0=first["V"], S0=first["S"])
+    E1 = oracle.energy(inst["Avs"], inst["dt"], first["V"], first["S"])
+    E2 = oracle.energy(inst["Avs"], inst["dt"], second["V"], second["S"])
+    assert np.max(np.abs(E2 - E1) / E1) < 1e-11
