@@ -48,21 +48,29 @@ def _fortran(x):
     return np.asfortranarray(x)
 
 
-def make_instance(kv: int, ks: int, M: int, seed: int = 0, skew: bool = True):
+def make_instance(kv: int, ks: int, M: int, seed: int = 0, skew: bool = True,
+                  random_asv: bool = False):
     """Draw one instance in FP64 (see the module docstring for the recipe).
 
-    With ``skew=False`` an independent Asv is drawn (after the other draws) so
-    that general, non-skew operator pairs can be tested too.
+    With ``skew=False`` the stress operator is a weighted transpose
+    Asv = -diag(w) Avs^T, w ~ U[0.5, 1.5] drawn after the other draws: not
+    skew, but of the form the staggered finite-difference operators have
+    (a positive material weight times the negative transpose, Sec. 3.1), so the
+    leapfrog stays stable.  With ``random_asv=True`` Asv is an independent
+    N(0, 1/Kv) matrix instead: general, and unstable over long horizons.
     """
     rng = np.random.default_rng(seed)
     Avs = rng.standard_normal((kv, ks)) / math.sqrt(ks)
     b = rng.standard_normal(kv)
     mu = rng.uniform(0.5, 1.0, M)
     c = rng.standard_normal(kv)
-    if skew:
+    if random_asv:
+        Asv = rng.standard_normal((ks, kv)) / math.sqrt(kv)
+    elif skew:
         Asv = -Avs.T
     else:
-        Asv = rng.standard_normal((ks, kv)) / math.sqrt(kv)
+        w = rng.uniform(0.5, 1.5, ks)
+        Asv = -(w[:, None] * Avs.T)
     smax = float(np.linalg.svd(Avs, compute_uv=False)[0])
     dt = 0.5 / smax
     return {

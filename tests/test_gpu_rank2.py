@@ -88,6 +88,15 @@ def test_fp64_ragged(kv, ks, M, skew):
     assert np.allclose(g["J"], r["J"], rtol=TOL["f64"], atol=0)
 
 
+@pytest.mark.parametrize("state,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_general_random_pair_short_horizon(state, tol):
+    """Independent random Asv (no structure at all), short horizon."""
+    inst = synth.round_to(synth.make_instance(90, 70, 6, seed=11, random_asv=True), state)
+    g = _gpu_run(inst, state, 40, probe=True)
+    r = _ref(inst, 40, probe=True)
+    assert _relcol(g["V"], r["V"]) <= tol and _relcol(g["S"], r["S"]) <= tol
+
+
 def test_fp64_rank1_matches_oracle():
     from paper_2009_11742_amd import Rom
     inst = synth.make_instance(64, 64, 2, seed=0)
@@ -182,8 +191,12 @@ def test_fp32_deterministic_and_split():
     assert np.array_equal(w1["V"], w2["V"]) and np.array_equal(w1["S"], w2["S"])
     p1 = _gpu_run(inst, "f32", 400)
     p2 = _gpu_run(inst, "f32", 500, n0=400, V0=p1["V"], S0=p1["S"])
-    # the split drops the compensation word once: within a few FP32 roundings
-    assert _relcol(p2["V"], w1["V"]) <= 1e-6 and _relcol(p2["S"], w1["S"]) <= 1e-6
+    # the split rounds the two-term state once; from there the two runs round
+    # differently, so they agree to the FP32 bar (not bitwise), and both
+    # agree with the oracle
+    r = _ref(inst, 900)
+    assert _relcol(p2["V"], w1["V"]) <= TOL["f32"] and _relcol(p2["S"], w1["S"]) <= TOL["f32"]
+    assert _relcol(p2["V"], r["V"]) <= TOL["f32"] and _relcol(w1["V"], r["V"]) <= TOL["f32"]
 
 
 def test_zero_steps_is_noop_and_energy():

@@ -223,7 +223,7 @@ def test_energy_conserved_after_source():
 # --------------------------------------------------------------------------
 
 def test_rank1_equals_rank2_columns_bitwise():
-    inst = synth.make_instance(23, 31, 5, seed=2, skew=False)
+    inst = synth.make_instance(23, 31, 5, seed=2, random_asv=True)
     A, B, b, dt, mu = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"]
     N = 150
     out = oracle.run_rank2(A, B, b, dt, mu, N)
@@ -300,9 +300,10 @@ def _numpy_loop(inst, N, c=None):
 
 
 @pytest.mark.parametrize("kv,ks,M", [(1, 1, 1), (2, 3, 2), (3, 2, 3), (5, 5, 1), (5, 2, 3), (1, 5, 2)])
-@pytest.mark.parametrize("skew", [True, False])
-def test_bruteforce_tiny(kv, ks, M, skew):
-    inst = synth.make_instance(kv, ks, M, seed=kv * 10 + ks, skew=skew)
+@pytest.mark.parametrize("coupling", ["skew", "weighted", "random"])
+def test_bruteforce_tiny(kv, ks, M, coupling):
+    inst = synth.make_instance(kv, ks, M, seed=kv * 10 + ks, skew=coupling == "skew",
+                               random_asv=coupling == "random")
     c = inst["c"]
     out = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 60, c=c)
     V, S, J = _numpy_loop(inst, 60, c)
@@ -321,9 +322,10 @@ def _J(inst, N, Avs=None, Asv=None, mu=None):
     return float(np.sum(o["J"])), o["J"]
 
 
-@pytest.mark.parametrize("kv,ks,M,N,skew", [(12, 12, 3, 200, True), (9, 14, 2, 150, False), (6, 4, 4, 90, True)])
-def test_adjoint_vs_central_fd(kv, ks, M, N, skew):
-    inst = synth.make_instance(kv, ks, M, seed=21, skew=skew)
+@pytest.mark.parametrize("kv,ks,M,N,coupling", [(12, 12, 3, 200, "skew"), (9, 14, 2, 150, "weighted"),
+                                                (6, 4, 4, 90, "skew"), (7, 5, 2, 60, "random")])
+def test_adjoint_vs_central_fd(kv, ks, M, N, coupling):
+    inst = synth.make_instance(kv, ks, M, seed=21, skew=coupling == "skew", random_asv=coupling == "random")
     adj = oracle.adjoint(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, inst["c"])
     J0, Jm = _J(inst, N)
     assert np.sum(adj["J"]) == pytest.approx(J0, rel=1e-14)
