@@ -225,7 +225,8 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (ctx->state_type == ROM_F32) {
-        if (ctx->kvp + ctx->ksp > rom::kMaxPadSum)
+        if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
+            rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
         a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
         e = rom::launch_rank2_f32_mfma(a, st);
