@@ -79,8 +79,9 @@ void free_ctx(rom_ctx *c) {
     hfree(c->avs_pk);
     hfree(c->asv_pk);
     hfree(c->b);
-    hfree(c->avs_t);
-    hfree(c->asv_t);
+    hfree(c->asvT_pk);
+    hfree(c->avsT_pk);
+    hfree(c->ws);
     hfree(c->status);
     delete c;
 }
@@ -243,9 +244,117 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
 rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps, const void *c,
                        const void *V0, const void *S0, double *J, void *dAvs, void *dAsv,
                        double *dmu, int32_t ckpt_stride, void *stream) {
-    (void)ctx; (void)M; (void)mu; (void)nsteps; (void)c; (void)V0; (void)S0; (void)J;
-    (void)dAvs; (void)dAsv; (void)dmu; (void)ckpt_stride; (void)stream;
-    return fail(ROM_E_UNSUPPORTED, "rom_adjoint: not available in this version");
+    if (!ctx) return fail(ROM_E_ARG, "rom_adjoint: NULL context");
+    if (M < 1) return fail(ROM_E_ARG, "rom_adjoint: M must be >= 1");
+    if (!mu || !c || !J) return fail(ROM_E_ARG, "rom_adjoint: mu, c and J are required");
+    if (nsteps < 1) return fail(ROM_E_ARG, "rom_adjoint: nsteps must be >= 1");
+    if (ckpt_stride < 0) return fail(ROM_E_ARG, "rom_adjoint: ckpt_stride must be >= 0");
+    if (ctx->state_type != ROM_F32 || ctx->op_type != ROM_F32)
+        return fail(ROM_E_UNSUPPORTED, "rom_adjoint: FP32 states and operators only in this version");
+    if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
+        rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
+        return fail(ROM_E_UNSUPPORTED, "rom_adjoint: Kv + Ks above the LDS-resident limit");
+    int64_t C = ckpt_stride > 0 ? ckpt_stride : (int64_t)ceil(sqrt((double)nsteps));
+    if (C < 1) C = 1;
+    if (C > nsteps) C = nsteps;
+    const int64_t nseg = (nsteps + C - 1) / C;
+    const int kv = ctx->kv, ks = ctx->ks;
+    const size_t mK = (size_t)M, v1 = (size_t)kv * mK, s1 = (size_t)ks * mK;
+    // workspace layout (floats, then doubles)
+    const size_t n_ck = (size_t)nseg * (v1 + s1);
+    const size_t n_vtr = (size_t)(C + 1) * v1, n_str = (size_t)(C + 1) * s1;
+    const size_t n_wtr = (size_t)C * v1, n_qtr = (size_t)C * s1;
+    const size_t n_cur = v1 + s1, n_pq = v1 + s1;
+    size_t nf = n_ck + n_vtr + n_str + n_wtr + n_qtr + n_cur + n_pq;
+    nf = (nf + 1) / 2 * 2;
+    const size_t n_ytr = (size_t)C * mK, n_da = 2 * (size_t)kv * ks;
+    const size_t bytes = nf * sizeof(float) + (n_ytr + n_da) * sizeof(double);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (!ctx->asvT_pk) {
+        size_t pk = sizeof(float) * (size_t)ctx->kvp * ctx->ksp;
+        e = hipMalloc(&ctx->asvT_pk, pk);
+        if (e == hipSuccess) e = hipMalloc(&ctx->avsT_pk, pk);
+        if (e != hipSuccess) {
+            hfree(ctx->asvT_pk); hfree(ctx->avsT_pk);
+            ctx->asvT_pk = ctx->avsT_pk = nullptr;
+            return fail(ROM_E_NOMEM, "rom_adjoint: device allocation failed");
+        }
+        // Asv^T is Kv x Ks (rows kvp, reduction ksp); Avs^T is Ks x Kv
+        e = rom::launch_pack_f32_from_f32((const float *)ctx->asv_cm, ks, kv, true, ctx->kvp,
+                                          ctx->ksp, ctx->asvT_pk, st);
+        if (e == hipSuccess)
+            e = rom::launch_pack_f32_from_f32((const float *)ctx->avs_cm, kv, ks, true, ctx->ksp,
+                                              ctx->kvp, ctx->avsT_pk, st);
+        if (e != hipSuccess) return hip_fail(e, "rom_adjoint: pack");
+    }
+    if (ctx->ws_bytes < bytes) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "rom_adjoint: synchronize");
+        hfree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+        e = hipMalloc(&ctx->ws, bytes);
+        if (e != hipSuccess) { ctx->ws = nullptr; return fail(ROM_E_NOMEM, "rom_adjoint: workspace allocation failed"); }
+        ctx->ws_bytes = bytes;
+    }
+    float *f = static_cast<float *>(ctx->ws);
+    float *ck = f;
+    float *vtr = ck + n_ck, *str = vtr + n_vtr, *wtr = str + n_str, *qtr = wtr + n_wtr;
+    float *curV = qtr + n_qtr, *curS = curV + v1, *P = curS + s1, *Q = P + v1;
+    double *ytr = reinterpret_cast<double *>(f + nf);
+    double *dA64 = ytr + n_ytr;
+    double *dAvs64 = dA64, *dAsv64 = dA64 + (size_t)kv * ks;
+
+#define ACHK(call, what) do { e = (call); if (e != hipSuccess) return hip_fail(e, what); } while (0)
+    // forward sweep: checkpoint before every segment, accumulate J
+    if (V0) ACHK(hipMemcpyAsync(curV, V0, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: copy");
+    else ACHK(hipMemsetAsync(curV, 0, v1 * 4, st), "rom_adjoint: memset");
+    if (S0) ACHK(hipMemcpyAsync(curS, S0, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: copy");
+    else ACHK(hipMemsetAsync(curS, 0, s1 * 4, st), "rom_adjoint: memset");
+    ACHK(hipMemsetAsync(J, 0, mK * 8, st), "rom_adjoint: memset");
+    rom::Rank2Args a;
+    a.b = ctx->b; a.c = c; a.mu = mu; a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp;
+    a.M = M; a.dt = ctx->dt; a.avs = ctx->avs_pk; a.asv = ctx->asv_pk; a.y = nullptr;
+    for (int64_t g = 0; g < nseg; ++g) {
+        const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
+        float *cg = ck + (size_t)g * (v1 + s1);
+        ACHK(hipMemcpyAsync(cg, curV, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
+        ACHK(hipMemcpyAsync(cg + v1, curS, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
+        a.V = curV; a.S = curS; a.J = J; a.n0 = nb; a.nsteps = len;
+        ACHK(rom::launch_rank2_f32_mfma(a, st), "rom_adjoint: forward launch");
+    }
+    // reverse sweep, segment by segment from the last
+    ACHK(hipMemsetAsync(P, 0, (v1 + s1) * 4, st), "rom_adjoint: memset");
+    ACHK(hipMemsetAsync(dA64, 0, n_da * 8, st), "rom_adjoint: memset");
+    if (dmu) ACHK(hipMemsetAsync(dmu, 0, mK * 8, st), "rom_adjoint: memset");
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
+        const float *cg = ck + (size_t)g * (v1 + s1);
+        ACHK(hipMemcpyAsync(curV, cg, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: restore");
+        ACHK(hipMemcpyAsync(curS, cg + v1, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: restore");
+        // recompute the segment, keeping every state and the probe trace
+        rom::Rank2Args fw = a;
+        fw.V = curV; fw.S = curS; fw.J = nullptr; fw.y = ytr; fw.n0 = nb; fw.nsteps = len;
+        fw.vtr = vtr; fw.str = str;
+        ACHK(rom::launch_rank2_f32_mfma(fw, st), "rom_adjoint: recompute launch");
+        // reverse steps nb + len - 1 .. nb
+        rom::Rank2Args ad = a;
+        ad.avs = ctx->asvT_pk; ad.asv = ctx->avsT_pk; ad.V = P; ad.S = Q; ad.J = nullptr;
+        ad.n0 = nb; ad.nsteps = len; ad.ytr = ytr; ad.wtr = wtr; ad.qtr = qtr; ad.dmu = dmu;
+        ACHK(rom::launch_adjoint_f32_mfma(ad, st), "rom_adjoint: reverse launch");
+        // dAvs += dt sum_n W^n (S^n)^T ;  dAsv += dt sum_n Q^{n+1} (V^{n+1})^T
+        if (dAvs)
+            ACHK(rom::launch_gemm_nt_acc64(wtr, str, kv, ks, len * M, ctx->dt, dAvs64, st),
+                 "rom_adjoint: gradient product");
+        if (dAsv)
+            ACHK(rom::launch_gemm_nt_acc64(qtr, vtr + v1, ks, kv, len * M, ctx->dt, dAsv64, st),
+                 "rom_adjoint: gradient product");
+    }
+    if (dAvs) ACHK(rom::launch_f64_to_f32(dAvs64, (float *)dAvs, (int64_t)kv * ks, st), "rom_adjoint: convert");
+    if (dAsv) ACHK(rom::launch_f64_to_f32(dAsv64, (float *)dAsv, (int64_t)kv * ks, st), "rom_adjoint: convert");
+#undef ACHK
+    return ROM_OK;
 }
 
 rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,

@@ -38,8 +38,12 @@ struct rom_ctx {
     float *avs_pk = nullptr, *asv_pk = nullptr;
     // Source vector in the state type, zero padded to kvp entries.
     void *b = nullptr;
-    // Transposed operators (column-major, state type) for the adjoint, lazily.
-    void *avs_t = nullptr, *asv_t = nullptr;
+    // Transposed operators packed like avs_pk / asv_pk for the adjoint sweep
+    // (lazily): asvT_pk holds Asv^T (Kv x Ks), avsT_pk holds Avs^T (Ks x Kv).
+    float *asvT_pk = nullptr, *avsT_pk = nullptr;
+    // Adjoint workspace (checkpoints, segment traces), grown on demand.
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
     // Device status word (in-kernel errors).
     int *status = nullptr;
 };
@@ -58,10 +62,27 @@ struct Rank2Args {
     int kv, ks, kvp, ksp, M;
     int64_t n0, nsteps;
     double dt;            // FP64 step (forcing time t_n = n * dt)
+    // forward only: state traces ((nsteps + 1) x K x M) or null
+    float *vtr = nullptr, *str = nullptr;
+    // adjoint only: forward probe trace (nsteps x M), W / Q traces
+    // (nsteps x K x M) and dJ/dmu (M, accumulated)
+    const double *ytr = nullptr;
+    float *wtr = nullptr, *qtr = nullptr;
+    double *dmu = nullptr;
 };
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st);
+hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st);
+// dA (rows x cols, FP64, column-major) += alpha * X * Y^T with X rows x R and
+// Y cols x R column-major FP32 (ld rows / cols).
+hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
+                                double alpha, double *dA, hipStream_t st);
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+// Pack a column-major FP32 matrix (rows x cols, or its transpose when
+// `transpose`) into the 4x4x1 MFMA panel layout with padded sizes.
+hipError_t launch_pack_f32_from_f32(const float *A, int rows, int cols, bool transpose, int prow,
+                                    int pcol, float *pk, hipStream_t st);
 template <typename T>
 hipError_t launch_rank2_valu(const Rank2Args &a, hipStream_t st);
 

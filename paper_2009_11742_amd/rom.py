@@ -119,3 +119,72 @@ class Rom:
             raise ValueError("y must be a contiguous float64 tensor of shape (nsteps, M)")
         check(_lib.load().rom_run_rank2(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
                                         _ptr(c), _ptr(J), _ptr(y), _stream_handle(stream)))
+
+    def adjoint(self, mu, nsteps, c, V0=None, S0=None, stride=0, grads=("dAvs", "dAsv", "dmu"),
+                stream=None):
+        """Probe QoI J_m = sum_n dt (c^T V_m^(n+1))^2 and its gradients.
+
+        Returns a dict with J (M,) float64 and the requested gradients of
+        J = sum_m J_m: dAvs (Kv, Ks) and dAsv (Ks, Kv) as float32 tensors
+        (row-major views of the column-major results), dmu (M,) float64.
+        """
+        M = int(mu.numel())
+        dev = mu.device
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        self._chk_state(c.view(1, -1), self.kv, 1, "c")
+        if V0 is not None:
+            self._chk_state(V0, self.kv, M, "V0")
+        if S0 is not None:
+            self._chk_state(S0, self.ks, M, "S0")
+        J = torch.zeros(M, dtype=torch.float64, device=dev)
+        # column-major Kv x Ks == row-major (Ks, Kv)
+        dAvs = torch.zeros((self.ks, self.kv), dtype=torch.float32, device=dev) if "dAvs" in grads else None
+        dAsv = torch.zeros((self.kv, self.ks), dtype=torch.float32, device=dev) if "dAsv" in grads else None
+        dmu = torch.zeros(M, dtype=torch.float64, device=dev) if "dmu" in grads else None
+        check(_lib.load().rom_adjoint(self._ctx, M, _ptr(mu), int(nsteps), _ptr(c), _ptr(V0), _ptr(S0),
+                                      _ptr(J), _ptr(dAvs), _ptr(dAsv), _ptr(dmu), int(stride),
+                                      _stream_handle(stream)))
+        out = {"J": J}
+        if dAvs is not None:
+            out["dAvs"] = dAvs.t()
+        if dAsv is not None:
+            out["dAsv"] = dAsv.t()
+        if dmu is not None:
+            out["dmu"] = dmu
+        return out
+
+
+class RomQoI(torch.autograd.Function):
+    """J = sum_m sum_n dt (c^T V_m^(n+1))^2 of an FP32 rank-2 run from zero state.
+
+    forward(Avs, Asv, mu, b, c, dt, nsteps) -> scalar J (float64).
+    Gradients flow to Avs (Kv x Ks), Asv (Ks x Kv) and mu (M,) through the
+    library's discrete adjoint (rom_adjoint); b, c and dt are constants.
+    The operators may live on any device; a library context is built from
+    their current values on every forward call.
+    """
+
+    @staticmethod
+    def forward(ctx, Avs, Asv, mu, b, c, dt, nsteps):
+        A = Avs.detach().to("cpu", torch.float64).numpy()
+        B = Asv.detach().to("cpu", torch.float64).numpy()
+        bb = torch.as_tensor(b).detach().to("cpu", torch.float64).numpy()
+        rom = Rom(A, B, bb, float(dt), state="f32")
+        dev = mu.device if mu.is_cuda else torch.device("cuda")
+        mu_d = mu.detach().to(dev, torch.float64).contiguous()
+        c_d = torch.as_tensor(c).detach().to(dev, torch.float32).contiguous()
+        out = rom.adjoint(mu_d, int(nsteps), c_d)
+        ctx.save_for_backward(Avs, Asv, mu)
+        ctx.grads = out
+        rom.close()
+        return out["J"].sum().to(mu.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        Avs, Asv, mu = ctx.saved_tensors
+        g = ctx.grads
+        gA = (gJ.to(g["dAvs"].device, torch.float64) * g["dAvs"].to(torch.float64)).to(Avs.device, Avs.dtype)
+        gB = (gJ.to(g["dAsv"].device, torch.float64) * g["dAsv"].to(torch.float64)).to(Asv.device, Asv.dtype)
+        gm = (gJ.to(g["dmu"].device, torch.float64) * g["dmu"]).to(mu.device, mu.dtype)
+        return gA, gB, gm, None, None, None, None
