@@ -186,14 +186,34 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
 
 /*
  * Grouped run: G independent ROM instances (each its own context, sizes and
- * samples) advanced `nsteps` steps from step 0 in ONE persistent launch
- * (batched products, the rank-3 direction of Sec. 5).  All contexts must
- * have F32 states and F32 operators.  Per instance i: M[i] samples, mu[i]
- * dev FP64, V[i] / S[i] dev states as in rom_run_rank2.
+ * samples) advanced `nsteps` steps from step 0 in ONE launch — the batched
+ * direction the paper names for many operator realisations (Sec. 5).  Work
+ * items are (instance, 4-sample column block) pairs dispatched largest
+ * operator first.  All contexts must have F32 states and operators, within
+ * the LDS-resident size limit.  Per instance i: M[i] samples, mu[i] dev FP64,
+ * V[i] / S[i] dev states as in rom_run_rank2 (host arrays of pointers).
+ * Each instance's result is bitwise identical to its own rom_run_rank2.
+ * The call uploads a small descriptor table with one stream synchronisation;
+ * use the plan API below for asynchronous or graph-captured runs.
  */
 rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M,
                            const double *const *mu, int64_t nsteps, void *const *V,
                            void *const *S, void *stream);
+
+/*
+ * Grouped plan: the validated descriptor table of a grouped run, uploaded
+ * once (synchronously) by rom_group_create.  rom_group_run is then a single
+ * kernel launch with no host-side data (so it can be captured in a HIP
+ * graph and replayed); it advances every instance over steps
+ * n0 .. n0+nsteps-1.  The plan stores the caller's device pointers, which
+ * must stay valid while the plan is used.  Contexts must outlive the plan.
+ */
+typedef struct rom_group rom_group;
+rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M,
+                            const double *const *mu, void *const *V, void *const *S,
+                            rom_group **out);
+rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream);
+rom_status rom_group_destroy(rom_group *g);
 
 /* Thread-local text describing the last non-OK status of this thread. */
 const char *rom_last_error(void);

@@ -21,7 +21,8 @@ ROM_SKEW_CHECK = 1
 
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
-           "rom_adjoint", "rom_run_grouped", "rom_last_error", "rom_version"]
+           "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
+           "rom_last_error", "rom_version"]
 
 
 class RomConfig(C.Structure):
@@ -72,6 +73,13 @@ def load():
         lib.rom_run_grouped.restype = C.c_int
         lib.rom_run_grouped.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_i32), C.POINTER(_vp),
                                         _i64, C.POINTER(_vp), C.POINTER(_vp), _vp]
+        lib.rom_group_create.restype = C.c_int
+        lib.rom_group_create.argtypes = [C.POINTER(_vp), _i32, C.POINTER(_i32), C.POINTER(_vp),
+                                         C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]
+        lib.rom_group_run.restype = C.c_int
+        lib.rom_group_run.argtypes = [_vp, _i64, _i64, _vp]
+        lib.rom_group_destroy.restype = C.c_int
+        lib.rom_group_destroy.argtypes = [_vp]
         lib.rom_last_error.restype = C.c_char_p
         lib.rom_last_error.argtypes = []
         lib.rom_version.restype = C.c_char_p

@@ -81,9 +81,7 @@ __device__ __forceinline__ double wave_sum(const double *yp, int jcol) {
 //   and a.wtr[n - n0] = P after the P update, and adds
 //   dt (b^T P) du/dmu(t_n) to a.dmu.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void rank2_f32_mfma_kernel(Rank2Args a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned char *smem) {
     const int kvp = a.kvp, ksp = a.ksp;
     const int ldv = kvp + 4, lds_ = ksp + 4;     // +4 floats: spread columns over banks
     float *Vh = reinterpret_cast<float *>(smem);
@@ -95,7 +93,6 @@ void rank2_f32_mfma_kernel(Rank2Args a) {
     float *cl = bl + kvp;                                         // probe, kvp (0 if none)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int col0 = blockIdx.x * NB;
     const float *Vin = static_cast<const float *>(a.V);
     const float *Sin = static_cast<const float *>(a.S);
     const float *bv = static_cast<const float *>(a.b);
@@ -186,6 +183,27 @@ void rank2_f32_mfma_kernel(Rank2Args a) {
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rank2_f32_mfma_kernel(Rank2Args a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    run_block<MODE>(a, blockIdx.x * NB, smem);
+}
+
+// Grouped forward run: workgroup i advances column block items[i].y of
+// instance items[i].x (items ordered by decreasing cost by the host, so the
+// largest blocks are dispatched first).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void grouped_f32_mfma_kernel(const Rank2Args *__restrict__ inst, const int2 *__restrict__ items,
+                             int64_t n0, int64_t nsteps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 it = items[blockIdx.x];
+    Rank2Args a = inst[it.x];
+    a.n0 = n0;
+    a.nsteps = nsteps;
+    run_block<kForward>(a, it.y * NB, smem);
+}
+
 }  // namespace
 
 size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp) {
@@ -207,7 +225,18 @@ hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_dev, int nitems,
+                                   size_t lds_bytes, int64_t n0, int64_t nsteps, hipStream_t st) {
+    if (nitems <= 0 || nsteps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grouped_f32_mfma_kernel, dim3(nitems), dim3(kThreads), lds_bytes, st, inst_dev,
+                       items_dev, n0, nsteps);
+    return hipGetLastError();
+}
+
 hipError_t rank2_f32_mfma_configure() {
+    hipError_t g = hipFuncSetAttribute((const void *)grouped_f32_mfma_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (g != hipSuccess) return g;
     hipError_t e = hipFuncSetAttribute((const void *)rank2_f32_mfma_kernel<kForward>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -357,10 +358,128 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     return ROM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validate a grouped request and build the per-instance arguments and the
+// (instance, column block) items, largest operator first.
+rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
+                       void *const *V, void *const *S, std::vector<rom::Rank2Args> &inst,
+                       std::vector<int2> &items, size_t &lds) {
+    if (!ctx || !M || !mu || !V || !S) return fail(ROM_E_ARG, "grouped: NULL array");
+    if (G < 1) return fail(ROM_E_ARG, "grouped: G must be >= 1");
+    inst.assign(G, rom::Rank2Args());
+    lds = 0;
+    for (int i = 0; i < G; ++i) {
+        rom_ctx *c = ctx[i];
+        if (!c) return fail(ROM_E_ARG, "grouped: NULL context");
+        if (M[i] < 1) return fail(ROM_E_ARG, "grouped: every M[i] must be >= 1");
+        if (!mu[i] || !V[i] || !S[i]) return fail(ROM_E_ARG, "grouped: NULL mu, V or S");
+        if (c->state_type != ROM_F32 || c->op_type != ROM_F32)
+            return fail(ROM_E_UNSUPPORTED, "grouped: FP32 states and operators only");
+        size_t b = rom::rank2_f32_mfma_lds_bytes(c->kvp, c->ksp);
+        if (c->kvp + c->ksp > rom::kMaxPadSum || b > 160 * 1024)
+            return fail(ROM_E_UNSUPPORTED, "grouped: an instance exceeds the LDS-resident limit");
+        if (b > lds) lds = b;
+        rom::Rank2Args &a = inst[i];
+        a.avs = c->avs_pk; a.asv = c->asv_pk; a.b = c->b; a.c = nullptr; a.mu = mu[i];
+        a.V = V[i]; a.S = S[i]; a.J = nullptr; a.y = nullptr;
+        a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.M = M[i];
+        a.n0 = 0; a.nsteps = 0; a.dt = c->dt;
+    }
+    std::vector<int> order(G);
+    for (int i = 0; i < G; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (int64_t)inst[x].kvp * inst[x].ksp > (int64_t)inst[y].kvp * inst[y].ksp;
+    });
+    items.clear();
+    for (int i : order)
+        for (int cb = 0; cb * rom::kColBlock < inst[i].M; ++cb) items.push_back(make_int2(i, cb));
+    return ROM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
+                            void *const *V, void *const *S, rom_group **out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(ROM_E_ARG, "rom_group_create: NULL out");
+    std::vector<rom::Rank2Args> inst;
+    std::vector<int2> items;
+    size_t lds = 0;
+    rom_status r = build_group(ctx, G, M, mu, V, S, inst, items, lds);
+    if (r != ROM_OK) return r;
+    rom_group *g = new (std::nothrow) rom_group();
+    if (!g) return fail(ROM_E_NOMEM, "rom_group_create: host allocation failed");
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "rom_group_create: hipGetDevice"); }
+    const size_t ib = sizeof(rom::Rank2Args) * inst.size();
+    const size_t bytes = ib + sizeof(int2) * items.size();
+    e = hipMalloc(&g->dev, bytes);
+    if (e != hipSuccess) { delete g; return fail(ROM_E_NOMEM, "rom_group_create: device allocation failed"); }
+    e = hipMemcpy(g->dev, inst.data(), ib, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(static_cast<char *>(g->dev) + ib, items.data(), sizeof(int2) * items.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) { hfree(g->dev); delete g; return hip_fail(e, "rom_group_create: upload"); }
+    g->G = G;
+    g->nitems = (int)items.size();
+    g->lds_bytes = lds;
+    g->inst = static_cast<const rom::Rank2Args *>(g->dev);
+    g->items = reinterpret_cast<const int2 *>(static_cast<char *>(g->dev) + ib);
+    *out = g;
+    return ROM_OK;
+}
+
+rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream) {
+    if (!g) return fail(ROM_E_ARG, "rom_group_run: NULL plan");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_group_run: n0 and nsteps must be >= 0");
+    hipError_t e = rom::launch_grouped_f32_mfma(g->inst, g->items, g->nitems, g->lds_bytes, n0, nsteps,
+                                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "rom_group_run: launch");
+    return ROM_OK;
+}
+
+rom_status rom_group_destroy(rom_group *g) {
+    if (!g) return ROM_OK;
+    hfree(g->dev);
+    delete g;
+    return ROM_OK;
+}
+
 rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
                            int64_t nsteps, void *const *V, void *const *S, void *stream) {
-    (void)ctx; (void)G; (void)M; (void)mu; (void)nsteps; (void)V; (void)S; (void)stream;
-    return fail(ROM_E_UNSUPPORTED, "rom_run_grouped: not available in this version");
+    if (nsteps < 0) return fail(ROM_E_ARG, "rom_run_grouped: nsteps must be >= 0");
+    std::vector<rom::Rank2Args> inst;
+    std::vector<int2> items;
+    size_t lds = 0;
+    rom_status r = build_group(ctx, G, M, mu, V, S, inst, items, lds);
+    if (r != ROM_OK) return r;
+    if (nsteps == 0) return ROM_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t ib = sizeof(rom::Rank2Args) * inst.size();
+    const size_t bytes = ib + sizeof(int2) * items.size();
+    // one contiguous host block, uploaded stream-ordered into stream-ordered
+    // device memory that is released after the launch on the same stream
+    std::vector<unsigned char> host(bytes);
+    memcpy(host.data(), inst.data(), ib);
+    memcpy(host.data() + ib, items.data(), sizeof(int2) * items.size());
+    void *dev = nullptr;
+    hipError_t e = hipMallocAsync(&dev, bytes, st);
+    if (e != hipSuccess) return fail(ROM_E_NOMEM, "rom_run_grouped: device allocation failed");
+    e = hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host block dies on return
+    if (e == hipSuccess)
+        e = rom::launch_grouped_f32_mfma(static_cast<const rom::Rank2Args *>(dev),
+                                         reinterpret_cast<const int2 *>(static_cast<char *>(dev) + ib),
+                                         (int)items.size(), lds, 0, nsteps, st);
+    hipError_t e2 = hipFreeAsync(dev, st);
+    if (e != hipSuccess) return hip_fail(e, "rom_run_grouped");
+    if (e2 != hipSuccess) return hip_fail(e2, "rom_run_grouped: free");
+    return ROM_OK;
 }
 
 }  // extern "C"

@@ -74,6 +74,11 @@ struct Rank2Args {
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st);
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st);
+// Grouped forward run over device arrays of per-instance arguments and
+// (instance, column block) items, steps n0 .. n0+nsteps-1 for all; LDS of
+// lds_bytes (the largest instance's need).
+hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_dev, int nitems,
+                                   size_t lds_bytes, int64_t n0, int64_t nsteps, hipStream_t st);
 // dA (rows x cols, FP64, column-major) += alpha * X * Y^T with X rows x R and
 // Y cols x R column-major FP32 (ld rows / cols).
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
@@ -98,3 +103,12 @@ hipError_t launch_pack_f32(const double *A, int rows, int cols, int rowsp, int c
                            hipStream_t st);
 
 }  // namespace rom
+
+struct rom_group {
+    int device = 0;
+    int G = 0, nitems = 0;
+    size_t lds_bytes = 0;
+    void *dev = nullptr;          // [G] Rank2Args then [nitems] int2 items
+    const rom::Rank2Args *inst = nullptr;
+    const int2 *items = nullptr;
+};

@@ -188,3 +188,58 @@ class RomQoI(torch.autograd.Function):
         gB = (gJ.to(g["dAsv"].device, torch.float64) * g["dAsv"].to(torch.float64)).to(Asv.device, Asv.dtype)
         gm = (gJ.to(g["dmu"].device, torch.float64) * g["dmu"]).to(mu.device, mu.dtype)
         return gA, gB, gm, None, None, None, None
+
+
+def _ptr_array(ptrs):
+    arr = (C.c_void_p * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def _group_args(roms, mus, Vs, Ss):
+    G = len(roms)
+    if not (len(mus) == len(Vs) == len(Ss) == G) or G < 1:
+        raise ValueError("roms, mus, Vs, Ss must have the same nonzero length")
+    for r, mu, V, S in zip(roms, mus, Vs, Ss):
+        M = int(mu.numel())
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        r._chk_state(V, r.kv, M, "V")
+        r._chk_state(S, r.ks, M, "S")
+    ctxs = _ptr_array([r.handle.value for r in roms])
+    Ms = (C.c_int32 * G)(*[int(mu.numel()) for mu in mus])
+    return (ctxs, G, Ms, _ptr_array([mu.data_ptr() for mu in mus]),
+            _ptr_array([V.data_ptr() for V in Vs]), _ptr_array([S.data_ptr() for S in Ss]))
+
+
+def run_grouped(roms, mus, Vs, Ss, nsteps, stream=None):
+    """Advance G instances (list of Rom, FP32) ``nsteps`` steps from 0 in one launch."""
+    ctxs, G, Ms, mup, Vp, Sp = _group_args(roms, mus, Vs, Ss)
+    check(_lib.load().rom_run_grouped(ctxs, G, Ms, mup, int(nsteps), Vp, Sp, _stream_handle(stream)))
+
+
+class GroupPlan:
+    """Uploaded descriptor table of a grouped run; ``run`` is one launch and
+    may be captured in a CUDA/HIP graph.  Keeps references to its tensors."""
+
+    def __init__(self, roms, mus, Vs, Ss):
+        ctxs, G, Ms, mup, Vp, Sp = _group_args(roms, mus, Vs, Ss)
+        self._keep = (list(roms), list(mus), list(Vs), list(Ss))
+        h = C.c_void_p()
+        check(_lib.load().rom_group_create(ctxs, G, Ms, mup, Vp, Sp, C.byref(h)))
+        self._h = h
+
+    def run(self, nsteps, n0=0, stream=None):
+        check(_lib.load().rom_group_run(self._h, int(n0), int(nsteps), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().rom_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
