@@ -114,6 +114,16 @@ typedef struct rom_ctx rom_ctx;
 rom_status rom_create(const rom_config *cfg, const double *Avs, const double *Asv,
                       const double *b, void *stream, rom_ctx **out);
 
+/*
+ * Copy the operators exactly as the context's products use them to host
+ * FP64 column-major arrays: Avs (Kv x Ks) and Asv (Ks x Kv) after rounding
+ * to op_type (FP32, BF16 via FP32) and, for FP8-E4M3, multiplied by the
+ * per-tensor scale, which is returned in *scale (1 otherwise; scale may be
+ * NULL).  Lets a caller integrate the same operators with another
+ * implementation.  Synchronises the device.
+ */
+rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *scale);
+
 /* Release every device buffer owned by the context.  NULL is accepted. */
 rom_status rom_destroy(rom_ctx *ctx);
 

@@ -36,7 +36,20 @@ __global__ void pack_f32_kernel(const double *__restrict__ A, int rows, int cols
     }
 }
 
+__global__ void f32_to_f64_kernel(const float *__restrict__ s, double *__restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (double)s[i];
+}
+
 }  // namespace
+
+hipError_t launch_convert_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(f32_to_f64_kernel, dim3(blocks), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_convert(const double *src, void *dst, int64_t n, rom_dtype to, hipStream_t st) {
     if (n <= 0) return hipSuccess;

@@ -14,6 +14,8 @@
 
 namespace rom {
 size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp);
+size_t rank2_lowp_lds_bytes(int kvp, int ksp);
+hipError_t rank2_lowp_configure();
 size_t rank2_valu_lds_bytes(rom_dtype st, int kv, int ks, int kvp, int ksp);
 hipError_t rank2_f32_mfma_configure();
 hipError_t rank2_valu_configure();
@@ -79,6 +81,8 @@ void free_ctx(rom_ctx *c) {
     hfree(c->asv_cm);
     hfree(c->avs_pk);
     hfree(c->asv_pk);
+    hfree(c->avs_lp);
+    hfree(c->asv_lp);
     hfree(c->b);
     hfree(c->asvT_pk);
     hfree(c->avsT_pk);
@@ -110,8 +114,10 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     if (cfg->op_type != ROM_F64 && cfg->op_type != ROM_F32 && cfg->op_type != ROM_BF16 &&
         cfg->op_type != ROM_F8E4M3)
         return fail(ROM_E_ARG, "rom_create: unknown op_type");
-    if (cfg->op_type != cfg->state_type)
-        return fail(ROM_E_UNSUPPORTED, "rom_create: op_type must equal state_type in this version");
+    const bool lowp = cfg->op_type == ROM_BF16 || cfg->op_type == ROM_F8E4M3;
+    if (lowp ? cfg->state_type != ROM_F32 : cfg->op_type != cfg->state_type)
+        return fail(ROM_E_UNSUPPORTED, "rom_create: supported (op, state) pairs are (F64, F64), "
+                                       "(F32, F32), (BF16, F32) and (F8E4M3, F32)");
     if (cfg->flags & ~(uint32_t)ROM_SKEW_CHECK) return fail(ROM_E_ARG, "rom_create: unknown flag bits");
     const size_t nA = (size_t)kv * ks;
     if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
@@ -136,6 +142,7 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     if (!g_configured) {
         e = rom::rank2_f32_mfma_configure();
         if (e == hipSuccess) e = rom::rank2_valu_configure();
+        if (e == hipSuccess) e = rom::rank2_lowp_configure();
         if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: kernel attributes"); }
         g_configured = true;
     }
@@ -169,7 +176,30 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), "rom_create: convert");
     CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), "rom_create: convert");
     CHK(rom::launch_convert(sb, c->b, c->kvp, c->state_type, st), "rom_create: convert");
-    if (c->state_type == ROM_F32) {
+    if (lowp) {
+        // BF16: round each operator (via FP32) to BF16; FP8: one scale
+        // amax(|fp32(Avs)|, |fp32(Asv)|) / 448 for both operators, so a skew
+        // pair stays exactly skew after quantisation.
+        const size_t eb = c->op_type == ROM_BF16 ? 2 : 1;
+        unsigned *amax = reinterpret_cast<unsigned *>(c->status);
+        CHK(hipMalloc(&c->avs_lp, eb * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
+        CHK(hipMalloc(&c->asv_lp, eb * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
+        if (c->op_type == ROM_F8E4M3) {
+            CHK(rom::launch_amax(sA, (int64_t)nA, amax, st), "rom_create: amax");
+            CHK(rom::launch_amax(sB, (int64_t)nA, amax, st), "rom_create: amax");
+        }
+        CHK(rom::launch_pack_lowp(sA, kv, ks, c->kvp, c->ksp, c->op_type, amax, c->avs_lp, st), "rom_create: pack");
+        CHK(rom::launch_pack_lowp(sB, ks, kv, c->ksp, c->kvp, c->op_type, amax, c->asv_lp, st), "rom_create: pack");
+        if (c->op_type == ROM_F8E4M3) {
+            unsigned bits = 0;
+            CHK(hipMemcpyAsync(&bits, amax, sizeof(bits), hipMemcpyDeviceToHost, st), "rom_create: readback");
+            CHK(hipStreamSynchronize(st), "rom_create: synchronize");
+            float am;
+            memcpy(&am, &bits, sizeof(am));
+            c->op_scale = am > 0.f ? am / 448.0f : 1.0f;
+            CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
+        }
+    } else if (c->state_type == ROM_F32) {
         CHK(hipMalloc(&c->avs_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
         CHK(hipMalloc(&c->asv_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
         CHK(rom::launch_pack_f32(sA, kv, ks, c->kvp, c->ksp, c->avs_pk, st), "rom_create: pack");
@@ -179,6 +209,35 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
 #undef CHK
     hfree(stage);
     *out = c;
+    return ROM_OK;
+}
+
+rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *scale) {
+    if (!ctx || !Avs || !Asv) return fail(ROM_E_ARG, "rom_get_operators: NULL argument");
+    const size_t nA = (size_t)ctx->kv * ctx->ks;
+    double *d = nullptr;
+    hipError_t e = hipMalloc(&d, 2 * nA * sizeof(double));
+    if (e != hipSuccess) return fail(ROM_E_NOMEM, "rom_get_operators: device allocation failed");
+    if (ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) {
+        e = rom::launch_unpack_lowp(ctx->avs_lp, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, ctx->op_type,
+                                    (double)ctx->op_scale, d, nullptr);
+        if (e == hipSuccess)
+            e = rom::launch_unpack_lowp(ctx->asv_lp, ctx->ks, ctx->kv, ctx->ksp, ctx->kvp, ctx->op_type,
+                                        (double)ctx->op_scale, d + nA, nullptr);
+    } else if (ctx->state_type == ROM_F32) {
+        e = rom::launch_convert_f32_to_f64(static_cast<const float *>(ctx->avs_cm), d, (int64_t)nA, nullptr);
+        if (e == hipSuccess)
+            e = rom::launch_convert_f32_to_f64(static_cast<const float *>(ctx->asv_cm), d + nA, (int64_t)nA, nullptr);
+    } else {
+        e = hipMemcpy(d, ctx->avs_cm, nA * sizeof(double), hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d + nA, ctx->asv_cm, nA * sizeof(double), hipMemcpyDeviceToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(Avs, d, nA * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(Asv, d + nA, nA * sizeof(double), hipMemcpyDeviceToHost);
+    hfree(d);
+    if (e != hipSuccess) return hip_fail(e, "rom_get_operators");
+    if (scale) *scale = ctx->op_type == ROM_F8E4M3 ? (double)ctx->op_scale : 1.0;
     return ROM_OK;
 }
 
@@ -192,6 +251,8 @@ rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu, 
     if (!ctx || !v || !s) return fail(ROM_E_ARG, "rom_step_rank1: NULL argument");
     if (n < 0) return fail(ROM_E_ARG, "rom_step_rank1: n must be >= 0");
     if (!isfinite(mu)) return fail(ROM_E_NONFINITE, "rom_step_rank1: mu not finite");
+    if (ctx->op_type != ctx->state_type)
+        return fail(ROM_E_UNSUPPORTED, "rom_step_rank1: needs op_type == state_type");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = ctx->state_type == ROM_F64
         ? rom::launch_rank1_step<double>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu, v, s, st)
@@ -226,7 +287,12 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if (ctx->state_type == ROM_F32) {
+    if (ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) {
+        if (rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
+            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
+        a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
+        e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
+    } else if (ctx->state_type == ROM_F32) {
         if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
             rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");

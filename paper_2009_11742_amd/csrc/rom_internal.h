@@ -36,6 +36,10 @@ struct rom_ctx {
     // avs_pk[t][k/4][lane][k%4] = Avs[64 t + lane][k], zero padded to kvp x ksp;
     // asv_pk likewise for Asv (ksp x kvp).
     float *avs_pk = nullptr, *asv_pk = nullptr;
+    // Low-precision operators (op_type BF16 / FP8): packed panels as void*
+    // in avs_lp / asv_lp, FP8 per-tensor scale (shared by both operators).
+    void *avs_lp = nullptr, *asv_lp = nullptr;
+    float op_scale = 1.0f;
     // Source vector in the state type, zero padded to kvp entries.
     void *b = nullptr;
     // Transposed operators packed like avs_pk / asv_pk for the adjoint sweep
@@ -74,6 +78,12 @@ struct Rank2Args {
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st);
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st);
+hipError_t launch_rank2_lowp(const Rank2Args &a, rom_dtype op, float scale, hipStream_t st);
+hipError_t launch_amax(const double *x, int64_t n, unsigned *out, hipStream_t st);
+hipError_t launch_unpack_lowp(const void *pk, int rows, int cols, int prow, int pcol, rom_dtype op,
+                              double scale, double *A, hipStream_t st);
+hipError_t launch_pack_lowp(const double *A, int rows, int cols, int prow, int pcol, rom_dtype op,
+                            const unsigned *amax_bits, void *pk, hipStream_t st);
 // Grouped forward run over device arrays of per-instance arguments and
 // (instance, column block) items, steps n0 .. n0+nsteps-1 for all; LDS of
 // lds_bytes (the largest instance's need).
@@ -99,6 +109,7 @@ hipError_t launch_rank1_step(const void *avs_cm, const void *asv_cm, const void 
 // Setup kernels: FP64 staging -> state-type column-major copies and packed
 // MFMA panels.
 hipError_t launch_convert(const double *src, void *dst, int64_t n, rom_dtype to, hipStream_t st);
+hipError_t launch_convert_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st);
 hipError_t launch_pack_f32(const double *A, int rows, int cols, int rowsp, int colsp, float *pk,
                            hipStream_t st);
 

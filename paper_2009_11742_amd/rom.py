@@ -16,6 +16,7 @@ from . import _lib
 from ._lib import RomConfig, check
 
 _DT = {"f64": (_lib.ROM_F64, torch.float64), "f32": (_lib.ROM_F32, torch.float32)}
+_OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": _lib.ROM_F8E4M3}
 
 
 def _stream_handle(stream):
@@ -39,10 +40,11 @@ class Rom:
     """One ROM instance on the current device.
 
     Avs (Kv x Ks), Asv (Ks x Kv) and b (Kv) are host arrays (copied).  ``state``
-    is 'f64' or 'f32'; the operators are used in the same precision.
+    is 'f64' or 'f32'; ``ops`` is the operator precision in the products
+    ('f64', 'f32', 'bf16', 'fp8'; default: the state precision).
     """
 
-    def __init__(self, Avs, Asv, b, dt, state="f32", skew_check=False, stream=None):
+    def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, stream=None):
         Avs = np.asarray(Avs)
         kv, ks = Avs.shape
         self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
@@ -50,13 +52,23 @@ class Rom:
         A = _host_f64(Avs, (kv, ks))
         B = _host_f64(Asv, (ks, kv))
         bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
-        cfg = RomConfig(kv, ks, float(dt), code, code, _lib.ROM_SKEW_CHECK if skew_check else 0)
+        self.ops = state if ops is None else ops
+        cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, _lib.ROM_SKEW_CHECK if skew_check else 0)
         ctx = C.c_void_p()
         lib = _lib.load()
         pd = C.POINTER(C.c_double)
         check(lib.rom_create(C.byref(cfg), A.ctypes.data_as(pd), B.ctypes.data_as(pd),
                              bb.ctypes.data_as(pd), _stream_handle(stream), C.byref(ctx)))
         self._ctx = ctx
+
+    def operators(self):
+        """(Avs, Asv, scale) exactly as the products use them (float64 numpy)."""
+        A = np.zeros((self.kv, self.ks), order="F")
+        B = np.zeros((self.ks, self.kv), order="F")
+        sc = C.c_double(0.0)
+        pd = C.POINTER(C.c_double)
+        check(_lib.load().rom_get_operators(self._ctx, A.ctypes.data_as(pd), B.ctypes.data_as(pd), C.byref(sc)))
+        return A, B, sc.value
 
     @property
     def handle(self):
