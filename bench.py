@@ -30,6 +30,22 @@ NSTEPS = 10000
 SEED = 0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
+# HBM bytes per launch of the rank-2 kernel at this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy
+# (factors 2.0 and 1.0); valid only for the kernel sources they were taken on.
+MEASURED_TRAFFIC = {"sources_sha1": "499ce5e67e587d758202c68c2dcdae2802fb58c0", "bytes": 5.468e6}
+KERNEL_SOURCES = ("paper_2009_11742_amd/csrc/k_rank2_f32.hip", "paper_2009_11742_amd/csrc/k_tile_f32.h",
+                  "paper_2009_11742_amd/csrc/k_common.h")
+
+
+def _measured_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return MEASURED_TRAFFIC["bytes"] if h.hexdigest() == MEASURED_TRAFFIC["sources_sha1"] else None
+
 
 def _err_cols(Xg, Xr):
     return float(np.max(np.linalg.norm(Xg - Xr, axis=0) / np.linalg.norm(Xr, axis=0)))
@@ -42,6 +58,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy"],
+                    help="rank2 (default, the reported line); the others print their own measurement line; "
+                         "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -57,6 +76,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "rank2":
+        print(json.dumps(OTHER[args.workload](args, torch, dev)))
+        return
     inst = synth.round_to(synth.make_instance(KV, KS, M, seed=SEED), "f32")
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
@@ -150,7 +172,7 @@ def main():
         "config": {"workload": "rank-2 FP32 leapfrog, Kv=Ks=256, M=256 samples, 10000 steps per run",
                    "kv": KV, "ks": KS, "M": M, "nsteps": NSTEPS, "seed": SEED},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": _measured_traffic(),
                      "kernel": "rank2_f32_mfma_kernel", "kernel_ms": float(np.mean(kern_ms)),
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
@@ -159,6 +181,109 @@ def main():
         "accuracy": errs,
     }
     print(json.dumps(out))
+
+
+def _events_time(torch, fn, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def workload_precision(args, torch, dev):
+    """K = M = 1024, 5000 steps with FP32, BF16 and FP8 operators."""
+    import synth
+    from paper_2009_11742_amd import Rom
+    K, M, N = 1024, 1024, 5000
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=0), "f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    out = {"workload": "precision: Kv=Ks=1024, M=1024, 5000 steps", "unit": "sample-steps/s", "runs": {}}
+    for ops in ("f32", "bf16", "fp8"):
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
+        V, S = rom.zeros(M, device=dev)
+
+        def run():
+            V.zero_(); S.zero_()
+            rom.run_rank2(mu, V, S, N)
+        wall, ms = _events_time(torch, run, max(1, args.steps // 2), 1)
+        ksec = float(np.mean(ms)) * 1e-3
+        peak = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}[ops]
+        tf = 4.0 * K * K * M * N / ksec / 1e12
+        out["runs"][ops] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf,
+                            "mfma_peak_tflops": peak, "frac": tf / peak}
+        rom.close()
+    return out
+
+
+def workload_grouped(args, torch, dev):
+    """64 instances, K in {128..768}, M log-uniform in [16, 512], 4000 steps."""
+    import synth
+    from paper_2009_11742_amd import GroupPlan, Rom
+    N = 4000
+    draws = synth.grouped_draws(64, base_seed=0)
+    roms, mus, Vs, Ss, flops, ss = [], [], [], [], 0.0, 0
+    for K, M, seed in draws:
+        inst = synth.round_to(synth.make_instance(K, K, M, seed=seed), "f32")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+        V, S = rom.zeros(M, device=dev)
+        roms.append(rom); Vs.append(V); Ss.append(S)
+        mus.append(torch.tensor(inst["mu"], dtype=torch.float64, device=dev))
+        flops += 4.0 * K * K * M * N
+        ss += M * N
+    plan = GroupPlan(roms, mus, Vs, Ss)
+
+    def run():
+        plan.run(N)
+    wall, ms = _events_time(torch, run, max(1, args.steps // 2), 1)
+    ksec = float(np.mean(ms)) * 1e-3
+    out = {"workload": "grouped: 64 instances, K in {128..768}, M log-uniform [16,512], 4000 steps",
+           "value": ss / ksec, "unit": "sample-steps/s", "tflops": flops / ksec / 1e12,
+           "frac_fp32_mfma": flops / ksec / 1e12 / 157.3, "ms_per_run": ksec * 1e3}
+    plan.close()
+    return out
+
+
+def workload_adjoint(args, torch, dev):
+    """K = 512, M = 256, 5000 steps: forward + checkpointed adjoint."""
+    import synth
+    from paper_2009_11742_amd import Rom
+    K, M, N = 512, 256, 5000
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=0), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device=dev)
+    wall, ms = _events_time(torch, lambda: rom.adjoint(mu, N, c), max(1, args.steps // 2), 1)
+    ksec = float(np.mean(ms)) * 1e-3
+    fwd = 4.0 * K * K * M * N
+    out = {"workload": "adjoint: Kv=Ks=512, M=256, 5000 steps, checkpoint stride ceil(sqrt(N))",
+           "value": M * N / ksec, "unit": "sample-steps/s (forward + reverse)", "ms_per_gradient": ksec * 1e3,
+           "forward_equivalent_tflops": fwd / ksec / 1e12,
+           "algorithmic_tflops": (3 * fwd + 2 * 2.0 * K * K * M * N) / ksec / 1e12}
+    rom.close()
+    return out
+
+
+def workload_copy(args, torch, dev):
+    """Plain device copy of 256 MiB (PMC FETCH_SIZE / WRITE_SIZE calibration)."""
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    wall, ms = _events_time(torch, lambda: b.copy_(a), 3, 1)
+    return {"workload": "copy", "bytes_read": n * 4, "bytes_written": n * 4, "ms": float(np.mean(ms)),
+            "GB_per_s": 2 * n * 4 / (float(np.mean(ms)) * 1e-3) / 1e9}
+
+
+OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
+         "copy": workload_copy}
 
 
 if __name__ == "__main__":
