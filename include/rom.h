@@ -85,7 +85,11 @@ typedef struct {
     int32_t kv;             /* velocity reduced size Kv >= 1                   */
     int32_t ks;             /* stress reduced size Ks >= 1                     */
     double dt;              /* time step > 0 (the value used, as given)        */
-    rom_dtype op_type;      /* operator precision in the products             */
+    rom_dtype op_type;      /* operator precision in the products: F64 with F64
+                               states, F32 with F32 states, BF16 / F8E4M3 with
+                               F32 states (low-precision products) or F64
+                               states (FP64 integration of the rounded
+                               operators, the long-horizon reference)        */
     rom_dtype state_type;   /* ROM_F64 or ROM_F32: state and I/O precision    */
     uint32_t flags;         /* ROM_SKEW_CHECK | ...                            */
 } rom_config;
@@ -123,6 +127,18 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
  * implementation.  Synchronises the device.
  */
 rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *scale);
+
+/*
+ * Modified discrete energy of the leapfrog per sample, in FP64:
+ *   E_m = |v_m|^2 + |s_m|^2 + dt v_m^T Avs s_m     (Avs as the products use it)
+ * V, S dev states of state type (Kv x M, Ks x M); E dev, M FP64 (set).  For
+ * a skew pair the unforced leapfrog conserves E exactly, and E is positive
+ * definite when dt * sigma_max(Avs) < 2: its drift over a long run measures
+ * the arithmetic, its size bounds the state (the stability check of the
+ * low-precision runs, used with an FP64-state context of the same rounded
+ * operators as the long-horizon reference).
+ */
+rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, double *E, void *stream);
 
 /* Release every device buffer owned by the context.  NULL is accepted. */
 rom_status rom_destroy(rom_ctx *ctx);

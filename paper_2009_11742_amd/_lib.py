@@ -22,7 +22,7 @@ ROM_SKEW_CHECK = 1
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
-           "rom_get_operators", "rom_last_error", "rom_version"]
+           "rom_get_operators", "rom_energy", "rom_last_error", "rom_version"]
 
 
 class RomConfig(C.Structure):
@@ -82,6 +82,8 @@ def load():
         lib.rom_group_destroy.argtypes = [_vp]
         lib.rom_get_operators.restype = C.c_int
         lib.rom_get_operators.argtypes = [_vp, _pd, _pd, _pd]
+        lib.rom_energy.restype = C.c_int
+        lib.rom_energy.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
         lib.rom_last_error.restype = C.c_char_p
         lib.rom_last_error.argtypes = []
         lib.rom_version.restype = C.c_char_p

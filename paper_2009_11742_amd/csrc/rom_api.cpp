@@ -83,6 +83,7 @@ void free_ctx(rom_ctx *c) {
     hfree(c->asv_pk);
     hfree(c->avs_lp);
     hfree(c->asv_lp);
+    hfree(c->avs_e64);
     hfree(c->b);
     hfree(c->asvT_pk);
     hfree(c->avsT_pk);
@@ -115,9 +116,9 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
         cfg->op_type != ROM_F8E4M3)
         return fail(ROM_E_ARG, "rom_create: unknown op_type");
     const bool lowp = cfg->op_type == ROM_BF16 || cfg->op_type == ROM_F8E4M3;
-    if (lowp ? cfg->state_type != ROM_F32 : cfg->op_type != cfg->state_type)
+    if (!lowp && cfg->op_type != cfg->state_type)
         return fail(ROM_E_UNSUPPORTED, "rom_create: supported (op, state) pairs are (F64, F64), "
-                                       "(F32, F32), (BF16, F32) and (F8E4M3, F32)");
+                                       "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
     if (cfg->flags & ~(uint32_t)ROM_SKEW_CHECK) return fail(ROM_E_ARG, "rom_create: unknown flag bits");
     const size_t nA = (size_t)kv * ks;
     if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
@@ -173,8 +174,10 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     CHK(hipMalloc(&c->b, (size_t)c->kvp * ts), "rom_create: device allocation");
     CHK(hipMalloc(&c->status, sizeof(int) * 4), "rom_create: device allocation");
     CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
-    CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), "rom_create: convert");
-    CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), "rom_create: convert");
+    if (!(lowp && c->state_type == ROM_F64)) {
+        CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), "rom_create: convert");
+        CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), "rom_create: convert");
+    }
     CHK(rom::launch_convert(sb, c->b, c->kvp, c->state_type, st), "rom_create: convert");
     if (lowp) {
         // BF16: round each operator (via FP32) to BF16; FP8: one scale
@@ -198,6 +201,14 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
             memcpy(&am, &bits, sizeof(am));
             c->op_scale = am > 0.f ? am / 448.0f : 1.0f;
             CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
+        }
+        if (c->state_type == ROM_F64) {
+            // FP64 states with rounded operators (the long-horizon reference of
+            // the rounded model): the FP64 path runs on the dequantised values
+            CHK(rom::launch_unpack_lowp(c->avs_lp, kv, ks, c->kvp, c->ksp, c->op_type, (double)c->op_scale,
+                                        static_cast<double *>(c->avs_cm), st), "rom_create: unpack");
+            CHK(rom::launch_unpack_lowp(c->asv_lp, ks, kv, c->ksp, c->kvp, c->op_type, (double)c->op_scale,
+                                        static_cast<double *>(c->asv_cm), st), "rom_create: unpack");
         }
     } else if (c->state_type == ROM_F32) {
         CHK(hipMalloc(&c->avs_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
@@ -238,6 +249,29 @@ rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *sca
     hfree(d);
     if (e != hipSuccess) return hip_fail(e, "rom_get_operators");
     if (scale) *scale = ctx->op_type == ROM_F8E4M3 ? (double)ctx->op_scale : 1.0;
+    return ROM_OK;
+}
+
+rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, double *E, void *stream) {
+    if (!ctx || !V || !S || !E) return fail(ROM_E_ARG, "rom_energy: NULL argument");
+    if (M < 1) return fail(ROM_E_ARG, "rom_energy: M must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (!ctx->avs_e64) {
+        const size_t nA = (size_t)ctx->kv * ctx->ks;
+        e = hipMalloc(&ctx->avs_e64, nA * sizeof(double));
+        if (e != hipSuccess) { ctx->avs_e64 = nullptr; return fail(ROM_E_NOMEM, "rom_energy: allocation failed"); }
+        if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3))
+            e = rom::launch_unpack_lowp(ctx->avs_lp, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, ctx->op_type,
+                                        (double)ctx->op_scale, ctx->avs_e64, st);
+        else if (ctx->state_type == ROM_F32)
+            e = rom::launch_convert_f32_to_f64(static_cast<const float *>(ctx->avs_cm), ctx->avs_e64, (int64_t)nA, st);
+        else
+            e = hipMemcpyAsync(ctx->avs_e64, ctx->avs_cm, nA * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "rom_energy: prepare");
+    }
+    e = rom::launch_energy(ctx->avs_e64, ctx->kv, ctx->ks, ctx->dt, ctx->state_type, V, S, M, E, st);
+    if (e != hipSuccess) return hip_fail(e, "rom_energy: launch");
     return ROM_OK;
 }
 
@@ -287,7 +321,7 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if (ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) {
+    if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) && ctx->state_type == ROM_F32) {
         if (rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
         a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;

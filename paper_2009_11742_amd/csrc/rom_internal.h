@@ -48,6 +48,9 @@ struct rom_ctx {
     // Adjoint workspace (checkpoints, segment traces), grown on demand.
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // FP64 column-major copy of Avs exactly as the products use it (for the
+    // energy), built on first use.
+    double *avs_e64 = nullptr;
     // Device status word (in-kernel errors).
     int *status = nullptr;
 };
@@ -94,6 +97,8 @@ hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
                                 double alpha, double *dA, hipStream_t st);
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_energy(const double *A64, int kv, int ks, double dt, rom_dtype st_type, const void *V,
+                         const void *S, int M, double *E, hipStream_t st);
 // Pack a column-major FP32 matrix (rows x cols, or its transpose when
 // `transpose`) into the 4x4x1 MFMA panel layout with padded sizes.
 hipError_t launch_pack_f32_from_f32(const float *A, int rows, int cols, bool transpose, int prow,

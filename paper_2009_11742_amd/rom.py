@@ -132,6 +132,15 @@ class Rom:
         check(_lib.load().rom_run_rank2(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
                                         _ptr(c), _ptr(J), _ptr(y), _stream_handle(stream)))
 
+    def energy(self, V, S, stream=None):
+        """Per-sample modified energy |v|^2 + |s|^2 + dt v^T Avs s (float64 tensor)."""
+        M = int(V.shape[0])
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        E = torch.zeros(M, dtype=torch.float64, device=V.device)
+        check(_lib.load().rom_energy(self._ctx, M, _ptr(V), _ptr(S), _ptr(E), _stream_handle(stream)))
+        return E
+
     def adjoint(self, mu, nsteps, c, V0=None, S0=None, stride=0, grads=("dAvs", "dAsv", "dmu"),
                 stream=None):
         """Probe QoI J_m = sum_n dt (c^T V_m^(n+1))^2 and its gradients.

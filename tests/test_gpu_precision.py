@@ -130,3 +130,57 @@ def test_precision_workload_k1024_m1024():
               % (ops, e_same, e_orig, q_same, q_orig))
         bar = 1e-5 if ops == "f32" else SAME_INPUT_BAR
         assert e_same <= bar and q_same <= bar
+
+
+@pytest.mark.parametrize("ops", ["bf16", "fp8"])
+def test_fp64_state_rounded_operators_stability(ops):
+    """Long-horizon reference of the rounded model: FP64 states with the
+    BF16 / FP8 operators.  Parity with the oracle on the same operators
+    (FP64 bar), exact energy conservation after the source has decayed, and
+    the FP32-state low-precision run's energy drift against it."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(128, 128, 4, seed=17), "f32")
+    r64 = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64", ops=ops)
+    r32 = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
+    A, B, _ = r64.operators()
+    A32, B32, _ = r32.operators()
+    assert np.array_equal(A, A32) and np.array_equal(B, B32)
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = r64.zeros(4)
+    r64.run_rank2(mu, V, S, 300)
+    torch.cuda.synchronize()
+    ref = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"], 300)
+    Vg = V.cpu().numpy().T
+    assert _relcol(Vg, ref["V"]) <= 1e-12 and _relcol(S.cpu().numpy().T, ref["S"]) <= 1e-12
+    E0 = r64.energy(V, S)
+    Eo = oracle.energy(A, inst["dt"], ref["V"], ref["S"])
+    assert np.allclose(E0.cpu().numpy(), Eo, rtol=1e-13, atol=0)
+    V32, S32 = r32.zeros(4)
+    r32.run_rank2(mu, V32, S32, 300)
+    r64.run_rank2(mu, V, S, 20000, n0=300)
+    r32.run_rank2(mu, V32, S32, 20000, n0=300)
+    torch.cuda.synchronize()
+    E1 = r64.energy(V, S).cpu().numpy()
+    E32 = r32.energy(V32, S32).cpu().numpy()
+    drift64 = float(np.max(np.abs(E1 - E0.cpu().numpy()) / E0.cpu().numpy()))
+    drift32 = float(np.max(np.abs(E32 - E1) / E1))
+    print("%s: FP64-state energy drift over 2e4 steps %.2e; FP32-state vs FP64-state energy %.2e" % (ops, drift64, drift32))
+    assert drift64 <= 1e-10
+    assert drift32 <= 1e-3
+    r64.close(); r32.close()
+
+
+def test_energy_kernel_matches_oracle():
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(70, 45, 6, seed=3, skew=False), "f32")
+    rng = np.random.default_rng(0)
+    V0 = rng.standard_normal((70, 6)).astype(np.float32).astype(np.float64)
+    S0 = rng.standard_normal((45, 6)).astype(np.float32).astype(np.float64)
+    ref = oracle.energy(inst["Avs"], inst["dt"], V0, S0)
+    for state, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state)
+        V = torch.tensor(np.ascontiguousarray(V0.T), dtype=tdt, device="cuda")
+        S = torch.tensor(np.ascontiguousarray(S0.T), dtype=tdt, device="cuda")
+        E = rom.energy(V, S).cpu().numpy()
+        assert np.allclose(E, ref, rtol=1e-13, atol=0)
+        rom.close()
