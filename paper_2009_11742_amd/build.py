@@ -24,6 +24,9 @@ ARCH = "gfx950"
 CFLAGS = [
     "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in VGPRs: the FP32 kernel's FP64 folds then read the
+    # chains directly instead of copying them out of AGPRs first
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function",
 ]
 

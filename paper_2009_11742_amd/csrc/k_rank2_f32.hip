@@ -39,14 +39,15 @@ enum Mode { kForward = 0, kAdjoint = 1 };
 // One half-step of one field: wave w owns row tiles w, w + 4, ...  Ends
 // with a barrier (the other half-step reads every row of this field).
 template <bool FORCED>
-__device__ __forceinline__ void half_step(const Field &f, int lane, int w, const float *bl,
-                                          const float *cl, float uh, float ul, float dtf,
+__device__ __forceinline__ void half_step(const Field &f, f4 (&a0)[kQ], f4 (&a1)[kQ], Stream &s,
+                                          const Field &fv, const Field &fs, int lane, int w,
+                                          const float *bl, const float *cl, double u, double dt,
                                           double &ypart) {
     const int j = lane & 3;
     for (int t = w; t < f.T; t += kWaves) {
-        f4 H, L;
-        tile_product(f.pk, t, f.kp, 0, f.kp / kChunk, f.X + j * f.ldx, lane, H, L);
-        finish_tile<FORCED>(f, t, H, L, lane, bl, cl, uh, ul, dtf, ypart);
+        double acc[4];
+        tile_product(f, f.X + j * f.ldx, a0, a1, s, fv, fs, w, lane, acc);
+        finish_tile<FORCED>(f, t, acc, lane, bl, cl, u, dt, ypart);
     }
     __syncthreads();
 }
@@ -92,7 +93,8 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     float *bl = reinterpret_cast<float *>(yp + kWaves * NB);    // source, kvp
     float *cl = bl + kvp;                                         // probe, kvp (0 if none)
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform
     const float *Vin = static_cast<const float *>(a.V);
     const float *Sin = static_cast<const float *>(a.S);
     const float *bv = static_cast<const float *>(a.b);
@@ -120,11 +122,13 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     const int m = col0 + j;
     const bool mok = m < a.M;
     const double muj = mok ? a.mu[m] : 1.0;
-    const float dtf = (float)a.dt;
     const bool probe = prb != nullptr;
     double Jacc = 0.0;
-    const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, Sh, lds_, Vh, Vl, ldv};
-    const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, Vh, ldv, Sh, Sl, lds_};
+    const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, ksp / kChunk, Sh, lds_, Vh, Vl, ldv};
+    const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, kvp / kChunk, Vh, ldv, Sh, Sl, lds_};
+    f4 a0[kQ], a1[kQ];
+    Stream str;
+    stream_start(str, a0, a1, fv, fs, w, lane);
     __syncthreads();
     if (MODE == kForward && a.vtr) {
         store_cols(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
@@ -143,12 +147,10 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
             // q^{n+1}, paired with V^{n+1} in the dAsv product
             store_cols(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
         }
-        const float uh = (float)u64;
-        const float ul = (float)(u64 - (double)uh);
 
         // ---- first half-step: V += dt (Avs S + b u^T)   |   P += dt (Asv^T Q + 2 y c)
         double ypart = 0.0;
-        half_step<true>(fv, lane, w, bl, cl, uh, ul, dtf, ypart);
+        half_step<true>(fv, a0, a1, str, fv, fs, lane, w, bl, cl, u64, a.dt, ypart);
         if (probe) {
             // sum over the 16 lanes that share column j (lane bits 2..5)
             for (int off = 4; off < 64; off <<= 1) ypart += __shfl_xor(ypart, off, 64);
@@ -159,7 +161,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
         // ---- second half-step: S += dt Asv V   |   Q += dt Avs^T P
         // (its barrier also publishes yp before it is read below)
         double dummy = 0.0;
-        half_step<false>(fs, lane, w, bl, cl, 0.f, 0.f, dtf, dummy);
+        half_step<false>(fs, a0, a1, str, fv, fs, lane, w, bl, cl, 0.0, a.dt, dummy);
         if (probe && tid < NB && col0 + tid < a.M) {
             const double yv = wave_sum(yp, tid);
             if (MODE == kForward) {
@@ -206,10 +208,7 @@ void grouped_f32_mfma_kernel(const Rank2Args *__restrict__ inst, const int2 *__r
 
 }  // namespace
 
-size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp) {
-    return sizeof(float) * (size_t)NB * 2 * ((kvp + 4) + (ksp + 4)) + sizeof(double) * kWaves * NB +
-           sizeof(float) * 2 * (size_t)kvp;
-}
+size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp) { return state_lds_bytes(kvp, ksp); }
 
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st) {
     const int blocks = (a.M + NB - 1) / NB;

@@ -1,7 +1,14 @@
 // Device building blocks of the FP32 column-block steppers (forward rank-2
 // and its adjoint): packed-operator x LDS-state tile products on
-// v_mfma_f32_4x4x1f32 with compensated accumulation, and the double-float
-// tile update.
+// v_mfma_f32_4x4x1f32, FP32 chains folded into FP64 tile sums, and the FP64
+// tile update of the (hi, lo) state pair.
+//
+// Cost model (measured on gfx950, one wave per SIMD): a 4x4x1 MFMA issues
+// about every 4.6 ns, and VALU, LDS and global-load instructions of the same
+// SIMD add their own time rather than hiding under the MFMAs.  The product
+// loop is therefore built to issue as few non-MFMA instructions per MFMA as
+// possible: one float4 operator load and one float4 state read per 4 MFMAs,
+// and 2 VALU ops per chain value folded.
 #pragma once
 
 #include "k_common.h"
@@ -12,7 +19,7 @@ namespace tile {
 
 using dev::f4;
 constexpr int NB = kColBlock;     // 4 sample columns per workgroup
-constexpr int kChunk = 32;        // k terms per compensated chunk (8 float4 loads)
+constexpr int kChunk = 32;        // k terms per operator chunk (8 float4 loads)
 constexpr int kQ = kChunk / 4;
 
 // Load the kQ float4 operator fragments of chunk `ch` of a panel tile.
@@ -29,6 +36,8 @@ __device__ __forceinline__ void lds_chunk(f4 (&dst)[kQ], const float *xcol, int 
     for (int q = 0; q < kQ; ++q) dst[q] = src[q];
 }
 
+// Exact fold of an FP32 partial sum into a (hi, lo) pair (two-sum); used by
+// the low-precision products.
 __device__ __forceinline__ void fold(f4 &hi, f4 &lo, const f4 &acc) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -39,85 +48,182 @@ __device__ __forceinline__ void fold(f4 &hi, f4 &lo, const f4 &acc) {
     }
 }
 
-// Product of one chunk, as two independent MFMA chains (even and odd
-// float4 groups) so consecutive MFMAs never wait on each other's result;
-// each chain's partial sum (16 terms) is folded into (hi, lo) exactly.
-__device__ __forceinline__ void mma_chunk(const f4 (&a)[kQ], const f4 (&x)[kQ], f4 &hi, f4 &lo) {
-    f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < kQ; q += 2) {
-        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q].x, x[q].x, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q + 1].x, x[q + 1].x, c1, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q].y, x[q].y, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q + 1].y, x[q + 1].y, c1, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q].z, x[q].z, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q + 1].z, x[q + 1].z, c1, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q].w, x[q].w, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a[q + 1].w, x[q + 1].w, c1, 0, 0, 0);
-    }
-    fold(hi, lo, c0);
-    fold(hi, lo, c1);
+__device__ __forceinline__ f4 mfma4(float a, float x, f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, x, c, 0, 0, 0);
 }
 
-// Compensated 64 x 4 tile of  P[t] * X  where P is a packed operator panel
-// (pk[t][k/4][lane][k%4] = P[64 t + lane][k]) and X the 4 LDS-resident
-// columns (this lane's column at xcol).  Returns per lane the rows
-// 64 t + 4 (lane / 4) + r, r = 0..3, of column lane % 4 as (H, L).
-// Only chunks [cb, ce) of the reduction are summed (an even count).
-// Operator fragments (from L2) and state values (from LDS) are both fetched
-// one chunk ahead of use with branch-free ping-pong buffers, so every wait
-// covers an access issued a full chunk earlier.
-__device__ __forceinline__ void tile_product(const f4 *__restrict__ pk, int t, int kp, int cb,
-                                             int ce, const float *xcol, int lane, f4 &H, f4 &L) {
-    const f4 *ap = pk + (size_t)t * (size_t)(kp / 4) * 64 + lane + (size_t)cb * kQ * 64;
-    xcol += cb * kChunk;
-    f4 hi = {0.f, 0.f, 0.f, 0.f}, lo = {0.f, 0.f, 0.f, 0.f};
-    const int nch = ce - cb;
-    f4 a0[kQ], a1[kQ], x0[kQ], x1[kQ];
-    // sched_barrier(0) keeps each prefetch batch where it is written: the
-    // scheduler would otherwise sink the loads next to their first use.
-    load_chunk(a0, ap, 0);
-    load_chunk(a1, ap, 1);
-    lds_chunk(x0, xcol, 0);
-    __builtin_amdgcn_sched_barrier(0);
-    for (int ch = 0; ch < nch; ch += 2) {
-        lds_chunk(x1, xcol, ch + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk(a0, x0, hi, lo);
-        __builtin_amdgcn_sched_barrier(0);
-        // refill with chunk ch+2 (or re-read the last chunk: in bounds, unused)
-        const int n2 = min(ch + 2, nch - 1);
-        load_chunk(a0, ap, n2);
-        lds_chunk(x0, xcol, n2);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk(a1, x1, hi, lo);
-        __builtin_amdgcn_sched_barrier(0);
-        load_chunk(a1, ap, min(ch + 3, nch - 1));
+// The FP32 products accumulate in two MFMA chains per chunk pair (c0: even
+// float4 groups, c1: odd ones; 32 terms each), and every finished chain is
+// folded into FP64 tile sums with one convert and one FP64 add per value.
+// Each chain rounds like a 32-term sequential FP32 sum; the FP64 sums add
+// nothing measurable to that.  The MFMAs alternate between the two chains
+// (a dependent 4x4x1 MFMA waits about twice its issue interval), and a
+// sched_barrier after every pair pins that order, which the scheduler would
+// otherwise trade for back-to-back dependent MFMAs.
+
+// First chunk of a pair: start fresh chains (c0, c1) and fold the previous
+// pair's chains (p0, p1) into acc, one fold step between two MFMA pairs,
+// from the third pair on (the previous chains have left the pipeline).
+__device__ __forceinline__ void mma_first(const f4 (&a)[kQ], const f4 (&x)[kQ], f4 &c0, f4 &c1,
+                                          const f4 &p0, const f4 &p1, double (&acc)[4]) {
+    c0 = f4{0.f, 0.f, 0.f, 0.f};
+    c1 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {          // pair i: component i % 4 of groups 2 (i / 4), +1
+        const int q = 2 * (i >> 2), e = i & 3;
+        c0 = mfma4(a[q][e], x[q][e], c0);
+        c1 = mfma4(a[q + 1][e], x[q + 1][e], c1);
+        if (i >= 2 && i < 10) {
+            const int k = i - 2;            // fold step k: element k % 4 of p0 (k < 4) or p1
+            acc[k & 3] += (double)(k < 4 ? p0[k & 3] : p1[k & 3]);
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
-    H = hi;
-    L = lo;
+}
+
+// Second chunk of a pair: continue the chains.
+__device__ __forceinline__ void mma_next(const f4 (&a)[kQ], const f4 (&x)[kQ], f4 &c0, f4 &c1) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = 2 * (i >> 2), e = i & 3;
+        c0 = mfma4(a[q][e], x[q][e], c0);
+        c1 = mfma4(a[q + 1][e], x[q + 1][e], c1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ __forceinline__ void fold64(double (&acc)[4], const f4 &p0, const f4 &p1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        acc[r] += (double)p0[r];
+        acc[r] += (double)p1[r];
+    }
 }
 
 constexpr int kWaves = 4;                 // one wave per SIMD
 constexpr int kThreads = kWaves * 64;
 
+// LDS of the states (hi, lo), probe partials and source / probe vectors.
+__host__ __device__ inline size_t state_lds_bytes(int kvp, int ksp) {
+    return sizeof(float) * (size_t)NB * 2 * ((kvp + 4) + (ksp + 4)) + sizeof(double) * kWaves * NB +
+           sizeof(float) * 2 * (size_t)kvp;
+}
+
 struct Field {
     const f4 *pk;      // packed operator panel of this half-step
     int T;             // row tiles of the updated field
     int kp;            // padded reduction length
+    int nch;           // reduction chunks per tile (kp / kChunk, even)
     const float *X;    // LDS: the other field's columns (hi words), ld ldx
     int ldx;
     float *Yh, *Yl;    // LDS: the updated field (hi, lo), ld ldy
     int ldy;
 };
 
-// Finish one 64 x 4 tile: (Yh, Yl) += dt * ((H + L) + forcing).  With
-// FORCED the rows also accumulate the probe partial c^T V.
+// Uniform address of chunk c of row tile t of a packed panel (add the lane
+// at the load).
+__device__ __forceinline__ const f4 *chunk_ptr(const f4 *pk, int kp, int t, int c) {
+    return pk + (size_t)t * kp * 16 + (size_t)c * (kQ * 64);
+}
+
+// Per-wave operator stream: the chunks of the wave's tiles in the order the
+// wave uses them (V-update tiles, S-update tiles, the next step's V-update
+// tiles, ...), consumed in pairs.  The operators do not change during a
+// run, so the stream runs ahead across tile and half-step boundaries and
+// the workgroup barriers never drain it.  `p` (wave-uniform) addresses the
+// next pair to load, (f, t, c) names it.
+struct Stream {
+    const f4 *p;
+    int f, t, c;
+};
+
+// Value select (the operands are loaded first).  A conditional on lvalues
+// selects addresses instead, which keeps the Field structs out of
+// registers and in private memory.
+template <class T>
+__device__ __forceinline__ T sel(bool c, T a, T b) {
+    return c ? a : b;
+}
+
+// Branch-free (scalar selects only), so the product loop stays one block.
+// A wave with no tile in the other field keeps cycling through its own.
+__device__ __forceinline__ void advance(Stream &s, const Field &fv, const Field &fs, int w) {
+    const bool onS = s.f != 0;
+    const int c = s.c + 2, t = s.t + kWaves;
+    const bool tile_end = c >= sel(onS, fs.nch, fv.nch);
+    const bool field_end = tile_end && t >= sel(onS, fs.T, fv.T);
+    const bool other = sel(onS, w < fv.T, w < fs.T);
+    const bool nS = (field_end && other) ? !onS : onS;
+    s.f = nS ? 1 : 0;
+    s.t = field_end ? w : (tile_end ? t : s.t);
+    s.c = tile_end ? 0 : c;
+    s.p = chunk_ptr(sel(nS, fs.pk, fv.pk), sel(nS, fs.kp, fv.kp), s.t, s.c);
+}
+
+// Point the stream at wave w's first pair and load it into (a0, a1).  A
+// wave with no tile leaves them untouched.
+__device__ __forceinline__ void stream_start(Stream &s, f4 (&a0)[kQ], f4 (&a1)[kQ], const Field &fv,
+                                             const Field &fs, int w, int lane) {
+    const bool sv = w < fv.T, ss = w < fs.T;
+    s.f = sv ? 0 : 1;
+    s.t = w;
+    s.c = 0;
+    s.p = chunk_ptr(sel(sv, fv.pk, fs.pk), sel(sv, fv.kp, fs.kp), s.t, s.c);
+    if (!sv && !ss) return;
+    // keep every a0 load ahead of every a1 load, as in the product loop, so
+    // the waits there can count on that order on every path
+    __builtin_amdgcn_sched_barrier(0);
+    load_chunk(a0, s.p + lane, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_chunk(a1, s.p + lane, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    advance(s, fv, fs, w);
+}
+
+// 64 x 4 tile product  P[t] * X  of field F (X: this lane's LDS column
+// xcol), summed in FP64 into acc.  The operator chunks come from the
+// stream, whose current pair sits in (a0, a1); each pair used is replaced
+// by the stream's next one.  State values are fetched one chunk ahead with
+// ping-pong buffers.  Per lane acc[r] is row 64 t + 4 (lane / 4) + r of
+// column lane % 4.
+__device__ __forceinline__ void tile_product(const Field &F, const float *xcol, f4 (&a0)[kQ],
+                                             f4 (&a1)[kQ], Stream &s, const Field &fv, const Field &fs,
+                                             int w, int lane, double (&acc)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+    f4 p0 = {0.f, 0.f, 0.f, 0.f}, p1 = {0.f, 0.f, 0.f, 0.f};
+    f4 x0[kQ], x1[kQ];
+    // sched_barrier(0) keeps each prefetch batch where it is written: the
+    // scheduler would otherwise sink the loads next to their first use.
+    lds_chunk(x0, xcol, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int c = 0; c < F.nch; c += 2) {
+        lds_chunk(x1, xcol, c + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        f4 c0, c1;
+        mma_first(a0, x0, c0, c1, p0, p1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(a0, s.p + lane, 0);
+        lds_chunk(x0, xcol, min(c + 2, F.nch - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mma_next(a1, x1, c0, c1);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(a1, s.p + lane, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        advance(s, fv, fs, w);
+        p0 = c0;
+        p1 = c1;
+    }
+    fold64(acc, p0, p1);
+}
+
+// Finish one 64 x 4 tile in FP64: y = (Yh + Yl) + dt (acc + b u), stored
+// back as the (hi, lo) pair.  With FORCED the rows also accumulate the
+// probe partial c^T V.
 template <bool FORCED>
-__device__ __forceinline__ void finish_tile(const Field &f, int t, f4 H, f4 L, int lane,
-                                            const float *bl, const float *cl, float uh, float ul,
-                                            float dtf, double &ypart) {
+__device__ __forceinline__ void finish_tile(const Field &f, int t, const double (&acc)[4], int lane,
+                                            const float *bl, const float *cl, double u, double dt,
+                                            double &ypart) {
     const int j = lane & 3;
     const int i0 = t * kTileRows + 4 * (lane >> 2);
     f4 yh = *(f4 *)(f.Yh + j * f.ldy + i0);
@@ -129,16 +235,13 @@ __device__ __forceinline__ void finish_tile(const Field &f, int t, f4 H, f4 L, i
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        float F = 0.f, Fe = 0.f;
-        if (FORCED) {
-            F = bb[r] * uh;
-            Fe = fmaf(bb[r], uh, -F) + bb[r] * ul;
-        }
-        float h = yh[r], l = yl[r];
-        dev::comp_update(h, l, H[r], L[r], F, Fe, dtf);
+        double inc = acc[r];
+        if (FORCED) inc = fma((double)bb[r], u, inc);
+        const double y = fma(dt, inc, (double)yh[r] + (double)yl[r]);
+        const float h = (float)y;
         yh[r] = h;
-        yl[r] = l;
-        if (FORCED) ypart += (double)cc[r] * ((double)h + (double)l);
+        yl[r] = (float)(y - (double)h);
+        if (FORCED) ypart += (double)cc[r] * y;
     }
     *(f4 *)(f.Yh + j * f.ldy + i0) = yh;
     *(f4 *)(f.Yl + j * f.ldy + i0) = yl;
