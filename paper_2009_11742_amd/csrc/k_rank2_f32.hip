@@ -39,14 +39,15 @@ enum Mode { kForward = 0, kAdjoint = 1 };
 // One half-step of one field: wave w owns row tiles w, w + 4, ...  Ends
 // with a barrier (the other half-step reads every row of this field).
 template <bool FORCED>
-__device__ __forceinline__ void half_step(const Field &f, f4 (&a0)[kQ], f4 (&a1)[kQ], Stream &s,
+__device__ __forceinline__ void half_step(const Field &f, const f4 (&res)[2 * kResPairs][kQ],
+                                          f4 (&a0)[kQ], f4 (&a1)[kQ], Stream &s,
                                           const Field &fv, const Field &fs, int lane, int w,
                                           const float *bl, const float *cl, double u, double dt,
                                           double &ypart) {
     const int j = lane & 3;
     for (int t = w; t < f.T; t += kWaves) {
         double acc[4];
-        tile_product(f, f.X + j * f.ldx, a0, a1, s, fv, fs, w, lane, acc);
+        tile_product(f, f.X + j * f.ldx, res, t == w ? f.rp : 0, a0, a1, s, fv, fs, w, lane, acc);
         finish_tile<FORCED>(f, t, acc, lane, bl, cl, u, dt, ypart);
     }
     __syncthreads();
@@ -124,8 +125,13 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     const double muj = mok ? a.mu[m] : 1.0;
     const bool probe = prb != nullptr;
     double Jacc = 0.0;
-    const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, ksp / kChunk, Sh, lds_, Vh, Vl, ldv};
-    const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, kvp / kChunk, Vh, ldv, Sh, Sl, lds_};
+    const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, ksp / kChunk,
+                      resident_pairs(ksp / kChunk), Sh, lds_, Vh, Vl, ldv};
+    const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, kvp / kChunk,
+                      resident_pairs(kvp / kChunk), Vh, ldv, Sh, Sl, lds_};
+    f4 resv[2 * kResPairs][kQ], ress[2 * kResPairs][kQ];
+    load_resident(resv, fv, w, lane);
+    load_resident(ress, fs, w, lane);
     f4 a0[kQ], a1[kQ];
     Stream str;
     stream_start(str, a0, a1, fv, fs, w, lane);
@@ -150,7 +156,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
 
         // ---- first half-step: V += dt (Avs S + b u^T)   |   P += dt (Asv^T Q + 2 y c)
         double ypart = 0.0;
-        half_step<true>(fv, a0, a1, str, fv, fs, lane, w, bl, cl, u64, a.dt, ypart);
+        half_step<true>(fv, resv, a0, a1, str, fv, fs, lane, w, bl, cl, u64, a.dt, ypart);
         if (probe) {
             // sum over the 16 lanes that share column j (lane bits 2..5)
             for (int off = 4; off < 64; off <<= 1) ypart += __shfl_xor(ypart, off, 64);
@@ -161,7 +167,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
         // ---- second half-step: S += dt Asv V   |   Q += dt Avs^T P
         // (its barrier also publishes yp before it is read below)
         double dummy = 0.0;
-        half_step<false>(fs, a0, a1, str, fv, fs, lane, w, bl, cl, 0.0, a.dt, dummy);
+        half_step<false>(fs, ress, a0, a1, str, fv, fs, lane, w, bl, cl, 0.0, a.dt, dummy);
         if (probe && tid < NB && col0 + tid < a.M) {
             const double yv = wave_sum(yp, tid);
             if (MODE == kForward) {

@@ -109,11 +109,24 @@ __host__ __device__ inline size_t state_lds_bytes(int kvp, int ksp) {
            sizeof(float) * 2 * (size_t)kvp;
 }
 
+// Register-resident operator: each wave keeps the first kResPairs chunk
+// pairs of its first row tile of each field in registers for the whole run
+// (8 chunks, 256 registers per lane, which one wave per SIMD leaves free),
+// so those chunks cost no load at all; the rest is streamed.  A field keeps
+// at least one streamed pair per tile.
+constexpr int kResPairs = 2;
+
+__host__ __device__ inline int resident_pairs(int nch) {
+    const int r = nch / 2 - 1;
+    return r < kResPairs ? r : kResPairs;
+}
+
 struct Field {
     const f4 *pk;      // packed operator panel of this half-step
     int T;             // row tiles of the updated field
     int kp;            // padded reduction length
     int nch;           // reduction chunks per tile (kp / kChunk, even)
+    int rp;            // resident pairs of the wave's first tile (resident_pairs(nch))
     const float *X;    // LDS: the other field's columns (hi words), ld ldx
     int ldx;
     float *Yh, *Yl;    // LDS: the updated field (hi, lo), ld ldy
@@ -147,6 +160,8 @@ __device__ __forceinline__ T sel(bool c, T a, T b) {
 
 // Branch-free (scalar selects only), so the product loop stays one block.
 // A wave with no tile in the other field keeps cycling through its own.
+// The resident pairs of the wave's first tile (t == w, reached exactly at a
+// field start) are skipped.
 __device__ __forceinline__ void advance(Stream &s, const Field &fv, const Field &fs, int w) {
     const bool onS = s.f != 0;
     const int c = s.c + 2, t = s.t + kWaves;
@@ -156,7 +171,7 @@ __device__ __forceinline__ void advance(Stream &s, const Field &fv, const Field 
     const bool nS = (field_end && other) ? !onS : onS;
     s.f = nS ? 1 : 0;
     s.t = field_end ? w : (tile_end ? t : s.t);
-    s.c = tile_end ? 0 : c;
+    s.c = field_end ? 2 * sel(nS, fs.rp, fv.rp) : (tile_end ? 0 : c);
     s.p = chunk_ptr(sel(nS, fs.pk, fv.pk), sel(nS, fs.kp, fv.kp), s.t, s.c);
 }
 
@@ -167,7 +182,7 @@ __device__ __forceinline__ void stream_start(Stream &s, f4 (&a0)[kQ], f4 (&a1)[k
     const bool sv = w < fv.T, ss = w < fs.T;
     s.f = sv ? 0 : 1;
     s.t = w;
-    s.c = 0;
+    s.c = 2 * sel(sv, fv.rp, fs.rp);
     s.p = chunk_ptr(sel(sv, fv.pk, fs.pk), sel(sv, fv.kp, fs.kp), s.t, s.c);
     if (!sv && !ss) return;
     // keep every a0 load ahead of every a1 load, as in the product loop, so
@@ -180,13 +195,24 @@ __device__ __forceinline__ void stream_start(Stream &s, f4 (&a0)[kQ], f4 (&a1)[k
     advance(s, fv, fs, w);
 }
 
+// Load the resident pairs of field F (wave w's first tile) into res.
+__device__ __forceinline__ void load_resident(f4 (&res)[2 * kResPairs][kQ], const Field &F, int w,
+                                              int lane) {
+    if (w >= F.T) return;
+    const f4 *ap = chunk_ptr(F.pk, F.kp, w, 0) + lane;
+#pragma unroll
+    for (int c = 0; c < 2 * kResPairs; ++c)
+        if (c < 2 * F.rp) load_chunk(res[c], ap, c);
+}
+
 // 64 x 4 tile product  P[t] * X  of field F (X: this lane's LDS column
-// xcol), summed in FP64 into acc.  The operator chunks come from the
-// stream, whose current pair sits in (a0, a1); each pair used is replaced
-// by the stream's next one.  State values are fetched one chunk ahead with
-// ping-pong buffers.  Per lane acc[r] is row 64 t + 4 (lane / 4) + r of
-// column lane % 4.
-__device__ __forceinline__ void tile_product(const Field &F, const float *xcol, f4 (&a0)[kQ],
+// xcol), summed in FP64 into acc.  The first nres chunk pairs come from the
+// registers `res`, the rest from the stream, whose current pair sits in
+// (a0, a1); each pair used is replaced by the stream's next one.  State
+// values are fetched one chunk ahead with ping-pong buffers.  Per lane
+// acc[r] is row 64 t + 4 (lane / 4) + r of column lane % 4.
+__device__ __forceinline__ void tile_product(const Field &F, const float *xcol,
+                                             const f4 (&res)[2 * kResPairs][kQ], int nres, f4 (&a0)[kQ],
                                              f4 (&a1)[kQ], Stream &s, const Field &fv, const Field &fs,
                                              int w, int lane, double (&acc)[4]) {
 #pragma unroll
@@ -197,7 +223,23 @@ __device__ __forceinline__ void tile_product(const Field &F, const float *xcol, 
     // scheduler would otherwise sink the loads next to their first use.
     lds_chunk(x0, xcol, 0);
     __builtin_amdgcn_sched_barrier(0);
-    for (int c = 0; c < F.nch; c += 2) {
+#pragma unroll
+    for (int rp = 0; rp < kResPairs; ++rp) {
+        if (rp < nres) {
+            lds_chunk(x1, xcol, 2 * rp + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            f4 c0, c1;
+            mma_first(res[2 * rp], x0, c0, c1, p0, p1, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            lds_chunk(x0, xcol, 2 * rp + 2);     // a streamed pair always follows
+            __builtin_amdgcn_sched_barrier(0);
+            mma_next(res[2 * rp + 1], x1, c0, c1);
+            __builtin_amdgcn_sched_barrier(0);
+            p0 = c0;
+            p1 = c1;
+        }
+    }
+    for (int c = 2 * nres; c < F.nch; c += 2) {
         lds_chunk(x1, xcol, c + 1);
         __builtin_amdgcn_sched_barrier(0);
         f4 c0, c1;
