@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the rank-2 kernel at this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy
 # (factors 2.0 and 1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha1": "499ce5e67e587d758202c68c2dcdae2802fb58c0", "bytes": 5.468e6}
+MEASURED_TRAFFIC = {"sources_sha1": "65412cd689bf41ad9c177e1510f5561d4fa1df0f", "bytes": 5.522e6}
 KERNEL_SOURCES = ("paper_2009_11742_amd/csrc/k_rank2_f32.hip", "paper_2009_11742_amd/csrc/k_tile_f32.h",
                   "paper_2009_11742_amd/csrc/k_common.h")
 
@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -108,7 +108,7 @@ def main():
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     ms_per_step = wall * 1e3 / args.steps
     value = M * NSTEPS * args.steps / wall
-    kavg_s = float(np.mean(kern_ms)) * 1e-3
+    kavg_s = float(np.median(kern_ms)) * 1e-3
     flops_per_launch = 4.0 * KV * KS * M * NSTEPS
     achieved = flops_per_launch / kavg_s / 1e12
 
@@ -116,29 +116,15 @@ def main():
     Sg = S.cpu().numpy().astype(np.float64).T
     Jg = J.cpu().numpy()
 
-    # ---- rank-1 path on the same GPU: one sample per stream, 2 launches per step
+    # ---- rank-1 path on the same GPU: one sample per stream, each sample's
+    # steps captured in a graph (2 kernel nodes per step), S concurrent streams
     rank1 = None
     if not args.no_rank1:
-        r1_steps = 500
-        best = None
-        for nstreams in (1, 8):
-            streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
-            vs = [torch.zeros(KV, dtype=torch.float32, device=dev) for _ in range(nstreams)]
-            ss = [torch.zeros(KS, dtype=torch.float32, device=dev) for _ in range(nstreams)]
-            rom.run_rank1(vs[0], ss[0], float(inst["mu"][0]), 20, stream=streams[0])  # warm-up
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for i in range(nstreams):
-                rom.run_rank1(vs[i], ss[i], float(inst["mu"][i]), r1_steps, stream=streams[i])
-            torch.cuda.synchronize()
-            dt1 = time.perf_counter() - t1
-            rate = nstreams * r1_steps / dt1
-            if best is None or rate > best[0]:
-                best = (rate, nstreams)
-        rank1 = {"value": best[0], "unit": "sample-steps/s", "streams": best[1],
-                 "sample": "%d samples x %d steps, %d launches per step" % (best[1], r1_steps, 2)}
+        rank1 = rank1_rate(torch, rom, inst, 500)
 
-    # ---- CPU baseline: the FP64 oracle on a bounded column sample
+    # ---- CPU baseline: the FP64 oracle on a bounded column sample (all host
+    # threads, plus its 1-thread rate), and a numpy/BLAS FP64 rank-2 loop as
+    # the CPU + BLAS context
     cpu = None
     errs = None
     if not args.no_cpu:
@@ -150,8 +136,14 @@ def main():
         ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][cols], NSTEPS,
                                c=inst["c"])
         tcpu = time.perf_counter() - t2
+        n1 = 2000
+        t3 = time.perf_counter()
+        oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][:1], n1, c=inst["c"])
+        t1thr = time.perf_counter() - t3
         cpu = {"value": len(cols) * NSTEPS / tcpu, "unit": "sample-steps/s", "cores": nthr, "kind": "oracle",
-               "sample": "%d of %d columns x %d steps (K=%d, FP64 plain loops), %.1f s" % (len(cols), M, NSTEPS, KV, tcpu)}
+               "sample": "%d of %d columns x %d steps (K=%d, FP64 plain loops), %.1f s" % (len(cols), M, NSTEPS, KV, tcpu),
+               "one_thread": {"value": n1 / t1thr, "sample": "1 column x %d steps" % n1},
+               "numpy_blas": numpy_blas_rate(inst)}
         errs = {"max_rel_state_err": max(_err_cols(Vg[:, cols], ref["V"]), _err_cols(Sg[:, cols], ref["S"])),
                 "max_rel_qoi_err": float(np.max(np.abs(Jg[cols] - ref["J"]) / ref["J"])),
                 "cols_checked": int(len(cols))}
@@ -173,7 +165,8 @@ def main():
                    "kv": KV, "ks": KS, "M": M, "nsteps": NSTEPS, "seed": SEED},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": _measured_traffic(),
-                     "kernel": "rank2_f32_mfma_kernel", "kernel_ms": float(np.mean(kern_ms)),
+                     "kernel": "rank2_f32_mfma_kernel", "kernel_ms": float(np.median(kern_ms)),
+                     "kernel_ms_runs": [float(x) for x in kern_ms],
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "rank1": rank1,
@@ -181,6 +174,70 @@ def main():
         "accuracy": errs,
     }
     print(json.dumps(out))
+
+
+def rank1_rate(torch, rom, inst, nsteps, stream_counts=(1, 8, 32)):
+    """Rank-1 sample-steps/s: sample i's nsteps steps captured in graph i
+    (two GEMV kernels per step), S graphs replayed on S streams at once; the
+    best S is reported.  Graph 0's result is checked against an eager run."""
+    kv, ks = inst["Avs"].shape
+    dev = torch.device("cuda:0")
+    ref_v = torch.zeros(kv, dtype=torch.float32, device=dev)
+    ref_s = torch.zeros(ks, dtype=torch.float32, device=dev)
+    rom.run_rank1(ref_v, ref_s, float(inst["mu"][0]), nsteps)
+    torch.cuda.synchronize()
+    cap = torch.cuda.Stream(device=dev)
+    best, exact = None, True
+    for nstreams in stream_counts:
+        graphs, states = [], []
+        for i in range(nstreams):
+            v = torch.zeros(kv, dtype=torch.float32, device=dev)
+            s = torch.zeros(ks, dtype=torch.float32, device=dev)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                rom.run_rank1(v, s, float(inst["mu"][i % len(inst["mu"])]), nsteps)
+            graphs.append(g)
+            states.append((v, s))
+        streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+        rates = []
+        for rep in range(3):
+            for v, s in states:
+                v.zero_(); s.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g, st in zip(graphs, streams):
+                with torch.cuda.stream(st):
+                    g.replay()
+            torch.cuda.synchronize()
+            rates.append(nstreams * nsteps / (time.perf_counter() - t0))
+            exact = exact and bool(torch.equal(states[0][0], ref_v) and torch.equal(states[0][1], ref_s))
+        rate = float(np.median(rates))
+        if best is None or rate > best[0]:
+            best = (rate, nstreams)
+        del graphs
+    return {"value": best[0], "unit": "sample-steps/s", "streams": best[1],
+            "graph_equals_eager": exact,
+            "sample": "%d samples x %d steps, one graph per sample (2 kernels per step), best of S in %s"
+                      % (best[1], nsteps, list(stream_counts))}
+
+
+def numpy_blas_rate(inst, ncols=16, nsteps=1000):
+    """FP64 rank-2 loop in numpy (BLAS GEMMs), the CPU + BLAS context."""
+    from threadpoolctl import threadpool_info
+    A, B, b, dt = inst["Avs"], inst["Asv"], inst["b"], inst["dt"]
+    mu = inst["mu"][:ncols]
+    V = np.zeros((A.shape[0], len(mu)))
+    S = np.zeros((A.shape[1], len(mu)))
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        a = (np.pi * (mu * (n * dt) - 1.5)) ** 2
+        u = (1.0 - 2.0 * a) * np.exp(-a)
+        V += dt * (A @ S + np.outer(b, u))
+        S += dt * (B @ V)
+    sec = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    return {"value": len(mu) * nsteps / sec, "threads": threads,
+            "sample": "%d columns x %d steps, numpy FP64 GEMMs" % (len(mu), nsteps)}
 
 
 def _events_time(torch, fn, steps, warmup):
@@ -214,8 +271,8 @@ def workload_precision(args, torch, dev):
         def run():
             V.zero_(); S.zero_()
             rom.run_rank2(mu, V, S, N)
-        wall, ms = _events_time(torch, run, max(1, args.steps // 2), 1)
-        ksec = float(np.mean(ms)) * 1e-3
+        wall, ms = _events_time(torch, run, 3, 1)
+        ksec = float(np.median(ms)) * 1e-3
         peak = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}[ops]
         tf = 4.0 * K * K * M * N / ksec / 1e12
         out["runs"][ops] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf,
@@ -243,8 +300,8 @@ def workload_grouped(args, torch, dev):
 
     def run():
         plan.run(N)
-    wall, ms = _events_time(torch, run, max(1, args.steps // 2), 1)
-    ksec = float(np.mean(ms)) * 1e-3
+    wall, ms = _events_time(torch, run, 3, 1)
+    ksec = float(np.median(ms)) * 1e-3
     out = {"workload": "grouped: 64 instances, K in {128..768}, M log-uniform [16,512], 4000 steps",
            "value": ss / ksec, "unit": "sample-steps/s", "tflops": flops / ksec / 1e12,
            "frac_fp32_mfma": flops / ksec / 1e12 / 157.3, "ms_per_run": ksec * 1e3}
@@ -261,8 +318,8 @@ def workload_adjoint(args, torch, dev):
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
     c = torch.tensor(inst["c"], dtype=torch.float32, device=dev)
-    wall, ms = _events_time(torch, lambda: rom.adjoint(mu, N, c), max(1, args.steps // 2), 1)
-    ksec = float(np.mean(ms)) * 1e-3
+    wall, ms = _events_time(torch, lambda: rom.adjoint(mu, N, c), 5, 1)
+    ksec = float(np.median(ms)) * 1e-3
     fwd = 4.0 * K * K * M * N
     out = {"workload": "adjoint: Kv=Ks=512, M=256, 5000 steps, checkpoint stride ceil(sqrt(N))",
            "value": M * N / ksec, "unit": "sample-steps/s (forward + reverse)", "ms_per_gradient": ksec * 1e3,
@@ -282,8 +339,37 @@ def workload_copy(args, torch, dev):
             "GB_per_s": 2 * n * 4 / (float(np.mean(ms)) * 1e-3) / 1e9}
 
 
+def workload_sweep(args, torch, dev):
+    """Rank-2 vs rank-1 over K in {256, 512, 1024} x M in {1, 4, 16, 64, 256,
+    1024} (FP32 operators and states, median of 3 timed runs per point)."""
+    import synth
+    from paper_2009_11742_amd import Rom
+    Ms = (1, 4, 16, 64, 256, 1024)
+    out = {"workload": "sweep: rank-2 vs rank-1, FP32, K x M", "unit": "sample-steps/s", "points": []}
+    for K in (256, 512, 1024):
+        inst = synth.round_to(synth.make_instance(K, K, max(Ms), seed=0), "f32")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+        r1 = rank1_rate(torch, rom, inst, 200, stream_counts=(8, 32))
+        N = {256: 2000, 512: 1000, 1024: 500}[K]
+        for M in Ms:
+            mu = torch.tensor(inst["mu"][:M], dtype=torch.float64, device=dev)
+            V, S = rom.zeros(M, device=dev)
+
+            def run():
+                V.zero_(); S.zero_()
+                rom.run_rank2(mu, V, S, N)
+            wall, ms = _events_time(torch, run, 3, 1)
+            ksec = float(np.median(ms)) * 1e-3
+            out["points"].append({"K": K, "M": M, "nsteps": N, "rank2": M * N / ksec,
+                                  "rank2_us_per_step": ksec / N * 1e6, "rank1": r1["value"],
+                                  "rank1_streams": r1["streams"], "ratio": M * N / ksec / r1["value"],
+                                  "tflops": 4.0 * K * K * M * N / ksec / 1e12})
+        rom.close()
+    return out
+
+
 OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
-         "copy": workload_copy}
+         "copy": workload_copy, "sweep": workload_sweep}
 
 
 if __name__ == "__main__":
