@@ -4,9 +4,13 @@
 // reverse sweep, and the final FP64 -> FP32 conversion.
 //
 // The gradient product reduces over segment_length * M terms (~1.8e4 at the
-// adjoint workload, ~1.3e6 over a whole run), so it accumulates in FP64 on
-// the vector ALUs (FP64 FMA runs at the FP64 matrix rate on MI355X): the
-// FP32 inputs are exact in FP64 and the reduction adds no visible error.
+// adjoint workload, ~1.3e6 over a whole run).  It runs on
+// v_mfma_f32_16x16x4f32: the FP32 trace values multiply exactly, each MFMA
+// chain sums kChainSteps * 4 = 64 terms in FP32, and every chain is folded
+// into FP64 sums, so the result keeps ~1e-7 relative accuracy over any
+// reduction length.  The reduction is split over waves and workgroups; the
+// FP64 partials are summed in a fixed order by a second kernel, so the
+// gradient is deterministic.
 #include "k_common.h"
 #include "rom_internal.h"
 
@@ -14,51 +18,118 @@ namespace rom {
 namespace {
 
 using dev::f4;
-constexpr int kTile = 64;   // output tile (rows x cols) per workgroup
-constexpr int kRb = 32;     // reduction block staged in LDS
+constexpr int kTile = 64;         // output rows and columns per wave (and per workgroup)
+constexpr int kChainSteps = 16;   // MFMA k-steps (4 terms each) per FP32 chain
+constexpr int kDepth = 4;         // k-steps of operand loads in flight
 
-// dA[r0:r0+64, c0:c0+64] += alpha * X[r0:, :] * Y[c0:, :]^T.  Thread (tx, ty)
-// of a 16 x 16 grid owns a 4 x 4 block of the output.
-__global__ __launch_bounds__(256) void gemm_nt_acc64_kernel(const float *__restrict__ X,
-                                                            const float *__restrict__ Y, int rows,
-                                                            int cols, int64_t R, double alpha,
-                                                            double *__restrict__ dA) {
-    __shared__ __align__(16) float Xs[kRb][kTile + 4];
-    __shared__ __align__(16) float Ys[kRb][kTile + 4];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+// Four consecutive rows r .. r+3 of column k of a column-major matrix with
+// `ld` rows, read at an address clamped into the matrix (column ke - 1 past
+// the end of the reduction, row 0 past the last row), so the load is always
+// in bounds and never has to be waited for before its use.  Values of rows
+// past the end only reach output rows that are never stored; values past
+// the end of the reduction are zeroed where they are used.  VEC: ld and r
+// are multiples of 4 (one aligned float4).
+template <bool VEC>
+__device__ __forceinline__ f4 load_rows4(const float *__restrict__ A, int r, int ld, int64_t k, int64_t ke) {
+    const float *col = A + (k < ke ? k : ke - 1) * ld;
+    if (VEC) return *reinterpret_cast<const f4 *>(col + (r < ld ? r : 0));
+    f4 v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = col[r + s < ld ? r + s : ld - 1];
+    return v;
+}
+
+// part[split][col][row] = sum over k in split's range of X[row][k] Y[col][k]
+// for the 64 x 64 output tile (blockIdx.x, blockIdx.y); split = 4 blockIdx.z
+// + wave.  Lane l loads rows r0 + 4 (l % 16) + s (s = 0..3) of reduction
+// index k0 + l / 16, which makes s the row phase of four 16-row MFMA A
+// fragments (and likewise four B fragments for the columns): 2 loads feed 16
+// MFMAs.  MFMA output register r of fragment pair (s, s') in lane l is row
+// r0 + 16 (l / 16) + 4 r + s, column c0 + 4 (l % 16) + s'.
+template <bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_nt_mfma_kernel(const float *__restrict__ X, const float *__restrict__ Y, int rows, int cols,
+                         int64_t R, int64_t kper, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     const int r0 = blockIdx.x * kTile, c0 = blockIdx.y * kTile;
-    double acc[4][4];
+    const int split = blockIdx.z * 4 + w;
+    const int64_t kb = (int64_t)split * kper;
+    const int64_t ke = kb + kper < R ? kb + kper : R;
+    const int rr = r0 + 4 * li, cc = c0 + 4 * li;
+    double acc[4][4][4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-    for (int64_t kb = 0; kb < R; kb += kRb) {
-        for (int e = threadIdx.x; e < kRb * kTile; e += 256) {
-            const int kk = e / kTile, i = e - kk * kTile;
-            const int64_t kc = kb + kk;
-            const int row = r0 + i, col = c0 + i;
-            Xs[kk][i] = (row < rows && kc < R) ? X[row + kc * rows] : 0.f;
-            Ys[kk][i] = (col < cols && kc < R) ? Y[col + kc * cols] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < kRb; ++kk) {
-            const f4 xv = *reinterpret_cast<const f4 *>(&Xs[kk][4 * tx]);
-            const f4 yv = *reinterpret_cast<const f4 *>(&Ys[kk][4 * ty]);
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int r = 0; r < 4; ++r) acc[s][t][r] = 0.0;
+    // operands of k-step j sit in ring slot j % kDepth, loaded kDepth steps
+    // before their MFMAs
+    f4 ra[kDepth], rb[kDepth];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma((double)xv[p], (double)yv[q], acc[p][q]);
-        }
-        __syncthreads();
+    for (int d = 0; d < kDepth; ++d) {
+        ra[d] = load_rows4<VEC>(X, rr, rows, kb + 4 * d + lk, ke);
+        rb[d] = load_rows4<VEC>(Y, cc, cols, kb + 4 * d + lk, ke);
     }
+    for (int64_t k0 = kb; k0 < ke; k0 += 4 * kChainSteps) {
+        f4 ch[4][4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = r0 + 4 * tx + p, col = c0 + 4 * ty + q;
-            if (row < rows && col < cols) dA[row + (int64_t)col * rows] += alpha * acc[p][q];
+            for (int t = 0; t < 4; ++t) ch[s][t] = f4{0.f, 0.f, 0.f, 0.f};
+        // the ring is carried by this (rolled) loop, so the compiler cannot
+        // sink a prefetch next to its use
+#pragma unroll 1
+        for (int g = 0; g < kChainSteps; g += kDepth) {
+#pragma unroll
+            for (int d = 0; d < kDepth; ++d) {
+                // k-step k0/4 + g + d; zero the A operand past the reduction
+                const bool kin = k0 + 4 * (g + d) + lk < ke;
+                f4 a;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a[s] = kin ? ra[d][s] : 0.f;
+                const f4 b = rb[d];
+                const int64_t kn = k0 + 4 * (g + d + kDepth) + lk;
+                ra[d] = load_rows4<VEC>(X, rr, rows, kn, ke);
+                rb[d] = load_rows4<VEC>(Y, cc, cols, kn, ke);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        ch[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[t], ch[s][t], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[s][t][r] += (double)ch[s][t][r];
+    }
+    double *P = part + (size_t)split * rows * cols;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 16 * lk + 4 * r + s, col = cc + t;
+                if (row < rows && col < cols) P[row + (size_t)col * rows] = acc[s][t][r];
+            }
+}
+
+// dA[i] += alpha * sum_p part[p][i], p = 0 .. nsplit - 1 in order.
+__global__ void reduce_parts_kernel(const double *__restrict__ part, int nsplit, int64_t n, double alpha,
+                                    double *__restrict__ dA) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int p = 0; p < nsplit; ++p) v += part[(size_t)p * n + i];
+        dA[i] += alpha * v;
+    }
 }
 
 __global__ void f64_to_f32_kernel(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
@@ -93,11 +164,30 @@ int grid_for(int64_t n, int cap) {
 
 }  // namespace
 
+// Workgroups along the reduction: enough tiles x splits to cover the CUs
+// (at most 8, at least 1).
+static int gemm_nt_zsplit(int rows, int cols) {
+    const int tiles = ((rows + kTile - 1) / kTile) * ((cols + kTile - 1) / kTile);
+    int z = (256 + tiles - 1) / tiles;
+    return z < 1 ? 1 : (z > 8 ? 8 : z);
+}
+
+int gemm_nt_splits(int rows, int cols) { return 4 * gemm_nt_zsplit(rows, cols); }
+
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
-                                double alpha, double *dA, hipStream_t st) {
+                                double alpha, double *dA, double *part, hipStream_t st) {
     if (R <= 0) return hipSuccess;
-    dim3 grid((rows + kTile - 1) / kTile, (cols + kTile - 1) / kTile);
-    hipLaunchKernelGGL(gemm_nt_acc64_kernel, grid, dim3(256), 0, st, X, Y, rows, cols, R, alpha, dA);
+    const int z = gemm_nt_zsplit(rows, cols), nsplit = 4 * z;
+    const int64_t kper = ((R + nsplit - 1) / nsplit + 3) / 4 * 4;
+    dim3 grid((rows + kTile - 1) / kTile, (cols + kTile - 1) / kTile, z);
+    if (rows % 4 == 0 && cols % 4 == 0)
+        hipLaunchKernelGGL(gemm_nt_mfma_kernel<true>, grid, dim3(256), 0, st, X, Y, rows, cols, R, kper, part);
+    else
+        hipLaunchKernelGGL(gemm_nt_mfma_kernel<false>, grid, dim3(256), 0, st, X, Y, rows, cols, R, kper, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)rows * cols;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(n, 4096)), dim3(256), 0, st, part, nsplit, n, alpha, dA);
     return hipGetLastError();
 }
 

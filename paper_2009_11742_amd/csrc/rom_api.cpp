@@ -369,7 +369,9 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     size_t nf = n_ck + n_vtr + n_str + n_wtr + n_qtr + n_cur + n_pq;
     nf = (nf + 1) / 2 * 2;
     const size_t n_ytr = (size_t)C * mK, n_da = 2 * (size_t)kv * ks;
-    const size_t bytes = nf * sizeof(float) + (n_ytr + n_da) * sizeof(double);
+    const int nsplit = std::max(rom::gemm_nt_splits(kv, ks), rom::gemm_nt_splits(ks, kv));
+    const size_t n_part = (size_t)nsplit * kv * ks;   // gradient-product partials
+    const size_t bytes = nf * sizeof(float) + (n_ytr + n_da + n_part) * sizeof(double);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (!ctx->asvT_pk) {
@@ -406,6 +408,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     double *ytr = reinterpret_cast<double *>(f + nf);
     double *dA64 = ytr + n_ytr;
     double *dAvs64 = dA64, *dAsv64 = dA64 + (size_t)kv * ks;
+    double *part = dA64 + n_da;
 
 #define ACHK(call, what) do { e = (call); if (e != hipSuccess) return hip_fail(e, what); } while (0)
     // forward sweep: checkpoint before every segment, accumulate J
@@ -446,10 +449,10 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         ACHK(rom::launch_adjoint_f32_mfma(ad, st), "rom_adjoint: reverse launch");
         // dAvs += dt sum_n W^n (S^n)^T ;  dAsv += dt sum_n Q^{n+1} (V^{n+1})^T
         if (dAvs)
-            ACHK(rom::launch_gemm_nt_acc64(wtr, str, kv, ks, len * M, ctx->dt, dAvs64, st),
+            ACHK(rom::launch_gemm_nt_acc64(wtr, str, kv, ks, len * M, ctx->dt, dAvs64, part, st),
                  "rom_adjoint: gradient product");
         if (dAsv)
-            ACHK(rom::launch_gemm_nt_acc64(qtr, vtr + v1, ks, kv, len * M, ctx->dt, dAsv64, st),
+            ACHK(rom::launch_gemm_nt_acc64(qtr, vtr + v1, ks, kv, len * M, ctx->dt, dAsv64, part, st),
                  "rom_adjoint: gradient product");
     }
     if (dAvs) ACHK(rom::launch_f64_to_f32(dAvs64, (float *)dAvs, (int64_t)kv * ks, st), "rom_adjoint: convert");

@@ -93,9 +93,11 @@ hipError_t launch_pack_lowp(const double *A, int rows, int cols, int prow, int p
 hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_dev, int nitems,
                                    size_t lds_bytes, int64_t n0, int64_t nsteps, hipStream_t st);
 // dA (rows x cols, FP64, column-major) += alpha * X * Y^T with X rows x R and
-// Y cols x R column-major FP32 (ld rows / cols).
+// Y cols x R column-major FP32 (ld rows / cols).  `part` is a workspace of
+// gemm_nt_splits(rows, cols) * rows * cols doubles.
+int gemm_nt_splits(int rows, int cols);
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
-                                double alpha, double *dA, hipStream_t st);
+                                double alpha, double *dA, double *part, hipStream_t st);
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_energy(const double *A64, int kv, int ks, double dt, rom_dtype st_type, const void *V,
                          const void *S, int M, double *E, hipStream_t st);
