@@ -75,10 +75,20 @@ typedef enum {
 
 /* rom_config.flags */
 enum {
-    ROM_SKEW_CHECK = 1u     /* if Asv == -Avs^T exactly, require
+    ROM_SKEW_CHECK = 1u,    /* if Asv == -Avs^T exactly, require
                                dt * sigma_max(Avs) < 2 (positivity of the
                                leapfrog's discrete energy); ROM_E_UNSTABLE
                                otherwise.  Non-skew pairs are not checked.   */
+    ROM_SCHED_COLUMNS = 2u, /* low-precision rank-2 runs: always the
+                               column-block kernel (each workgroup owns 4
+                               samples and the whole operator)                */
+    ROM_SCHED_ROWSPLIT = 4u /* low-precision rank-2 runs: the row-split
+                               kernel (operator rows split over the
+                               workgroups of a 64-sample group, exchanged
+                               every half-step) wherever it applies: Kv == Ks
+                               in {256, 512, 1024}, ceil(M/64) * K/64 <= 256,
+                               a 256-CU device.  Neither flag: row-split where
+                               it applies, column-block elsewhere.           */
 };
 
 typedef struct {
@@ -142,6 +152,14 @@ rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, dou
 
 /* Release every device buffer owned by the context.  NULL is accepted. */
 rom_status rom_destroy(rom_ctx *ctx);
+
+/*
+ * Report in-kernel failures of the work enqueued so far: synchronises
+ * `stream`, returns ROM_E_TIMEOUT if a row-split run's group barrier ran out
+ * of time (its results are then invalid; the kernel still ended), and clears
+ * the condition.  ROM_OK otherwise.
+ */
+rom_status rom_check(rom_ctx *ctx, void *stream);
 
 /*
  * Rank-1 step (Sec. 2.2 eq. (2.3); Sec. 2.3): advance ONE sample by one

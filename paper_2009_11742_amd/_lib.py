@@ -18,11 +18,13 @@ STATUS_NAMES = ["ROM_OK", "ROM_E_ARG", "ROM_E_NOMEM", "ROM_E_DEVICE", "ROM_E_UNS
                 "ROM_E_UNSUPPORTED", "ROM_E_NONFINITE", "ROM_E_TIMEOUT"]
 ROM_F64, ROM_F32, ROM_BF16, ROM_F8E4M3 = range(4)
 ROM_SKEW_CHECK = 1
+ROM_SCHED_COLUMNS = 2
+ROM_SCHED_ROWSPLIT = 4
 
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
-           "rom_get_operators", "rom_energy", "rom_last_error", "rom_version"]
+           "rom_get_operators", "rom_energy", "rom_check", "rom_last_error", "rom_version"]
 
 
 class RomConfig(C.Structure):
@@ -84,6 +86,8 @@ def load():
         lib.rom_get_operators.argtypes = [_vp, _pd, _pd, _pd]
         lib.rom_energy.restype = C.c_int
         lib.rom_energy.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
+        lib.rom_check.restype = C.c_int
+        lib.rom_check.argtypes = [_vp, _vp]
         lib.rom_last_error.restype = C.c_char_p
         lib.rom_last_error.argtypes = []
         lib.rom_version.restype = C.c_char_p

@@ -1,0 +1,475 @@
+// Rank-2 leapfrog stepper, row-split schedule: low-precision (BF16 /
+// FP8-E4M3) operators, FP32 states.
+//
+// Method: Sec. 2.4 eq. (2.5) for the staggered system of Sec. 3.1 eq. (3.3),
+// one step being  V <- V + dt (Avs S + b u(t_n; mu)^T),  S <- S + dt Asv V.
+//
+// Why a second schedule.  The column-block kernels give every workgroup a
+// few sample columns and the whole operator, so each CU streams the full
+// operator every step; with BF16 / FP8 operators at K = 1024 that stream
+// (4 MB / 2 MB per step per CU) bounds the step far above the MFMA time.
+// Here the operator rows are split instead: the workgroups of a column
+// group (kRows = 64 rows each, R = K / 64 of them) cover K rows of both
+// fields for kCols = 64 sample columns.  Each keeps its operator rows in
+// registers for the whole run (every wave holds a quarter of the reduction
+// of both fields as BF16 MFMA fragments: 256 registers per lane at K =
+// 1024), so no operator bytes move after the start.  The price is one
+// exchange per half-step: a workgroup publishes its updated rows, as the
+// BF16 (hi, lo) pair the products consume, and the group meets at a
+// barrier before the other half-step reads them.
+//
+// The exchange stays inside one XCD: a workgroup reads the XCD it runs on
+// (HW_REG_XCC_ID) and takes a group slot on that XCD with an atomic, so a
+// group's members share an L2 and the exchange needs no L2 write-back or
+// invalidate, only each wave's L1 invalidated after the barrier.  The
+// launch is cooperative (all workgroups resident; one per CU); every wait
+// is bounded, and a wait that runs out sets ROM_E_TIMEOUT in the status
+// word and makes every later wait return at once, so the kernel always ends.
+//
+// Products: v_mfma_f32_16x16x32_bf16 (A lane l: row l % 16, terms
+// 8 (l / 16) .. +7; B lane l: terms 8 (l / 16) .. +7, column l % 16;
+// D register r of lane l: row 4 (l / 16) + r, column l % 16).  Wave w of a
+// workgroup sums reduction terms [w kp/4, (w+1) kp/4) for all 64 x 64
+// outputs, with the state operand fed as x_hi + x_lo (two MFMAs); the four
+// partials meet in LDS, where each thread finishes 16 outputs: FP64 sum,
+// scale (FP8), forcing, and the FP64 update of the FP32 (hi, lo) state.
+#include <string>
+
+#include "k_common.h"
+#include "rom_internal.h"
+
+namespace rom {
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+using dev::f4;
+
+constexpr int kRows = 64;          // rows per workgroup tile
+constexpr int kCols = 64;          // sample columns per group
+constexpr int kWaves = 4;
+constexpr int kThreads = 256;
+constexpr int kLd = kRows + 4;     // LDS column stride (floats)
+constexpr long kSpinMax = 1L << 20;
+constexpr int kCntStride = 64;     // counters 256 bytes apart
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+struct SplitArgs {
+    const u4 *opv, *ops;        // packed BF16 fragments of Avs and Asv
+    const float *b, *c;         // source (kv), probe (kv) or null
+    const double *mu;
+    float *V, *S;               // caller states, ld kv / ks
+    double *J, *y;
+    unsigned short *xv, *xs;    // exchange: [group][col][hi k | lo k] BF16
+    double *yp;                 // probe partials [group][row tile][col]
+    unsigned *cnt;              // group counters, kCntStride apart
+    unsigned *slots;            // per-XCD slot counters (8)
+    int *status;                // status[1] <- ROM_E_TIMEOUT
+    int kv, kp, M, G, R;
+    int64_t n0, nsteps;
+    double dt;
+    float scale;
+};
+
+// Group barrier number `phase` (1, 2, ...): publish-side stores of this
+// workgroup are complete when every thread has passed s_waitcnt; thread 0
+// counts the workgroup in and waits for the whole group.
+__device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt, unsigned target) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(&a.status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+               __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinMax) {
+                __hip_atomic_store(&a.status[1], (int)ROM_E_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.status[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    // the group's rows were written through other CUs' L1s into the shared
+    // L2: drop this CU's L1 copies before reading them
+    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Products of one half-step for wave w: acc[rb][cb] (rows 16 rb.., columns
+// 16 cb..) = sum over this wave's KB k-blocks of op fragments x (x_hi + x_lo).
+// x points at the group's exchange block of the other field.
+template <int KB>
+__device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, int kp, int w,
+                                         int lane, f4 (&acc)[4][4]) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    const int kq = kp / 4;
+    // lane's B fragment of column block cb, k-block kb: 8 terms at
+    // x[(16 cb + l % 16) * 2 kp + {0 | kp} + w kq + 32 kb + 8 (l / 16)]
+    const unsigned short *xl = x + (size_t)(lane & 15) * 2 * kp + w * kq + 8 * (lane >> 4);
+    u4 bh[2][4], bl[2][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        bh[0][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp);
+        bl[0][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + kp);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int cur = kb & 1, nxt = cur ^ 1;
+        if (kb + 1 < KB) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                bh[nxt][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + 32 * (kb + 1));
+                bl[nxt][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + kp + 32 * (kb + 1));
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const bf8 A = as_bf8(op[rb][kb]);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(bh[cur][cb]), acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(bl[cur][cb]), acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int KB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rank2_split_kernel(SplitArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *sth = reinterpret_cast<float *>(smem);          // [field][col][kLd] hi
+    float *stl = sth + 2 * kCols * kLd;                     // lo
+    float *part = stl + 2 * kCols * kLd;                    // [wave][col][kLd]
+    float *bl = part + kWaves * kCols * kLd;                // own rows of b
+    float *cl = bl + kRows;                                 // own rows of c
+    __shared__ int sh_slot;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kp = a.kp, R = a.R;
+
+    // ---- group slot on this workgroup's XCD
+    if (tid == 0) {
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID
+        const unsigned s = __hip_atomic_fetch_add(&a.slots[xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh_slot = (int)(xcc + 8u * s);
+    }
+    __syncthreads();
+    const int code = __builtin_amdgcn_readfirstlane(sh_slot);
+    const int xcc = code & 7, s = code >> 3;
+    const int r = s % R;                       // row tile
+    const int g = (s / R) * 8 + xcc;           // group, interleaved over the XCDs
+    if (g >= a.G) return;                      // idle workgroup (never counted)
+    const int col0 = g * kCols;
+    unsigned *cnt = a.cnt + (size_t)g * kCntStride;
+    unsigned phase = 0;
+
+    // ---- operator fragments (registers for the whole run)
+    u4 opv[4][KB], ops[4][KB];
+    {
+        const u4 *pv = a.opv + ((size_t)(r * kWaves + w) * 4 * KB) * 64 + lane;
+        const u4 *ps = a.ops + ((size_t)(r * kWaves + w) * 4 * KB) * 64 + lane;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                opv[rb][kb] = pv[(rb * KB + kb) * 64];
+                ops[rb][kb] = ps[(rb * KB + kb) * 64];
+            }
+    }
+
+    // ---- own tiles of V and S, b, c
+    const int row0 = r * kRows;
+    for (int idx = tid; idx < 2 * kCols * kRows; idx += kThreads) {
+        const int f = idx / (kCols * kRows), rem = idx - f * kCols * kRows;
+        const int j = rem / kRows, i = rem - j * kRows;
+        const int m = col0 + j, row = row0 + i;
+        const float *src = f == 0 ? a.V : a.S;
+        float v = 0.f;
+        if (m < a.M && row < a.kv) v = src[(size_t)m * a.kv + row];
+        sth[(f * kCols + j) * kLd + i] = v;
+        stl[(f * kCols + j) * kLd + i] = 0.f;
+    }
+    for (int i = tid; i < kRows; i += kThreads) {
+        const int row = row0 + i;
+        bl[i] = row < a.kv ? a.b[row] : 0.f;
+        cl[i] = (a.c != nullptr && row < a.kv) ? a.c[row] : 0.f;
+    }
+    __syncthreads();
+
+    // finishing thread: column fj, rows 16 fs .. 16 fs + 15
+    const int fj = tid >> 2, fs = tid & 3;
+    const int fm = col0 + fj;
+    const bool fok = fm < a.M;
+    const double fmu = fok ? a.mu[fm] : 1.0;
+    const size_t xoff = ((size_t)g * kCols + fj) * 2 * kp + row0 + 16 * fs;   // this thread's published rows
+
+    // publish rows of field f (hi words) as BF16 (hi, lo) into x
+    auto publish = [&](int f, unsigned short *x) {
+        const float *h = sth + (f * kCols + fj) * kLd + 16 * fs;
+        u4 ph[2], pl[2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float v0 = h[2 * q], v1 = h[2 * q + 1];
+            const unsigned short a0 = bf16_rne(v0), a1 = bf16_rne(v1);
+            const unsigned short l0 = bf16_rne(v0 - __uint_as_float((unsigned)a0 << 16));
+            const unsigned short l1 = bf16_rne(v1 - __uint_as_float((unsigned)a1 << 16));
+            ph[q >> 2][q & 3] = (unsigned)a0 | ((unsigned)a1 << 16);
+            pl[q >> 2][q & 3] = (unsigned)l0 | ((unsigned)l1 << 16);
+        }
+        u4 *dh = reinterpret_cast<u4 *>(x + xoff);
+        u4 *dl = reinterpret_cast<u4 *>(x + xoff + kp);
+        dh[0] = ph[0]; dh[1] = ph[1];
+        dl[0] = pl[0]; dl[1] = pl[1];
+    };
+
+    // products -> LDS partials -> finished rows (FP64 update) -> published
+    auto half_step = [&](int f, const u4 (&op)[4][KB], const unsigned short *xother, unsigned short *xmine,
+                         double u, bool forced) -> double {
+        f4 acc[4][4];
+        products<KB>(op, xother + (size_t)g * kCols * 2 * kp, kp, w, lane, acc);
+        float *pw = part + w * kCols * kLd;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                *reinterpret_cast<f4 *>(pw + (16 * cb + (lane & 15)) * kLd + 16 * rb + 4 * (lane >> 4)) = acc[rb][cb];
+        __syncthreads();
+        double ypart = 0.0;
+        float *h = sth + (f * kCols + fj) * kLd + 16 * fs;
+        float *l = stl + (f * kCols + fj) * kLd + 16 * fs;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f4 p0 = *reinterpret_cast<const f4 *>(part + (0 * kCols + fj) * kLd + 16 * fs + 4 * q);
+            f4 p1 = *reinterpret_cast<const f4 *>(part + (1 * kCols + fj) * kLd + 16 * fs + 4 * q);
+            f4 p2 = *reinterpret_cast<const f4 *>(part + (2 * kCols + fj) * kLd + 16 * fs + 4 * q);
+            f4 p3 = *reinterpret_cast<const f4 *>(part + (3 * kCols + fj) * kLd + 16 * fs + 4 * q);
+            f4 hh = *reinterpret_cast<const f4 *>(h + 4 * q);
+            f4 ll = *reinterpret_cast<const f4 *>(l + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * fs + 4 * q + e;
+                double inc = (((double)p0[e] + (double)p1[e]) + ((double)p2[e] + (double)p3[e])) * (double)a.scale;
+                if (forced) inc = fma((double)bl[i], u, inc);
+                const double yv = fma(a.dt, inc, (double)hh[e] + (double)ll[e]);
+                const float hv = (float)yv;
+                hh[e] = hv;
+                ll[e] = (float)(yv - (double)hv);
+                if (forced) ypart += (double)cl[i] * yv;
+            }
+            *reinterpret_cast<f4 *>(h + 4 * q) = hh;
+            *reinterpret_cast<f4 *>(l + 4 * q) = ll;
+        }
+        publish(f, xmine);
+        return ypart;
+    };
+
+    // ---- initial exchange: S rows (the first half-step reads S)
+    publish(1, a.xs);
+    group_barrier(a, cnt, (unsigned)R * ++phase);
+
+    double Jacc = 0.0;
+    const bool probe = a.c != nullptr;
+    for (int64_t k = 0; k < a.nsteps; ++k) {
+        const int64_t n = a.n0 + k;
+        const double t = (double)n * a.dt;
+        const double u = fok ? dev::ricker(t, fmu) : 0.0;
+        double yp = half_step(0, opv, a.xs, a.xv, u, true);
+        if (probe) {
+            // sum the 4 strips of column fj, then publish this tile's partial
+            yp += __shfl_xor(yp, 1, 64);
+            yp += __shfl_xor(yp, 2, 64);
+            if (fs == 0) a.yp[((size_t)g * R + r) * kCols + fj] = yp;
+        }
+        group_barrier(a, cnt, (unsigned)R * ++phase);
+        if (probe && r == 0 && fs == 0 && fok) {
+            double yv = 0.0;
+            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * kCols + fj];
+            Jacc += a.dt * (yv * yv);
+            if (a.y) a.y[(size_t)k * a.M + fm] = yv;
+        }
+        half_step(1, ops, a.xv, a.xs, 0.0, false);
+        group_barrier(a, cnt, (unsigned)R * ++phase);
+    }
+
+    // ---- write back (hi + lo), J
+    for (int idx = tid; idx < 2 * kCols * kRows; idx += kThreads) {
+        const int f = idx / (kCols * kRows), rem = idx - f * kCols * kRows;
+        const int j = rem / kRows, i = rem - j * kRows;
+        const int m = col0 + j, row = row0 + i;
+        if (m < a.M && row < a.kv) {
+            float *dst = f == 0 ? a.V : a.S;
+            dst[(size_t)m * a.kv + row] = sth[(f * kCols + j) * kLd + i] + stl[(f * kCols + j) * kLd + i];
+        }
+    }
+    if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
+}
+
+// Split-layout BF16 fragments from the low-precision packed operator:
+// dst[t][w][rb][kb][lane][e] = op[64 t + 16 rb + lane % 16][w kp/4 + 32 kb +
+// 8 (lane / 16) + e], read from the column-block layout
+// (BF16: pk[t][k/8][row][8]; FP8: pk[t][k/16][row][16] E4M3 bytes, widened
+// exactly to BF16).
+__global__ void split_pack_kernel(const unsigned char *__restrict__ src, int fp8, int T, int kp,
+                                  unsigned short *__restrict__ dst) {
+    const int KB = kp / 128;
+    const int64_t total = (int64_t)T * kWaves * 4 * KB * 64 * 8;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q = idx;
+        const int e = (int)(q % 8); q /= 8;
+        const int lane = (int)(q % 64); q /= 64;
+        const int kb = (int)(q % KB); q /= KB;
+        const int rb = (int)(q % 4); q /= 4;
+        const int w = (int)(q % kWaves); q /= kWaves;
+        const int t = (int)q;
+        const int i = 16 * rb + (lane & 15);                    // row within tile
+        const int k = w * (kp / 4) + 32 * kb + 8 * (lane >> 4) + e;
+        unsigned short v;
+        if (!fp8) {
+            const unsigned short *s16 = reinterpret_cast<const unsigned short *>(src);
+            v = s16[(((int64_t)t * (kp / 8) + k / 8) * 64 + i) * 8 + k % 8];
+        } else {
+            const unsigned char byte = src[(((int64_t)t * (kp / 16) + k / 16) * 64 + i) * 16 + k % 16];
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            const f2 wv = __builtin_amdgcn_cvt_pk_f32_fp8((int)byte, false);
+            v = (unsigned short)(__float_as_uint(wv.x) >> 16);   // E4M3 values are exact in BF16
+        }
+        dst[idx] = v;
+    }
+}
+
+__global__ void split_zero_kernel(unsigned *__restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+}  // namespace
+
+size_t rank2_split_lds_bytes() {
+    return sizeof(float) * ((size_t)2 * 2 * kCols * kLd + (size_t)kWaves * kCols * kLd + 2 * kRows);
+}
+
+// Supported shapes: Kv == Ks == K with K in {256, 512, 1024} (register-
+// resident fragments), and G x R <= 256 workgroups (one per CU, all
+// resident).  Returns the group count, or 0 if the row-split schedule does
+// not apply.
+int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M) {
+    if (kv != ks || kvp != ksp) return 0;
+    if (kvp != 256 && kvp != 512 && kvp != 1024) return 0;
+    const int R = kvp / kRows;
+    const int G = (M + kCols - 1) / kCols;
+    if ((int64_t)G * R > 256) return 0;
+    return G;
+}
+
+size_t rank2_split_workspace_bytes(int kvp, int G) {
+    const size_t R = kvp / kRows;
+    return sizeof(unsigned short) * 2 * (size_t)G * kCols * 2 * kvp   // xv, xs
+           + sizeof(double) * (size_t)G * R * kCols                    // yp
+           + sizeof(unsigned) * (256 * kCntStride + 64);               // counters, slots
+}
+
+hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st) {
+    const int T = kvp / kRows;
+    const int64_t total = (int64_t)T * 64 * ksp;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(split_pack_kernel, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const unsigned char *>(lp), fp8 ? 1 : 0, T, ksp,
+                       static_cast<unsigned short *>(dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
+                              int G, int *status, hipStream_t st) {
+    SplitArgs a;
+    a.opv = static_cast<const u4 *>(opv);
+    a.ops = static_cast<const u4 *>(ops);
+    a.b = static_cast<const float *>(r2.b);
+    a.c = static_cast<const float *>(r2.c);
+    a.mu = r2.mu;
+    a.V = static_cast<float *>(r2.V);
+    a.S = static_cast<float *>(r2.S);
+    a.J = r2.J;
+    a.y = r2.y;
+    a.kv = r2.kv;
+    a.kp = r2.kvp;
+    a.M = r2.M;
+    a.G = G;
+    a.R = r2.kvp / kRows;
+    a.n0 = r2.n0;
+    a.nsteps = r2.nsteps;
+    a.dt = r2.dt;
+    a.scale = scale;
+    a.status = status;
+    unsigned short *x = static_cast<unsigned short *>(ws);
+    const size_t xsz = (size_t)G * kCols * 2 * a.kp;
+    a.xv = x;
+    a.xs = x + xsz;
+    a.yp = reinterpret_cast<double *>(x + 2 * xsz);
+    a.cnt = reinterpret_cast<unsigned *>(a.yp + (size_t)G * a.R * kCols);
+    a.slots = a.cnt + 256 * kCntStride;
+    // counters and slots start at zero; status[2] (the abort flag) too
+    hipLaunchKernelGGL(split_zero_kernel, dim3(64), dim3(256), 0, st, a.cnt, 256 * kCntStride + 64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(split_zero_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned *>(status + 2), 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void *args[] = {&a};
+    const size_t lds = rank2_split_lds_bytes();
+    switch (a.kp) {
+    case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<2>, dim3(256), dim3(kThreads), args, lds, st);
+    case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<4>, dim3(256), dim3(kThreads), args, lds, st);
+    case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<8>, dim3(256), dim3(kThreads), args, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The schedule needs all 256 workgroups resident at once, one per CU, 32 on
+// each of the 8 XCDs (the group-slot logic counts on it), and cooperative
+// launch support.
+bool rank2_split_device_ok() {
+    int dev = 0, ncu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return false;
+    if (ncu != 256 || !coop) return false;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0) return false;
+    const size_t lds = rank2_split_lds_bytes();
+    const void *k[3] = {(const void *)rank2_split_kernel<2>, (const void *)rank2_split_kernel<4>,
+                        (const void *)rank2_split_kernel<8>};
+    for (const void *f : k) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) return false;
+    }
+    return true;
+}
+
+hipError_t rank2_split_configure() {
+    // exactly the dynamic LDS the launch asks for (the kernel also has a few
+    // bytes of static LDS, so the 160 KB maximum would be refused)
+    const int lds = (int)rank2_split_lds_bytes();
+    hipError_t e;
+    e = hipFuncSetAttribute((const void *)rank2_split_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)rank2_split_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)rank2_split_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+}  // namespace rom

@@ -88,11 +88,45 @@ void free_ctx(rom_ctx *c) {
     hfree(c->asvT_pk);
     hfree(c->avsT_pk);
     hfree(c->ws);
+    hfree(c->avs_sp);
+    hfree(c->asv_sp);
+    hfree(c->sp_ws);
     hfree(c->status);
     delete c;
 }
 
 bool g_configured = false;
+
+// Row-split operands and workspace of a context (built on first use).
+rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
+    hipError_t e;
+    if (!ctx->avs_sp) {
+        const size_t bytes = sizeof(uint16_t) * (size_t)ctx->kvp * ctx->ksp;
+        e = hipMalloc(&ctx->avs_sp, bytes);
+        if (e == hipSuccess) e = hipMalloc(&ctx->asv_sp, bytes);
+        if (e != hipSuccess) {
+            hfree(ctx->avs_sp); hfree(ctx->asv_sp);
+            ctx->avs_sp = ctx->asv_sp = nullptr;
+            return fail(ROM_E_NOMEM, "rom_run_rank2: device allocation failed");
+        }
+        const bool fp8 = ctx->op_type == ROM_F8E4M3;
+        e = rom::launch_split_pack(ctx->avs_lp, fp8, ctx->kvp, ctx->ksp, ctx->avs_sp, st);
+        if (e == hipSuccess) e = rom::launch_split_pack(ctx->asv_lp, fp8, ctx->ksp, ctx->kvp, ctx->asv_sp, st);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: split pack");
+    }
+    const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
+    if (ctx->sp_ws_bytes < need) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: synchronize");
+        hfree(ctx->sp_ws);
+        ctx->sp_ws = nullptr;
+        ctx->sp_ws_bytes = 0;
+        e = hipMalloc(&ctx->sp_ws, need);
+        if (e != hipSuccess) { ctx->sp_ws = nullptr; return fail(ROM_E_NOMEM, "rom_run_rank2: workspace allocation failed"); }
+        ctx->sp_ws_bytes = need;
+    }
+    return ROM_OK;
+}
 
 }  // namespace
 
@@ -119,7 +153,10 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     if (!lowp && cfg->op_type != cfg->state_type)
         return fail(ROM_E_UNSUPPORTED, "rom_create: supported (op, state) pairs are (F64, F64), "
                                        "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
-    if (cfg->flags & ~(uint32_t)ROM_SKEW_CHECK) return fail(ROM_E_ARG, "rom_create: unknown flag bits");
+    if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT))
+        return fail(ROM_E_ARG, "rom_create: unknown flag bits");
+    if ((cfg->flags & ROM_SCHED_COLUMNS) && (cfg->flags & ROM_SCHED_ROWSPLIT))
+        return fail(ROM_E_ARG, "rom_create: ROM_SCHED_COLUMNS and ROM_SCHED_ROWSPLIT exclude each other");
     const size_t nA = (size_t)kv * ks;
     if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
         return fail(ROM_E_NONFINITE, "rom_create: non-finite value in Avs, Asv or b");
@@ -144,6 +181,7 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
         e = rom::rank2_f32_mfma_configure();
         if (e == hipSuccess) e = rom::rank2_valu_configure();
         if (e == hipSuccess) e = rom::rank2_lowp_configure();
+        if (e == hipSuccess) e = rom::rank2_split_configure();
         if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: kernel attributes"); }
         g_configured = true;
     }
@@ -281,6 +319,23 @@ rom_status rom_destroy(rom_ctx *ctx) {
     return ROM_OK;
 }
 
+rom_status rom_check(rom_ctx *ctx, void *stream) {
+    if (!ctx) return fail(ROM_E_ARG, "rom_check: NULL context");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "rom_check: synchronize");
+    int w[2] = {0, 0};
+    e = hipMemcpy(w, ctx->status + 1, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "rom_check: read status");
+    if (w[0] != 0 || w[1] != 0) {
+        e = hipMemset(ctx->status + 1, 0, sizeof(w));
+        if (e != hipSuccess) return hip_fail(e, "rom_check: clear status");
+        if (w[0] == ROM_E_TIMEOUT)
+            return fail(ROM_E_TIMEOUT, "rom_check: a row-split group barrier timed out; the run's results are invalid");
+    }
+    return ROM_OK;
+}
+
 rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu, void *stream) {
     if (!ctx || !v || !s) return fail(ROM_E_ARG, "rom_step_rank1: NULL argument");
     if (n < 0) return fail(ROM_E_ARG, "rom_step_rank1: n must be >= 0");
@@ -324,8 +379,17 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) && ctx->state_type == ROM_F32) {
         if (rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
-        a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
-        e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
+        const int G = (ctx->flags & ROM_SCHED_COLUMNS) ? 0
+                      : rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
+        if (G > 0 && ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
+        if (G > 0 && ctx->sp_ok == 1) {
+            rom_status rs = prepare_split(ctx, G, st);
+            if (rs != ROM_OK) return rs;
+            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, ctx->op_scale, ctx->sp_ws, G, ctx->status, st);
+        } else {
+            a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
+            e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
+        }
     } else if (ctx->state_type == ROM_F32) {
         if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
             rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)

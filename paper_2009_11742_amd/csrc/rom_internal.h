@@ -51,7 +51,16 @@ struct rom_ctx {
     // FP64 column-major copy of Avs exactly as the products use it (for the
     // energy), built on first use.
     double *avs_e64 = nullptr;
-    // Device status word (in-kernel errors).
+    // Row-split schedule (low-precision runs): operators as BF16 MFMA
+    // fragments in the split layout (built on first use), its workspace
+    // (exchange rows, probe partials, barrier counters), and whether this
+    // device can host it (-1 unknown, 0 no, 1 yes).
+    void *avs_sp = nullptr, *asv_sp = nullptr;
+    void *sp_ws = nullptr;
+    size_t sp_ws_bytes = 0;
+    int sp_ok = -1;
+    // Device status words: [0] scratch of rom_create, [1] in-kernel error
+    // (ROM_E_TIMEOUT), [2] abort flag of the row-split barriers.
     int *status = nullptr;
 };
 
@@ -96,6 +105,15 @@ hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_
 // Y cols x R column-major FP32 (ld rows / cols).  `part` is a workspace of
 // gemm_nt_splits(rows, cols) * rows * cols doubles.
 int gemm_nt_splits(int rows, int cols);
+// Row-split low-precision kernel.
+size_t rank2_split_lds_bytes();
+int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M);
+size_t rank2_split_workspace_bytes(int kvp, int G);
+hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st);
+hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &a, float scale, void *ws,
+                              int G, int *status, hipStream_t st);
+hipError_t rank2_split_configure();
+bool rank2_split_device_ok();
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
                                 double alpha, double *dA, double *part, hipStream_t st);
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);

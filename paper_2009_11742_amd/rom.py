@@ -17,6 +17,9 @@ from ._lib import RomConfig, check
 
 _DT = {"f64": (_lib.ROM_F64, torch.float64), "f32": (_lib.ROM_F32, torch.float32)}
 _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": _lib.ROM_F8E4M3}
+# low-precision rank-2 schedule: "auto" (row-split where it applies),
+# "columns" (column-block kernel), "rowsplit" (row-split where it applies)
+_SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT}
 
 
 def _stream_handle(stream):
@@ -44,7 +47,7 @@ class Rom:
     ('f64', 'f32', 'bf16', 'fp8'; default: the state precision).
     """
 
-    def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, stream=None):
+    def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, schedule="auto", stream=None):
         Avs = np.asarray(Avs)
         kv, ks = Avs.shape
         self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
@@ -53,13 +56,19 @@ class Rom:
         B = _host_f64(Asv, (ks, kv))
         bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
         self.ops = state if ops is None else ops
-        cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, _lib.ROM_SKEW_CHECK if skew_check else 0)
+        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule]
+        cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
         ctx = C.c_void_p()
         lib = _lib.load()
         pd = C.POINTER(C.c_double)
         check(lib.rom_create(C.byref(cfg), A.ctypes.data_as(pd), B.ctypes.data_as(pd),
                              bb.ctypes.data_as(pd), _stream_handle(stream), C.byref(ctx)))
         self._ctx = ctx
+
+    def check(self, stream=None):
+        """Synchronise `stream` and raise if an in-kernel wait of the work
+        enqueued so far timed out (ROM_E_TIMEOUT; results invalid)."""
+        check(_lib.load().rom_check(self._ctx, _stream_handle(stream)))
 
     def operators(self):
         """(Avs, Asv, scale) exactly as the products use them (float64 numpy)."""

@@ -1,0 +1,110 @@
+"""Row-split schedule of the low-precision rank-2 run (BF16 / FP8 operators,
+FP32 states): operator rows split over the workgroups of a 64-sample group,
+exchanged every half-step.
+
+Parity is taken against the same-input FP64 oracle (the operators exactly as
+the products use them), with the bar of the column-block low-precision
+kernel: each state value enters the products as a BF16 (hi, lo) pair
+(~2^-17 relative), which random-walks to ~1e-4 over a few thousand steps; the
+tests allow 2e-3.  Every run is followed by rom_check (no barrier timed out).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+BAR = 2e-3
+
+
+def _relcol(X, R):
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)))
+
+
+def _run(inst, ops, N, schedule, probe=True, trace=False, n_split=None):
+    from paper_2009_11742_amd import Rom
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, schedule=schedule)
+    M = len(inst["mu"])
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(M)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda") if probe else None
+    J = torch.zeros(M, dtype=torch.float64, device="cuda") if probe else None
+    y = torch.zeros((N, M), dtype=torch.float64, device="cuda") if trace else None
+    if n_split is None:
+        rom.run_rank2(mu, V, S, N, c=c, J=J, y=y)
+    else:
+        rom.run_rank2(mu, V, S, n_split, c=c, J=J)
+        rom.run_rank2(mu, V, S, N - n_split, n0=n_split, c=c, J=J)
+    rom.check()
+    A, B, _ = rom.operators()
+    out = {"V": V.cpu().numpy().astype(np.float64).T, "S": S.cpu().numpy().astype(np.float64).T,
+           "J": J.cpu().numpy() if probe else None, "y": y.cpu().numpy() if trace else None, "A": A, "B": B}
+    rom.close()
+    return out
+
+
+@pytest.mark.parametrize("ops", ["bf16", "fp8"])
+@pytest.mark.parametrize("K,M,N", [(256, 100, 1500), (512, 64, 800), (256, 200, 600)])
+def test_rowsplit_same_input_parity(ops, K, M, N):
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=K + M), "f32")
+    g = _run(inst, ops, N, "rowsplit", trace=True)
+    ref = oracle.run_rank2(g["A"], g["B"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"], trace=True)
+    e = max(_relcol(g["V"], ref["V"]), _relcol(g["S"], ref["S"]))
+    eJ = float(np.max(np.abs(g["J"] - ref["J"]) / ref["J"]))
+    ey = float(np.max(np.abs(g["y"] - ref["y"])) / np.max(np.abs(ref["y"])))
+    print("rowsplit %s K=%d M=%d N=%d: state %.2e  J %.2e  y %.2e" % (ops, K, M, N, e, eJ, ey))
+    assert e <= BAR and eJ <= BAR and ey <= BAR
+    assert np.all(np.isfinite(g["V"])) and np.all(np.isfinite(g["S"]))
+
+
+@pytest.mark.parametrize("ops", ["bf16", "fp8"])
+def test_rowsplit_agrees_with_column_block(ops):
+    """Both schedules integrate the same rounded model: each within the bar
+    of the same-input oracle and of each other."""
+    inst = synth.round_to(synth.make_instance(256, 256, 70, seed=11), "f32")
+    N = 1000
+    a = _run(inst, ops, N, "rowsplit")
+    b = _run(inst, ops, N, "columns")
+    assert np.array_equal(a["A"], b["A"]) and np.array_equal(a["B"], b["B"])
+    ref = oracle.run_rank2(a["A"], a["B"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    for g in (a, b):
+        assert max(_relcol(g["V"], ref["V"]), _relcol(g["S"], ref["S"])) <= BAR
+    assert _relcol(a["V"], b["V"]) <= BAR
+
+
+def test_rowsplit_run_split_and_offset():
+    """Two runs (n0 = 0 and n0 = 400) equal one run of 1000 steps up to the
+    state rounding at the boundary."""
+    inst = synth.round_to(synth.make_instance(256, 256, 64, seed=5), "f32")
+    N = 1000
+    one = _run(inst, "bf16", N, "rowsplit")
+    two = _run(inst, "bf16", N, "rowsplit", n_split=400)
+    ref = oracle.run_rank2(one["A"], one["B"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    assert _relcol(two["V"], one["V"]) <= 1e-4
+    assert max(_relcol(two["V"], ref["V"]), _relcol(two["S"], ref["S"])) <= BAR
+    assert float(np.max(np.abs(two["J"] - ref["J"]) / ref["J"])) <= BAR
+
+
+def test_rowsplit_k1024_m1024_sampled():
+    """K = M = 1024 (the precision workload's shape), 600 steps, BF16 and
+    FP8: three sampled columns against the same-input oracle."""
+    inst = synth.round_to(synth.make_instance(1024, 1024, 1024, seed=0), "f32")
+    N = 600
+    cols = np.array([0, 517, 1023])
+    for ops in ("bf16", "fp8"):
+        g = _run(inst, ops, N, "rowsplit")
+
+        def ref(ci):
+            return oracle.run_rank2(g["A"], g["B"], inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N, c=inst["c"])
+        with cf.ThreadPoolExecutor(max_workers=3) as ex:
+            refs = list(ex.map(ref, cols))
+        e = max(max(_relcol(g["V"][:, ci:ci + 1], r["V"]), _relcol(g["S"][:, ci:ci + 1], r["S"]))
+                for ci, r in zip(cols, refs))
+        eJ = max(abs(g["J"][ci] - r["J"][0]) / r["J"][0] for ci, r in zip(cols, refs))
+        print("rowsplit %s K=M=1024 N=%d sampled: state %.2e J %.2e" % (ops, N, e, eJ))
+        assert e <= BAR and eJ <= BAR
