@@ -67,7 +67,7 @@ struct SplitArgs {
     const double *mu;
     float *V, *S;               // caller states, ld kv / ks
     double *J, *y;
-    unsigned short *xv, *xs;    // exchange: [group][col][hi k | lo k] BF16
+    unsigned short *xv, *xs;    // exchange, BF16 in MFMA B-fragment order (see frag_offset)
     double *yp;                 // probe partials [group][row tile][col]
     unsigned *cnt;              // group counters, kCntStride apart
     unsigned *slots;            // per-XCD slot counters (8)
@@ -105,43 +105,77 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
 
 // Products of one half-step for wave w: acc[rb][cb] (rows 16 rb.., columns
 // 16 cb..) = sum over this wave's KB k-blocks of op fragments x (x_hi + x_lo).
-// x points at the group's exchange block of the other field.
+// x points at the group's exchange block of the other field.  The B
+// fragments of k-block kb are loaded kDepth k-blocks ahead into a register
+// ring; the loop is fully unrolled (static fragment indices) and
+// sched_barriers keep every load batch ahead of the MFMAs it must precede,
+// which the scheduler would otherwise sink next to their use under this
+// kernel's register pressure.
+constexpr int kDepth = 2;
+
+// Exchange layout: per group, [k-block (kp/32)][column block (4)][hi | lo]
+// [lane (64)][8 terms], lane = 16 ((k % 32) / 8) + column % 16 -- exactly the
+// B fragments, so one wave load reads 1 KB contiguous.  Offset (in BF16
+// elements) of fragment (kb, cb, hl) within a group's block:
+__device__ __forceinline__ size_t frag_offset(int kb, int cb, int hl) {
+    return ((size_t)(kb * 4 + cb) * 2 + hl) * 512;
+}
+
+// (the fragment base is wave-uniform and the lane offset an unsigned 32-bit
+// value, so the loads take the scalar-base + vector-offset form and need no
+// 64-bit address registers)
+typedef const __attribute__((address_space(1))) unsigned short gbf16;   // global memory
+typedef const __attribute__((address_space(1))) unsigned char gbyte;
+typedef const __attribute__((address_space(1))) u4 gu4;
+
+__device__ __forceinline__ void load_b(gbf16 *xg, int kb, unsigned loff, u4 (&bh)[4], u4 (&bl)[4]) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        gbyte *ph = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 0));
+        gbyte *pl = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 1));
+        bh[cb] = *reinterpret_cast<gu4 *>(ph + loff);
+        bl[cb] = *reinterpret_cast<gu4 *>(pl + loff);
+    }
+}
+
 template <int KB>
-__device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, int kp, int w,
-                                         int lane, f4 (&acc)[4][4]) {
+__device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, int w, int lane,
+                                         f4 (&acc)[4][4]) {
+    constexpr int D = KB < kDepth ? KB : kDepth;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
-    const int kq = kp / 4;
-    // lane's B fragment of column block cb, k-block kb: 8 terms at
-    // x[(16 cb + l % 16) * 2 kp + {0 | kp} + w kq + 32 kb + 8 (l / 16)]
-    const unsigned short *xl = x + (size_t)(lane & 15) * 2 * kp + w * kq + 8 * (lane >> 4);
-    u4 bh[2][4], bl[2][4];
+    // The fragment addresses are the same every step; without this opaque
+    // redefinition of the base the compiler hoists all of them out of the
+    // time loop and spills them.
+    uint64_t bits = reinterpret_cast<uint64_t>(x);
+    asm volatile("" : "+s"(bits));
+    gbf16 *xg = reinterpret_cast<gbf16 *>(bits);
+    // this wave's k-blocks are w KB .. w KB + KB - 1 of the group's block
+    const int kb0 = w * KB;
+    u4 rh[D][4], rl[D][4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        bh[0][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp);
-        bl[0][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + kp);
-    }
+    for (int d = 0; d < D; ++d) load_b(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-        const int cur = kb & 1, nxt = cur ^ 1;
-        if (kb + 1 < KB) {
+        const int slot = kb % D;
+        u4 h[4], l[4];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                bh[nxt][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + 32 * (kb + 1));
-                bl[nxt][cb] = *reinterpret_cast<const u4 *>(xl + (size_t)16 * cb * 2 * kp + kp + 32 * (kb + 1));
-            }
-        }
+        for (int cb = 0; cb < 4; ++cb) { h[cb] = rh[slot][cb]; l[cb] = rl[slot][cb]; }
+        if (kb + D < KB) load_b(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
             const bf8 A = as_bf8(op[rb][kb]);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(bh[cur][cb]), acc[rb][cb], 0, 0, 0);
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(bl[cur][cb]), acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(h[cb]), acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(l[cb]), acc[rb][cb], 0, 0, 0);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -214,32 +248,38 @@ void rank2_split_kernel(SplitArgs a) {
     const int fm = col0 + fj;
     const bool fok = fm < a.M;
     const double fmu = fok ? a.mu[fm] : 1.0;
-    const size_t xoff = ((size_t)g * kCols + fj) * 2 * kp + row0 + 16 * fs;   // this thread's published rows
 
-    // publish rows of field f (hi words) as BF16 (hi, lo) into x
+    // publish rows of field f (hi words) as BF16 (hi, lo) into x, in the
+    // B-fragment order: rows row0 + 16 fs + 8 h + e (h = 0, 1) of column fj
+    // are terms e of lane 16 (((16 fs + 8 h) % 32) / 8) + fj % 16 of k-block
+    // (row0 + 16 fs) / 32, column block fj / 16
     auto publish = [&](int f, unsigned short *x) {
         const float *h = sth + (f * kCols + fj) * kLd + 16 * fs;
-        u4 ph[2], pl[2];
+        unsigned short *xg = x + (size_t)g * kCols * 2 * kp;
+        const int kb = (row0 + 16 * fs) / 32, cb = fj / 16;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float v0 = h[2 * q], v1 = h[2 * q + 1];
-            const unsigned short a0 = bf16_rne(v0), a1 = bf16_rne(v1);
-            const unsigned short l0 = bf16_rne(v0 - __uint_as_float((unsigned)a0 << 16));
-            const unsigned short l1 = bf16_rne(v1 - __uint_as_float((unsigned)a1 << 16));
-            ph[q >> 2][q & 3] = (unsigned)a0 | ((unsigned)a1 << 16);
-            pl[q >> 2][q & 3] = (unsigned)l0 | ((unsigned)l1 << 16);
+        for (int half = 0; half < 2; ++half) {
+            u4 ph, pl;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float v0 = h[8 * half + 2 * q], v1 = h[8 * half + 2 * q + 1];
+                const unsigned short a0 = bf16_rne(v0), a1 = bf16_rne(v1);
+                const unsigned short l0 = bf16_rne(v0 - __uint_as_float((unsigned)a0 << 16));
+                const unsigned short l1 = bf16_rne(v1 - __uint_as_float((unsigned)a1 << 16));
+                ph[q] = (unsigned)a0 | ((unsigned)a1 << 16);
+                pl[q] = (unsigned)l0 | ((unsigned)l1 << 16);
+            }
+            const int ln = 16 * (((16 * fs + 8 * half) % 32) / 8) + (fj & 15);
+            *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 0) + 8 * ln) = ph;
+            *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 1) + 8 * ln) = pl;
         }
-        u4 *dh = reinterpret_cast<u4 *>(x + xoff);
-        u4 *dl = reinterpret_cast<u4 *>(x + xoff + kp);
-        dh[0] = ph[0]; dh[1] = ph[1];
-        dl[0] = pl[0]; dl[1] = pl[1];
     };
 
     // products -> LDS partials -> finished rows (FP64 update) -> published
     auto half_step = [&](int f, const u4 (&op)[4][KB], const unsigned short *xother, unsigned short *xmine,
                          double u, bool forced) -> double {
         f4 acc[4][4];
-        products<KB>(op, xother + (size_t)g * kCols * 2 * kp, kp, w, lane, acc);
+        products<KB>(op, xother + (size_t)g * kCols * 2 * kp, w, lane, acc);
         float *pw = part + w * kCols * kLd;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
