@@ -42,6 +42,8 @@ namespace rom {
 namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 using dev::f4;
 
@@ -52,12 +54,6 @@ constexpr int kThreads = 256;
 constexpr int kLd = kRows + 4;     // LDS column stride (floats)
 constexpr long kSpinMax = 1L << 20;
 constexpr int kCntStride = 64;     // counters 256 bytes apart
-
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
 
 __device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
@@ -262,12 +258,13 @@ void rank2_split_kernel(SplitArgs a) {
             u4 ph, pl;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float v0 = h[8 * half + 2 * q], v1 = h[8 * half + 2 * q + 1];
-                const unsigned short a0 = bf16_rne(v0), a1 = bf16_rne(v1);
-                const unsigned short l0 = bf16_rne(v0 - __uint_as_float((unsigned)a0 << 16));
-                const unsigned short l1 = bf16_rne(v1 - __uint_as_float((unsigned)a1 << 16));
-                ph[q] = (unsigned)a0 | ((unsigned)a1 << 16);
-                pl[q] = (unsigned)l0 | ((unsigned)l1 << 16);
+                // hardware round-to-nearest-even, two values per instruction
+                const f2 v = {h[8 * half + 2 * q], h[8 * half + 2 * q + 1]};
+                const bf2 hi = __builtin_convertvector(v, bf2);
+                const f2 r = v - __builtin_convertvector(hi, f2);
+                const bf2 lo = __builtin_convertvector(r, bf2);
+                ph[q] = __builtin_bit_cast(unsigned, hi);
+                pl[q] = __builtin_bit_cast(unsigned, lo);
             }
             const int ln = 16 * (((16 * fs + 8 * half) % 32) / 8) + (fj & 15);
             *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 0) + 8 * ln) = ph;
@@ -301,7 +298,9 @@ void rank2_split_kernel(SplitArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = 16 * fs + 4 * q + e;
-                double inc = (((double)p0[e] + (double)p1[e]) + ((double)p2[e] + (double)p3[e])) * (double)a.scale;
+                // the wave partials are FP32 chain sums; one more FP32 rounding is
+                // far below the BF16 state operand's
+                double inc = (double)((p0[e] + p1[e]) + (p2[e] + p3[e])) * (double)a.scale;
                 if (forced) inc = fma((double)bl[i], u, inc);
                 const double yv = fma(a.dt, inc, (double)hh[e] + (double)ll[e]);
                 const float hv = (float)yv;
