@@ -79,16 +79,18 @@ enum {
                                dt * sigma_max(Avs) < 2 (positivity of the
                                leapfrog's discrete energy); ROM_E_UNSTABLE
                                otherwise.  Non-skew pairs are not checked.   */
-    ROM_SCHED_COLUMNS = 2u, /* low-precision rank-2 runs: always the
-                               column-block kernel (each workgroup owns 4
-                               samples and the whole operator)                */
-    ROM_SCHED_ROWSPLIT = 4u /* low-precision rank-2 runs: the row-split
-                               kernel (operator rows split over the
-                               workgroups of a 64-sample group, exchanged
-                               every half-step) wherever it applies: Kv == Ks
-                               in {256, 512, 1024}, ceil(M/64) * K/64 <= 256,
-                               a 256-CU device.  Neither flag: row-split where
-                               it applies, column-block elsewhere.           */
+    ROM_SCHED_COLUMNS = 2u, /* FP32-state rank-2 runs (FP32, BF16, FP8
+                               operators): always the column-block kernels
+                               (each workgroup owns 4 samples and the whole
+                               operator)                                      */
+    ROM_SCHED_ROWSPLIT = 4u /* FP32-state rank-2 runs: the row-split kernels
+                               (operator rows split over the workgroups of a
+                               64-sample group, exchanged every half-step)
+                               wherever they apply: Kv == Ks in {256, 512,
+                               1024}, ceil(M/64) * K/64 <= 256, a 256-CU
+                               gfx950.  Neither flag: row-split where it
+                               applies and fills at least 128 workgroups,
+                               column-block elsewhere.                        */
 };
 
 typedef struct {

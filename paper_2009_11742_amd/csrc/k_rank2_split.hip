@@ -356,6 +356,248 @@ void rank2_split_kernel(SplitArgs a) {
     if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 operators, FP32 states, same row-split schedule.  The FP32 operator
+// rows of a workgroup (512 KB at K = 1024) do not fit in registers, so each
+// wave streams its quarter of the reduction of the current field from L2
+// every half-step; products on v_mfma_f32_16x16x4f32 (A lane l: row l % 16,
+// term l / 16; B lane l: term l / 16, column l % 16; D as above).  Operands
+// come in k-groups of 16 terms (4 MFMA k-steps): lane l holds terms
+// 4 j + l / 16 (j = 0..3) as one float4, for the operator
+//   opf[t][w][kg][rb][lane] = op[64 t + 16 rb + l % 16][w kp/4 + 16 kg + 4 j + l / 16]
+// and for the exchanged state, per group,
+//   xf[kgg][cb][lane] = x[16 kgg + 4 j + l / 16][16 cb + l % 16]
+// (kgg = the global k-group), so every wave load is 1 KB contiguous.  FP32
+// chains of 64 terms are folded into FP64 sums (the products' FP32 rounding
+// then stays at the column-block kernel's level); the four wave partials
+// meet in LDS in FP64, and the state (hi, lo) of a finishing thread's 16
+// entries per field lives in its registers.
+constexpr int kChainGroups = 4;    // k-groups per FP32 chain (64 terms)
+constexpr int kLdD = kRows + 2;    // LDS column stride of the FP64 partials (doubles)
+
+typedef const __attribute__((address_space(1))) f4 gf4;
+
+template <int KG>
+__device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, int w, int lane,
+                                             double (&acc)[4][4][4]) {
+    constexpr int D = KG < 2 ? KG : 2;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[rb][cb][r] = 0.0;
+    // opaque per-step bases (see products): no hoisted, spilled addresses
+    uint64_t ob = reinterpret_cast<uint64_t>(opw), xb = reinterpret_cast<uint64_t>(xgrp);
+    asm volatile("" : "+s"(ob), "+s"(xb));
+    const unsigned loff = 16u * (unsigned)lane;
+    gbyte *opb = reinterpret_cast<gbyte *>(ob);
+    gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KG * 4 * 1024;   // this wave's k-groups
+    auto load = [&](int kg, f4 (&a)[4], f4 (&b)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
+            b[q] = *reinterpret_cast<gf4 *>(xbb + (size_t)(kg * 4 + q) * 1024 + loff);
+        }
+    };
+    f4 ra[D][4], rbx[D][4];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(d, ra[d], rbx[d]);
+    __builtin_amdgcn_sched_barrier(0);
+    f4 c[4][4];
+#pragma unroll
+    for (int kg = 0; kg < KG; ++kg) {
+        const int slot = kg % D;
+        f4 a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { a[q] = ra[slot][q]; b[q] = rbx[slot][q]; }
+        if (kg + D < KG) load(kg + D, ra[slot], rbx[slot]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kg % kChainGroups == 0) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) c[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j], c[rb][cb], 0, 0, 0);
+        if (kg % kChainGroups == kChainGroups - 1 || kg == KG - 1) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[rb][cb][r] += (double)c[rb][cb][r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int KG>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rank2_split_f32_kernel(SplitArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *part = reinterpret_cast<double *>(smem);        // [wave][col][kLdD]
+    float *bl = reinterpret_cast<float *>(part + kWaves * kCols * kLdD);
+    float *cl = bl + kRows;
+    __shared__ int sh_slot;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kp = a.kp, R = a.R;
+
+    if (tid == 0) {
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID
+        const unsigned s = __hip_atomic_fetch_add(&a.slots[xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh_slot = (int)(xcc + 8u * s);
+    }
+    __syncthreads();
+    const int code = __builtin_amdgcn_readfirstlane(sh_slot);
+    const int xcc = code & 7, s = code >> 3;
+    const int r = s % R;
+    const int g = (s / R) * 8 + xcc;
+    if (g >= a.G) return;
+    const int col0 = g * kCols;
+    unsigned *cnt = a.cnt + (size_t)g * kCntStride;
+    unsigned phase = 0;
+    const int row0 = r * kRows;
+
+    for (int i = tid; i < kRows; i += kThreads) {
+        const int row = row0 + i;
+        bl[i] = row < a.kv ? a.b[row] : 0.f;
+        cl[i] = (a.c != nullptr && row < a.kv) ? a.c[row] : 0.f;
+    }
+    // finishing thread: column fj, rows 16 fs .. 16 fs + 15; its state
+    // entries of both fields stay in registers
+    const int fj = tid >> 2, fs = tid & 3;
+    const int fm = col0 + fj;
+    const bool fok = fm < a.M;
+    const double fmu = fok ? a.mu[fm] : 1.0;
+    float sh[2][16], sl[2][16];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = row0 + 16 * fs + e;
+            const float *src = f == 0 ? a.V : a.S;
+            sh[f][e] = (fok && row < a.kv) ? src[(size_t)fm * a.kv + row] : 0.f;
+            sl[f][e] = 0.f;
+        }
+    __syncthreads();
+
+    // this wave's operator panel (k-groups w KG .. of row tile r)
+    const f4 *opvw = reinterpret_cast<const f4 *>(a.opv) + (size_t)(r * kWaves + w) * KG * 4 * 64;
+    const f4 *opsw = reinterpret_cast<const f4 *>(a.ops) + (size_t)(r * kWaves + w) * KG * 4 * 64;
+    float *xv = reinterpret_cast<float *>(a.xv), *xs = reinterpret_cast<float *>(a.xs);
+
+    // publish this thread's 16 rows (hi words) of field f in fragment order:
+    // rows row0 + 16 fs + 4 j + q of column fj are term j of lane
+    // 16 q + fj % 16 in k-group (row0 + 16 fs) / 16, column block fj / 16
+    auto publish = [&](int f, float *x) {
+        float *xg = x + (size_t)g * kCols * kp;
+        const int kgg = (row0 + 16 * fs) / 16, cb = fj / 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const f4 v = {sh[f][q], sh[f][4 + q], sh[f][8 + q], sh[f][12 + q]};
+            *reinterpret_cast<f4 *>(xg + ((size_t)(kgg * 4 + cb) * 64 + 16 * q + (fj & 15)) * 4) = v;
+        }
+    };
+
+    auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, double u,
+                         bool forced) -> double {
+        double acc[4][4][4];
+        products_f32<KG>(opw, xother + (size_t)g * kCols * kp, w, lane, acc);
+        double *pw = part + w * kCols * kLdD;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                double *d = pw + (16 * cb + (lane & 15)) * kLdD + 16 * rb + 4 * (lane >> 4);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) d[rr] = acc[rb][cb][rr];
+            }
+        __syncthreads();
+        double ypart = 0.0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = 16 * fs + e;
+            double inc = (part[(0 * kCols + fj) * kLdD + i] + part[(1 * kCols + fj) * kLdD + i]) +
+                         (part[(2 * kCols + fj) * kLdD + i] + part[(3 * kCols + fj) * kLdD + i]);
+            if (forced) inc = fma((double)bl[i], u, inc);
+            const double yv = fma(a.dt, inc, (double)sh[f][e] + (double)sl[f][e]);
+            const float hv = (float)yv;
+            sh[f][e] = hv;
+            sl[f][e] = (float)(yv - (double)hv);
+            if (forced) ypart += (double)cl[i] * yv;
+        }
+        publish(f, xmine);
+        __syncthreads();   // partials read before the next half-step writes them
+        return ypart;
+    };
+
+    publish(1, xs);
+    group_barrier(a, cnt, (unsigned)R * ++phase);
+
+    double Jacc = 0.0;
+    const bool probe = a.c != nullptr;
+    for (int64_t k = 0; k < a.nsteps; ++k) {
+        const int64_t n = a.n0 + k;
+        const double t = (double)n * a.dt;
+        const double u = fok ? dev::ricker(t, fmu) : 0.0;
+        double yp = half_step(0, opvw, xs, xv, u, true);
+        if (probe) {
+            yp += __shfl_xor(yp, 1, 64);
+            yp += __shfl_xor(yp, 2, 64);
+            if (fs == 0) a.yp[((size_t)g * R + r) * kCols + fj] = yp;
+        }
+        group_barrier(a, cnt, (unsigned)R * ++phase);
+        if (probe && r == 0 && fs == 0 && fok) {
+            double yv = 0.0;
+            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * kCols + fj];
+            Jacc += a.dt * (yv * yv);
+            if (a.y) a.y[(size_t)k * a.M + fm] = yv;
+        }
+        half_step(1, opsw, xv, xs, 0.0, false);
+        group_barrier(a, cnt, (unsigned)R * ++phase);
+    }
+
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = row0 + 16 * fs + e;
+            float *dst = f == 0 ? a.V : a.S;
+            if (fok && row < a.kv) dst[(size_t)fm * a.kv + row] = sh[f][e] + sl[f][e];
+        }
+    if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
+}
+
+// FP32 split-layout operator from a column-major FP32 matrix (rows x cols,
+// ld rows), zero padded: dst[t][w][kg][rb][lane][j] (see above).
+__global__ void split_pack_f32_kernel(const float *__restrict__ A, int rows, int cols, int T, int kp,
+                                      float *__restrict__ dst) {
+    const int KG = kp / 64;
+    const int64_t total = (int64_t)T * kWaves * KG * 4 * 64 * 4;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q = idx;
+        const int j = (int)(q % 4); q /= 4;
+        const int lane = (int)(q % 64); q /= 64;
+        const int rb = (int)(q % 4); q /= 4;
+        const int kg = (int)(q % KG); q /= KG;
+        const int w = (int)(q % kWaves); q /= kWaves;
+        const int t = (int)q;
+        const int row = 64 * t + 16 * rb + (lane & 15);
+        const int k = w * (kp / 4) + 16 * kg + 4 * j + (lane >> 4);
+        dst[idx] = (row < rows && k < cols) ? A[row + (int64_t)k * rows] : 0.f;
+    }
+}
+
 // Split-layout BF16 fragments from the low-precision packed operator:
 // dst[t][w][rb][kb][lane][e] = op[64 t + 16 rb + lane % 16][w kp/4 + 32 kb +
 // 8 (lane / 16) + e], read from the column-block layout
@@ -420,6 +662,20 @@ size_t rank2_split_workspace_bytes(int kvp, int G) {
            + sizeof(unsigned) * (256 * kCntStride + 64);               // counters, slots
 }
 
+size_t rank2_split_f32_lds_bytes() {
+    return sizeof(double) * (size_t)kWaves * kCols * kLdD + sizeof(float) * 2 * kRows;
+}
+
+hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st) {
+    const int T = prow / kRows;
+    const int64_t total = (int64_t)T * 64 * pcol;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(split_pack_f32_kernel, dim3(blocks), dim3(256), 0, st, A, rows, cols, T, pcol,
+                       static_cast<float *>(dst));
+    return hipGetLastError();
+}
+
 hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st) {
     const int T = kvp / kRows;
     const int64_t total = (int64_t)T * 64 * ksp;
@@ -432,7 +688,7 @@ hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *d
 }
 
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
-                              int G, int *status, hipStream_t st) {
+                              int G, int *status, bool f32, hipStream_t st) {
     SplitArgs a;
     a.opv = static_cast<const u4 *>(opv);
     a.ops = static_cast<const u4 *>(ops);
@@ -468,6 +724,15 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     void *args[] = {&a};
+    if (f32) {
+        const size_t lds = rank2_split_f32_lds_bytes();
+        switch (a.kp) {
+        case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<4>, dim3(256), dim3(kThreads), args, lds, st);
+        case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<8>, dim3(256), dim3(kThreads), args, lds, st);
+        case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<16>, dim3(256), dim3(kThreads), args, lds, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     const size_t lds = rank2_split_lds_bytes();
     switch (a.kp) {
     case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<2>, dim3(256), dim3(kThreads), args, lds, st);
@@ -496,6 +761,14 @@ bool rank2_split_device_ok() {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) return false;
     }
+    const void *kf[3] = {(const void *)rank2_split_f32_kernel<4>, (const void *)rank2_split_f32_kernel<8>,
+                         (const void *)rank2_split_f32_kernel<16>};
+    for (const void *f : kf) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, rank2_split_f32_lds_bytes()) != hipSuccess ||
+            nb < 1)
+            return false;
+    }
     return true;
 }
 
@@ -508,7 +781,14 @@ hipError_t rank2_split_configure() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)rank2_split_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)rank2_split_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    e = hipFuncSetAttribute((const void *)rank2_split_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    const int lf = (int)rank2_split_f32_lds_bytes();
+    e = hipFuncSetAttribute((const void *)rank2_split_f32_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)rank2_split_f32_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)rank2_split_f32_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
 }
 
 }  // namespace rom

@@ -97,11 +97,28 @@ void free_ctx(rom_ctx *c) {
 
 bool g_configured = false;
 
+// Row-split or column-block schedule for a rank-2 run of M samples: the
+// row-split kernel applies to Kv == Ks in {256, 512, 1024} on a 256-CU
+// gfx950; by default it is taken when its G x R workgroups fill at least
+// half of the CUs (below that the column-block kernels, which never wait
+// for one another, are faster), ROM_SCHED_ROWSPLIT takes it wherever it
+// applies and ROM_SCHED_COLUMNS never.  Returns the group count G (0 =
+// column-block).
+int split_groups_for(rom_ctx *ctx, int32_t M) {
+    if (ctx->flags & ROM_SCHED_COLUMNS) return 0;
+    const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
+    if (G == 0) return 0;
+    if (!(ctx->flags & ROM_SCHED_ROWSPLIT) && G * (ctx->kvp / rom::kTileRows) < 128) return 0;
+    if (ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
+    return ctx->sp_ok == 1 ? G : 0;
+}
+
 // Row-split operands and workspace of a context (built on first use).
 rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
     hipError_t e;
     if (!ctx->avs_sp) {
-        const size_t bytes = sizeof(uint16_t) * (size_t)ctx->kvp * ctx->ksp;
+        const bool f32 = ctx->op_type == ROM_F32;
+        const size_t bytes = (f32 ? sizeof(float) : sizeof(uint16_t)) * (size_t)ctx->kvp * ctx->ksp;
         e = hipMalloc(&ctx->avs_sp, bytes);
         if (e == hipSuccess) e = hipMalloc(&ctx->asv_sp, bytes);
         if (e != hipSuccess) {
@@ -109,9 +126,17 @@ rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
             ctx->avs_sp = ctx->asv_sp = nullptr;
             return fail(ROM_E_NOMEM, "rom_run_rank2: device allocation failed");
         }
-        const bool fp8 = ctx->op_type == ROM_F8E4M3;
-        e = rom::launch_split_pack(ctx->avs_lp, fp8, ctx->kvp, ctx->ksp, ctx->avs_sp, st);
-        if (e == hipSuccess) e = rom::launch_split_pack(ctx->asv_lp, fp8, ctx->ksp, ctx->kvp, ctx->asv_sp, st);
+        if (f32) {
+            e = rom::launch_split_pack_f32(static_cast<const float *>(ctx->avs_cm), ctx->kv, ctx->ks, ctx->kvp,
+                                           ctx->ksp, ctx->avs_sp, st);
+            if (e == hipSuccess)
+                e = rom::launch_split_pack_f32(static_cast<const float *>(ctx->asv_cm), ctx->ks, ctx->kv, ctx->ksp,
+                                               ctx->kvp, ctx->asv_sp, st);
+        } else {
+            const bool fp8 = ctx->op_type == ROM_F8E4M3;
+            e = rom::launch_split_pack(ctx->avs_lp, fp8, ctx->kvp, ctx->ksp, ctx->avs_sp, st);
+            if (e == hipSuccess) e = rom::launch_split_pack(ctx->asv_lp, fp8, ctx->ksp, ctx->kvp, ctx->asv_sp, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: split pack");
     }
     const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
@@ -379,13 +404,12 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) && ctx->state_type == ROM_F32) {
         if (rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
-        const int G = (ctx->flags & ROM_SCHED_COLUMNS) ? 0
-                      : rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
-        if (G > 0 && ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
-        if (G > 0 && ctx->sp_ok == 1) {
+        const int G = split_groups_for(ctx, M);
+        if (G > 0) {
             rom_status rs = prepare_split(ctx, G, st);
             if (rs != ROM_OK) return rs;
-            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, ctx->op_scale, ctx->sp_ws, G, ctx->status, st);
+            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, ctx->op_scale, ctx->sp_ws, G, ctx->status,
+                                        false, st);
         } else {
             a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
             e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
@@ -394,8 +418,15 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
             rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
-        a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
-        e = rom::launch_rank2_f32_mfma(a, st);
+        const int G = split_groups_for(ctx, M);
+        if (G > 0) {
+            rom_status rs = prepare_split(ctx, G, st);
+            if (rs != ROM_OK) return rs;
+            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, 1.0f, ctx->sp_ws, G, ctx->status, true, st);
+        } else {
+            a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
+            e = rom::launch_rank2_f32_mfma(a, st);
+        }
     } else {
         if (rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) > 150 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: FP64 states above the LDS-resident limit");

@@ -111,7 +111,9 @@ int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M);
 size_t rank2_split_workspace_bytes(int kvp, int G);
 hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st);
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &a, float scale, void *ws,
-                              int G, int *status, hipStream_t st);
+                              int G, int *status, bool f32, hipStream_t st);
+size_t rank2_split_f32_lds_bytes();
+hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st);
 hipError_t rank2_split_configure();
 bool rank2_split_device_ok();
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,

@@ -1,12 +1,13 @@
-"""Row-split schedule of the low-precision rank-2 run (BF16 / FP8 operators,
-FP32 states): operator rows split over the workgroups of a 64-sample group,
+"""Row-split schedule of the FP32-state rank-2 run (FP32, BF16 and FP8
+operators): operator rows split over the workgroups of a 64-sample group,
 exchanged every half-step.
 
-Parity is taken against the same-input FP64 oracle (the operators exactly as
-the products use them), with the bar of the column-block low-precision
+BF16 / FP8: parity against the same-input FP64 oracle (the operators exactly
+as the products use them), with the bar of the column-block low-precision
 kernel: each state value enters the products as a BF16 (hi, lo) pair
 (~2^-17 relative), which random-walks to ~1e-4 over a few thousand steps; the
-tests allow 2e-3.  Every run is followed by rom_check (no barrier timed out).
+tests allow 2e-3.  FP32: the FP32 bar, 1e-5.  Every run is followed by
+rom_check (no barrier timed out).
 """
 import concurrent.futures as cf
 
@@ -108,3 +109,36 @@ def test_rowsplit_k1024_m1024_sampled():
         eJ = max(abs(g["J"][ci] - r["J"][0]) / r["J"][0] for ci, r in zip(cols, refs))
         print("rowsplit %s K=M=1024 N=%d sampled: state %.2e J %.2e" % (ops, N, e, eJ))
         assert e <= BAR and eJ <= BAR
+
+
+# ---- FP32 operators (row-split FP32 kernel): the FP32 bar, 1e-5
+F32_BAR = 1e-5
+
+
+@pytest.mark.parametrize("K,M,N", [(256, 100, 2000), (512, 130, 1000)])
+def test_rowsplit_f32_parity(K, M, N):
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=2 * K + M), "f32")
+    g = _run(inst, "f32", N, "rowsplit", trace=True)
+    ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"], trace=True)
+    e = max(_relcol(g["V"], ref["V"]), _relcol(g["S"], ref["S"]))
+    eJ = float(np.max(np.abs(g["J"] - ref["J"]) / ref["J"]))
+    ey = float(np.max(np.abs(g["y"] - ref["y"])) / np.max(np.abs(ref["y"])))
+    print("rowsplit f32 K=%d M=%d N=%d: state %.2e  J %.2e  y %.2e" % (K, M, N, e, eJ, ey))
+    assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
+
+
+def test_rowsplit_f32_k1024_m1024_sampled():
+    inst = synth.round_to(synth.make_instance(1024, 1024, 1024, seed=0), "f32")
+    N = 600
+    cols = np.array([0, 333, 1023])
+    g = _run(inst, "f32", N, "auto")
+
+    def ref(ci):
+        return oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N, c=inst["c"])
+    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+        refs = list(ex.map(ref, cols))
+    e = max(max(_relcol(g["V"][:, ci:ci + 1], r["V"]), _relcol(g["S"][:, ci:ci + 1], r["S"]))
+            for ci, r in zip(cols, refs))
+    eJ = max(abs(g["J"][ci] - r["J"][0]) / r["J"][0] for ci, r in zip(cols, refs))
+    print("rowsplit f32 K=M=1024 N=%d sampled: state %.2e J %.2e" % (N, e, eJ))
+    assert e <= F32_BAR and eJ <= F32_BAR
