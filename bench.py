@@ -276,7 +276,7 @@ def workload_precision(args, torch, dev):
         peak = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}[ops]
         tf = 4.0 * K * K * M * N / ksec / 1e12
         out["runs"][ops] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf,
-                            "mfma_peak_tflops": peak, "frac": tf / peak}
+                            "mfma_peak_tflops": peak, "frac": tf / peak, "schedule": rom.last_schedule}
         rom.close()
     return out
 
@@ -360,10 +360,15 @@ def workload_sweep(args, torch, dev):
                 rom.run_rank2(mu, V, S, N)
             wall, ms = _events_time(torch, run, 3, 1)
             ksec = float(np.median(ms)) * 1e-3
-            out["points"].append({"K": K, "M": M, "nsteps": N, "rank2": M * N / ksec,
-                                  "rank2_us_per_step": ksec / N * 1e6, "rank1": r1["value"],
-                                  "rank1_streams": r1["streams"], "ratio": M * N / ksec / r1["value"],
-                                  "tflops": 4.0 * K * K * M * N / ksec / 1e12})
+            pt = {"K": K, "M": M, "nsteps": N, "rank2": M * N / ksec,
+                  "rank2_us_per_step": ksec / N * 1e6, "rank1": r1["value"],
+                  "rank1_streams": r1["streams"], "ratio": M * N / ksec / r1["value"],
+                  "tflops": 4.0 * K * K * M * N / ksec / 1e12, "schedule": rom.last_schedule}
+            try:
+                pt["tuner_us_per_step"] = rom.schedule_times(M)
+            except Exception:
+                pt["tuner_us_per_step"] = None     # row-split does not apply: column-block only
+            out["points"].append(pt)
         rom.close()
     return out
 

@@ -88,9 +88,8 @@ enum {
                                64-sample group, exchanged every half-step)
                                wherever they apply: Kv == Ks in {256, 512,
                                1024}, ceil(M/64) * K/64 <= 256, a 256-CU
-                               gfx950.  Neither flag: row-split where it
-                               applies and fills at least 128 workgroups,
-                               column-block elsewhere.                        */
+                               gfx950.  Neither flag: the schedule
+                               autotuner decides (see rom_last_schedule).    */
 };
 
 typedef struct {
@@ -154,6 +153,25 @@ rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, dou
 
 /* Release every device buffer owned by the context.  NULL is accepted. */
 rom_status rom_destroy(rom_ctx *ctx);
+
+/*
+ * Schedule of a rank-2 run with FP32 states.  Two kernel families compute
+ * it: column-block (each workgroup owns 4 samples and streams the whole
+ * operator; workgroups never wait for one another) and row-split (operator
+ * rows split over the workgroups of a 64-sample group and kept in registers
+ * or streamed per quarter, rows exchanged at a group barrier every
+ * half-step).  Without a ROM_SCHED_* flag the first run of each shape (Kv,
+ * Ks, M rounded up to 64, operator type) times both for 32 steps on scratch
+ * states and keeps the faster for the process (that run synchronises the
+ * stream; a stream being captured is not tuned and uses column-block).
+ *
+ * rom_last_schedule: 0 column-block, 1 row-split for the context's last
+ * FP32-state rank-2 run; -1 if none.  rom_schedule_times: the tuner's
+ * per-step times (microseconds) of both schedules for the context's shape at
+ * M samples; ROM_E_ARG if that shape has not been tuned.
+ */
+int32_t rom_last_schedule(rom_ctx *ctx);
+rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double *us_columns, double *us_rowsplit);
 
 /*
  * Report in-kernel failures of the work enqueued so far: synchronises

@@ -24,7 +24,8 @@ ROM_SCHED_ROWSPLIT = 4
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
-           "rom_get_operators", "rom_energy", "rom_check", "rom_last_error", "rom_version"]
+           "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
+           "rom_last_error", "rom_version"]
 
 
 class RomConfig(C.Structure):
@@ -88,6 +89,10 @@ def load():
         lib.rom_energy.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
         lib.rom_check.restype = C.c_int
         lib.rom_check.argtypes = [_vp, _vp]
+        lib.rom_last_schedule.restype = C.c_int32
+        lib.rom_last_schedule.argtypes = [_vp]
+        lib.rom_schedule_times.restype = C.c_int
+        lib.rom_schedule_times.argtypes = [_vp, _i32, C.POINTER(_d), C.POINTER(_d)]
         lib.rom_last_error.restype = C.c_char_p
         lib.rom_last_error.argtypes = []
         lib.rom_version.restype = C.c_char_p

@@ -6,7 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -97,18 +100,13 @@ void free_ctx(rom_ctx *c) {
 
 bool g_configured = false;
 
-// Row-split or column-block schedule for a rank-2 run of M samples: the
-// row-split kernel applies to Kv == Ks in {256, 512, 1024} on a 256-CU
-// gfx950; by default it is taken when its G x R workgroups fill at least
-// half of the CUs (below that the column-block kernels, which never wait
-// for one another, are faster), ROM_SCHED_ROWSPLIT takes it wherever it
-// applies and ROM_SCHED_COLUMNS never.  Returns the group count G (0 =
-// column-block).
-int split_groups_for(rom_ctx *ctx, int32_t M) {
+// Row-split groups for a rank-2 run of M samples with FP32 states, or 0 if
+// the row-split kernels do not apply (Kv == Ks in {256, 512, 1024}, at most
+// 256 workgroups, a 256-CU gfx950) or ROM_SCHED_COLUMNS forbids them.
+int split_candidate(rom_ctx *ctx, int32_t M) {
     if (ctx->flags & ROM_SCHED_COLUMNS) return 0;
     const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
     if (G == 0) return 0;
-    if (!(ctx->flags & ROM_SCHED_ROWSPLIT) && G * (ctx->kvp / rom::kTileRows) < 128) return 0;
     if (ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
     return ctx->sp_ok == 1 ? G : 0;
 }
@@ -151,6 +149,96 @@ rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
         ctx->sp_ws_bytes = need;
     }
     return ROM_OK;
+}
+
+// Launch one rank-2 run with FP32 states on the chosen schedule.
+rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, bool split, int G, hipStream_t st) {
+    hipError_t e;
+    const bool lowp = ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3;
+    if (split) {
+        rom_status rs = prepare_split(ctx, G, st);
+        if (rs != ROM_OK) return rs;
+        e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, lowp ? ctx->op_scale : 1.0f, ctx->sp_ws, G,
+                                    ctx->status, !lowp, st);
+    } else if (lowp) {
+        a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
+        e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
+    } else {
+        a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
+        e = rom::launch_rank2_f32_mfma(a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: launch");
+    return ROM_OK;
+}
+
+// Schedule autotuner.  The faster of the column-block and row-split kernels
+// depends on K, M and the operator type in ways a fixed rule misses (the
+// row-split kernel pays two group barriers per step but streams no
+// operator; the column-block kernels never wait but stream the whole
+// operator per CU).  On the first automatic run of a shape (Kv_pad, Ks_pad,
+// M rounded up to the 64-sample group, operator type) both schedules run
+// kTuneSteps steps on scratch states (after a warm-up launch each), timed
+// with events on the caller's stream, and the faster one is remembered for
+// the process.  That first run synchronises the stream; a stream being
+// captured is never tuned (the column-block kernels are used until an
+// eager run has tuned the shape).
+struct TuneKey {
+    int kvp, ksp, mpad, op;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(kvp, ksp, mpad, op) < std::tie(o.kvp, o.ksp, o.mpad, o.op);
+    }
+};
+struct TuneEntry {
+    int split;
+    float us_columns, us_split;   // per step
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+constexpr int kTuneSteps = 32;
+
+rom_status tune_schedule(rom_ctx *ctx, const rom::Rank2Args &run, int G, hipStream_t st, TuneEntry &out) {
+    const size_t vb = sizeof(float) * (size_t)ctx->kv * run.M, sb = sizeof(float) * (size_t)ctx->ks * run.M;
+    void *V = nullptr, *S = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best[2] = {0.f, 0.f};
+    rom_status rs = ROM_OK;
+    hipError_t e = hipMalloc(&V, vb);
+    if (e == hipSuccess) e = hipMalloc(&S, sb);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rs = hip_fail(e, "rom_run_rank2: schedule tuning setup");
+    rom::Rank2Args a = run;
+    a.V = V; a.S = S; a.c = nullptr; a.J = nullptr; a.y = nullptr; a.n0 = 0;
+    for (int split = 0; split < 2 && rs == ROM_OK; ++split) {
+        best[split] = 1e30f;
+        for (int rep = 0; rep < 3 && rs == ROM_OK; ++rep) {   // rep 0: warm-up
+            e = hipMemsetAsync(V, 0, vb, st);
+            if (e == hipSuccess) e = hipMemsetAsync(S, 0, sb, st);
+            if (e != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: schedule tuning"); break; }
+            a.nsteps = rep == 0 ? 2 : kTuneSteps;
+            if (rep > 0 && (e = hipEventRecord(e0, st)) != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: tuning"); break; }
+            rs = launch_fp32_state_run(ctx, a, split == 1, G, st);
+            if (rs != ROM_OK) break;
+            if (rep > 0) {
+                float ms = 0.f;
+                e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: tuning"); break; }
+                best[split] = std::min(best[split], ms * 1e3f / kTuneSteps);
+            }
+        }
+    }
+    if (rs == ROM_OK) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rs = hip_fail(e, "rom_run_rank2: tuning");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    hfree(V);
+    hfree(S);
+    if (rs == ROM_OK) out = TuneEntry{best[1] < best[0] ? 1 : 0, best[0], best[1]};
+    return rs;
 }
 
 }  // namespace
@@ -344,6 +432,20 @@ rom_status rom_destroy(rom_ctx *ctx) {
     return ROM_OK;
 }
 
+int32_t rom_last_schedule(rom_ctx *ctx) { return ctx ? ctx->last_schedule : -1; }
+
+rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double *us_columns, double *us_rowsplit) {
+    if (!ctx || M < 1 || !us_columns || !us_rowsplit) return fail(ROM_E_ARG, "rom_schedule_times: bad argument");
+    const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(M, 64), (int)ctx->op_type};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end() || it->second.split < 0)
+        return fail(ROM_E_ARG, "rom_schedule_times: this shape has not been tuned");
+    *us_columns = it->second.us_columns;
+    *us_rowsplit = it->second.us_split;
+    return ROM_OK;
+}
+
 rom_status rom_check(rom_ctx *ctx, void *stream) {
     if (!ctx) return fail(ROM_E_ARG, "rom_check: NULL context");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -401,32 +503,41 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3) && ctx->state_type == ROM_F32) {
-        if (rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
+    if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3 || ctx->op_type == ROM_F32) &&
+        ctx->state_type == ROM_F32) {
+        const bool lowp = ctx->op_type != ROM_F32;
+        if (lowp && rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
-        const int G = split_groups_for(ctx, M);
-        if (G > 0) {
-            rom_status rs = prepare_split(ctx, G, st);
-            if (rs != ROM_OK) return rs;
-            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, ctx->op_scale, ctx->sp_ws, G, ctx->status,
-                                        false, st);
-        } else {
-            a.avs = ctx->avs_lp; a.asv = ctx->asv_lp;
-            e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
-        }
-    } else if (ctx->state_type == ROM_F32) {
-        if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
-            rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
+        if (!lowp && (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
+                      rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024))
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
-        const int G = split_groups_for(ctx, M);
+        const int G = split_candidate(ctx, M);
+        bool split = false;
         if (G > 0) {
-            rom_status rs = prepare_split(ctx, G, st);
-            if (rs != ROM_OK) return rs;
-            e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, 1.0f, ctx->sp_ws, G, ctx->status, true, st);
-        } else {
-            a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
-            e = rom::launch_rank2_f32_mfma(a, st);
+            if (ctx->flags & ROM_SCHED_ROWSPLIT) {
+                split = true;
+            } else {
+                const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(M, 64), (int)ctx->op_type};
+                TuneEntry te{-1, 0.f, 0.f};
+                {
+                    std::lock_guard<std::mutex> lk(g_tune_mu);
+                    auto it = g_tune.find(key);
+                    if (it != g_tune.end()) te = it->second;
+                }
+                if (te.split < 0) {
+                    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+                        rom_status rs = tune_schedule(ctx, a, G, st, te);
+                        if (rs != ROM_OK) return rs;
+                        std::lock_guard<std::mutex> lk(g_tune_mu);
+                        g_tune[key] = te;
+                    }
+                }
+                split = te.split == 1;
+            }
         }
+        ctx->last_schedule = split ? 1 : 0;
+        return launch_fp32_state_run(ctx, a, split, G, st);
     } else {
         if (rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) > 150 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: FP64 states above the LDS-resident limit");

@@ -59,6 +59,9 @@ struct rom_ctx {
     void *sp_ws = nullptr;
     size_t sp_ws_bytes = 0;
     int sp_ok = -1;
+    // Schedule of the last FP32-state rank-2 run (0 column-block, 1
+    // row-split, -1 none yet).
+    int last_schedule = -1;
     // Device status words: [0] scratch of rom_create, [1] in-kernel error
     // (ROM_E_TIMEOUT), [2] abort flag of the row-split barriers.
     int *status = nullptr;

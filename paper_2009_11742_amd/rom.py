@@ -70,6 +70,19 @@ class Rom:
         enqueued so far timed out (ROM_E_TIMEOUT; results invalid)."""
         check(_lib.load().rom_check(self._ctx, _stream_handle(stream)))
 
+    @property
+    def last_schedule(self):
+        """'columns' or 'rowsplit' for the last FP32-state rank-2 run (None if none)."""
+        v = _lib.load().rom_last_schedule(self._ctx)
+        return {0: "columns", 1: "rowsplit"}.get(v)
+
+    def schedule_times(self, M):
+        """The schedule autotuner's per-step times in microseconds,
+        {'columns': t, 'rowsplit': t}, for this context's shape at M samples."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        check(_lib.load().rom_schedule_times(self._ctx, int(M), C.byref(a), C.byref(b)))
+        return {"columns": a.value, "rowsplit": b.value}
+
     def operators(self):
         """(Avs, Asv, scale) exactly as the products use them (float64 numpy)."""
         A = np.zeros((self.kv, self.ks), order="F")

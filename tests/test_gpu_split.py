@@ -142,3 +142,28 @@ def test_rowsplit_f32_k1024_m1024_sampled():
     eJ = max(abs(g["J"][ci] - r["J"][0]) / r["J"][0] for ci, r in zip(cols, refs))
     print("rowsplit f32 K=M=1024 N=%d sampled: state %.2e J %.2e" % (N, e, eJ))
     assert e <= F32_BAR and eJ <= F32_BAR
+
+
+@pytest.mark.parametrize("K,M,ops", [(1024, 1024, "f32"), (256, 256, "f32"), (512, 512, "bf16")])
+def test_schedule_autotuner(K, M, ops):
+    """Without a schedule flag the first run of a shape times both schedules
+    and keeps the faster; the run that follows uses it and is correct."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=7), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(M)
+    N = 200
+    rom.run_rank2(mu, V, S, N)
+    rom.check()
+    t = rom.schedule_times(M)
+    chosen = rom.last_schedule
+    print("autotuner K=%d M=%d %s: columns %.2f us/step, rowsplit %.2f us/step -> %s"
+          % (K, M, ops, t["columns"], t["rowsplit"], chosen))
+    assert chosen == ("rowsplit" if t["rowsplit"] < t["columns"] else "columns")
+    A, B, _ = rom.operators()
+    col = M // 3
+    r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"][col:col + 1], N)
+    bar = F32_BAR if ops == "f32" else BAR
+    assert _relcol(V.cpu().numpy().astype(np.float64).T[:, col:col + 1], r["V"]) <= bar
+    rom.close()
