@@ -282,30 +282,50 @@ def workload_precision(args, torch, dev):
 
 
 def workload_grouped(args, torch, dev):
-    """64 instances, K in {128..768}, M log-uniform in [16, 512], 4000 steps."""
+    """64 instances, K in {128..768}, M log-uniform in [16, 512], 4000 steps.
+    The headline run takes each instance's column tile (4 or 8 samples per
+    workgroup) from the tile autotuner; all-4 and all-8 runs are timed beside
+    it, and the tuner's per-bucket tile table is reported."""
     import synth
-    from paper_2009_11742_amd import GroupPlan, Rom
+    from paper_2009_11742_amd import GroupPlan, Rom, tuning
     N = 4000
     draws = synth.grouped_draws(64, base_seed=0)
-    roms, mus, Vs, Ss, flops, ss = [], [], [], [], 0.0, 0
+    insts, flops, ss = [], 0.0, 0
     for K, M, seed in draws:
-        inst = synth.round_to(synth.make_instance(K, K, M, seed=seed), "f32")
-        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
-        V, S = rom.zeros(M, device=dev)
-        roms.append(rom); Vs.append(V); Ss.append(S)
-        mus.append(torch.tensor(inst["mu"], dtype=torch.float64, device=dev))
+        insts.append(synth.round_to(synth.make_instance(K, K, M, seed=seed), "f32"))
         flops += 4.0 * K * K * M * N
         ss += M * N
-    plan = GroupPlan(roms, mus, Vs, Ss)
+    mus = [torch.tensor(inst["mu"], dtype=torch.float64, device=dev) for inst in insts]
 
-    def run():
-        plan.run(N)
-    wall, ms = _events_time(torch, run, 3, 1)
-    ksec = float(np.median(ms)) * 1e-3
+    def timed(schedule):
+        roms, Vs, Ss = [], [], []
+        for inst in insts:
+            rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=schedule)
+            V, S = rom.zeros(len(inst["mu"]), device=dev)
+            roms.append(rom); Vs.append(V); Ss.append(S)
+        plan = GroupPlan(roms, mus, Vs, Ss)
+        wall, ms = _events_time(torch, lambda: plan.run(N), 3, 1)
+        plan.close()
+        for r in roms:
+            r.close()
+        return float(np.median(ms)) * 1e-3
+
+    ksec = timed("auto")
+    fixed = {"4": timed("columns") * 1e3, "8": timed("columns8") * 1e3}
+    table = {}
+    for d in tuning.entries():
+        if d["m_pad"] == 0 and d["kv_pad"] == d["ks_pad"]:
+            table[d["kv_pad"]] = {"us_wg_4": round(d["us"][0], 3), "us_wg_8": round(d["us"][2], 3)}
+    n8 = 0
+    for (K, M, _), inst in zip(draws, insts):
+        t = table.get(-(-K // 64) * 64)
+        if t and 0 <= t["us_wg_8"] and -(-M // 8) * t["us_wg_8"] < -(-M // 4) * t["us_wg_4"]:
+            n8 += 1
     out = {"workload": "grouped: 64 instances, K in {128..768}, M log-uniform [16,512], 4000 steps",
            "value": ss / ksec, "unit": "sample-steps/s", "tflops": flops / ksec / 1e12,
-           "frac_fp32_mfma": flops / ksec / 1e12 / 157.3, "ms_per_run": ksec * 1e3}
-    plan.close()
+           "frac_fp32_mfma": flops / ksec / 1e12 / 157.3, "ms_per_run": ksec * 1e3,
+           "ms_per_run_fixed_tile": fixed, "instances_on_8_column_tiles": n8,
+           "tile_table_us_per_workgroup_step": table}
     return out
 
 

@@ -80,16 +80,20 @@ enum {
                                leapfrog's discrete energy); ROM_E_UNSTABLE
                                otherwise.  Non-skew pairs are not checked.   */
     ROM_SCHED_COLUMNS = 2u, /* FP32-state rank-2 runs (FP32, BF16, FP8
-                               operators): always the column-block kernels
-                               (each workgroup owns 4 samples and the whole
-                               operator)                                      */
-    ROM_SCHED_ROWSPLIT = 4u /* FP32-state rank-2 runs: the row-split kernels
+                               operators): always the 4-column column-block
+                               kernels (each workgroup owns 4 samples and
+                               streams the whole operator)                    */
+    ROM_SCHED_ROWSPLIT = 4u,/* FP32-state rank-2 runs: the row-split kernels
                                (operator rows split over the workgroups of a
                                64-sample group, exchanged every half-step)
                                wherever they apply: Kv == Ks in {256, 512,
                                1024}, ceil(M/64) * K/64 <= 256, a 256-CU
-                               gfx950.  Neither flag: the schedule
-                               autotuner decides (see rom_last_schedule).    */
+                               gfx950; else 4-column blocks                   */
+    ROM_SCHED_COLUMNS8 = 8u /* FP32 operators and states: 8-column blocks
+                               (two column sets per operator fragment) where
+                               the states of 8 samples fit in LDS; else 4.
+                               At most one ROM_SCHED_* flag; none: the
+                               schedule autotuner decides (rom_last_schedule)*/
 };
 
 typedef struct {
@@ -155,23 +159,66 @@ rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, dou
 rom_status rom_destroy(rom_ctx *ctx);
 
 /*
- * Schedule of a rank-2 run with FP32 states.  Two kernel families compute
- * it: column-block (each workgroup owns 4 samples and streams the whole
- * operator; workgroups never wait for one another) and row-split (operator
- * rows split over the workgroups of a 64-sample group and kept in registers
- * or streamed per quarter, rows exchanged at a group barrier every
- * half-step).  Without a ROM_SCHED_* flag the first run of each shape (Kv,
- * Ks, M rounded up to 64, operator type) times both for 32 steps on scratch
- * states and keeps the faster for the process (that run synchronises the
- * stream; a stream being captured is not tuned and uses column-block).
+ * Schedule of a rank-2 run with FP32 states.  Three kernel schedules
+ * compute it with the same per-sample results up to rounding order:
+ *   ROM_SCHEDULE_COLUMNS4  each workgroup owns 4 samples and streams the
+ *                          whole operator; workgroups never wait for one
+ *                          another;
+ *   ROM_SCHEDULE_ROWSPLIT  operator rows split over the workgroups of a
+ *                          64-sample group, kept in registers or streamed
+ *                          per quarter, rows exchanged at a group barrier
+ *                          every half-step;
+ *   ROM_SCHEDULE_COLUMNS8  as COLUMNS4 with 8 samples per workgroup (FP32
+ *                          operators): half the operator bytes per flop,
+ *                          half the workgroups.  Bitwise equal to COLUMNS4.
+ * Without a ROM_SCHED_* flag the first run of each shape (Kv_pad, Ks_pad, M
+ * rounded up to 64, operator type) times every schedule that applies for 32
+ * steps on scratch states and keeps the fastest for the process (that run
+ * synchronises the stream; a stream being captured is not tuned and uses
+ * COLUMNS4), unless the process-wide tuning table already holds the shape.
  *
- * rom_last_schedule: 0 column-block, 1 row-split for the context's last
- * FP32-state rank-2 run; -1 if none.  rom_schedule_times: the tuner's
- * per-step times (microseconds) of both schedules for the context's shape at
- * M samples; ROM_E_ARG if that shape has not been tuned.
+ * The grouped launch (rom_run_grouped, rom_group_create) picks each
+ * instance's column tile (4 or 8 samples) from the per-workgroup step times
+ * of its (Kv_pad, Ks_pad) bucket, tuned on first use (one workgroup, 256
+ * steps per tile) and kept in the same table with m_pad = 0; the instance
+ * takes the tile minimising ceil(M / tile) x time.  A context flag
+ * ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8 fixes the instance's tile.
+ *
+ * rom_last_schedule: the schedule of the context's last FP32-state rank-2
+ * run; -1 if none.  rom_schedule_times: the table's per-step times
+ * (microseconds) of each schedule for the context's shape at M samples,
+ * negative where a schedule does not apply; ROM_E_ARG if that shape is not
+ * in the table.
+ *
+ * Tuning table: rom_tune_count / rom_tune_get export the process-wide
+ * entries (index order is the key order), rom_tune_put adds or replaces one
+ * (its schedule must be one that applies when a run uses it; a run whose
+ * table schedule does not apply falls back to COLUMNS4), rom_tune_clear
+ * empties the table.  The table is shared by all contexts and threads.
  */
+typedef enum {
+    ROM_SCHEDULE_COLUMNS4 = 0,
+    ROM_SCHEDULE_ROWSPLIT = 1,
+    ROM_SCHEDULE_COLUMNS8 = 2
+} rom_schedule;
+#define ROM_NSCHEDULES 3
+
+typedef struct {
+    int32_t kv_pad, ks_pad; /* Kv, Ks rounded up to multiples of 64           */
+    int32_t m_pad;          /* M rounded up to a multiple of 64; 0: grouped
+                               per-workgroup tile entry                        */
+    rom_dtype op_type;      /* operator type of the shape                      */
+    int32_t schedule;       /* rom_schedule chosen                             */
+    double us[ROM_NSCHEDULES]; /* per-step time of each schedule (us), < 0 if
+                               not applicable or not measured                  */
+} rom_tune_entry;
+
 int32_t rom_last_schedule(rom_ctx *ctx);
-rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double *us_columns, double *us_rowsplit);
+rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double us[ROM_NSCHEDULES]);
+int32_t rom_tune_count(void);
+rom_status rom_tune_get(int32_t i, rom_tune_entry *out);
+rom_status rom_tune_put(const rom_tune_entry *e);
+void rom_tune_clear(void);
 
 /*
  * Report in-kernel failures of the work enqueued so far: synchronises
@@ -252,11 +299,13 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
  * Grouped run: G independent ROM instances (each its own context, sizes and
  * samples) advanced `nsteps` steps from step 0 in ONE launch — the batched
  * direction the paper names for many operator realisations (Sec. 5).  Work
- * items are (instance, 4-sample column block) pairs dispatched largest
- * operator first.  All contexts must have F32 states and operators, within
- * the LDS-resident size limit.  Per instance i: M[i] samples, mu[i] dev FP64,
- * V[i] / S[i] dev states as in rom_run_rank2 (host arrays of pointers).
- * Each instance's result is bitwise identical to its own rom_run_rank2.
+ * items are (instance, column block of 4 or 8 samples: see the tile
+ * autotuner above) pairs, dispatched longest tuned step time first.  All
+ * contexts must have F32 states and operators, within the LDS-resident size
+ * limit.  Per instance i: M[i] samples, mu[i] dev FP64, V[i] / S[i] dev
+ * states as in rom_run_rank2 (host arrays of pointers).  Each instance's
+ * result is bitwise identical to its own rom_run_rank2 on a column-block
+ * schedule.
  * The call uploads a small descriptor table with one stream synchronisation;
  * use the plan API below for asynchronous or graph-captured runs.
  */

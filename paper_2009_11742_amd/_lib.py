@@ -20,17 +20,26 @@ ROM_F64, ROM_F32, ROM_BF16, ROM_F8E4M3 = range(4)
 ROM_SKEW_CHECK = 1
 ROM_SCHED_COLUMNS = 2
 ROM_SCHED_ROWSPLIT = 4
+ROM_SCHED_COLUMNS8 = 8
+ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8 = range(3)
+ROM_NSCHEDULES = 3
 
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
+           "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear",
            "rom_last_error", "rom_version"]
 
 
 class RomConfig(C.Structure):
     _fields_ = [("kv", C.c_int32), ("ks", C.c_int32), ("dt", C.c_double),
                 ("op_type", C.c_int), ("state_type", C.c_int), ("flags", C.c_uint32)]
+
+
+class RomTuneEntry(C.Structure):
+    _fields_ = [("kv_pad", C.c_int32), ("ks_pad", C.c_int32), ("m_pad", C.c_int32),
+                ("op_type", C.c_int), ("schedule", C.c_int32), ("us", C.c_double * ROM_NSCHEDULES)]
 
 
 class RomError(RuntimeError):
@@ -92,7 +101,15 @@ def load():
         lib.rom_last_schedule.restype = C.c_int32
         lib.rom_last_schedule.argtypes = [_vp]
         lib.rom_schedule_times.restype = C.c_int
-        lib.rom_schedule_times.argtypes = [_vp, _i32, C.POINTER(_d), C.POINTER(_d)]
+        lib.rom_schedule_times.argtypes = [_vp, _i32, C.POINTER(_d)]
+        lib.rom_tune_count.restype = C.c_int32
+        lib.rom_tune_count.argtypes = []
+        lib.rom_tune_get.restype = C.c_int
+        lib.rom_tune_get.argtypes = [_i32, C.POINTER(RomTuneEntry)]
+        lib.rom_tune_put.restype = C.c_int
+        lib.rom_tune_put.argtypes = [C.POINTER(RomTuneEntry)]
+        lib.rom_tune_clear.restype = None
+        lib.rom_tune_clear.argtypes = []
         lib.rom_last_error.restype = C.c_char_p
         lib.rom_last_error.argtypes = []
         lib.rom_version.restype = C.c_char_p

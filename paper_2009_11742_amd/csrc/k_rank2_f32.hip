@@ -5,15 +5,18 @@
 //     V <- V + dt (Avs S + b u(t_n; mu)^T)      then      S <- S + dt Asv V .
 //
 // Decomposition (MI355X): the sample columns are independent, so each
-// workgroup owns kColBlock (4) columns for the WHOLE run and never talks to
-// another workgroup: no grid or group barrier is needed (a cross-workgroup
+// workgroup owns 4 or 8 columns (one or two column sets) for the WHOLE run
+// and never talks to another workgroup: no grid or group barrier is needed (a cross-workgroup
 // barrier costs about 1 us on this part, more than the products of one
 // half-step).  The workgroup keeps its V and S columns, plus a compensation
 // word per entry, resident in LDS; every half-step it streams the packed
 // operator panels from L2 (the operators stay L2 resident across steps) and
 // multiplies them with v_mfma_f32_4x4x1f32, whose 16 blocks cover a 64-row
 // tile x 4 columns per instruction (lane l holds operator row l of the tile,
-// the B operand is the state column l % 4 broadcast from LDS).
+// the B operand is the state column l % 4 broadcast from LDS).  The
+// streamed operator bytes per CU, not the MFMAs, bound a 4-column block;
+// an 8-column block reuses each operator fragment for two MFMAs and pays
+// off wherever there are more blocks than CUs.
 //
 // The same kernel, in adjoint mode, runs the discrete adjoint of that step
 // backwards in time (see the adjoint entry point): the adjoint state (P, Q)
@@ -38,36 +41,29 @@ enum Mode { kForward = 0, kAdjoint = 1 };
 
 // One half-step of one field: wave w owns row tiles w, w + 4, ...  Ends
 // with a barrier (the other half-step reads every row of this field).
-template <bool FORCED>
-__device__ __forceinline__ void half_step(const Field &f, const f4 (&res)[2 * kResPairs][kQ],
+template <bool FORCED, int NS>
+__device__ __forceinline__ void half_step(const Field &f, const f4 (&res)[2 * res_pairs(NS)][kQ],
                                           f4 (&a0)[kQ], f4 (&a1)[kQ], Stream &s,
                                           const Field &fv, const Field &fs, int lane, int w,
-                                          const float *bl, const float *cl, double u, double dt,
-                                          double &ypart) {
+                                          const float *bl, const float *cl, const double (&u)[NS],
+                                          double dt, double (&ypart)[NS]) {
     const int j = lane & 3;
     for (int t = w; t < f.T; t += kWaves) {
-        double acc[4];
-        tile_product(f, f.X + j * f.ldx, res, t == w ? f.rp : 0, a0, a1, s, fv, fs, w, lane, acc);
-        finish_tile<FORCED>(f, t, acc, lane, bl, cl, u, dt, ypart);
+        double acc[NS][4];
+        tile_product<NS>(f, f.X + j * f.ldx, res, t == w ? f.rp : 0, a0, a1, s, fv, fs, w, lane, acc);
+        finish_tile<FORCED, NS>(f, t, acc, lane, bl, cl, u, dt, ypart);
     }
     __syncthreads();
 }
 
-// Copy the (hi + lo) LDS columns of this workgroup to a K x M global matrix.
+// Copy the (hi + lo) LDS columns (nb of them) of this workgroup to a K x M
+// global matrix.
 __device__ __forceinline__ void store_cols(float *dst, const float *hi, const float *lo, int ld,
-                                           int K, int Kp, int col0, int M, int tid) {
-    for (int idx = tid; idx < NB * Kp; idx += kThreads) {
+                                           int K, int Kp, int col0, int M, int nb, int tid) {
+    for (int idx = tid; idx < nb * Kp; idx += kThreads) {
         int jj = idx / Kp, i = idx - jj * Kp, mm = col0 + jj;
         if (mm < M && i < K) dst[(size_t)mm * K + i] = hi[jj * ld + i] + lo[jj * ld + i];
     }
-}
-
-// Sum the per-wave probe partials written to yp (after a barrier).
-__device__ __forceinline__ double wave_sum(const double *yp, int jcol) {
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) v += yp[q * NB + jcol];
-    return v;
 }
 
 // One workgroup per CU, one wave per SIMD: the compiler may use the whole
@@ -77,21 +73,22 @@ __device__ __forceinline__ double wave_sum(const double *yp, int jcol) {
 // Forward: (V, S) = (a.V, a.S), operators (Avs, Asv) packed, source b,
 //   probe c; optional state traces a.vtr / a.str (entry k = state after k
 //   steps, k = 0..nsteps).
-// Adjoint: (P, Q) = (a.V, a.S), operators (Asv^T, Avs^T) packed, source c
-//   with amplitude 2 y (y = the forward probe trace a.ytr), probe b; step
-//   n = n0 + nsteps - 1 - k at iteration k; writes a.qtr[n - n0] = Q before
-//   and a.wtr[n - n0] = P after the P update, and adds
-//   dt (b^T P) du/dmu(t_n) to a.dmu.
-template <int MODE>
+// Adjoint (NS = 1): (P, Q) = (a.V, a.S), operators (Asv^T, Avs^T) packed,
+//   source c with amplitude 2 y (y = the forward probe trace a.ytr), probe
+//   b; step n = n0 + nsteps - 1 - k at iteration k; writes
+//   a.qtr[n - n0] = Q before and a.wtr[n - n0] = P after the P update, and
+//   adds dt (b^T P) du/dmu(t_n) to a.dmu.
+template <int MODE, int NS>
 __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned char *smem) {
+    constexpr int NC = NB * NS;                  // columns of this workgroup
     const int kvp = a.kvp, ksp = a.ksp;
     const int ldv = kvp + 4, lds_ = ksp + 4;     // +4 floats: spread columns over banks
     float *Vh = reinterpret_cast<float *>(smem);
-    float *Vl = Vh + NB * ldv;
-    float *Sh = Vl + NB * ldv;
-    float *Sl = Sh + NB * lds_;
-    double *yp = reinterpret_cast<double *>(Sl + NB * lds_);   // [kWaves][NB]
-    float *bl = reinterpret_cast<float *>(yp + kWaves * NB);    // source, kvp
+    float *Vl = Vh + NC * ldv;
+    float *Sh = Vl + NC * ldv;
+    float *Sl = Sh + NC * lds_;
+    double *yp = reinterpret_cast<double *>(Sl + NC * lds_);   // [kWaves][NC]
+    float *bl = reinterpret_cast<float *>(yp + kWaves * NC);    // source, kvp
     float *cl = bl + kvp;                                         // probe, kvp (0 if none)
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -101,12 +98,12 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     const float *bv = static_cast<const float *>(a.b);
     const float *cv = static_cast<const float *>(a.c);
 
-    for (int idx = tid; idx < NB * kvp; idx += kThreads) {
+    for (int idx = tid; idx < NC * kvp; idx += kThreads) {
         int jj = idx / kvp, i = idx - jj * kvp, mm = col0 + jj;
         Vh[jj * ldv + i] = (mm < a.M && i < a.kv) ? Vin[(size_t)mm * a.kv + i] : 0.f;
         Vl[jj * ldv + i] = 0.f;
     }
-    for (int idx = tid; idx < NB * ksp; idx += kThreads) {
+    for (int idx = tid; idx < NC * ksp; idx += kThreads) {
         int jj = idx / ksp, i = idx - jj * ksp, mm = col0 + jj;
         Sh[jj * lds_ + i] = (mm < a.M && i < a.ks) ? Sin[(size_t)mm * a.ks + i] : 0.f;
         Sl[jj * lds_ + i] = 0.f;
@@ -120,56 +117,74 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     }
 
     const int j = lane & 3;            // column of this lane in the MFMA output
-    const int m = col0 + j;
-    const bool mok = m < a.M;
-    const double muj = mok ? a.mu[m] : 1.0;
+    int m[NS];
+    bool mok[NS];
+    double muj[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        m[q] = col0 + j + 4 * q;
+        mok[q] = m[q] < a.M;
+        muj[q] = mok[q] ? a.mu[m[q]] : 1.0;
+    }
     const bool probe = prb != nullptr;
     double Jacc = 0.0;
     const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, ksp / kChunk,
-                      resident_pairs(ksp / kChunk), Sh, lds_, Vh, Vl, ldv};
+                      resident_pairs(ksp / kChunk, NS), Sh, lds_, Vh, Vl, ldv};
     const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, kvp / kChunk,
-                      resident_pairs(kvp / kChunk), Vh, ldv, Sh, Sl, lds_};
-    f4 resv[2 * kResPairs][kQ], ress[2 * kResPairs][kQ];
-    load_resident(resv, fv, w, lane);
-    load_resident(ress, fs, w, lane);
+                      resident_pairs(kvp / kChunk, NS), Vh, ldv, Sh, Sl, lds_};
+    f4 resv[2 * res_pairs(NS)][kQ], ress[2 * res_pairs(NS)][kQ];
+    load_resident<NS>(resv, fv, w, lane);
+    load_resident<NS>(ress, fs, w, lane);
     f4 a0[kQ], a1[kQ];
     Stream str;
     stream_start(str, a0, a1, fv, fs, w, lane);
     __syncthreads();
     if (MODE == kForward && a.vtr) {
-        store_cols(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
-        store_cols(a.str, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+        store_cols(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
+        store_cols(a.str, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
     }
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const int64_t n = MODE == kForward ? a.n0 + k : a.n0 + a.nsteps - 1 - k;
         const int64_t r = n - a.n0;                    // trace row of step n
         const double t = (double)n * a.dt;
-        double u64;
-        if (MODE == kForward) {
-            u64 = mok ? dev::ricker(t, muj) : 0.0;
-        } else {
-            u64 = mok ? 2.0 * a.ytr[(size_t)r * a.M + m] : 0.0;
-            // q^{n+1}, paired with V^{n+1} in the dAsv product
-            store_cols(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+        double u64[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            if (MODE == kForward)
+                u64[q] = mok[q] ? dev::ricker(t, muj[q]) : 0.0;
+            else
+                u64[q] = mok[q] ? 2.0 * a.ytr[(size_t)r * a.M + m[q]] : 0.0;
         }
+        if (MODE == kAdjoint)   // q^{n+1}, paired with V^{n+1} in the dAsv product
+            store_cols(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
 
         // ---- first half-step: V += dt (Avs S + b u^T)   |   P += dt (Asv^T Q + 2 y c)
-        double ypart = 0.0;
-        half_step<true>(fv, resv, a0, a1, str, fv, fs, lane, w, bl, cl, u64, a.dt, ypart);
+        double ypart[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) ypart[q] = 0.0;
+        half_step<true, NS>(fv, resv, a0, a1, str, fv, fs, lane, w, bl, cl, u64, a.dt, ypart);
         if (probe) {
-            // sum over the 16 lanes that share column j (lane bits 2..5)
-            for (int off = 4; off < 64; off <<= 1) ypart += __shfl_xor(ypart, off, 64);
-            if (lane < NB) yp[w * NB + lane] = ypart;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                // sum over the 16 lanes that share column j (lane bits 2..5)
+                double v = ypart[q];
+                for (int off = 4; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+                if (lane < NB) yp[w * NC + 4 * q + lane] = v;
+            }
         }
         if (MODE == kAdjoint)   // w^n, paired with S^n in the dAvs product
-            store_cols(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
+            store_cols(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
         // ---- second half-step: S += dt Asv V   |   Q += dt Avs^T P
         // (its barrier also publishes yp before it is read below)
-        double dummy = 0.0;
-        half_step<false>(fs, ress, a0, a1, str, fv, fs, lane, w, bl, cl, 0.0, a.dt, dummy);
-        if (probe && tid < NB && col0 + tid < a.M) {
-            const double yv = wave_sum(yp, tid);
+        double zero[NS], dummy[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) zero[q] = dummy[q] = 0.0;
+        half_step<false, NS>(fs, ress, a0, a1, str, fv, fs, lane, w, bl, cl, zero, a.dt, dummy);
+        if (probe && tid < NC && col0 + tid < a.M) {
+            double yv = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) yv += yp[q * NC + tid];
             if (MODE == kForward) {
                 Jacc += a.dt * (yv * yv);
                 if (a.y) a.y[(size_t)k * a.M + col0 + tid] = yv;
@@ -178,29 +193,30 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
             }
         }
         if (MODE == kForward && a.vtr) {
-            store_cols(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
-            store_cols(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+            store_cols(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
+            store_cols(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
         }
     }
 
-    store_cols(static_cast<float *>(a.V), Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
-    store_cols(static_cast<float *>(a.S), Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
-    if (probe && tid < NB && col0 + tid < a.M) {
+    store_cols(static_cast<float *>(a.V), Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
+    store_cols(static_cast<float *>(a.S), Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
+    if (probe && tid < NC && col0 + tid < a.M) {
         if (MODE == kForward && a.J) a.J[col0 + tid] += Jacc;
         if (MODE == kAdjoint && a.dmu) a.dmu[col0 + tid] += Jacc;
     }
 }
 
-template <int MODE>
+template <int MODE, int NS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_f32_mfma_kernel(Rank2Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_block<MODE>(a, blockIdx.x * NB, smem);
+    run_block<MODE, NS>(a, blockIdx.x * NB * NS, smem);
 }
 
-// Grouped forward run: workgroup i advances column block items[i].y of
-// instance items[i].x (items ordered by decreasing cost by the host, so the
-// largest blocks are dispatched first).
+// Grouped forward run: workgroup i advances the column block of instance
+// items[i].x that starts at column items[i].y, with the instance's column
+// sets (a.nset); items are ordered by decreasing cost by the host, so the
+// largest blocks are dispatched first.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void grouped_f32_mfma_kernel(const Rank2Args *__restrict__ inst, const int2 *__restrict__ items,
                              int64_t n0, int64_t nsteps) {
@@ -209,24 +225,33 @@ void grouped_f32_mfma_kernel(const Rank2Args *__restrict__ inst, const int2 *__r
     Rank2Args a = inst[it.x];
     a.n0 = n0;
     a.nsteps = nsteps;
-    run_block<kForward>(a, it.y * NB, smem);
+    if (a.nset == 2)
+        run_block<kForward, 2>(a, it.y, smem);
+    else
+        run_block<kForward, 1>(a, it.y, smem);
 }
 
 }  // namespace
 
-size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp) { return state_lds_bytes(kvp, ksp); }
+size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp, int nset) {
+    return state_lds_bytes(kvp, ksp, NB * nset);
+}
 
-hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st) {
-    const int blocks = (a.M + NB - 1) / NB;
-    const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp);
-    hipLaunchKernelGGL(rank2_f32_mfma_kernel<kForward>, dim3(blocks), dim3(kThreads), lds, st, a);
+hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st) {
+    const int nc = NB * nset;
+    const int blocks = (a.M + nc - 1) / nc;
+    const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, nset);
+    if (nset == 2)
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 2>), dim3(blocks), dim3(kThreads), lds, st, a);
+    else
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1>), dim3(blocks), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st) {
     const int blocks = (a.M + NB - 1) / NB;
-    const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp);
-    hipLaunchKernelGGL(rank2_f32_mfma_kernel<kAdjoint>, dim3(blocks), dim3(kThreads), lds, st, a);
+    const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1);
+    hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1>), dim3(blocks), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -239,14 +264,15 @@ hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_
 }
 
 hipError_t rank2_f32_mfma_configure() {
-    hipError_t g = hipFuncSetAttribute((const void *)grouped_f32_mfma_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (g != hipSuccess) return g;
-    hipError_t e = hipFuncSetAttribute((const void *)rank2_f32_mfma_kernel<kForward>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)rank2_f32_mfma_kernel<kAdjoint>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *fns[] = {(const void *)grouped_f32_mfma_kernel,
+                         (const void *)rank2_f32_mfma_kernel<kForward, 1>,
+                         (const void *)rank2_f32_mfma_kernel<kForward, 2>,
+                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rom

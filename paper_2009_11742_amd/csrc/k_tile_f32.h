@@ -18,9 +18,14 @@ namespace rom {
 namespace tile {
 
 using dev::f4;
-constexpr int NB = kColBlock;     // 4 sample columns per workgroup
+constexpr int NB = kColBlock;     // 4 sample columns per column set
 constexpr int kChunk = 32;        // k terms per operator chunk (8 float4 loads)
 constexpr int kQ = kChunk / 4;
+
+// Column sets: a workgroup owns NS sets of 4 sample columns (NS = 1 or 2).
+// Every operator fragment loaded feeds one MFMA per set, so two sets halve
+// the operator bytes each CU fetches per flop (the column-block products
+// are bound by the L1 fill of the streamed operator, not by the MFMAs).
 
 // Load the kQ float4 operator fragments of chunk `ch` of a panel tile.
 __device__ __forceinline__ void load_chunk(f4 (&dst)[kQ], const f4 *ap, int ch) {
@@ -29,11 +34,16 @@ __device__ __forceinline__ void load_chunk(f4 (&dst)[kQ], const f4 *ap, int ch) 
     for (int q = 0; q < kQ; ++q) dst[q] = src[q * 64];
 }
 
-// Load the kChunk state values of chunk `ch` of this lane's LDS column.
-__device__ __forceinline__ void lds_chunk(f4 (&dst)[kQ], const float *xcol, int ch) {
-    const f4 *src = reinterpret_cast<const f4 *>(xcol + ch * kChunk);
+// Load the kChunk state values of chunk `ch` of the lane's LDS column of
+// every set (set s: column j + 4 s, ld apart).
+template <int NS>
+__device__ __forceinline__ void lds_chunk(f4 (&dst)[NS][kQ], const float *xcol, int ld, int ch) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[q] = src[q];
+    for (int s = 0; s < NS; ++s) {
+        const f4 *src = reinterpret_cast<const f4 *>(xcol + 4 * s * ld + ch * kChunk);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) dst[s][q] = src[q];
+    }
 }
 
 // Exact fold of an FP32 partial sum into a (hi, lo) pair (two-sum); used by
@@ -52,73 +62,87 @@ __device__ __forceinline__ f4 mfma4(float a, float x, f4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, x, c, 0, 0, 0);
 }
 
-// The FP32 products accumulate in two MFMA chains per chunk pair (c0: even
-// float4 groups, c1: odd ones; 32 terms each), and every finished chain is
-// folded into FP64 tile sums with one convert and one FP64 add per value.
-// Each chain rounds like a 32-term sequential FP32 sum; the FP64 sums add
-// nothing measurable to that.  The MFMAs alternate between the two chains
-// (a dependent 4x4x1 MFMA waits about twice its issue interval), and a
-// sched_barrier after every pair pins that order, which the scheduler would
-// otherwise trade for back-to-back dependent MFMAs.
+// The FP32 products accumulate in two MFMA chains per set and chunk pair
+// (c[s][0]: even float4 groups, c[s][1]: odd ones; 32 terms each), and
+// every finished chain is folded into FP64 tile sums with one convert and
+// one FP64 add per value.  Each chain rounds like a 32-term sequential FP32
+// sum; the FP64 sums add nothing measurable to that.  The MFMAs alternate
+// between chains (a dependent 4x4x1 MFMA waits about twice its issue
+// interval), and a sched_barrier after every group pins that order, which
+// the scheduler would otherwise trade for back-to-back dependent MFMAs.
 
-// First chunk of a pair: start fresh chains (c0, c1) and fold the previous
-// pair's chains (p0, p1) into acc, one fold step between two MFMA pairs,
-// from the third pair on (the previous chains have left the pipeline).
-__device__ __forceinline__ void mma_first(const f4 (&a)[kQ], const f4 (&x)[kQ], f4 &c0, f4 &c1,
-                                          const f4 &p0, const f4 &p1, double (&acc)[4]) {
-    c0 = f4{0.f, 0.f, 0.f, 0.f};
-    c1 = f4{0.f, 0.f, 0.f, 0.f};
+// First chunk of a pair: start fresh chains and fold the previous pair's
+// chains p into acc, one fold step per set between two MFMA groups, from
+// the third group on (the previous chains have left the pipeline).
+template <int NS>
+__device__ __forceinline__ void mma_first(const f4 (&a)[kQ], const f4 (&x)[NS][kQ], f4 (&c)[NS][2],
+                                          const f4 (&p)[NS][2], double (&acc)[NS][4]) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {          // pair i: component i % 4 of groups 2 (i / 4), +1
+    for (int s = 0; s < NS; ++s) c[s][0] = c[s][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {          // group i: component i % 4 of float4s 2 (i / 4), +1
         const int q = 2 * (i >> 2), e = i & 3;
-        c0 = mfma4(a[q][e], x[q][e], c0);
-        c1 = mfma4(a[q + 1][e], x[q + 1][e], c1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            c[s][0] = mfma4(a[q][e], x[s][q][e], c[s][0]);
+            c[s][1] = mfma4(a[q + 1][e], x[s][q + 1][e], c[s][1]);
+        }
         if (i >= 2 && i < 10) {
-            const int k = i - 2;            // fold step k: element k % 4 of p0 (k < 4) or p1
-            acc[k & 3] += (double)(k < 4 ? p0[k & 3] : p1[k & 3]);
+            const int k = i - 2;            // fold step k: element k % 4 of chain k / 4
+#pragma unroll
+            for (int s = 0; s < NS; ++s) acc[s][k & 3] += (double)p[s][k >> 2][k & 3];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 // Second chunk of a pair: continue the chains.
-__device__ __forceinline__ void mma_next(const f4 (&a)[kQ], const f4 (&x)[kQ], f4 &c0, f4 &c1) {
+template <int NS>
+__device__ __forceinline__ void mma_next(const f4 (&a)[kQ], const f4 (&x)[NS][kQ], f4 (&c)[NS][2]) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int q = 2 * (i >> 2), e = i & 3;
-        c0 = mfma4(a[q][e], x[q][e], c0);
-        c1 = mfma4(a[q + 1][e], x[q + 1][e], c1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            c[s][0] = mfma4(a[q][e], x[s][q][e], c[s][0]);
+            c[s][1] = mfma4(a[q + 1][e], x[s][q + 1][e], c[s][1]);
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-__device__ __forceinline__ void fold64(double (&acc)[4], const f4 &p0, const f4 &p1) {
+template <int NS>
+__device__ __forceinline__ void fold64(double (&acc)[NS][4], const f4 (&p)[NS][2]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        acc[r] += (double)p0[r];
-        acc[r] += (double)p1[r];
-    }
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc[s][r] += (double)p[s][0][r];
+            acc[s][r] += (double)p[s][1][r];
+        }
 }
 
 constexpr int kWaves = 4;                 // one wave per SIMD
 constexpr int kThreads = kWaves * 64;
 
-// LDS of the states (hi, lo), probe partials and source / probe vectors.
-__host__ __device__ inline size_t state_lds_bytes(int kvp, int ksp) {
-    return sizeof(float) * (size_t)NB * 2 * ((kvp + 4) + (ksp + 4)) + sizeof(double) * kWaves * NB +
+// LDS of the states (hi, lo) of nb columns, probe partials and source /
+// probe vectors.
+__host__ __device__ inline size_t state_lds_bytes(int kvp, int ksp, int nb) {
+    return sizeof(float) * (size_t)nb * 2 * ((kvp + 4) + (ksp + 4)) + sizeof(double) * kWaves * nb +
            sizeof(float) * 2 * (size_t)kvp;
 }
 
-// Register-resident operator: each wave keeps the first kResPairs chunk
-// pairs of its first row tile of each field in registers for the whole run
-// (8 chunks, 256 registers per lane, which one wave per SIMD leaves free),
-// so those chunks cost no load at all; the rest is streamed.  A field keeps
-// at least one streamed pair per tile.
-constexpr int kResPairs = 2;
+// Register-resident operator: each wave keeps the first res_pairs(NS)
+// chunk pairs of its first row tile of each field in registers for the
+// whole run (8 chunks = 256 registers per lane with one set, 4 chunks with
+// two, whose state buffers and chains take the rest), so those chunks cost
+// no load at all; the rest is streamed.  A field keeps at least one
+// streamed pair per tile.
+__host__ __device__ constexpr int res_pairs(int ns) { return ns == 1 ? 2 : 1; }
 
-__host__ __device__ inline int resident_pairs(int nch) {
+__host__ __device__ inline int resident_pairs(int nch, int ns) {
     const int r = nch / 2 - 1;
-    return r < kResPairs ? r : kResPairs;
+    return r < res_pairs(ns) ? r : res_pairs(ns);
 }
 
 struct Field {
@@ -196,97 +220,110 @@ __device__ __forceinline__ void stream_start(Stream &s, f4 (&a0)[kQ], f4 (&a1)[k
 }
 
 // Load the resident pairs of field F (wave w's first tile) into res.
-__device__ __forceinline__ void load_resident(f4 (&res)[2 * kResPairs][kQ], const Field &F, int w,
+template <int NS>
+__device__ __forceinline__ void load_resident(f4 (&res)[2 * res_pairs(NS)][kQ], const Field &F, int w,
                                               int lane) {
     if (w >= F.T) return;
     const f4 *ap = chunk_ptr(F.pk, F.kp, w, 0) + lane;
 #pragma unroll
-    for (int c = 0; c < 2 * kResPairs; ++c)
+    for (int c = 0; c < 2 * res_pairs(NS); ++c)
         if (c < 2 * F.rp) load_chunk(res[c], ap, c);
 }
 
-// 64 x 4 tile product  P[t] * X  of field F (X: this lane's LDS column
-// xcol), summed in FP64 into acc.  The first nres chunk pairs come from the
-// registers `res`, the rest from the stream, whose current pair sits in
-// (a0, a1); each pair used is replaced by the stream's next one.  State
-// values are fetched one chunk ahead with ping-pong buffers.  Per lane
-// acc[r] is row 64 t + 4 (lane / 4) + r of column lane % 4.
+// 64 x 4 NS tile product  P[t] * X  of field F (X: this lane's LDS column
+// xcol of set 0; set s is 4 s columns further), summed in FP64 into acc.
+// The first nres chunk pairs come from the registers `res`, the rest from
+// the stream, whose current pair sits in (a0, a1); each pair used is
+// replaced by the stream's next one.  State values are fetched one chunk
+// ahead with ping-pong buffers.  Per lane acc[s][r] is row
+// 64 t + 4 (lane / 4) + r of column 4 s + lane % 4.
+template <int NS>
 __device__ __forceinline__ void tile_product(const Field &F, const float *xcol,
-                                             const f4 (&res)[2 * kResPairs][kQ], int nres, f4 (&a0)[kQ],
-                                             f4 (&a1)[kQ], Stream &s, const Field &fv, const Field &fs,
-                                             int w, int lane, double (&acc)[4]) {
+                                             const f4 (&res)[2 * res_pairs(NS)][kQ], int nres,
+                                             f4 (&a0)[kQ], f4 (&a1)[kQ], Stream &s, const Field &fv,
+                                             const Field &fs, int w, int lane, double (&acc)[NS][4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = 0.0;
-    f4 p0 = {0.f, 0.f, 0.f, 0.f}, p1 = {0.f, 0.f, 0.f, 0.f};
-    f4 x0[kQ], x1[kQ];
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[q][r] = 0.0;
+    f4 p[NS][2];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) p[q][0] = p[q][1] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 x0[NS][kQ], x1[NS][kQ];
     // sched_barrier(0) keeps each prefetch batch where it is written: the
     // scheduler would otherwise sink the loads next to their first use.
-    lds_chunk(x0, xcol, 0);
+    lds_chunk<NS>(x0, xcol, F.ldx, 0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int rp = 0; rp < kResPairs; ++rp) {
+    for (int rp = 0; rp < res_pairs(NS); ++rp) {
         if (rp < nres) {
-            lds_chunk(x1, xcol, 2 * rp + 1);
+            lds_chunk<NS>(x1, xcol, F.ldx, 2 * rp + 1);
             __builtin_amdgcn_sched_barrier(0);
-            f4 c0, c1;
-            mma_first(res[2 * rp], x0, c0, c1, p0, p1, acc);
+            f4 c[NS][2];
+            mma_first<NS>(res[2 * rp], x0, c, p, acc);
             __builtin_amdgcn_sched_barrier(0);
-            lds_chunk(x0, xcol, 2 * rp + 2);     // a streamed pair always follows
+            lds_chunk<NS>(x0, xcol, F.ldx, 2 * rp + 2);     // a streamed pair always follows
             __builtin_amdgcn_sched_barrier(0);
-            mma_next(res[2 * rp + 1], x1, c0, c1);
+            mma_next<NS>(res[2 * rp + 1], x1, c);
             __builtin_amdgcn_sched_barrier(0);
-            p0 = c0;
-            p1 = c1;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) p[q][0] = c[q][0], p[q][1] = c[q][1];
         }
     }
-    for (int c = 2 * nres; c < F.nch; c += 2) {
-        lds_chunk(x1, xcol, c + 1);
+    for (int ch = 2 * nres; ch < F.nch; ch += 2) {
+        lds_chunk<NS>(x1, xcol, F.ldx, ch + 1);
         __builtin_amdgcn_sched_barrier(0);
-        f4 c0, c1;
-        mma_first(a0, x0, c0, c1, p0, p1, acc);
+        f4 c[NS][2];
+        mma_first<NS>(a0, x0, c, p, acc);
         __builtin_amdgcn_sched_barrier(0);
         load_chunk(a0, s.p + lane, 0);
-        lds_chunk(x0, xcol, min(c + 2, F.nch - 1));
+        lds_chunk<NS>(x0, xcol, F.ldx, min(ch + 2, F.nch - 1));
         __builtin_amdgcn_sched_barrier(0);
-        mma_next(a1, x1, c0, c1);
+        mma_next<NS>(a1, x1, c);
         __builtin_amdgcn_sched_barrier(0);
         load_chunk(a1, s.p + lane, 1);
         __builtin_amdgcn_sched_barrier(0);
         advance(s, fv, fs, w);
-        p0 = c0;
-        p1 = c1;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) p[q][0] = c[q][0], p[q][1] = c[q][1];
     }
-    fold64(acc, p0, p1);
+    fold64<NS>(acc, p);
 }
 
-// Finish one 64 x 4 tile in FP64: y = (Yh + Yl) + dt (acc + b u), stored
+// Finish one 64 x 4 NS tile in FP64: y = (Yh + Yl) + dt (acc + b u), stored
 // back as the (hi, lo) pair.  With FORCED the rows also accumulate the
-// probe partial c^T V.
-template <bool FORCED>
-__device__ __forceinline__ void finish_tile(const Field &f, int t, const double (&acc)[4], int lane,
-                                            const float *bl, const float *cl, double u, double dt,
-                                            double &ypart) {
+// probe partials c^T V of each set (u[s]: the forcing of the lane's column
+// of set s).
+template <bool FORCED, int NS>
+__device__ __forceinline__ void finish_tile(const Field &f, int t, const double (&acc)[NS][4], int lane,
+                                            const float *bl, const float *cl, const double (&u)[NS],
+                                            double dt, double (&ypart)[NS]) {
     const int j = lane & 3;
     const int i0 = t * kTileRows + 4 * (lane >> 2);
-    f4 yh = *(f4 *)(f.Yh + j * f.ldy + i0);
-    f4 yl = *(f4 *)(f.Yl + j * f.ldy + i0);
     f4 bb = {0.f, 0.f, 0.f, 0.f}, cc = {0.f, 0.f, 0.f, 0.f};
     if (FORCED) {
         bb = *(const f4 *)(bl + i0);
         cc = *(const f4 *)(cl + i0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        double inc = acc[r];
-        if (FORCED) inc = fma((double)bb[r], u, inc);
-        const double y = fma(dt, inc, (double)yh[r] + (double)yl[r]);
-        const float h = (float)y;
-        yh[r] = h;
-        yl[r] = (float)(y - (double)h);
-        if (FORCED) ypart += (double)cc[r] * y;
+    for (int q = 0; q < NS; ++q) {
+        float *yhp = f.Yh + (j + 4 * q) * f.ldy + i0;
+        float *ylp = f.Yl + (j + 4 * q) * f.ldy + i0;
+        f4 yh = *(f4 *)yhp;
+        f4 yl = *(f4 *)ylp;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double inc = acc[q][r];
+            if (FORCED) inc = fma((double)bb[r], u[q], inc);
+            const double y = fma(dt, inc, (double)yh[r] + (double)yl[r]);
+            const float h = (float)y;
+            yh[r] = h;
+            yl[r] = (float)(y - (double)h);
+            if (FORCED) ypart[q] += (double)cc[r] * y;
+        }
+        *(f4 *)yhp = yh;
+        *(f4 *)ylp = yl;
     }
-    *(f4 *)(f.Yh + j * f.ldy + i0) = yh;
-    *(f4 *)(f.Yl + j * f.ldy + i0) = yl;
 }
 
 }  // namespace tile

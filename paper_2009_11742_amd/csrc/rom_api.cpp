@@ -16,7 +16,6 @@
 #include "rom_internal.h"
 
 namespace rom {
-size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp);
 size_t rank2_lowp_lds_bytes(int kvp, int ksp);
 hipError_t rank2_lowp_configure();
 size_t rank2_valu_lds_bytes(rom_dtype st, int kv, int ks, int kvp, int ksp);
@@ -102,9 +101,8 @@ bool g_configured = false;
 
 // Row-split groups for a rank-2 run of M samples with FP32 states, or 0 if
 // the row-split kernels do not apply (Kv == Ks in {256, 512, 1024}, at most
-// 256 workgroups, a 256-CU gfx950) or ROM_SCHED_COLUMNS forbids them.
+// 256 workgroups, a 256-CU gfx950).
 int split_candidate(rom_ctx *ctx, int32_t M) {
-    if (ctx->flags & ROM_SCHED_COLUMNS) return 0;
     const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
     if (G == 0) return 0;
     if (ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
@@ -151,11 +149,19 @@ rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
     return ROM_OK;
 }
 
-// Launch one rank-2 run with FP32 states on the chosen schedule.
-rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, bool split, int G, hipStream_t st) {
+// Whether the 8-column blocks apply: FP32 operators and the states of 8
+// samples within the LDS.
+bool cols8_ok(const rom_ctx *ctx) {
+    return ctx->op_type == ROM_F32 && ctx->kvp + ctx->ksp <= rom::kMaxPadSum &&
+           rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 2) <= 160 * 1024;
+}
+
+// Launch one rank-2 run with FP32 states on schedule `sched` (a
+// rom_schedule that applies; G: row-split groups).
+rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, int sched, int G, hipStream_t st) {
     hipError_t e;
     const bool lowp = ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3;
-    if (split) {
+    if (sched == ROM_SCHEDULE_ROWSPLIT) {
         rom_status rs = prepare_split(ctx, G, st);
         if (rs != ROM_OK) return rs;
         e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, lowp ? ctx->op_scale : 1.0f, ctx->sp_ws, G,
@@ -165,23 +171,19 @@ rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, bool split, int
         e = rom::launch_rank2_lowp(a, ctx->op_type, ctx->op_scale, st);
     } else {
         a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
-        e = rom::launch_rank2_f32_mfma(a, st);
+        e = rom::launch_rank2_f32_mfma(a, sched == ROM_SCHEDULE_COLUMNS8 ? 2 : 1, st);
     }
     if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: launch");
     return ROM_OK;
 }
 
-// Schedule autotuner.  The faster of the column-block and row-split kernels
-// depends on K, M and the operator type in ways a fixed rule misses (the
-// row-split kernel pays two group barriers per step but streams no
-// operator; the column-block kernels never wait but stream the whole
-// operator per CU).  On the first automatic run of a shape (Kv_pad, Ks_pad,
-// M rounded up to the 64-sample group, operator type) both schedules run
-// kTuneSteps steps on scratch states (after a warm-up launch each), timed
-// with events on the caller's stream, and the faster one is remembered for
-// the process.  That first run synchronises the stream; a stream being
-// captured is never tuned (the column-block kernels are used until an
-// eager run has tuned the shape).
+// Schedule autotuner.  Which kernel schedule is fastest depends on K, M and
+// the operator type in ways a fixed rule misses: the row-split kernels pay
+// two group barriers per step but stream no operator; the column-block
+// kernels never wait but stream the whole operator per CU, 8-column blocks
+// half as much per flop on half as many CUs.  Entries are keyed by
+// (Kv_pad, Ks_pad, M rounded up to 64, operator type); m_pad = 0 keys the
+// per-workgroup tile times of the grouped launch.
 struct TuneKey {
     int kvp, ksp, mpad, op;
     bool operator<(const TuneKey &o) const {
@@ -189,56 +191,147 @@ struct TuneKey {
     }
 };
 struct TuneEntry {
-    int split;
-    float us_columns, us_split;   // per step
+    int sched;
+    float us[ROM_NSCHEDULES];     // per step, < 0: not applicable / not timed
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneEntry> g_tune;
-constexpr int kTuneSteps = 32;
+constexpr int kTuneSteps = 32;    // timed steps per schedule of a run shape
+constexpr int kTileSteps = 256;   // timed steps per tile of one workgroup
 
-rom_status tune_schedule(rom_ctx *ctx, const rom::Rank2Args &run, int G, hipStream_t st, TuneEntry &out) {
+bool tune_find(const TuneKey &k, TuneEntry &out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tune_store(const TuneKey &k, const TuneEntry &te) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[k] = te;
+}
+
+bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Time each schedule of `cands` (bit per rom_schedule) for `nsteps` steps of
+// `run` (its M) on scratch states, after a 2-step warm-up; best of two runs,
+// per step, into us (entries not in cands untouched).
+rom_status time_schedules(rom_ctx *ctx, const rom::Rank2Args &run, unsigned cands, int G, int64_t nsteps,
+                          hipStream_t st, float (&us)[ROM_NSCHEDULES]) {
     const size_t vb = sizeof(float) * (size_t)ctx->kv * run.M, sb = sizeof(float) * (size_t)ctx->ks * run.M;
-    void *V = nullptr, *S = nullptr;
+    const size_t mb = sizeof(double) * (size_t)run.M;
+    void *V = nullptr, *S = nullptr, *mu = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    float best[2] = {0.f, 0.f};
     rom_status rs = ROM_OK;
     hipError_t e = hipMalloc(&V, vb);
     if (e == hipSuccess) e = hipMalloc(&S, sb);
+    if (e == hipSuccess && !run.mu) e = hipMalloc(&mu, mb);
+    if (e == hipSuccess && mu) e = hipMemsetAsync(mu, 0, mb, st);   // any finite mu times the same
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e != hipSuccess) rs = hip_fail(e, "rom_run_rank2: schedule tuning setup");
+    if (e != hipSuccess) rs = hip_fail(e, "schedule tuning: setup");
     rom::Rank2Args a = run;
     a.V = V; a.S = S; a.c = nullptr; a.J = nullptr; a.y = nullptr; a.n0 = 0;
-    for (int split = 0; split < 2 && rs == ROM_OK; ++split) {
-        best[split] = 1e30f;
+    if (mu) a.mu = static_cast<const double *>(mu);
+    for (int sc = 0; sc < ROM_NSCHEDULES && rs == ROM_OK; ++sc) {
+        if (!(cands >> sc & 1u)) continue;
+        float best = 1e30f;
         for (int rep = 0; rep < 3 && rs == ROM_OK; ++rep) {   // rep 0: warm-up
             e = hipMemsetAsync(V, 0, vb, st);
             if (e == hipSuccess) e = hipMemsetAsync(S, 0, sb, st);
-            if (e != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: schedule tuning"); break; }
-            a.nsteps = rep == 0 ? 2 : kTuneSteps;
-            if (rep > 0 && (e = hipEventRecord(e0, st)) != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: tuning"); break; }
-            rs = launch_fp32_state_run(ctx, a, split == 1, G, st);
-            if (rs != ROM_OK) break;
-            if (rep > 0) {
-                float ms = 0.f;
-                e = hipEventRecord(e1, st);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) { rs = hip_fail(e, "rom_run_rank2: tuning"); break; }
-                best[split] = std::min(best[split], ms * 1e3f / kTuneSteps);
-            }
+            if (e == hipSuccess && rep > 0) e = hipEventRecord(e0, st);
+            if (e != hipSuccess) { rs = hip_fail(e, "schedule tuning"); break; }
+            a.nsteps = rep == 0 ? 2 : nsteps;
+            rs = launch_fp32_state_run(ctx, a, sc, G, st);
+            if (rs != ROM_OK || rep == 0) continue;
+            float ms = 0.f;
+            e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rs = hip_fail(e, "schedule tuning"); break; }
+            best = std::min(best, ms * 1e3f / (float)nsteps);
         }
+        if (rs == ROM_OK) us[sc] = best;
     }
     if (rs == ROM_OK) {
         e = hipStreamSynchronize(st);
-        if (e != hipSuccess) rs = hip_fail(e, "rom_run_rank2: tuning");
+        if (e != hipSuccess) rs = hip_fail(e, "schedule tuning");
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     hfree(V);
     hfree(S);
-    if (rs == ROM_OK) out = TuneEntry{best[1] < best[0] ? 1 : 0, best[0], best[1]};
+    hfree(mu);
     return rs;
+}
+
+int fastest(const float (&us)[ROM_NSCHEDULES]) {
+    int best = ROM_SCHEDULE_COLUMNS4;
+    for (int sc = 0; sc < ROM_NSCHEDULES; ++sc)
+        if (us[sc] >= 0.f && (us[best] < 0.f || us[sc] < us[best])) best = sc;
+    return best;
+}
+
+// Schedule of an FP32-state rank-2 run (flags, table, or tuned now).
+rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, int &sched, int &G) {
+    G = split_candidate(ctx, a.M);
+    unsigned cands = 1u << ROM_SCHEDULE_COLUMNS4;
+    if (G > 0) cands |= 1u << ROM_SCHEDULE_ROWSPLIT;
+    if (cols8_ok(ctx)) cands |= 1u << ROM_SCHEDULE_COLUMNS8;
+    sched = ROM_SCHEDULE_COLUMNS4;
+    if (ctx->flags & ROM_SCHED_COLUMNS) return ROM_OK;
+    if (ctx->flags & ROM_SCHED_ROWSPLIT) {
+        if (G > 0) sched = ROM_SCHEDULE_ROWSPLIT;
+        return ROM_OK;
+    }
+    if (ctx->flags & ROM_SCHED_COLUMNS8) {
+        if (cols8_ok(ctx)) sched = ROM_SCHEDULE_COLUMNS8;
+        return ROM_OK;
+    }
+    const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(a.M, 64), (int)ctx->op_type};
+    TuneEntry te;
+    if (!tune_find(key, te)) {
+        if (stream_capturing(st)) return ROM_OK;
+        te.sched = ROM_SCHEDULE_COLUMNS4;
+        for (float &u : te.us) u = -1.f;
+        rom_status rs = time_schedules(ctx, a, cands, G, kTuneSteps, st, te.us);
+        if (rs != ROM_OK) return rs;
+        te.sched = fastest(te.us);
+        tune_store(key, te);
+    }
+    if (cands >> te.sched & 1u) sched = te.sched;
+    return ROM_OK;
+}
+
+// Per-workgroup step times of the 4- and 8-column tiles of a context's
+// shape (grouped launch), from the table or tuned now on `st`.  Untimed
+// entries stay negative.
+rom_status tile_times(rom_ctx *c, hipStream_t st, TuneEntry &te) {
+    const TuneKey key{c->kvp, c->ksp, 0, (int)ROM_F32};
+    if (tune_find(key, te)) return ROM_OK;
+    te.sched = ROM_SCHEDULE_COLUMNS4;
+    for (float &u : te.us) u = -1.f;
+    if (stream_capturing(st)) return ROM_OK;
+    rom::Rank2Args a;
+    a.b = c->b; a.mu = nullptr;
+    a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.dt = c->dt;
+    a.M = rom::kColBlock;
+    rom_status rs = time_schedules(c, a, 1u << ROM_SCHEDULE_COLUMNS4, 0, kTileSteps, st, te.us);
+    if (rs == ROM_OK && cols8_ok(c)) {
+        a.M = 2 * rom::kColBlock;
+        rs = time_schedules(c, a, 1u << ROM_SCHEDULE_COLUMNS8, 0, kTileSteps, st, te.us);
+    }
+    if (rs != ROM_OK) return rs;
+    // per-sample throughput decides the entry's tile
+    te.sched = (te.us[ROM_SCHEDULE_COLUMNS8] >= 0.f &&
+                te.us[ROM_SCHEDULE_COLUMNS8] < 2.f * te.us[ROM_SCHEDULE_COLUMNS4])
+                   ? ROM_SCHEDULE_COLUMNS8 : ROM_SCHEDULE_COLUMNS4;
+    tune_store(key, te);
+    return ROM_OK;
 }
 
 }  // namespace
@@ -266,10 +359,12 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     if (!lowp && cfg->op_type != cfg->state_type)
         return fail(ROM_E_UNSUPPORTED, "rom_create: supported (op, state) pairs are (F64, F64), "
                                        "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
-    if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT))
+    if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8))
         return fail(ROM_E_ARG, "rom_create: unknown flag bits");
-    if ((cfg->flags & ROM_SCHED_COLUMNS) && (cfg->flags & ROM_SCHED_ROWSPLIT))
-        return fail(ROM_E_ARG, "rom_create: ROM_SCHED_COLUMNS and ROM_SCHED_ROWSPLIT exclude each other");
+    {
+        const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
+        if (sf & (sf - 1)) return fail(ROM_E_ARG, "rom_create: at most one ROM_SCHED_* flag");
+    }
     const size_t nA = (size_t)kv * ks;
     if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
         return fail(ROM_E_NONFINITE, "rom_create: non-finite value in Avs, Asv or b");
@@ -434,16 +529,55 @@ rom_status rom_destroy(rom_ctx *ctx) {
 
 int32_t rom_last_schedule(rom_ctx *ctx) { return ctx ? ctx->last_schedule : -1; }
 
-rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double *us_columns, double *us_rowsplit) {
-    if (!ctx || M < 1 || !us_columns || !us_rowsplit) return fail(ROM_E_ARG, "rom_schedule_times: bad argument");
-    const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(M, 64), (int)ctx->op_type};
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it == g_tune.end() || it->second.split < 0)
-        return fail(ROM_E_ARG, "rom_schedule_times: this shape has not been tuned");
-    *us_columns = it->second.us_columns;
-    *us_rowsplit = it->second.us_split;
+rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double us[ROM_NSCHEDULES]) {
+    if (!ctx || M < 1 || !us) return fail(ROM_E_ARG, "rom_schedule_times: bad argument");
+    TuneEntry te;
+    if (!tune_find(TuneKey{ctx->kvp, ctx->ksp, rom::round_up(M, 64), (int)ctx->op_type}, te))
+        return fail(ROM_E_ARG, "rom_schedule_times: this shape is not in the tuning table");
+    for (int sc = 0; sc < ROM_NSCHEDULES; ++sc) us[sc] = te.us[sc];
     return ROM_OK;
+}
+
+int32_t rom_tune_count(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int32_t)g_tune.size();
+}
+
+rom_status rom_tune_get(int32_t i, rom_tune_entry *out) {
+    if (!out) return fail(ROM_E_ARG, "rom_tune_get: NULL out");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (i < 0 || i >= (int32_t)g_tune.size()) return fail(ROM_E_ARG, "rom_tune_get: index out of range");
+    auto it = g_tune.begin();
+    std::advance(it, i);
+    out->kv_pad = it->first.kvp;
+    out->ks_pad = it->first.ksp;
+    out->m_pad = it->first.mpad;
+    out->op_type = (rom_dtype)it->first.op;
+    out->schedule = it->second.sched;
+    for (int sc = 0; sc < ROM_NSCHEDULES; ++sc) out->us[sc] = it->second.us[sc];
+    return ROM_OK;
+}
+
+rom_status rom_tune_put(const rom_tune_entry *e) {
+    if (!e) return fail(ROM_E_ARG, "rom_tune_put: NULL entry");
+    if (e->kv_pad < 64 || e->ks_pad < 64 || e->kv_pad % 64 || e->ks_pad % 64 || e->m_pad < 0 || e->m_pad % 64)
+        return fail(ROM_E_ARG, "rom_tune_put: sizes must be positive multiples of 64 (m_pad may be 0)");
+    if (e->op_type < ROM_F64 || e->op_type > ROM_F8E4M3)
+        return fail(ROM_E_ARG, "rom_tune_put: bad op_type");
+    if (e->schedule < 0 || e->schedule >= ROM_NSCHEDULES)
+        return fail(ROM_E_ARG, "rom_tune_put: bad schedule");
+    if (e->m_pad == 0 && e->schedule == ROM_SCHEDULE_ROWSPLIT)
+        return fail(ROM_E_ARG, "rom_tune_put: a grouped tile entry names a column tile");
+    TuneEntry te;
+    te.sched = e->schedule;
+    for (int sc = 0; sc < ROM_NSCHEDULES; ++sc) te.us[sc] = (float)e->us[sc];
+    tune_store(TuneKey{e->kv_pad, e->ks_pad, e->m_pad, (int)e->op_type}, te);
+    return ROM_OK;
+}
+
+void rom_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
 }
 
 rom_status rom_check(rom_ctx *ctx, void *stream) {
@@ -509,35 +643,13 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         if (lowp && rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
         if (!lowp && (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
-                      rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024))
+                      rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 1) > 160 * 1024))
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
-        const int G = split_candidate(ctx, M);
-        bool split = false;
-        if (G > 0) {
-            if (ctx->flags & ROM_SCHED_ROWSPLIT) {
-                split = true;
-            } else {
-                const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(M, 64), (int)ctx->op_type};
-                TuneEntry te{-1, 0.f, 0.f};
-                {
-                    std::lock_guard<std::mutex> lk(g_tune_mu);
-                    auto it = g_tune.find(key);
-                    if (it != g_tune.end()) te = it->second;
-                }
-                if (te.split < 0) {
-                    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-                    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-                        rom_status rs = tune_schedule(ctx, a, G, st, te);
-                        if (rs != ROM_OK) return rs;
-                        std::lock_guard<std::mutex> lk(g_tune_mu);
-                        g_tune[key] = te;
-                    }
-                }
-                split = te.split == 1;
-            }
-        }
-        ctx->last_schedule = split ? 1 : 0;
-        return launch_fp32_state_run(ctx, a, split, G, st);
+        int sched = ROM_SCHEDULE_COLUMNS4, G = 0;
+        rom_status rs = pick_schedule(ctx, a, st, sched, G);
+        if (rs != ROM_OK) return rs;
+        ctx->last_schedule = sched;
+        return launch_fp32_state_run(ctx, a, sched, G, st);
     } else {
         if (rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) > 150 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: FP64 states above the LDS-resident limit");
@@ -559,7 +671,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     if (ctx->state_type != ROM_F32 || ctx->op_type != ROM_F32)
         return fail(ROM_E_UNSUPPORTED, "rom_adjoint: FP32 states and operators only in this version");
     if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
-        rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
+        rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 1) > 160 * 1024)
         return fail(ROM_E_UNSUPPORTED, "rom_adjoint: Kv + Ks above the LDS-resident limit");
     int64_t C = ckpt_stride > 0 ? ckpt_stride : (int64_t)ceil(sqrt((double)nsteps));
     if (C < 1) C = 1;
@@ -632,7 +744,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         ACHK(hipMemcpyAsync(cg, curV, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
         ACHK(hipMemcpyAsync(cg + v1, curS, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
         a.V = curV; a.S = curS; a.J = J; a.n0 = nb; a.nsteps = len;
-        ACHK(rom::launch_rank2_f32_mfma(a, st), "rom_adjoint: forward launch");
+        ACHK(rom::launch_rank2_f32_mfma(a, 1, st), "rom_adjoint: forward launch");
     }
     // reverse sweep, segment by segment from the last
     ACHK(hipMemsetAsync(P, 0, (v1 + s1) * 4, st), "rom_adjoint: memset");
@@ -647,7 +759,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         rom::Rank2Args fw = a;
         fw.V = curV; fw.S = curS; fw.J = nullptr; fw.y = ytr; fw.n0 = nb; fw.nsteps = len;
         fw.vtr = vtr; fw.str = str;
-        ACHK(rom::launch_rank2_f32_mfma(fw, st), "rom_adjoint: recompute launch");
+        ACHK(rom::launch_rank2_f32_mfma(fw, 1, st), "rom_adjoint: recompute launch");
         // reverse steps nb + len - 1 .. nb
         rom::Rank2Args ad = a;
         ad.avs = ctx->asvT_pk; ad.asv = ctx->avsT_pk; ad.V = P; ad.S = Q; ad.J = nullptr;
@@ -671,14 +783,17 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
 
 namespace {
 
-// Validate a grouped request and build the per-instance arguments and the
-// (instance, column block) items, largest operator first.
+// Validate a grouped request and build the per-instance arguments (each
+// with its column tile) and the (instance, first column) items, longest
+// tuned step time first.  Tile times missing from the table are tuned on
+// `st` (synchronously).
 rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
-                       void *const *V, void *const *S, std::vector<rom::Rank2Args> &inst,
+                       void *const *V, void *const *S, hipStream_t st, std::vector<rom::Rank2Args> &inst,
                        std::vector<int2> &items, size_t &lds) {
     if (!ctx || !M || !mu || !V || !S) return fail(ROM_E_ARG, "grouped: NULL array");
     if (G < 1) return fail(ROM_E_ARG, "grouped: G must be >= 1");
     inst.assign(G, rom::Rank2Args());
+    std::vector<float> cost(G, 0.f);
     lds = 0;
     for (int i = 0; i < G; ++i) {
         rom_ctx *c = ctx[i];
@@ -687,24 +802,45 @@ rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const d
         if (!mu[i] || !V[i] || !S[i]) return fail(ROM_E_ARG, "grouped: NULL mu, V or S");
         if (c->state_type != ROM_F32 || c->op_type != ROM_F32)
             return fail(ROM_E_UNSUPPORTED, "grouped: FP32 states and operators only");
-        size_t b = rom::rank2_f32_mfma_lds_bytes(c->kvp, c->ksp);
-        if (c->kvp + c->ksp > rom::kMaxPadSum || b > 160 * 1024)
+        if (c->kvp + c->ksp > rom::kMaxPadSum || rom::rank2_f32_mfma_lds_bytes(c->kvp, c->ksp, 1) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "grouped: an instance exceeds the LDS-resident limit");
+    }
+    for (int i = 0; i < G; ++i) {
+        rom_ctx *c = ctx[i];
+        int nset = 1;
+        float t4 = -1.f, t8 = -1.f;
+        if (c->flags & ROM_SCHED_COLUMNS8) {
+            nset = cols8_ok(c) ? 2 : 1;
+        } else if (!(c->flags & ROM_SCHED_COLUMNS)) {
+            TuneEntry te;
+            rom_status rs = tile_times(c, st, te);
+            if (rs != ROM_OK) return rs;
+            t4 = te.us[ROM_SCHEDULE_COLUMNS4];
+            t8 = cols8_ok(c) ? te.us[ROM_SCHEDULE_COLUMNS8] : -1.f;
+            const int b4 = (M[i] + rom::kColBlock - 1) / rom::kColBlock;
+            const int b8 = (M[i] + 2 * rom::kColBlock - 1) / (2 * rom::kColBlock);
+            if (t4 >= 0.f && t8 >= 0.f && (float)b8 * t8 < (float)b4 * t4) nset = 2;
+        }
+        // item cost: the tuned per-workgroup step time, else operator size x columns
+        const float tt = nset == 2 ? t8 : t4;
+        cost[i] = tt >= 0.f ? tt : 1e-6f * (float)c->kvp * (float)c->ksp * (float)nset;
+        const size_t b = rom::rank2_f32_mfma_lds_bytes(c->kvp, c->ksp, nset);
         if (b > lds) lds = b;
         rom::Rank2Args &a = inst[i];
         a.avs = c->avs_pk; a.asv = c->asv_pk; a.b = c->b; a.c = nullptr; a.mu = mu[i];
         a.V = V[i]; a.S = S[i]; a.J = nullptr; a.y = nullptr;
         a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.M = M[i];
         a.n0 = 0; a.nsteps = 0; a.dt = c->dt;
+        a.nset = nset;
     }
     std::vector<int> order(G);
     for (int i = 0; i < G; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return (int64_t)inst[x].kvp * inst[x].ksp > (int64_t)inst[y].kvp * inst[y].ksp;
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     items.clear();
-    for (int i : order)
-        for (int cb = 0; cb * rom::kColBlock < inst[i].M; ++cb) items.push_back(make_int2(i, cb));
+    for (int i : order) {
+        const int nc = rom::kColBlock * inst[i].nset;
+        for (int c0 = 0; c0 < inst[i].M; c0 += nc) items.push_back(make_int2(i, c0));
+    }
     return ROM_OK;
 }
 
@@ -719,7 +855,7 @@ rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M, co
     std::vector<rom::Rank2Args> inst;
     std::vector<int2> items;
     size_t lds = 0;
-    rom_status r = build_group(ctx, G, M, mu, V, S, inst, items, lds);
+    rom_status r = build_group(ctx, G, M, mu, V, S, nullptr, inst, items, lds);
     if (r != ROM_OK) return r;
     rom_group *g = new (std::nothrow) rom_group();
     if (!g) return fail(ROM_E_NOMEM, "rom_group_create: host allocation failed");
@@ -765,10 +901,10 @@ rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M, con
     std::vector<rom::Rank2Args> inst;
     std::vector<int2> items;
     size_t lds = 0;
-    rom_status r = build_group(ctx, G, M, mu, V, S, inst, items, lds);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rom_status r = build_group(ctx, G, M, mu, V, S, st, inst, items, lds);
     if (r != ROM_OK) return r;
     if (nsteps == 0) return ROM_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t ib = sizeof(rom::Rank2Args) * inst.size();
     const size_t bytes = ib + sizeof(int2) * items.size();
     // one contiguous host block, uploaded stream-ordered into stream-ordered

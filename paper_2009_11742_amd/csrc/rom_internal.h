@@ -11,7 +11,8 @@ namespace rom {
 // Row tile of the rank-2 MFMA kernel: one v_mfma_f32_4x4x1f32 (16 blocks)
 // covers 64 operator rows x 4 sample columns for one k.
 constexpr int kTileRows = 64;
-// Sample columns owned by one workgroup of the rank-2 FP32 kernel.
+// Sample columns of one column set of the column-block kernels (a
+// workgroup of the FP32 kernel owns one or two sets).
 constexpr int kColBlock = 4;
 // Largest Kv_pad + Ks_pad the LDS-resident state of the rank-2 kernels holds.
 constexpr int kMaxPadSum = 4096;
@@ -59,8 +60,8 @@ struct rom_ctx {
     void *sp_ws = nullptr;
     size_t sp_ws_bytes = 0;
     int sp_ok = -1;
-    // Schedule of the last FP32-state rank-2 run (0 column-block, 1
-    // row-split, -1 none yet).
+    // Schedule of the last FP32-state rank-2 run (a rom_schedule, -1 none
+    // yet).
     int last_schedule = -1;
     // Device status words: [0] scratch of rom_create, [1] in-kernel error
     // (ROM_E_TIMEOUT), [2] abort flag of the row-split barriers.
@@ -88,10 +89,14 @@ struct Rank2Args {
     const double *ytr = nullptr;
     float *wtr = nullptr, *qtr = nullptr;
     double *dmu = nullptr;
+    // column sets per workgroup of the FP32 column-block kernels (grouped
+    // runs read it per instance): 1 = 4 samples, 2 = 8 samples
+    int nset = 1;
 };
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_rank2_f32_mfma(const Rank2Args &a, hipStream_t st);
+hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st);
+size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp, int nset);
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st);
 hipError_t launch_rank2_lowp(const Rank2Args &a, rom_dtype op, float scale, hipStream_t st);
 hipError_t launch_amax(const double *x, int64_t n, unsigned *out, hipStream_t st);

@@ -12,14 +12,18 @@ import ctypes as C
 import numpy as np
 import torch
 
-from . import _lib
+from . import _lib, tuning
 from ._lib import RomConfig, check
+
+tuning.load_default()
 
 _DT = {"f64": (_lib.ROM_F64, torch.float64), "f32": (_lib.ROM_F32, torch.float32)}
 _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": _lib.ROM_F8E4M3}
-# low-precision rank-2 schedule: "auto" (row-split where it applies),
-# "columns" (column-block kernel), "rowsplit" (row-split where it applies)
-_SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT}
+# FP32-state rank-2 schedule: "auto" (the autotuner's table), "columns"
+# (4-column blocks), "rowsplit" (row-split where it applies), "columns8"
+# (8-column blocks, FP32 operators)
+_SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT,
+          "columns8": _lib.ROM_SCHED_COLUMNS8}
 
 
 def _stream_handle(stream):
@@ -72,16 +76,17 @@ class Rom:
 
     @property
     def last_schedule(self):
-        """'columns' or 'rowsplit' for the last FP32-state rank-2 run (None if none)."""
+        """'columns', 'rowsplit' or 'columns8' for the last FP32-state rank-2
+        run (None if none)."""
         v = _lib.load().rom_last_schedule(self._ctx)
-        return {0: "columns", 1: "rowsplit"}.get(v)
+        return None if v < 0 else tuning.SCHEDULES[v]
 
     def schedule_times(self, M):
-        """The schedule autotuner's per-step times in microseconds,
-        {'columns': t, 'rowsplit': t}, for this context's shape at M samples."""
-        a, b = C.c_double(0.0), C.c_double(0.0)
-        check(_lib.load().rom_schedule_times(self._ctx, int(M), C.byref(a), C.byref(b)))
-        return {"columns": a.value, "rowsplit": b.value}
+        """The tuning table's per-step times in microseconds for this
+        context's shape at M samples: {schedule name: t or None}."""
+        us = (C.c_double * _lib.ROM_NSCHEDULES)()
+        check(_lib.load().rom_schedule_times(self._ctx, int(M), us))
+        return {name: (us[i] if us[i] >= 0 else None) for i, name in enumerate(tuning.SCHEDULES)}
 
     def operators(self):
         """(Avs, Asv, scale) exactly as the products use them (float64 numpy)."""

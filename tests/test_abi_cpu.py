@@ -109,3 +109,80 @@ def test_run_rejects_bad_arguments():
     assert lib.rom_step_rank1(fake, d, d, -1, 0.7, None) == _lib.ROM_E_ARG
     assert lib.rom_step_rank1(fake, d, d, 0, float("inf"), None) == _lib.ROM_E_NONFINITE
     assert lib.rom_destroy(None) == _lib.ROM_OK
+
+
+def test_create_rejects_two_schedule_flags():
+    A, B, b, dt = _inst()
+    for f in (_lib.ROM_SCHED_COLUMNS | _lib.ROM_SCHED_COLUMNS8, _lib.ROM_SCHED_ROWSPLIT | _lib.ROM_SCHED_COLUMNS8,
+              _lib.ROM_SCHED_COLUMNS | _lib.ROM_SCHED_ROWSPLIT):
+        cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_F32, f)
+        assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
+    assert "ROM_SCHED" in _lib.load().rom_last_error().decode()
+
+
+def test_tune_table_put_get_clear_and_file_round_trip(tmp_path):
+    """The tuning table is host state: entries round-trip through put / get
+    (key order) and through the text format; bad entries are refused."""
+    from paper_2009_11742_amd import tuning
+    lib = _lib.load()
+    saved = tuning.entries()
+    try:
+        tuning.clear()
+        assert lib.rom_tune_count() == 0
+        tuning.put(512, 512, 1024, "f32", "columns", [17.4, 27.2, -1.0])
+        tuning.put(256, 256, 256, "f32", "columns8", [4.9, 18.5, 4.1])
+        tuning.put(1024, 1024, 1024, "bf16", "rowsplit", [60.0, 11.0, -1.0])
+        tuning.put(768, 768, 0, "f32", "columns8", [40.0, -1.0, 45.0])
+        tuning.put(256, 256, 256, "f32", "columns", [4.9, 18.5, 5.5])      # replaces
+        e = tuning.entries()
+        assert [(d["kv_pad"], d["m_pad"]) for d in e] == [(256, 256), (512, 1024), (768, 0), (1024, 1024)]
+        assert e[0]["schedule"] == "columns" and e[0]["us"] == pytest.approx([4.9, 18.5, 5.5])
+        assert e[3]["op"] == "bf16" and e[3]["schedule"] == "rowsplit"
+        bad = [(100, 256, 64, "f32", "columns"), (256, 256, 65, "f32", "columns"),
+               (256, 256, 0, "f32", "rowsplit"), (0, 256, 64, "f32", "columns")]
+        for kv, ks, m, op, sc in bad:
+            with pytest.raises(_lib.RomError):
+                tuning.put(kv, ks, m, op, sc, [1.0, 1.0, 1.0])
+        ent = _lib.RomTuneEntry(256, 256, 64, _lib.ROM_F32, 3)
+        assert lib.rom_tune_put(ent) == _lib.ROM_E_ARG
+        assert lib.rom_tune_get(99, _lib.RomTuneEntry()) == _lib.ROM_E_ARG
+        p = tmp_path / "table.txt"
+        tuning.save(str(p), header="test table")
+        text = p.read_text()
+        assert text.startswith("# test table") and "512 512 1024 f32 columns 17.400 27.200 -1.000" in text
+        tuning.clear()
+        assert tuning.load(str(p)) == 4
+        assert tuning.entries() == e
+        p.write_text("256 256 64 f32 columns 1.0\n")
+        with pytest.raises(ValueError):
+            tuning.load(str(p))
+    finally:
+        tuning.clear()
+        for d in saved:
+            tuning.put(d["kv_pad"], d["ks_pad"], d["m_pad"], d["op"], d["schedule"], d["us"])
+
+
+def test_shipped_tune_table_is_well_formed():
+    """The shipped table parses, and each entry's schedule is the fastest of
+    its measured times (the autotuner's rule), grouped tile entries by
+    per-sample throughput."""
+    from paper_2009_11742_amd import tuning
+    if not os.path.exists(tuning.DEFAULT_TABLE):
+        pytest.skip("no shipped tuning table")
+    saved = tuning.entries()
+    try:
+        tuning.clear()
+        n = tuning.load(tuning.DEFAULT_TABLE)
+        assert n >= 1
+        for d in tuning.entries():
+            us = d["us"]
+            if d["m_pad"] == 0:
+                want = "columns8" if 0 <= us[2] < 2 * us[0] else "columns"
+            else:
+                ok = [(u, name) for u, name in zip(us, tuning.SCHEDULES) if u >= 0]
+                want = min(ok)[1]
+            assert d["schedule"] == want, d
+    finally:
+        tuning.clear()
+        for d in saved:
+            tuning.put(d["kv_pad"], d["ks_pad"], d["m_pad"], d["op"], d["schedule"], d["us"])

@@ -33,9 +33,15 @@ def _setup(specs):
     return insts, roms, mus, Vs, Ss
 
 
-def _standalone(rom, mu, nsteps):
-    V, S = rom.zeros(int(mu.numel()))
-    rom.run_rank2(mu, V, S, nsteps)
+def _standalone(inst, mu, nsteps):
+    """The instance's own rank-2 run on the 4-column schedule (a fresh
+    context from the same inputs packs the same operators)."""
+    from paper_2009_11742_amd import Rom
+    r = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule="columns")
+    V, S = r.zeros(int(mu.numel()))
+    r.run_rank2(mu, V, S, nsteps)
+    torch.cuda.synchronize()
+    r.close()
     return V, S
 
 
@@ -49,8 +55,7 @@ def test_grouped_small_matches_standalone_and_oracle():
     run_grouped(roms, mus, Vs, Ss, N)
     torch.cuda.synchronize()
     for inst, rom, mu, V, S in zip(insts, roms, mus, Vs, Ss):
-        V1, S1 = _standalone(rom, mu, N)
-        torch.cuda.synchronize()
+        V1, S1 = _standalone(inst, mu, N)
         assert torch.equal(V, V1) and torch.equal(S, S1)
         r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
         assert _relcol(V.cpu().numpy().astype(np.float64).T, r["V"]) <= TOL
@@ -102,9 +107,8 @@ def test_grouped_full_workload():
     N = 4000
     run_grouped(roms, mus, Vs, Ss, N)
     torch.cuda.synchronize()
-    for rom, mu, V, S in zip(roms, mus, Vs, Ss):
-        V1, S1 = _standalone(rom, mu, N)
-        torch.cuda.synchronize()
+    for inst, mu, V, S in zip(insts, mus, Vs, Ss):
+        V1, S1 = _standalone(inst, mu, N)
         assert torch.equal(V, V1) and torch.equal(S, S1)
     picks = np.linspace(0, 63, 8).round().astype(int)
 
@@ -120,3 +124,32 @@ def test_grouped_full_workload():
         errs = list(ex.map(check, picks))
     print("grouped sampled errors", ["%.2e" % e for e in errs])
     assert max(errs) <= TOL
+
+
+@pytest.mark.parametrize("tile_small,tile_big", [("columns", "columns8"), ("columns8", "columns")])
+def test_grouped_tiles_from_table(tile_small, tile_big):
+    """The grouped plan takes each instance's tile from the table's
+    per-workgroup entries: forcing 8-column tiles on one K bucket and 4 on
+    the other, every instance still equals its standalone run bitwise."""
+    from paper_2009_11742_amd import run_grouped, tuning
+    saved = tuning.entries()
+    try:
+        tuning.clear()
+        # us = (4-column, -, 8-column) per-workgroup step times; 8 wins when t8 < 2 t4
+        fast8, slow8 = [10.0, -1.0, 12.0], [10.0, -1.0, 30.0]
+        tuning.put(128, 128, 0, "f32", tile_small, fast8 if tile_small == "columns8" else slow8)
+        tuning.put(320, 320, 0, "f32", tile_big, fast8 if tile_big == "columns8" else slow8)
+        specs = [(128, 128, 37, 11), (300, 300, 21, 12), (128, 128, 8, 13), (300, 300, 5, 14)]
+        insts, roms, mus, Vs, Ss = _setup(specs)
+        N = 600
+        run_grouped(roms, mus, Vs, Ss, N)
+        torch.cuda.synchronize()
+        for inst, mu, V, S in zip(insts, mus, Vs, Ss):
+            V1, S1 = _standalone(inst, mu, N)
+            assert torch.equal(V, V1) and torch.equal(S, S1)
+            r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
+            assert _relcol(V.cpu().numpy().astype(np.float64).T, r["V"]) <= TOL
+    finally:
+        tuning.clear()
+        for d in saved:
+            tuning.put(d["kv_pad"], d["ks_pad"], d["m_pad"], d["op"], d["schedule"], d["us"])

@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-def _rom(inst, state):
+def _rom(inst, state, schedule="auto"):
     from paper_2009_11742_amd import Rom
-    return Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state)
+    return Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state, schedule=schedule)
 
 
 def _relcol(X, R):
@@ -29,8 +29,9 @@ def _relcol(X, R):
     return float(np.max(np.linalg.norm(X - R, axis=0) / np.where(nr > 0, nr, 1.0)))
 
 
-def _gpu_run(inst, state, nsteps, cols=None, probe=False, trace=False, n0=0, V0=None, S0=None):
-    rom = _rom(inst, state)
+def _gpu_run(inst, state, nsteps, cols=None, probe=False, trace=False, n0=0, V0=None, S0=None,
+             schedule="auto"):
+    rom = _rom(inst, state, schedule)
     mu_np = inst["mu"] if cols is None else inst["mu"][cols]
     M = len(mu_np)
     dt_t = rom.torch_dtype
@@ -212,3 +213,20 @@ def test_zero_steps_is_noop_and_energy():
     E1 = oracle.energy(inst["Avs"], inst["dt"], first["V"], first["S"])
     E2 = oracle.energy(inst["Avs"], inst["dt"], second["V"], second["S"])
     assert np.max(np.abs(E2 - E1) / E1) < 1e-11
+
+
+@pytest.mark.parametrize("kv,ks,M,N", [(256, 256, 13, 1500), (192, 320, 37, 800), (70, 45, 9, 1200),
+                                       (512, 512, 8, 400), (1024, 1024, 21, 150)])
+def test_fp32_columns8_bitwise_equals_columns4(kv, ks, M, N):
+    """8-column blocks run each column's products in the same chunk and fold
+    order as 4-column blocks: states, J and the probe trace are bitwise
+    equal, and within the FP32 bar of the oracle (ragged M, Kv != Ks)."""
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=kv + 3 * ks + M, skew=(kv == ks)), "f32")
+    a = _gpu_run(inst, "f32", N, probe=True, trace=True, schedule="columns")
+    b = _gpu_run(inst, "f32", N, probe=True, trace=True, schedule="columns8")
+    for k in ("V", "S", "J", "y"):
+        assert np.array_equal(a[k], b[k]), k
+    cols = np.arange(M) if M * N * kv * ks <= 4e10 else np.array([0, M // 2, M - 1])
+    r = _ref(inst, N, cols=cols, probe=True)
+    assert _relcol(b["V"][:, cols], r["V"]) <= TOL["f32"] and _relcol(b["S"][:, cols], r["S"]) <= TOL["f32"]
+    assert np.max(np.abs(b["J"][cols] - r["J"]) / r["J"]) <= TOL["f32"]

@@ -146,8 +146,9 @@ def test_rowsplit_f32_k1024_m1024_sampled():
 
 @pytest.mark.parametrize("K,M,ops", [(1024, 1024, "f32"), (256, 256, "f32"), (512, 512, "bf16")])
 def test_schedule_autotuner(K, M, ops):
-    """Without a schedule flag the first run of a shape times both schedules
-    and keeps the faster; the run that follows uses it and is correct."""
+    """Without a schedule flag the first run of a shape times every schedule
+    that applies and keeps the fastest (or takes the table's entry); the run
+    uses it and is correct."""
     from paper_2009_11742_amd import Rom
     inst = synth.round_to(synth.make_instance(K, K, M, seed=7), "f32")
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
@@ -158,12 +159,47 @@ def test_schedule_autotuner(K, M, ops):
     rom.check()
     t = rom.schedule_times(M)
     chosen = rom.last_schedule
-    print("autotuner K=%d M=%d %s: columns %.2f us/step, rowsplit %.2f us/step -> %s"
-          % (K, M, ops, t["columns"], t["rowsplit"], chosen))
-    assert chosen == ("rowsplit" if t["rowsplit"] < t["columns"] else "columns")
+    print("autotuner K=%d M=%d %s: %s -> %s" % (K, M, ops, t, chosen))
+    timed = {k: v for k, v in t.items() if v is not None}
+    assert chosen == min(timed, key=timed.get)
+    assert (t["columns8"] is None) == (ops != "f32")
     A, B, _ = rom.operators()
     col = M // 3
     r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"][col:col + 1], N)
     bar = F32_BAR if ops == "f32" else BAR
     assert _relcol(V.cpu().numpy().astype(np.float64).T[:, col:col + 1], r["V"]) <= bar
     rom.close()
+
+
+def test_online_tuning_and_table_entries_steer_the_schedule():
+    """An empty table is filled by the first run of a shape; an entry put in
+    the table decides the schedule of later runs of that shape."""
+    from paper_2009_11742_amd import Rom, tuning
+    saved = tuning.entries()
+    try:
+        tuning.clear()
+        K, M, N = 256, 100, 300
+        inst = synth.round_to(synth.make_instance(K, K, M, seed=3), "f32")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+        mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+        V, S = rom.zeros(M)
+        rom.run_rank2(mu, V, S, N)
+        rom.check()
+        e = [d for d in tuning.entries() if d["m_pad"] == 128]
+        assert len(e) == 1 and all(u > 0 for u in e[0]["us"]), e
+        ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
+        outs = {}
+        for sched in ("rowsplit", "columns8", "columns"):
+            tuning.put(K, K, 128, "f32", sched, e[0]["us"])
+            V, S = rom.zeros(M)
+            rom.run_rank2(mu, V, S, N)
+            rom.check()
+            assert rom.last_schedule == sched
+            outs[sched] = V.clone()
+            assert _relcol(V.cpu().numpy().astype(np.float64).T, ref["V"]) <= F32_BAR
+        assert torch.equal(outs["columns"], outs["columns8"])
+        rom.close()
+    finally:
+        tuning.clear()
+        for d in saved:
+            tuning.put(d["kv_pad"], d["ks_pad"], d["m_pad"], d["op"], d["schedule"], d["us"])
