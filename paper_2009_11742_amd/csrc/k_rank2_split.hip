@@ -31,8 +31,9 @@
 // D register r of lane l: row 4 (l / 16) + r, column l % 16).  Wave w of a
 // workgroup sums reduction terms [w kp/4, (w+1) kp/4) for all 64 x 64
 // outputs, with the state operand fed as x_hi + x_lo (two MFMAs); the four
-// partials meet in LDS, where each thread finishes 16 outputs: FP64 sum,
-// scale (FP8), forcing, and the FP64 update of the FP32 (hi, lo) state.
+// FP32 partials meet in LDS, where each thread finishes 16 outputs: their
+// FP32 sum, then in FP64 the scale (FP8), forcing and the update of the
+// FP32 (hi, lo) state.
 #include <string>
 
 #include "k_common.h"
