@@ -57,12 +57,26 @@ __device__ __forceinline__ void half_step(const Field &f, const f4 (&res)[2 * re
 }
 
 // Copy the (hi + lo) LDS columns (nb of them) of this workgroup to a K x M
-// global matrix.
-__device__ __forceinline__ void store_cols(float *dst, const float *hi, const float *lo, int ld,
-                                           int K, int Kp, int col0, int M, int nb, int tid) {
-    for (int idx = tid; idx < nb * Kp; idx += kThreads) {
-        int jj = idx / Kp, i = idx - jj * Kp, mm = col0 + jj;
-        if (mm < M && i < K) dst[(size_t)mm * K + i] = hi[jj * ld + i] + lo[jj * ld + i];
+// global matrix: column by column, float4 stores where the matrix is
+// 16-byte aligned and K a multiple of 4 (every column then starts aligned),
+// no per-element index division.
+__device__ __forceinline__ void store_cols(float *dst, const float *hi, const float *lo, int ld, int K, int Kp,
+                                           int col0, int M, int nb, int tid) {
+    (void)Kp;
+    const int ncol = min(nb, M - col0);
+    if ((K & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        const int q4 = K >> 2;
+        for (int jj = 0; jj < ncol; ++jj) {
+            f4 *d = reinterpret_cast<f4 *>(dst + (size_t)(col0 + jj) * K);
+            const f4 *h = reinterpret_cast<const f4 *>(hi + jj * ld);
+            const f4 *l = reinterpret_cast<const f4 *>(lo + jj * ld);
+            for (int q = tid; q < q4; q += kThreads) d[q] = h[q] + l[q];
+        }
+    } else {
+        for (int jj = 0; jj < ncol; ++jj) {
+            float *d = dst + (size_t)(col0 + jj) * K;
+            for (int i = tid; i < K; i += kThreads) d[i] = hi[jj * ld + i] + lo[jj * ld + i];
+        }
     }
 }
 

@@ -94,6 +94,13 @@ void free_ctx(rom_ctx *c) {
     hfree(c->asv_sp);
     hfree(c->sp_ws);
     hfree(c->status);
+    for (hipStream_t &sd : c->side)
+        if (sd) {
+            (void)hipStreamSynchronize(sd);
+            (void)hipStreamDestroy(sd);
+        }
+    for (hipEvent_t &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete c;
 }
 
@@ -680,18 +687,30 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     const int kv = ctx->kv, ks = ctx->ks;
     const size_t mK = (size_t)M, v1 = (size_t)kv * mK, s1 = (size_t)ks * mK;
     // workspace layout (floats, then doubles)
+    // The recompute of segment g - 1 (side stream 0), the reverse sweep of
+    // segment g (the caller's stream) and the gradient products of segment
+    // g + 1 (side stream 1) run at the same time: the state and probe traces
+    // of a segment live in one of kTr buffer sets, its W and Q traces in one
+    // of kWq, each reused only after the products of its previous segment.
+    constexpr int kTr = 3, kWq = 2;
     const size_t n_ck = (size_t)nseg * (v1 + s1);
     const size_t n_vtr = (size_t)(C + 1) * v1, n_str = (size_t)(C + 1) * s1;
     const size_t n_wtr = (size_t)C * v1, n_qtr = (size_t)C * s1;
     const size_t n_cur = v1 + s1, n_pq = v1 + s1;
-    size_t nf = n_ck + n_vtr + n_str + n_wtr + n_qtr + n_cur + n_pq;
-    nf = (nf + 1) / 2 * 2;
+    size_t nf = n_ck + kTr * (n_vtr + n_str) + kWq * (n_wtr + n_qtr) + n_cur + n_pq;
+    nf = (nf + 3) / 4 * 4;
     const size_t n_ytr = (size_t)C * mK, n_da = 2 * (size_t)kv * ks;
     const int nsplit = std::max(rom::gemm_nt_splits(kv, ks), rom::gemm_nt_splits(ks, kv));
     const size_t n_part = (size_t)nsplit * kv * ks;   // gradient-product partials
-    const size_t bytes = nf * sizeof(float) + (n_ytr + n_da + n_part) * sizeof(double);
+    const size_t bytes = nf * sizeof(float) + (kTr * n_ytr + n_da + n_part) * sizeof(double);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
+    if (!ctx->side[0]) {
+        e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking);
+        for (int i = 0; i < 13 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "rom_adjoint: stream / event creation");
+    }
     if (!ctx->asvT_pk) {
         size_t pk = sizeof(float) * (size_t)ctx->kvp * ctx->ksp;
         e = hipMalloc(&ctx->asvT_pk, pk);
@@ -721,10 +740,14 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     }
     float *f = static_cast<float *>(ctx->ws);
     float *ck = f;
-    float *vtr = ck + n_ck, *str = vtr + n_vtr, *wtr = str + n_str, *qtr = wtr + n_wtr;
-    float *curV = qtr + n_qtr, *curS = curV + v1, *P = curS + s1, *Q = P + v1;
-    double *ytr = reinterpret_cast<double *>(f + nf);
-    double *dA64 = ytr + n_ytr;
+    float *vtrb[kTr], *strb[kTr], *wtrb[kWq], *qtrb[kWq];
+    float *fp = ck + n_ck;
+    for (int i = 0; i < kTr; ++i) { vtrb[i] = fp; strb[i] = fp + n_vtr; fp += n_vtr + n_str; }
+    for (int i = 0; i < kWq; ++i) { wtrb[i] = fp; qtrb[i] = fp + n_wtr; fp += n_wtr + n_qtr; }
+    float *curV = fp, *curS = curV + v1, *P = curS + s1, *Q = P + v1;
+    double *ytrb[kTr];
+    for (int i = 0; i < kTr; ++i) ytrb[i] = reinterpret_cast<double *>(f + nf) + i * n_ytr;
+    double *dA64 = ytrb[kTr - 1] + n_ytr;
     double *dAvs64 = dA64, *dAsv64 = dA64 + (size_t)kv * ks;
     double *part = dA64 + n_da;
 
@@ -746,33 +769,69 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         a.V = curV; a.S = curS; a.J = J; a.n0 = nb; a.nsteps = len;
         ACHK(rom::launch_rank2_f32_mfma(a, 1, st), "rom_adjoint: forward launch");
     }
-    // reverse sweep, segment by segment from the last
+    // reverse sweep, segment by segment from the last.  Segment g's state
+    // and probe traces (set g % kTr) are written by its recompute (side
+    // stream 0) and read by its reverse sweep (this stream) and its gradient
+    // products (side stream 1), as are its W and Q traces (set g % kWq,
+    // written by the reverse sweep); a set is rewritten only after the
+    // products of the segment that used it before.  Events: ev[0] forward
+    // sweep done; ev[1 + i] trace set i free; ev[4 + i] trace set i
+    // recomputed; ev[7 + i] W/Q set i free; ev[9 + i] reverse sweep into W/Q
+    // set i done; ev[11], ev[12] side streams drained.
+    hipStream_t s2 = ctx->side[0], s3 = ctx->side[1];
+    hipEvent_t ev_fwd = ctx->ev[0], *ev_tr_free = ctx->ev + 1, *ev_rec = ctx->ev + 4;
+    hipEvent_t *ev_wq_free = ctx->ev + 7, *ev_rev = ctx->ev + 9;
+    auto recompute = [&](int64_t g) -> hipError_t {
+        const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
+        const float *cg = ck + (size_t)g * (v1 + s1);
+        const int b = (int)(g % kTr);
+        hipError_t r = hipSuccess;
+        if (g + kTr < nseg) r = hipStreamWaitEvent(s2, ev_tr_free[b], 0);
+        if (r == hipSuccess) r = hipMemcpyAsync(curV, cg, v1 * 4, hipMemcpyDeviceToDevice, s2);
+        if (r == hipSuccess) r = hipMemcpyAsync(curS, cg + v1, s1 * 4, hipMemcpyDeviceToDevice, s2);
+        // recompute the segment, keeping every state and the probe trace
+        rom::Rank2Args fw = a;
+        fw.V = curV; fw.S = curS; fw.J = nullptr; fw.y = ytrb[b]; fw.n0 = nb; fw.nsteps = len;
+        fw.vtr = vtrb[b]; fw.str = strb[b];
+        if (r == hipSuccess) r = rom::launch_rank2_f32_mfma(fw, 1, s2);
+        if (r == hipSuccess) r = hipEventRecord(ev_rec[b], s2);
+        return r;
+    };
     ACHK(hipMemsetAsync(P, 0, (v1 + s1) * 4, st), "rom_adjoint: memset");
     ACHK(hipMemsetAsync(dA64, 0, n_da * 8, st), "rom_adjoint: memset");
     if (dmu) ACHK(hipMemsetAsync(dmu, 0, mK * 8, st), "rom_adjoint: memset");
+    ACHK(hipEventRecord(ev_fwd, st), "rom_adjoint: event");
+    ACHK(hipStreamWaitEvent(s2, ev_fwd, 0), "rom_adjoint: event");
+    ACHK(hipStreamWaitEvent(s3, ev_fwd, 0), "rom_adjoint: event");
+    ACHK(recompute(nseg - 1), "rom_adjoint: recompute");
     for (int64_t g = nseg - 1; g >= 0; --g) {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
-        const float *cg = ck + (size_t)g * (v1 + s1);
-        ACHK(hipMemcpyAsync(curV, cg, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: restore");
-        ACHK(hipMemcpyAsync(curS, cg + v1, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: restore");
-        // recompute the segment, keeping every state and the probe trace
-        rom::Rank2Args fw = a;
-        fw.V = curV; fw.S = curS; fw.J = nullptr; fw.y = ytr; fw.n0 = nb; fw.nsteps = len;
-        fw.vtr = vtr; fw.str = str;
-        ACHK(rom::launch_rank2_f32_mfma(fw, 1, st), "rom_adjoint: recompute launch");
+        const int b = (int)(g % kTr), bw = (int)(g % kWq);
+        if (g >= 1) ACHK(recompute(g - 1), "rom_adjoint: recompute");
+        ACHK(hipStreamWaitEvent(st, ev_rec[b], 0), "rom_adjoint: event");
+        if (g + kWq < nseg) ACHK(hipStreamWaitEvent(st, ev_wq_free[bw], 0), "rom_adjoint: event");
         // reverse steps nb + len - 1 .. nb
         rom::Rank2Args ad = a;
         ad.avs = ctx->asvT_pk; ad.asv = ctx->avsT_pk; ad.V = P; ad.S = Q; ad.J = nullptr;
-        ad.n0 = nb; ad.nsteps = len; ad.ytr = ytr; ad.wtr = wtr; ad.qtr = qtr; ad.dmu = dmu;
+        ad.n0 = nb; ad.nsteps = len; ad.ytr = ytrb[b]; ad.wtr = wtrb[bw]; ad.qtr = qtrb[bw]; ad.dmu = dmu;
         ACHK(rom::launch_adjoint_f32_mfma(ad, st), "rom_adjoint: reverse launch");
+        ACHK(hipEventRecord(ev_rev[bw], st), "rom_adjoint: event");
         // dAvs += dt sum_n W^n (S^n)^T ;  dAsv += dt sum_n Q^{n+1} (V^{n+1})^T
+        ACHK(hipStreamWaitEvent(s3, ev_rev[bw], 0), "rom_adjoint: event");
         if (dAvs)
-            ACHK(rom::launch_gemm_nt_acc64(wtr, str, kv, ks, len * M, ctx->dt, dAvs64, part, st),
+            ACHK(rom::launch_gemm_nt_acc64(wtrb[bw], strb[b], kv, ks, len * M, ctx->dt, dAvs64, part, s3),
                  "rom_adjoint: gradient product");
         if (dAsv)
-            ACHK(rom::launch_gemm_nt_acc64(qtr, vtr + v1, ks, kv, len * M, ctx->dt, dAsv64, part, st),
+            ACHK(rom::launch_gemm_nt_acc64(qtrb[bw], vtrb[b] + v1, ks, kv, len * M, ctx->dt, dAsv64, part, s3),
                  "rom_adjoint: gradient product");
+        ACHK(hipEventRecord(ev_tr_free[b], s3), "rom_adjoint: event");
+        ACHK(hipEventRecord(ev_wq_free[bw], s3), "rom_adjoint: event");
     }
+    // join: nothing of this call stays on the side streams
+    ACHK(hipEventRecord(ctx->ev[11], s2), "rom_adjoint: event");
+    ACHK(hipEventRecord(ctx->ev[12], s3), "rom_adjoint: event");
+    ACHK(hipStreamWaitEvent(st, ctx->ev[11], 0), "rom_adjoint: event");
+    ACHK(hipStreamWaitEvent(st, ctx->ev[12], 0), "rom_adjoint: event");
     if (dAvs) ACHK(rom::launch_f64_to_f32(dAvs64, (float *)dAvs, (int64_t)kv * ks, st), "rom_adjoint: convert");
     if (dAsv) ACHK(rom::launch_f64_to_f32(dAsv64, (float *)dAsv, (int64_t)kv * ks, st), "rom_adjoint: convert");
 #undef ACHK

@@ -66,6 +66,12 @@ struct rom_ctx {
     // Device status words: [0] scratch of rom_create, [1] in-kernel error
     // (ROM_E_TIMEOUT), [2] abort flag of the row-split barriers.
     int *status = nullptr;
+    // Adjoint pipeline (built on first use): side streams (default
+    // priority) that recompute the next segment ([0]) and run the gradient
+    // products of the last one ([1]) while the caller's stream runs the
+    // current segment's reverse sweep, and their events (see rom_adjoint).
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev[13] = {};
 };
 
 namespace rom {

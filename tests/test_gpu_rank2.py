@@ -216,11 +216,14 @@ def test_zero_steps_is_noop_and_energy():
 
 
 @pytest.mark.parametrize("kv,ks,M,N", [(256, 256, 13, 1500), (192, 320, 37, 800), (70, 45, 9, 1200),
-                                       (512, 512, 8, 400), (1024, 1024, 21, 150)])
+                                       (512, 512, 8, 400), (1024, 1024, 21, 150), (64, 64, 5, 800),
+                                       (128, 128, 9, 1000), (320, 448, 17, 600), (576, 576, 12, 300),
+                                       (704, 128, 6, 500), (960, 900, 9, 200)])
 def test_fp32_columns8_bitwise_equals_columns4(kv, ks, M, N):
     """8-column blocks run each column's products in the same chunk and fold
     order as 4-column blocks: states, J and the probe trace are bitwise
-    equal, and within the FP32 bar of the oracle (ragged M, Kv != Ks)."""
+    equal, and within the FP32 bar of the oracle (ragged M, Kv != Ks, row
+    tile counts K/64 from 1 to 16, so the waves' tile rounds are uneven)."""
     inst = synth.round_to(synth.make_instance(kv, ks, M, seed=kv + 3 * ks + M, skew=(kv == ks)), "f32")
     a = _gpu_run(inst, "f32", N, probe=True, trace=True, schedule="columns")
     b = _gpu_run(inst, "f32", N, probe=True, trace=True, schedule="columns8")
