@@ -8,6 +8,10 @@ namespace dev {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left free (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVm0 = 0x0F70;
+
 // Error-free sum: s + e == a + b exactly (Knuth's two-sum, 6 flops, no
 // assumption on magnitudes).  Built with -ffp-contract=off so nothing here
 // is fused or reassociated.

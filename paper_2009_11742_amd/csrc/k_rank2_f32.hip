@@ -149,6 +149,11 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     f4 resv[2 * res_pairs(NS)][kQ], ress[2 * res_pairs(NS)][kQ];
     load_resident<NS>(resv, fv, w, lane);
     load_resident<NS>(ress, fs, w, lane);
+    // Let the resident loads land before the time loop: otherwise the
+    // wait-count analysis merges "maybe still loading" into the loop header
+    // and waits before every use of a resident register, which (counters
+    // retire in order) also waits out the operator stream's prefetch.
+    __builtin_amdgcn_s_waitcnt(dev::kWaitVm0);
     f4 a0[kQ], a1[kQ];
     Stream str;
     stream_start(str, a0, a1, fv, fs, w, lane);
