@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -130,7 +130,7 @@ def main():
     if not args.no_cpu:
         import oracle
         nthr = oracle.num_threads()
-        ncol = max(16, nthr)
+        ncol = min(M, 8 * max(2, nthr))      # ~10 s of oracle work on 16 host threads
         cols = np.linspace(0, M - 1, ncol).round().astype(int)
         t2 = time.perf_counter()
         ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][cols], NSTEPS,
@@ -393,8 +393,36 @@ def workload_sweep(args, torch, dev):
     return out
 
 
+def workload_plain(args, torch, dev):
+    """The plain-method workload: K = 64, M in {1, 8}, 2000 steps, FP64
+    states and operators (latency bound: two dependent half-steps per step,
+    no roofline).  Error against the FP64 oracle on every column."""
+    import oracle
+    import synth
+    from paper_2009_11742_amd import Rom
+    N = 2000
+    out = {"workload": "plain: Kv=Ks=64, M in {1, 8}, 2000 steps, FP64", "unit": "sample-steps/s", "runs": {}}
+    for M in (1, 8):
+        inst = synth.make_instance(64, 64, M, seed=0)
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64")
+        mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+        V, S = rom.zeros(M, device=dev)
+
+        def run():
+            V.zero_(); S.zero_()
+            rom.run_rank2(mu, V, S, N)
+        wall, ms = _events_time(torch, run, 5, 1)
+        ksec = float(np.median(ms)) * 1e-3
+        ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
+        err = max(_err_cols(V.cpu().numpy().T, ref["V"]), _err_cols(S.cpu().numpy().T, ref["S"]))
+        out["runs"]["M%d" % M] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6,
+                                  "max_rel_err_vs_oracle": err}
+        rom.close()
+    return out
+
+
 OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
-         "copy": workload_copy, "sweep": workload_sweep}
+         "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain}
 
 
 if __name__ == "__main__":

@@ -1,0 +1,119 @@
+"""Edge cases of the GPU path: the largest LDS-resident FP32 state
+(Kv_pad + Ks_pad = 4096), the first size past it (ROM_E_UNSUPPORTED), the
+8-column flag where 8 samples' state does not fit (falls back to 4), a
+single sample on every FP32 schedule, a one-step adjoint and a stride >= N
+adjoint, and a grouped run of one instance with one sample.  Bars as
+elsewhere: 1e-5 (FP32 states), 1e-4 (adjoint gradients)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _relcol(X, R):
+    nr = np.linalg.norm(R, axis=0)
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.where(nr > 0, nr, 1.0)))
+
+
+def _run(inst, N, schedule="auto", probe=True):
+    from paper_2009_11742_amd import Rom
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=schedule)
+    M = len(inst["mu"])
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(M)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda") if probe else None
+    J = torch.zeros(M, dtype=torch.float64, device="cuda") if probe else None
+    rom.run_rank2(mu, V, S, N, c=c, J=J)
+    rom.check()
+    out = {"V": V.cpu().numpy().astype(np.float64).T, "S": S.cpu().numpy().astype(np.float64).T,
+           "J": J.cpu().numpy() if probe else None, "schedule": rom.last_schedule}
+    rom.close()
+    return out
+
+
+@pytest.mark.parametrize("kv,ks,M", [(2048, 2048, 5), (3000, 1000, 3)])
+def test_largest_lds_resident_state(kv, ks, M):
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=kv + ks, skew=(kv == ks)), "f32")
+    N = 20
+    g = _run(inst, N)
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    e = max(_relcol(g["V"], r["V"]), _relcol(g["S"], r["S"]))
+    print("largest state kv=%d ks=%d M=%d: err %.2e schedule %s" % (kv, ks, M, e, g["schedule"]))
+    assert e <= 1e-5
+    assert np.max(np.abs(g["J"] - r["J"]) / r["J"]) <= 1e-5
+
+
+def test_past_the_lds_limit_is_unsupported():
+    from paper_2009_11742_amd import Rom, RomError
+    from paper_2009_11742_amd import _lib
+    inst = synth.round_to(synth.make_instance(2049, 2048, 2, seed=1, skew=False), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(2)
+    with pytest.raises(RomError) as ei:
+        rom.run_rank2(mu, V, S, 5)
+    assert ei.value.status == _lib.ROM_E_UNSUPPORTED
+    assert torch.count_nonzero(V) == 0 and torch.count_nonzero(S) == 0     # nothing written
+    rom.close()
+
+
+def test_columns8_flag_falls_back_where_8_samples_do_not_fit():
+    inst = synth.round_to(synth.make_instance(1536, 1536, 9, seed=3), "f32")
+    N = 30
+    g = _run(inst, N, schedule="columns8")
+    assert g["schedule"] == "columns"
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    assert max(_relcol(g["V"], r["V"]), _relcol(g["S"], r["S"])) <= 1e-5
+
+
+@pytest.mark.parametrize("schedule", ["columns", "columns8", "rowsplit"])
+def test_single_sample_every_schedule(schedule):
+    inst = synth.round_to(synth.make_instance(256, 256, 1, seed=4), "f32")
+    N = 800
+    g = _run(inst, N, schedule=schedule)
+    assert g["schedule"] == schedule
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    assert max(_relcol(g["V"], r["V"]), _relcol(g["S"], r["S"])) <= 1e-5
+    assert abs(g["J"][0] - r["J"][0]) / r["J"][0] <= 1e-5
+
+
+@pytest.mark.parametrize("N,stride", [(1, 0), (37, 37), (37, 1000)])
+def test_adjoint_short_and_single_segment(N, stride):
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(48, 40, 3, seed=9, skew=False), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    out = rom.adjoint(mu, N, c, stride=stride)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    rom.close()
+    r = oracle.adjoint(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, inst["c"])
+    for k in ("J", "dAvs", "dAsv", "dmu"):
+        nr = float(np.linalg.norm(r[k]))
+        if nr == 0.0:
+            # one step from rest: S^0 = 0 and q starts at 0, so the operator
+            # gradients are exactly zero
+            assert float(np.linalg.norm(g[k])) == 0.0, k
+            continue
+        e = float(np.linalg.norm(g[k] - r[k])) / nr
+        assert e <= 1e-4, (k, e)
+
+
+def test_grouped_single_instance_single_sample():
+    from paper_2009_11742_amd import Rom, run_grouped
+    inst = synth.round_to(synth.make_instance(96, 160, 1, seed=12, skew=False), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(1)
+    run_grouped([rom], [mu], [V], [S], 900)
+    torch.cuda.synchronize()
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 900)
+    assert _relcol(V.cpu().numpy().astype(np.float64).T, r["V"]) <= 1e-5
+    assert _relcol(S.cpu().numpy().astype(np.float64).T, r["S"]) <= 1e-5
+    rom.close()
