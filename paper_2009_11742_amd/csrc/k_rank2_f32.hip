@@ -80,6 +80,41 @@ __device__ __forceinline__ void store_cols(float *dst, const float *hi, const fl
     }
 }
 
+// Trace stores inside the time loop.  A store loop with a run-time trip
+// count leaves the compiler unable to count the vector-memory operations in
+// flight, so the next wait on an operator-stream load would wait for the
+// stores as well.  The fixed form issues exactly NC float4 stores per thread
+// (no branch): thread tid writes float4 tid mod K/4 of every column; threads
+// past K/4 and columns past M rewrite an element another store of the same
+// call also writes, with the same value.  Needs K % 4 == 0, K <= 4 kThreads
+// and a 16-byte aligned destination (the host checks).
+enum Traces { kNoTraces = 0, kFixedTraces = 1, kLoopTraces = 2 };
+
+template <int NC>
+__device__ __forceinline__ void store_cols_fixed(float *dst, const float *hi, const float *lo, int ld, int K,
+                                                 int col0, int M, int tid) {
+    const int q4 = K >> 2;
+    const int q = tid % q4;
+    const int last = min(NC, M - col0) - 1;
+    f4 *d = reinterpret_cast<f4 *>(dst);
+#pragma unroll
+    for (int jj = 0; jj < NC; ++jj) {
+        const int c = min(jj, last);
+        const f4 h = reinterpret_cast<const f4 *>(hi + c * ld)[q];
+        const f4 l = reinterpret_cast<const f4 *>(lo + c * ld)[q];
+        d[(size_t)(col0 + c) * q4 + q] = h + l;
+    }
+}
+
+template <int TR, int NC>
+__device__ __forceinline__ void store_trace(float *dst, const float *hi, const float *lo, int ld, int K, int Kp,
+                                            int col0, int M, int tid) {
+    if (TR == kFixedTraces)
+        store_cols_fixed<NC>(dst, hi, lo, ld, K, col0, M, tid);
+    else
+        store_cols(dst, hi, lo, ld, K, Kp, col0, M, NC, tid);
+}
+
 // One workgroup per CU, one wave per SIMD: the compiler may use the whole
 // register file for the prefetch buffers instead of trading them for
 // occupancy.
@@ -92,7 +127,7 @@ __device__ __forceinline__ void store_cols(float *dst, const float *hi, const fl
 //   b; step n = n0 + nsteps - 1 - k at iteration k; writes
 //   a.qtr[n - n0] = Q before and a.wtr[n - n0] = P after the P update, and
 //   adds dt (b^T P) du/dmu(t_n) to a.dmu.
-template <int MODE, int NS>
+template <int MODE, int NS, int TR>
 __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned char *smem) {
     constexpr int NC = NB * NS;                  // columns of this workgroup
     const int kvp = a.kvp, ksp = a.ksp;
@@ -142,6 +177,13 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     }
     const bool probe = prb != nullptr;
     double Jacc = 0.0;
+    // With traces (recompute and adjoint launches, probe always present)
+    // every thread takes part in the per-step probe epilogue for a valid
+    // column pc (threads past the block's columns repeat the last one), so
+    // that epilogue has no branch either; pc == tid for the threads that
+    // write J / dmu.
+    const int pc = min(tid % NC, min(NC, a.M - col0) - 1);
+    const double mupc = a.mu[col0 + pc];
     const Field fv = {static_cast<const f4 *>(a.avs), kvp / kTileRows, ksp, ksp / kChunk,
                       resident_pairs(ksp / kChunk, NS), Sh, lds_, Vh, Vl, ldv};
     const Field fs = {static_cast<const f4 *>(a.asv), ksp / kTileRows, kvp, kvp / kChunk,
@@ -158,9 +200,9 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     Stream str;
     stream_start(str, a0, a1, fv, fs, w, lane);
     __syncthreads();
-    if (MODE == kForward && a.vtr) {
-        store_cols(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
-        store_cols(a.str, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
+    if (MODE == kForward && TR != kNoTraces) {
+        store_trace<TR, NC>(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
+        store_trace<TR, NC>(a.str, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
     }
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
@@ -172,11 +214,11 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
         for (int q = 0; q < NS; ++q) {
             if (MODE == kForward)
                 u64[q] = mok[q] ? dev::ricker(t, muj[q]) : 0.0;
-            else
-                u64[q] = mok[q] ? 2.0 * a.ytr[(size_t)r * a.M + m[q]] : 0.0;
+            else   // clamped column: the load is unconditional, the value selected
+                u64[q] = mok[q] ? 2.0 * a.ytr[(size_t)r * a.M + min(m[q], a.M - 1)] : 0.0;
         }
         if (MODE == kAdjoint)   // q^{n+1}, paired with V^{n+1} in the dAsv product
-            store_cols(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
+            store_trace<TR, NC>(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
 
         // ---- first half-step: V += dt (Avs S + b u^T)   |   P += dt (Asv^T Q + 2 y c)
         double ypart[NS];
@@ -193,14 +235,24 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
             }
         }
         if (MODE == kAdjoint)   // w^n, paired with S^n in the dAvs product
-            store_cols(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
+            store_trace<TR, NC>(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
         // ---- second half-step: S += dt Asv V   |   Q += dt Avs^T P
         // (its barrier also publishes yp before it is read below)
         double zero[NS], dummy[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) zero[q] = dummy[q] = 0.0;
         half_step<false, NS>(fs, ress, a0, a1, str, fv, fs, lane, w, bl, cl, zero, a.dt, dummy);
-        if (probe && tid < NC && col0 + tid < a.M) {
+        if (TR != kNoTraces) {
+            double yv = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) yv += yp[q * NC + pc];
+            if (MODE == kForward) {
+                Jacc += a.dt * (yv * yv);
+                a.y[(size_t)k * a.M + col0 + pc] = yv;
+            } else {
+                Jacc += a.dt * yv * dev::ricker_dmu(t, mupc);
+            }
+        } else if (probe && tid < NC && col0 + tid < a.M) {
             double yv = 0.0;
 #pragma unroll
             for (int q = 0; q < kWaves; ++q) yv += yp[q * NC + tid];
@@ -211,9 +263,9 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
                 Jacc += a.dt * yv * dev::ricker_dmu(t, a.mu[col0 + tid]);
             }
         }
-        if (MODE == kForward && a.vtr) {
-            store_cols(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
-            store_cols(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
+        if (MODE == kForward && TR != kNoTraces) {
+            store_trace<TR, NC>(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
+            store_trace<TR, NC>(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
         }
     }
 
@@ -225,11 +277,11 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     }
 }
 
-template <int MODE, int NS>
+template <int MODE, int NS, int TR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_f32_mfma_kernel(Rank2Args a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_block<MODE, NS>(a, blockIdx.x * NB * NS, smem);
+    run_block<MODE, NS, TR>(a, blockIdx.x * NB * NS, smem);
 }
 
 // Grouped forward run: workgroup i advances the column block of instance
@@ -245,9 +297,9 @@ void grouped_f32_mfma_kernel(const Rank2Args *__restrict__ inst, const int2 *__r
     a.n0 = n0;
     a.nsteps = nsteps;
     if (a.nset == 2)
-        run_block<kForward, 2>(a, it.y, smem);
+        run_block<kForward, 2, kNoTraces>(a, it.y, smem);
     else
-        run_block<kForward, 1>(a, it.y, smem);
+        run_block<kForward, 1, kNoTraces>(a, it.y, smem);
 }
 
 }  // namespace
@@ -256,21 +308,45 @@ size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp, int nset) {
     return state_lds_bytes(kvp, ksp, NB * nset);
 }
 
+// Whether the fixed-count trace stores apply to traces of Kv and Ks rows
+// at these addresses (and the probe the branch-free epilogue needs is
+// there: c with its trace y forward, b in the adjoint).
+static bool fixed_traces_ok(const Rank2Args &a, const void *t0, const void *t1, bool adjoint) {
+    const bool probe = adjoint ? (a.b != nullptr && a.ytr != nullptr) : (a.c != nullptr && a.y != nullptr);
+    return probe && a.kv % 4 == 0 && a.ks % 4 == 0 && a.kv <= 4 * kThreads && a.ks <= 4 * kThreads &&
+           (reinterpret_cast<uintptr_t>(t0) & 15) == 0 && (reinterpret_cast<uintptr_t>(t1) & 15) == 0;
+}
+
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st) {
     const int nc = NB * nset;
     const int blocks = (a.M + nc - 1) / nc;
     const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, nset);
-    if (nset == 2)
-        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 2>), dim3(blocks), dim3(kThreads), lds, st, a);
-    else
-        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1>), dim3(blocks), dim3(kThreads), lds, st, a);
+    if (a.vtr) {   // state traces: one column set
+        if (fixed_traces_ok(a, a.vtr, a.str, false))
+            hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kFixedTraces>), dim3((a.M + NB - 1) / NB),
+                               dim3(kThreads), rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1), st, a);
+        else
+            hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kLoopTraces>), dim3((a.M + NB - 1) / NB),
+                               dim3(kThreads), rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1), st, a);
+    } else if (nset == 2) {
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 2, kNoTraces>), dim3(blocks), dim3(kThreads), lds, st,
+                           a);
+    } else {
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kNoTraces>), dim3(blocks), dim3(kThreads), lds, st,
+                           a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st) {
     const int blocks = (a.M + NB - 1) / NB;
     const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1);
-    hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1>), dim3(blocks), dim3(kThreads), lds, st, a);
+    if (fixed_traces_ok(a, a.wtr, a.qtr, true))
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1, kFixedTraces>), dim3(blocks), dim3(kThreads), lds,
+                           st, a);
+    else
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1, kLoopTraces>), dim3(blocks), dim3(kThreads), lds,
+                           st, a);
     return hipGetLastError();
 }
 
@@ -284,9 +360,12 @@ hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_
 
 hipError_t rank2_f32_mfma_configure() {
     const void *fns[] = {(const void *)grouped_f32_mfma_kernel,
-                         (const void *)rank2_f32_mfma_kernel<kForward, 1>,
-                         (const void *)rank2_f32_mfma_kernel<kForward, 2>,
-                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1>};
+                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kNoTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kForward, 2, kNoTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kFixedTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kLoopTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kFixedTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kLoopTraces>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
