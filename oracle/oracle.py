@@ -142,6 +142,52 @@ def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=F
     return out
 
 
+def receivers(Avs, Asv, b, dt, mu, nsteps, C, V=None, S=None, n0=0):
+    """Seismograms at R receivers (the reconstruction of the velocity at
+    target points from single rows of the velocity basis, Sec. 4.5):
+    Y[k, r, m] = C[r] . V_m after step n0 + k, for k = 0 .. nsteps - 1.
+
+    C is R x Kv (one receiver row per row).  The run is stepped one step at a
+    time through run_rank2, which is bitwise identical to one run in the
+    oracle.  Returns Y (nsteps, R, M) and the final V, S.
+    """
+    Avs = _f64(Avs); Asv = _f64(Asv)
+    kv, ks = Avs.shape
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    M = mu.size
+    Cm = np.asarray(C, dtype=np.float64).reshape(-1, kv)
+    R = Cm.shape[0]
+    V = np.zeros((kv, M), order="F") if V is None else np.array(V, dtype=np.float64, order="F", copy=True)
+    S = np.zeros((ks, M), order="F") if S is None else np.array(S, dtype=np.float64, order="F", copy=True)
+    Y = np.zeros((int(nsteps), R, M))
+    for k in range(int(nsteps)):
+        out = run_rank2(Avs, Asv, b, dt, mu, 1, V=V, S=S, n0=n0 + k)
+        V, S = out["V"], out["S"]
+        for r in range(R):
+            for m in range(M):
+                Y[k, r, m] = float(np.dot(Cm[r], V[:, m]))
+    return {"Y": Y, "V": V, "S": S}
+
+
+def percentile_index(p, M):
+    """0-based index of the nearest-rank p-th percentile of M sorted values:
+    the ceil(p M / 100)-th smallest, at least the smallest."""
+    return max(1, -(-int(p) * int(M) // 100)) - 1
+
+
+def ensemble_stats(Y, percentiles=(5, 50, 95)):
+    """Statistics over the sample axis (last) of Y (..., M): mean, variance
+    (population, 1/M) and nearest-rank percentiles.  Returns an array
+    (..., 2 + len(percentiles)): mean, var, then the percentiles."""
+    Y = np.asarray(Y, dtype=np.float64)
+    M = Y.shape[-1]
+    mean = Y.sum(axis=-1) / M
+    var = ((Y - mean[..., None]) ** 2).sum(axis=-1) / M
+    srt = np.sort(Y, axis=-1)
+    cols = [mean, var] + [srt[..., percentile_index(p, M)] for p in percentiles]
+    return np.stack(cols, axis=-1)
+
+
 def energy(Avs, dt, V, S):
     """Modified discrete energy |v|^2 + |s|^2 + dt v^T Avs s per column."""
     Avs = _f64(Avs)

@@ -409,3 +409,56 @@ def test_quantize_e4m3_matches_torch():
     assert s2 == 1.0
     ref2 = torch.clamp(torch.from_numpy(y).to(torch.float32), -448, 448).to(torch.float8_e4m3fn).to(torch.float64).numpy()
     assert np.array_equal(deq2, ref2)
+
+
+# --------------------------------------------------------------------------
+# Receivers (seismograms from single basis rows, Sec. 4.5) and ensemble
+# statistics (mean and percentile bounds over the ensemble)
+# --------------------------------------------------------------------------
+
+def test_receivers_single_row_reproduces_probe_qoi_and_trace():
+    """With one receiver row equal to the probe c, the seismogram is the
+    probe trace y and dt sum_n y^2 is the probe QoI J of run_rank2."""
+    inst = synth.make_instance(24, 20, 5, seed=31, skew=False)
+    N = 60
+    rc = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, inst["c"][None, :])
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"], trace=True)
+    assert np.allclose(rc["Y"][:, 0, :], r["y"], rtol=1e-13, atol=1e-15 * np.max(np.abs(r["y"])))
+    J = inst["dt"] * np.sum(rc["Y"][:, 0, :] ** 2, axis=0)
+    assert np.allclose(J, r["J"], rtol=1e-12)
+    assert np.array_equal(rc["V"], r["V"]) and np.array_equal(rc["S"], r["S"])
+
+
+def test_receivers_linear_in_rows_and_offset_run():
+    inst = synth.make_instance(16, 16, 3, seed=32)
+    rng = np.random.default_rng(1)
+    C1, C2 = rng.standard_normal((2, 16)), rng.standard_normal((2, 16))
+    N = 40
+    y1 = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, C1)["Y"]
+    y2 = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, C2)["Y"]
+    y12 = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, C1 + 2.0 * C2)["Y"]
+    assert np.allclose(y12, y1 + 2.0 * y2, rtol=1e-12, atol=1e-14 * np.max(np.abs(y12)))
+    # a run split at step 15 gives the same rows
+    a = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], 15, C1)
+    b2 = oracle.receivers(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N - 15, C1, V=a["V"], S=a["S"], n0=15)
+    assert np.array_equal(np.concatenate([a["Y"], b2["Y"]]), y1)
+
+
+def test_ensemble_stats_closed_forms():
+    # 1..M: mean (M+1)/2, population variance (M^2-1)/12; nearest rank
+    for M in (1, 2, 7, 20, 100, 256, 1000):
+        Y = np.random.default_rng(M).permutation(np.arange(1, M + 1, dtype=np.float64))[None, :]
+        st = oracle.ensemble_stats(Y)[0]
+        assert st[0] == pytest.approx((M + 1) / 2, rel=1e-15)
+        assert st[1] == pytest.approx((M * M - 1) / 12, rel=1e-13, abs=1e-15)
+        for k, p in enumerate((5, 50, 95)):
+            assert st[2 + k] == max(1, math.ceil(p * M / 100))    # the value equals its rank
+    # every percentile is one of the samples, and p05 <= p50 <= p95
+    Y = np.random.default_rng(0).standard_normal((7, 3, 33))
+    st = oracle.ensemble_stats(Y)
+    for i in range(7):
+        for r in range(3):
+            assert all(v in Y[i, r] for v in st[i, r, 2:])
+            assert st[i, r, 2] <= st[i, r, 3] <= st[i, r, 4]
+    assert oracle.percentile_index(5, 20) == 0 and oracle.percentile_index(50, 20) == 9
+    assert oracle.percentile_index(95, 20) == 18 and oracle.percentile_index(95, 1) == 0
