@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -421,8 +421,43 @@ def workload_plain(args, torch, dev):
     return out
 
 
+def workload_receivers(args, torch, dev):
+    """The bench workload (K = 256, M = 256, 10^4 steps, FP32) with 16
+    receiver rows: seismograms (FP64) and per-step ensemble statistics,
+    timed against the plain run of the same shape (4-column schedule)."""
+    import synth
+    from paper_2009_11742_amd import Rom
+    R = 16
+    inst = synth.round_to(synth.make_instance(KV, KS, M, seed=SEED), "f32")
+    C = torch.tensor(np.asarray(np.random.default_rng(7).standard_normal((R, KV)), dtype=np.float32), device=dev)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule="columns")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    V, S = rom.zeros(M, device=dev)
+    Y = torch.empty((NSTEPS, R, M), dtype=torch.float64, device=dev)
+    st = torch.empty((NSTEPS, R, 5), dtype=torch.float64, device=dev)
+    from paper_2009_11742_amd import _lib
+    from paper_2009_11742_amd.rom import _ptr, _stream_handle
+
+    def run_rc():
+        V.zero_(); S.zero_()
+        _lib.check(_lib.load().rom_run_receivers(rom.handle, M, _ptr(mu), 0, NSTEPS, _ptr(V), _ptr(S), R, _ptr(C),
+                                                 _ptr(Y), _ptr(st), _stream_handle(None)))
+
+    def run_plain():
+        V.zero_(); S.zero_()
+        rom.run_rank2(mu, V, S, NSTEPS)
+    _, ms_rc = _events_time(torch, run_rc, 3, 1)
+    _, ms_pl = _events_time(torch, run_plain, 3, 1)
+    t_rc, t_pl = float(np.median(ms_rc)) * 1e-3, float(np.median(ms_pl)) * 1e-3
+    rom.close()
+    return {"workload": "receivers: Kv=Ks=256, M=256, 10000 steps, R=16 receivers, Y + mean/var/p5/p50/p95 per step",
+            "value": M * NSTEPS / t_rc, "unit": "sample-steps/s", "ms_per_run": t_rc * 1e3,
+            "plain_ms_per_run": t_pl * 1e3, "overhead": t_rc / t_pl - 1.0}
+
+
 OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
-         "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain}
+         "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain,
+         "receivers": workload_receivers}
 
 
 if __name__ == "__main__":

@@ -296,6 +296,38 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
                        void *stream);
 
 /*
+ * Seismograms at R receivers and their ensemble statistics (Sec. 4.5: the
+ * velocity at a target point is reconstructed from a single row of the
+ * velocity basis, and the ensemble over the forcing parameter is summarised
+ * by its mean and percentile bounds).  Advances all M samples by `nsteps`
+ * steps from step n0 like rom_run_rank2 and records, for every step n and
+ * receiver r,
+ *   Y[n][r][m] = C[r] . V_m after step n0 + n
+ * and over the M samples: mean, population variance (1/M) and the
+ * nearest-rank 5th, 50th and 95th percentiles (the ceil(p M / 100)-th
+ * smallest value).
+ *
+ *   M        samples, 1 .. 1024
+ *   mu, V, S as rom_run_rank2 (V, S updated in place)
+ *   R        receivers, 1 .. 64, with R x M <= 8192
+ *   C        dev, R x Kv row-major state type (FP32): one receiver row each
+ *   Y        dev, nsteps x R x M FP64 seismograms, or NULL
+ *   stats    dev, nsteps x R x 5 FP64 (mean, variance, p5, p50, p95), or
+ *            NULL
+ *
+ * FP32 states and operators only, on the 4-column column-block schedule.
+ * The run is stepped in chunks whose state traces stay in device memory
+ * (up to 2 x 256 MiB of workspace, kept by the context); the seismograms and
+ * statistics of a chunk are computed on an internal stream while the next
+ * chunk steps.  Chunk boundaries round the state once, as a split
+ * rom_run_rank2 does.  Errors: ROM_E_ARG, ROM_E_UNSUPPORTED (sizes above),
+ * ROM_E_NOMEM, ROM_E_DEVICE.
+ */
+rom_status rom_run_receivers(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
+                             void *V, void *S, int32_t R, const void *C, double *Y, double *stats,
+                             void *stream);
+
+/*
  * Grouped run: G independent ROM instances (each its own context, sizes and
  * samples) advanced `nsteps` steps from step 0 in ONE launch — the batched
  * direction the paper names for many operator realisations (Sec. 5).  Work

@@ -28,7 +28,7 @@ ROM_NSCHEDULES = 3
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
-           "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear",
+           "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_last_error", "rom_version"]
 
 
@@ -102,6 +102,8 @@ def load():
         lib.rom_last_schedule.argtypes = [_vp]
         lib.rom_schedule_times.restype = C.c_int
         lib.rom_schedule_times.argtypes = [_vp, _i32, C.POINTER(_d)]
+        lib.rom_run_receivers.restype = C.c_int
+        lib.rom_run_receivers.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp]
         lib.rom_tune_count.restype = C.c_int32
         lib.rom_tune_count.argtypes = []
         lib.rom_tune_get.restype = C.c_int

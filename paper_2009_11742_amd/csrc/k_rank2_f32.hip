@@ -57,63 +57,34 @@ __device__ __forceinline__ void half_step(const Field &f, const f4 (&res)[2 * re
 }
 
 // Copy the (hi + lo) LDS columns (nb of them) of this workgroup to a K x M
-// global matrix: column by column, float4 stores where the matrix is
-// 16-byte aligned and K a multiple of 4 (every column then starts aligned),
-// no per-element index division.
-__device__ __forceinline__ void store_cols(float *dst, const float *hi, const float *lo, int ld, int K, int Kp,
-                                           int col0, int M, int nb, int tid) {
-    (void)Kp;
+// global matrix.  The (column, element) pairs are spread over all threads
+// (each stored once, the waves evenly loaded), as float4 where the matrix is
+// 16-byte aligned and K a multiple of 4 (every column then starts aligned).
+__device__ __forceinline__ void store_cols(float *dst, const float *hi, const float *lo, int ld, int K, int col0,
+                                           int M, int nb, int tid) {
     const int ncol = min(nb, M - col0);
     if ((K & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
         const int q4 = K >> 2;
-        for (int jj = 0; jj < ncol; ++jj) {
-            f4 *d = reinterpret_cast<f4 *>(dst + (size_t)(col0 + jj) * K);
-            const f4 *h = reinterpret_cast<const f4 *>(hi + jj * ld);
-            const f4 *l = reinterpret_cast<const f4 *>(lo + jj * ld);
-            for (int q = tid; q < q4; q += kThreads) d[q] = h[q] + l[q];
+        f4 *d = reinterpret_cast<f4 *>(dst) + (size_t)col0 * q4;
+        for (int idx = tid; idx < ncol * q4; idx += kThreads) {
+            const int c = idx / q4, q = idx - c * q4;
+            d[(size_t)c * q4 + q] = reinterpret_cast<const f4 *>(hi + c * ld)[q] +
+                                    reinterpret_cast<const f4 *>(lo + c * ld)[q];
         }
     } else {
-        for (int jj = 0; jj < ncol; ++jj) {
-            float *d = dst + (size_t)(col0 + jj) * K;
-            for (int i = tid; i < K; i += kThreads) d[i] = hi[jj * ld + i] + lo[jj * ld + i];
+        float *d = dst + (size_t)col0 * K;
+        for (int idx = tid; idx < ncol * K; idx += kThreads) {
+            const int c = idx / K, i = idx - c * K;
+            d[(size_t)c * K + i] = hi[c * ld + i] + lo[c * ld + i];
         }
     }
 }
 
-// Trace stores inside the time loop.  A store loop with a run-time trip
-// count leaves the compiler unable to count the vector-memory operations in
-// flight, so the next wait on an operator-stream load would wait for the
-// stores as well.  The fixed form issues exactly NC float4 stores per thread
-// (no branch): thread tid writes float4 tid mod K/4 of every column; threads
-// past K/4 and columns past M rewrite an element another store of the same
-// call also writes, with the same value.  Needs K % 4 == 0, K <= 4 kThreads
-// and a 16-byte aligned destination (the host checks).
-enum Traces { kNoTraces = 0, kFixedTraces = 1, kLoopTraces = 2 };
-
-template <int NC>
-__device__ __forceinline__ void store_cols_fixed(float *dst, const float *hi, const float *lo, int ld, int K,
-                                                 int col0, int M, int tid) {
-    const int q4 = K >> 2;
-    const int q = tid % q4;
-    const int last = min(NC, M - col0) - 1;
-    f4 *d = reinterpret_cast<f4 *>(dst);
-#pragma unroll
-    for (int jj = 0; jj < NC; ++jj) {
-        const int c = min(jj, last);
-        const f4 h = reinterpret_cast<const f4 *>(hi + c * ld)[q];
-        const f4 l = reinterpret_cast<const f4 *>(lo + c * ld)[q];
-        d[(size_t)(col0 + c) * q4 + q] = h + l;
-    }
-}
-
-template <int TR, int NC>
-__device__ __forceinline__ void store_trace(float *dst, const float *hi, const float *lo, int ld, int K, int Kp,
-                                            int col0, int M, int tid) {
-    if (TR == kFixedTraces)
-        store_cols_fixed<NC>(dst, hi, lo, ld, K, col0, M, tid);
-    else
-        store_cols(dst, hi, lo, ld, K, Kp, col0, M, NC, tid);
-}
+// Kernel variants: without state traces (every plain run), or writing them
+// every step (the adjoint's recompute and reverse sweeps, receiver runs),
+// which always come with a probe (c with its trace y forward, b in the
+// adjoint), so their per-step probe epilogue needs no branch.
+enum Traces { kNoTraces = 0, kTraces = 1 };
 
 // One workgroup per CU, one wave per SIMD: the compiler may use the whole
 // register file for the prefetch buffers instead of trading them for
@@ -200,9 +171,9 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     Stream str;
     stream_start(str, a0, a1, fv, fs, w, lane);
     __syncthreads();
-    if (MODE == kForward && TR != kNoTraces) {
-        store_trace<TR, NC>(a.vtr, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
-        store_trace<TR, NC>(a.str, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+    if (MODE == kForward && TR == kTraces) {
+        store_cols(a.vtr, Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+        store_cols(a.str, Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
     }
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
@@ -218,7 +189,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
                 u64[q] = mok[q] ? 2.0 * a.ytr[(size_t)r * a.M + min(m[q], a.M - 1)] : 0.0;
         }
         if (MODE == kAdjoint)   // q^{n+1}, paired with V^{n+1} in the dAsv product
-            store_trace<TR, NC>(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+            store_cols(a.qtr + (size_t)r * a.M * a.ks, Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
 
         // ---- first half-step: V += dt (Avs S + b u^T)   |   P += dt (Asv^T Q + 2 y c)
         double ypart[NS];
@@ -235,14 +206,14 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
             }
         }
         if (MODE == kAdjoint)   // w^n, paired with S^n in the dAvs product
-            store_trace<TR, NC>(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
+            store_cols(a.wtr + (size_t)r * a.M * a.kv, Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
         // ---- second half-step: S += dt Asv V   |   Q += dt Avs^T P
         // (its barrier also publishes yp before it is read below)
         double zero[NS], dummy[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) zero[q] = dummy[q] = 0.0;
         half_step<false, NS>(fs, ress, a0, a1, str, fv, fs, lane, w, bl, cl, zero, a.dt, dummy);
-        if (TR != kNoTraces) {
+        if (TR == kTraces) {
             double yv = 0.0;
 #pragma unroll
             for (int q = 0; q < kWaves; ++q) yv += yp[q * NC + pc];
@@ -263,14 +234,14 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
                 Jacc += a.dt * yv * dev::ricker_dmu(t, a.mu[col0 + tid]);
             }
         }
-        if (MODE == kForward && TR != kNoTraces) {
-            store_trace<TR, NC>(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, kvp, col0, a.M, tid);
-            store_trace<TR, NC>(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, ksp, col0, a.M, tid);
+        if (MODE == kForward && TR == kTraces) {
+            store_cols(a.vtr + (size_t)(k + 1) * a.M * a.kv, Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+            store_cols(a.str + (size_t)(k + 1) * a.M * a.ks, Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
         }
     }
 
-    store_cols(static_cast<float *>(a.V), Vh, Vl, ldv, a.kv, kvp, col0, a.M, NC, tid);
-    store_cols(static_cast<float *>(a.S), Sh, Sl, lds_, a.ks, ksp, col0, a.M, NC, tid);
+    store_cols(static_cast<float *>(a.V), Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+    store_cols(static_cast<float *>(a.S), Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
     if (probe && tid < NC && col0 + tid < a.M) {
         if (MODE == kForward && a.J) a.J[col0 + tid] += Jacc;
         if (MODE == kAdjoint && a.dmu) a.dmu[col0 + tid] += Jacc;
@@ -308,13 +279,9 @@ size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp, int nset) {
     return state_lds_bytes(kvp, ksp, NB * nset);
 }
 
-// Whether the fixed-count trace stores apply to traces of Kv and Ks rows
-// at these addresses (and the probe the branch-free epilogue needs is
-// there: c with its trace y forward, b in the adjoint).
-static bool fixed_traces_ok(const Rank2Args &a, const void *t0, const void *t1, bool adjoint) {
-    const bool probe = adjoint ? (a.b != nullptr && a.ytr != nullptr) : (a.c != nullptr && a.y != nullptr);
-    return probe && a.kv % 4 == 0 && a.ks % 4 == 0 && a.kv <= 4 * kThreads && a.ks <= 4 * kThreads &&
-           (reinterpret_cast<uintptr_t>(t0) & 15) == 0 && (reinterpret_cast<uintptr_t>(t1) & 15) == 0;
+// Traced launches need the probe of their branch-free epilogue.
+static bool traces_probe_ok(const Rank2Args &a, bool adjoint) {
+    return adjoint ? (a.b != nullptr && a.ytr != nullptr) : (a.c != nullptr && a.y != nullptr);
 }
 
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st) {
@@ -322,12 +289,8 @@ hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st) {
     const int blocks = (a.M + nc - 1) / nc;
     const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, nset);
     if (a.vtr) {   // state traces: one column set
-        if (fixed_traces_ok(a, a.vtr, a.str, false))
-            hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kFixedTraces>), dim3((a.M + NB - 1) / NB),
-                               dim3(kThreads), rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1), st, a);
-        else
-            hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kLoopTraces>), dim3((a.M + NB - 1) / NB),
-                               dim3(kThreads), rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1), st, a);
+        if (!traces_probe_ok(a, false) || nset != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 1, kTraces>), dim3(blocks), dim3(kThreads), lds, st, a);
     } else if (nset == 2) {
         hipLaunchKernelGGL((rank2_f32_mfma_kernel<kForward, 2, kNoTraces>), dim3(blocks), dim3(kThreads), lds, st,
                            a);
@@ -341,12 +304,8 @@ hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st) {
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st) {
     const int blocks = (a.M + NB - 1) / NB;
     const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1);
-    if (fixed_traces_ok(a, a.wtr, a.qtr, true))
-        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1, kFixedTraces>), dim3(blocks), dim3(kThreads), lds,
-                           st, a);
-    else
-        hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1, kLoopTraces>), dim3(blocks), dim3(kThreads), lds,
-                           st, a);
+    if (!traces_probe_ok(a, true)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((rank2_f32_mfma_kernel<kAdjoint, 1, kTraces>), dim3(blocks), dim3(kThreads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -362,10 +321,8 @@ hipError_t rank2_f32_mfma_configure() {
     const void *fns[] = {(const void *)grouped_f32_mfma_kernel,
                          (const void *)rank2_f32_mfma_kernel<kForward, 1, kNoTraces>,
                          (const void *)rank2_f32_mfma_kernel<kForward, 2, kNoTraces>,
-                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kFixedTraces>,
-                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kLoopTraces>,
-                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kFixedTraces>,
-                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kLoopTraces>};
+                         (const void *)rank2_f32_mfma_kernel<kForward, 1, kTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kTraces>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

@@ -101,6 +101,9 @@ void free_ctx(rom_ctx *c) {
         }
     for (hipEvent_t &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t &ev : c->rc_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    hfree(c->rc_ws);
     delete c;
 }
 
@@ -397,6 +400,7 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
         if (e == hipSuccess) e = rom::rank2_valu_configure();
         if (e == hipSuccess) e = rom::rank2_lowp_configure();
         if (e == hipSuccess) e = rom::rank2_split_configure();
+        if (e == hipSuccess) e = rom::receivers_configure();
         if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: kernel attributes"); }
         g_configured = true;
     }
@@ -835,6 +839,95 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     if (dAvs) ACHK(rom::launch_f64_to_f32(dAvs64, (float *)dAvs, (int64_t)kv * ks, st), "rom_adjoint: convert");
     if (dAsv) ACHK(rom::launch_f64_to_f32(dAsv64, (float *)dAsv, (int64_t)kv * ks, st), "rom_adjoint: convert");
 #undef ACHK
+    return ROM_OK;
+}
+
+rom_status rom_run_receivers(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps, void *V,
+                             void *S, int32_t R, const void *C, double *Y, double *stats, void *stream) {
+    if (!ctx) return fail(ROM_E_ARG, "rom_run_receivers: NULL context");
+    if (M < 1 || M > 1024) return fail(ROM_E_ARG, "rom_run_receivers: M must be in [1, 1024]");
+    if (R < 1 || R > 64) return fail(ROM_E_ARG, "rom_run_receivers: R must be in [1, 64]");
+    if (!mu || !V || !S || !C) return fail(ROM_E_ARG, "rom_run_receivers: NULL mu, V, S or C");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_run_receivers: n0 and nsteps must be >= 0");
+    if (ctx->state_type != ROM_F32 || ctx->op_type != ROM_F32)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_receivers: FP32 states and operators only");
+    if (ctx->kvp + ctx->ksp > rom::kMaxPadSum || rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 1) > 160 * 1024)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_receivers: Kv + Ks above the LDS-resident limit");
+    if ((int64_t)R * M > 8192 || rom::receivers_lds_bytes(ctx->kv, M, R) > 160 * 1024)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_receivers: R x M or R x Kv too large for one workgroup's LDS");
+    if (nsteps == 0) return ROM_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    const int kv = ctx->kv, ks = ctx->ks;
+    // chunk length: one set of state traces within 256 MiB
+    const size_t per_step = (size_t)(kv + ks) * M * sizeof(float);
+    int64_t L = (int64_t)((256u << 20) / per_step);
+    L = std::max<int64_t>(1, std::min<int64_t>(L, std::min<int64_t>(nsteps, 4096)));
+    const size_t n_tr = (size_t)(L + 1) * (kv + ks) * M;              // floats per set: V then S traces
+    const size_t n_set = ((n_tr + 3) / 4 * 4 * sizeof(float) + (size_t)L * M * sizeof(double) + 255) / 256 * 256;
+    const size_t bytes = 2 * n_set;
+    if (!ctx->side[0]) {
+        e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking);
+        for (int i = 0; i < 13 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: stream / event creation");
+    }
+    if (!ctx->rc_ev[0]) {
+        e = hipSuccess;
+        for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ctx->rc_ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: event creation");
+    }
+    if (ctx->rc_ws_bytes < bytes) {
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->side[0]);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: synchronize");
+        hfree(ctx->rc_ws);
+        ctx->rc_ws = nullptr;
+        ctx->rc_ws_bytes = 0;
+        e = hipMalloc(&ctx->rc_ws, bytes);
+        if (e != hipSuccess) { ctx->rc_ws = nullptr; return fail(ROM_E_NOMEM, "rom_run_receivers: workspace allocation failed"); }
+        ctx->rc_ws_bytes = bytes;
+    }
+    float *vtr[2], *str[2];
+    double *ysc[2];
+    for (int b = 0; b < 2; ++b) {
+        char *base = static_cast<char *>(ctx->rc_ws) + b * n_set;
+        vtr[b] = reinterpret_cast<float *>(base);
+        str[b] = vtr[b] + (size_t)(L + 1) * kv * M;
+        ysc[b] = reinterpret_cast<double *>(base + (n_tr + 3) / 4 * 4 * sizeof(float));
+    }
+    // Chunk c is stepped on the caller's stream into trace set c % 2 (the
+    // first receiver row doubles as the stepper's probe, whose trace goes to
+    // scratch), and its seismograms and statistics are taken on the side
+    // stream while the next chunk steps; a set is stepped into again only
+    // after the side stream has read it.
+    hipStream_t s2 = ctx->side[0];
+    rom::Rank2Args a;
+    a.b = ctx->b; a.c = C; a.mu = mu; a.V = V; a.S = S; a.J = nullptr;
+    a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M; a.dt = ctx->dt;
+    a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
+    const int64_t nchunk = (nsteps + L - 1) / L;
+    for (int64_t c = 0; c < nchunk; ++c) {
+        const int b = (int)(c & 1);
+        const int64_t len = std::min<int64_t>(L, nsteps - c * L);
+        if (c >= 2) {
+            e = hipStreamWaitEvent(st, ctx->rc_ev[2 + b], 0);
+            if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: event");
+        }
+        a.n0 = n0 + c * L; a.nsteps = len; a.vtr = vtr[b]; a.str = str[b]; a.y = ysc[b];
+        e = rom::launch_rank2_f32_mfma(a, 1, st);
+        if (e == hipSuccess) e = hipEventRecord(ctx->rc_ev[b], st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s2, ctx->rc_ev[b], 0);
+        if (e == hipSuccess)
+            e = rom::launch_receivers(vtr[b], kv, M, (int)len, static_cast<const float *>(C), R,
+                                      Y ? Y + (size_t)c * L * R * M : nullptr,
+                                      stats ? stats + (size_t)c * L * R * 5 : nullptr, s2);
+        if (e == hipSuccess) e = hipEventRecord(ctx->rc_ev[2 + b], s2);
+        if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: launch");
+    }
+    e = hipEventRecord(ctx->rc_ev[4], s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->rc_ev[4], 0);
+    if (e != hipSuccess) return hip_fail(e, "rom_run_receivers: event");
     return ROM_OK;
 }
 

@@ -72,6 +72,12 @@ struct rom_ctx {
     // current segment's reverse sweep, and their events (see rom_adjoint).
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t ev[13] = {};
+    // Receiver runs: two sets of chunk traces (states and probe scratch),
+    // and events [b] set b stepped, [2 + b] set b read, [4] side stream
+    // drained.
+    void *rc_ws = nullptr;
+    size_t rc_ws_bytes = 0;
+    hipEvent_t rc_ev[5] = {};
 };
 
 namespace rom {
@@ -129,6 +135,12 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
 size_t rank2_split_f32_lds_bytes();
 hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st);
 hipError_t rank2_split_configure();
+// Receivers: Y and ensemble statistics of L steps from a chunk's state
+// traces (see k_receivers.hip).
+size_t receivers_lds_bytes(int kv, int M, int R);
+hipError_t launch_receivers(const float *vtr, int kv, int M, int L, const float *C, int R, double *Y,
+                            double *stats, hipStream_t st);
+hipError_t receivers_configure();
 bool rank2_split_device_ok();
 hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int cols, int64_t R,
                                 double alpha, double *dA, double *part, hipStream_t st);

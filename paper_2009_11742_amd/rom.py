@@ -88,6 +88,28 @@ class Rom:
         check(_lib.load().rom_schedule_times(self._ctx, int(M), us))
         return {name: (us[i] if us[i] >= 0 else None) for i, name in enumerate(tuning.SCHEDULES)}
 
+    def run_receivers(self, mu, V, S, nsteps, C, n0=0, want_Y=True, want_stats=True, stream=None):
+        """Advance like run_rank2 and return the seismograms at the receiver
+        rows C ((R, Kv) tensor of the state dtype): {"Y": (nsteps, R, M)
+        float64 or None, "stats": (nsteps, R, 5) float64 or None} with
+        stats = mean, population variance, 5th / 50th / 95th percentile
+        (nearest rank) over the M samples."""
+        M = int(mu.numel())
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        if C.dim() != 2 or C.shape[1] != self.kv or C.dtype != self.torch_dtype or not C.is_cuda \
+                or not C.is_contiguous():
+            raise ValueError("C must be a contiguous (R, Kv) CUDA tensor of the state dtype")
+        R = int(C.shape[0])
+        dev = mu.device
+        Y = torch.empty((int(nsteps), R, M), dtype=torch.float64, device=dev) if want_Y else None
+        st = torch.empty((int(nsteps), R, 5), dtype=torch.float64, device=dev) if want_stats else None
+        check(_lib.load().rom_run_receivers(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S), R,
+                                            _ptr(C), _ptr(Y), _ptr(st), _stream_handle(stream)))
+        return {"Y": Y, "stats": st}
+
     def operators(self):
         """(Avs, Asv, scale) exactly as the products use them (float64 numpy)."""
         A = np.zeros((self.kv, self.ks), order="F")

@@ -186,3 +186,19 @@ def test_shipped_tune_table_is_well_formed():
         tuning.clear()
         for d in saved:
             tuning.put(d["kv_pad"], d["ks_pad"], d["m_pad"], d["op"], d["schedule"], d["us"])
+
+
+def test_receivers_rejects_bad_arguments():
+    lib = _lib.load()
+    d = C.c_void_p(0x1000)
+    fake = C.c_void_p(0x10)
+    E = _lib.ROM_E_ARG
+    assert lib.rom_run_receivers(None, 4, d, 0, 10, d, d, 2, d, d, d, None) == E
+    assert lib.rom_run_receivers(fake, 0, d, 0, 10, d, d, 2, d, d, d, None) == E          # M
+    assert lib.rom_run_receivers(fake, 1025, d, 0, 10, d, d, 2, d, d, d, None) == E       # M > 1024
+    assert lib.rom_run_receivers(fake, 4, d, 0, 10, d, d, 0, d, d, d, None) == E          # R
+    assert lib.rom_run_receivers(fake, 4, d, 0, 10, d, d, 65, d, d, d, None) == E         # R > 64
+    assert lib.rom_run_receivers(fake, 4, d, 0, 10, d, d, 2, None, d, d, None) == E       # C
+    assert lib.rom_run_receivers(fake, 4, None, 0, 10, d, d, 2, d, d, d, None) == E       # mu
+    assert lib.rom_run_receivers(fake, 4, d, -1, 10, d, d, 2, d, d, d, None) == E         # n0
+    assert "rom_run_receivers" in lib.rom_last_error().decode()
