@@ -174,8 +174,10 @@ rom_status rom_destroy(rom_ctx *ctx);
  * Without a ROM_SCHED_* flag the first run of each shape (Kv_pad, Ks_pad, M
  * rounded up to 64, operator type) times every schedule that applies for 32
  * steps on scratch states and keeps the fastest for the process (that run
- * synchronises the stream; a stream being captured is not tuned and uses
- * COLUMNS4), unless the process-wide tuning table already holds the shape.
+ * synchronises the stream), unless the process-wide tuning table already
+ * holds the shape.  A stream being captured into a graph is never tuned and
+ * never takes ROWSPLIT (whatever the flags or the table say): it runs the
+ * table's column-block choice, else COLUMNS4.
  *
  * The grouped launch (rom_run_grouped, rom_group_create) picks each
  * instance's column tile (4 or 8 samples) from the per-workgroup step times

@@ -287,8 +287,12 @@ int fastest(const float (&us)[ROM_NSCHEDULES]) {
 }
 
 // Schedule of an FP32-state rank-2 run (flags, table, or tuned now).
+// A stream being captured into a graph gets a column-block schedule: the
+// row-split path may allocate its workspace and synchronise, and its
+// cooperative launch is not used inside graphs.
 rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, int &sched, int &G) {
-    G = split_candidate(ctx, a.M);
+    const bool capturing = stream_capturing(st);
+    G = capturing ? 0 : split_candidate(ctx, a.M);
     unsigned cands = 1u << ROM_SCHEDULE_COLUMNS4;
     if (G > 0) cands |= 1u << ROM_SCHEDULE_ROWSPLIT;
     if (cols8_ok(ctx)) cands |= 1u << ROM_SCHEDULE_COLUMNS8;
@@ -305,7 +309,7 @@ rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, 
     const TuneKey key{ctx->kvp, ctx->ksp, rom::round_up(a.M, 64), (int)ctx->op_type};
     TuneEntry te;
     if (!tune_find(key, te)) {
-        if (stream_capturing(st)) return ROM_OK;
+        if (capturing) return ROM_OK;
         te.sched = ROM_SCHEDULE_COLUMNS4;
         for (float &u : te.us) u = -1.f;
         rom_status rs = time_schedules(ctx, a, cands, G, kTuneSteps, st, te.us);

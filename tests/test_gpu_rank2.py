@@ -233,3 +233,42 @@ def test_fp32_columns8_bitwise_equals_columns4(kv, ks, M, N):
     r = _ref(inst, N, cols=cols, probe=True)
     assert _relcol(b["V"][:, cols], r["V"]) <= TOL["f32"] and _relcol(b["S"][:, cols], r["S"]) <= TOL["f32"]
     assert np.max(np.abs(b["J"][cols] - r["J"]) / r["J"]) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("schedule", ["auto", "columns8", "rowsplit"])
+def test_rank2_run_captured_in_graph_replays(schedule):
+    """rom_run_rank2 captured into a HIP graph (column-block schedules under
+    capture) replays three times, each replay bitwise equal to an eager run
+    of the same schedule, with eager work and synchronisation in between."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(256, 256, 24, seed=13), "f32")
+    eager_sched = "columns" if schedule == "rowsplit" else schedule
+    rom_e = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=eager_sched)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=schedule)
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    N = 300
+    Ve, Se = rom_e.zeros(24)
+    Je = torch.zeros(24, dtype=torch.float64, device="cuda")
+    rom_e.run_rank2(mu, Ve, Se, N, c=c, J=Je)
+    torch.cuda.synchronize()
+    V, S = rom.zeros(24)
+    J = torch.zeros(24, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            rom.run_rank2(mu, V, S, N, c=c, J=J, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        V.zero_(); S.zero_(); J.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(V, Ve) and torch.equal(S, Se) and torch.equal(J, Je), (schedule, rep)
+        Ve2, Se2 = rom_e.zeros(24)
+        rom_e.run_rank2(mu, Ve2, Se2, 5)          # eager work between replays
+        torch.cuda.synchronize()
+    assert rom.last_schedule in ("columns", "columns8")
+    rom.close(); rom_e.close()
