@@ -42,8 +42,13 @@
  *    pointers are ordinary host memory.  The library never frees caller
  *    memory.  Device buffers of state type hold `double` for ROM_F64 and
  *    `float` for ROM_F32 states.
- *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only
- *    enqueue work on it; results are ready when the stream is synchronised.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work on it and results are ready when it is synchronised.  Some calls
+ *    also run work on internal streams of the context (default priority)
+ *    and join them back into `stream` before returning (rom_adjoint,
+ *    rom_run_receivers); a few synchronise `stream` (a rank-2 run that tunes
+ *    its schedule, rom_create, rom_check, rom_run_grouped), as their
+ *    comments say.
  *  - A context is not thread-safe; distinct contexts are independent.
  */
 #ifndef ROM_H
@@ -291,6 +296,12 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  *   dAsv          dev, Ks x Kv state type: dJ/dAsv with Avs fixed (set)
  *   dmu           dev, M FP64: dJ/dmu_m (set)
  * Any of dAvs, dAsv, dmu may be NULL.  dt is held fixed.
+ *
+ * FP32 states and operators.  The recompute of the next segment and the
+ * gradient products of the last run on two internal streams beside the
+ * reverse sweep on `stream`; the context keeps the workspace (checkpoints,
+ * three sets of state and probe traces, two of W/Q traces: about 0.45 GB at
+ * Kv = Ks = 512, M = 256, N = 5000) until rom_destroy.
  */
 rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps,
                        const void *c, const void *V0, const void *S0, double *J,
