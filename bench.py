@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -455,9 +455,47 @@ def workload_receivers(args, torch, dev):
             "plain_ms_per_run": t_pl * 1e3, "overhead": t_rc / t_pl - 1.0}
 
 
+def workload_rank3(args, torch, dev):
+    """Affine family: Q = 4 terms of Kv = Ks = 512, P = 64 parameter points
+    of M = 64 samples each, 2000 steps.  Each point's operators are assembled
+    and packed on the device from the resident terms (timed per instance);
+    the P instances then run in one grouped launch (timed per run)."""
+    import synth
+    from paper_2009_11742_amd import AffineFamily, GroupPlan
+    K, Q, P, M, N = 512, 4, 64, 64, 2000
+    fam_in = synth.make_affine_family(K, K, Q, P, M, seed=0)
+    b32 = fam_in["b"].astype(np.float32).astype(np.float64)
+    fam = AffineFamily(fam_in["Avs_terms"], fam_in["Asv_terms"], b32, 0.1, state="f32")
+    dts = [float(np.float32(0.5 / float(np.abs(th) @ fam_in["smax"]))) for th in fam_in["theta"]]
+    torch.cuda.synchronize()
+    roms = [fam.instance(fam_in["theta"][0], dt=dts[0])]   # first call: warm
+    roms[0].close()
+    t0 = time.perf_counter()
+    roms = [fam.instance(th, dt=d) for th, d in zip(fam_in["theta"], dts)]
+    torch.cuda.synchronize()
+    t_asm = (time.perf_counter() - t0) / P
+    mus = [torch.tensor(m, dtype=torch.float64, device=dev) for m in fam_in["mu"]]
+    Vs, Ss = [], []
+    for r in roms:
+        V, S = r.zeros(M, device=dev)
+        Vs.append(V); Ss.append(S)
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    _, ms = _events_time(torch, lambda: plan.run(N), 3, 1)
+    ksec = float(np.median(ms)) * 1e-3
+    plan.close()
+    for r in roms:
+        r.close()
+    fam.close()
+    flops = 4.0 * K * K * M * N * P
+    return {"workload": "rank3: affine family, Q=4 terms, Kv=Ks=512, P=64 points x M=64 samples, 2000 steps",
+            "value": P * M * N / ksec, "unit": "sample-steps/s", "ms_per_run": ksec * 1e3,
+            "tflops": flops / ksec / 1e12, "frac_fp32_mfma": flops / ksec / 1e12 / 157.3,
+            "assembly_ms_per_instance": t_asm * 1e3}
+
+
 OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
          "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain,
-         "receivers": workload_receivers}
+         "receivers": workload_receivers, "rank3": workload_rank3}
 
 
 if __name__ == "__main__":

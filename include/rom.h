@@ -373,6 +373,43 @@ rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M,
 rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream);
 rom_status rom_group_destroy(rom_group *g);
 
+/*
+ * Affine operator families (the rank-3 direction of Sec. 5: many operator
+ * parameters at once).  Operators that depend affinely on parameters,
+ *   Avs(theta) = sum_q theta_q Avs_q,   Asv(theta) = sum_q theta_q Asv_q,
+ * are kept as their Q terms on the device; each parameter point becomes an
+ * ordinary context whose operators are assembled on the device in FP64
+ * (terms added in order q = 0, 1, ..., each product and sum rounded once)
+ * and then rounded and packed exactly as rom_create does with host
+ * operators.  All instances of a family run together in one grouped launch
+ * (rom_run_grouped / rom_group_create) or alone.
+ *
+ * rom_affine_create:
+ *   cfg      as rom_create (its dt is the instances' default)
+ *   Q        terms, 1 .. 16
+ *   Avs_q    host, Q consecutive Kv x Ks column-major FP64 matrices
+ *   Asv_q    host, Q consecutive Ks x Kv column-major FP64 matrices
+ *   b        host, Kv FP64 (shared source)
+ *   stream   for the uploads (synchronised before return)
+ * rom_affine_instance:
+ *   theta    host, Q FP64 coefficients
+ *   dt       > 0, or 0 for the family's dt
+ *   out      the new context (destroy with rom_destroy); the call
+ *            synchronises `stream`.  With ROM_SKEW_CHECK and skew terms the
+ *            assembled Avs is checked as in rom_create (ROM_E_UNSTABLE).
+ * Instances own their operators: a family may be destroyed while its
+ * instances are still in use.  Host arrays may be freed on return.
+ * Errors: ROM_E_ARG (NULL pointer, Q outside 1..16, cfg rejected as by
+ * rom_create, dt negative or non-finite), ROM_E_NONFINITE (NaN/Inf in the
+ * terms, b or theta), ROM_E_UNSTABLE, ROM_E_NOMEM, ROM_E_DEVICE; *out is
+ * NULL on any error.  rom_affine_destroy(NULL) is a no-op.
+ */
+typedef struct rom_affine rom_affine;
+rom_status rom_affine_create(const rom_config *cfg, int32_t Q, const double *Avs_q, const double *Asv_q,
+                             const double *b, void *stream, rom_affine **out);
+rom_status rom_affine_instance(rom_affine *A, const double *theta, double dt, void *stream, rom_ctx **out);
+rom_status rom_affine_destroy(rom_affine *A);
+
 /* Thread-local text describing the last non-OK status of this thread. */
 const char *rom_last_error(void);
 

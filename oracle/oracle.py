@@ -169,6 +169,26 @@ def receivers(Avs, Asv, b, dt, mu, nsteps, C, V=None, S=None, n0=0):
     return {"Y": Y, "V": V, "S": S}
 
 
+def affine_operator(terms, theta):
+    """Operator of an affinely parametrised family at one parameter point:
+    sum_q theta_q T_q, the parametrisation under which the reduced operators
+    of many parameter points can be assembled from Q precomputed terms
+    (Sec. 2 allows an affine system matrix; Sec. 5 names fast assembly as the
+    condition for the rank-3 generalisation).
+
+    terms: (Q, R, C) array, theta: Q coefficients.  Summed in FP64 in the
+    order q = 0, 1, ..., Q-1, each product and sum rounded on its own.
+    """
+    T = np.asarray(terms, dtype=np.float64)
+    th = np.asarray(theta, dtype=np.float64).reshape(-1)
+    if T.ndim != 3 or T.shape[0] != th.size:
+        raise ValueError("terms must be (Q, R, C) with Q = len(theta)")
+    acc = th[0] * T[0]
+    for q in range(1, th.size):
+        acc = acc + th[q] * T[q]
+    return acc
+
+
 def percentile_index(p, M):
     """0-based index of the nearest-rank p-th percentile of M sorted values:
     the ceil(p M / 100)-th smallest, at least the smallest."""

@@ -5,12 +5,12 @@ The computation lives in the HIP library ``librom.so`` (C ABI declared in
 """
 from ._lib import RomError, load as load_library, LIB_PATH  # noqa: F401
 
-__all__ = ["RomError", "load_library", "LIB_PATH", "Rom", "RomQoI", "run_grouped", "GroupPlan"]
+__all__ = ["RomError", "load_library", "LIB_PATH", "Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily"]
 
 
 def __getattr__(name):
     # torch is imported lazily so the CPU-only ABI checks stay light
-    if name in ("Rom", "RomQoI", "run_grouped", "GroupPlan"):
+    if name in ("Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily"):
         from . import rom
         return getattr(rom, name)
     raise AttributeError(name)

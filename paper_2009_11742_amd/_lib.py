@@ -29,6 +29,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
+           "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
            "rom_last_error", "rom_version"]
 
 
@@ -102,6 +103,12 @@ def load():
         lib.rom_last_schedule.argtypes = [_vp]
         lib.rom_schedule_times.restype = C.c_int
         lib.rom_schedule_times.argtypes = [_vp, _i32, C.POINTER(_d)]
+        lib.rom_affine_create.restype = C.c_int
+        lib.rom_affine_create.argtypes = [C.POINTER(RomConfig), _i32, _pd, _pd, _pd, _vp, C.POINTER(_vp)]
+        lib.rom_affine_instance.restype = C.c_int
+        lib.rom_affine_instance.argtypes = [_vp, _pd, _d, _vp, C.POINTER(_vp)]
+        lib.rom_affine_destroy.restype = C.c_int
+        lib.rom_affine_destroy.argtypes = [_vp]
         lib.rom_run_receivers.restype = C.c_int
         lib.rom_run_receivers.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp]
         lib.rom_tune_count.restype = C.c_int32

@@ -2,6 +2,8 @@
 // and source are converted to the state type and packed into the panels the
 // rank-2 MFMA kernel streams (the time-independent terms are prepared once,
 // as the paper does for its precomputed reduced operators, Sec. 2.2).
+#include <algorithm>
+
 #include "k_common.h"
 #include "rom_internal.h"
 
@@ -65,6 +67,32 @@ hipError_t launch_pack_f32(const double *A, int rows, int cols, int rowsp, int c
     int blocks = (int)((total + 255) / 256);
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(pack_f32_kernel, dim3(blocks), dim3(256), 0, st, A, rows, cols, rowsp, colsp, pk);
+    return hipGetLastError();
+}
+
+}  // namespace rom
+
+namespace rom {
+namespace {
+
+// out[i] = sum_q theta[q] terms[q n + i], terms added in turn (q = 0, 1, ...;
+// product then sum, each rounded: the build does not contract).
+__global__ void affine_combine_kernel(const double *__restrict__ terms, int Q, int64_t n, AffineCoeffs th,
+                                      double *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = th.c[0] * terms[i];
+        for (int q = 1; q < Q; ++q) acc = acc + th.c[q] * terms[(size_t)q * n + i];
+        out[i] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_affine_combine(const double *terms, int Q, int64_t n, const AffineCoeffs &th, double *out,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(affine_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, terms, Q, n, th, out);
     return hipGetLastError();
 }
 

@@ -356,56 +356,61 @@ const char *rom_last_error(void) { return g_err.c_str(); }
 
 const char *rom_version(void) { return "rank2rom-mi355x 0.1 (gfx950)"; }
 
-rom_status rom_create(const rom_config *cfg, const double *Avs, const double *Asv,
-                      const double *b, void *stream, rom_ctx **out) {
-    if (out) *out = nullptr;
-    if (!cfg || !Avs || !Asv || !b || !out) return fail(ROM_E_ARG, "rom_create: NULL argument");
+}  // extern "C"
+
+namespace {
+
+// Checks of a configuration shared by rom_create and affine instances.
+rom_status check_config(const rom_config *cfg, const char *who) {
     const int kv = cfg->kv, ks = cfg->ks;
-    if (kv < 1 || ks < 1) return fail(ROM_E_ARG, "rom_create: kv and ks must be >= 1");
-    if (kv > 65536 || ks > 65536) return fail(ROM_E_UNSUPPORTED, "rom_create: kv/ks above 65536");
-    if (!(cfg->dt > 0.0) || !isfinite(cfg->dt)) return fail(ROM_E_ARG, "rom_create: dt must be finite and > 0");
+    std::string w(who);
+    if (kv < 1 || ks < 1) return fail(ROM_E_ARG, w + ": kv and ks must be >= 1");
+    if (kv > 65536 || ks > 65536) return fail(ROM_E_UNSUPPORTED, w + ": kv/ks above 65536");
+    if (!(cfg->dt > 0.0) || !isfinite(cfg->dt)) return fail(ROM_E_ARG, w + ": dt must be finite and > 0");
     if (cfg->state_type != ROM_F64 && cfg->state_type != ROM_F32)
-        return fail(ROM_E_ARG, "rom_create: state_type must be ROM_F64 or ROM_F32");
+        return fail(ROM_E_ARG, w + ": state_type must be ROM_F64 or ROM_F32");
     if (cfg->op_type != ROM_F64 && cfg->op_type != ROM_F32 && cfg->op_type != ROM_BF16 &&
         cfg->op_type != ROM_F8E4M3)
-        return fail(ROM_E_ARG, "rom_create: unknown op_type");
+        return fail(ROM_E_ARG, w + ": unknown op_type");
     const bool lowp = cfg->op_type == ROM_BF16 || cfg->op_type == ROM_F8E4M3;
     if (!lowp && cfg->op_type != cfg->state_type)
-        return fail(ROM_E_UNSUPPORTED, "rom_create: supported (op, state) pairs are (F64, F64), "
-                                       "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
+        return fail(ROM_E_UNSUPPORTED, w + ": supported (op, state) pairs are (F64, F64), "
+                                          "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
     if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8))
-        return fail(ROM_E_ARG, "rom_create: unknown flag bits");
-    {
-        const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
-        if (sf & (sf - 1)) return fail(ROM_E_ARG, "rom_create: at most one ROM_SCHED_* flag");
-    }
-    const size_t nA = (size_t)kv * ks;
-    if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
-        return fail(ROM_E_NONFINITE, "rom_create: non-finite value in Avs, Asv or b");
+        return fail(ROM_E_ARG, w + ": unknown flag bits");
+    const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
+    if (sf & (sf - 1)) return fail(ROM_E_ARG, w + ": at most one ROM_SCHED_* flag");
+    return ROM_OK;
+}
 
-    bool skew = true;
-    for (int i = 0; i < ks && skew; ++i)
+// Whether Asv == -Avs^T exactly (host arrays).
+bool is_skew(const double *Avs, const double *Asv, int kv, int ks) {
+    for (int i = 0; i < ks; ++i)
         for (int j = 0; j < kv; ++j)
-            if (Asv[i + (size_t)j * ks] != -Avs[j + (size_t)i * kv]) { skew = false; break; }
-    if ((cfg->flags & ROM_SKEW_CHECK) && skew) {
-        double smax = sigma_max(Avs, kv, ks);
-        if (cfg->dt * smax * (1.0 + 1e-9) >= 2.0)
-            return fail(ROM_E_UNSTABLE, "rom_create: dt * sigma_max(Avs) >= 2 for a skew pair "
-                                        "(leapfrog energy not positive)");
-    }
+            if (Asv[i + (size_t)j * ks] != -Avs[j + (size_t)i * kv]) return false;
+    return true;
+}
 
-    hipStream_t st = static_cast<hipStream_t>(stream);
+// Build a context from FP64 operators already in device memory: sA (Kv x
+// Ks) and sB (Ks x Kv) column-major, sb the source padded to Kv_pad
+// entries.  The device arrays stay the caller's; the call synchronises st.
+rom_status build_ctx(const rom_config *cfg, bool skew, const double *sA, const double *sB, const double *sb,
+                     hipStream_t st, const char *who, rom_ctx **out) {
+    const int kv = cfg->kv, ks = cfg->ks;
+    const size_t nA = (size_t)kv * ks;
+    const bool lowp = cfg->op_type == ROM_BF16 || cfg->op_type == ROM_F8E4M3;
+    std::string w(who);
     rom_ctx *c = new (std::nothrow) rom_ctx();
-    if (!c) return fail(ROM_E_NOMEM, "rom_create: host allocation failed");
+    if (!c) return fail(ROM_E_NOMEM, w + ": host allocation failed");
     hipError_t e = hipGetDevice(&c->device);
-    if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: hipGetDevice"); }
+    if (e != hipSuccess) { free_ctx(c); return hip_fail(e, (w + ": hipGetDevice").c_str()); }
     if (!g_configured) {
         e = rom::rank2_f32_mfma_configure();
         if (e == hipSuccess) e = rom::rank2_valu_configure();
         if (e == hipSuccess) e = rom::rank2_lowp_configure();
         if (e == hipSuccess) e = rom::rank2_split_configure();
         if (e == hipSuccess) e = rom::receivers_configure();
-        if (e != hipSuccess) { free_ctx(c); return hip_fail(e, "rom_create: kernel attributes"); }
+        if (e != hipSuccess) { free_ctx(c); return hip_fail(e, (w + ": kernel attributes").c_str()); }
         g_configured = true;
     }
     c->kv = kv; c->ks = ks;
@@ -413,75 +418,102 @@ rom_status rom_create(const rom_config *cfg, const double *Avs, const double *As
     c->dt = cfg->dt; c->op_type = cfg->op_type; c->state_type = cfg->state_type;
     c->flags = cfg->flags; c->skew = skew;
     const size_t ts = tsize(c->state_type);
-
-    double *stage = nullptr;
-    const size_t stage_n = 2 * nA + (size_t)c->kvp;
-    e = hipMalloc(&stage, stage_n * sizeof(double));
-    if (e != hipSuccess) { free_ctx(c); return fail(ROM_E_NOMEM, "rom_create: device allocation failed"); }
-    double *sA = stage, *sB = stage + nA, *sb = stage + 2 * nA;
-    std::vector<double> bpad(c->kvp, 0.0);
-    memcpy(bpad.data(), b, sizeof(double) * kv);
 #define CHK(call, what)                                                           \
     do {                                                                          \
         e = (call);                                                               \
-        if (e != hipSuccess) { hfree(stage); free_ctx(c);                      \
-            return e == hipErrorOutOfMemory ? fail(ROM_E_NOMEM, what) : hip_fail(e, what); } \
+        if (e != hipSuccess) { free_ctx(c);                                       \
+            return e == hipErrorOutOfMemory ? fail(ROM_E_NOMEM, w + what) : hip_fail(e, (w + what).c_str()); } \
     } while (0)
-    CHK(hipMemcpyAsync(sA, Avs, nA * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
-    CHK(hipMemcpyAsync(sB, Asv, nA * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
-    CHK(hipMemcpyAsync(sb, bpad.data(), c->kvp * sizeof(double), hipMemcpyHostToDevice, st), "rom_create: upload");
-    CHK(hipMalloc(&c->avs_cm, nA * ts), "rom_create: device allocation");
-    CHK(hipMalloc(&c->asv_cm, nA * ts), "rom_create: device allocation");
-    CHK(hipMalloc(&c->b, (size_t)c->kvp * ts), "rom_create: device allocation");
-    CHK(hipMalloc(&c->status, sizeof(int) * 4), "rom_create: device allocation");
-    CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
+    CHK(hipMalloc(&c->avs_cm, nA * ts), ": device allocation");
+    CHK(hipMalloc(&c->asv_cm, nA * ts), ": device allocation");
+    CHK(hipMalloc(&c->b, (size_t)c->kvp * ts), ": device allocation");
+    CHK(hipMalloc(&c->status, sizeof(int) * 4), ": device allocation");
+    CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), ": memset");
     if (!(lowp && c->state_type == ROM_F64)) {
-        CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), "rom_create: convert");
-        CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), "rom_create: convert");
+        CHK(rom::launch_convert(sA, c->avs_cm, nA, c->state_type, st), ": convert");
+        CHK(rom::launch_convert(sB, c->asv_cm, nA, c->state_type, st), ": convert");
     }
-    CHK(rom::launch_convert(sb, c->b, c->kvp, c->state_type, st), "rom_create: convert");
+    CHK(rom::launch_convert(sb, c->b, c->kvp, c->state_type, st), ": convert");
     if (lowp) {
         // BF16: round each operator (via FP32) to BF16; FP8: one scale
         // amax(|fp32(Avs)|, |fp32(Asv)|) / 448 for both operators, so a skew
         // pair stays exactly skew after quantisation.
         const size_t eb = c->op_type == ROM_BF16 ? 2 : 1;
         unsigned *amax = reinterpret_cast<unsigned *>(c->status);
-        CHK(hipMalloc(&c->avs_lp, eb * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
-        CHK(hipMalloc(&c->asv_lp, eb * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
+        CHK(hipMalloc(&c->avs_lp, eb * (size_t)c->kvp * c->ksp), ": device allocation");
+        CHK(hipMalloc(&c->asv_lp, eb * (size_t)c->kvp * c->ksp), ": device allocation");
         if (c->op_type == ROM_F8E4M3) {
-            CHK(rom::launch_amax(sA, (int64_t)nA, amax, st), "rom_create: amax");
-            CHK(rom::launch_amax(sB, (int64_t)nA, amax, st), "rom_create: amax");
+            CHK(rom::launch_amax(sA, (int64_t)nA, amax, st), ": amax");
+            CHK(rom::launch_amax(sB, (int64_t)nA, amax, st), ": amax");
         }
-        CHK(rom::launch_pack_lowp(sA, kv, ks, c->kvp, c->ksp, c->op_type, amax, c->avs_lp, st), "rom_create: pack");
-        CHK(rom::launch_pack_lowp(sB, ks, kv, c->ksp, c->kvp, c->op_type, amax, c->asv_lp, st), "rom_create: pack");
+        CHK(rom::launch_pack_lowp(sA, kv, ks, c->kvp, c->ksp, c->op_type, amax, c->avs_lp, st), ": pack");
+        CHK(rom::launch_pack_lowp(sB, ks, kv, c->ksp, c->kvp, c->op_type, amax, c->asv_lp, st), ": pack");
         if (c->op_type == ROM_F8E4M3) {
             unsigned bits = 0;
-            CHK(hipMemcpyAsync(&bits, amax, sizeof(bits), hipMemcpyDeviceToHost, st), "rom_create: readback");
-            CHK(hipStreamSynchronize(st), "rom_create: synchronize");
+            CHK(hipMemcpyAsync(&bits, amax, sizeof(bits), hipMemcpyDeviceToHost, st), ": readback");
+            CHK(hipStreamSynchronize(st), ": synchronize");
             float am;
             memcpy(&am, &bits, sizeof(am));
             c->op_scale = am > 0.f ? am / 448.0f : 1.0f;
-            CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), "rom_create: memset");
+            CHK(hipMemsetAsync(c->status, 0, sizeof(int) * 4, st), ": memset");
         }
         if (c->state_type == ROM_F64) {
             // FP64 states with rounded operators (the long-horizon reference of
             // the rounded model): the FP64 path runs on the dequantised values
             CHK(rom::launch_unpack_lowp(c->avs_lp, kv, ks, c->kvp, c->ksp, c->op_type, (double)c->op_scale,
-                                        static_cast<double *>(c->avs_cm), st), "rom_create: unpack");
+                                        static_cast<double *>(c->avs_cm), st), ": unpack");
             CHK(rom::launch_unpack_lowp(c->asv_lp, ks, kv, c->ksp, c->kvp, c->op_type, (double)c->op_scale,
-                                        static_cast<double *>(c->asv_cm), st), "rom_create: unpack");
+                                        static_cast<double *>(c->asv_cm), st), ": unpack");
         }
     } else if (c->state_type == ROM_F32) {
-        CHK(hipMalloc(&c->avs_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
-        CHK(hipMalloc(&c->asv_pk, sizeof(float) * (size_t)c->kvp * c->ksp), "rom_create: device allocation");
-        CHK(rom::launch_pack_f32(sA, kv, ks, c->kvp, c->ksp, c->avs_pk, st), "rom_create: pack");
-        CHK(rom::launch_pack_f32(sB, ks, kv, c->ksp, c->kvp, c->asv_pk, st), "rom_create: pack");
+        CHK(hipMalloc(&c->avs_pk, sizeof(float) * (size_t)c->kvp * c->ksp), ": device allocation");
+        CHK(hipMalloc(&c->asv_pk, sizeof(float) * (size_t)c->kvp * c->ksp), ": device allocation");
+        CHK(rom::launch_pack_f32(sA, kv, ks, c->kvp, c->ksp, c->avs_pk, st), ": pack");
+        CHK(rom::launch_pack_f32(sB, ks, kv, c->ksp, c->kvp, c->asv_pk, st), ": pack");
     }
-    CHK(hipStreamSynchronize(st), "rom_create: synchronize");
+    CHK(hipStreamSynchronize(st), ": synchronize");
 #undef CHK
-    hfree(stage);
     *out = c;
     return ROM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rom_status rom_create(const rom_config *cfg, const double *Avs, const double *Asv,
+                      const double *b, void *stream, rom_ctx **out) {
+    if (out) *out = nullptr;
+    if (!cfg || !Avs || !Asv || !b || !out) return fail(ROM_E_ARG, "rom_create: NULL argument");
+    rom_status rs = check_config(cfg, "rom_create");
+    if (rs != ROM_OK) return rs;
+    const int kv = cfg->kv, ks = cfg->ks;
+    const size_t nA = (size_t)kv * ks;
+    if (!all_finite(Avs, nA) || !all_finite(Asv, nA) || !all_finite(b, kv))
+        return fail(ROM_E_NONFINITE, "rom_create: non-finite value in Avs, Asv or b");
+    const bool skew = is_skew(Avs, Asv, kv, ks);
+    if ((cfg->flags & ROM_SKEW_CHECK) && skew) {
+        double smax = sigma_max(Avs, kv, ks);
+        if (cfg->dt * smax * (1.0 + 1e-9) >= 2.0)
+            return fail(ROM_E_UNSTABLE, "rom_create: dt * sigma_max(Avs) >= 2 for a skew pair "
+                                        "(leapfrog energy not positive)");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t kvp = (size_t)rom::round_up(kv, 64);
+    double *stage = nullptr;
+    hipError_t e = hipMalloc(&stage, (2 * nA + kvp) * sizeof(double));
+    if (e != hipSuccess) return fail(ROM_E_NOMEM, "rom_create: device allocation failed");
+    double *sA = stage, *sB = stage + nA, *sb = stage + 2 * nA;
+    std::vector<double> bpad(kvp, 0.0);
+    memcpy(bpad.data(), b, sizeof(double) * kv);
+    e = hipMemcpyAsync(sA, Avs, nA * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sB, Asv, nA * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sb, bpad.data(), kvp * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { hfree(stage); return hip_fail(e, "rom_create: upload"); }
+    rs = build_ctx(cfg, skew, sA, sB, sb, st, "rom_create", out);
+    (void)hipStreamSynchronize(st);   // the staging buffer is read until here
+    hfree(stage);
+    return rs;
 }
 
 rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *scale) {
@@ -533,6 +565,92 @@ rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, dou
     }
     e = rom::launch_energy(ctx->avs_e64, ctx->kv, ctx->ks, ctx->dt, ctx->state_type, V, S, M, E, st);
     if (e != hipSuccess) return hip_fail(e, "rom_energy: launch");
+    return ROM_OK;
+}
+
+rom_status rom_affine_create(const rom_config *cfg, int32_t Q, const double *Avs_q, const double *Asv_q,
+                             const double *b, void *stream, rom_affine **out) {
+    if (out) *out = nullptr;
+    if (!cfg || !Avs_q || !Asv_q || !b || !out) return fail(ROM_E_ARG, "rom_affine_create: NULL argument");
+    if (Q < 1 || Q > rom::kMaxAffine) return fail(ROM_E_ARG, "rom_affine_create: Q must be in [1, 16]");
+    rom_status rs = check_config(cfg, "rom_affine_create");
+    if (rs != ROM_OK) return rs;
+    const int kv = cfg->kv, ks = cfg->ks;
+    const size_t nA = (size_t)kv * ks;
+    if (!all_finite(Avs_q, nA * Q) || !all_finite(Asv_q, nA * Q) || !all_finite(b, kv))
+        return fail(ROM_E_NONFINITE, "rom_affine_create: non-finite value in the terms or b");
+    bool skew = true;
+    for (int q = 0; q < Q && skew; ++q) skew = is_skew(Avs_q + q * nA, Asv_q + q * nA, kv, ks);
+    rom_affine *A = new (std::nothrow) rom_affine();
+    if (!A) return fail(ROM_E_NOMEM, "rom_affine_create: host allocation failed");
+    A->cfg = *cfg;
+    A->Q = Q;
+    A->skew = skew;
+    if ((cfg->flags & ROM_SKEW_CHECK) && skew) A->host_avs.assign(Avs_q, Avs_q + nA * Q);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t kvp = (size_t)rom::round_up(kv, 64);
+    std::vector<double> bp(kvp, 0.0);
+    memcpy(bp.data(), b, sizeof(double) * kv);
+    hipError_t e = hipMalloc(&A->terms, 2 * nA * Q * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&A->bpad, kvp * sizeof(double));
+    if (e != hipSuccess) {
+        hfree(A->terms); hfree(A->bpad); delete A;
+        return fail(ROM_E_NOMEM, "rom_affine_create: device allocation failed");
+    }
+    e = hipMemcpyAsync(A->terms, Avs_q, nA * Q * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(A->terms + nA * Q, Asv_q, nA * Q * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(A->bpad, bp.data(), kvp * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        hfree(A->terms); hfree(A->bpad); delete A;
+        return hip_fail(e, "rom_affine_create: upload");
+    }
+    *out = A;
+    return ROM_OK;
+}
+
+rom_status rom_affine_instance(rom_affine *A, const double *theta, double dt, void *stream, rom_ctx **out) {
+    if (out) *out = nullptr;
+    if (!A || !theta || !out) return fail(ROM_E_ARG, "rom_affine_instance: NULL argument");
+    if (!all_finite(theta, A->Q)) return fail(ROM_E_NONFINITE, "rom_affine_instance: non-finite coefficient");
+    if (dt < 0.0 || !isfinite(dt)) return fail(ROM_E_ARG, "rom_affine_instance: dt must be finite and >= 0");
+    rom_config cfg = A->cfg;
+    if (dt > 0.0) cfg.dt = dt;
+    const int kv = cfg.kv, ks = cfg.ks;
+    const size_t nA = (size_t)kv * ks;
+    if ((cfg.flags & ROM_SKEW_CHECK) && A->skew) {
+        // the same sum, in the same order, on the host
+        std::vector<double> Avs(nA);
+        for (size_t i = 0; i < nA; ++i) {
+            double acc = theta[0] * A->host_avs[i];
+            for (int q = 1; q < A->Q; ++q) acc = acc + theta[q] * A->host_avs[(size_t)q * nA + i];
+            Avs[i] = acc;
+        }
+        if (cfg.dt * sigma_max(Avs.data(), kv, ks) * (1.0 + 1e-9) >= 2.0)
+            return fail(ROM_E_UNSTABLE, "rom_affine_instance: dt * sigma_max(Avs) >= 2 for a skew pair "
+                                        "(leapfrog energy not positive)");
+    }
+    rom::AffineCoeffs th{};
+    for (int q = 0; q < A->Q; ++q) th.c[q] = theta[q];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *stage = nullptr;
+    hipError_t e = hipMalloc(&stage, 2 * nA * sizeof(double));
+    if (e != hipSuccess) return fail(ROM_E_NOMEM, "rom_affine_instance: device allocation failed");
+    e = rom::launch_affine_combine(A->terms, A->Q, (int64_t)nA, th, stage, st);
+    if (e == hipSuccess) e = rom::launch_affine_combine(A->terms + nA * A->Q, A->Q, (int64_t)nA, th, stage + nA, st);
+    if (e != hipSuccess) { hfree(stage); return hip_fail(e, "rom_affine_instance: assemble"); }
+    rom_status rs = build_ctx(&cfg, A->skew, stage, stage + nA, A->bpad, st, "rom_affine_instance", out);
+    (void)hipStreamSynchronize(st);
+    hfree(stage);
+    return rs;
+}
+
+rom_status rom_affine_destroy(rom_affine *A) {
+    if (!A) return ROM_OK;
+    hfree(A->terms);
+    hfree(A->bpad);
+    delete A;
     return ROM_OK;
 }
 

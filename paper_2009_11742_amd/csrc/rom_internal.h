@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "rom.h"
 
 namespace rom {
@@ -159,6 +161,15 @@ hipError_t launch_rank1_step(const void *avs_cm, const void *asv_cm, const void 
                              int ks, double dt, int64_t n, double mu, void *v, void *s,
                              hipStream_t st);
 
+// Affine operators: coefficients of up to kMaxAffine terms, by value.
+constexpr int kMaxAffine = 16;
+struct AffineCoeffs {
+    double c[kMaxAffine];
+};
+// out (n) = sum_q th.c[q] terms[q n ..], q = 0 .. Q-1 in order (FP64).
+hipError_t launch_affine_combine(const double *terms, int Q, int64_t n, const AffineCoeffs &th, double *out,
+                                 hipStream_t st);
+
 // Setup kernels: FP64 staging -> state-type column-major copies and packed
 // MFMA panels.
 hipError_t launch_convert(const double *src, void *dst, int64_t n, rom_dtype to, hipStream_t st);
@@ -175,4 +186,15 @@ struct rom_group {
     void *dev = nullptr;          // [G] Rank2Args then [nitems] int2 items
     const rom::Rank2Args *inst = nullptr;
     const int2 *items = nullptr;
+};
+
+// Affine family of operator pairs (rank-3 direction): the Q terms of both
+// operators and the padded source on the device, for assembling instances.
+struct rom_affine {
+    rom_config cfg{};
+    int Q = 0;
+    bool skew = false;               // every term pair is skew
+    double *terms = nullptr;         // device: Q x (Kv x Ks) Avs terms, then Q x (Ks x Kv) Asv terms
+    double *bpad = nullptr;          // device: Kv_pad
+    std::vector<double> host_avs;    // Avs terms on the host (skew check), if requested
 };

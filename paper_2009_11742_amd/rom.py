@@ -69,6 +69,16 @@ class Rom:
                              bb.ctypes.data_as(pd), _stream_handle(stream), C.byref(ctx)))
         self._ctx = ctx
 
+    @classmethod
+    def _adopt(cls, ctx, kv, ks, dt, state, ops):
+        """Wrap a context the library created (it is destroyed with this object)."""
+        self = cls.__new__(cls)
+        self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
+        _, self.torch_dtype = _DT[state]
+        self.ops = ops
+        self._ctx = ctx
+        return self
+
     def check(self, stream=None):
         """Synchronise `stream` and raise if an in-kernel wait of the work
         enqueued so far timed out (ROM_E_TIMEOUT; results invalid)."""
@@ -306,6 +316,54 @@ class GroupPlan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().rom_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AffineFamily:
+    """Operators that depend affinely on parameters, Avs(theta) = sum_q
+    theta_q Avs_q and Asv(theta) likewise, kept as their Q terms on the
+    device.  ``instance(theta)`` returns a Rom whose operators are assembled
+    on the device (the rank-3 direction: run many instances together with
+    run_grouped)."""
+
+    def __init__(self, Avs_terms, Asv_terms, b, dt, state="f32", ops=None, skew_check=False, schedule="auto",
+                 stream=None):
+        At = np.asarray(Avs_terms, dtype=np.float64)
+        Bt = np.asarray(Asv_terms, dtype=np.float64)
+        Q, kv, ks = At.shape
+        if Bt.shape != (Q, ks, kv):
+            raise ValueError("Asv_terms must have shape (Q, Ks, Kv)")
+        # Q consecutive column-major matrices
+        Ac = np.ascontiguousarray(np.transpose(At, (0, 2, 1)))
+        Bc = np.ascontiguousarray(np.transpose(Bt, (0, 2, 1)))
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
+        self.Q, self.kv, self.ks, self.dt, self.state = int(Q), int(kv), int(ks), float(dt), state
+        code, _ = _DT[state]
+        self.ops = state if ops is None else ops
+        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule]
+        cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
+        h = C.c_void_p()
+        pd = C.POINTER(C.c_double)
+        check(_lib.load().rom_affine_create(C.byref(cfg), int(Q), Ac.ctypes.data_as(pd), Bc.ctypes.data_as(pd),
+                                            bb.ctypes.data_as(pd), _stream_handle(stream), C.byref(h)))
+        self._h = h
+
+    def instance(self, theta, dt=0.0, stream=None):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(self.Q))
+        ctx = C.c_void_p()
+        check(_lib.load().rom_affine_instance(self._h, th.ctypes.data_as(C.POINTER(C.c_double)), float(dt),
+                                              _stream_handle(stream), C.byref(ctx)))
+        return Rom._adopt(ctx, self.kv, self.ks, dt if dt > 0 else self.dt, self.state, self.ops)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().rom_affine_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-__all__ = ["make_instance", "round_to", "grouped_draws", "CONFIGS"]
+__all__ = ["make_instance", "round_to", "grouped_draws", "make_affine_family", "CONFIGS"]
 
 # The five workloads (sizes and step counts) this build measures or checks.
 CONFIGS = {
@@ -106,3 +106,28 @@ def grouped_draws(G: int = 64, base_seed: int = 0):
         M = int(min(512, max(16, round(math.exp(rng.uniform(math.log(16), math.log(512)))))))
         out.append((K, M, base_seed + i))
     return out
+
+
+def make_affine_family(kv: int, ks: int, Q: int, P: int, M: int, seed: int = 0, skew: bool = True):
+    """Q affine terms of each operator and P parameter points, in FP64.
+
+    Avs_q ~ N(0, 1/Ks) entrywise, Asv_q = -Avs_q^T (skew) or
+    -diag(w) Avs_q^T with one w ~ U[0.5, 1.5] shared by all terms; b as in
+    ``make_instance``; theta[p] ~ U[0.2, 0.8]^Q; mu[p] ~ U[0.5, 1.0]^M.
+    ``smax`` holds sigma_max of each Avs term (FP64 SVD), so a caller can
+    bound sigma_max of any combination by sum_q |theta_q| smax_q.  Terms are
+    returned as (Q, Kv, Ks) and (Q, Ks, Kv) arrays (row index second).
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((Q, kv, ks)) / math.sqrt(ks)
+    b = rng.standard_normal(kv)
+    if skew:
+        B = -np.transpose(A, (0, 2, 1)).copy()
+    else:
+        w = rng.uniform(0.5, 1.5, ks)
+        B = -(w[None, :, None] * np.transpose(A, (0, 2, 1)))
+    theta = rng.uniform(0.2, 0.8, (P, Q))
+    mu = rng.uniform(0.5, 1.0, (P, M))
+    smax = np.array([float(np.linalg.svd(A[q], compute_uv=False)[0]) for q in range(Q)])
+    return {"Avs_terms": A, "Asv_terms": B, "b": b, "theta": theta, "mu": mu, "smax": smax,
+            "kv": kv, "ks": ks, "Q": Q, "P": P, "M": M, "seed": seed}

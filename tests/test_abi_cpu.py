@@ -202,3 +202,25 @@ def test_receivers_rejects_bad_arguments():
     assert lib.rom_run_receivers(fake, 4, None, 0, 10, d, d, 2, d, d, d, None) == E       # mu
     assert lib.rom_run_receivers(fake, 4, d, -1, 10, d, d, 2, d, d, d, None) == E         # n0
     assert "rom_run_receivers" in lib.rom_last_error().decode()
+
+
+def test_affine_rejects_bad_arguments():
+    lib = _lib.load()
+    A, B, b, dt = _inst()
+    pd = C.POINTER(C.c_double)
+    AA = np.concatenate([A.ravel(order="F")] * 2)
+    BB = np.concatenate([B.ravel(order="F")] * 2)
+    out = C.c_void_p(123)
+    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_F32, 0)
+    E = _lib.ROM_E_ARG
+    assert lib.rom_affine_create(None, 2, AA.ctypes.data_as(pd), BB.ctypes.data_as(pd), b.ctypes.data_as(pd), None, C.byref(out)) == E
+    assert not out.value
+    for Q in (0, 17):
+        assert lib.rom_affine_create(C.byref(cfg), Q, AA.ctypes.data_as(pd), BB.ctypes.data_as(pd), b.ctypes.data_as(pd), None, C.byref(out)) == E
+    bad = _lib.RomConfig(8, 8, -1.0, _lib.ROM_F32, _lib.ROM_F32, 0)
+    assert lib.rom_affine_create(C.byref(bad), 2, AA.ctypes.data_as(pd), BB.ctypes.data_as(pd), b.ctypes.data_as(pd), None, C.byref(out)) == E
+    AA2 = AA.copy(); AA2[5] = np.nan
+    assert lib.rom_affine_create(C.byref(cfg), 2, AA2.ctypes.data_as(pd), BB.ctypes.data_as(pd), b.ctypes.data_as(pd), None, C.byref(out)) == _lib.ROM_E_NONFINITE
+    th = np.ones(2)
+    assert lib.rom_affine_instance(None, th.ctypes.data_as(pd), 0.0, None, C.byref(out)) == E
+    assert lib.rom_affine_destroy(None) == _lib.ROM_OK

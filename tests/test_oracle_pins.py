@@ -462,3 +462,53 @@ def test_ensemble_stats_closed_forms():
             assert st[i, r, 2] <= st[i, r, 3] <= st[i, r, 4]
     assert oracle.percentile_index(5, 20) == 0 and oracle.percentile_index(50, 20) == 9
     assert oracle.percentile_index(95, 20) == 18 and oracle.percentile_index(95, 1) == 0
+
+
+# ---- affine operator families (rank-3 direction)
+
+def test_affine_operator_hand_example():
+    """Two non-symmetric 2 x 3 terms with integer entries and dyadic
+    coefficients: the sum is exact and written out by hand."""
+    T = np.array([[[1., 2., 3.], [4., 5., 6.]],
+                  [[0., -1., 0.], [2., 0., -8.]]])
+    got = oracle.affine_operator(T, [0.5, 0.25])
+    want = np.array([[0.5, 0.75, 1.5], [2.5, 2.5, 1.0]])
+    assert np.array_equal(got, want)
+
+
+def test_affine_operator_unit_coefficients_pick_terms():
+    syn = synth.make_affine_family(7, 5, 4, 1, 1, seed=2)
+    for q in range(4):
+        e = np.zeros(4); e[q] = 1.0
+        assert np.array_equal(oracle.affine_operator(syn["Avs_terms"], e), syn["Avs_terms"][q])
+
+
+def test_affine_family_of_multiples_runs_as_scaled_operator():
+    """Terms c_q A (scalars c_q): the instance is (sum theta_q c_q) A, so its
+    run equals the run of that scaled operator, and sigma_max scales by the
+    same factor."""
+    inst = synth.make_instance(24, 24, 3, seed=4)
+    A, B = inst["Avs"], inst["Asv"]
+    cs = np.array([0.5, -0.25, 2.0])
+    th = np.array([0.75, 0.5, 0.125])
+    f = float(th @ cs)                       # 0.5
+    Ai = oracle.affine_operator(np.stack([c * A for c in cs]), th)
+    Bi = oracle.affine_operator(np.stack([c * B for c in cs]), th)
+    bound = 8 * np.finfo(float).eps * float(np.abs(th) @ np.abs(cs))
+    assert np.max(np.abs(Ai - f * A)) <= bound * np.max(np.abs(A))
+    assert np.max(np.abs(Bi - f * B)) <= bound * np.max(np.abs(B))
+    s = np.linalg.svd(Ai, compute_uv=False)[0] / np.linalg.svd(A, compute_uv=False)[0]
+    assert abs(s - f) < 1e-13
+    r1 = oracle.run_rank2(Ai, Bi, inst["b"], inst["dt"], inst["mu"], 300)
+    r2 = oracle.run_rank2(f * A, f * B, inst["b"], inst["dt"], inst["mu"], 300)
+    e = np.max(np.linalg.norm(r1["V"] - r2["V"], axis=0) / np.linalg.norm(r2["V"], axis=0))
+    assert e < 1e-12
+
+
+def test_affine_operator_linear_in_theta():
+    syn = synth.make_affine_family(9, 6, 3, 2, 1, seed=8)
+    T = syn["Avs_terms"]
+    t1, t2 = syn["theta"]
+    lhs = oracle.affine_operator(T, 2.0 * t1 - 3.0 * t2)
+    rhs = 2.0 * oracle.affine_operator(T, t1) - 3.0 * oracle.affine_operator(T, t2)
+    assert np.max(np.abs(lhs - rhs)) < 1e-13 * np.max(np.abs(lhs))
