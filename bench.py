@@ -480,16 +480,29 @@ def workload_rank3(args, torch, dev):
         V, S = r.zeros(M, device=dev)
         Vs.append(V); Ss.append(S)
     plan = GroupPlan(roms, mus, Vs, Ss)
+    schedule, plan_us = plan.schedule, plan.times
     _, ms = _events_time(torch, lambda: plan.run(N), 3, 1)
     ksec = float(np.median(ms)) * 1e-3
+    plan.check()
     plan.close()
     for r in roms:
         r.close()
     fam.close()
+    # the column-block plan of the same instances, for comparison
+    famc = AffineFamily(fam_in["Avs_terms"], fam_in["Asv_terms"], b32, 0.1, state="f32", schedule="columns")
+    romc = [famc.instance(th, dt=d) for th, d in zip(fam_in["theta"], dts)]
+    planc = GroupPlan(romc, mus, Vs, Ss)
+    _, msc = _events_time(torch, lambda: planc.run(N), 3, 1)
+    planc.close()
+    for r in romc:
+        r.close()
+    famc.close()
     flops = 4.0 * K * K * M * N * P
     return {"workload": "rank3: affine family, Q=4 terms, Kv=Ks=512, P=64 points x M=64 samples, 2000 steps",
             "value": P * M * N / ksec, "unit": "sample-steps/s", "ms_per_run": ksec * 1e3,
             "tflops": flops / ksec / 1e12, "frac_fp32_mfma": flops / ksec / 1e12 / 157.3,
+            "plan": schedule, "plan_tuning_us_per_step": plan_us,
+            "column_plan_ms_per_run": float(np.median(msc)),
             "assembly_ms_per_instance": t_asm * 1e3}
 
 

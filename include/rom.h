@@ -351,8 +351,9 @@ rom_status rom_run_receivers(rom_ctx *ctx, int32_t M, const double *mu, int64_t 
  * states as in rom_run_rank2 (host arrays of pointers).  Each instance's
  * result is bitwise identical to its own rom_run_rank2 on a column-block
  * schedule.
- * The call uploads a small descriptor table with one stream synchronisation;
- * use the plan API below for asynchronous or graph-captured runs.
+ * The call builds a plan (below), runs it and synchronises `stream`
+ * before releasing the plan; use the plan API for asynchronous or
+ * graph-captured runs.
  */
 rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M,
                            const double *const *mu, int64_t nsteps, void *const *V,
@@ -372,6 +373,35 @@ rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M,
                             rom_group **out);
 rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream);
 rom_status rom_group_destroy(rom_group *g);
+
+/*
+ * Row-split grouped plan.  When every instance is square (Kv == Ks) with
+ * the same padded K in {256, 512, 1024} and none is pinned to column blocks
+ * (ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8), a plan can instead split each
+ * instance's samples into groups of 64 and the operator rows of a group
+ * over K / 64 workgroups, as the row-split schedule of rom_run_rank2 does
+ * for one instance; 256 / (K / 64) groups run per cooperative launch, the
+ * launches one after another.  Each instance's result is then bitwise
+ * identical to its own rom_run_rank2 on the row-split schedule.  Which plan
+ * runs: row-split if every context has ROM_SCHED_ROWSPLIT, else the faster
+ * of the two, timed once per shape (padded K and the list of M) on scratch
+ * states when the plan is made (rom_group_create: on the default stream;
+ * rom_run_grouped: on `stream`) and remembered for the process.  A plan
+ * keeps the column-block form too: a run enqueued on a stream that is being
+ * captured into a graph uses it.  Making such a plan also packs each
+ * context's row-split operators (2 K^2 floats per context, kept by it).
+ *
+ * rom_group_schedule: ROM_SCHEDULE_ROWSPLIT or ROM_SCHEDULE_COLUMNS4 (the
+ *   column-block plan, whatever tiles its instances take); -1 for NULL.
+ * rom_group_times: per-step microseconds of the column-block (us[0]) and
+ *   row-split (us[1]) plans if this plan timed them, else negative.
+ * rom_group_check: as rom_check, for the row-split plan's group barriers
+ *   (synchronises `stream`).  rom_run_grouped synchronises `stream` after
+ *   its run and returns ROM_E_TIMEOUT itself.
+ */
+int32_t rom_group_schedule(const rom_group *g);
+rom_status rom_group_times(const rom_group *g, double us[2]);
+rom_status rom_group_check(rom_group *g, void *stream);
 
 /*
  * Affine operator families (the rank-3 direction of Sec. 5: many operator

@@ -27,6 +27,7 @@ ROM_NSCHEDULES = 3
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
+           "rom_group_schedule", "rom_group_times", "rom_group_check",
            "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
@@ -93,6 +94,12 @@ def load():
         lib.rom_group_run.argtypes = [_vp, _i64, _i64, _vp]
         lib.rom_group_destroy.restype = C.c_int
         lib.rom_group_destroy.argtypes = [_vp]
+        lib.rom_group_schedule.restype = _i32
+        lib.rom_group_schedule.argtypes = [_vp]
+        lib.rom_group_times.restype = C.c_int
+        lib.rom_group_times.argtypes = [_vp, _pd]
+        lib.rom_group_check.restype = C.c_int
+        lib.rom_group_check.argtypes = [_vp, _vp]
         lib.rom_get_operators.restype = C.c_int
         lib.rom_get_operators.argtypes = [_vp, _pd, _pd, _pd]
         lib.rom_energy.restype = C.c_int

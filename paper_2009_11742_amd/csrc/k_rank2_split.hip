@@ -58,6 +58,13 @@ constexpr int kCntStride = 64;     // counters 256 bytes apart
 
 __device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
+// A 64-bit value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 struct SplitArgs {
     const u4 *opv, *ops;        // packed BF16 fragments of Avs and Asv
     const float *b, *c;         // source (kv), probe (kv) or null
@@ -69,6 +76,8 @@ struct SplitArgs {
     unsigned *cnt;              // group counters, kCntStride apart
     unsigned *slots;            // per-XCD slot counters (8)
     int *status;                // status[1] <- ROM_E_TIMEOUT
+    const SplitGroup *grp;      // grouped FP32 runs: per-group instance data, from grp[g0]
+    int g0;
     int kv, kp, M, G, R;
     int64_t n0, nsteps;
     double dt;
@@ -439,7 +448,12 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, i
     }
 }
 
-template <int KG>
+// GR: grouped run of many instances with the same padded K.  Group g then
+// takes its operators, source, mu, states, sizes, first sample column and
+// dt from a.grp[a.g0 + g] (the probe is off); otherwise they come from the
+// arguments and group g owns columns 64 g .. 64 g + 63.  The arithmetic of
+// a column is the same either way.
+template <int KG, bool GR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_split_f32_kernel(SplitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -463,37 +477,58 @@ void rank2_split_f32_kernel(SplitArgs a) {
     const int r = s % R;
     const int g = (s / R) * 8 + xcc;
     if (g >= a.G) return;
-    const int col0 = g * kCols;
+    int kv = a.kv, M = a.M, col0 = g * kCols;
+    double dt = a.dt;
+    const float *bsrc = a.b, *csrc = a.c;
+    const double *mup = a.mu;
+    float *Vp = a.V, *Sp = a.S;
+    const void *opv = a.opv, *ops = a.ops;
+    if constexpr (GR) {
+        // the descriptor is the same for the whole workgroup: keep its
+        // fields in scalar registers (the operator bases must be scalar)
+        const SplitGroup &q = a.grp[a.g0 + g];
+        kv = __builtin_amdgcn_readfirstlane(q.kv);
+        M = __builtin_amdgcn_readfirstlane(q.M);
+        col0 = __builtin_amdgcn_readfirstlane(q.col0);
+        dt = __builtin_bit_cast(double, uniform64(__builtin_bit_cast(uint64_t, q.dt)));
+        bsrc = reinterpret_cast<const float *>(uniform64(reinterpret_cast<uint64_t>(q.b)));
+        csrc = nullptr;
+        mup = reinterpret_cast<const double *>(uniform64(reinterpret_cast<uint64_t>(q.mu)));
+        Vp = reinterpret_cast<float *>(uniform64(reinterpret_cast<uint64_t>(q.V)));
+        Sp = reinterpret_cast<float *>(uniform64(reinterpret_cast<uint64_t>(q.S)));
+        opv = reinterpret_cast<const void *>(uniform64(reinterpret_cast<uint64_t>(q.opv)));
+        ops = reinterpret_cast<const void *>(uniform64(reinterpret_cast<uint64_t>(q.ops)));
+    }
     unsigned *cnt = a.cnt + (size_t)g * kCntStride;
     unsigned phase = 0;
     const int row0 = r * kRows;
 
     for (int i = tid; i < kRows; i += kThreads) {
         const int row = row0 + i;
-        bl[i] = row < a.kv ? a.b[row] : 0.f;
-        cl[i] = (a.c != nullptr && row < a.kv) ? a.c[row] : 0.f;
+        bl[i] = row < kv ? bsrc[row] : 0.f;
+        cl[i] = (csrc != nullptr && row < kv) ? csrc[row] : 0.f;
     }
     // finishing thread: column fj, rows 16 fs .. 16 fs + 15; its state
     // entries of both fields stay in registers
     const int fj = tid >> 2, fs = tid & 3;
     const int fm = col0 + fj;
-    const bool fok = fm < a.M;
-    const double fmu = fok ? a.mu[fm] : 1.0;
+    const bool fok = fm < M;
+    const double fmu = fok ? mup[fm] : 1.0;
     float sh[2][16], sl[2][16];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int row = row0 + 16 * fs + e;
-            const float *src = f == 0 ? a.V : a.S;
-            sh[f][e] = (fok && row < a.kv) ? src[(size_t)fm * a.kv + row] : 0.f;
+            const float *src = f == 0 ? Vp : Sp;
+            sh[f][e] = (fok && row < kv) ? src[(size_t)fm * kv + row] : 0.f;
             sl[f][e] = 0.f;
         }
     __syncthreads();
 
     // this wave's operator panel (k-groups w KG .. of row tile r)
-    const f4 *opvw = reinterpret_cast<const f4 *>(a.opv) + (size_t)(r * kWaves + w) * KG * 4 * 64;
-    const f4 *opsw = reinterpret_cast<const f4 *>(a.ops) + (size_t)(r * kWaves + w) * KG * 4 * 64;
+    const f4 *opvw = reinterpret_cast<const f4 *>(opv) + (size_t)(r * kWaves + w) * KG * 4 * 64;
+    const f4 *opsw = reinterpret_cast<const f4 *>(ops) + (size_t)(r * kWaves + w) * KG * 4 * 64;
     float *xv = reinterpret_cast<float *>(a.xv), *xs = reinterpret_cast<float *>(a.xs);
 
     // publish this thread's 16 rows (hi words) of field f in fragment order:
@@ -530,7 +565,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
             double inc = (part[(0 * kCols + fj) * kLdD + i] + part[(1 * kCols + fj) * kLdD + i]) +
                          (part[(2 * kCols + fj) * kLdD + i] + part[(3 * kCols + fj) * kLdD + i]);
             if (forced) inc = fma((double)bl[i], u, inc);
-            const double yv = fma(a.dt, inc, (double)sh[f][e] + (double)sl[f][e]);
+            const double yv = fma(dt, inc, (double)sh[f][e] + (double)sl[f][e]);
             const float hv = (float)yv;
             sh[f][e] = hv;
             sl[f][e] = (float)(yv - (double)hv);
@@ -545,10 +580,10 @@ void rank2_split_f32_kernel(SplitArgs a) {
     group_barrier(a, cnt, (unsigned)R * ++phase);
 
     double Jacc = 0.0;
-    const bool probe = a.c != nullptr;
+    const bool probe = csrc != nullptr;
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const int64_t n = a.n0 + k;
-        const double t = (double)n * a.dt;
+        const double t = (double)n * dt;
         const double u = fok ? dev::ricker(t, fmu) : 0.0;
         double yp = half_step(0, opvw, xs, xv, u, true);
         if (probe) {
@@ -560,8 +595,8 @@ void rank2_split_f32_kernel(SplitArgs a) {
         if (probe && r == 0 && fs == 0 && fok) {
             double yv = 0.0;
             for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * kCols + fj];
-            Jacc += a.dt * (yv * yv);
-            if (a.y) a.y[(size_t)k * a.M + fm] = yv;
+            Jacc += dt * (yv * yv);
+            if (a.y) a.y[(size_t)k * M + fm] = yv;
         }
         half_step(1, opsw, xv, xs, 0.0, false);
         group_barrier(a, cnt, (unsigned)R * ++phase);
@@ -572,8 +607,8 @@ void rank2_split_f32_kernel(SplitArgs a) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int row = row0 + 16 * fs + e;
-            float *dst = f == 0 ? a.V : a.S;
-            if (fok && row < a.kv) dst[(size_t)fm * a.kv + row] = sh[f][e] + sl[f][e];
+            float *dst = f == 0 ? Vp : Sp;
+            if (fok && row < kv) dst[(size_t)fm * kv + row] = sh[f][e] + sl[f][e];
         }
     if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
 }
@@ -688,6 +723,67 @@ hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *d
     return hipGetLastError();
 }
 
+namespace {
+
+// Carve a workspace of rank2_split_workspace_bytes(kp, G) into the exchange
+// buffers, probe partials, group counters and XCD slot counters, and
+// enqueue the clearing of the counters and of the abort flag status[2].
+hipError_t split_workspace(SplitArgs &a, void *ws, int G, hipStream_t st) {
+    unsigned short *x = static_cast<unsigned short *>(ws);
+    const size_t xsz = (size_t)G * kCols * 2 * a.kp;
+    a.xv = x;
+    a.xs = x + xsz;
+    a.yp = reinterpret_cast<double *>(x + 2 * xsz);
+    a.cnt = reinterpret_cast<unsigned *>(a.yp + (size_t)G * a.R * kCols);
+    a.slots = a.cnt + 256 * kCntStride;
+    hipLaunchKernelGGL(split_zero_kernel, dim3(64), dim3(256), 0, st, a.cnt, 256 * kCntStride + 64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(split_zero_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned *>(a.status + 2), 1);
+    return hipGetLastError();
+}
+
+template <bool GR>
+hipError_t launch_split_f32(int kp, void **args, hipStream_t st) {
+    const size_t lds = rank2_split_f32_lds_bytes();
+    switch (kp) {
+    case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<4, GR>, dim3(256), dim3(kThreads), args, lds, st);
+    case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<8, GR>, dim3(256), dim3(kThreads), args, lds, st);
+    case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<16, GR>, dim3(256), dim3(kThreads), args, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+const void *const kSplitF32Kernels[6] = {
+    (const void *)rank2_split_f32_kernel<4, false>, (const void *)rank2_split_f32_kernel<8, false>,
+    (const void *)rank2_split_f32_kernel<16, false>, (const void *)rank2_split_f32_kernel<4, true>,
+    (const void *)rank2_split_f32_kernel<8, true>, (const void *)rank2_split_f32_kernel<16, true>};
+
+}  // namespace
+
+int rank2_split_groups_per_launch(int kvp) { return 256 / (kvp / kRows); }
+
+hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
+                                    int64_t n0, int64_t nsteps, hipStream_t st) {
+    if (G <= 0 || nsteps <= 0) return hipSuccess;
+    if ((kvp != 256 && kvp != 512 && kvp != 1024) || G > rank2_split_groups_per_launch(kvp))
+        return hipErrorInvalidValue;
+    SplitArgs a{};
+    a.grp = grp_dev;
+    a.g0 = g0;
+    a.kp = kvp;
+    a.G = G;
+    a.R = kvp / kRows;
+    a.n0 = n0;
+    a.nsteps = nsteps;
+    a.scale = 1.0f;
+    a.status = status;
+    hipError_t e = split_workspace(a, ws, G, st);
+    if (e != hipSuccess) return e;
+    void *args[] = {&a};
+    return launch_split_f32<true>(kvp, args, st);
+}
+
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
                               int G, int *status, bool f32, hipStream_t st) {
     SplitArgs a;
@@ -710,30 +806,12 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     a.dt = r2.dt;
     a.scale = scale;
     a.status = status;
-    unsigned short *x = static_cast<unsigned short *>(ws);
-    const size_t xsz = (size_t)G * kCols * 2 * a.kp;
-    a.xv = x;
-    a.xs = x + xsz;
-    a.yp = reinterpret_cast<double *>(x + 2 * xsz);
-    a.cnt = reinterpret_cast<unsigned *>(a.yp + (size_t)G * a.R * kCols);
-    a.slots = a.cnt + 256 * kCntStride;
-    // counters and slots start at zero; status[2] (the abort flag) too
-    hipLaunchKernelGGL(split_zero_kernel, dim3(64), dim3(256), 0, st, a.cnt, 256 * kCntStride + 64);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(split_zero_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned *>(status + 2), 1);
-    e = hipGetLastError();
+    a.grp = nullptr;
+    a.g0 = 0;
+    hipError_t e = split_workspace(a, ws, G, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
-    if (f32) {
-        const size_t lds = rank2_split_f32_lds_bytes();
-        switch (a.kp) {
-        case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<4>, dim3(256), dim3(kThreads), args, lds, st);
-        case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<8>, dim3(256), dim3(kThreads), args, lds, st);
-        case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<16>, dim3(256), dim3(kThreads), args, lds, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
+    if (f32) return launch_split_f32<false>(a.kp, args, st);
     const size_t lds = rank2_split_lds_bytes();
     switch (a.kp) {
     case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<2>, dim3(256), dim3(kThreads), args, lds, st);
@@ -762,9 +840,7 @@ bool rank2_split_device_ok() {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) return false;
     }
-    const void *kf[3] = {(const void *)rank2_split_f32_kernel<4>, (const void *)rank2_split_f32_kernel<8>,
-                         (const void *)rank2_split_f32_kernel<16>};
-    for (const void *f : kf) {
+    for (const void *f : kSplitF32Kernels) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, rank2_split_f32_lds_bytes()) != hipSuccess ||
             nb < 1)
@@ -785,11 +861,11 @@ hipError_t rank2_split_configure() {
     e = hipFuncSetAttribute((const void *)rank2_split_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     const int lf = (int)rank2_split_f32_lds_bytes();
-    e = hipFuncSetAttribute((const void *)rank2_split_f32_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)rank2_split_f32_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)rank2_split_f32_kernel<16>, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+    for (const void *f : kSplitF32Kernels) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rom

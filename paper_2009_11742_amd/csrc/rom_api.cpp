@@ -119,8 +119,8 @@ int split_candidate(rom_ctx *ctx, int32_t M) {
     return ctx->sp_ok == 1 ? G : 0;
 }
 
-// Row-split operands and workspace of a context (built on first use).
-rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
+// Row-split operator packs of a context (built on first use).
+rom_status prepare_split_pack(rom_ctx *ctx, hipStream_t st) {
     hipError_t e;
     if (!ctx->avs_sp) {
         const bool f32 = ctx->op_type == ROM_F32;
@@ -145,6 +145,14 @@ rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
         }
         if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: split pack");
     }
+    return ROM_OK;
+}
+
+// Row-split operands and workspace of a context (built on first use).
+rom_status prepare_split(rom_ctx *ctx, int G, hipStream_t st) {
+    rom_status rs = prepare_split_pack(ctx, st);
+    if (rs != ROM_OK) return rs;
+    hipError_t e;
     const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
     if (ctx->sp_ws_bytes < need) {
         e = hipStreamSynchronize(st);
@@ -1118,6 +1126,243 @@ rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const d
     return ROM_OK;
 }
 
+// Row-split form of a grouped request, if it applies: every instance
+// square (Kv == Ks) with the same padded K in {256, 512, 1024}, FP32
+// operators, a device that runs the row-split kernels, and no instance
+// pinned to column blocks.  One descriptor per 64-sample group, instance
+// by instance.  Packs the instances' row-split operators on `st`.
+rom_status build_split_groups(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
+                              void *const *V, void *const *S, hipStream_t st, std::vector<rom::SplitGroup> &groups,
+                              std::vector<int> &owner, int &kvp, bool &forced) {
+    groups.clear();
+    owner.clear();
+    kvp = ctx[0]->kvp;
+    forced = true;
+    for (int i = 0; i < G; ++i) {
+        rom_ctx *c = ctx[i];
+        if (c->kv != c->ks || c->kvp != kvp || (c->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_COLUMNS8)))
+            return ROM_OK;
+        if (!(c->flags & ROM_SCHED_ROWSPLIT)) forced = false;
+        if (split_candidate(c, 64) == 0) return ROM_OK;
+    }
+    for (int i = 0; i < G; ++i) {
+        rom_status rs = prepare_split_pack(ctx[i], st);
+        if (rs != ROM_OK) return rs;
+        for (int c0 = 0; c0 < M[i]; c0 += 64) {
+            rom::SplitGroup q{};
+            q.opv = ctx[i]->avs_sp; q.ops = ctx[i]->asv_sp;
+            q.b = static_cast<const float *>(ctx[i]->b);
+            q.mu = mu[i];
+            q.V = static_cast<float *>(V[i]); q.S = static_cast<float *>(S[i]);
+            q.dt = ctx[i]->dt;
+            q.kv = ctx[i]->kv; q.M = M[i]; q.col0 = c0;
+            groups.push_back(q);
+            owner.push_back(i);
+        }
+    }
+    return ROM_OK;
+}
+
+// Row-split launches of a grouped run: groups in launches of at most
+// rank2_split_groups_per_launch(kvp), one after another on `st`.
+hipError_t launch_split_groups(const rom::SplitGroup *dev, int ngroups, int kvp, void *ws, int *status, int64_t n0,
+                               int64_t nsteps, hipStream_t st) {
+    const int per = rom::rank2_split_groups_per_launch(kvp);
+    for (int g0 = 0; g0 < ngroups; g0 += per) {
+        hipError_t e = rom::launch_grouped_split_f32(dev, g0, std::min(per, ngroups - g0), kvp, ws, status, n0,
+                                                     nsteps, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Which plan a grouped shape runs: timed once per shape (padded K and the
+// instances' sample counts) and remembered for the process.
+std::mutex g_gsched_mu;
+std::map<std::vector<int>, int> g_gsched;
+
+// Time both plans of a grouped run (per step: best of two runs of
+// kTuneSteps steps after a 2-step warm-up) on scratch states; the caller's
+// mu arrays are read.  A row-split run whose barrier timed out is reported
+// as not applicable (t_split < 0) and its status cleared.
+rom_status time_group_plans(const std::vector<rom::Rank2Args> &inst, const std::vector<int2> &items, size_t lds,
+                            const std::vector<rom::SplitGroup> &groups, const std::vector<int> &owner, int kvp,
+                            void *ws, int *status, hipStream_t st, float &t_col, float &t_split) {
+    const int G = (int)inst.size();
+    std::vector<size_t> off(G + 1, 0);
+    for (int i = 0; i < G; ++i) off[i + 1] = off[i] + (size_t)(inst[i].kv + inst[i].ks) * inst[i].M;
+    std::vector<rom::Rank2Args> ic(inst);
+    std::vector<rom::SplitGroup> gc(groups);
+    float *scr = nullptr;
+    void *dev = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rom_status rs = ROM_OK;
+    const size_t ib = sizeof(rom::Rank2Args) * ic.size(), tb = sizeof(int2) * items.size();
+    const size_t gb = sizeof(rom::SplitGroup) * gc.size();
+    hipError_t e = hipMalloc(&scr, sizeof(float) * off[G]);
+    if (e == hipSuccess) e = hipMalloc(&dev, ib + tb + gb);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        for (int i = 0; i < G; ++i) {
+            ic[i].V = scr + off[i];
+            ic[i].S = scr + off[i] + (size_t)inst[i].kv * inst[i].M;
+        }
+        for (size_t q = 0; q < gc.size(); ++q) {
+            gc[q].V = static_cast<float *>(ic[owner[q]].V);
+            gc[q].S = static_cast<float *>(ic[owner[q]].S);
+        }
+        char *d = static_cast<char *>(dev);
+        e = hipMemsetAsync(scr, 0, sizeof(float) * off[G], st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d, ic.data(), ib, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d + ib, items.data(), tb, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d + ib + tb, gc.data(), gb, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) rs = hip_fail(e, "grouped plan tuning: setup");
+    const char *d = static_cast<const char *>(dev);
+    float best[2] = {1e30f, 1e30f};
+    for (int plan = 0; plan < 2 && rs == ROM_OK; ++plan) {
+        for (int rep = 0; rep < 3 && rs == ROM_OK; ++rep) {   // rep 0: warm-up
+            const int64_t n = rep == 0 ? 2 : kTuneSteps;
+            e = rep > 0 ? hipEventRecord(e0, st) : hipSuccess;
+            if (e == hipSuccess)
+                e = plan == 0 ? rom::launch_grouped_f32_mfma(reinterpret_cast<const rom::Rank2Args *>(d),
+                                                             reinterpret_cast<const int2 *>(d + ib), (int)items.size(),
+                                                             lds, 0, n, st)
+                              : launch_split_groups(reinterpret_cast<const rom::SplitGroup *>(d + ib + tb),
+                                                    (int)gc.size(), kvp, ws, status, 0, n, st);
+            if (e == hipSuccess && rep > 0) e = hipEventRecord(e1, st);
+            if (e == hipSuccess && rep > 0) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess && rep > 0) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rs = hip_fail(e, "grouped plan tuning"); break; }
+            if (rep > 0) best[plan] = std::min(best[plan], ms * 1e3f / (float)n);
+        }
+    }
+    if (rs == ROM_OK) e = hipStreamSynchronize(st);
+    if (rs == ROM_OK && e != hipSuccess) rs = hip_fail(e, "grouped plan tuning");
+    if (rs == ROM_OK) {
+        int w[2] = {0, 0};
+        e = hipMemcpy(w, status + 1, sizeof(w), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && (w[0] != 0 || w[1] != 0)) {
+            best[1] = -1.f;
+            e = hipMemset(status + 1, 0, sizeof(w));
+        }
+        if (e != hipSuccess) rs = hip_fail(e, "grouped plan tuning: status");
+    }
+    t_col = best[0];
+    t_split = best[1];
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    hfree(scr);
+    hfree(dev);
+    return rs;
+}
+
+// Free a plan's device memory (its work must have completed).
+void free_group(rom_group *g) {
+    hfree(g->dev);
+    hfree(g->sp_dev);
+    hfree(g->sp_ws);
+    hfree(g->sp_status);
+    delete g;
+}
+
+// Build a plan: the column-block descriptor table always (graph capture runs
+// it), the row-split table and its workspace when that plan applies and is
+// forced or timed faster.  Tuning runs on `st` and synchronises it.
+rom_status make_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu, void *const *V,
+                      void *const *S, hipStream_t st, const char *who, rom_group **out) {
+    std::string w(who);
+    std::vector<rom::Rank2Args> inst;
+    std::vector<int2> items;
+    size_t lds = 0;
+    rom_status r = build_group(ctx, G, M, mu, V, S, st, inst, items, lds);
+    if (r != ROM_OK) return r;
+    std::vector<rom::SplitGroup> groups;
+    std::vector<int> owner;
+    int kvp = 0;
+    bool forced = false;
+    r = build_split_groups(ctx, G, M, mu, V, S, st, groups, owner, kvp, forced);
+    if (r != ROM_OK) return r;
+    if (!groups.empty() && !stream_capturing(st)) {
+        hipError_t es = hipStreamSynchronize(st);   // the packs are complete before any plan runs
+        if (es != hipSuccess) return hip_fail(es, (std::string(who) + ": synchronize").c_str());
+    }
+    rom_group *g = new (std::nothrow) rom_group();
+    if (!g) return fail(ROM_E_NOMEM, w + ": host allocation failed");
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { free_group(g); return hip_fail(e, (w + ": hipGetDevice").c_str()); }
+    const size_t ib = sizeof(rom::Rank2Args) * inst.size();
+    const size_t bytes = ib + sizeof(int2) * items.size();
+    e = hipMalloc(&g->dev, bytes);
+    if (e != hipSuccess) { free_group(g); return fail(ROM_E_NOMEM, w + ": device allocation failed"); }
+    e = hipMemcpy(g->dev, inst.data(), ib, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(static_cast<char *>(g->dev) + ib, items.data(), sizeof(int2) * items.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) { free_group(g); return hip_fail(e, (w + ": upload").c_str()); }
+    g->G = G;
+    g->nitems = (int)items.size();
+    g->lds_bytes = lds;
+    g->inst = static_cast<const rom::Rank2Args *>(g->dev);
+    g->items = reinterpret_cast<const int2 *>(static_cast<char *>(g->dev) + ib);
+    if (!groups.empty() && !stream_capturing(st)) {
+        const int per = rom::rank2_split_groups_per_launch(kvp);
+        const size_t wsb = rom::rank2_split_workspace_bytes(kvp, std::min(per, (int)groups.size()));
+        e = hipMalloc(&g->sp_ws, wsb);
+        if (e == hipSuccess) e = hipMalloc(&g->sp_status, sizeof(int) * 4);
+        if (e == hipSuccess) e = hipMalloc(&g->sp_dev, sizeof(rom::SplitGroup) * groups.size());
+        if (e != hipSuccess) { free_group(g); return fail(ROM_E_NOMEM, w + ": device allocation failed"); }
+        e = hipMemset(g->sp_status, 0, sizeof(int) * 4);
+        if (e == hipSuccess)
+            e = hipMemcpy(g->sp_dev, groups.data(), sizeof(rom::SplitGroup) * groups.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { free_group(g); return hip_fail(e, (w + ": upload").c_str()); }
+        g->kvp = kvp;
+        g->ngroups = (int)groups.size();
+        bool use = forced;
+        if (!forced) {
+            std::vector<int> key{kvp};
+            for (int i = 0; i < G; ++i) key.push_back(M[i]);
+            int dec = -1;
+            {
+                std::lock_guard<std::mutex> lk(g_gsched_mu);
+                auto it = g_gsched.find(key);
+                if (it != g_gsched.end()) dec = it->second;
+            }
+            if (dec < 0) {
+                float tc = -1.f, ts = -1.f;
+                r = time_group_plans(inst, items, lds, groups, owner, kvp, g->sp_ws, g->sp_status, st, tc, ts);
+                if (r != ROM_OK) { free_group(g); return r; }
+                g->us[0] = tc;
+                g->us[1] = ts;
+                dec = (ts >= 0.f && ts < tc) ? 1 : 0;
+                std::lock_guard<std::mutex> lk(g_gsched_mu);
+                g_gsched[key] = dec;
+            }
+            use = dec == 1;
+        }
+        if (!use) {
+            hfree(g->sp_dev); hfree(g->sp_ws); hfree(g->sp_status);
+            g->sp_dev = g->sp_ws = nullptr;
+            g->sp_status = nullptr;
+            g->ngroups = 0;
+        }
+    }
+    *out = g;
+    return ROM_OK;
+}
+
+// Enqueue a plan's run: row-split launches when the plan has them and the
+// stream is not being captured, else the column-block launch.
+hipError_t run_group(rom_group *g, int64_t n0, int64_t nsteps, hipStream_t st) {
+    if (g->ngroups > 0 && !stream_capturing(st))
+        return launch_split_groups(static_cast<const rom::SplitGroup *>(g->sp_dev), g->ngroups, g->kvp, g->sp_ws,
+                                   g->sp_status, n0, nsteps, st);
+    return rom::launch_grouped_f32_mfma(g->inst, g->items, g->nitems, g->lds_bytes, n0, nsteps, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1126,79 +1371,69 @@ rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M, co
                             void *const *V, void *const *S, rom_group **out) {
     if (out) *out = nullptr;
     if (!out) return fail(ROM_E_ARG, "rom_group_create: NULL out");
-    std::vector<rom::Rank2Args> inst;
-    std::vector<int2> items;
-    size_t lds = 0;
-    rom_status r = build_group(ctx, G, M, mu, V, S, nullptr, inst, items, lds);
-    if (r != ROM_OK) return r;
-    rom_group *g = new (std::nothrow) rom_group();
-    if (!g) return fail(ROM_E_NOMEM, "rom_group_create: host allocation failed");
-    hipError_t e = hipGetDevice(&g->device);
-    if (e != hipSuccess) { delete g; return hip_fail(e, "rom_group_create: hipGetDevice"); }
-    const size_t ib = sizeof(rom::Rank2Args) * inst.size();
-    const size_t bytes = ib + sizeof(int2) * items.size();
-    e = hipMalloc(&g->dev, bytes);
-    if (e != hipSuccess) { delete g; return fail(ROM_E_NOMEM, "rom_group_create: device allocation failed"); }
-    e = hipMemcpy(g->dev, inst.data(), ib, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(static_cast<char *>(g->dev) + ib, items.data(), sizeof(int2) * items.size(),
-                      hipMemcpyHostToDevice);
-    if (e != hipSuccess) { hfree(g->dev); delete g; return hip_fail(e, "rom_group_create: upload"); }
-    g->G = G;
-    g->nitems = (int)items.size();
-    g->lds_bytes = lds;
-    g->inst = static_cast<const rom::Rank2Args *>(g->dev);
-    g->items = reinterpret_cast<const int2 *>(static_cast<char *>(g->dev) + ib);
-    *out = g;
-    return ROM_OK;
+    return make_group(ctx, G, M, mu, V, S, nullptr, "rom_group_create", out);
 }
 
 rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream) {
     if (!g) return fail(ROM_E_ARG, "rom_group_run: NULL plan");
     if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_group_run: n0 and nsteps must be >= 0");
-    hipError_t e = rom::launch_grouped_f32_mfma(g->inst, g->items, g->nitems, g->lds_bytes, n0, nsteps,
-                                                static_cast<hipStream_t>(stream));
+    hipError_t e = run_group(g, n0, nsteps, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "rom_group_run: launch");
+    return ROM_OK;
+}
+
+int32_t rom_group_schedule(const rom_group *g) {
+    if (!g) return -1;
+    return g->ngroups > 0 ? ROM_SCHEDULE_ROWSPLIT : ROM_SCHEDULE_COLUMNS4;
+}
+
+rom_status rom_group_times(const rom_group *g, double us[2]) {
+    if (!g || !us) return fail(ROM_E_ARG, "rom_group_times: NULL argument");
+    us[0] = g->us[0];
+    us[1] = g->us[1];
+    return ROM_OK;
+}
+
+rom_status rom_group_check(rom_group *g, void *stream) {
+    if (!g) return fail(ROM_E_ARG, "rom_group_check: NULL plan");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "rom_group_check: synchronize");
+    if (!g->sp_status) return ROM_OK;
+    int w[2] = {0, 0};
+    e = hipMemcpy(w, g->sp_status + 1, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "rom_group_check: read status");
+    if (w[0] != 0 || w[1] != 0) {
+        e = hipMemset(g->sp_status + 1, 0, sizeof(w));
+        if (e != hipSuccess) return hip_fail(e, "rom_group_check: clear status");
+        if (w[0] == ROM_E_TIMEOUT)
+            return fail(ROM_E_TIMEOUT, "rom_group_check: a row-split group barrier timed out; the run's results are invalid");
+    }
     return ROM_OK;
 }
 
 rom_status rom_group_destroy(rom_group *g) {
     if (!g) return ROM_OK;
-    hfree(g->dev);
-    delete g;
+    free_group(g);
     return ROM_OK;
 }
 
 rom_status rom_run_grouped(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
                            int64_t nsteps, void *const *V, void *const *S, void *stream) {
     if (nsteps < 0) return fail(ROM_E_ARG, "rom_run_grouped: nsteps must be >= 0");
-    std::vector<rom::Rank2Args> inst;
-    std::vector<int2> items;
-    size_t lds = 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    rom_status r = build_group(ctx, G, M, mu, V, S, st, inst, items, lds);
+    rom_group *g = nullptr;
+    rom_status r = make_group(ctx, G, M, mu, V, S, st, "rom_run_grouped", &g);
     if (r != ROM_OK) return r;
-    if (nsteps == 0) return ROM_OK;
-    const size_t ib = sizeof(rom::Rank2Args) * inst.size();
-    const size_t bytes = ib + sizeof(int2) * items.size();
-    // one contiguous host block, uploaded stream-ordered into stream-ordered
-    // device memory that is released after the launch on the same stream
-    std::vector<unsigned char> host(bytes);
-    memcpy(host.data(), inst.data(), ib);
-    memcpy(host.data() + ib, items.data(), sizeof(int2) * items.size());
-    void *dev = nullptr;
-    hipError_t e = hipMallocAsync(&dev, bytes, st);
-    if (e != hipSuccess) return fail(ROM_E_NOMEM, "rom_run_grouped: device allocation failed");
-    e = hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host block dies on return
-    if (e == hipSuccess)
-        e = rom::launch_grouped_f32_mfma(static_cast<const rom::Rank2Args *>(dev),
-                                         reinterpret_cast<const int2 *>(static_cast<char *>(dev) + ib),
-                                         (int)items.size(), lds, 0, nsteps, st);
-    hipError_t e2 = hipFreeAsync(dev, st);
-    if (e != hipSuccess) return hip_fail(e, "rom_run_grouped");
-    if (e2 != hipSuccess) return hip_fail(e2, "rom_run_grouped: free");
-    return ROM_OK;
+    hipError_t e = nsteps > 0 ? run_group(g, 0, nsteps, st) : hipSuccess;
+    // the plan's memory is released once its run has completed
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess && e2 == hipSuccess && g->ngroups > 0) {
+        r = rom_group_check(g, stream);
+    }
+    free_group(g);
+    if (e != hipSuccess) return hip_fail(e, "rom_run_grouped: launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "rom_run_grouped: synchronize");
+    return r;
 }
 
 }  // extern "C"

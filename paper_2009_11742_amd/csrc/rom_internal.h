@@ -161,6 +161,27 @@ hipError_t launch_rank1_step(const void *avs_cm, const void *asv_cm, const void 
                              int ks, double dt, int64_t n, double mu, void *v, void *s,
                              hipStream_t st);
 
+// Grouped row-split run (FP32 operators, Kv == Ks, one padded K for all
+// instances): one descriptor per 64-sample group.  opv / ops are the
+// instance's row-split FP32 operator packs, b its padded FP32 source, mu /
+// V / S its own arrays (ld kv); the group owns samples col0 .. col0 + 63
+// of the instance's M.
+struct SplitGroup {
+    const void *opv, *ops;
+    const float *b;
+    const double *mu;
+    float *V, *S;
+    double dt;
+    int kv, M, col0, pad_;
+};
+// Groups one cooperative launch holds at padded size kvp (256 / (kvp / 64)).
+int rank2_split_groups_per_launch(int kvp);
+// Groups g0 .. g0 + G - 1 of the device table grp_dev, nsteps steps from
+// n0; ws holds rank2_split_workspace_bytes(kvp, G) bytes; status as for
+// launch_rank2_split.
+hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
+                                    int64_t n0, int64_t nsteps, hipStream_t st);
+
 // Affine operators: coefficients of up to kMaxAffine terms, by value.
 constexpr int kMaxAffine = 16;
 struct AffineCoeffs {
@@ -186,6 +207,12 @@ struct rom_group {
     void *dev = nullptr;          // [G] Rank2Args then [nitems] int2 items
     const rom::Rank2Args *inst = nullptr;
     const int2 *items = nullptr;
+    // row-split plan (used when ngroups > 0)
+    int ngroups = 0, kvp = 0;
+    void *sp_dev = nullptr;       // [ngroups] SplitGroup
+    void *sp_ws = nullptr;        // exchange workspace of one launch
+    int *sp_status = nullptr;     // [4]: [1] ROM_E_TIMEOUT, [2] abort flag
+    float us[2] = {-1.f, -1.f};   // timed per-step us of the two plans, if timed
 };
 
 // Affine family of operator pairs (rank-3 direction): the Q terms of both

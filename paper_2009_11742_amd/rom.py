@@ -300,8 +300,12 @@ def run_grouped(roms, mus, Vs, Ss, nsteps, stream=None):
 
 
 class GroupPlan:
-    """Uploaded descriptor table of a grouped run; ``run`` is one launch and
-    may be captured in a CUDA/HIP graph.  Keeps references to its tensors."""
+    """Uploaded descriptor table of a grouped run.  ``run`` enqueues the
+    plan's launches (column blocks: one launch, which may be captured in a
+    HIP graph; row-split: one cooperative launch per 256 / (K / 64) groups,
+    and a captured run takes the column-block form).  ``schedule`` is
+    "rowsplit" or "columns"; ``times`` the timed per-step microseconds of
+    both plans, if this plan timed them.  Keeps references to its tensors."""
 
     def __init__(self, roms, mus, Vs, Ss):
         ctxs, G, Ms, mup, Vp, Sp = _group_args(roms, mus, Vs, Ss)
@@ -312,6 +316,20 @@ class GroupPlan:
 
     def run(self, nsteps, n0=0, stream=None):
         check(_lib.load().rom_group_run(self._h, int(n0), int(nsteps), _stream_handle(stream)))
+
+    @property
+    def schedule(self):
+        sc = _lib.load().rom_group_schedule(self._h)
+        return "rowsplit" if sc == _lib.ROM_SCHEDULE_ROWSPLIT else "columns"
+
+    @property
+    def times(self):
+        us = (C.c_double * 2)()
+        check(_lib.load().rom_group_times(self._h, us))
+        return {"columns": us[0] if us[0] >= 0 else None, "rowsplit": us[1] if us[1] >= 0 else None}
+
+    def check(self, stream=None):
+        check(_lib.load().rom_group_check(self._h, _stream_handle(stream)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

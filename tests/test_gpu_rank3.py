@@ -108,3 +108,42 @@ def test_affine_skew_check():
         fam.instance(th, dt=2.01 / smax)
     assert ei.value.status == _lib.ROM_E_UNSTABLE
     fam.close()
+
+
+def test_rank3_rowsplit_plan_matches_standalone():
+    """Instances of a K = 256 family pinned to the row-split schedule run as
+    one row-split grouped plan, each bitwise equal to its own row-split
+    run; one sampled column per instance against the oracle."""
+    from paper_2009_11742_amd import AffineFamily, GroupPlan
+    fam_in = synth.make_affine_family(256, 256, 3, 5, 64, seed=4)
+    b32 = fam_in["b"].astype(np.float32).astype(np.float64)
+    fam = AffineFamily(fam_in["Avs_terms"], fam_in["Asv_terms"], b32, 0.1, state="f32", schedule="rowsplit")
+    roms, mus, Vs, Ss, dts = [], [], [], [], []
+    for th, mu in zip(fam_in["theta"], fam_in["mu"]):
+        dt = float(np.float32(0.5 / float(np.abs(th) @ fam_in["smax"])))
+        r = fam.instance(th, dt=dt)
+        V, S = r.zeros(len(mu))
+        roms.append(r); dts.append(dt); Vs.append(V); Ss.append(S)
+        mus.append(torch.tensor(mu, dtype=torch.float64, device="cuda"))
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    assert plan.schedule == "rowsplit"
+    N = 600
+    plan.run(N)
+    plan.check()
+    torch.cuda.synchronize()
+    for p, r in enumerate(roms):
+        V1, S1 = r.zeros(64)
+        r.run_rank2(mus[p], V1, S1, N)
+        r.check()
+        assert r.last_schedule == "rowsplit"
+        torch.cuda.synchronize()
+        assert torch.equal(Vs[p], V1) and torch.equal(Ss[p], S1), p
+        Ag, Bg, _ = r.operators()
+        col = 17 * p % 64
+        ref = oracle.run_rank2(Ag, Bg, b32, dts[p], fam_in["mu"][p][col:col + 1], N)
+        e = _relcol(Vs[p].cpu().numpy().astype(np.float64).T[:, col:col + 1], ref["V"])
+        assert e <= 1e-5, (p, e)
+    plan.close()
+    for r in roms:
+        r.close()
+    fam.close()
