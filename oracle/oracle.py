@@ -68,6 +68,10 @@ def _load():
             lib.orc_round_bf16.argtypes = [_d]
             lib.orc_quantize_e4m3.restype = _d
             lib.orc_quantize_e4m3.argtypes = [_i64, _pd, _pd, _d]
+            _pi = C.POINTER(C.c_int32)
+            lib.orc_fom_run.restype = _i
+            lib.orc_fom_run.argtypes = [_i, _i, _pi, _pi, _pd, _pi, _pi, _pd, _pd, _d, _i, _pd, _i64, _i64,
+                                        _pd, _pd]
             _lib = lib
     return _lib
 
@@ -187,6 +191,89 @@ def affine_operator(terms, theta):
     for q in range(1, th.size):
         acc = acc + th[q] * T[q]
     return acc
+
+
+def _csr3(A):
+    ptr, col, val = A
+    return (np.ascontiguousarray(ptr, dtype=np.int32), np.ascontiguousarray(col, dtype=np.int32),
+            np.ascontiguousarray(val, dtype=np.float64))
+
+
+def fom_run(Av, As, f, dt, mu, nsteps, V=None, S=None, n0=0):
+    """Rank-2 full-order model of the staggered system (Sec. 3, eq. (3.2)),
+    leapfrog as for the ROM.  Av (Nv x Ns) and As (Ns x Nv) are CSR triples
+    (ptr, col, val); f the Nv source vector; states row-major (N x M, one
+    sample per column).  Returns the final V and S."""
+    avp, avc, avv = _csr3(Av)
+    asp, asc, asv = _csr3(As)
+    nv, ns = avp.size - 1, asp.size - 1
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    M = mu.size
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(nv))
+    V = np.zeros((nv, M)) if V is None else np.array(V, dtype=np.float64, order="C", copy=True)
+    S = np.zeros((ns, M)) if S is None else np.array(S, dtype=np.float64, order="C", copy=True)
+    assert V.shape == (nv, M) and S.shape == (ns, M)
+    pi = C.POINTER(C.c_int32)
+    rc = _load().orc_fom_run(nv, ns, avp.ctypes.data_as(pi), avc.ctypes.data_as(pi), _p(avv),
+                             asp.ctypes.data_as(pi), asc.ctypes.data_as(pi), _p(asv), _p(f), float(dt), M,
+                             _p(mu), int(n0), int(nsteps), _p(V), _p(S))
+    if rc != 0:
+        raise MemoryError("oracle run failed")
+    return {"V": V, "S": S}
+
+
+def csr_dense(A, ncols):
+    """Dense form of a CSR triple (duplicates summed)."""
+    ptr, col, val = _csr3(A)
+    n = ptr.size - 1
+    D = np.zeros((n, ncols))
+    for r in range(n):
+        for k in range(ptr[r], ptr[r + 1]):
+            D[r, col[k]] += val[k]
+    return D
+
+
+def project(Av, As, f, Phi_v, Phi_s):
+    """Galerkin projection of the full-order operators onto orthonormal
+    bases (Sec. 2.2 and eq. (3.3)): Avs = Phi_v^T Av Phi_s,
+    Asv = Phi_s^T As Phi_v, b = Phi_v^T f.  Phi_v (Nv x Kv), Phi_s (Ns x Kv)
+    dense; the sparse products go row by row over the stored entries, the
+    reductions over the full-order index are library matrix products."""
+    Phi_v = np.asarray(Phi_v, dtype=np.float64)
+    Phi_s = np.asarray(Phi_s, dtype=np.float64)
+
+    def spmm(A, X):
+        ptr, col, val = _csr3(A)
+        Y = np.zeros((ptr.size - 1, X.shape[1]))
+        rows = np.repeat(np.arange(ptr.size - 1), np.diff(ptr))
+        np.add.at(Y, rows, val[:, None] * X[col])
+        return Y
+    Avs = Phi_v.T @ spmm(Av, Phi_s)
+    Asv = Phi_s.T @ spmm(As, Phi_v)
+    b = Phi_v.T @ np.asarray(f, dtype=np.float64)
+    return Avs, Asv, b
+
+
+def pod_rank(sigma, tol):
+    """Smallest k whose leading singular values hold at least 1 - tol of
+    the snapshot energy sum sigma_i^2 (Sec. 4.4's truncation criterion)."""
+    e = np.asarray(sigma, dtype=np.float64) ** 2
+    tot = e.sum()
+    c = np.cumsum(e)
+    return int(np.searchsorted(c, (1.0 - tol) * tot, side="left") + 1) if tot > 0 else 0
+
+
+def pod(X, tol=None, k=None):
+    """Proper orthogonal decomposition of a snapshot matrix X (N x ns, one
+    snapshot per column): the left singular vectors of the thin SVD, kept to
+    k columns (given, or by the energy criterion with tolerance tol).
+    Returns (Phi (N x k), sigma (all ns, descending), k)."""
+    X = np.asarray(X, dtype=np.float64)
+    U, s, _ = np.linalg.svd(X, full_matrices=False)
+    if k is None:
+        k = pod_rank(s, tol) if tol is not None else s.size
+    k = min(int(k), s.size)
+    return U[:, :k], s, k
 
 
 def percentile_index(p, M):

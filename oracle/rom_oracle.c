@@ -396,3 +396,48 @@ double orc_quantize_e4m3(int64_t n, const double *x, double *out, double amax_in
     }
     return (double)scale;
 }
+
+/* ---- full-order model (FOM) ---------------------------------------------
+ * The rank-2 FOM of the staggered shear-wave system (Sec. 3, eq. (3.2)):
+ *
+ *   dV/dt = Av S + f u(t; mu)^T,    dS/dt = As V
+ *
+ * with sparse Av (Nv x Ns) and As (Ns x Nv) in CSR form (row pointers,
+ * column indices, values; the entries of a row in the stored order), f the
+ * (sparse) point-source vector and the same leapfrog as the ROM: for
+ * n = n0 .. n0+nsteps-1, t_n = n dt,
+ *
+ *   V[r, m] <- V[r, m] + dt * ((sum_k Av[r, k] S[k, m]) + f[r] u_m(t_n))
+ *   S[r, m] <- S[r, m] + dt * (sum_k As[r, k] V[k, m])     (the new V)
+ *
+ * States are row-major here (element (r, m) at [r*M + m], the layout of the
+ * paper's rank-2 FOM runs), sums in the stored entry order. */
+static void csr_update(int nrows, const int *ptr, const int *col, const double *val,
+                       const double *X, int M, const double *f, const double *u, double dt, double *Y)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < nrows; ++r)
+        for (int m = 0; m < M; ++m) {
+            double inc = 0.0;
+            for (int k = ptr[r]; k < ptr[r + 1]; ++k) inc = inc + val[k] * X[(int64_t)col[k] * M + m];
+            if (f) inc = inc + f[r] * u[m];
+            Y[(int64_t)r * M + m] = Y[(int64_t)r * M + m] + dt * inc;
+        }
+}
+
+int orc_fom_run(int nv, int ns, const int *avp, const int *avc, const double *avv,
+                const int *asp, const int *asc, const double *asv, const double *f,
+                double dt, int M, const double *mu, int64_t n0, int64_t nsteps,
+                double *V, double *S)
+{
+    double *u = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+    if (!u) return 1;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const double t = (double)(n0 + k) * dt;
+        for (int m = 0; m < M; ++m) u[m] = orc_ricker(t, mu[m]);
+        csr_update(nv, avp, avc, avv, S, M, f, u, dt, V);
+        csr_update(ns, asp, asc, asv, V, M, NULL, u, dt, S);
+    }
+    free(u);
+    return 0;
+}

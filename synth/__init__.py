@@ -27,7 +27,8 @@ import math
 
 import numpy as np
 
-__all__ = ["make_instance", "round_to", "grouped_draws", "make_affine_family", "CONFIGS"]
+__all__ = ["make_instance", "round_to", "grouped_draws", "make_affine_family", "make_shear_fom",
+           "shear_fom_sizes", "fom_periods", "CONFIGS"]
 
 # The five workloads (sizes and step counts) this build measures or checks.
 CONFIGS = {
@@ -131,3 +132,111 @@ def make_affine_family(kv: int, ks: int, Q: int, P: int, M: int, seed: int = 0, 
     smax = np.array([float(np.linalg.svd(A[q], compute_uv=False)[0]) for q in range(Q)])
     return {"Avs_terms": A, "Asv_terms": B, "b": b, "theta": theta, "mu": mu, "smax": smax,
             "kv": kv, "ks": ks, "Q": Q, "P": P, "M": M, "seed": seed}
+
+
+def _csr(nrows, rows, cols, vals):
+    """CSR (rowptr int32, col int32, val float64) from COO lists; entries of a
+    row sorted by column."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    ptr = np.zeros(nrows + 1, dtype=np.int64)
+    np.add.at(ptr, rows + 1, 1)
+    ptr = np.cumsum(ptr)
+    return ptr.astype(np.int32), cols.astype(np.int32), vals
+
+
+def shear_fom_sizes(nr: int, nth: int):
+    """(N_v, N_s) of the staggered grid of ``make_shear_fom``."""
+    return nr * nth, (nr - 1) * nth + nr * (nth - 1)
+
+
+def make_shear_fom(nr: int, nth: int, rho: float = 2500.0, vs: float = 5000.0, r_cmb: float = 3480e3,
+                   r_earth: float = 6371e3, src_depth: float = 640e3, dt: float | None = None):
+    """Sparse full-order operators of the axisymmetric shear-wave system on
+    a staggered grid (Sec. 3, eqs. (3.1)-(3.2)), for a single homogeneous
+    layer (density rho, shear velocity vs: the setup of the paper's FOM
+    scaling runs, Appendix A).  Second-order centred differences:
+
+    grid      velocity v at (r_i, th_j), r_i = r_cmb + i dr (i < nr),
+              th_j = j dth (j < nth, dth = pi / (nth - 1));
+              s_rp at (r_{i+1/2}, th_j), i < nr - 1;  s_tp at (r_i, th_{j+1/2}),
+              j < nth - 1.  Index v: i nth + j; stresses: all s_rp (i (nth) + j)
+              first, then s_tp (i (nth - 1) + j).
+    velocity  rho dv/dt = d s_rp/dr + (1/r) d s_tp/dth + (3 s_rp + 2 cot(th) s_tp)/r + f;
+              d/dr and d/dth as centred differences of the two neighbours, the
+              undifferentiated stresses as their two-neighbour means.  Rows on
+              the axis (j = 0, nth - 1) are zero (v = 0 there).  At r_cmb and
+              r_earth (i = 0, nr - 1) the free surface sets s_rp = 0 at the
+              velocity point: d s_rp/dr is the one-sided difference over half
+              a cell, and the s_rp mean is zero.
+    stresses  d s_rp/dt = mu (dv/dr - v/r) at r_{i+1/2} (zero on the axis);
+              d s_tp/dt = mu ((1/r) dv/dth - cot(th) v / r) at th_{j+1/2}; v
+              undifferentiated as the two-neighbour mean; mu = rho vs^2.
+    source    f = e_src / rho at the velocity point nearest to depth
+              src_depth in r, at the first theta > 0 (Sec. 3.2).
+    dt        default 0.4 min(dr, r_cmb dth) / vs (inside the CFL limit).
+
+    Returns Av (N_v x N_s) and As (N_s x N_v) as CSR (ptr, col, val), f, the
+    grid sizes and dt.
+    """
+    dr = (r_earth - r_cmb) / (nr - 1)
+    dth = math.pi / (nth - 1)
+    mu_s = rho * vs * vs
+    nv = nr * nth
+    nrp = (nr - 1) * nth
+    ntp = nr * (nth - 1)
+    ns = nrp + ntp
+
+    cat = np.concatenate
+    # velocity rows (off-axis j = 1 .. nth - 2)
+    I, J = np.meshgrid(np.arange(nr), np.arange(1, nth - 1), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    r = r_cmb + I * dr
+    cot = np.cos(J * dth) / np.sin(J * dth)
+    row = I * nth + J
+    inner = (I > 0) & (I < nr - 1)
+    lo, hi = I == 0, I == nr - 1
+    rows = [row[inner], row[inner], row[lo], row[hi], row, row]
+    cols = [I[inner] * nth + J[inner], (I[inner] - 1) * nth + J[inner], 0 * nth + J[lo], (nr - 2) * nth + J[hi],
+            nrp + I * (nth - 1) + J, nrp + I * (nth - 1) + J - 1]
+    vals = [(1.0 / dr + 1.5 / r[inner]) / rho, (-1.0 / dr + 1.5 / r[inner]) / rho,
+            np.full(lo.sum(), (2.0 / dr) / rho), np.full(hi.sum(), (-2.0 / dr) / rho),
+            (1.0 / (r * dth) + cot / r) / rho, (-1.0 / (r * dth) + cot / r) / rho]
+    Av = _csr(nv, cat(rows), cat(cols), cat(vals))
+
+    # s_rp rows (off-axis), then s_tp rows
+    I, J = np.meshgrid(np.arange(nr - 1), np.arange(1, nth - 1), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    rh = r_cmb + (I + 0.5) * dr
+    row = I * nth + J
+    rows = [row, row]
+    cols = [(I + 1) * nth + J, I * nth + J]
+    vals = [mu_s * (1.0 / dr - 0.5 / rh), mu_s * (-1.0 / dr - 0.5 / rh)]
+    I, J = np.meshgrid(np.arange(nr), np.arange(nth - 1), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    r = r_cmb + I * dr
+    coth = np.cos((J + 0.5) * dth) / np.sin((J + 0.5) * dth)
+    row = nrp + I * (nth - 1) + J
+    rows += [row, row]
+    cols += [I * nth + J + 1, I * nth + J]
+    vals += [mu_s * (1.0 / (r * dth) - 0.5 * coth / r), mu_s * (-1.0 / (r * dth) - 0.5 * coth / r)]
+    As = _csr(ns, cat(rows), cat(cols), cat(vals))
+
+    i_src = int(round((r_earth - src_depth - r_cmb) / dr))
+    i_src = min(max(i_src, 0), nr - 1)
+    f = np.zeros(nv)
+    f[i_src * nth + 1] = 1.0 / rho
+    if dt is None:
+        dt = 0.4 * min(dr, r_cmb * dth) / vs
+    return {"Av": Av, "As": As, "f": f, "nv": nv, "ns": ns, "nr": nr, "nth": nth, "dr": dr, "dth": dth,
+            "r_cmb": r_cmb, "rho": rho, "vs": vs, "src": i_src * nth + 1, "dt": float(dt)}
+
+
+def fom_periods(M: int, seed: int = 0, lo: float = 60.0, hi: float = 80.0):
+    """Centre frequencies mu = 1 / T of M forcing samples, periods
+    T ~ U(lo, hi) seconds (the rank-2 FOM runs of Appendix A)."""
+    rng = np.random.default_rng(seed)
+    return 1.0 / rng.uniform(lo, hi, M)

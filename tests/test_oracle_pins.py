@@ -512,3 +512,146 @@ def test_affine_operator_linear_in_theta():
     lhs = oracle.affine_operator(T, 2.0 * t1 - 3.0 * t2)
     rhs = 2.0 * oracle.affine_operator(T, t1) - 3.0 * oracle.affine_operator(T, t2)
     assert np.max(np.abs(lhs - rhs)) < 1e-13 * np.max(np.abs(lhs))
+
+
+# ---- full-order model, Galerkin projection and POD (offline side)
+
+def test_fom_grid_sizes_match_the_paper():
+    """The velocity grids of the FOM scaling runs (256 x 1024 ... 2048 x
+    8192) give the total degree-of-freedom counts printed with them
+    (Sec. 4.1)."""
+    want = {(256, 1024): 785152, (512, 2048): 3143168, (1024, 4096): 12577792, (2048, 8192): 50321408}
+    for (nr, nth), n in want.items():
+        nv, ns = synth.shear_fom_sizes(nr, nth)
+        assert nv + ns == n
+    d = synth.make_shear_fom(256, 1024)
+    assert d["nv"] + d["ns"] == 785152
+
+
+def test_fom_operator_structure():
+    """About four entries per velocity row and two per stress row (Sec. 3.1):
+    interior velocity rows 4, radial-boundary rows 3 (free surface), axis
+    rows 0 (v = 0 there); s_rp rows 2 (0 on the axis), s_tp rows 2."""
+    nr, nth = 7, 9
+    d = synth.make_shear_fom(nr, nth)
+    nv = np.diff(d["Av"][0]).reshape(nr, nth)
+    assert np.all(nv[:, 0] == 0) and np.all(nv[:, -1] == 0)
+    assert np.all(nv[1:-1, 1:-1] == 4) and np.all(nv[0, 1:-1] == 3) and np.all(nv[-1, 1:-1] == 3)
+    ns = np.diff(d["As"][0])
+    nrp = (nr - 1) * nth
+    srp = ns[:nrp].reshape(nr - 1, nth)
+    assert np.all(srp[:, 0] == 0) and np.all(srp[:, -1] == 0) and np.all(srp[:, 1:-1] == 2)
+    assert np.all(ns[nrp:] == 2)
+    assert np.count_nonzero(d["f"]) == 1 and d["f"][d["src"]] == 1.0 / d["rho"]
+    assert d["src"] % nth == 1
+
+
+def _fom_consistency_errors(nr, nth):
+    """Max errors of As v and Av s against the continuous right-hand sides of
+    eq. (3.1) for smooth fields (v = sin(pi x) sin(2 th), s_rp = sin(pi x)
+    sin(th), s_tp = cos(pi x) sin(2 th), x = (r - r_cmb) / L), over interior
+    points (two cells away from the radial boundaries)."""
+    d = synth.make_shear_fom(nr, nth)
+    rc, L = d["r_cmb"], 6371e3 - d["r_cmb"]
+    dr, dth, rho, mu = d["dr"], d["dth"], d["rho"], d["rho"] * d["vs"] ** 2
+    Av = oracle.csr_dense(d["Av"], d["ns"])
+    As = oracle.csr_dense(d["As"], d["nv"])
+    k = math.pi / L
+    # velocity field on the velocity points
+    I, J = np.meshgrid(np.arange(nr), np.arange(nth), indexing="ij")
+    r, th = rc + I * dr, J * dth
+    v = np.sin(k * (r - rc)) * np.sin(2 * th)
+    Sv = As @ v.ravel()
+    nrp = (nr - 1) * nth
+    Ih, Jh = np.meshgrid(np.arange(nr - 1), np.arange(nth), indexing="ij")
+    rh, thh = rc + (Ih + 0.5) * dr, Jh * dth
+    want_rp = mu * (k * np.cos(k * (rh - rc)) * np.sin(2 * thh) - np.sin(k * (rh - rc)) * np.sin(2 * thh) / rh)
+    It, Jt = np.meshgrid(np.arange(nr), np.arange(nth - 1), indexing="ij")
+    rt, tht = rc + It * dr, (Jt + 0.5) * dth
+    want_tp = mu * (np.sin(k * (rt - rc)) * 2 * np.cos(2 * tht) / rt
+                    - np.cos(tht) / np.sin(tht) * np.sin(k * (rt - rc)) * np.sin(2 * tht) / rt)
+    e_rp = np.abs(Sv[:nrp].reshape(nr - 1, nth) - want_rp)[2:-2, 1:-1].max() / np.abs(want_rp).max()
+    e_tp = np.abs(Sv[nrp:].reshape(nr, nth - 1) - want_tp)[2:-2, :].max() / np.abs(want_tp).max()
+    # stress fields on their points
+    srp = np.sin(k * (rh - rc)) * np.sin(thh)
+    stp = np.cos(k * (rt - rc)) * np.sin(2 * tht)
+    Vs = Av @ np.concatenate([srp.ravel(), stp.ravel()])
+    s_rp = lambda rr, tt: np.sin(k * (rr - rc)) * np.sin(tt)
+    want_v = (k * np.cos(k * (r - rc)) * np.sin(th) + np.cos(k * (r - rc)) * 2 * np.cos(2 * th) / r
+              + (3 * s_rp(r, th) + 2 * np.cos(k * (r - rc)) * np.sin(2 * th) * np.cos(th) / np.sin(np.where(J > 0, th, 1.0))) / r) / rho
+    e_v = np.abs(Vs.reshape(nr, nth) - want_v)[2:-2, 1:-1].max() / np.abs(want_v[2:-2, 1:-1]).max()
+    return e_rp, e_tp, e_v
+
+
+def test_fom_operators_second_order_consistent():
+    """Halving the grid spacing cuts the truncation error of both operators
+    about fourfold (second-order centred differences, Sec. 3.1)."""
+    e1 = _fom_consistency_errors(17, 33)
+    e2 = _fom_consistency_errors(33, 65)
+    ratios = [a / b for a, b in zip(e1, e2)]
+    print("FOM consistency errors", e1, e2, "ratios", ratios)
+    assert all(3.5 < q < 4.5 for q in ratios), ratios
+    assert max(e2) < 1e-2
+
+
+def test_fom_rank1_columns_equal_rank2_bitwise():
+    d = synth.make_shear_fom(6, 10)
+    mu = synth.fom_periods(4, seed=3)
+    r2 = oracle.fom_run(d["Av"], d["As"], d["f"], d["dt"], mu, 300)
+    for m in (0, 3):
+        r1 = oracle.fom_run(d["Av"], d["As"], d["f"], d["dt"], mu[m:m + 1], 300)
+        assert np.array_equal(r1["V"][:, 0], r2["V"][:, m]) and np.array_equal(r1["S"][:, 0], r2["S"][:, m])
+
+
+def test_full_basis_rom_reproduces_fom():
+    """With orthonormal bases spanning the whole velocity and stress spaces,
+    the Galerkin ROM is the FOM in rotated coordinates: Phi_v V_rom equals
+    V_fom up to rounding.  This ties the FOM stepper, the projection and the
+    ROM oracle (separate code) together."""
+    d = synth.make_shear_fom(5, 7)
+    rng = np.random.default_rng(1)
+    Pv, _ = np.linalg.qr(rng.standard_normal((d["nv"], d["nv"])))
+    Ps, _ = np.linalg.qr(rng.standard_normal((d["ns"], d["ns"])))
+    Avs, Asv, b = oracle.project(d["Av"], d["As"], d["f"], Pv, Ps)
+    mu = synth.fom_periods(3, seed=2)
+    N = 200
+    rom = oracle.run_rank2(Avs, Asv, b, d["dt"], mu, N)
+    fom = oracle.fom_run(d["Av"], d["As"], d["f"], d["dt"], mu, N)
+    ev = np.linalg.norm(Pv @ rom["V"] - fom["V"]) / np.linalg.norm(fom["V"])
+    es = np.linalg.norm(Ps @ rom["S"] - fom["S"]) / np.linalg.norm(fom["S"])
+    print("full-basis ROM vs FOM: %.2e %.2e" % (ev, es))
+    assert ev < 1e-10 and es < 1e-10
+
+
+def test_projection_onto_coordinate_basis_is_submatrix():
+    d = synth.make_shear_fom(6, 9)
+    Av = oracle.csr_dense(d["Av"], d["ns"])
+    As = oracle.csr_dense(d["As"], d["nv"])
+    iv = np.array([3, 10, 11, 25, 40])
+    is_ = np.array([0, 7, 30, 31, 50, 60, 70])
+    Pv = np.eye(d["nv"])[:, iv]
+    Ps = np.eye(d["ns"])[:, is_]
+    Avs, Asv, b = oracle.project(d["Av"], d["As"], d["f"], Pv, Ps)
+    assert np.array_equal(Avs, Av[np.ix_(iv, is_)]) and np.array_equal(Asv, As[np.ix_(is_, iv)])
+    assert np.array_equal(b, d["f"][iv])
+
+
+def test_pod_recovers_a_constructed_spectrum():
+    """X = U diag(s) W^T with known orthonormal U, W: POD returns s and the
+    leading columns of U (up to sign); the energy criterion keeps the
+    smallest k whose energy fraction reaches 1 - tol."""
+    rng = np.random.default_rng(4)
+    N, ns = 400, 30
+    U, _ = np.linalg.qr(rng.standard_normal((N, ns)))
+    W, _ = np.linalg.qr(rng.standard_normal((ns, ns)))
+    s = 10.0 ** (-np.arange(ns, dtype=float) / 2.0)    # energies 10^-i
+    X = U @ np.diag(s) @ W.T
+    Phi, sig, k = oracle.pod(X, tol=3e-6)
+    assert np.allclose(sig, s, rtol=1e-9, atol=1e-14 * s[0])
+    # energy left out after k modes: sum_{i>=k} 10^-i / sum_i 10^-i = 10^-k
+    # (to 1e-30), which first falls to 3e-6 at k = 6
+    assert k == 6
+    G = Phi.T @ U[:, :k]
+    assert np.allclose(np.abs(np.diag(G)), 1.0, atol=1e-10)
+    # energies 16 and 9 of 25: one mode holds 0.64
+    assert oracle.pod_rank([4.0, 3.0], 0.36) == 1 and oracle.pod_rank([4.0, 3.0], 0.35) == 2
