@@ -440,6 +440,74 @@ rom_status rom_affine_create(const rom_config *cfg, int32_t Q, const double *Avs
 rom_status rom_affine_instance(rom_affine *A, const double *theta, double dt, void *stream, rom_ctx **out);
 rom_status rom_affine_destroy(rom_affine *A);
 
+/*
+ * Full-order model (FOM) and the offline stage (NEXT to the ROM path).
+ *
+ * The rank-2 FOM of the staggered system (Sec. 3, eq. (3.2)):
+ *   dV/dt = Av S + f u(t; mu)^T,   dS/dt = As V,
+ * with sparse Av (Nv x Ns) and As (Ns x Nv), stepped by the ROM's leapfrog
+ * (V first, then S with the new V; forcing at t_n = n dt).  FOM states are
+ * ROW-major, unlike ROM states: element (r, m) of an N x M state is at
+ * [r*M + m] (one degree of freedom's M samples contiguous).  FP64 only.
+ *
+ * rom_fom_create:
+ *   Nv, Ns          sizes of the velocity and stress spaces
+ *   av_ptr/col/val  host CSR of Av: row pointers (Nv + 1, starting at 0,
+ *                   non-decreasing), column indices (< Ns), FP64 values
+ *   as_ptr/col/val  host CSR of As (Ns rows, columns < Nv)
+ *   f               host, Nv FP64 source vector (the point source e_src / rho
+ *                   of Sec. 3.2; any vector is accepted)
+ *   dt              time step (> 0)
+ *   The arrays are copied (and the call synchronises `stream`); the host
+ *   arrays may be freed on return.  Errors: ROM_E_ARG (NULL, bad sizes, bad
+ *   CSR structure), ROM_E_NONFINITE, ROM_E_NOMEM, ROM_E_DEVICE.
+ * rom_fom_run: nsteps steps from step n0 of M samples: mu dev M FP64, V dev
+ *   Nv x M and S dev Ns x M FP64 row-major, updated in place.  Two kernel
+ *   launches per step, enqueued on `stream`.
+ * rom_fom_project: the Galerkin ROM operators of orthonormal bases
+ *   (Sec. 2.2, eq. (3.3)): Avs = Phi_v^T Av Phi_s (dev Kv x Ks, column-major:
+ *   the rom_create layout), Asv = Phi_s^T As Phi_v (dev Ks x Kv), b =
+ *   Phi_v^T f (dev Kv).  phi_v: dev Nv x Kv and phi_s: dev Ns x Ks, ROW-major
+ *   (the layout rom_pod writes).  Enqueued on `stream` (stream-ordered
+ *   scratch of (Nv Ks + Ns Kv) doubles plus split partials).
+ * rom_fom_destroy(NULL) is a no-op.
+ */
+typedef struct rom_fom rom_fom;
+rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const int32_t *av_col,
+                          const double *av_val, const int32_t *as_ptr, const int32_t *as_col,
+                          const double *as_val, const double *f, double dt, void *stream,
+                          rom_fom **out);
+rom_status rom_fom_run(rom_fom *F, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
+                       double *V, double *S, void *stream);
+rom_status rom_fom_project(rom_fom *F, int32_t kv, int32_t ks, const double *phi_v,
+                           const double *phi_s, double *Avs, double *Asv, double *b, void *stream);
+rom_status rom_fom_destroy(rom_fom *F);
+
+/*
+ * POD of a snapshot matrix (Sec. 4.4): the leading left singular vectors of
+ * X (dev n x ns FP64, ROW-major, one snapshot per column, n >= ns,
+ * ns <= 2048), kept to k columns: with tol >= 0 the smallest k whose
+ * singular values hold at least (1 - tol) of sum sigma_i^2, capped at kmax;
+ * with tol < 0, k = kmax (capped at the number of nonzero sigma).
+ *   phi     dev n x kmax FP64 ROW-major out: columns 0 .. k-1 the modes
+ *           (orthonormal), the rest zero
+ *   sigma   host ns FP64 out: all singular values, descending
+ *   k       host out: the number of modes kept
+ * Method: the Gram matrix X^T X (device) and its eigen-decomposition (host
+ * Jacobi) give the numerical rank r (eigenvalues above 100 ns u l_1, so
+ * modes with sigma_i / sigma_1 below about 1e-6 / sqrt(ns / 100) are never
+ * kept) and V_r; Y = X V_r is orthonormalised by two Cholesky QR passes
+ * (device products, host factors) into Q; the SVD of Q^T X (host Jacobi)
+ * gives sigma_0 .. sigma_{r-1} and the modes Q U (device).  sigma_i for
+ * i >= r is the square root of the Gram eigenvalue (inaccurate, and below
+ * the rank threshold).  Synchronises `stream`; allocates 2 n ns + 2 ns^2
+ * doubles plus split partials for the call.  Errors: ROM_E_ARG,
+ * ROM_E_NONFINITE (zero or non-finite X), ROM_E_UNSUPPORTED (the Cholesky
+ * QR of the dominant subspace failed), ROM_E_NOMEM, ROM_E_DEVICE.
+ */
+rom_status rom_pod(int64_t n, int32_t ns, const double *X, double tol, int32_t kmax, double *phi,
+                   double *sigma, int32_t *k, void *stream);
+
 /* Thread-local text describing the last non-OK status of this thread. */
 const char *rom_last_error(void);
 

@@ -5,12 +5,13 @@ The computation lives in the HIP library ``librom.so`` (C ABI declared in
 """
 from ._lib import RomError, load as load_library, LIB_PATH  # noqa: F401
 
-__all__ = ["RomError", "load_library", "LIB_PATH", "Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily"]
+__all__ = ["RomError", "load_library", "LIB_PATH", "Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily",
+           "Fom", "pod"]
 
 
 def __getattr__(name):
     # torch is imported lazily so the CPU-only ABI checks stay light
-    if name in ("Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily"):
+    if name in ("Rom", "RomQoI", "run_grouped", "GroupPlan", "AffineFamily", "Fom", "pod"):
         from . import rom
         return getattr(rom, name)
     raise AttributeError(name)

@@ -31,6 +31,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_
            "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
+           "rom_fom_create", "rom_fom_run", "rom_fom_project", "rom_fom_destroy", "rom_pod",
            "rom_last_error", "rom_version"]
 
 
@@ -94,6 +95,17 @@ def load():
         lib.rom_group_run.argtypes = [_vp, _i64, _i64, _vp]
         lib.rom_group_destroy.restype = C.c_int
         lib.rom_group_destroy.argtypes = [_vp]
+        _pi32 = C.POINTER(_i32)
+        lib.rom_fom_create.restype = C.c_int
+        lib.rom_fom_create.argtypes = [_i32, _i32, _pi32, _pi32, _pd, _pi32, _pi32, _pd, _pd, _d, _vp, C.POINTER(_vp)]
+        lib.rom_fom_run.restype = C.c_int
+        lib.rom_fom_run.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp]
+        lib.rom_fom_project.restype = C.c_int
+        lib.rom_fom_project.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+        lib.rom_fom_destroy.restype = C.c_int
+        lib.rom_fom_destroy.argtypes = [_vp]
+        lib.rom_pod.restype = C.c_int
+        lib.rom_pod.argtypes = [_i64, _i32, _vp, _d, _i32, _vp, _pd, _pi32, _vp]
         lib.rom_group_schedule.restype = _i32
         lib.rom_group_schedule.argtypes = [_vp]
         lib.rom_group_times.restype = C.c_int

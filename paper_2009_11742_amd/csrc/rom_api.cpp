@@ -37,6 +37,15 @@ rom_status hip_fail(hipError_t e, const char *where) {
     return ROM_E_DEVICE;
 }
 
+}  // namespace
+
+namespace rom {
+rom_status api_fail(rom_status s, const std::string &msg) { return fail(s, msg); }
+rom_status api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
+}  // namespace rom
+
+namespace {
+
 bool all_finite(const double *x, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!isfinite(x[i])) return false;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "rom.h"
@@ -181,6 +182,30 @@ int rank2_split_groups_per_launch(int kvp);
 // launch_rank2_split.
 hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
                                     int64_t n0, int64_t nsteps, hipStream_t st);
+
+// Full-order side.  A CSR operator on the device.
+struct FomCsr {
+    const int *ptr = nullptr, *col = nullptr;
+    const double *val = nullptr;
+    int nrows = 0;
+};
+// One FOM leapfrog step n (t_n = n dt) of M row-major samples:
+// V += dt (Av S + f u^T), then S += dt As V.
+hipError_t launch_fom_step(const FomCsr &Av, const FomCsr &As, const double *f, const double *mu, int M, int64_t n,
+                           double dt, double *V, double *S, hipStream_t st);
+// Y (rows x M, row-major) = A X (X row-major with M columns).
+hipError_t launch_fom_spmm(const FomCsr &A, const double *X, int M, double *Y, hipStream_t st);
+// C (K1 x K2 column-major) = P^T Q, P (N x K1) and Q (N x K2) row-major;
+// part holds gemm_tn_splits(N, K1, K2) K1 K2 doubles.
+int gemm_tn_splits(int64_t N, int K1, int K2);
+hipError_t launch_gemm_tn(const double *P, const double *Q, int64_t N, int K1, int K2, double *part, double *C,
+                          hipStream_t st);
+// Y (N x K2 row-major) = X (N x K1 row-major) B (K1 x K2 column-major).
+hipError_t launch_gemm_nn(const double *X, const double *B, int64_t N, int K1, int K2, double *Y, hipStream_t st);
+
+// Error reporting of the C-ABI (rom_last_error text), for the API sources.
+rom_status api_fail(rom_status s, const std::string &msg);
+rom_status api_hip_fail(hipError_t e, const char *where);
 
 // Affine operators: coefficients of up to kMaxAffine terms, by value.
 constexpr int kMaxAffine = 16;

@@ -389,3 +389,90 @@ class AffineFamily:
             self.close()
         except Exception:
             pass
+
+
+def _f64_dev(X, name, shape=None):
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or not X.is_cuda or not X.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 CUDA tensor" % name)
+    if shape is not None and tuple(X.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(X.shape)))
+    return X
+
+
+class Fom:
+    """Full-order model of the staggered system on the device (sparse Av,
+    As in CSR, source f, time step dt).  States are row-major torch tensors
+    (N x M, float64): ``zeros(M)`` makes a pair."""
+
+    def __init__(self, Av, As, f, dt, stream=None):
+        avp, avc, avv = (np.ascontiguousarray(Av[0], dtype=np.int32), np.ascontiguousarray(Av[1], dtype=np.int32),
+                         np.ascontiguousarray(Av[2], dtype=np.float64))
+        asp, asc, asv = (np.ascontiguousarray(As[0], dtype=np.int32), np.ascontiguousarray(As[1], dtype=np.int32),
+                         np.ascontiguousarray(As[2], dtype=np.float64))
+        self.nv, self.ns = avp.size - 1, asp.size - 1
+        ff = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(self.nv))
+        self.dt = float(dt)
+        pi = C.POINTER(C.c_int32)
+        pd = C.POINTER(C.c_double)
+        h = C.c_void_p()
+        check(_lib.load().rom_fom_create(self.nv, self.ns, avp.ctypes.data_as(pi), avc.ctypes.data_as(pi),
+                                         avv.ctypes.data_as(pd), asp.ctypes.data_as(pi), asc.ctypes.data_as(pi),
+                                         asv.ctypes.data_as(pd), ff.ctypes.data_as(pd), self.dt,
+                                         _stream_handle(stream), C.byref(h)))
+        self._h = h
+
+    def zeros(self, M, device="cuda"):
+        return (torch.zeros((self.nv, M), dtype=torch.float64, device=device),
+                torch.zeros((self.ns, M), dtype=torch.float64, device=device))
+
+    def run(self, mu, V, S, nsteps, n0=0, stream=None):
+        M = int(mu.numel())
+        _f64_dev(mu, "mu")
+        _f64_dev(V, "V", (self.nv, M))
+        _f64_dev(S, "S", (self.ns, M))
+        check(_lib.load().rom_fom_run(self._h, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
+                                      _stream_handle(stream)))
+
+    def project(self, phi_v, phi_s, stream=None):
+        """ROM operators of the row-major bases phi_v (Nv x Kv) and phi_s
+        (Ns x Ks): returns (Avs (Kv x Ks), Asv (Ks x Kv), b (Kv)) as float64
+        CUDA tensors (the operators column-major, i.e. transposed views)."""
+        _f64_dev(phi_v, "phi_v")
+        _f64_dev(phi_s, "phi_s")
+        if phi_v.shape[0] != self.nv or phi_s.shape[0] != self.ns:
+            raise ValueError("bases must have Nv and Ns rows")
+        kv, ks = int(phi_v.shape[1]), int(phi_s.shape[1])
+        Avs = torch.empty((ks, kv), dtype=torch.float64, device=phi_v.device)
+        Asv = torch.empty((kv, ks), dtype=torch.float64, device=phi_v.device)
+        b = torch.empty(kv, dtype=torch.float64, device=phi_v.device)
+        check(_lib.load().rom_fom_project(self._h, kv, ks, _ptr(phi_v), _ptr(phi_s), _ptr(Avs), _ptr(Asv), _ptr(b),
+                                          _stream_handle(stream)))
+        return Avs.t(), Asv.t(), b
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().rom_fom_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pod(X, tol=None, kmax=None, stream=None):
+    """POD modes of the row-major snapshot matrix X (n x ns float64 CUDA):
+    returns (Phi (n x k) float64 CUDA, sigma (ns,) numpy, k).  With tol the
+    energy criterion picks k (capped at kmax); without, k = kmax (default
+    ns)."""
+    _f64_dev(X, "X")
+    n, ns = int(X.shape[0]), int(X.shape[1])
+    kmax = ns if kmax is None else int(kmax)
+    phi = torch.empty((n, kmax), dtype=torch.float64, device=X.device)
+    sigma = np.zeros(ns)
+    k = C.c_int32(0)
+    check(_lib.load().rom_pod(n, ns, _ptr(X), -1.0 if tol is None else float(tol), kmax, _ptr(phi),
+                              sigma.ctypes.data_as(C.POINTER(C.c_double)), C.byref(k), _stream_handle(stream)))
+    kk = int(k.value)
+    return (phi if kk == kmax else phi[:, :kk].contiguous()), sigma, kk

@@ -224,3 +224,38 @@ def test_affine_rejects_bad_arguments():
     th = np.ones(2)
     assert lib.rom_affine_instance(None, th.ctypes.data_as(pd), 0.0, None, C.byref(out)) == E
     assert lib.rom_affine_destroy(None) == _lib.ROM_OK
+
+
+def test_fom_and_pod_reject_bad_arguments():
+    lib = _lib.load()
+    pi = C.POINTER(C.c_int32)
+    pd = C.POINTER(C.c_double)
+    out = C.c_void_p(7)
+    ptr = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([0, 1], dtype=np.int32)
+    val = np.array([1.0, 2.0])
+    f = np.zeros(2)
+    E = _lib.ROM_E_ARG
+
+    def create(nv, ns, ap, ac, av, sp, sc, sv, ff, dt):
+        return lib.rom_fom_create(nv, ns, ap.ctypes.data_as(pi), ac.ctypes.data_as(pi), av.ctypes.data_as(pd),
+                                  sp.ctypes.data_as(pi), sc.ctypes.data_as(pi), sv.ctypes.data_as(pd),
+                                  ff.ctypes.data_as(pd), dt, None, C.byref(out))
+    assert create(0, 2, ptr, col, val, ptr, col, val, f, 0.1) == E and not out.value
+    assert create(2, 2, ptr, col, val, ptr, col, val, f, 0.0) == E
+    bad = np.array([0, 2, 1], dtype=np.int32)                 # decreasing row pointer
+    assert create(2, 2, bad, col, val, ptr, col, val, f, 0.1) == E
+    badc = np.array([0, 5], dtype=np.int32)                   # column out of range
+    assert create(2, 2, ptr, badc, val, ptr, col, val, f, 0.1) == E
+    nanv = np.array([1.0, np.nan])
+    assert create(2, 2, ptr, col, nanv, ptr, col, val, f, 0.1) == _lib.ROM_E_NONFINITE
+    assert lib.rom_fom_run(None, 1, None, 0, 1, None, None, None) == E
+    assert lib.rom_fom_project(None, 1, 1, None, None, None, None, None, None) == E
+    assert lib.rom_fom_destroy(None) == _lib.ROM_OK
+    k = C.c_int32(5)
+    sig = np.zeros(4)
+    assert lib.rom_pod(10, 4, None, 0.0, 2, None, sig.ctypes.data_as(pd), C.byref(k), None) == E and k.value == 0
+    X = C.c_void_p(16)   # never dereferenced: the arguments are rejected first
+    assert lib.rom_pod(3, 4, X, 0.0, 2, X, sig.ctypes.data_as(pd), C.byref(k), None) == E      # n < ns
+    assert lib.rom_pod(10, 4, X, 0.0, 5, X, sig.ctypes.data_as(pd), C.byref(k), None) == E     # kmax > ns
+    assert lib.rom_pod(10, 4, X, 1.0, 2, X, sig.ctypes.data_as(pd), C.byref(k), None) == E     # tol >= 1
