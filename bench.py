@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -506,9 +506,92 @@ def workload_rank3(args, torch, dev):
             "assembly_ms_per_instance": t_asm * 1e3}
 
 
+def _fom_bytes(d, M):
+    """Algorithmic HBM bytes of one FOM step (FP64): both CSR operators once,
+    per half-step the updated state read and written and the other state
+    read once, and the source vector."""
+    nzv, nzs = int(d["Av"][0][-1]), int(d["As"][0][-1])
+    a = 4 * (d["nv"] + 1) + 12 * nzv + 4 * (d["ns"] + 1) + 12 * nzs
+    return a + 8 * M * (3 * d["nv"] + 3 * d["ns"]) + 8 * d["nv"]
+
+
+def workload_fom(args, torch, dev):
+    """Rank-2 FOM stepping (the contrast workload: sparse, bandwidth-bound):
+    velocity grids 256 x 1024 and 512 x 2048 (785,152 and 3,143,168 DOF),
+    M in {1, 4, 16, 48} forcing periods, dt = 0.05 s (Appendix A), 200 timed
+    steps.  Reports per point the step time, sample-steps/s, algorithmic
+    GB/s against the 8 TB/s HBM peak, and the rank-2 gain
+    s(M) = M t(1) / t(M) of Appendix B."""
+    import synth
+    from paper_2009_11742_amd import Fom
+    N = 200
+    out = {"workload": "fom: shear-wave FOM, grids 256x1024 and 512x2048, M in {1,4,16,48}, dt 0.05, 200 steps",
+           "unit": "sample-steps/s", "hbm_peak_GBps": 8000.0, "points": []}
+    for nr, nth in ((256, 1024), (512, 2048)):
+        d = synth.make_shear_fom(nr, nth, dt=0.05)
+        F = Fom(d["Av"], d["As"], d["f"], d["dt"])
+        t1 = None
+        for M in (1, 4, 16, 48):
+            mu = torch.tensor(synth.fom_periods(M, seed=M), dtype=torch.float64, device=dev)
+            V, S = F.zeros(M, device=dev)
+
+            def run():
+                F.run(mu, V, S, N)
+            _, ms = _events_time(torch, run, 3, 1)
+            t = float(np.median(ms)) * 1e-3 / N
+            t1 = t if M == 1 else t1
+            gbs = _fom_bytes(d, M) / t / 1e9
+            out["points"].append({"grid": "%dx%d" % (nr, nth), "dof": d["nv"] + d["ns"], "M": M,
+                                  "us_per_step": t * 1e6, "value": M / t, "GBps": gbs, "frac_hbm": gbs / 8000.0,
+                                  "rank2_gain": M * t1 / t})
+        F.close()
+    return out
+
+
+def workload_offline(args, torch, dev):
+    """Offline stage on the 256 x 1024 grid: 256 FOM snapshots (8 periods x
+    32 snapshots, every 10th step at the CFL time step), POD of the velocity
+    and stress snapshot matrices (energy 1e-10), Galerkin projection onto the
+    resulting bases.  Reports times and the ranks."""
+    import synth
+    from paper_2009_11742_amd import Fom, pod
+    d = synth.make_shear_fom(256, 1024)
+    F = Fom(d["Av"], d["As"], d["f"], d["dt"])
+    M, nsnap, every = 8, 32, 10
+    mu = torch.tensor(synth.fom_periods(M, seed=0), dtype=torch.float64, device=dev)
+    V, S = F.zeros(M, device=dev)
+    XV = torch.empty((d["nv"], M * nsnap), dtype=torch.float64, device=dev)
+    XS = torch.empty((d["ns"], M * nsnap), dtype=torch.float64, device=dev)
+    for c in range(nsnap):
+        F.run(mu, V, S, every, n0=c * every)
+        XV[:, c * M:(c + 1) * M] = V
+        XS[:, c * M:(c + 1) * M] = S
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Pv, sv, kv = pod(XV, tol=1e-10)
+    t1 = time.perf_counter()
+    Ps, ss, ks = pod(XS, tol=1e-10)
+    t2 = time.perf_counter()
+    Pv2, _, _ = pod(XV, tol=1e-10)                    # second call: warm
+    t3 = time.perf_counter()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    F.project(Pv, Ps)                                 # warm-up
+    ev[0].record()
+    for _ in range(3):
+        F.project(Pv, Ps)
+    ev[1].record()
+    torch.cuda.synchronize()
+    F.close()
+    return {"workload": "offline: 256x1024 grid, 256 snapshots, POD (energy 1e-10) + Galerkin projection",
+            "kv": kv, "ks": ks, "pod_velocity_ms": (t1 - t0) * 1e3, "pod_stress_ms": (t2 - t1) * 1e3,
+            "pod_velocity_warm_ms": (t3 - t2) * 1e3, "project_ms": ev[0].elapsed_time(ev[1]) / 3,
+            "sigma_ratio_kept": float(sv[kv - 1] / sv[0])}
+
+
 OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
          "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain,
-         "receivers": workload_receivers, "rank3": workload_rank3}
+         "receivers": workload_receivers, "rank3": workload_rank3, "fom": workload_fom,
+         "offline": workload_offline}
 
 
 if __name__ == "__main__":
