@@ -53,15 +53,15 @@ def _load():
             lib.orc_ricker_dmu.restype = _d
             lib.orc_ricker_dmu.argtypes = [_d, _d]
             lib.orc_step_rank1.restype = None
-            lib.orc_step_rank1.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i64, _d, _pd, _pd]
+            lib.orc_step_rank1.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i64, _d, _pd, _pd, _i]
             lib.orc_run_rank2.restype = _i
             lib.orc_run_rank2.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i, _pd, _i64, _i64,
-                                          _pd, _pd, _pd, _pd, _pd]
+                                          _pd, _pd, _pd, _pd, _pd, _i]
             lib.orc_energy.restype = None
             lib.orc_energy.argtypes = [_i, _i, _pd, _d, _i, _pd, _pd, _pd]
             lib.orc_adjoint.restype = _i
             lib.orc_adjoint.argtypes = [_i, _i, _pd, _pd, _pd, _d, _i, _pd, _i64, _pd,
-                                        _pd, _pd, _pd, _pd, _pd, _pd, _i64]
+                                        _pd, _pd, _pd, _pd, _pd, _pd, _i64, _i]
             lib.orc_num_threads.restype = _i
             lib.orc_num_threads.argtypes = []
             lib.orc_round_bf16.restype = _d
@@ -71,7 +71,11 @@ def _load():
             _pi = C.POINTER(C.c_int32)
             lib.orc_fom_run.restype = _i
             lib.orc_fom_run.argtypes = [_i, _i, _pi, _pi, _pd, _pi, _pi, _pd, _pd, _d, _i, _pd, _i64, _i64,
-                                        _pd, _pd]
+                                        _pd, _pd, _i]
+            lib.orc_gauss1.restype = _d
+            lib.orc_gauss1.argtypes = [_d, _d]
+            lib.orc_gauss1_dmu.restype = _d
+            lib.orc_gauss1_dmu.argtypes = [_d, _d]
             _lib = lib
     return _lib
 
@@ -92,6 +96,29 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+SOURCES = {"ricker": 0, "gauss1": 1}
+
+
+def _src(source):
+    """Source kind: 'ricker' (0) or 'gauss1' (1, first derivative of a
+    Gaussian); see rom_oracle.c for both signals."""
+    if isinstance(source, str):
+        return SOURCES[source]
+    if int(source) not in (0, 1):
+        raise ValueError("source must be 'ricker' or 'gauss1'")
+    return int(source)
+
+
+def gauss1(t, mu):
+    lib = _load()
+    return np.vectorize(lambda tt, mm: lib.orc_gauss1(float(tt), float(mm)))(t, mu)
+
+
+def gauss1_dmu(t, mu):
+    lib = _load()
+    return np.vectorize(lambda tt, mm: lib.orc_gauss1_dmu(float(tt), float(mm)))(t, mu)
+
+
 def ricker(t, mu):
     lib = _load()
     return np.vectorize(lambda tt, mm: lib.orc_ricker(float(tt), float(mm)))(t, mu)
@@ -102,7 +129,7 @@ def ricker_dmu(t, mu):
     return np.vectorize(lambda tt, mm: lib.orc_ricker_dmu(float(tt), float(mm)))(t, mu)
 
 
-def step_rank1(Avs, Asv, b, dt, n, mu, v, s):
+def step_rank1(Avs, Asv, b, dt, n, mu, v, s, source="ricker"):
     """One rank-1 leapfrog step of one sample; returns new (v, s)."""
     Avs = _f64(Avs); Asv = _f64(Asv)
     kv, ks = Avs.shape
@@ -111,11 +138,11 @@ def step_rank1(Avs, Asv, b, dt, n, mu, v, s):
     v = np.array(v, dtype=np.float64).reshape(kv).copy()
     s = np.array(s, dtype=np.float64).reshape(ks).copy()
     _load().orc_step_rank1(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), int(n), float(mu),
-                           _p(v), _p(s))
+                           _p(v), _p(s), _src(source))
     return v, s
 
 
-def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=False):
+def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=False, source="ricker"):
     """Integrate ``nsteps`` steps from step index ``n0``.
 
     Returns a dict with V, S (Kv x M / Ks x M, Fortran order) and, when a probe
@@ -135,7 +162,7 @@ def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=F
     J = np.zeros(M) if cc is not None else None
     y = np.zeros((int(nsteps), M)) if (cc is not None and trace) else None
     rc = _load().orc_run_rank2(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), M, _p(mu), int(n0),
-                               int(nsteps), _p(V), _p(S), _p(cc), _p(J), _p(y))
+                               int(nsteps), _p(V), _p(S), _p(cc), _p(J), _p(y), _src(source))
     if rc != 0:
         raise MemoryError("oracle run failed")
     out = {"V": V, "S": S}
@@ -146,7 +173,7 @@ def run_rank2(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, c=None, trace=F
     return out
 
 
-def receivers(Avs, Asv, b, dt, mu, nsteps, C, V=None, S=None, n0=0):
+def receivers(Avs, Asv, b, dt, mu, nsteps, C, V=None, S=None, n0=0, source="ricker"):
     """Seismograms at R receivers (the reconstruction of the velocity at
     target points from single rows of the velocity basis, Sec. 4.5):
     Y[k, r, m] = C[r] . V_m after step n0 + k, for k = 0 .. nsteps - 1.
@@ -165,7 +192,7 @@ def receivers(Avs, Asv, b, dt, mu, nsteps, C, V=None, S=None, n0=0):
     S = np.zeros((ks, M), order="F") if S is None else np.array(S, dtype=np.float64, order="F", copy=True)
     Y = np.zeros((int(nsteps), R, M))
     for k in range(int(nsteps)):
-        out = run_rank2(Avs, Asv, b, dt, mu, 1, V=V, S=S, n0=n0 + k)
+        out = run_rank2(Avs, Asv, b, dt, mu, 1, V=V, S=S, n0=n0 + k, source=source)
         V, S = out["V"], out["S"]
         for r in range(R):
             for m in range(M):
@@ -199,7 +226,7 @@ def _csr3(A):
             np.ascontiguousarray(val, dtype=np.float64))
 
 
-def fom_run(Av, As, f, dt, mu, nsteps, V=None, S=None, n0=0):
+def fom_run(Av, As, f, dt, mu, nsteps, V=None, S=None, n0=0, source="ricker"):
     """Rank-2 full-order model of the staggered system (Sec. 3, eq. (3.2)),
     leapfrog as for the ROM.  Av (Nv x Ns) and As (Ns x Nv) are CSR triples
     (ptr, col, val); f the Nv source vector; states row-major (N x M, one
@@ -216,7 +243,7 @@ def fom_run(Av, As, f, dt, mu, nsteps, V=None, S=None, n0=0):
     pi = C.POINTER(C.c_int32)
     rc = _load().orc_fom_run(nv, ns, avp.ctypes.data_as(pi), avc.ctypes.data_as(pi), _p(avv),
                              asp.ctypes.data_as(pi), asc.ctypes.data_as(pi), _p(asv), _p(f), float(dt), M,
-                             _p(mu), int(n0), int(nsteps), _p(V), _p(S))
+                             _p(mu), int(n0), int(nsteps), _p(V), _p(S), _src(source))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return {"V": V, "S": S}
@@ -306,7 +333,7 @@ def energy(Avs, dt, V, S):
     return E
 
 
-def adjoint(Avs, Asv, b, dt, mu, nsteps, c, V0=None, S0=None, stride=0):
+def adjoint(Avs, Asv, b, dt, mu, nsteps, c, V0=None, S0=None, stride=0, source="ricker"):
     """J and its partial gradients w.r.t. Avs, Asv and mu (discrete adjoint)."""
     Avs = _f64(Avs); Asv = _f64(Asv)
     kv, ks = Avs.shape
@@ -319,7 +346,8 @@ def adjoint(Avs, Asv, b, dt, mu, nsteps, c, V0=None, S0=None, stride=0):
     J = np.zeros(M); dmu = np.zeros(M)
     dAvs = np.zeros((kv, ks), order="F"); dAsv = np.zeros((ks, kv), order="F")
     rc = _load().orc_adjoint(kv, ks, _p(Avs), _p(Asv), _p(b), float(dt), M, _p(mu), int(nsteps),
-                             _p(c), _p(V0), _p(S0), _p(J), _p(dAvs), _p(dAsv), _p(dmu), int(stride))
+                             _p(c), _p(V0), _p(S0), _p(J), _p(dAvs), _p(dAsv), _p(dmu), int(stride),
+                             _src(source))
     if rc != 0:
         raise MemoryError("oracle adjoint failed")
     return {"J": J, "dAvs": dAvs, "dAsv": dAsv, "dmu": dmu}

@@ -61,14 +61,43 @@ double orc_ricker_dmu(double t, double mu)
     return (2.0 * a - 3.0) * exp(-a) * (2.0 * M_PI * M_PI * t * x);
 }
 
+/* The paper's second signal (Sec. 3.2; the source of its FOM scaling runs,
+ * Appendix A): the first derivative of a Gaussian, no formula given.  Read
+ * here with the period T = 1/mu and the delay 3T of Appendix A, unit peak:
+ *   u = -sqrt(2e) x exp(-x^2),   x = pi (mu t - 3)
+ * (the time derivative of exp(-x^2), scaled so that max |u| = 1). */
+double orc_gauss1(double t, double mu)
+{
+    double x = M_PI * (mu * t - 3.0);
+    return -sqrt(2.0 * exp(1.0)) * x * exp(-x * x);
+}
+
+/* d u / d mu of the above (the delay 3/mu moves with mu): dx/dmu = pi t */
+double orc_gauss1_dmu(double t, double mu)
+{
+    double x = M_PI * (mu * t - 3.0);
+    return -sqrt(2.0 * exp(1.0)) * (1.0 - 2.0 * x * x) * exp(-x * x) * (M_PI * t);
+}
+
+/* Signal of source kind src (0: Ricker, 1: Gaussian derivative). */
+static double src_u(int src, double t, double mu)
+{
+    return src == 1 ? orc_gauss1(t, mu) : orc_ricker(t, mu);
+}
+
+static double src_dmu(int src, double t, double mu)
+{
+    return src == 1 ? orc_gauss1_dmu(t, mu) : orc_ricker_dmu(t, mu);
+}
+
 /* ---- rank-1 (Sec. 2.2 eq. (2.3), M = 1): one trajectory, two GEMVs ------- */
 
 /* One leapfrog step at t_n = n*dt for a single sample. v (Kv), s (Ks) in/out. */
 void orc_step_rank1(int kv, int ks, const double *Avs, const double *Asv,
                     const double *b, double dt, int64_t n, double mu,
-                    double *v, double *s)
+                    double *v, double *s, int src)
 {
-    double u = orc_ricker((double)n * dt, mu);
+    double u = src_u(src, (double)n * dt, mu);
     for (int i = 0; i < kv; ++i) {
         double r = 0.0;
         for (int j = 0; j < ks; ++j) r = r + Avs[i + (int64_t)j * kv] * s[j];
@@ -87,7 +116,7 @@ void orc_step_rank1(int kv, int ks, const double *Avs, const double *Asv,
  * R is scratch of max(Kv, Ks) * M doubles. */
 static void rank2_step(int kv, int ks, const double *Avs, const double *Asv,
                        const double *b, double dt, int M, const double *mu,
-                       int64_t n, double *V, double *S, double *R)
+                       int64_t n, double *V, double *S, double *R, int src)
 {
     double t = (double)n * dt;
     /* R = Avs * S  (Kv x M) */
@@ -99,7 +128,7 @@ static void rank2_step(int kv, int ks, const double *Avs, const double *Asv,
                 r = r + Avs[i + (int64_t)j * kv] * S[j + (int64_t)m * ks];
             R[i + (int64_t)m * kv] = r;
         }
-        double u = orc_ricker(t, mu[m]);
+        double u = src_u(src, t, mu[m]);
         for (int i = 0; i < kv; ++i)
             V[i + (int64_t)m * kv] = V[i + (int64_t)m * kv] + dt * (R[i + (int64_t)m * kv] + b[i] * u);
     }
@@ -136,7 +165,7 @@ static void probe(int kv, int M, const double *c, const double *V, double *y)
 int orc_run_rank2(int kv, int ks, const double *Avs, const double *Asv,
                   const double *b, double dt, int M, const double *mu,
                   int64_t n0, int64_t nsteps, double *V, double *S,
-                  const double *c, double *J, double *ytrace)
+                  const double *c, double *J, double *ytrace, int src)
 {
     int kmax = kv > ks ? kv : ks;
     double *R = (double *)malloc(sizeof(double) * (size_t)kmax * (size_t)(M > 0 ? M : 1));
@@ -144,7 +173,7 @@ int orc_run_rank2(int kv, int ks, const double *Avs, const double *Asv,
     if (!R || !y) { free(R); free(y); return -1; }
     for (int64_t k = 0; k < nsteps; ++k) {
         int64_t n = n0 + k;
-        rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, n, V, S, R);
+        rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, n, V, S, R, src);
         if (c) {
             probe(kv, M, c, V, y);
             for (int m = 0; m < M; ++m) {
@@ -204,7 +233,7 @@ int orc_adjoint(int kv, int ks, const double *Avs, const double *Asv,
                 const double *b, double dt, int M, const double *mu,
                 int64_t nsteps, const double *c, const double *V0,
                 const double *S0, double *J, double *dAvs, double *dAsv,
-                double *dmu, int64_t stride)
+                double *dmu, int64_t stride, int src)
 {
     if (nsteps < 0 || M < 0 || kv <= 0 || ks <= 0) return -1;
     if (stride <= 0) {
@@ -242,7 +271,7 @@ int orc_adjoint(int kv, int ks, const double *Avs, const double *Asv,
             memcpy(ckV + (size_t)(n / stride) * vsz, V, vsz * sizeof(double));
             memcpy(ckS + (size_t)(n / stride) * ssz, S, ssz * sizeof(double));
         }
-        rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, n, V, S, R);
+        rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, n, V, S, R, src);
         probe(kv, M, c, V, y);
         for (int m = 0; m < M; ++m) J[m] = J[m] + dt * (y[m] * y[m]);
     }
@@ -257,7 +286,7 @@ int orc_adjoint(int kv, int ks, const double *Avs, const double *Asv,
         memcpy(V, segV, vsz * sizeof(double));
         memcpy(S, segS, ssz * sizeof(double));
         for (int64_t k = 0; k < len; ++k) {
-            rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, nb + k, V, S, R);
+            rank2_step(kv, ks, Avs, Asv, b, dt, M, mu, nb + k, V, S, R, src);
             memcpy(segV + (size_t)(k + 1) * vsz, V, vsz * sizeof(double));
             memcpy(segS + (size_t)(k + 1) * ssz, S, ssz * sizeof(double));
         }
@@ -301,7 +330,7 @@ int orc_adjoint(int kv, int ks, const double *Avs, const double *Asv,
             for (int m = 0; m < M; ++m) {
                 double bw = 0.0;
                 for (int i = 0; i < kv; ++i) bw = bw + b[i] * W[i + (int64_t)m * kv];
-                dmu[m] = dmu[m] + dt * bw * orc_ricker_dmu(t, mu[m]);
+                dmu[m] = dmu[m] + dt * bw * src_dmu(src, t, mu[m]);
                 for (int i = 0; i < kv; ++i) P[i + (int64_t)m * kv] = W[i + (int64_t)m * kv];
                 for (int j = 0; j < ks; ++j) {
                     double r = 0.0;
@@ -428,13 +457,13 @@ static void csr_update(int nrows, const int *ptr, const int *col, const double *
 int orc_fom_run(int nv, int ns, const int *avp, const int *avc, const double *avv,
                 const int *asp, const int *asc, const double *asv, const double *f,
                 double dt, int M, const double *mu, int64_t n0, int64_t nsteps,
-                double *V, double *S)
+                double *V, double *S, int src)
 {
     double *u = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
     if (!u) return 1;
     for (int64_t k = 0; k < nsteps; ++k) {
         const double t = (double)(n0 + k) * dt;
-        for (int m = 0; m < M; ++m) u[m] = orc_ricker(t, mu[m]);
+        for (int m = 0; m < M; ++m) u[m] = src_u(src, t, mu[m]);
         csr_update(nv, avp, avc, avv, S, M, f, u, dt, V);
         csr_update(ns, asp, asc, asv, V, M, NULL, u, dt, S);
     }

@@ -655,3 +655,49 @@ def test_pod_recovers_a_constructed_spectrum():
     assert np.allclose(np.abs(np.diag(G)), 1.0, atol=1e-10)
     # energies 16 and 9 of 25: one mode holds 0.64
     assert oracle.pod_rank([4.0, 3.0], 0.36) == 1 and oracle.pod_rank([4.0, 3.0], 0.35) == 2
+
+
+# ---- the second source signal: first derivative of a Gaussian
+
+@pytest.mark.parametrize("mu", [1.0 / 60.0, 0.7])
+def test_gauss1_shape(mu):
+    """Unit peak at x = -1/sqrt(2) (t = (3 - 1/(sqrt(2) pi)) / mu), zero at the
+    delay 3/mu, odd about it, and proportional to the time derivative of the
+    Gaussian exp(-(pi (mu t - 3))^2) (central differences of that bump)."""
+    t0 = 3.0 / mu
+    tp = (3.0 - 1.0 / (math.sqrt(2.0) * math.pi)) / mu
+    assert abs(float(oracle.gauss1(tp, mu)) - 1.0) < 1e-14
+    assert abs(float(oracle.gauss1(t0, mu))) < 1e-13       # t0 = 3 / mu rounds
+    ts = np.linspace(0.0, 2 * t0, 801)
+    u = oracle.gauss1(ts, mu)
+    assert np.max(np.abs(u)) <= 1.0 + 1e-14
+    assert np.allclose(oracle.gauss1(t0 + (ts - t0), mu), -oracle.gauss1(t0 - (ts - t0), mu), atol=1e-13)
+    h = 1e-4 / mu
+    bump = lambda t: np.exp(-(math.pi * (mu * t - 3.0)) ** 2)
+    d = (bump(ts + h) - bump(ts - h)) / (2 * h)
+    scale = math.sqrt(2.0 * math.e) / (2.0 * math.pi * mu)
+    assert np.max(np.abs(u - scale * d)) < 1e-7
+
+
+@pytest.mark.parametrize("t,mu", [(100.0, 1.0 / 65.0), (3.0, 0.9), (5.0, 0.55)])
+def test_gauss1_dmu_matches_fd(t, mu):
+    h = 1e-6 * mu
+    fd = (float(oracle.gauss1(t, mu + h)) - float(oracle.gauss1(t, mu - h))) / (2 * h)
+    assert abs(float(oracle.gauss1_dmu(t, mu)) - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_source_kind_reaches_the_step():
+    """With zero operators the leapfrog only accumulates the forcing:
+    V_N = dt sum_n b u(t_n), S stays 0 -- for each source kind."""
+    kv, ks, M, N, dt = 3, 2, 4, 300, 0.01
+    b = np.array([1.0, -2.0, 0.5])
+    mu = np.array([0.6, 0.7, 0.8, 0.95])
+    Z1, Z2 = np.zeros((kv, ks), order="F"), np.zeros((ks, kv), order="F")
+    for src, fn in (("ricker", oracle.ricker), ("gauss1", oracle.gauss1)):
+        r = oracle.run_rank2(Z1, Z2, b, dt, mu, N, source=src)
+        t = np.arange(N) * dt
+        want = dt * np.outer(b, [np.sum(fn(t, m)) for m in mu])
+        assert np.allclose(r["V"], want, rtol=1e-12, atol=1e-15) and not np.any(r["S"])
+    a = oracle.run_rank2(Z1, Z2, b, dt, mu, N, source="ricker")["V"]
+    g = oracle.run_rank2(Z1, Z2, b, dt, mu, N, source="gauss1")["V"]
+    assert np.max(np.abs(a - g)) > 1e-3
