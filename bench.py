@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the rank-2 kernel at this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy
 # (factors 2.0 and 1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha1": "e9c1d43c74ab4d36a017040a689cd0afcb3a5483", "bytes": 5.512e6}
+MEASURED_TRAFFIC = {"sources_sha1": "39b7c1d9d7734bdf94433c3175deefc153b846b3", "bytes": 5.514e6}
 KERNEL_SOURCES = ("paper_2009_11742_amd/csrc/k_rank2_f32.hip", "paper_2009_11742_amd/csrc/k_tile_f32.h",
                   "paper_2009_11742_amd/csrc/k_common.h")
 

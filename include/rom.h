@@ -94,11 +94,17 @@ enum {
                                wherever they apply: Kv == Ks in {256, 512,
                                1024}, ceil(M/64) * K/64 <= 256, a 256-CU
                                gfx950; else 4-column blocks                   */
-    ROM_SCHED_COLUMNS8 = 8u /* FP32 operators and states: 8-column blocks
+    ROM_SCHED_COLUMNS8 = 8u,/* FP32 operators and states: 8-column blocks
                                (two column sets per operator fragment) where
                                the states of 8 samples fit in LDS; else 4.
                                At most one ROM_SCHED_* flag; none: the
                                schedule autotuner decides (rom_last_schedule)*/
+    ROM_SOURCE_GAUSS1 = 16u /* source signal: the first derivative of a
+                               Gaussian (Sec. 3.2), period 1/mu, delay 3/mu,
+                               unit peak: u = -sqrt(2e) x exp(-x^2),
+                               x = pi (mu t - 3); default: the Ricker wavelet
+                               (1 - 2a) exp(-a), a = pi^2 (mu t - 1.5)^2.  The
+                               adjoint's dJ/dmu differentiates the chosen one */
 };
 
 typedef struct {
@@ -458,6 +464,7 @@ rom_status rom_affine_destroy(rom_affine *A);
  *   f               host, Nv FP64 source vector (the point source e_src / rho
  *                   of Sec. 3.2; any vector is accepted)
  *   dt              time step (> 0)
+ *   flags           0 (Ricker source) or ROM_SOURCE_GAUSS1
  *   The arrays are copied (and the call synchronises `stream`); the host
  *   arrays may be freed on return.  Errors: ROM_E_ARG (NULL, bad sizes, bad
  *   CSR structure), ROM_E_NONFINITE, ROM_E_NOMEM, ROM_E_DEVICE.
@@ -475,8 +482,8 @@ rom_status rom_affine_destroy(rom_affine *A);
 typedef struct rom_fom rom_fom;
 rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const int32_t *av_col,
                           const double *av_val, const int32_t *as_ptr, const int32_t *as_col,
-                          const double *as_val, const double *f, double dt, void *stream,
-                          rom_fom **out);
+                          const double *as_val, const double *f, double dt, uint32_t flags,
+                          void *stream, rom_fom **out);
 rom_status rom_fom_run(rom_fom *F, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
                        double *V, double *S, void *stream);
 rom_status rom_fom_project(rom_fom *F, int32_t kv, int32_t ks, const double *phi_v,

@@ -21,6 +21,7 @@ ROM_SKEW_CHECK = 1
 ROM_SCHED_COLUMNS = 2
 ROM_SCHED_ROWSPLIT = 4
 ROM_SCHED_COLUMNS8 = 8
+ROM_SOURCE_GAUSS1 = 16
 ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8 = range(3)
 ROM_NSCHEDULES = 3
 
@@ -97,7 +98,8 @@ def load():
         lib.rom_group_destroy.argtypes = [_vp]
         _pi32 = C.POINTER(_i32)
         lib.rom_fom_create.restype = C.c_int
-        lib.rom_fom_create.argtypes = [_i32, _i32, _pi32, _pi32, _pd, _pi32, _pi32, _pd, _pd, _d, _vp, C.POINTER(_vp)]
+        lib.rom_fom_create.argtypes = [_i32, _i32, _pi32, _pi32, _pd, _pi32, _pi32, _pd, _pd, _d, C.c_uint32, _vp,
+                                       C.POINTER(_vp)]
         lib.rom_fom_run.restype = C.c_int
         lib.rom_fom_run.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp]
         lib.rom_fom_project.restype = C.c_int

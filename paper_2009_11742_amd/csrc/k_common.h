@@ -38,6 +38,45 @@ __device__ __forceinline__ double ricker_dmu(double t, double mu) {
     return (2.0 * a - 3.0) * exp(-a) * (2.0 * pi * pi * t * x);
 }
 
+// First derivative of a Gaussian, the second source signal (Sec. 3.2; the
+// appendix's FOM runs use it), with period 1/mu and delay 3/mu, unit peak:
+// u = -sqrt(2e) x exp(-x^2), x = pi (mu t - 3).
+__device__ __forceinline__ double gauss1(double t, double mu) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const double s2e = 2.331643981597124;      // sqrt(2 e)
+    const double x = pi * (mu * t - 3.0);
+    return -s2e * x * exp(-x * x);
+}
+
+// d u / d mu of gauss1 (the delay moves with mu): dx/dmu = pi t.
+__device__ __forceinline__ double gauss1_dmu(double t, double mu) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const double s2e = 2.331643981597124;
+    const double x = pi * (mu * t - 3.0);
+    return -s2e * (1.0 - 2.0 * x * x) * exp(-x * x) * (pi * t);
+}
+
+// Source kinds (rom_config.flags ROM_SOURCE_GAUSS1 selects the second).
+enum Source { kRicker = 0, kGauss1 = 1 };
+
+// Both signals are a polynomial times exp(-x^2) in x = pi (mu t - d):
+// Ricker d = 1.5, (1 - 2 x^2); gauss1 d = 3, -sqrt(2e) x.  One expression
+// with the coefficients chosen per kind (scalar selects, a single exp) gives
+// each signal exactly as ricker() and gauss1() above compute it: the zero
+// coefficients add exact zeros.
+__device__ __forceinline__ double forcing(int src, double t, double mu) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const bool g = src == kGauss1;
+    const double d = g ? 3.0 : 1.5, c0 = g ? 0.0 : 1.0, c1 = g ? -2.331643981597124 : 0.0, c2 = g ? 0.0 : -2.0;
+    const double x = pi * (mu * t - d);
+    const double a = x * x;
+    return ((c0 + c1 * x) + c2 * a) * exp(-a);
+}
+
+__device__ __forceinline__ double forcing_dmu(int src, double t, double mu) {
+    return src == kGauss1 ? gauss1_dmu(t, mu) : ricker_dmu(t, mu);
+}
+
 // State increment in double-float arithmetic, one element:
 //   (vh, vl) += d * ((H + L) + (F + Fe))
 // where (H, L) is the compensated product row, (F, Fe) the forcing term and d

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kThr) void fom_csr_kernel(const int *__restrict__ p
                                                        const double *__restrict__ val, const double *__restrict__ X,
                                                        double *__restrict__ Y, int64_t nrows, int M,
                                                        const double *__restrict__ f, const double *__restrict__ mu,
-                                                       double t, double dt) {
+                                                       double t, double dt, int src) {
     const int64_t total = nrows * M;
     for (int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThr) {
         int64_t r;
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kThr) void fom_csr_kernel(const int *__restrict__ p
         }
         if (MODE == 1) {
             const double fr = f[r];
-            if (fr != 0.0) inc = inc + fr * dev::ricker(t, mu[m]);
+            if (fr != 0.0) inc = inc + fr * dev::forcing(src, t, mu[m]);
         }
         Y[e] = Y[e] + dt * inc;
     }
@@ -70,16 +70,16 @@ __global__ __launch_bounds__(kThr) void fom_csr_kernel(const int *__restrict__ p
 
 template <int MODE>
 hipError_t launch_csr(const FomCsr &A, const double *X, double *Y, int M, const double *f, const double *mu,
-                      double t, double dt, hipStream_t st) {
+                      double t, double dt, int src, hipStream_t st) {
     const int64_t total = (int64_t)A.nrows * M;
     if (total <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((total + kThr - 1) / kThr, 65536);
     if (total < (int64_t)1 << 32)
         hipLaunchKernelGGL((fom_csr_kernel<MODE, false>), dim3((unsigned)blocks), dim3(kThr), 0, st, A.ptr, A.col,
-                           A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt);
+                           A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt, src);
     else
         hipLaunchKernelGGL((fom_csr_kernel<MODE, true>), dim3((unsigned)blocks), dim3(kThr), 0, st, A.ptr, A.col,
-                           A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt);
+                           A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt, src);
     return hipGetLastError();
 }
 
@@ -207,15 +207,15 @@ __global__ __launch_bounds__(kThr) void gemm_nn_kernel(const double *__restrict_
 }  // namespace
 
 hipError_t launch_fom_step(const FomCsr &Av, const FomCsr &As, const double *f, const double *mu, int M, int64_t n,
-                           double dt, double *V, double *S, hipStream_t st) {
+                           double dt, int source, double *V, double *S, hipStream_t st) {
     const double t = (double)n * dt;
-    hipError_t e = launch_csr<1>(Av, S, V, M, f, mu, t, dt, st);
+    hipError_t e = launch_csr<1>(Av, S, V, M, f, mu, t, dt, source, st);
     if (e != hipSuccess) return e;
-    return launch_csr<2>(As, V, S, M, nullptr, nullptr, t, dt, st);
+    return launch_csr<2>(As, V, S, M, nullptr, nullptr, t, dt, source, st);
 }
 
 hipError_t launch_fom_spmm(const FomCsr &A, const double *X, int M, double *Y, hipStream_t st) {
-    return launch_csr<0>(A, X, Y, M, nullptr, nullptr, 0.0, 0.0, st);
+    return launch_csr<0>(A, X, Y, M, nullptr, nullptr, 0.0, 0.0, 0, st);
 }
 
 int gemm_tn_splits(int64_t N, int K1, int K2) {

@@ -21,7 +21,7 @@ template <bool FORCED>
 __global__ __launch_bounds__(256) void gemv_half_f32(const float *__restrict__ A, int rows, int cols,
                                                      const float *__restrict__ x, float *__restrict__ y,
                                                      const float *__restrict__ b, double dt, double t,
-                                                     double mu) {
+                                                     double mu, int src) {
     __shared__ float ph[4][64], pl[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void gemv_half_f32(const float *__restrict__ A
         }
         float F = 0.f, Fe = 0.f;
         if (FORCED) {
-            double u = dev::ricker(t, mu);
+            double u = dev::forcing(src, t, mu);
             float uh = (float)u, ul = (float)(u - (double)uh);
             F = b[i] * uh;
             Fe = fmaf(b[i], uh, -F) + b[i] * ul;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void gemv_half_f32(const float *__restrict__ A
 __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ A, int rows, int cols,
                                                      const double *__restrict__ x, double *__restrict__ y,
                                                      const double *__restrict__ b, double dt, double t,
-                                                     double mu, int forced) {
+                                                     double mu, int forced, int src) {
     __shared__ double part[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ 
     __syncthreads();
     if (w == 0 && i < rows) {
         double r = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-        double f = forced ? b[i] * dev::ricker(t, mu) : 0.0;
+        double f = forced ? b[i] * dev::forcing(src, t, mu) : 0.0;
         y[i] = y[i] + dt * (r + f);
     }
 }
@@ -88,29 +88,29 @@ __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ 
 
 template <>
 hipError_t launch_rank1_step<float>(const void *avs_cm, const void *asv_cm, const void *b, int kv,
-                                    int ks, double dt, int64_t n, double mu, void *v, void *s,
+                                    int ks, double dt, int64_t n, double mu, int source, void *v, void *s,
                                     hipStream_t st) {
     const double t = (double)n * dt;
     hipLaunchKernelGGL(gemv_half_f32<true>, dim3((kv + 63) / 64), dim3(256), 0, st,
                        (const float *)avs_cm, kv, ks, (const float *)s, (float *)v,
-                       (const float *)b, dt, t, mu);
+                       (const float *)b, dt, t, mu, source);
     hipLaunchKernelGGL(gemv_half_f32<false>, dim3((ks + 63) / 64), dim3(256), 0, st,
                        (const float *)asv_cm, ks, kv, (const float *)v, (float *)s,
-                       (const float *)nullptr, dt, t, mu);
+                       (const float *)nullptr, dt, t, mu, source);
     return hipGetLastError();
 }
 
 template <>
 hipError_t launch_rank1_step<double>(const void *avs_cm, const void *asv_cm, const void *b, int kv,
-                                     int ks, double dt, int64_t n, double mu, void *v, void *s,
+                                     int ks, double dt, int64_t n, double mu, int source, void *v, void *s,
                                      hipStream_t st) {
     const double t = (double)n * dt;
     hipLaunchKernelGGL(gemv_half_f64, dim3((kv + 63) / 64), dim3(256), 0, st,
                        (const double *)avs_cm, kv, ks, (const double *)s, (double *)v,
-                       (const double *)b, dt, t, mu, 1);
+                       (const double *)b, dt, t, mu, 1, source);
     hipLaunchKernelGGL(gemv_half_f64, dim3((ks + 63) / 64), dim3(256), 0, st,
                        (const double *)asv_cm, ks, kv, (const double *)v, (double *)s,
-                       (const double *)nullptr, dt, t, mu, 0);
+                       (const double *)nullptr, dt, t, mu, 0, source);
     return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             if (MODE == kForward)
-                u64[q] = mok[q] ? dev::ricker(t, muj[q]) : 0.0;
+                u64[q] = mok[q] ? dev::forcing(a.source, t, muj[q]) : 0.0;
             else   // clamped column: the load is unconditional, the value selected
                 u64[q] = mok[q] ? 2.0 * a.ytr[(size_t)r * a.M + min(m[q], a.M - 1)] : 0.0;
         }
@@ -221,7 +221,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
                 Jacc += a.dt * (yv * yv);
                 a.y[(size_t)k * a.M + col0 + pc] = yv;
             } else {
-                Jacc += a.dt * yv * dev::ricker_dmu(t, mupc);
+                Jacc += a.dt * yv * dev::forcing_dmu(a.source, t, mupc);
             }
         } else if (probe && tid < NC && col0 + tid < a.M) {
             double yv = 0.0;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
                 Jacc += a.dt * (yv * yv);
                 if (a.y) a.y[(size_t)k * a.M + col0 + tid] = yv;
             } else {
-                Jacc += a.dt * yv * dev::ricker_dmu(t, a.mu[col0 + tid]);
+                Jacc += a.dt * yv * dev::forcing_dmu(a.source, t, a.mu[col0 + tid]);
             }
         }
         if (MODE == kForward && TR == kTraces) {

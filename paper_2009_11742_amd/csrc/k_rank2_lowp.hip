@@ -298,7 +298,7 @@ void rank2_lowp_kernel(Rank2Args a, float scale) {
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const double t = (double)(a.n0 + k) * a.dt;
-        const double u64 = mok ? dev::ricker(t, muj) : 0.0;
+        const double u64 = mok ? dev::forcing(a.source, t, muj) : 0.0;
         const float uh = (float)u64;
         const float ul = (float)(u64 - (double)uh);
         double ypart = 0.0;

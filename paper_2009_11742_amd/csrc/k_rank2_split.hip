@@ -78,6 +78,7 @@ struct SplitArgs {
     int *status;                // status[1] <- ROM_E_TIMEOUT
     const SplitGroup *grp;      // grouped FP32 runs: per-group instance data, from grp[g0]
     int g0;
+    int source;                 // source signal (dev::Source)
     int kv, kp, M, G, R;
     int64_t n0, nsteps;
     double dt;
@@ -334,7 +335,7 @@ void rank2_split_kernel(SplitArgs a) {
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const int64_t n = a.n0 + k;
         const double t = (double)n * a.dt;
-        const double u = fok ? dev::ricker(t, fmu) : 0.0;
+        const double u = fok ? dev::forcing(a.source, t, fmu) : 0.0;
         double yp = half_step(0, opv, a.xs, a.xv, u, true);
         if (probe) {
             // sum the 4 strips of column fj, then publish this tile's partial
@@ -477,7 +478,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     const int r = s % R;
     const int g = (s / R) * 8 + xcc;
     if (g >= a.G) return;
-    int kv = a.kv, M = a.M, col0 = g * kCols;
+    int kv = a.kv, M = a.M, col0 = g * kCols, src = a.source;
     double dt = a.dt;
     const float *bsrc = a.b, *csrc = a.c;
     const double *mup = a.mu;
@@ -490,6 +491,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
         kv = __builtin_amdgcn_readfirstlane(q.kv);
         M = __builtin_amdgcn_readfirstlane(q.M);
         col0 = __builtin_amdgcn_readfirstlane(q.col0);
+        src = __builtin_amdgcn_readfirstlane(q.source);
         dt = __builtin_bit_cast(double, uniform64(__builtin_bit_cast(uint64_t, q.dt)));
         bsrc = reinterpret_cast<const float *>(uniform64(reinterpret_cast<uint64_t>(q.b)));
         csrc = nullptr;
@@ -584,7 +586,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const int64_t n = a.n0 + k;
         const double t = (double)n * dt;
-        const double u = fok ? dev::ricker(t, fmu) : 0.0;
+        const double u = fok ? dev::forcing(src, t, fmu) : 0.0;
         double yp = half_step(0, opvw, xs, xv, u, true);
         if (probe) {
             yp += __shfl_xor(yp, 1, 64);
@@ -804,6 +806,7 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     a.n0 = r2.n0;
     a.nsteps = r2.nsteps;
     a.dt = r2.dt;
+    a.source = r2.source;
     a.scale = scale;
     a.status = status;
     a.grp = nullptr;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
         const double t = (double)(a.n0 + k) * a.dt;
-        if (tid < NB) ur[tid] = (col0 + tid < a.M) ? dev::ricker(t, a.mu[col0 + tid]) : 0.0;
+        if (tid < NB) ur[tid] = (col0 + tid < a.M) ? dev::forcing(a.source, t, a.mu[col0 + tid]) : 0.0;
         __syncthreads();
         // ---- velocity half-step
         for (int i = w * 64 + lane; i < kv; i += 256) {

@@ -118,6 +118,9 @@ void free_ctx(rom_ctx *c) {
 
 bool g_configured = false;
 
+// Source signal of a context (rom_config flag ROM_SOURCE_GAUSS1).
+int ctx_source(const rom_ctx *c) { return (c->flags & ROM_SOURCE_GAUSS1) ? 1 : 0; }
+
 // Row-split groups for a rank-2 run of M samples with FP32 states, or 0 if
 // the row-split kernels do not apply (Kv == Ks in {256, 512, 1024}, at most
 // 256 workgroups, a 256-CU gfx950).
@@ -349,7 +352,7 @@ rom_status tile_times(rom_ctx *c, hipStream_t st, TuneEntry &te) {
     if (stream_capturing(st)) return ROM_OK;
     rom::Rank2Args a;
     a.b = c->b; a.mu = nullptr;
-    a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.dt = c->dt;
+    a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.dt = c->dt; a.source = ctx_source(c);
     a.M = rom::kColBlock;
     rom_status rs = time_schedules(c, a, 1u << ROM_SCHEDULE_COLUMNS4, 0, kTileSteps, st, te.us);
     if (rs == ROM_OK && cols8_ok(c)) {
@@ -393,7 +396,8 @@ rom_status check_config(const rom_config *cfg, const char *who) {
     if (!lowp && cfg->op_type != cfg->state_type)
         return fail(ROM_E_UNSUPPORTED, w + ": supported (op, state) pairs are (F64, F64), "
                                           "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
-    if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8))
+    if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 |
+                                 ROM_SOURCE_GAUSS1))
         return fail(ROM_E_ARG, w + ": unknown flag bits");
     const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
     if (sf & (sf - 1)) return fail(ROM_E_ARG, w + ": at most one ROM_SCHED_* flag");
@@ -755,8 +759,10 @@ rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu, 
         return fail(ROM_E_UNSUPPORTED, "rom_step_rank1: needs op_type == state_type");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = ctx->state_type == ROM_F64
-        ? rom::launch_rank1_step<double>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu, v, s, st)
-        : rom::launch_rank1_step<float>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu, v, s, st);
+        ? rom::launch_rank1_step<double>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu,
+                                         ctx_source(ctx), v, s, st)
+        : rom::launch_rank1_step<float>(ctx->avs_cm, ctx->asv_cm, ctx->b, ctx->kv, ctx->ks, ctx->dt, n, mu,
+                                        ctx_source(ctx), v, s, st);
     if (e != hipSuccess) return hip_fail(e, "rom_step_rank1: launch");
     return ROM_OK;
 }
@@ -784,7 +790,7 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
     rom::Rank2Args a;
     a.b = ctx->b; a.c = c; a.mu = mu; a.V = V; a.S = S; a.J = J; a.y = y;
     a.kv = ctx->kv; a.ks = ctx->ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M;
-    a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt;
+    a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt; a.source = ctx_source(ctx);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     if ((ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3 || ctx->op_type == ROM_F32) &&
@@ -903,7 +909,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     ACHK(hipMemsetAsync(J, 0, mK * 8, st), "rom_adjoint: memset");
     rom::Rank2Args a;
     a.b = ctx->b; a.c = c; a.mu = mu; a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp;
-    a.M = M; a.dt = ctx->dt; a.avs = ctx->avs_pk; a.asv = ctx->asv_pk; a.y = nullptr;
+    a.M = M; a.dt = ctx->dt; a.avs = ctx->avs_pk; a.asv = ctx->asv_pk; a.y = nullptr; a.source = ctx_source(ctx);
     for (int64_t g = 0; g < nseg; ++g) {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
         float *cg = ck + (size_t)g * (v1 + s1);
@@ -1043,7 +1049,7 @@ rom_status rom_run_receivers(rom_ctx *ctx, int32_t M, const double *mu, int64_t 
     hipStream_t s2 = ctx->side[0];
     rom::Rank2Args a;
     a.b = ctx->b; a.c = C; a.mu = mu; a.V = V; a.S = S; a.J = nullptr;
-    a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M; a.dt = ctx->dt;
+    a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M; a.dt = ctx->dt; a.source = ctx_source(ctx);
     a.avs = ctx->avs_pk; a.asv = ctx->asv_pk;
     const int64_t nchunk = (nsteps + L - 1) / L;
     for (int64_t c = 0; c < nchunk; ++c) {
@@ -1121,7 +1127,7 @@ rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const d
         a.avs = c->avs_pk; a.asv = c->asv_pk; a.b = c->b; a.c = nullptr; a.mu = mu[i];
         a.V = V[i]; a.S = S[i]; a.J = nullptr; a.y = nullptr;
         a.kv = c->kv; a.ks = c->ks; a.kvp = c->kvp; a.ksp = c->ksp; a.M = M[i];
-        a.n0 = 0; a.nsteps = 0; a.dt = c->dt;
+        a.n0 = 0; a.nsteps = 0; a.dt = c->dt; a.source = ctx_source(c);
         a.nset = nset;
     }
     std::vector<int> order(G);
@@ -1164,6 +1170,7 @@ rom_status build_split_groups(rom_ctx *const *ctx, int32_t G, const int32_t *M, 
             q.mu = mu[i];
             q.V = static_cast<float *>(V[i]); q.S = static_cast<float *>(S[i]);
             q.dt = ctx[i]->dt;
+            q.source = ctx_source(ctx[i]);
             q.kv = ctx[i]->kv; q.M = M[i]; q.col0 = c0;
             groups.push_back(q);
             owner.push_back(i);

@@ -32,6 +32,7 @@ struct rom_fom {
     int device = 0;
     int nv = 0, ns = 0;
     double dt = 0.0;
+    int source = 0;
     rom::FomCsr av, as;
     double *f = nullptr;
     void *mem = nullptr;          // one device block holding everything above
@@ -170,11 +171,12 @@ extern "C" {
 
 rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const int32_t *av_col, const double *av_val,
                           const int32_t *as_ptr, const int32_t *as_col, const double *as_val, const double *f,
-                          double dt, void *stream, rom_fom **out) {
+                          double dt, uint32_t flags, void *stream, rom_fom **out) {
     if (out) *out = nullptr;
     if (!out || !f) return api_fail(ROM_E_ARG, "rom_fom_create: NULL argument");
     if (nv < 1 || ns < 1) return api_fail(ROM_E_ARG, "rom_fom_create: Nv and Ns must be >= 1");
     if (!(dt > 0.0) || !isfinite(dt)) return api_fail(ROM_E_ARG, "rom_fom_create: dt must be finite and > 0");
+    if (flags & ~(uint32_t)ROM_SOURCE_GAUSS1) return api_fail(ROM_E_ARG, "rom_fom_create: unknown flag bits");
     rom_status rs = check_csr(nv, ns, av_ptr, av_col, av_val, "rom_fom_create: Av");
     if (rs == ROM_OK) rs = check_csr(ns, nv, as_ptr, as_col, as_val, "rom_fom_create: As");
     if (rs != ROM_OK) return rs;
@@ -209,7 +211,7 @@ rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const i
     if (e == hipSuccess) e = hipMemcpyAsync(F->f, f, sizeof(double) * (size_t)nv, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { dfree(F->mem); delete F; return api_hip_fail(e, "rom_fom_create: upload"); }
-    F->nv = nv; F->ns = ns; F->dt = dt;
+    F->nv = nv; F->ns = ns; F->dt = dt; F->source = (flags & ROM_SOURCE_GAUSS1) ? 1 : 0;
     F->av.ptr = avp; F->av.col = avc; F->av.val = avv; F->av.nrows = nv;
     F->as.ptr = asp; F->as.col = asc; F->as.val = asv; F->as.nrows = ns;
     *out = F;
@@ -223,7 +225,7 @@ rom_status rom_fom_run(rom_fom *F, int32_t M, const double *mu, int64_t n0, int6
     if (n0 < 0 || nsteps < 0) return api_fail(ROM_E_ARG, "rom_fom_run: n0 and nsteps must be >= 0");
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = rom::launch_fom_step(F->av, F->as, F->f, mu, M, n0 + k, F->dt, V, S, st);
+        hipError_t e = rom::launch_fom_step(F->av, F->as, F->f, mu, M, n0 + k, F->dt, F->source, V, S, st);
         if (e != hipSuccess) return api_hip_fail(e, "rom_fom_run: launch");
     }
     return ROM_OK;

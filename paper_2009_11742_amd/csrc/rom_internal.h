@@ -107,6 +107,8 @@ struct Rank2Args {
     // column sets per workgroup of the FP32 column-block kernels (grouped
     // runs read it per instance): 1 = 4 samples, 2 = 8 samples
     int nset = 1;
+    // source signal: 0 Ricker, 1 first derivative of a Gaussian
+    int source = 0;
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -159,7 +161,7 @@ hipError_t launch_rank2_valu(const Rank2Args &a, hipStream_t st);
 
 template <typename T>
 hipError_t launch_rank1_step(const void *avs_cm, const void *asv_cm, const void *b, int kv,
-                             int ks, double dt, int64_t n, double mu, void *v, void *s,
+                             int ks, double dt, int64_t n, double mu, int source, void *v, void *s,
                              hipStream_t st);
 
 // Grouped row-split run (FP32 operators, Kv == Ks, one padded K for all
@@ -173,7 +175,7 @@ struct SplitGroup {
     const double *mu;
     float *V, *S;
     double dt;
-    int kv, M, col0, pad_;
+    int kv, M, col0, source;
 };
 // Groups one cooperative launch holds at padded size kvp (256 / (kvp / 64)).
 int rank2_split_groups_per_launch(int kvp);
@@ -192,7 +194,7 @@ struct FomCsr {
 // One FOM leapfrog step n (t_n = n dt) of M row-major samples:
 // V += dt (Av S + f u^T), then S += dt As V.
 hipError_t launch_fom_step(const FomCsr &Av, const FomCsr &As, const double *f, const double *mu, int M, int64_t n,
-                           double dt, double *V, double *S, hipStream_t st);
+                           double dt, int source, double *V, double *S, hipStream_t st);
 // Y (rows x M, row-major) = A X (X row-major with M columns).
 hipError_t launch_fom_spmm(const FomCsr &A, const double *X, int M, double *Y, hipStream_t st);
 // C (K1 x K2 column-major) = P^T Q, P (N x K1) and Q (N x K2) row-major;

@@ -22,6 +22,8 @@ _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": 
 # FP32-state rank-2 schedule: "auto" (the autotuner's table), "columns"
 # (4-column blocks), "rowsplit" (row-split where it applies), "columns8"
 # (8-column blocks, FP32 operators)
+# source signal: the Ricker wavelet or the first derivative of a Gaussian
+_SOURCE = {"ricker": 0, "gauss1": _lib.ROM_SOURCE_GAUSS1}
 _SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT,
           "columns8": _lib.ROM_SCHED_COLUMNS8}
 
@@ -51,7 +53,8 @@ class Rom:
     ('f64', 'f32', 'bf16', 'fp8'; default: the state precision).
     """
 
-    def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, schedule="auto", stream=None):
+    def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, schedule="auto", stream=None,
+                 source="ricker"):
         Avs = np.asarray(Avs)
         kv, ks = Avs.shape
         self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
@@ -60,7 +63,7 @@ class Rom:
         B = _host_f64(Asv, (ks, kv))
         bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
         self.ops = state if ops is None else ops
-        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule]
+        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source]
         cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
         ctx = C.c_void_p()
         lib = _lib.load()
@@ -351,7 +354,7 @@ class AffineFamily:
     run_grouped)."""
 
     def __init__(self, Avs_terms, Asv_terms, b, dt, state="f32", ops=None, skew_check=False, schedule="auto",
-                 stream=None):
+                 stream=None, source="ricker"):
         At = np.asarray(Avs_terms, dtype=np.float64)
         Bt = np.asarray(Asv_terms, dtype=np.float64)
         Q, kv, ks = At.shape
@@ -364,7 +367,7 @@ class AffineFamily:
         self.Q, self.kv, self.ks, self.dt, self.state = int(Q), int(kv), int(ks), float(dt), state
         code, _ = _DT[state]
         self.ops = state if ops is None else ops
-        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule]
+        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source]
         cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
         h = C.c_void_p()
         pd = C.POINTER(C.c_double)
@@ -404,7 +407,7 @@ class Fom:
     As in CSR, source f, time step dt).  States are row-major torch tensors
     (N x M, float64): ``zeros(M)`` makes a pair."""
 
-    def __init__(self, Av, As, f, dt, stream=None):
+    def __init__(self, Av, As, f, dt, stream=None, source="ricker"):
         avp, avc, avv = (np.ascontiguousarray(Av[0], dtype=np.int32), np.ascontiguousarray(Av[1], dtype=np.int32),
                          np.ascontiguousarray(Av[2], dtype=np.float64))
         asp, asc, asv = (np.ascontiguousarray(As[0], dtype=np.int32), np.ascontiguousarray(As[1], dtype=np.int32),
@@ -417,7 +420,7 @@ class Fom:
         h = C.c_void_p()
         check(_lib.load().rom_fom_create(self.nv, self.ns, avp.ctypes.data_as(pi), avc.ctypes.data_as(pi),
                                          avv.ctypes.data_as(pd), asp.ctypes.data_as(pi), asc.ctypes.data_as(pi),
-                                         asv.ctypes.data_as(pd), ff.ctypes.data_as(pd), self.dt,
+                                         asv.ctypes.data_as(pd), ff.ctypes.data_as(pd), self.dt, _SOURCE[source],
                                          _stream_handle(stream), C.byref(h)))
         self._h = h
 

@@ -237,16 +237,17 @@ def test_fom_and_pod_reject_bad_arguments():
     f = np.zeros(2)
     E = _lib.ROM_E_ARG
 
-    def create(nv, ns, ap, ac, av, sp, sc, sv, ff, dt):
+    def create(nv, ns, ap, ac, av, sp, sc, sv, ff, dt, flags=0):
         return lib.rom_fom_create(nv, ns, ap.ctypes.data_as(pi), ac.ctypes.data_as(pi), av.ctypes.data_as(pd),
                                   sp.ctypes.data_as(pi), sc.ctypes.data_as(pi), sv.ctypes.data_as(pd),
-                                  ff.ctypes.data_as(pd), dt, None, C.byref(out))
+                                  ff.ctypes.data_as(pd), dt, flags, None, C.byref(out))
     assert create(0, 2, ptr, col, val, ptr, col, val, f, 0.1) == E and not out.value
     assert create(2, 2, ptr, col, val, ptr, col, val, f, 0.0) == E
     bad = np.array([0, 2, 1], dtype=np.int32)                 # decreasing row pointer
     assert create(2, 2, bad, col, val, ptr, col, val, f, 0.1) == E
     badc = np.array([0, 5], dtype=np.int32)                   # column out of range
     assert create(2, 2, ptr, badc, val, ptr, col, val, f, 0.1) == E
+    assert create(2, 2, ptr, col, val, ptr, col, val, f, 0.1, flags=32) == E        # unknown flag
     nanv = np.array([1.0, np.nan])
     assert create(2, 2, ptr, col, nanv, ptr, col, val, f, 0.1) == _lib.ROM_E_NONFINITE
     assert lib.rom_fom_run(None, 1, None, 0, 1, None, None, None) == E

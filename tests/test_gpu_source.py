@@ -1,0 +1,142 @@
+"""The second source signal (first derivative of a Gaussian, rom_config flag
+ROM_SOURCE_GAUSS1) on every stepping path, against the FP64 oracle run with
+the same source: FP32 column blocks (4 and 8 samples), FP32 and BF16
+row-split, the low-precision column blocks, the FP64 path, rank-1 steps,
+the adjoint's dJ/dmu, both grouped plans and the FOM.  Bars as for the
+Ricker runs: FP64 1e-12, FP32 1e-5, BF16 2e-3, adjoint 1e-4.  A Ricker run
+of the same inputs differs from these by far more than the bars.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+SRC = "gauss1"
+
+
+def _relcol(X, R):
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)))
+
+
+def _rom(inst, **kw):
+    from paper_2009_11742_amd import Rom
+    return Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], source=SRC, **kw)
+
+
+def _run(rom, inst, N):
+    M = len(inst["mu"])
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(M)
+    c = torch.tensor(inst["c"], dtype=V.dtype, device="cuda")
+    J = torch.zeros(M, dtype=torch.float64, device="cuda")
+    rom.run_rank2(mu, V, S, N, c=c, J=J)
+    rom.check()
+    torch.cuda.synchronize()
+    return V.cpu().numpy().astype(np.float64).T, S.cpu().numpy().astype(np.float64).T, J.cpu().numpy()
+
+
+@pytest.mark.parametrize("state,ops,schedule,K,M,bar", [
+    ("f32", "f32", "columns", 128, 9, 1e-5), ("f32", "f32", "columns8", 96, 13, 1e-5),
+    ("f32", "f32", "rowsplit", 256, 70, 1e-5), ("f32", "bf16", "rowsplit", 256, 64, 2e-3),
+    ("f32", "bf16", "columns", 128, 6, 2e-3), ("f64", "f64", "auto", 64, 5, 1e-12)])
+def test_rank2_gauss1_matches_oracle(state, ops, schedule, K, M, bar):
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=K + M), state)
+    N = 800
+    rom = _rom(inst, state=state, ops=ops, schedule=schedule)
+    V, S, J = _run(rom, inst, N)
+    A, B, _ = rom.operators()
+    r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"], N, c=inst["c"], source=SRC)
+    e = max(_relcol(V, r["V"]), _relcol(S, r["S"]))
+    eJ = float(np.max(np.abs(J - r["J"]) / r["J"]))
+    rr = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"], N, source="ricker")
+    print("gauss1 %s/%s %s K=%d M=%d: state %.2e J %.2e (vs Ricker run %.2e)"
+          % (state, ops, schedule, K, M, e, eJ, _relcol(V, rr["V"])))
+    assert e <= bar and eJ <= bar
+    assert _relcol(V, rr["V"]) > 100 * bar
+    rom.close()
+
+
+@pytest.mark.parametrize("state", ["f32", "f64"])
+def test_rank1_gauss1_matches_oracle(state):
+    inst = synth.round_to(synth.make_instance(48, 40, 1, seed=3, skew=False), state)
+    rom = _rom(inst, state=state)
+    dt = torch.float32 if state == "f32" else torch.float64
+    v = torch.zeros(48, dtype=dt, device="cuda")
+    s = torch.zeros(40, dtype=dt, device="cuda")
+    N = 400
+    for n in range(N):
+        rom.step_rank1(v, s, n, float(inst["mu"][0]))
+    torch.cuda.synchronize()
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, source=SRC)
+    e = _relcol(v.cpu().numpy().astype(np.float64)[:, None], r["V"])
+    assert e <= (1e-5 if state == "f32" else 1e-12), e
+    rom.close()
+
+
+def test_adjoint_gauss1_matches_oracle():
+    inst = synth.round_to(synth.make_instance(40, 40, 5, seed=8), "f32")
+    rom = _rom(inst, state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    N = 300
+    out = rom.adjoint(mu, N, c)
+    torch.cuda.synchronize()
+    r = oracle.adjoint(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, inst["c"], source=SRC)
+    for k in ("J", "dAvs", "dAsv", "dmu"):
+        g = out[k].cpu().numpy().astype(np.float64)
+        e = float(np.linalg.norm(g - r[k]) / np.linalg.norm(r[k]))
+        print("adjoint gauss1", k, "%.2e" % e)
+        assert e <= 1e-4, (k, e)
+    rom.close()
+
+
+@pytest.mark.parametrize("schedule", ["columns", "rowsplit"])
+def test_grouped_gauss1_plans(schedule):
+    """Both grouped plans carry each instance's source: two Gaussian-source
+    instances and one Ricker instance in one plan, each equal to its own
+    standalone run of the same schedule."""
+    from paper_2009_11742_amd import GroupPlan, Rom
+    specs = [(256, 64, 1, SRC), (256, 30, 2, "ricker"), (256, 100, 3, SRC)]
+    roms, mus, Vs, Ss, insts = [], [], [], [], []
+    for K, M, seed, src in specs:
+        inst = synth.round_to(synth.make_instance(K, K, M, seed=seed), "f32")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=schedule, source=src)
+        V, S = rom.zeros(M)
+        roms.append(rom); Vs.append(V); Ss.append(S); insts.append((inst, src))
+        mus.append(torch.tensor(inst["mu"], dtype=torch.float64, device="cuda"))
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    assert plan.schedule == ("rowsplit" if schedule == "rowsplit" else "columns")
+    N = 500
+    plan.run(N)
+    plan.check()
+    torch.cuda.synchronize()
+    for (inst, src), rom, mu, V, S in zip(insts, roms, mus, Vs, Ss):
+        V1, S1 = rom.zeros(len(inst["mu"]))
+        rom.run_rank2(mu, V1, S1, N)
+        rom.check()
+        torch.cuda.synchronize()
+        assert torch.equal(V, V1) and torch.equal(S, S1)
+        r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, source=src)
+        assert _relcol(V.cpu().numpy().astype(np.float64).T, r["V"]) <= 1e-5
+    plan.close()
+    for r_ in roms:
+        r_.close()
+
+
+def test_fom_gauss1_matches_oracle():
+    from paper_2009_11742_amd import Fom
+    d = synth.make_shear_fom(12, 20)
+    mu = synth.fom_periods(4, seed=2)
+    F = Fom(d["Av"], d["As"], d["f"], d["dt"], source=SRC)
+    mut = torch.tensor(mu, dtype=torch.float64, device="cuda")
+    V, S = F.zeros(4)
+    N = 400
+    F.run(mut, V, S, N)
+    torch.cuda.synchronize()
+    r = oracle.fom_run(d["Av"], d["As"], d["f"], d["dt"], mu, N, source=SRC)
+    assert _relcol(V.cpu().numpy(), r["V"]) <= 1e-12 and _relcol(S.cpu().numpy(), r["S"]) <= 1e-12
+    F.close()
