@@ -348,15 +348,17 @@ rom_status rom_run_receivers(rom_ctx *ctx, int32_t M, const double *mu, int64_t 
 
 /*
  * Grouped run: G independent ROM instances (each its own context, sizes and
- * samples) advanced `nsteps` steps from step 0 in ONE launch — the batched
- * direction the paper names for many operator realisations (Sec. 5).  Work
- * items are (instance, column block of 4 or 8 samples: see the tile
- * autotuner above) pairs, dispatched longest tuned step time first.  All
- * contexts must have F32 states and operators, within the LDS-resident size
- * limit.  Per instance i: M[i] samples, mu[i] dev FP64, V[i] / S[i] dev
- * states as in rom_run_rank2 (host arrays of pointers).  Each instance's
- * result is bitwise identical to its own rom_run_rank2 on a column-block
- * schedule.
+ * samples) advanced `nsteps` steps from step 0 together — the batched
+ * direction the paper names for many operator realisations (Sec. 5).  On
+ * the column-block plan it is ONE launch whose work items are (instance,
+ * column block of 4 or 8 samples: see the tile autotuner above) pairs,
+ * dispatched longest tuned step time first; instances of one square K may
+ * run on the row-split plan instead (below).  All contexts must have F32
+ * states and operators, within the LDS-resident size limit.  Per instance
+ * i: M[i] samples, mu[i] dev FP64, V[i] / S[i] dev states as in
+ * rom_run_rank2 (host arrays of pointers).  Each instance's result is
+ * bitwise identical to its own rom_run_rank2 on the plan's schedule
+ * (column blocks, or row-split).
  * The call builds a plan (below), runs it and synchronises `stream`
  * before releasing the plan; use the plan API for asynchronous or
  * graph-captured runs.

@@ -68,18 +68,94 @@ __global__ __launch_bounds__(kThr) void fom_csr_kernel(const int *__restrict__ p
     }
 }
 
+// The same products from the padded (ELL) copy of the operator: row r's
+// entries at [r W, r W + W), unused slots with column -1.  A thread's column
+// and value loads then do not wait for the row pointers, which leaves two
+// dependent memory trips per element (entries, then the gathered states)
+// instead of three.  Entries are summed in stored order, as above.
+template <int MODE, bool WIDE, int W>
+__global__ __launch_bounds__(kThr) void fom_ell_kernel(const int *__restrict__ ecol, const double *__restrict__ eval,
+                                                       const double *__restrict__ X, double *__restrict__ Y,
+                                                       int64_t nrows, int M, const double *__restrict__ f,
+                                                       const double *__restrict__ mu, double t, double dt, int src) {
+    const int64_t total = nrows * M;
+    for (int64_t e = (int64_t)blockIdx.x * kThr + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThr) {
+        int64_t r;
+        int m;
+        if (WIDE) {
+            r = e / M;
+            m = (int)(e - r * M);
+        } else {
+            const unsigned ue = (unsigned)e, uM = (unsigned)M;
+            const unsigned ur = ue / uM;
+            r = ur;
+            m = (int)(ue - ur * uM);
+        }
+        int c[W];
+        double v[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            c[k] = ecol[r * W + k];
+            v[k] = eval[r * W + k];
+        }
+        double y = 0.0;
+        if (MODE != 0) y = Y[e];
+        double x[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) x[k] = X[(int64_t)(c[k] < 0 ? 0 : c[k]) * M + m];
+        double inc = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (c[k] >= 0) inc = inc + v[k] * x[k];
+        if (MODE == 0) {
+            Y[e] = inc;
+            continue;
+        }
+        if (MODE == 1) {
+            const double fr = f[r];
+            if (fr != 0.0) inc = inc + fr * dev::forcing(src, t, mu[m]);
+        }
+        Y[e] = y + dt * inc;
+    }
+}
+
+template <int MODE, bool WIDE>
+void launch_ell(const FomCsr &A, unsigned blocks, const double *X, double *Y, int M, const double *f,
+                const double *mu, double t, double dt, int src, hipStream_t st) {
+    const int64_t n = A.nrows;
+    switch (A.W) {
+    case 2:
+        hipLaunchKernelGGL((fom_ell_kernel<MODE, WIDE, 2>), dim3(blocks), dim3(kThr), 0, st, A.ecol, A.eval, X, Y, n,
+                           M, f, mu, t, dt, src);
+        break;
+    case 4:
+        hipLaunchKernelGGL((fom_ell_kernel<MODE, WIDE, 4>), dim3(blocks), dim3(kThr), 0, st, A.ecol, A.eval, X, Y, n,
+                           M, f, mu, t, dt, src);
+        break;
+    default:
+        hipLaunchKernelGGL((fom_ell_kernel<MODE, WIDE, 8>), dim3(blocks), dim3(kThr), 0, st, A.ecol, A.eval, X, Y, n,
+                           M, f, mu, t, dt, src);
+        break;
+    }
+}
+
 template <int MODE>
 hipError_t launch_csr(const FomCsr &A, const double *X, double *Y, int M, const double *f, const double *mu,
                       double t, double dt, int src, hipStream_t st) {
     const int64_t total = (int64_t)A.nrows * M;
     if (total <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((total + kThr - 1) / kThr, 65536);
-    if (total < (int64_t)1 << 32)
+    const bool wide = total >= (int64_t)1 << 32;
+    if (A.W > 0) {
+        if (wide) launch_ell<MODE, true>(A, (unsigned)blocks, X, Y, M, f, mu, t, dt, src, st);
+        else launch_ell<MODE, false>(A, (unsigned)blocks, X, Y, M, f, mu, t, dt, src, st);
+    } else if (!wide) {
         hipLaunchKernelGGL((fom_csr_kernel<MODE, false>), dim3((unsigned)blocks), dim3(kThr), 0, st, A.ptr, A.col,
                            A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt, src);
-    else
+    } else {
         hipLaunchKernelGGL((fom_csr_kernel<MODE, true>), dim3((unsigned)blocks), dim3(kThr), 0, st, A.ptr, A.col,
                            A.val, X, Y, (int64_t)A.nrows, M, f, mu, t, dt, src);
+    }
     return hipGetLastError();
 }
 

@@ -68,6 +68,31 @@ rom_status check_csr(int nrows, int ncols, const int32_t *ptr, const int32_t *co
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Padded (ELL) copy of a CSR operator when its longest row has at most 8
+// entries: width W in {2, 4, 8}, entries in stored order, unused slots
+// column -1 and value 0.  W = 0: no copy (the kernels use the CSR form).
+struct Ell {
+    int W = 0;
+    std::vector<int> col;
+    std::vector<double> val;
+};
+
+Ell make_ell(int nrows, const int32_t *ptr, const int32_t *col, const double *val) {
+    Ell E;
+    int wmax = 0;
+    for (int r = 0; r < nrows; ++r) wmax = std::max(wmax, (int)(ptr[r + 1] - ptr[r]));
+    if (wmax > 8) return E;
+    E.W = wmax <= 2 ? 2 : (wmax <= 4 ? 4 : 8);
+    E.col.assign((size_t)nrows * E.W, -1);
+    E.val.assign((size_t)nrows * E.W, 0.0);
+    for (int r = 0; r < nrows; ++r)
+        for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+            E.col[(size_t)r * E.W + (k - ptr[r])] = col[k];
+            E.val[(size_t)r * E.W + (k - ptr[r])] = val[k];
+        }
+    return E;
+}
+
 // ---- small dense linear algebra on the host (column-major n x n) ---------
 
 // Upper Cholesky factor R of the symmetric positive definite A (A = R^T R);
@@ -186,7 +211,10 @@ rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const i
     const size_t b_avv = align256(sizeof(double) * (size_t)nzv), b_asp = align256(sizeof(int) * (size_t)(ns + 1));
     const size_t b_asc = align256(sizeof(int) * (size_t)nzs), b_asv = align256(sizeof(double) * (size_t)nzs);
     const size_t b_f = align256(sizeof(double) * (size_t)nv);
-    const size_t total = b_avp + b_avc + b_avv + b_asp + b_asc + b_asv + b_f;
+    const Ell ev = make_ell(nv, av_ptr, av_col, av_val), es = make_ell(ns, as_ptr, as_col, as_val);
+    const size_t b_evc = align256(sizeof(int) * ev.col.size()), b_evv = align256(sizeof(double) * ev.val.size());
+    const size_t b_esc = align256(sizeof(int) * es.col.size()), b_esv = align256(sizeof(double) * es.val.size());
+    const size_t total = b_avp + b_avc + b_avv + b_asp + b_asc + b_asv + b_f + b_evc + b_evv + b_esc + b_esv;
     rom_fom *F = new (std::nothrow) rom_fom();
     if (!F) return api_fail(ROM_E_NOMEM, "rom_fom_create: host allocation failed");
     hipError_t e = hipGetDevice(&F->device);
@@ -200,7 +228,11 @@ rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const i
     int *asp = reinterpret_cast<int *>(m); m += b_asp;
     int *asc = reinterpret_cast<int *>(m); m += b_asc;
     double *asv = reinterpret_cast<double *>(m); m += b_asv;
-    F->f = reinterpret_cast<double *>(m);
+    F->f = reinterpret_cast<double *>(m); m += b_f;
+    int *evc = reinterpret_cast<int *>(m); m += b_evc;
+    double *evv = reinterpret_cast<double *>(m); m += b_evv;
+    int *esc = reinterpret_cast<int *>(m); m += b_esc;
+    double *esv = reinterpret_cast<double *>(m);
     hipStream_t st = static_cast<hipStream_t>(stream);
     e = hipMemcpyAsync(avp, av_ptr, sizeof(int) * (size_t)(nv + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nzv) e = hipMemcpyAsync(avc, av_col, sizeof(int) * (size_t)nzv, hipMemcpyHostToDevice, st);
@@ -209,11 +241,21 @@ rom_status rom_fom_create(int32_t nv, int32_t ns, const int32_t *av_ptr, const i
     if (e == hipSuccess && nzs) e = hipMemcpyAsync(asc, as_col, sizeof(int) * (size_t)nzs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nzs) e = hipMemcpyAsync(asv, as_val, sizeof(double) * (size_t)nzs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(F->f, f, sizeof(double) * (size_t)nv, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && ev.W)
+        e = hipMemcpyAsync(evc, ev.col.data(), sizeof(int) * ev.col.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && ev.W)
+        e = hipMemcpyAsync(evv, ev.val.data(), sizeof(double) * ev.val.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && es.W)
+        e = hipMemcpyAsync(esc, es.col.data(), sizeof(int) * es.col.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && es.W)
+        e = hipMemcpyAsync(esv, es.val.data(), sizeof(double) * es.val.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { dfree(F->mem); delete F; return api_hip_fail(e, "rom_fom_create: upload"); }
     F->nv = nv; F->ns = ns; F->dt = dt; F->source = (flags & ROM_SOURCE_GAUSS1) ? 1 : 0;
     F->av.ptr = avp; F->av.col = avc; F->av.val = avv; F->av.nrows = nv;
     F->as.ptr = asp; F->as.col = asc; F->as.val = asv; F->as.nrows = ns;
+    if (ev.W) { F->av.ecol = evc; F->av.eval = evv; F->av.W = ev.W; }
+    if (es.W) { F->as.ecol = esc; F->as.eval = esv; F->as.W = es.W; }
     *out = F;
     return ROM_OK;
 }

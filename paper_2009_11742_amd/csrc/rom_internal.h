@@ -185,11 +185,17 @@ int rank2_split_groups_per_launch(int kvp);
 hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
                                     int64_t n0, int64_t nsteps, hipStream_t st);
 
-// Full-order side.  A CSR operator on the device.
+// Full-order side.  A sparse operator on the device: CSR, and when no row
+// holds more than 8 entries also a padded (ELL) copy of width W in {2, 4, 8}
+// (row r's entries at [r W, r W + W), unused slots with column -1), which
+// the kernels then use.
 struct FomCsr {
     const int *ptr = nullptr, *col = nullptr;
     const double *val = nullptr;
     int nrows = 0;
+    const int *ecol = nullptr;
+    const double *eval = nullptr;
+    int W = 0;
 };
 // One FOM leapfrog step n (t_n = n dt) of M row-major samples:
 // V += dt (Av S + f u^T), then S += dt As V.

@@ -297,7 +297,9 @@ def _group_args(roms, mus, Vs, Ss):
 
 
 def run_grouped(roms, mus, Vs, Ss, nsteps, stream=None):
-    """Advance G instances (list of Rom, FP32) ``nsteps`` steps from 0 in one launch."""
+    """Advance G instances (list of Rom, FP32) ``nsteps`` steps from 0 together
+    (one column-block launch, or the row-split plan's launches; see
+    GroupPlan).  Synchronises the stream."""
     ctxs, G, Ms, mup, Vp, Sp = _group_args(roms, mus, Vs, Ss)
     check(_lib.load().rom_run_grouped(ctxs, G, Ms, mup, int(nsteps), Vp, Sp, _stream_handle(stream)))
 

@@ -117,3 +117,69 @@ def test_grouped_single_instance_single_sample():
     assert _relcol(V.cpu().numpy().astype(np.float64).T, r["V"]) <= 1e-5
     assert _relcol(S.cpu().numpy().astype(np.float64).T, r["S"]) <= 1e-5
     rom.close()
+
+
+def test_zero_steps_change_nothing():
+    """nsteps = 0 is a valid no-op on every entry point that steps."""
+    from paper_2009_11742_amd import Fom, GroupPlan, Rom
+    inst = synth.round_to(synth.make_instance(64, 64, 3, seed=2), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(3)
+    V.fill_(1.0); S.fill_(2.0)
+    rom.run_rank2(mu, V, S, 0)
+    plan = GroupPlan([rom], [mu], [V], [S])
+    plan.run(0)
+    d = synth.make_shear_fom(5, 6)
+    F = Fom(d["Av"], d["As"], d["f"], d["dt"])
+    Vf, Sf = F.zeros(2)
+    Vf.fill_(3.0)
+    F.run(mu[:2], Vf, Sf, 0)
+    torch.cuda.synchronize()
+    assert torch.all(V == 1.0) and torch.all(S == 2.0) and torch.all(Vf == 3.0) and torch.all(Sf == 0.0)
+    plan.close(); rom.close(); F.close()
+
+
+def test_pod_rank_one_and_square_snapshots():
+    """A rank-one snapshot matrix keeps exactly one mode (the normalised
+    common direction) whatever the tolerance; a square full-rank one (n = ns)
+    keeps all modes when asked, orthonormal."""
+    from paper_2009_11742_amd import pod
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(500)
+    X = np.outer(u, rng.standard_normal(12))
+    Phi, sig, k = pod(torch.tensor(X, device="cuda"), tol=0.0, kmax=12)
+    assert k == 1
+    p = Phi.cpu().numpy()[:, 0]
+    assert abs(abs(p @ u) / np.linalg.norm(u) - 1.0) < 1e-13
+    assert abs(sig[0] - np.linalg.norm(X, 2)) <= 1e-13 * sig[0]
+    Y = rng.standard_normal((40, 40))
+    Phi, sig, k = pod(torch.tensor(Y, device="cuda"))
+    P = Phi.cpu().numpy()
+    assert k == 40 and np.max(np.abs(P.T @ P - np.eye(40))) < 1e-12
+    assert np.max(np.abs(sig - np.linalg.svd(Y, compute_uv=False)) / sig) < 1e-11
+
+
+def test_fom_csr_with_empty_rows_and_one_dof():
+    """CSR operators with empty rows (the axis rows of the grid) and a 1 x 1
+    system: the FOM run equals the oracle."""
+    from paper_2009_11742_amd import Fom
+    ptr = np.array([0, 0, 2, 2], dtype=np.int32)        # rows 0 and 2 empty
+    col = np.array([0, 1], dtype=np.int32)
+    Av = (ptr, col, np.array([0.5, -1.0]))
+    As = (np.array([0, 1, 2], dtype=np.int32), np.array([1, 1], dtype=np.int32), np.array([2.0, -0.25]))
+    f = np.array([0.0, 1.0, 0.5])
+    mu = np.array([0.6, 0.9])
+    for Avx, Asx, ff, nv, ns in ((Av, As, f, 3, 2),
+                                 ((np.array([0, 1], np.int32), np.array([0], np.int32), np.array([-1.0])),
+                                  (np.array([0, 1], np.int32), np.array([0], np.int32), np.array([1.0])),
+                                  np.array([1.0]), 1, 1)):
+        F = Fom(Avx, Asx, ff, 0.05)
+        V = torch.zeros((nv, 2), dtype=torch.float64, device="cuda")
+        S = torch.zeros((ns, 2), dtype=torch.float64, device="cuda")
+        F.run(torch.tensor(mu, device="cuda"), V, S, 300)
+        torch.cuda.synchronize()
+        r = oracle.fom_run(Avx, Asx, ff, 0.05, mu, 300)
+        assert np.max(np.abs(V.cpu().numpy() - r["V"])) <= 1e-12 * max(1.0, np.abs(r["V"]).max())
+        assert np.max(np.abs(S.cpu().numpy() - r["S"])) <= 1e-12 * max(1.0, np.abs(r["S"]).max())
+        F.close()
