@@ -147,3 +147,51 @@ def test_rank3_rowsplit_plan_matches_standalone():
     for r in roms:
         r.close()
     fam.close()
+
+
+def test_rank3_full_workload_sampled():
+    """The rank-3 measurement workload as bench.py runs it: Q = 4 terms,
+    K = 512, 64 parameter points x 64 samples, 2000 steps, on the plan the
+    timing picks; four instances bitwise equal to their own runs of that
+    schedule, one sampled column each within 1e-5 of the oracle."""
+    import concurrent.futures as cf
+    from paper_2009_11742_amd import AffineFamily, GroupPlan
+    K, Q, P, M, N = 512, 4, 64, 64, 2000
+    fam_in = synth.make_affine_family(K, K, Q, P, M, seed=0)
+    b32 = fam_in["b"].astype(np.float32).astype(np.float64)
+    fam = AffineFamily(fam_in["Avs_terms"], fam_in["Asv_terms"], b32, 0.1, state="f32")
+    dts = [float(np.float32(0.5 / float(np.abs(th) @ fam_in["smax"]))) for th in fam_in["theta"]]
+    roms = [fam.instance(th, dt=d) for th, d in zip(fam_in["theta"], dts)]
+    mus = [torch.tensor(m, dtype=torch.float64, device="cuda") for m in fam_in["mu"]]
+    Vs, Ss = zip(*[r.zeros(M) for r in roms])
+    plan = GroupPlan(roms, mus, list(Vs), list(Ss))
+    plan.run(N)
+    plan.check()
+    torch.cuda.synchronize()
+    sched = plan.schedule
+    picks = [0, 21, 42, 63]
+    for p in picks:
+        from paper_2009_11742_amd import Rom
+        Ag, Bg, _ = roms[p].operators()
+        ref = Rom(Ag, Bg, b32, dts[p], state="f32", schedule=sched)
+        V1, S1 = ref.zeros(M)
+        ref.run_rank2(mus[p], V1, S1, N)
+        ref.check()
+        torch.cuda.synchronize()
+        assert torch.equal(Vs[p], V1) and torch.equal(Ss[p], S1), p
+        ref.close()
+
+    def check(p):
+        Ag, Bg, _ = roms[p].operators()
+        col = (13 * p) % M
+        r = oracle.run_rank2(Ag, Bg, b32, dts[p], fam_in["mu"][p][col:col + 1], N)
+        return max(_relcol(Vs[p].cpu().numpy().astype(np.float64).T[:, col:col + 1], r["V"]),
+                   _relcol(Ss[p].cpu().numpy().astype(np.float64).T[:, col:col + 1], r["S"]))
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        errs = list(ex.map(check, picks))
+    print("rank-3 full workload (%s plan): sampled errors %s" % (sched, ["%.2e" % e for e in errs]))
+    assert max(errs) <= 1e-5
+    plan.close()
+    for r in roms:
+        r.close()
+    fam.close()
