@@ -33,7 +33,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the rank-2 kernel at this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy
 # (factors 2.0 and 1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha1": "39b7c1d9d7734bdf94433c3175deefc153b846b3", "bytes": 5.514e6}
+MEASURED_TRAFFIC = {"sources_sha1": "fc1d167ba1c60b4cffde49fcd47937f7c17e8d02", "bytes": 5.516e6}
 KERNEL_SOURCES = ("paper_2009_11742_amd/csrc/k_rank2_f32.hip", "paper_2009_11742_amd/csrc/k_tile_f32.h",
                   "paper_2009_11742_amd/csrc/k_common.h")
 
@@ -340,11 +340,13 @@ def workload_adjoint(args, torch, dev):
     c = torch.tensor(inst["c"], dtype=torch.float32, device=dev)
     wall, ms = _events_time(torch, lambda: rom.adjoint(mu, N, c), 5, 1)
     ksec = float(np.median(ms)) * 1e-3
+    _, ms_rev = _events_time(torch, lambda: rom.adjoint(mu, N, c, stride=-1), 5, 1)
     fwd = 4.0 * K * K * M * N
     out = {"workload": "adjoint: Kv=Ks=512, M=256, 5000 steps, checkpoint stride ceil(sqrt(N))",
            "value": M * N / ksec, "unit": "sample-steps/s (forward + reverse)", "ms_per_gradient": ksec * 1e3,
            "forward_equivalent_tflops": fwd / ksec / 1e12,
-           "algorithmic_tflops": (3 * fwd + 2 * 2.0 * K * K * M * N) / ksec / 1e12}
+           "algorithmic_tflops": (3 * fwd + 2 * 2.0 * K * K * M * N) / ksec / 1e12,
+           "ms_per_gradient_time_reversal": float(np.median(ms_rev))}
     rom.close()
     return out
 

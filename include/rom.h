@@ -292,7 +292,13 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  *   J = sum_m sum_{n=0}^{N-1} dt (c^T V_m^(n+1))^2
  * (differentiation of the leapfrog, the sensitivity use named in Sec. 5).
  * Reverse sweep with the transposed operators; forward states are rebuilt
- * from checkpoints every `ckpt_stride` steps (0 = ceil(sqrt(nsteps))).
+ * from checkpoints every `ckpt_stride` steps (0 = ceil(sqrt(nsteps))), or,
+ * with ckpt_stride = -1, without checkpoints: by stepping the leapfrog
+ * backwards from the final state (it is time-reversible; Sec. 3.1), in
+ * segments of ceil(sqrt(nsteps)) steps.  The reversal is exact only in exact
+ * arithmetic: the rebuilt states carry the rounding of the forward and
+ * backward steps, which grows with N (about 1e-6 relative at N = 5000 in
+ * FP32); the checkpoints are the reference.
  *
  *   M, mu, c      as rom_run_rank2 (c required)
  *   nsteps        N >= 1
@@ -305,9 +311,10 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  *
  * FP32 states and operators.  The recompute of the next segment and the
  * gradient products of the last run on two internal streams beside the
- * reverse sweep on `stream`; the context keeps the workspace (checkpoints,
- * three sets of state and probe traces, two of W/Q traces: about 0.45 GB at
- * Kv = Ks = 512, M = 256, N = 5000) until rom_destroy.
+ * reverse sweep on `stream`; the context keeps the workspace (checkpoints
+ * unless ckpt_stride = -1, three sets of state and probe traces, two of W/Q
+ * traces: about 0.45 GB at Kv = Ks = 512, M = 256, N = 5000, 0.07 GB less
+ * without checkpoints) until rom_destroy.
  */
 rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps,
                        const void *c, const void *V0, const void *S0, double *J,

@@ -11,6 +11,8 @@
 // reduction length.  The reduction is split over waves and workgroups; the
 // FP64 partials are summed in a fixed order by a second kernel, so the
 // gradient is deterministic.
+#include <algorithm>
+
 #include "k_common.h"
 #include "rom_internal.h"
 
@@ -132,6 +134,22 @@ __global__ void reduce_parts_kernel(const double *__restrict__ part, int nsplit,
     }
 }
 
+// ytr[k M + m] = c . (state m at trace entry k + 1) for k < len: the forward
+// probe trace of a segment recovered from its state traces (one wave per
+// value, lanes striding over the rows, FP64 sums).
+__global__ __launch_bounds__(256) void probe_trace_kernel(const float *__restrict__ vtr, const float *__restrict__ c,
+                                                          int kv, int M, int64_t len, double *__restrict__ ytr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nval = len * M;
+    for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < nval; idx += (int64_t)gridDim.x * 4) {
+        const float *v = vtr + (size_t)(idx + M) * kv;      // entry k + 1, column m: (k + 1) M + m = idx + M
+        double acc = 0.0;
+        for (int i = lane; i < kv; i += 64) acc += (double)c[i] * (double)v[i];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) ytr[idx] = acc;
+    }
+}
+
 __global__ void f64_to_f32_kernel(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -188,6 +206,15 @@ hipError_t launch_gemm_nt_acc64(const float *X, const float *Y, int rows, int co
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)rows * cols;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(n, 4096)), dim3(256), 0, st, part, nsplit, n, alpha, dA);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_trace(const float *vtr, const float *c, int kv, int M, int64_t len, double *ytr,
+                              hipStream_t st) {
+    const int64_t nval = len * M;
+    if (nval <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((nval + 3) / 4, 16384);
+    hipLaunchKernelGGL(probe_trace_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vtr, c, kv, M, len, ytr);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ namespace {
 using namespace tile;
 using dev::f4;
 
-enum Mode { kForward = 0, kAdjoint = 1 };
+enum Mode { kForward = 0, kAdjoint = 1, kInverse = 2 };
 
 // One half-step of one field: wave w owns row tiles w, w + 4, ...  Ends
 // with a barrier (the other half-step reads every row of this field).
@@ -98,6 +98,13 @@ enum Traces { kNoTraces = 0, kTraces = 1 };
 //   b; step n = n0 + nsteps - 1 - k at iteration k; writes
 //   a.qtr[n - n0] = Q before and a.wtr[n - n0] = P after the P update, and
 //   adds dt (b^T P) du/dmu(t_n) to a.dmu.
+// Inverse (NS = 1, traces): the forward step undone, which the leapfrog
+//   allows exactly in exact arithmetic (it is time-reversible): from the
+//   state after step n0 + nsteps - 1, iteration k takes step
+//   n = n0 + nsteps - 1 - k back, S <- S - dt Asv V, then
+//   V <- V - dt (Avs S + b u(t_n)), and stores the state before step n at
+//   trace entry n - n0 (entry nsteps: the state given), so the traces come
+//   out in the forward layout.  No probe.
 template <int MODE, int NS, int TR>
 __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned char *smem) {
     constexpr int NC = NB * NS;                  // columns of this workgroup
@@ -128,9 +135,10 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
         Sh[jj * lds_ + i] = (mm < a.M && i < a.ks) ? Sin[(size_t)mm * a.ks + i] : 0.f;
         Sl[jj * lds_ + i] = 0.f;
     }
-    // forward: source b, probe c;  adjoint: source c, probe b
-    const float *src = MODE == kForward ? bv : cv;
-    const float *prb = MODE == kForward ? cv : bv;
+    // forward: source b, probe c;  adjoint: source c, probe b;  inverse:
+    // source b, no probe
+    const float *src = MODE == kAdjoint ? cv : bv;
+    const float *prb = MODE == kForward ? cv : (MODE == kAdjoint ? bv : nullptr);
     for (int i = tid; i < kvp; i += kThreads) {
         bl[i] = (src != nullptr && i < a.kv) ? src[i] : 0.f;
         cl[i] = (prb != nullptr && i < a.kv) ? prb[i] : 0.f;
@@ -169,6 +177,31 @@ __device__ __forceinline__ void run_block(const Rank2Args &a, int col0, unsigned
     __builtin_amdgcn_s_waitcnt(dev::kWaitVm0);
     f4 a0[kQ], a1[kQ];
     Stream str;
+    if constexpr (MODE == kInverse) {
+        // S half-steps first: the operator stream starts with (and then
+        // alternates from) the S-update tiles
+        stream_start(str, a0, a1, fs, fv, w, lane);
+        __syncthreads();
+        store_cols(a.vtr + (size_t)a.nsteps * a.M * a.kv, Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+        store_cols(a.str + (size_t)a.nsteps * a.M * a.ks, Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
+        double zero[NS], dummy[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) zero[q] = dummy[q] = 0.0;
+        for (int64_t k = 0; k < a.nsteps; ++k) {
+            const int64_t n = a.n0 + a.nsteps - 1 - k;
+            const double t = (double)n * a.dt;
+            double u64[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) u64[q] = mok[q] ? dev::forcing(a.source, t, muj[q]) : 0.0;
+            half_step<false, NS>(fs, ress, a0, a1, str, fs, fv, lane, w, bl, cl, zero, -a.dt, dummy);
+            half_step<true, NS>(fv, resv, a0, a1, str, fs, fv, lane, w, bl, cl, u64, -a.dt, dummy);
+            store_cols(a.vtr + (size_t)(n - a.n0) * a.M * a.kv, Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+            store_cols(a.str + (size_t)(n - a.n0) * a.M * a.ks, Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
+        }
+        store_cols(static_cast<float *>(a.V), Vh, Vl, ldv, a.kv, col0, a.M, NC, tid);
+        store_cols(static_cast<float *>(a.S), Sh, Sl, lds_, a.ks, col0, a.M, NC, tid);
+        return;
+    }
     stream_start(str, a0, a1, fv, fs, w, lane);
     __syncthreads();
     if (MODE == kForward && TR == kTraces) {
@@ -309,6 +342,14 @@ hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_inverse_f32_mfma(const Rank2Args &a, hipStream_t st) {
+    const int blocks = (a.M + NB - 1) / NB;
+    const size_t lds = rank2_f32_mfma_lds_bytes(a.kvp, a.ksp, 1);
+    if (!a.vtr || !a.str) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((rank2_f32_mfma_kernel<kInverse, 1, kTraces>), dim3(blocks), dim3(kThreads), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_dev, int nitems,
                                    size_t lds_bytes, int64_t n0, int64_t nsteps, hipStream_t st) {
     if (nitems <= 0 || nsteps <= 0) return hipSuccess;
@@ -322,7 +363,8 @@ hipError_t rank2_f32_mfma_configure() {
                          (const void *)rank2_f32_mfma_kernel<kForward, 1, kNoTraces>,
                          (const void *)rank2_f32_mfma_kernel<kForward, 2, kNoTraces>,
                          (const void *)rank2_f32_mfma_kernel<kForward, 1, kTraces>,
-                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kTraces>};
+                         (const void *)rank2_f32_mfma_kernel<kAdjoint, 1, kTraces>,
+                         (const void *)rank2_f32_mfma_kernel<kInverse, 1, kTraces>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

@@ -823,12 +823,15 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     if (M < 1) return fail(ROM_E_ARG, "rom_adjoint: M must be >= 1");
     if (!mu || !c || !J) return fail(ROM_E_ARG, "rom_adjoint: mu, c and J are required");
     if (nsteps < 1) return fail(ROM_E_ARG, "rom_adjoint: nsteps must be >= 1");
-    if (ckpt_stride < 0) return fail(ROM_E_ARG, "rom_adjoint: ckpt_stride must be >= 0");
+    if (ckpt_stride < -1) return fail(ROM_E_ARG, "rom_adjoint: ckpt_stride must be >= -1");
     if (ctx->state_type != ROM_F32 || ctx->op_type != ROM_F32)
         return fail(ROM_E_UNSUPPORTED, "rom_adjoint: FP32 states and operators only in this version");
     if (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
         rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 1) > 160 * 1024)
         return fail(ROM_E_UNSUPPORTED, "rom_adjoint: Kv + Ks above the LDS-resident limit");
+    // ckpt_stride -1: no checkpoints, the states are recovered by stepping
+    // the leapfrog backwards from the final state (segments of sqrt(N) steps)
+    const bool rev = ckpt_stride == -1;
     int64_t C = ckpt_stride > 0 ? ckpt_stride : (int64_t)ceil(sqrt((double)nsteps));
     if (C < 1) C = 1;
     if (C > nsteps) C = nsteps;
@@ -842,7 +845,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     // of a segment live in one of kTr buffer sets, its W and Q traces in one
     // of kWq, each reused only after the products of its previous segment.
     constexpr int kTr = 3, kWq = 2;
-    const size_t n_ck = (size_t)nseg * (v1 + s1);
+    const size_t n_ck = rev ? 0 : (size_t)nseg * (v1 + s1);
     const size_t n_vtr = (size_t)(C + 1) * v1, n_str = (size_t)(C + 1) * s1;
     const size_t n_wtr = (size_t)C * v1, n_qtr = (size_t)C * s1;
     const size_t n_cur = v1 + s1, n_pq = v1 + s1;
@@ -910,7 +913,11 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     rom::Rank2Args a;
     a.b = ctx->b; a.c = c; a.mu = mu; a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp;
     a.M = M; a.dt = ctx->dt; a.avs = ctx->avs_pk; a.asv = ctx->asv_pk; a.y = nullptr; a.source = ctx_source(ctx);
-    for (int64_t g = 0; g < nseg; ++g) {
+    if (rev) {
+        a.V = curV; a.S = curS; a.J = J; a.n0 = 0; a.nsteps = nsteps;
+        ACHK(rom::launch_rank2_f32_mfma(a, 1, st), "rom_adjoint: forward launch");
+    }
+    for (int64_t g = 0; g < nseg && !rev; ++g) {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
         float *cg = ck + (size_t)g * (v1 + s1);
         ACHK(hipMemcpyAsync(cg, curV, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
@@ -932,10 +939,22 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     hipEvent_t *ev_wq_free = ctx->ev + 7, *ev_rev = ctx->ev + 9;
     auto recompute = [&](int64_t g) -> hipError_t {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
-        const float *cg = ck + (size_t)g * (v1 + s1);
         const int b = (int)(g % kTr);
         hipError_t r = hipSuccess;
         if (g + kTr < nseg) r = hipStreamWaitEvent(s2, ev_tr_free[b], 0);
+        if (rev) {
+            // (curV, curS) hold the state after the segment: step it back,
+            // keeping every state, then recover the probe trace from them
+            rom::Rank2Args iv = a;
+            iv.V = curV; iv.S = curS; iv.c = nullptr; iv.J = nullptr; iv.y = nullptr; iv.n0 = nb; iv.nsteps = len;
+            iv.vtr = vtrb[b]; iv.str = strb[b];
+            if (r == hipSuccess) r = rom::launch_inverse_f32_mfma(iv, s2);
+            if (r == hipSuccess) r = rom::launch_probe_trace(vtrb[b], static_cast<const float *>(c), kv, M, len,
+                                                             ytrb[b], s2);
+            if (r == hipSuccess) r = hipEventRecord(ev_rec[b], s2);
+            return r;
+        }
+        const float *cg = ck + (size_t)g * (v1 + s1);
         if (r == hipSuccess) r = hipMemcpyAsync(curV, cg, v1 * 4, hipMemcpyDeviceToDevice, s2);
         if (r == hipSuccess) r = hipMemcpyAsync(curS, cg + v1, s1 * 4, hipMemcpyDeviceToDevice, s2);
         // recompute the segment, keeping every state and the probe trace

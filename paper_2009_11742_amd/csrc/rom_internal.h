@@ -115,6 +115,13 @@ struct Rank2Args {
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st);
 size_t rank2_f32_mfma_lds_bytes(int kvp, int ksp, int nset);
 hipError_t launch_adjoint_f32_mfma(const Rank2Args &a, hipStream_t st);
+// The forward steps n0 .. n0 + nsteps - 1 undone from the state after them
+// (a.V, a.S in/out), the state before each step stored at trace entry
+// n - n0 of a.vtr / a.str (entry nsteps: the state given).
+hipError_t launch_inverse_f32_mfma(const Rank2Args &a, hipStream_t st);
+// ytr (len x M) = c^T of trace entries 1 .. len of vtr ((len + 1) x M x kv).
+hipError_t launch_probe_trace(const float *vtr, const float *c, int kv, int M, int64_t len, double *ytr,
+                              hipStream_t st);
 hipError_t launch_rank2_lowp(const Rank2Args &a, rom_dtype op, float scale, hipStream_t st);
 hipError_t launch_amax(const double *x, int64_t n, unsigned *out, hipStream_t st);
 hipError_t launch_unpack_lowp(const void *pk, int rows, int cols, int prow, int pcol, rom_dtype op,

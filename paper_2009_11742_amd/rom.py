@@ -206,6 +206,8 @@ class Rom:
     def adjoint(self, mu, nsteps, c, V0=None, S0=None, stride=0, grads=("dAvs", "dAsv", "dmu"),
                 stream=None):
         """Probe QoI J_m = sum_n dt (c^T V_m^(n+1))^2 and its gradients.
+        ``stride``: checkpoint stride (0: ceil(sqrt(nsteps))), or -1 for no
+        checkpoints (states rebuilt by stepping the leapfrog backwards).
 
         Returns a dict with J (M,) float64 and the requested gradients of
         J = sum_m J_m: dAvs (Kv, Ks) and dAsv (Ks, Kv) as float32 tensors
