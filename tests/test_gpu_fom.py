@@ -181,3 +181,35 @@ def test_offline_online_chain_reproduces_the_fom():
     assert max(chain) <= 1e-6
     rom.close()
     F.close()
+
+
+def test_fom_wide_rows_take_the_csr_kernel():
+    """Operators with a row of more than 8 entries keep the CSR kernel (no
+    padded copy); a random sparse pair with rows of 0 - 12 entries, stepped
+    and projected, against the oracle."""
+    from paper_2009_11742_amd import Fom
+    rng = np.random.default_rng(9)
+    nv, ns = 50, 70
+
+    def rand_csr(nr, nc, scale):
+        lens = rng.integers(0, 13, nr)
+        lens[3] = 12                        # at least one row wider than 8
+        ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+        col = np.concatenate([np.sort(rng.choice(nc, l, replace=False)) for l in lens]).astype(np.int32)
+        val = rng.standard_normal(int(ptr[-1])) * scale
+        return ptr, col, val
+    Av, As = rand_csr(nv, ns, 0.05), rand_csr(ns, nv, 0.05)
+    f = np.zeros(nv); f[7] = 1.0
+    mu = np.array([0.6, 0.8, 0.95])
+    F = Fom(Av, As, f, 0.1)
+    V, S = F.zeros(3)
+    F.run(torch.tensor(mu, device="cuda"), V, S, 200)
+    torch.cuda.synchronize()
+    r = oracle.fom_run(Av, As, f, 0.1, mu, 200)
+    assert _relcol(V.cpu().numpy(), r["V"]) <= 1e-12 and _relcol(S.cpu().numpy(), r["S"]) <= 1e-12
+    Pv, _ = np.linalg.qr(rng.standard_normal((nv, 9)))
+    Ps, _ = np.linalg.qr(rng.standard_normal((ns, 11)))
+    Avs, Asv, b = F.project(torch.tensor(Pv, device="cuda"), torch.tensor(Ps, device="cuda"))
+    Ar, Br, br = oracle.project(Av, As, f, Pv, Ps)
+    assert _rel(Avs.cpu().numpy(), Ar) <= 1e-12 and _rel(Asv.cpu().numpy(), Br) <= 1e-12
+    F.close()
