@@ -516,8 +516,9 @@ rom_status rom_fom_destroy(rom_fom *F);
  * (device products, host factors) into Q; the SVD of Q^T X (host Jacobi)
  * gives sigma_0 .. sigma_{r-1} and the modes Q U (device).  sigma_i for
  * i >= r is the square root of the Gram eigenvalue (inaccurate, and below
- * the rank threshold).  Synchronises `stream`; allocates 2 n ns + 2 ns^2
- * doubles plus split partials for the call.  Errors: ROM_E_ARG,
+ * the rank threshold).  The host Jacobi solves use up to 16 threads (about
+ * 0.05 s at ns = 256, 3 s at ns = 1024).  Synchronises `stream`; allocates
+ * 2 n ns + 2 ns^2 doubles plus split partials for the call.  Errors: ROM_E_ARG,
  * ROM_E_NONFINITE (zero or non-finite X), ROM_E_UNSUPPORTED (the Cholesky
  * QR of the dominant subspace failed), ROM_E_NOMEM, ROM_E_DEVICE.
  */

@@ -22,8 +22,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rom_internal.h"
@@ -127,35 +129,96 @@ void inverse_upper(const std::vector<double> &R, int n, std::vector<double> &Ri)
     }
 }
 
-// Singular values (descending, c of them) and left singular vectors of the
-// m x c column-major A by one-sided Jacobi: rotate column pairs until all
-// are orthogonal to working precision; then sigma_j = |a_j| and u_j =
-// a_j / sigma_j (U is m x c; columns of zero norm stay zero).
-void jacobi_svd_left(std::vector<double> A, int m, int c, std::vector<double> &sigma, std::vector<double> &U) {
+// One Hestenes rotation of columns p, q of the m x c column-major A:
+// makes them orthogonal; returns whether it rotated.  A column whose squared
+// norm is at most `tiny` (eps^2 times the squared Frobenius norm of A) is
+// numerically zero: rounding noise keeps such columns from ever testing
+// orthogonal, and their rotations cannot change any column above the floor,
+// so pairs with one are skipped.
+bool rotate_pair(double *A, int m, int p, int q, double tiny) {
     const double eps = 2.220446049250313e-16;
-    for (int sweep = 0; sweep < 80; ++sweep) {
-        bool rotated = false;
-        for (int p = 0; p < c - 1; ++p)
-            for (int q = p + 1; q < c; ++q) {
-                double *ap = &A[(size_t)p * m], *aq = &A[(size_t)q * m];
-                double alpha = 0.0, beta = 0.0, gamma = 0.0;
-                for (int i = 0; i < m; ++i) {
-                    alpha += ap[i] * ap[i];
-                    beta += aq[i] * aq[i];
-                    gamma += ap[i] * aq[i];
+    double *ap = A + (size_t)p * m, *aq = A + (size_t)q * m;
+    double alpha = 0.0, beta = 0.0, gamma = 0.0;
+    for (int i = 0; i < m; ++i) {
+        alpha += ap[i] * ap[i];
+        beta += aq[i] * aq[i];
+        gamma += ap[i] * aq[i];
+    }
+    if (alpha <= tiny || beta <= tiny) return false;
+    if (gamma == 0.0 || fabs(gamma) <= eps * sqrt(alpha * beta)) return false;
+    const double zeta = (beta - alpha) / (2.0 * gamma);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    for (int i = 0; i < m; ++i) {
+        const double x = ap[i], y = aq[i];
+        ap[i] = cs * x - sn * y;
+        aq[i] = sn * x + cs * y;
+    }
+    return true;
+}
+
+// Singular values (descending, c of them) and left singular vectors of the
+// m x c column-major A by one-sided Jacobi (Hestenes): rotate column pairs
+// until all are orthogonal to working precision; then sigma_j = |a_j| and
+// u_j = a_j / sigma_j (U is m x c; columns of zero norm stay zero).  Pairs
+// are visited in round-robin order (each round pairs every column with one
+// other, so its rotations touch disjoint columns), and the rounds of larger
+// problems are shared out over host threads; the order of a round does not
+// change its result, so the output does not depend on the thread count.
+void jacobi_svd_left(std::vector<double> A, int m, int c, std::vector<double> &sigma, std::vector<double> &U) {
+    double fro2 = 0.0;
+    for (size_t i = 0; i < A.size(); ++i) fro2 += A[i] * A[i];
+    const double tiny = 4.930380657631324e-32 * fro2;      // eps^2 |A|_F^2
+    const int cc = c + (c & 1);                  // even count; index c (if any) is a dummy
+    const int npair = cc / 2;
+    int nthr = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if ((double)npair * m < 32768.0) nthr = 1;   // too little work per round to share
+    nthr = std::min(nthr, std::max(1, npair / 4));
+    // circle method: position 0 fixed, the others rotate one place per round
+    std::vector<int> ring(cc);
+    for (int i = 0; i < cc; ++i) ring[i] = i;
+    std::atomic<int> arrive{0}, gen{0};
+    std::atomic<bool> rotated{false}, done{false};
+    auto barrier = [&](int nth) {
+        const int g = gen.load(std::memory_order_acquire);
+        if (arrive.fetch_add(1, std::memory_order_acq_rel) == nth - 1) {
+            arrive.store(0, std::memory_order_relaxed);
+            gen.fetch_add(1, std::memory_order_acq_rel);
+        } else {
+            while (gen.load(std::memory_order_acquire) == g) std::this_thread::yield();
+        }
+    };
+    auto worker = [&](int tid) {
+        for (int sweep = 0; sweep < 80; ++sweep) {
+            for (int r = 0; r < cc - 1; ++r) {
+                for (int k = tid; k < npair; k += nthr) {
+                    int p = ring[k], q = ring[cc - 1 - k];
+                    if (p > q) std::swap(p, q);
+                    if (q < c && rotate_pair(A.data(), m, p, q, tiny)) rotated.store(true, std::memory_order_relaxed);
                 }
-                if (gamma == 0.0 || fabs(gamma) <= eps * sqrt(alpha * beta)) continue;
-                rotated = true;
-                const double zeta = (beta - alpha) / (2.0 * gamma);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                for (int i = 0; i < m; ++i) {
-                    const double x = ap[i], y = aq[i];
-                    ap[i] = cs * x - sn * y;
-                    aq[i] = sn * x + cs * y;
+                barrier(nthr);
+                if (tid == 0) {                  // next round's pairing
+                    const int last = ring[cc - 1];
+                    for (int i = cc - 1; i > 1; --i) ring[i] = ring[i - 1];
+                    if (cc > 1) ring[1] = last;
                 }
+                barrier(nthr);
             }
-        if (!rotated) break;
+            if (tid == 0) {
+                done.store(!rotated.load(std::memory_order_relaxed), std::memory_order_relaxed);
+                rotated.store(false, std::memory_order_relaxed);
+            }
+            barrier(nthr);
+            if (done.load(std::memory_order_relaxed)) break;
+        }
+    };
+    if (nthr == 1) {
+        worker(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthr; ++t) pool.emplace_back(worker, t);
+        worker(0);
+        for (std::thread &th : pool) th.join();
     }
     std::vector<double> nrm(c);
     for (int j = 0; j < c; ++j) {
