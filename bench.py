@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--fom-point", default=None,
+                    help="fom workload: one point only, GRIDxM (e.g. 512x2048x48), timed over --steps runs")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
     ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
@@ -529,19 +531,24 @@ def workload_fom(args, torch, dev):
     N = 200
     out = {"workload": "fom: shear-wave FOM, grids 256x1024 and 512x2048, M in {1,4,16,48}, dt 0.05, 200 steps",
            "unit": "sample-steps/s", "hbm_peak_GBps": 8000.0, "points": []}
-    for nr, nth in ((256, 1024), (512, 2048)):
+    grids, Ms, runs = ((256, 1024), (512, 2048)), (1, 4, 16, 48), 3
+    if args.fom_point:
+        nr, nth, mm = (int(x) for x in args.fom_point.split("x"))
+        grids, Ms, runs = ((nr, nth),), (mm,), max(1, args.steps)
+        out["workload"] = "fom: shear-wave FOM, grid %dx%d, M = %d, dt 0.05, 200 steps" % (nr, nth, mm)
+    for nr, nth in grids:
         d = synth.make_shear_fom(nr, nth, dt=0.05)
         F = Fom(d["Av"], d["As"], d["f"], d["dt"])
         t1 = None
-        for M in (1, 4, 16, 48):
+        for M in Ms:
             mu = torch.tensor(synth.fom_periods(M, seed=M), dtype=torch.float64, device=dev)
             V, S = F.zeros(M, device=dev)
 
             def run():
                 F.run(mu, V, S, N)
-            _, ms = _events_time(torch, run, 3, 1)
+            _, ms = _events_time(torch, run, runs, 1)
             t = float(np.median(ms)) * 1e-3 / N
-            t1 = t if M == 1 else t1
+            t1 = t if M == 1 else (t1 if t1 is not None else float("nan"))
             gbs = _fom_bytes(d, M) / t / 1e9
             out["points"].append({"grid": "%dx%d" % (nr, nth), "dof": d["nv"] + d["ns"], "M": M,
                                   "us_per_step": t * 1e6, "value": M / t, "GBps": gbs, "frac_hbm": gbs / 8000.0,
