@@ -183,3 +183,86 @@ def test_fom_csr_with_empty_rows_and_one_dof():
         assert np.max(np.abs(V.cpu().numpy() - r["V"])) <= 1e-12 * max(1.0, np.abs(r["V"]).max())
         assert np.max(np.abs(S.cpu().numpy() - r["S"])) <= 1e-12 * max(1.0, np.abs(r["S"]).max())
         F.close()
+
+
+def _guarded(shape, dtype, pad=320, fill=0.0):
+    """A tensor of `shape` inside a larger buffer whose `pad` elements on each
+    side hold a sentinel: writes past the tensor's ends show up there."""
+    n = int(np.prod(shape))
+    buf = torch.full((n + 2 * pad,), 7777.0, dtype=dtype, device="cuda")
+    t = buf[pad:pad + n].view(*shape)
+    t.fill_(fill)
+    return buf, t
+
+
+def _canaries_intact(buf, n, pad=320):
+    torch.cuda.synchronize()
+    return bool(torch.all(buf[:pad] == 7777.0)) and bool(torch.all(buf[pad + n:] == 7777.0))
+
+
+@pytest.mark.parametrize("kv,ks,M,state,ops,schedule", [
+    (70, 45, 13, "f32", "f32", "columns"), (70, 45, 13, "f32", "f32", "columns8"),
+    (256, 256, 70, "f32", "f32", "rowsplit"), (256, 256, 70, "f32", "bf16", "rowsplit"),
+    (70, 45, 13, "f32", "bf16", "columns"), (33, 50, 5, "f64", "f64", "auto")])
+def test_no_writes_outside_the_outputs(kv, ks, M, state, ops, schedule):
+    """Canary-padded states, QoI and trace buffers on ragged K and M: every
+    kernel path writes only inside the arrays it is given."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=kv + M, skew=(kv == ks)), state)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state, ops=ops, schedule=schedule)
+    dt = torch.float32 if state == "f32" else torch.float64
+    N = 50
+    bV, V = _guarded((M, kv), dt)
+    bS, S = _guarded((M, ks), dt)
+    bJ, J = _guarded((M,), torch.float64)
+    by, y = _guarded((N, M), torch.float64)
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(inst["c"], dtype=dt, device="cuda")
+    rom.run_rank2(mu, V, S, N, c=c, J=J, y=y)
+    rom.check()
+    for b, t in ((bV, V), (bS, S), (bJ, J), (by, y)):
+        assert _canaries_intact(b, t.numel())
+    assert torch.all(torch.isfinite(V)) and float(V.abs().max()) > 0
+    rom.close()
+
+
+def test_no_writes_outside_the_outputs_adjoint_grouped_receivers_fom():
+    from paper_2009_11742_amd import Fom, GroupPlan, Rom, pod
+    inst = synth.round_to(synth.make_instance(70, 45, 6, seed=4, skew=False), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    out = rom.adjoint(mu, 40, c)                      # outputs allocated by the binding: compare with a guarded run
+    bV, V = _guarded((6, 70), torch.float32)
+    bS, S = _guarded((6, 45), torch.float32)
+    plan = GroupPlan([rom], [mu], [V], [S])
+    plan.run(60)
+    assert _canaries_intact(bV, V.numel()) and _canaries_intact(bS, S.numel())
+    bY, Y = _guarded((30, 3, 6), torch.float64)
+    bst, st = _guarded((30, 3, 5), torch.float64)
+    C3 = torch.tensor(np.random.default_rng(1).standard_normal((3, 70)), dtype=torch.float32, device="cuda")
+    from paper_2009_11742_amd import _lib
+    from paper_2009_11742_amd.rom import _ptr, _stream_handle
+    V.zero_(); S.zero_()
+    _lib.check(_lib.load().rom_run_receivers(rom.handle, 6, _ptr(mu), 0, 30, _ptr(V), _ptr(S), 3, _ptr(C3),
+                                             _ptr(Y), _ptr(st), _stream_handle(None)))
+    assert _canaries_intact(bY, Y.numel()) and _canaries_intact(bst, st.numel())
+    assert all(torch.all(torch.isfinite(v)) for v in out.values())
+    plan.close(); rom.close()
+    d = synth.make_shear_fom(9, 13)
+    F = Fom(d["Av"], d["As"], d["f"], d["dt"])
+    bFV, FV = _guarded((d["nv"], 3), torch.float64)
+    bFS, FS = _guarded((d["ns"], 3), torch.float64)
+    F.run(mu[:3], FV, FS, 80)
+    assert _canaries_intact(bFV, FV.numel()) and _canaries_intact(bFS, FS.numel())
+    X = torch.tensor(np.random.default_rng(2).standard_normal((d["nv"], 20)), device="cuda")
+    Phi, _, k = pod(X, kmax=7)
+    Pv = Phi.contiguous()
+    Ps = torch.tensor(np.linalg.qr(np.random.default_rng(3).standard_normal((d["ns"], 5)))[0], device="cuda")
+    bA, A = _guarded((5, 7), torch.float64)          # Kv x Ks column-major = (Ks, Kv) row-major
+    bB, B = _guarded((7, 5), torch.float64)
+    bb, bvec = _guarded((7,), torch.float64)
+    _lib.check(_lib.load().rom_fom_project(F._h, 7, 5, _ptr(Pv), _ptr(Ps), _ptr(A), _ptr(B), _ptr(bvec),
+                                           _stream_handle(None)))
+    assert _canaries_intact(bA, A.numel()) and _canaries_intact(bB, B.numel()) and _canaries_intact(bb, 7)
+    F.close()

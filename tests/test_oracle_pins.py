@@ -701,3 +701,50 @@ def test_source_kind_reaches_the_step():
     a = oracle.run_rank2(Z1, Z2, b, dt, mu, N, source="ricker")["V"]
     g = oracle.run_rank2(Z1, Z2, b, dt, mu, N, source="gauss1")["V"]
     assert np.max(np.abs(a - g)) > 1e-3
+
+
+# ---- adjoint by complex step: directional derivatives exact to rounding
+
+def _complex_J(Avs, Asv, b, dt, mu, N, c, ricker):
+    """The probe QoI of the leapfrog, written out again in complex arithmetic
+    (numpy, separate from the oracle's C): J = sum_m sum_n dt (c^T V_m)^2."""
+    kv, ks = Avs.shape
+    M = len(mu)
+    V = np.zeros((kv, M), dtype=complex)
+    S = np.zeros((ks, M), dtype=complex)
+    J = 0.0 + 0.0j
+    for n in range(N):
+        u = ricker(n * dt, mu)
+        V = V + dt * (Avs @ S + np.outer(b, u))
+        S = S + dt * (Asv @ V)
+        y = c @ V
+        J = J + dt * np.sum(y * y)
+    return J
+
+
+def _ricker_c(t, mu):
+    a = (np.pi * (mu * t - 1.5)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+@pytest.mark.parametrize("kv,ks,M,N", [(5, 4, 3, 60), (7, 7, 2, 120)])
+def test_adjoint_complex_step(kv, ks, M, N):
+    """Complex-step directional derivatives (h = 1e-30, no cancellation) of
+    the QoI along random directions of Avs, Asv and mu equal the oracle
+    adjoint's inner products to 1e-10: a pin of the adjoint far tighter than
+    finite differences (the dot-product test of the tangent and the
+    adjoint)."""
+    inst = synth.make_instance(kv, ks, M, seed=kv + N, skew=False)
+    A, B, b, dt, mu, c = inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], inst["c"]
+    adj = oracle.adjoint(A, B, b, dt, mu, N, c)
+    h = 1e-30
+    rng = np.random.default_rng(3)
+    J0 = _complex_J(A, B, b, dt, mu, N, c, _ricker_c).real
+    assert abs(J0 - np.sum(adj["J"])) <= 1e-12 * abs(J0)
+    for _ in range(2):
+        DA = rng.standard_normal(A.shape)
+        DB = rng.standard_normal(B.shape)
+        Dm = rng.standard_normal(M)
+        d = _complex_J(A + 1j * h * DA, B + 1j * h * DB, b, dt, mu + 1j * h * Dm, N, c, _ricker_c).imag / h
+        an = float(np.sum(adj["dAvs"] * DA) + np.sum(adj["dAsv"] * DB) + np.sum(adj["dmu"] * Dm))
+        assert abs(an - d) <= 1e-10 * max(abs(d), 1e-300), (an, d)
