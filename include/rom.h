@@ -242,6 +242,15 @@ void rom_tune_clear(void);
 rom_status rom_check(rom_ctx *ctx, void *stream);
 
 /*
+ * End-of-run health check: scans the states V (dev Kv x M) and S (dev Ks x
+ * M, the context's state type) for NaN or infinite values (an unstable time
+ * step, or non-finite inputs that reached the states) and returns
+ * ROM_E_NONFINITE if there is one.  Synchronises `stream`; writes nothing
+ * of the caller's.
+ */
+rom_status rom_check_finite(rom_ctx *ctx, int32_t M, const void *V, const void *S, void *stream);
+
+/*
  * Rank-1 step (Sec. 2.2 eq. (2.3); Sec. 2.3): advance ONE sample by one
  * leapfrog step at t_n = n dt, as two matrix-vector products that re-read
  * the operators from device memory.

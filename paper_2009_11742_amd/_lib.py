@@ -29,7 +29,7 @@ ROM_NSCHEDULES = 3
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_group_schedule", "rom_group_times", "rom_group_check",
-           "rom_get_operators", "rom_energy", "rom_check", "rom_last_schedule", "rom_schedule_times",
+           "rom_get_operators", "rom_energy", "rom_check", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
            "rom_fom_create", "rom_fom_run", "rom_fom_project", "rom_fom_destroy", "rom_pod",
@@ -108,6 +108,8 @@ def load():
         lib.rom_fom_destroy.argtypes = [_vp]
         lib.rom_pod.restype = C.c_int
         lib.rom_pod.argtypes = [_i64, _i32, _vp, _d, _i32, _vp, _pd, _pi32, _vp]
+        lib.rom_check_finite.restype = C.c_int
+        lib.rom_check_finite.argtypes = [_vp, _i32, _vp, _vp, _vp]
         lib.rom_group_schedule.restype = _i32
         lib.rom_group_schedule.argtypes = [_vp]
         lib.rom_group_times.restype = C.c_int

@@ -96,4 +96,26 @@ hipError_t launch_affine_combine(const double *terms, int Q, int64_t n, const Af
     return hipGetLastError();
 }
 
+namespace {
+
+// flag |= 1 if any of the n values (FP64 if f64, else FP32) is NaN or
+// infinite.
+__global__ void nonfinite_kernel(const void *__restrict__ x, int64_t n, int f64, int *__restrict__ flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = f64 ? static_cast<const double *>(x)[i] : (double)static_cast<const float *>(x)[i];
+        bad |= !isfinite(v);
+    }
+    if (bad) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+hipError_t launch_nonfinite(const void *x, int64_t n, bool f64, int *flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, n, f64 ? 1 : 0, flag);
+    return hipGetLastError();
+}
+
 }  // namespace rom

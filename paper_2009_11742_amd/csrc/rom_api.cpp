@@ -751,6 +751,23 @@ rom_status rom_check(rom_ctx *ctx, void *stream) {
     return ROM_OK;
 }
 
+rom_status rom_check_finite(rom_ctx *ctx, int32_t M, const void *V, const void *S, void *stream) {
+    if (!ctx || !V || !S) return fail(ROM_E_ARG, "rom_check_finite: NULL argument");
+    if (M < 1) return fail(ROM_E_ARG, "rom_check_finite: M must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool f64 = ctx->state_type == ROM_F64;
+    int *flag = ctx->status + 3;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    if (e == hipSuccess) e = rom::launch_nonfinite(V, (int64_t)ctx->kv * M, f64, flag, st);
+    if (e == hipSuccess) e = rom::launch_nonfinite(S, (int64_t)ctx->ks * M, f64, flag, st);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "rom_check_finite");
+    if (h) return fail(ROM_E_NONFINITE, "rom_check_finite: the states hold NaN or infinite values");
+    return ROM_OK;
+}
+
 rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu, void *stream) {
     if (!ctx || !v || !s) return fail(ROM_E_ARG, "rom_step_rank1: NULL argument");
     if (n < 0) return fail(ROM_E_ARG, "rom_step_rank1: n must be >= 0");

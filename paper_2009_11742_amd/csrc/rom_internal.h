@@ -222,6 +222,9 @@ hipError_t launch_gemm_nn(const double *X, const double *B, int64_t N, int K1, i
 rom_status api_fail(rom_status s, const std::string &msg);
 rom_status api_hip_fail(hipError_t e, const char *where);
 
+// *flag |= 1 if any of the n values is NaN or infinite.
+hipError_t launch_nonfinite(const void *x, int64_t n, bool f64, int *flag, hipStream_t st);
+
 // Affine operators: coefficients of up to kMaxAffine terms, by value.
 constexpr int kMaxAffine = 16;
 struct AffineCoeffs {

@@ -82,6 +82,13 @@ class Rom:
         self._ctx = ctx
         return self
 
+    def check_finite(self, V, S, stream=None):
+        """Raise RomError (ROM_E_NONFINITE) if V or S holds NaN or Inf."""
+        M = int(V.shape[0])
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        check(_lib.load().rom_check_finite(self._ctx, M, _ptr(V), _ptr(S), _stream_handle(stream)))
+
     def check(self, stream=None):
         """Synchronise `stream` and raise if an in-kernel wait of the work
         enqueued so far timed out (ROM_E_TIMEOUT; results invalid)."""

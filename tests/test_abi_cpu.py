@@ -260,3 +260,9 @@ def test_fom_and_pod_reject_bad_arguments():
     assert lib.rom_pod(3, 4, X, 0.0, 2, X, sig.ctypes.data_as(pd), C.byref(k), None) == E      # n < ns
     assert lib.rom_pod(10, 4, X, 0.0, 5, X, sig.ctypes.data_as(pd), C.byref(k), None) == E     # kmax > ns
     assert lib.rom_pod(10, 4, X, 1.0, 2, X, sig.ctypes.data_as(pd), C.byref(k), None) == E     # tol >= 1
+
+
+def test_check_finite_rejects_bad_arguments():
+    lib = _lib.load()
+    E = _lib.ROM_E_ARG
+    assert lib.rom_check_finite(None, 4, None, None, None) == E

@@ -266,3 +266,32 @@ def test_no_writes_outside_the_outputs_adjoint_grouped_receivers_fom():
                                            _stream_handle(None)))
     assert _canaries_intact(bA, A.numel()) and _canaries_intact(bB, B.numel()) and _canaries_intact(bb, 7)
     F.close()
+
+
+@pytest.mark.parametrize("state", ["f32", "f64"])
+def test_check_finite_reports_blown_up_states(state):
+    """rom_check_finite passes a healthy run, and flags a state that holds a
+    NaN and a run whose unstable pair (independent random Asv, long
+    horizon) overflowed."""
+    from paper_2009_11742_amd import Rom, RomError, _lib
+    inst = synth.round_to(synth.make_instance(40, 40, 4, seed=1), state)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state)
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(4)
+    rom.run_rank2(mu, V, S, 200)
+    rom.check_finite(V, S)
+    S[2, 7] = float("nan")
+    with pytest.raises(RomError) as ei:
+        rom.check_finite(V, S)
+    assert ei.value.status == _lib.ROM_E_NONFINITE
+    rom.close()
+    bad = synth.round_to(synth.make_instance(40, 40, 4, seed=2, random_asv=True), state)
+    rom = Rom(bad["Avs"], bad["Asv"], bad["b"], 4.0 * bad["dt"], state=state)
+    V, S = rom.zeros(4)
+    rom.run_rank2(mu, V, S, 20000)
+    torch.cuda.synchronize()
+    assert not bool(torch.all(torch.isfinite(V)))        # the pair did blow up
+    with pytest.raises(RomError) as ei:
+        rom.check_finite(V, S)
+    assert ei.value.status == _lib.ROM_E_NONFINITE
+    rom.close()
