@@ -360,6 +360,31 @@ def round_bf16(x):
     return np.vectorize(lambda v: lib.orc_round_bf16(float(v)))(x).astype(np.float64)
 
 
+def run_rank2_state_bf16(Avs, Asv, b, dt, mu, nsteps, V=None, S=None, n0=0, source="ricker"):
+    """The leapfrog of eq. (3.3) (Sec. 3.1) with the state operand of every
+    product rounded to BF16 (x -> FP32 -> bfloat16, RNE), the precision
+    extension's single-operand form: per step
+        V <- V + dt (Avs bf16(S) + b u(t_n; mu)^T),  then  S <- S + dt Asv bf16(V)
+    with the new V; everything else in FP64.  A plain numpy loop (the
+    rounding makes the result depend on every intermediate), for a few steps
+    on small sizes.  Returns V, S (Fortran order).
+    """
+    Avs = _f64(Avs); Asv = _f64(Asv)
+    kv, ks = Avs.shape
+    assert Asv.shape == (ks, kv)
+    mu = np.asarray(mu, dtype=np.float64).reshape(-1)
+    M = mu.size
+    b = _f64(b).reshape(kv)
+    V = np.zeros((kv, M), order="F") if V is None else np.array(V, dtype=np.float64, order="F", copy=True)
+    S = np.zeros((ks, M), order="F") if S is None else np.array(S, dtype=np.float64, order="F", copy=True)
+    signal = ricker if _src(source) == 0 else gauss1
+    for n in range(int(n0), int(n0) + int(nsteps)):
+        u = np.atleast_1d(signal(n * float(dt), mu))
+        V = V + float(dt) * (Avs @ round_bf16(S) + np.outer(b, u))
+        S = S + float(dt) * (Asv @ round_bf16(V))
+    return {"V": np.asfortranarray(V), "S": np.asfortranarray(S)}
+
+
 def quantize_e4m3(x, amax=0.0):
     """Per-tensor scaled FP8 E4M3 quantisation; returns (dequantised, scale)."""
     x = np.asarray(x, dtype=np.float64)

@@ -391,6 +391,42 @@ def test_round_bf16_matches_torch():
     assert np.array_equal(ours, ref)
 
 
+def test_state_bf16_oracle_hand_example():
+    """Two steps of the rounded-state-operand leapfrog, 1 x 1, worked by hand
+    in exact dyadic arithmetic: S0 = 1 + 2^-9 rounds to 1 (BF16 spacing 2^-7
+    on [1, 2)), V1 = 1 + 0.25 * 0.5 * 1 = 1.125, S1 = S0 - 0.125 * 1.125 =
+    0.861328125 = 220.5 * 2^-8, which rounds (tie, to even) to 0.859375;
+    V2 = 1.125 + 0.125 * 0.859375 = 1.232421875 rounds to 1.234375 (157.75 *
+    2^-7 -> 158), S2 = S1 - 0.125 * 1.234375 = 0.70703125.  The unrounded
+    leapfrog gives V1 = 1.125244140625 instead."""
+    out = oracle.run_rank2_state_bf16([[0.5]], [[-0.5]], [0.0], 0.25, [1.0], 2,
+                                      V=[[1.0]], S=[[1.0 + 2.0 ** -9]])
+    assert out["V"][0, 0] == 1.232421875
+    assert out["S"][0, 0] == 0.70703125
+    one = oracle.run_rank2_state_bf16([[0.5]], [[-0.5]], [0.0], 0.25, [1.0], 1,
+                                      V=[[1.0]], S=[[1.0 + 2.0 ** -9]])
+    assert one["V"][0, 0] == 1.125 and one["S"][0, 0] == 0.861328125
+    plain = oracle.run_rank2([[0.5]], [[-0.5]], [0.0], 0.25, [1.0], 1, V=[[1.0]], S=[[1.0 + 2.0 ** -9]])
+    assert plain["V"][0, 0] == 1.125244140625
+
+
+def test_state_bf16_oracle_forcing_unrounded():
+    """With zero operators the rounding never enters (it acts on product
+    operands only), so the model equals the plain leapfrog bitwise: the
+    forcing b u(t_n) is added in FP64 at the same step times."""
+    rng = np.random.default_rng(5)
+    kv, ks, M = 5, 3, 4
+    b = rng.standard_normal(kv)
+    mu = rng.uniform(0.5, 1.0, M)
+    V0, S0 = rng.standard_normal((kv, M)), rng.standard_normal((ks, M))
+    for source in ("ricker", "gauss1"):
+        a = oracle.run_rank2_state_bf16(np.zeros((kv, ks)), np.zeros((ks, kv)), b, 0.25, mu, 9, V=V0, S=S0,
+                                        n0=3, source=source)
+        p = oracle.run_rank2(np.zeros((kv, ks)), np.zeros((ks, kv)), b, 0.25, mu, 9, V=V0, S=S0, n0=3,
+                             source=source)
+        assert np.array_equal(a["V"], p["V"]) and np.array_equal(a["S"], p["S"])
+
+
 def test_quantize_e4m3_matches_torch():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(1)
