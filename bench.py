@@ -259,15 +259,18 @@ def _events_time(torch, fn, steps, warmup):
 
 
 def workload_precision(args, torch, dev):
-    """K = M = 1024, 5000 steps with FP32, BF16 and FP8 operators."""
+    """K = M = 1024, 5000 steps with FP32, BF16 and FP8 operators (the BF16 /
+    FP8 products with the state operand as a BF16 pair, and as one BF16
+    value: the *_single runs)."""
     import synth
     from paper_2009_11742_amd import Rom
     K, M, N = 1024, 1024, 5000
     inst = synth.round_to(synth.make_instance(K, K, M, seed=0), "f32")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
     out = {"workload": "precision: Kv=Ks=1024, M=1024, 5000 steps", "unit": "sample-steps/s", "runs": {}}
-    for ops in ("f32", "bf16", "fp8"):
-        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
+    for ops, operand in (("f32", "pair"), ("bf16", "pair"), ("fp8", "pair"), ("bf16", "single"),
+                         ("fp8", "single")):
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, state_operand=operand)
         V, S = rom.zeros(M, device=dev)
 
         def run():
@@ -277,7 +280,7 @@ def workload_precision(args, torch, dev):
         ksec = float(np.median(ms)) * 1e-3
         peak = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}[ops]
         tf = 4.0 * K * K * M * N / ksec / 1e12
-        out["runs"][ops] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf,
+        out["runs"][ops if operand == "pair" else ops + "_single"] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf,
                             "mfma_peak_tflops": peak, "frac": tf / peak, "schedule": rom.last_schedule}
         rom.close()
     return out

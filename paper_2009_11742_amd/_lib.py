@@ -22,6 +22,7 @@ ROM_SCHED_COLUMNS = 2
 ROM_SCHED_ROWSPLIT = 4
 ROM_SCHED_COLUMNS8 = 8
 ROM_SOURCE_GAUSS1 = 16
+ROM_STATE_BF16 = 32
 ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8 = range(3)
 ROM_NSCHEDULES = 3
 

@@ -16,7 +16,9 @@
 //  * State operand: each FP32 state value x is fed as the BF16 pair
 //    x_hi = bf16(x), x_lo = bf16(x - x_hi) (two MFMA passes), about 16
 //    significant bits; the products accumulate in FP32 and are folded every
-//    32 terms into a compensated (hi, lo) pair.
+//    32 terms into a compensated (hi, lo) pair.  The single-pass variant
+//    (SINGLE) feeds x_hi alone: one MFMA per operator fragment, about 8
+//    significant bits of the state per product.
 //  * State: FP32 hi/lo pairs in LDS with the double-float update of the FP32
 //    kernel; the BF16 split of every updated entry is written next to it.
 #include "k_tile_f32.h"
@@ -75,17 +77,19 @@ __device__ __forceinline__ s4 as_s4(unsigned lo, unsigned hi) {
 }
 
 // Product of one 32-term chunk for a 64 x 4 tile: A fragments `a` (8 operand
-// quads), state splits xh / xl (8 quads each, this lane's column).
+// quads), state splits xh / xl (8 quads each, this lane's column; xl unused
+// when SINGLE).
+template <bool SINGLE>
 __device__ __forceinline__ void mma_chunk_lp(const s4 (&a)[8], const s4 (&xh)[8], const s4 (&xl)[8],
                                              f4 &hi, f4 &lo) {
     f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         c0 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a[q], xh[q], c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a[q], xl[q], c1, 0, 0, 0);
+        if constexpr (!SINGLE) c1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a[q], xl[q], c1, 0, 0, 0);
     }
     tile::fold(hi, lo, c0);
-    tile::fold(hi, lo, c1);
+    if constexpr (!SINGLE) tile::fold(hi, lo, c1);
 }
 
 template <int OP>
@@ -138,7 +142,7 @@ __device__ __forceinline__ void lds_split(s4 (&x)[8], const unsigned short *col,
     }
 }
 
-template <int OP>
+template <int OP, bool SINGLE>
 __device__ __forceinline__ void tile_product_lp(const u4 *__restrict__ pk, int t, int kp,
                                                 const unsigned short *xh_col,
                                                 const unsigned short *xl_col, int lane, f4 &H,
@@ -152,22 +156,22 @@ __device__ __forceinline__ void tile_product_lp(const u4 *__restrict__ pk, int t
     f0.load(ap, 0);
     f1.load(ap, 1);
     lds_split(x0h, xh_col, 0);
-    lds_split(x0l, xl_col, 0);
+    if constexpr (!SINGLE) lds_split(x0l, xl_col, 0);
     __builtin_amdgcn_sched_barrier(0);
     for (int ch = 0; ch < nch; ch += 2) {
         lds_split(x1h, xh_col, ch + 1);
-        lds_split(x1l, xl_col, ch + 1);
+        if constexpr (!SINGLE) lds_split(x1l, xl_col, ch + 1);
         __builtin_amdgcn_sched_barrier(0);
         f0.operands(a);
-        mma_chunk_lp(a, x0h, x0l, hi, lo);
+        mma_chunk_lp<SINGLE>(a, x0h, x0l, hi, lo);
         __builtin_amdgcn_sched_barrier(0);
         const int n2 = min(ch + 2, nch - 1);
         f0.load(ap, n2);
         lds_split(x0h, xh_col, n2);
-        lds_split(x0l, xl_col, n2);
+        if constexpr (!SINGLE) lds_split(x0l, xl_col, n2);
         __builtin_amdgcn_sched_barrier(0);
         f1.operands(a);
-        mma_chunk_lp(a, x1h, x1l, hi, lo);
+        mma_chunk_lp<SINGLE>(a, x1h, x1l, hi, lo);
         __builtin_amdgcn_sched_barrier(0);
         f1.load(ap, min(ch + 3, nch - 1));
         __builtin_amdgcn_sched_barrier(0);
@@ -187,8 +191,9 @@ struct LpField {
     int ldby;
 };
 
-// (Yh, Yl) += dt * (scale * (H + L) + forcing), then refresh the BF16 split.
-template <bool FORCED>
+// (Yh, Yl) += dt * (scale * (H + L) + forcing), then refresh the BF16 split
+// (x_hi only when SINGLE).
+template <bool FORCED, bool SINGLE>
 __device__ __forceinline__ void finish_tile_lp(const LpField &f, int t, f4 H, f4 L, int lane,
                                                const float *bl, const float *cl, float uh, float ul,
                                                float dtf, float scale, double &ypart) {
@@ -223,20 +228,22 @@ __device__ __forceinline__ void finish_tile_lp(const LpField &f, int t, f4 H, f4
     *(f4 *)(f.Yh + j * f.ldy + i0) = yh;
     *(f4 *)(f.Yl + j * f.ldy + i0) = yl;
     unsigned p0 = (unsigned)sh[0] | ((unsigned)sh[1] << 16), p1 = (unsigned)sh[2] | ((unsigned)sh[3] << 16);
-    unsigned q0 = (unsigned)sl[0] | ((unsigned)sl[1] << 16), q1 = (unsigned)sl[2] | ((unsigned)sl[3] << 16);
     *reinterpret_cast<unsigned long long *>(f.Bh + j * f.ldby + i0) = (unsigned long long)p0 | ((unsigned long long)p1 << 32);
-    *reinterpret_cast<unsigned long long *>(f.Bl + j * f.ldby + i0) = (unsigned long long)q0 | ((unsigned long long)q1 << 32);
+    if constexpr (!SINGLE) {
+        unsigned q0 = (unsigned)sl[0] | ((unsigned)sl[1] << 16), q1 = (unsigned)sl[2] | ((unsigned)sl[3] << 16);
+        *reinterpret_cast<unsigned long long *>(f.Bl + j * f.ldby + i0) = (unsigned long long)q0 | ((unsigned long long)q1 << 32);
+    }
 }
 
-template <int OP, bool FORCED>
+template <int OP, bool FORCED, bool SINGLE>
 __device__ __forceinline__ void half_step_lp(const LpField &f, int lane, int w, const float *bl,
                                              const float *cl, float uh, float ul, float dtf,
                                              float scale, double &ypart) {
     const int j = lane & 3;
     for (int t = w; t < f.T; t += kWaves) {
         f4 H, L;
-        tile_product_lp<OP>(f.pk, t, f.kp, f.Xh + j * f.ldbx, f.Xl + j * f.ldbx, lane, H, L);
-        finish_tile_lp<FORCED>(f, t, H, L, lane, bl, cl, uh, ul, dtf, scale, ypart);
+        tile_product_lp<OP, SINGLE>(f.pk, t, f.kp, f.Xh + j * f.ldbx, f.Xl + j * f.ldbx, lane, H, L);
+        finish_tile_lp<FORCED, SINGLE>(f, t, H, L, lane, bl, cl, uh, ul, dtf, scale, ypart);
     }
     __syncthreads();
 }
@@ -256,7 +263,7 @@ __device__ __forceinline__ void load_field(const float *src, int K, int Kp, int 
     }
 }
 
-template <int OP>
+template <int OP, bool SINGLE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_lowp_kernel(Rank2Args a, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -302,13 +309,13 @@ void rank2_lowp_kernel(Rank2Args a, float scale) {
         const float uh = (float)u64;
         const float ul = (float)(u64 - (double)uh);
         double ypart = 0.0;
-        half_step_lp<OP, true>(fv, lane, w, bl, cl, uh, ul, dtf, scale, ypart);
+        half_step_lp<OP, true, SINGLE>(fv, lane, w, bl, cl, uh, ul, dtf, scale, ypart);
         if (probe) {
             for (int off = 4; off < 64; off <<= 1) ypart += __shfl_xor(ypart, off, 64);
             if (lane < NB) yp[w * NB + lane] = ypart;
         }
         double dummy = 0.0;
-        half_step_lp<OP, false>(fs, lane, w, bl, cl, 0.f, 0.f, dtf, scale, dummy);
+        half_step_lp<OP, false, SINGLE>(fs, lane, w, bl, cl, 0.f, 0.f, dtf, scale, dummy);
         if (probe && tid < NB && col0 + tid < a.M) {
             double yv = 0.0;
 #pragma unroll
@@ -440,19 +447,27 @@ size_t rank2_lowp_lds_bytes(int kvp, int ksp) {
 hipError_t launch_rank2_lowp(const Rank2Args &a, rom_dtype op, float scale, hipStream_t st) {
     const int blocks = (a.M + NB - 1) / NB;
     const size_t lds = rank2_lowp_lds_bytes(a.kvp, a.ksp);
-    if (op == ROM_BF16)
-        hipLaunchKernelGGL(rank2_lowp_kernel<ROM_BF16>, dim3(blocks), dim3(kThreads), lds, st, a, 1.0f);
+    if (op == ROM_BF16 && a.single)
+        hipLaunchKernelGGL((rank2_lowp_kernel<ROM_BF16, true>), dim3(blocks), dim3(kThreads), lds, st, a, 1.0f);
+    else if (op == ROM_BF16)
+        hipLaunchKernelGGL((rank2_lowp_kernel<ROM_BF16, false>), dim3(blocks), dim3(kThreads), lds, st, a, 1.0f);
+    else if (a.single)
+        hipLaunchKernelGGL((rank2_lowp_kernel<ROM_F8E4M3, true>), dim3(blocks), dim3(kThreads), lds, st, a, scale);
     else
-        hipLaunchKernelGGL(rank2_lowp_kernel<ROM_F8E4M3>, dim3(blocks), dim3(kThreads), lds, st, a, scale);
+        hipLaunchKernelGGL((rank2_lowp_kernel<ROM_F8E4M3, false>), dim3(blocks), dim3(kThreads), lds, st, a, scale);
     return hipGetLastError();
 }
 
 hipError_t rank2_lowp_configure() {
-    hipError_t e = hipFuncSetAttribute((const void *)rank2_lowp_kernel<ROM_BF16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)rank2_lowp_kernel<ROM_F8E4M3>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *fns[] = {(const void *)rank2_lowp_kernel<ROM_BF16, false>,
+                         (const void *)rank2_lowp_kernel<ROM_BF16, true>,
+                         (const void *)rank2_lowp_kernel<ROM_F8E4M3, false>,
+                         (const void *)rank2_lowp_kernel<ROM_F8E4M3, true>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_amax(const double *x, int64_t n, unsigned *out, hipStream_t st) {

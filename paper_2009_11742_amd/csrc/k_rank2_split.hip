@@ -30,7 +30,8 @@
 // 8 (l / 16) .. +7; B lane l: terms 8 (l / 16) .. +7, column l % 16;
 // D register r of lane l: row 4 (l / 16) + r, column l % 16).  Wave w of a
 // workgroup sums reduction terms [w kp/4, (w+1) kp/4) for all 64 x 64
-// outputs, with the state operand fed as x_hi + x_lo (two MFMAs); the four
+// outputs, with the state operand fed as x_hi + x_lo (two MFMAs; x_hi alone,
+// one MFMA, in the single-pass variant, which also publishes x_hi only); the four
 // FP32 partials meet in LDS, where each thread finishes 16 outputs: their
 // FP32 sum, then in FP64 the scale (FP8), forcing and the update of the
 // FP32 (hi, lo) state.
@@ -135,17 +136,20 @@ typedef const __attribute__((address_space(1))) unsigned short gbf16;   // globa
 typedef const __attribute__((address_space(1))) unsigned char gbyte;
 typedef const __attribute__((address_space(1))) u4 gu4;
 
+template <bool SINGLE>
 __device__ __forceinline__ void load_b(gbf16 *xg, int kb, unsigned loff, u4 (&bh)[4], u4 (&bl)[4]) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         gbyte *ph = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 0));
-        gbyte *pl = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 1));
         bh[cb] = *reinterpret_cast<gu4 *>(ph + loff);
-        bl[cb] = *reinterpret_cast<gu4 *>(pl + loff);
+        if constexpr (!SINGLE) {
+            gbyte *pl = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 1));
+            bl[cb] = *reinterpret_cast<gu4 *>(pl + loff);
+        }
     }
 }
 
-template <int KB>
+template <int KB, bool SINGLE>
 __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, int w, int lane,
                                          f4 (&acc)[4][4]) {
     constexpr int D = KB < kDepth ? KB : kDepth;
@@ -163,15 +167,18 @@ __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned s
     const int kb0 = w * KB;
     u4 rh[D][4], rl[D][4];
 #pragma unroll
-    for (int d = 0; d < D; ++d) load_b(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
+    for (int d = 0; d < D; ++d) load_b<SINGLE>(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const int slot = kb % D;
         u4 h[4], l[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) { h[cb] = rh[slot][cb]; l[cb] = rl[slot][cb]; }
-        if (kb + D < KB) load_b(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
+        for (int cb = 0; cb < 4; ++cb) {
+            h[cb] = rh[slot][cb];
+            if constexpr (!SINGLE) l[cb] = rl[slot][cb];
+        }
+        if (kb + D < KB) load_b<SINGLE>(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
@@ -179,14 +186,15 @@ __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned s
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(h[cb]), acc[rb][cb], 0, 0, 0);
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(l[cb]), acc[rb][cb], 0, 0, 0);
+                if constexpr (!SINGLE)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(l[cb]), acc[rb][cb], 0, 0, 0);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <int KB>
+template <int KB, bool SINGLE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_split_kernel(SplitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -279,7 +287,7 @@ void rank2_split_kernel(SplitArgs a) {
             }
             const int ln = 16 * (((16 * fs + 8 * half) % 32) / 8) + (fj & 15);
             *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 0) + 8 * ln) = ph;
-            *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 1) + 8 * ln) = pl;
+            if constexpr (!SINGLE) *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 1) + 8 * ln) = pl;
         }
     };
 
@@ -287,7 +295,7 @@ void rank2_split_kernel(SplitArgs a) {
     auto half_step = [&](int f, const u4 (&op)[4][KB], const unsigned short *xother, unsigned short *xmine,
                          double u, bool forced) -> double {
         f4 acc[4][4];
-        products<KB>(op, xother + (size_t)g * kCols * 2 * kp, w, lane, acc);
+        products<KB, SINGLE>(op, xother + (size_t)g * kCols * 2 * kp, w, lane, acc);
         float *pw = part + w * kCols * kLd;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
@@ -761,6 +769,12 @@ const void *const kSplitF32Kernels[6] = {
     (const void *)rank2_split_f32_kernel<16, false>, (const void *)rank2_split_f32_kernel<4, true>,
     (const void *)rank2_split_f32_kernel<8, true>, (const void *)rank2_split_f32_kernel<16, true>};
 
+// Low-precision kernels by (K = 256, 512, 1024) x (pair, single-pass).
+const void *const kSplitLpKernels[6] = {
+    (const void *)rank2_split_kernel<2, false>, (const void *)rank2_split_kernel<2, true>,
+    (const void *)rank2_split_kernel<4, false>, (const void *)rank2_split_kernel<4, true>,
+    (const void *)rank2_split_kernel<8, false>, (const void *)rank2_split_kernel<8, true>};
+
 }  // namespace
 
 int rank2_split_groups_per_launch(int kvp) { return 256 / (kvp / kRows); }
@@ -816,12 +830,10 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     void *args[] = {&a};
     if (f32) return launch_split_f32<false>(a.kp, args, st);
     const size_t lds = rank2_split_lds_bytes();
-    switch (a.kp) {
-    case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<2>, dim3(256), dim3(kThreads), args, lds, st);
-    case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<4>, dim3(256), dim3(kThreads), args, lds, st);
-    case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_kernel<8>, dim3(256), dim3(kThreads), args, lds, st);
-    default: return hipErrorInvalidValue;
-    }
+    const int idx = a.kp == 256 ? 0 : (a.kp == 512 ? 1 : (a.kp == 1024 ? 2 : -1));
+    if (idx < 0) return hipErrorInvalidValue;
+    return hipLaunchCooperativeKernel(kSplitLpKernels[2 * idx + (r2.single ? 1 : 0)], dim3(256), dim3(kThreads),
+                                      args, lds, st);
 }
 
 // The schedule needs all 256 workgroups resident at once, one per CU, 32 on
@@ -837,9 +849,7 @@ bool rank2_split_device_ok() {
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0) return false;
     const size_t lds = rank2_split_lds_bytes();
-    const void *k[3] = {(const void *)rank2_split_kernel<2>, (const void *)rank2_split_kernel<4>,
-                        (const void *)rank2_split_kernel<8>};
-    for (const void *f : k) {
+    for (const void *f : kSplitLpKernels) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) return false;
     }
@@ -857,12 +867,10 @@ hipError_t rank2_split_configure() {
     // bytes of static LDS, so the 160 KB maximum would be refused)
     const int lds = (int)rank2_split_lds_bytes();
     hipError_t e;
-    e = hipFuncSetAttribute((const void *)rank2_split_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)rank2_split_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)rank2_split_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
+    for (const void *f : kSplitLpKernels) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
     const int lf = (int)rank2_split_f32_lds_bytes();
     for (const void *f : kSplitF32Kernels) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf);

@@ -191,6 +191,7 @@ bool cols8_ok(const rom_ctx *ctx) {
 rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, int sched, int G, hipStream_t st) {
     hipError_t e;
     const bool lowp = ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3;
+    a.single = (lowp && (ctx->flags & ROM_STATE_BF16)) ? 1 : 0;
     if (sched == ROM_SCHEDULE_ROWSPLIT) {
         rom_status rs = prepare_split(ctx, G, st);
         if (rs != ROM_OK) return rs;
@@ -397,8 +398,10 @@ rom_status check_config(const rom_config *cfg, const char *who) {
         return fail(ROM_E_UNSUPPORTED, w + ": supported (op, state) pairs are (F64, F64), "
                                           "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
     if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 |
-                                 ROM_SOURCE_GAUSS1))
+                                 ROM_SOURCE_GAUSS1 | ROM_STATE_BF16))
         return fail(ROM_E_ARG, w + ": unknown flag bits");
+    if ((cfg->flags & ROM_STATE_BF16) && !(lowp && cfg->state_type == ROM_F32))
+        return fail(ROM_E_ARG, w + ": ROM_STATE_BF16 needs BF16 or F8E4M3 operators with F32 states");
     const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
     if (sf & (sf - 1)) return fail(ROM_E_ARG, w + ": at most one ROM_SCHED_* flag");
     return ROM_OK;

@@ -109,6 +109,9 @@ struct Rank2Args {
     int nset = 1;
     // source signal: 0 Ricker, 1 first derivative of a Gaussian
     int source = 0;
+    // BF16 / FP8 operators: 1 = the state enters the products as bf16(x)
+    // alone (one MFMA pass), 0 = as the BF16 pair (x_hi, x_lo)
+    int single = 0;
 };
 
 // Launchers (return hipSuccess or the launch error).

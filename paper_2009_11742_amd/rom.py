@@ -24,6 +24,8 @@ _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": 
 # (8-column blocks, FP32 operators)
 # source signal: the Ricker wavelet or the first derivative of a Gaussian
 _SOURCE = {"ricker": 0, "gauss1": _lib.ROM_SOURCE_GAUSS1}
+# state operand of the BF16 / FP8 products: the BF16 pair or bf16(x) alone
+_STATE_OPERAND = {"pair": 0, "single": _lib.ROM_STATE_BF16}
 _SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT,
           "columns8": _lib.ROM_SCHED_COLUMNS8}
 
@@ -50,11 +52,14 @@ class Rom:
 
     Avs (Kv x Ks), Asv (Ks x Kv) and b (Kv) are host arrays (copied).  ``state``
     is 'f64' or 'f32'; ``ops`` is the operator precision in the products
-    ('f64', 'f32', 'bf16', 'fp8'; default: the state precision).
+    ('f64', 'f32', 'bf16', 'fp8'; default: the state precision).  With BF16 /
+    FP8 operators and FP32 states, ``state_operand`` 'pair' feeds each state
+    value to the products as two BF16 values (about 16 bits), 'single' as one
+    (one MFMA pass, about 8 bits; faster, less accurate).
     """
 
     def __init__(self, Avs, Asv, b, dt, state="f32", ops=None, skew_check=False, schedule="auto", stream=None,
-                 source="ricker"):
+                 source="ricker", state_operand="pair"):
         Avs = np.asarray(Avs)
         kv, ks = Avs.shape
         self.kv, self.ks, self.dt, self.state = int(kv), int(ks), float(dt), state
@@ -63,7 +68,8 @@ class Rom:
         B = _host_f64(Asv, (ks, kv))
         bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(kv))
         self.ops = state if ops is None else ops
-        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source]
+        flags = ((_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source] |
+                 _STATE_OPERAND[state_operand])
         cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
         ctx = C.c_void_p()
         lib = _lib.load()

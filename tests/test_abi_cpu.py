@@ -120,6 +120,19 @@ def test_create_rejects_two_schedule_flags():
     assert "ROM_SCHED" in _lib.load().rom_last_error().decode()
 
 
+def test_create_rejects_state_bf16_without_lowp_operators():
+    """The single BF16 state operand exists only for BF16 / FP8 operators
+    with FP32 states; other pairs are refused before any device work."""
+    A, B, b, dt = _inst()
+    for op, st in ((_lib.ROM_F32, _lib.ROM_F32), (_lib.ROM_F64, _lib.ROM_F64), (_lib.ROM_BF16, _lib.ROM_F64),
+                   (_lib.ROM_F8E4M3, _lib.ROM_F64)):
+        cfg = _lib.RomConfig(8, 8, dt, op, st, _lib.ROM_STATE_BF16)
+        assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
+        assert "ROM_STATE_BF16" in _lib.load().rom_last_error().decode()
+    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_BF16, _lib.ROM_F32, 64)     # unknown bit
+    assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
+
+
 def test_tune_table_put_get_clear_and_file_round_trip(tmp_path):
     """The tuning table is host state: entries round-trip through put / get
     (key order) and through the text format; bad entries are refused."""

@@ -24,6 +24,10 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 SAME_INPUT_BAR = 2e-3
+# single BF16 state operand (ROM_STATE_BF16) at K = M = 1024, 5000 steps: a
+# numpy emulation (FP32 products of BF16-rounded states) gives 3.3e-2 against
+# the same-input oracle; see test_gpu_state_bf16.py for the derivation
+SINGLE_WORKLOAD_BAR = 1e-1
 
 
 def _relcol(X, R):
@@ -56,9 +60,9 @@ def test_quantized_operators_equal_oracle_rounding(ops, kv, ks, skew):
     rom.close()
 
 
-def _run(inst, ops, nsteps, cols=None):
+def _run(inst, ops, nsteps, cols=None, operand="pair"):
     from paper_2009_11742_amd import Rom
-    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, state_operand=operand)
     mu_np = inst["mu"] if cols is None else inst["mu"][cols]
     M = len(mu_np)
     mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
@@ -93,17 +97,20 @@ def test_lowp_same_input_parity(ops, kv, ks, M, N, skew):
 
 
 def test_precision_workload_k1024_m1024():
-    """K = M = 1024, 5000 steps: BF16 and FP8 operators (and FP32 for
-    reference), errors on 3 sampled columns against both oracles."""
+    """K = M = 1024, 5000 steps: BF16 and FP8 operators with the state
+    operand as a BF16 pair or as one BF16 value (and FP32 for reference),
+    errors on 3 sampled columns against both oracles."""
     inst = synth.round_to(synth.make_instance(1024, 1024, 1024, seed=0), "f32")
     N = 5000
     cols = np.array([0, 511, 1023])
     results = {}
-    for ops in ("f32", "bf16", "fp8"):
-        V, S, J, secs, (A, B, sc) = _run(inst, ops, N)
-        results[ops] = (V[:, cols], S[:, cols], J[cols], secs, A, B)
+    modes = (("f32", "pair"), ("bf16", "pair"), ("fp8", "pair"), ("bf16", "single"), ("fp8", "single"))
+    for ops, operand in modes:
+        key = ops if operand == "pair" else ops + "_single"
+        V, S, J, secs, (A, B, sc) = _run(inst, ops, N, operand=operand)
+        results[key] = (V[:, cols], S[:, cols], J[cols], secs, A, B)
         print("%s: %.1f ms per run, %.2f us per step, %.1f TFLOP/s algorithmic"
-              % (ops, secs * 1e3, secs / N * 1e6, 4.0 * 1024 ** 3 * N / secs / 1e12))
+              % (key, secs * 1e3, secs / N * 1e6, 4.0 * 1024 ** 3 * N / secs / 1e12))
 
     jobs = {"orig": (inst["Avs"], inst["Asv"]), "bf16": results["bf16"][4:6], "fp8": results["fp8"][4:6]}
 
@@ -117,8 +124,9 @@ def test_precision_workload_k1024_m1024():
     refs = {}
     for key, ci, r in outs:
         refs.setdefault(key, [None] * len(cols))[ci] = r
-    for ops in ("f32", "bf16", "fp8"):
-        V, S, J = results[ops][:3]
+    for key in results:
+        V, S, J = results[key][:3]
+        ops = key.split("_")[0]
         same_key = "orig" if ops == "f32" else ops
         e_same = max(max(_relcol(V[:, i:i + 1], refs[same_key][i]["V"]), _relcol(S[:, i:i + 1], refs[same_key][i]["S"]))
                      for i in range(len(cols)))
@@ -127,9 +135,12 @@ def test_precision_workload_k1024_m1024():
         q_same = max(abs(J[i] - refs[same_key][i]["J"][0]) / refs[same_key][i]["J"][0] for i in range(len(cols)))
         q_orig = max(abs(J[i] - refs["orig"][i]["J"][0]) / refs["orig"][i]["J"][0] for i in range(len(cols)))
         print("%s K=M=1024 N=5000: state err same-input %.2e original %.2e | QoI err same-input %.2e original %.2e"
-              % (ops, e_same, e_orig, q_same, q_orig))
-        bar = 1e-5 if ops == "f32" else SAME_INPUT_BAR
-        assert e_same <= bar and q_same <= bar
+              % (key, e_same, e_orig, q_same, q_orig))
+        if key.endswith("_single"):
+            assert 1e-3 <= e_same <= SINGLE_WORKLOAD_BAR and q_same <= SINGLE_WORKLOAD_BAR
+        else:
+            bar = 1e-5 if ops == "f32" else SAME_INPUT_BAR
+            assert e_same <= bar and q_same <= bar
 
 
 @pytest.mark.parametrize("ops", ["bf16", "fp8"])

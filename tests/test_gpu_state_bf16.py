@@ -1,0 +1,110 @@
+"""Single BF16 state operand (ROM_STATE_BF16) with BF16 / FP8-E4M3 operators.
+
+With the flag each FP32 state value enters the products as bf16(x) alone (one
+MFMA pass) instead of the pair bf16(x) + bf16(x - bf16(x)), on both the
+column-block and the row-split kernels.
+
+* One step from random FP32 states is pinned sharply.  The first half-step
+  reads the given S, which the GPU and the oracle round identically, so V
+  must match the rounded-operand oracle to FP32 accumulation error (1e-5),
+  and be clearly away from the unrounded leapfrog.  S then reads the new V,
+  where a rounding decision can flip between the GPU's and the oracle's
+  values; that costs at most one BF16 step of one operand, hence 1e-3.
+* Long runs are bounded by what the arithmetic allows.  The rounding is redone
+  every half-step, a relative perturbation of about dt ||A|| 2^-9 per step
+  that random-walks; the GPU's FP32 sums then decide different roundings than
+  any FP64 model, so no oracle follows the trajectory more closely than that
+  walk.  A numpy emulation of the test cases (FP32 products of BF16-rounded
+  states against the FP64 same-input oracle) gives 1.1e-2 to 2.4e-2; the
+  tests allow 8e-2 and require at least 1e-3, which shows that the rounding
+  took place (the two-pass pair stays below 2e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+FIRST_V_BAR = 1e-5
+FIRST_S_BAR = 1e-3
+SINGLE_BAR = 8e-2
+SINGLE_FLOOR = 1e-3
+PAIR_BAR = 2e-3
+
+
+def _relcol(X, R):
+    return float(np.max(np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)))
+
+
+def _rom(inst, ops, schedule, operand):
+    from paper_2009_11742_amd import Rom
+    return Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, schedule=schedule,
+               state_operand=operand)
+
+
+@pytest.mark.parametrize("ops", ["bf16", "fp8"])
+@pytest.mark.parametrize("schedule,kv,ks,M", [("columns", 256, 256, 64), ("rowsplit", 256, 256, 64),
+                                              ("rowsplit", 512, 512, 37), ("columns", 100, 70, 9)])
+def test_first_step_rounds_the_state_operand(ops, schedule, kv, ks, M):
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=kv + 7 * M, skew=kv == ks), "f32")
+    rng = np.random.default_rng(kv + M)
+    V0 = rng.standard_normal((kv, M)).astype(np.float32).astype(np.float64)
+    S0 = rng.standard_normal((ks, M)).astype(np.float32).astype(np.float64)
+    n0 = 8                                      # the sources are well away from zero here
+    rom = _rom(inst, ops, schedule, "single")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V = torch.tensor(V0.T.copy(), dtype=torch.float32, device="cuda")
+    S = torch.tensor(S0.T.copy(), dtype=torch.float32, device="cuda")
+    rom.run_rank2(mu, V, S, 1, n0=n0)
+    torch.cuda.synchronize()
+    assert rom.last_schedule == schedule
+    A, B, _ = rom.operators()
+    rom.close()
+    Vg = V.cpu().numpy().astype(np.float64).T
+    Sg = S.cpu().numpy().astype(np.float64).T
+    model = oracle.run_rank2_state_bf16(A, B, inst["b"], inst["dt"], inst["mu"], 1, V=V0, S=S0, n0=n0)
+    plain = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"], 1, V=V0, S=S0, n0=n0)
+    eV, eVp = _relcol(Vg, model["V"]), _relcol(Vg, plain["V"])
+    eS = _relcol(Sg, model["S"])
+    print("%s %s K=(%d,%d) M=%d: V vs rounded model %.2e, vs unrounded %.2e; S vs model %.2e"
+          % (ops, schedule, kv, ks, M, eV, eVp, eS))
+    assert eV <= FIRST_V_BAR
+    assert eVp >= 10 * FIRST_V_BAR
+    assert eS <= FIRST_S_BAR
+
+
+def _run(inst, ops, schedule, operand, N):
+    rom = _rom(inst, ops, schedule, operand)
+    M = len(inst["mu"])
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(M)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    J = torch.zeros(M, dtype=torch.float64, device="cuda")
+    rom.run_rank2(mu, V, S, N, c=c, J=J)
+    torch.cuda.synchronize()
+    A, B, _ = rom.operators()
+    rom.close()
+    return V.cpu().numpy().astype(np.float64).T, S.cpu().numpy().astype(np.float64).T, J.cpu().numpy(), A, B
+
+
+@pytest.mark.parametrize("ops", ["bf16", "fp8"])
+@pytest.mark.parametrize("kv,ks,M,N,skew,schedule", [(128, 128, 8, 2000, True, "auto"),
+                                                     (100, 70, 5, 1500, False, "auto"),
+                                                     (256, 256, 64, 1000, True, "rowsplit")])
+def test_single_operand_long_runs(ops, kv, ks, M, N, skew, schedule):
+    inst = synth.round_to(synth.make_instance(kv, ks, M, seed=3 * kv + ks, skew=skew), "f32")
+    Vs, Ss, Js, A, B = _run(inst, ops, schedule, "single", N)
+    Vp, Sp, Jp, _, _ = _run(inst, ops, schedule, "pair", N)
+    same = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    e_single = max(_relcol(Vs, same["V"]), _relcol(Ss, same["S"]))
+    e_pair = max(_relcol(Vp, same["V"]), _relcol(Sp, same["S"]))
+    eJ = float(np.max(np.abs(Js - same["J"]) / same["J"]))
+    print("%s %s K=(%d,%d) M=%d N=%d: single %.2e (QoI %.2e), pair %.2e"
+          % (ops, schedule, kv, ks, M, N, e_single, eJ, e_pair))
+    assert np.all(np.isfinite(Vs)) and np.all(np.isfinite(Ss))
+    assert SINGLE_FLOOR <= e_single <= SINGLE_BAR
+    assert eJ <= SINGLE_BAR
+    assert e_pair <= PAIR_BAR
