@@ -384,26 +384,36 @@ void rank2_split_kernel(SplitArgs a) {
 // come in k-groups of 16 terms (4 MFMA k-steps): lane l holds terms
 // 4 j + l / 16 (j = 0..3) as one float4, for the operator
 //   opf[t][w][kg][rb][lane] = op[64 t + 16 rb + l % 16][w kp/4 + 16 kg + 4 j + l / 16]
-// and for the exchanged state, per group,
-//   xf[kgg][cb][lane] = x[16 kgg + 4 j + l / 16][16 cb + l % 16]
+// and for the exchanged state, per group of NC = 16 NCB columns,
+//   xf[kgg][cb][lane] = x[16 kgg + 4 j + l / 16][16 cb + l % 16]   (cb < NCB)
 // (kgg = the global k-group), so every wave load is 1 KB contiguous.  FP32
 // chains of 64 terms are folded into FP64 sums (the products' FP32 rounding
 // then stays at the column-block kernel's level); the four wave partials
-// meet in LDS in FP64, and the state (hi, lo) of a finishing thread's 16
+// meet in LDS in FP64, and the state (hi, lo) of a finishing thread's 4 NCB
 // entries per field lives in its registers.
+//
+// Group width: each workgroup streams its 64 operator rows whatever the
+// width, while its products and exchanged reads scale with NC, so the host
+// takes the narrowest group (16, 32 or 64 columns) that still fits all
+// workgroups on the chip: at M = 256 and K = 512 that is 16 columns on 128
+// CUs instead of 64 columns on 32.  A column's state arithmetic (the
+// k-quarter per wave, the 64-term chains, the fold and the partial-sum
+// order) does not depend on NC, so every width gives bitwise the same
+// states; only the probe's FP64 row sum (4 NCB rows per thread, then a
+// shuffle tree) is associated differently.
 constexpr int kChainGroups = 4;    // k-groups per FP32 chain (64 terms)
 constexpr int kLdD = kRows + 2;    // LDS column stride of the FP64 partials (doubles)
 
 typedef const __attribute__((address_space(1))) f4 gf4;
 
-template <int KG>
+template <int KG, int NCB>
 __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, int w, int lane,
-                                             double (&acc)[4][4][4]) {
+                                             double (&acc)[4][NCB][4]) {
     constexpr int D = KG < 2 ? KG : 2;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[rb][cb][r] = 0.0;
     // opaque per-step bases (see products): no hoisted, spilled addresses
@@ -411,45 +421,46 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, i
     asm volatile("" : "+s"(ob), "+s"(xb));
     const unsigned loff = 16u * (unsigned)lane;
     gbyte *opb = reinterpret_cast<gbyte *>(ob);
-    gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KG * 4 * 1024;   // this wave's k-groups
-    auto load = [&](int kg, f4 (&a)[4], f4 (&b)[4]) {
+    gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KG * NCB * 1024;   // this wave's k-groups
+    auto load = [&](int kg, f4 (&a)[4], f4 (&b)[NCB]) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
-            b[q] = *reinterpret_cast<gf4 *>(xbb + (size_t)(kg * 4 + q) * 1024 + loff);
-        }
+        for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
+#pragma unroll
+        for (int q = 0; q < NCB; ++q) b[q] = *reinterpret_cast<gf4 *>(xbb + (size_t)(kg * NCB + q) * 1024 + loff);
     };
-    f4 ra[D][4], rbx[D][4];
+    f4 ra[D][4], rbx[D][NCB];
 #pragma unroll
     for (int d = 0; d < D; ++d) load(d, ra[d], rbx[d]);
     __builtin_amdgcn_sched_barrier(0);
-    f4 c[4][4];
+    f4 c[4][NCB];
 #pragma unroll
     for (int kg = 0; kg < KG; ++kg) {
         const int slot = kg % D;
-        f4 a[4], b[4];
+        f4 a[4], b[NCB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { a[q] = ra[slot][q]; b[q] = rbx[slot][q]; }
+        for (int q = 0; q < 4; ++q) a[q] = ra[slot][q];
+#pragma unroll
+        for (int q = 0; q < NCB; ++q) b[q] = rbx[slot][q];
         if (kg + D < KG) load(kg + D, ra[slot], rbx[slot]);
         __builtin_amdgcn_sched_barrier(0);
         if (kg % kChainGroups == 0) {
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) c[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int cb = 0; cb < NCB; ++cb) c[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
+                for (int cb = 0; cb < NCB; ++cb)
                     c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j], c[rb][cb], 0, 0, 0);
         if (kg % kChainGroups == kChainGroups - 1 || kg == KG - 1) {
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
+                for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[rb][cb][r] += (double)c[rb][cb][r];
         }
@@ -457,17 +468,28 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, i
     }
 }
 
-// GR: grouped run of many instances with the same padded K.  Group g then
-// takes its operators, source, mu, states, sizes, first sample column and
-// dt from a.grp[a.g0 + g] (the probe is off); otherwise they come from the
-// arguments and group g owns columns 64 g .. 64 g + 63.  The arithmetic of
-// a column is the same either way.
-template <int KG, bool GR>
+// GR: grouped run of many instances with the same padded K (64-column
+// groups).  Group g then takes its operators, source, mu, states, sizes,
+// first sample column and dt from a.grp[a.g0 + g] (the probe is off);
+// otherwise they come from the arguments and group g owns columns NC g ..
+// NC g + NC - 1.  The arithmetic of a column is the same either way.
+//
+// Finishing threads: TPC = 256 / NC threads per column; thread fs of column
+// fj owns the rows 16 kgl + 4 j + q0 + qq (j = 0..3, qq < NCB) of the row
+// tile, kgl = fs / (4 / NCB), q0 = NCB (fs % (4 / NCB)), as entry e = NCB j +
+// qq of its registers: with the exchange layout above, the entries of one qq
+// are the 4 terms of one lane's fragment, published as one float4.
+template <int KG, bool GR, int NCB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_split_f32_kernel(SplitArgs a) {
+    static_assert(NCB == 1 || NCB == 2 || NCB == 4, "16, 32 or 64 columns per group");
+    static_assert(!GR || NCB == 4, "grouped runs use 64-column groups");
+    constexpr int NC = 16 * NCB;               // columns per group
+    constexpr int TPC = kThreads / NC;         // finishing threads per column
+    constexpr int RPT = 4 * NCB;               // rows per finishing thread and field
     extern __shared__ __align__(16) unsigned char smem[];
     double *part = reinterpret_cast<double *>(smem);        // [wave][col][kLdD]
-    float *bl = reinterpret_cast<float *>(part + kWaves * kCols * kLdD);
+    float *bl = reinterpret_cast<float *>(part + kWaves * NC * kLdD);
     float *cl = bl + kRows;
     __shared__ int sh_slot;
 
@@ -486,7 +508,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     const int r = s % R;
     const int g = (s / R) * 8 + xcc;
     if (g >= a.G) return;
-    int kv = a.kv, M = a.M, col0 = g * kCols, src = a.source;
+    int kv = a.kv, M = a.M, col0 = g * NC, src = a.source;
     double dt = a.dt;
     const float *bsrc = a.b, *csrc = a.c;
     const double *mup = a.mu;
@@ -518,18 +540,20 @@ void rank2_split_f32_kernel(SplitArgs a) {
         bl[i] = row < kv ? bsrc[row] : 0.f;
         cl[i] = (csrc != nullptr && row < kv) ? csrc[row] : 0.f;
     }
-    // finishing thread: column fj, rows 16 fs .. 16 fs + 15; its state
-    // entries of both fields stay in registers
-    const int fj = tid >> 2, fs = tid & 3;
+    // finishing thread: column fj, RPT rows (see above); its state entries of
+    // both fields stay in registers
+    const int fj = tid / TPC, fs = tid % TPC;
+    const int kgl = fs / (4 / NCB), q0 = NCB * (fs % (4 / NCB));
+    auto frow = [&](int e) { return 16 * kgl + 4 * (e / NCB) + q0 + e % NCB; };   // row within the tile
     const int fm = col0 + fj;
     const bool fok = fm < M;
     const double fmu = fok ? mup[fm] : 1.0;
-    float sh[2][16], sl[2][16];
+    float sh[2][RPT], sl[2][RPT];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int row = row0 + 16 * fs + e;
+        for (int e = 0; e < RPT; ++e) {
+            const int row = row0 + frow(e);
             const float *src = f == 0 ? Vp : Sp;
             sh[f][e] = (fok && row < kv) ? src[(size_t)fm * kv + row] : 0.f;
             sl[f][e] = 0.f;
@@ -541,28 +565,28 @@ void rank2_split_f32_kernel(SplitArgs a) {
     const f4 *opsw = reinterpret_cast<const f4 *>(ops) + (size_t)(r * kWaves + w) * KG * 4 * 64;
     float *xv = reinterpret_cast<float *>(a.xv), *xs = reinterpret_cast<float *>(a.xs);
 
-    // publish this thread's 16 rows (hi words) of field f in fragment order:
-    // rows row0 + 16 fs + 4 j + q of column fj are term j of lane
-    // 16 q + fj % 16 in k-group (row0 + 16 fs) / 16, column block fj / 16
+    // publish this thread's rows (hi words) of field f in fragment order:
+    // row row0 + 16 kgl + 4 j + q of column fj is term j of lane 16 q + fj % 16
+    // in k-group (row0 + 16 kgl) / 16, column block fj / 16
     auto publish = [&](int f, float *x) {
-        float *xg = x + (size_t)g * kCols * kp;
-        const int kgg = (row0 + 16 * fs) / 16, cb = fj / 16;
+        float *xg = x + (size_t)g * NC * kp;
+        const int kgg = (row0 + 16 * kgl) / 16, cb = fj / 16;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const f4 v = {sh[f][q], sh[f][4 + q], sh[f][8 + q], sh[f][12 + q]};
-            *reinterpret_cast<f4 *>(xg + ((size_t)(kgg * 4 + cb) * 64 + 16 * q + (fj & 15)) * 4) = v;
+        for (int qq = 0; qq < NCB; ++qq) {
+            const f4 v = {sh[f][qq], sh[f][NCB + qq], sh[f][2 * NCB + qq], sh[f][3 * NCB + qq]};
+            *reinterpret_cast<f4 *>(xg + ((size_t)(kgg * NCB + cb) * 64 + 16 * (q0 + qq) + (fj & 15)) * 4) = v;
         }
     };
 
     auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, double u,
                          bool forced) -> double {
-        double acc[4][4][4];
-        products_f32<KG>(opw, xother + (size_t)g * kCols * kp, w, lane, acc);
-        double *pw = part + w * kCols * kLdD;
+        double acc[4][NCB][4];
+        products_f32<KG, NCB>(opw, xother + (size_t)g * NC * kp, w, lane, acc);
+        double *pw = part + w * NC * kLdD;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < NCB; ++cb) {
                 double *d = pw + (16 * cb + (lane & 15)) * kLdD + 16 * rb + 4 * (lane >> 4);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) d[rr] = acc[rb][cb][rr];
@@ -570,10 +594,10 @@ void rank2_split_f32_kernel(SplitArgs a) {
         __syncthreads();
         double ypart = 0.0;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int i = 16 * fs + e;
-            double inc = (part[(0 * kCols + fj) * kLdD + i] + part[(1 * kCols + fj) * kLdD + i]) +
-                         (part[(2 * kCols + fj) * kLdD + i] + part[(3 * kCols + fj) * kLdD + i]);
+        for (int e = 0; e < RPT; ++e) {
+            const int i = frow(e);
+            double inc = (part[(0 * NC + fj) * kLdD + i] + part[(1 * NC + fj) * kLdD + i]) +
+                         (part[(2 * NC + fj) * kLdD + i] + part[(3 * NC + fj) * kLdD + i]);
             if (forced) inc = fma((double)bl[i], u, inc);
             const double yv = fma(dt, inc, (double)sh[f][e] + (double)sl[f][e]);
             const float hv = (float)yv;
@@ -597,14 +621,15 @@ void rank2_split_f32_kernel(SplitArgs a) {
         const double u = fok ? dev::forcing(src, t, fmu) : 0.0;
         double yp = half_step(0, opvw, xs, xv, u, true);
         if (probe) {
-            yp += __shfl_xor(yp, 1, 64);
-            yp += __shfl_xor(yp, 2, 64);
-            if (fs == 0) a.yp[((size_t)g * R + r) * kCols + fj] = yp;
+            // sum over the TPC consecutive threads of column fj
+#pragma unroll
+            for (int off = 1; off < TPC; off <<= 1) yp += __shfl_xor(yp, off, 64);
+            if (fs == 0) a.yp[((size_t)g * R + r) * NC + fj] = yp;
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
             double yv = 0.0;
-            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * kCols + fj];
+            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * NC + fj];
             Jacc += dt * (yv * yv);
             if (a.y) a.y[(size_t)k * M + fm] = yv;
         }
@@ -615,8 +640,8 @@ void rank2_split_f32_kernel(SplitArgs a) {
 #pragma unroll
     for (int f = 0; f < 2; ++f)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int row = row0 + 16 * fs + e;
+        for (int e = 0; e < RPT; ++e) {
+            const int row = row0 + frow(e);
             float *dst = f == 0 ? Vp : Sp;
             if (fok && row < kv) dst[(size_t)fm * kv + row] = sh[f][e] + sl[f][e];
         }
@@ -753,21 +778,24 @@ hipError_t split_workspace(SplitArgs &a, void *ws, int G, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <bool GR>
-hipError_t launch_split_f32(int kp, void **args, hipStream_t st) {
-    const size_t lds = rank2_split_f32_lds_bytes();
-    switch (kp) {
-    case 256: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<4, GR>, dim3(256), dim3(kThreads), args, lds, st);
-    case 512: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<8, GR>, dim3(256), dim3(kThreads), args, lds, st);
-    case 1024: return hipLaunchCooperativeKernel((const void *)rank2_split_f32_kernel<16, GR>, dim3(256), dim3(kThreads), args, lds, st);
-    default: return hipErrorInvalidValue;
-    }
-}
+// FP32 kernels: single runs by (K = 256, 512, 1024) x (group width 16, 32,
+// 64 columns), then the grouped (64-column) kernels by K.
+const void *const kSplitF32Kernels[12] = {
+    (const void *)rank2_split_f32_kernel<4, false, 1>,  (const void *)rank2_split_f32_kernel<4, false, 2>,
+    (const void *)rank2_split_f32_kernel<4, false, 4>,  (const void *)rank2_split_f32_kernel<8, false, 1>,
+    (const void *)rank2_split_f32_kernel<8, false, 2>,  (const void *)rank2_split_f32_kernel<8, false, 4>,
+    (const void *)rank2_split_f32_kernel<16, false, 1>, (const void *)rank2_split_f32_kernel<16, false, 2>,
+    (const void *)rank2_split_f32_kernel<16, false, 4>, (const void *)rank2_split_f32_kernel<4, true, 4>,
+    (const void *)rank2_split_f32_kernel<8, true, 4>,   (const void *)rank2_split_f32_kernel<16, true, 4>};
 
-const void *const kSplitF32Kernels[6] = {
-    (const void *)rank2_split_f32_kernel<4, false>, (const void *)rank2_split_f32_kernel<8, false>,
-    (const void *)rank2_split_f32_kernel<16, false>, (const void *)rank2_split_f32_kernel<4, true>,
-    (const void *)rank2_split_f32_kernel<8, true>, (const void *)rank2_split_f32_kernel<16, true>};
+// wi: group width 16 << wi columns (single runs; grouped runs take 64).
+template <bool GR>
+hipError_t launch_split_f32(int kp, int wi, void **args, hipStream_t st) {
+    const int ki = kp == 256 ? 0 : (kp == 512 ? 1 : (kp == 1024 ? 2 : -1));
+    if (ki < 0 || wi < 0 || wi > 2) return hipErrorInvalidValue;
+    const void *f = GR ? kSplitF32Kernels[9 + ki] : kSplitF32Kernels[3 * ki + wi];
+    return hipLaunchCooperativeKernel(f, dim3(256), dim3(kThreads), args, rank2_split_f32_lds_bytes(), st);
+}
 
 // Low-precision kernels by (K = 256, 512, 1024) x (pair, single-pass).
 const void *const kSplitLpKernels[6] = {
@@ -797,7 +825,7 @@ hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, in
     hipError_t e = split_workspace(a, ws, G, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
-    return launch_split_f32<true>(kvp, args, st);
+    return launch_split_f32<true>(kvp, 2, args, st);
 }
 
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
@@ -828,7 +856,15 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     hipError_t e = split_workspace(a, ws, G, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
-    if (f32) return launch_split_f32<false>(a.kp, args, st);
+    if (f32) {
+        // the narrowest column group (16, 32 or 64 columns) whose workgroups
+        // all fit; the workspace, carved for G 64-column groups, covers it
+        // (ceil(M / nc) nc <= ceil(M / 64) 64)
+        int wi = 0;
+        while (wi < 2 && (int64_t)((a.M + (16 << wi) - 1) / (16 << wi)) * a.R > 256) ++wi;
+        a.G = (a.M + (16 << wi) - 1) / (16 << wi);
+        return launch_split_f32<false>(a.kp, wi, args, st);
+    }
     const size_t lds = rank2_split_lds_bytes();
     const int idx = a.kp == 256 ? 0 : (a.kp == 512 ? 1 : (a.kp == 1024 ? 2 : -1));
     if (idx < 0) return hipErrorInvalidValue;

@@ -933,9 +933,19 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     rom::Rank2Args a;
     a.b = ctx->b; a.c = c; a.mu = mu; a.kv = kv; a.ks = ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp;
     a.M = M; a.dt = ctx->dt; a.avs = ctx->avs_pk; a.asv = ctx->asv_pk; a.y = nullptr; a.source = ctx_source(ctx);
+    // The forward sweep is a plain run with a probe: it takes the schedule a
+    // rom_run_rank2 of this shape would (flags, table or tuner), e.g. the
+    // row-split kernels where they beat the column blocks.  The recompute
+    // and reverse sweeps need the traced column-block kernels.
+    int fsched = ROM_SCHEDULE_COLUMNS4, fG = 0;
+    a.V = curV; a.S = curS; a.J = J; a.n0 = 0; a.nsteps = nsteps;
+    {
+        rom_status rs = pick_schedule(ctx, a, st, fsched, fG);
+        if (rs != ROM_OK) return rs;
+    }
     if (rev) {
-        a.V = curV; a.S = curS; a.J = J; a.n0 = 0; a.nsteps = nsteps;
-        ACHK(rom::launch_rank2_f32_mfma(a, 1, st), "rom_adjoint: forward launch");
+        rom_status rs = launch_fp32_state_run(ctx, a, fsched, fG, st);
+        if (rs != ROM_OK) return rs;
     }
     for (int64_t g = 0; g < nseg && !rev; ++g) {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
@@ -943,7 +953,8 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         ACHK(hipMemcpyAsync(cg, curV, v1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
         ACHK(hipMemcpyAsync(cg + v1, curS, s1 * 4, hipMemcpyDeviceToDevice, st), "rom_adjoint: checkpoint");
         a.V = curV; a.S = curS; a.J = J; a.n0 = nb; a.nsteps = len;
-        ACHK(rom::launch_rank2_f32_mfma(a, 1, st), "rom_adjoint: forward launch");
+        rom_status rs = launch_fp32_state_run(ctx, a, fsched, fG, st);
+        if (rs != ROM_OK) return rs;
     }
     // reverse sweep, segment by segment from the last.  Segment g's state
     // and probe traces (set g % kTr) are written by its recompute (side

@@ -127,6 +127,45 @@ def test_rowsplit_f32_parity(K, M, N):
     assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
 
 
+@pytest.mark.parametrize("K,Ms", [(256, (1000, 2000, 4000)), (512, (500, 1000, 2000))])
+def test_rowsplit_f32_group_width_bitwise(K, Ms):
+    """FP32 row-split runs take the narrowest column group (16, 32 or 64
+    samples) whose R = K / 64 workgroups per group all fit in 256; the Ms
+    here select the three widths in turn.  A column's state arithmetic does
+    not depend on the width, so the shared samples (a prefix of the same mu)
+    agree bitwise in V and S; the probe's FP64 row sum is spread over 4 NCB
+    rows per thread and a shuffle tree over 16 / NCB threads, so J and the
+    trace agree to FP64 reassociation (1e-14)."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(K, K, max(Ms), seed=K + 5), "f32")
+    N = 120
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule="rowsplit")
+    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    outs = []
+    for M in Ms:
+        mu = torch.tensor(inst["mu"][:M], dtype=torch.float64, device="cuda")
+        V, S = rom.zeros(M)
+        J = torch.zeros(M, dtype=torch.float64, device="cuda")
+        y = torch.zeros((N, M), dtype=torch.float64, device="cuda")
+        rom.run_rank2(mu, V, S, N, c=c, J=J, y=y)
+        rom.check()
+        assert rom.last_schedule == "rowsplit"
+        outs.append((V.cpu().numpy(), S.cpu().numpy(), J.cpu().numpy(), y.cpu().numpy()))
+    m0 = Ms[0]
+    for V, S, J, y in outs[1:]:
+        assert np.array_equal(V[:m0], outs[0][0]) and np.array_equal(S[:m0], outs[0][1])
+        assert np.allclose(J[:m0], outs[0][2], rtol=1e-14, atol=0)
+        assert np.max(np.abs(y[:, :m0] - outs[0][3])) <= 1e-14 * np.max(np.abs(outs[0][3]))
+    cols = np.array([0, m0 // 2, m0 - 1])
+    A, B, _ = rom.operators()
+    rom.close()
+    for ci in cols:
+        r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N, c=inst["c"])
+        g = outs[0]
+        assert _relcol(g[0][ci:ci + 1].astype(np.float64).T, r["V"]) <= F32_BAR
+        assert abs(g[2][ci] - r["J"][0]) <= F32_BAR * r["J"][0]
+
+
 def test_rowsplit_f32_k1024_m1024_sampled():
     inst = synth.round_to(synth.make_instance(1024, 1024, 1024, seed=0), "f32")
     N = 600
