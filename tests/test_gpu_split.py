@@ -127,7 +127,7 @@ def test_rowsplit_f32_parity(K, M, N):
     assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
 
 
-@pytest.mark.parametrize("K,Ms", [(256, (1000, 2000, 4000)), (512, (500, 1000, 2000))])
+@pytest.mark.parametrize("K,Ms", [(256, (1000, 2000, 4000)), (512, (500, 1000, 2000)), (1024, (250, 500, 1000))])
 def test_rowsplit_f32_group_width_bitwise(K, Ms):
     """FP32 row-split runs take the narrowest column group (16, 32 or 64
     samples) whose R = K / 64 workgroups per group all fit in 256; the Ms
