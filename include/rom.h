@@ -90,10 +90,13 @@ enum {
                                streams the whole operator)                    */
     ROM_SCHED_ROWSPLIT = 4u,/* FP32-state rank-2 runs: the row-split kernels
                                (operator rows split over the workgroups of a
-                               64-sample group, exchanged every half-step)
+                               sample group, exchanged every half-step)
                                wherever they apply: Kv == Ks in {256, 512,
                                1024}, ceil(M/64) * K/64 <= 256, a 256-CU
-                               gfx950; else 4-column blocks                   */
+                               gfx950; else 4-column blocks.  Groups of 64
+                               samples with BF16 / FP8 operators; with FP32
+                               operators the narrowest of 16, 32, 64 whose
+                               ceil(M/width) * K/64 workgroups fit in 256   */
     ROM_SCHED_COLUMNS8 = 8u,/* FP32 operators and states: 8-column blocks
                                (two column sets per operator fragment) where
                                the states of 8 samples fit in LDS; else 4.
@@ -188,9 +191,10 @@ rom_status rom_destroy(rom_ctx *ctx);
  *                          whole operator; workgroups never wait for one
  *                          another;
  *   ROM_SCHEDULE_ROWSPLIT  operator rows split over the workgroups of a
- *                          64-sample group, kept in registers or streamed
- *                          per quarter, rows exchanged at a group barrier
- *                          every half-step;
+ *                          sample group (16, 32 or 64 samples, see
+ *                          ROM_SCHED_ROWSPLIT), kept in registers or
+ *                          streamed per quarter, rows exchanged at a group
+ *                          barrier every half-step;
  *   ROM_SCHEDULE_COLUMNS8  as COLUMNS4 with 8 samples per workgroup (FP32
  *                          operators): half the operator bytes per flop,
  *                          half the workgroups.  Bitwise equal to COLUMNS4.
