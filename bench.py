@@ -60,7 +60,8 @@ def main():
     ap.add_argument("--fom-point", default=None,
                     help="fom workload: one point only, GRIDxM (e.g. 512x2048x48), timed over --steps runs")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
-    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline"],
+    ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline",
+                             "forward512"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -400,6 +401,41 @@ def workload_sweep(args, torch, dev):
     return out
 
 
+def workload_forward512(args, torch, dev):
+    """The forward run at the adjoint's shape: K = 512, M = 256, 5000 steps,
+    FP32, on the schedule the tuning table gives (the row-split kernel with
+    16-sample groups on 128 CUs); median of 5 runs, error against the oracle
+    on 3 sampled columns."""
+    import oracle
+    import synth
+    from paper_2009_11742_amd import Rom
+    K, M, N = 512, 256, 5000
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=0), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    V, S = rom.zeros(M, device=dev)
+
+    def run():
+        V.zero_(); S.zero_()
+        rom.run_rank2(mu, V, S, N)
+    wall, ms = _events_time(torch, run, 5, 1)
+    rom.check()
+    ksec = float(np.median(ms)) * 1e-3
+    tf = 4.0 * K * K * M * N / ksec / 1e12
+    cols = (0, 128, 255)
+    Vg, Sg = V.cpu().numpy().astype(np.float64).T, S.cpu().numpy().astype(np.float64).T
+    err = 0.0
+    for ci in cols:
+        r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N)
+        err = max(err, _err_cols(Vg[:, ci:ci + 1], r["V"]), _err_cols(Sg[:, ci:ci + 1], r["S"]))
+    out = {"workload": "forward512: rank-2 FP32, Kv=Ks=512, M=256, 5000 steps", "unit": "sample-steps/s",
+           "value": M * N / ksec, "us_per_step": ksec / N * 1e6, "tflops": tf, "mfma_peak_tflops": 157.3,
+           "frac": tf / 157.3, "schedule": rom.last_schedule, "max_rel_err_vs_oracle": err,
+           "cols_checked": len(cols)}
+    rom.close()
+    return out
+
+
 def workload_plain(args, torch, dev):
     """The plain-method workload: K = 64, M in {1, 8}, 2000 steps, FP64
     states and operators (latency bound: two dependent half-steps per step,
@@ -600,7 +636,7 @@ def workload_offline(args, torch, dev):
             "sigma_ratio_kept": float(sv[kv - 1] / sv[0])}
 
 
-OTHER = {"precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
+OTHER = {"forward512": workload_forward512, "precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
          "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain,
          "receivers": workload_receivers, "rank3": workload_rank3, "fom": workload_fom,
          "offline": workload_offline}
