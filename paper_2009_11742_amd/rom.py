@@ -371,7 +371,7 @@ class AffineFamily:
     run_grouped)."""
 
     def __init__(self, Avs_terms, Asv_terms, b, dt, state="f32", ops=None, skew_check=False, schedule="auto",
-                 stream=None, source="ricker"):
+                 stream=None, source="ricker", state_operand="pair"):
         At = np.asarray(Avs_terms, dtype=np.float64)
         Bt = np.asarray(Asv_terms, dtype=np.float64)
         Q, kv, ks = At.shape
@@ -384,7 +384,8 @@ class AffineFamily:
         self.Q, self.kv, self.ks, self.dt, self.state = int(Q), int(kv), int(ks), float(dt), state
         code, _ = _DT[state]
         self.ops = state if ops is None else ops
-        flags = (_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source]
+        flags = ((_lib.ROM_SKEW_CHECK if skew_check else 0) | _SCHED[schedule] | _SOURCE[source] |
+                 _STATE_OPERAND[state_operand])
         cfg = RomConfig(kv, ks, float(dt), _OPS[self.ops], code, flags)
         h = C.c_void_p()
         pd = C.POINTER(C.c_double)
