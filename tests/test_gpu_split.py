@@ -1,6 +1,7 @@
 """Row-split schedule of the FP32-state rank-2 run (FP32, BF16 and FP8
-operators): operator rows split over the workgroups of a 64-sample group,
-exchanged every half-step.
+operators): operator rows split over the workgroups of a sample group (64
+samples with BF16 / FP8 operators; with FP32 the narrowest of 16, 32 and 64
+that fits the chip), exchanged every half-step.
 
 BF16 / FP8: parity against the same-input FP64 oracle (the operators exactly
 as the products use them), with the bar of the column-block low-precision
