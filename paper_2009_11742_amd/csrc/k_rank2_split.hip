@@ -10,7 +10,9 @@
 // (4 MB / 2 MB per step per CU) bounds the step far above the MFMA time.
 // Here the operator rows are split instead: the workgroups of a column
 // group (kRows = 64 rows each, R = K / 64 of them) cover K rows of both
-// fields for kCols = 64 sample columns.  Each keeps its operator rows in
+// fields for a group of samples: 16, 32 or 64 columns (the narrowest whose
+// workgroups all fit on the chip; kCols = 64 sizes the buffers).  Each keeps
+// its operator rows in
 // registers for the whole run (every wave holds a quarter of the reduction
 // of both fields as BF16 MFMA fragments: 256 registers per lane at K =
 // 1024), so no operator bytes move after the start.  The price is one
@@ -106,9 +108,14 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
         }
     }
     __syncthreads();
-    // the group's rows were written through other CUs' L1s into the shared
-    // L2: drop this CU's L1 copies before reading them
-    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    // The group's rows were written through other CUs' L1s into the shared
+    // L2.  This CU's L1 may still hold the lines of its previous read of the
+    // same addresses, so every read of data other workgroups wrote (exchange
+    // fragments, probe partials) is a device-scope load (XBuf, ld_shared),
+    // which the L1 does not serve.  An L1 invalidate here would do too, but only in
+    // its agent-scope form (the workgroup-scope one does not reach the L1
+    // outside threadgroup-split mode), and that one costs several us per
+    // barrier.
 }
 
 // Products of one half-step for wave w: acc[rb][cb] (rows 16 rb.., columns
@@ -121,70 +128,95 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
 // kernel's register pressure.
 constexpr int kDepth = 2;
 
-// Exchange layout: per group, [k-block (kp/32)][column block (4)][hi | lo]
-// [lane (64)][8 terms], lane = 16 ((k % 32) / 8) + column % 16 -- exactly the
-// B fragments, so one wave load reads 1 KB contiguous.  Offset (in BF16
-// elements) of fragment (kb, cb, hl) within a group's block:
+// Exchange layout: per group of NCB 16-column blocks, [k-block (kp/32)]
+// [column block (NCB)][hi | lo][lane (64)][8 terms], lane = 16 ((k % 32) / 8)
+// + column % 16 -- exactly the B fragments, so one wave load reads 1 KB
+// contiguous.  Offset (in BF16 elements) of fragment (kb, cb, hl) within a
+// group's block:
+template <int NCB>
 __device__ __forceinline__ size_t frag_offset(int kb, int cb, int hl) {
-    return ((size_t)(kb * 4 + cb) * 2 + hl) * 512;
+    return ((size_t)(kb * NCB + cb) * 2 + hl) * 512;
 }
 
-// (the fragment base is wave-uniform and the lane offset an unsigned 32-bit
-// value, so the loads take the scalar-base + vector-offset form and need no
-// 64-bit address registers)
-typedef const __attribute__((address_space(1))) unsigned short gbf16;   // global memory
+// Global memory bytes: with a wave-uniform base and an unsigned 32-bit lane
+// offset, loads take the scalar-base + vector-offset form and need no 64-bit
+// address registers (the FP32 operator stream).
 typedef const __attribute__((address_space(1))) unsigned char gbyte;
-typedef const __attribute__((address_space(1))) u4 gu4;
 
-template <bool SINGLE>
-__device__ __forceinline__ void load_b(gbf16 *xg, int kb, unsigned loff, u4 (&bh)[4], u4 (&bl)[4]) {
+// A group's exchange block, read with 16-byte buffer loads under the
+// device-scope cache policy (sc1): the vector L1 does not serve them from
+// lines it kept from an earlier read of the same addresses, which other
+// workgroups have rewritten since.  The base is wave-uniform; offsets are in
+// bytes, and one past the block reads zeros (the buffer's bound) instead of
+// faulting.
+constexpr int kDeviceScope = 16;             // cache-policy bit SC1
+constexpr int kRawBufferWord3 = 0x00020000;  // untyped 32-bit data format
+struct XBuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ XBuf(uint64_t base, unsigned bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(base), (short)0, (int)bytes, kRawBufferWord3)) {}
+    __device__ __forceinline__ u4 ld(unsigned off) const {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kDeviceScope);
+    }
+};
+
+// The same guarantee as two relaxed device-scope 8-byte loads
+// (global_load_dwordx2 ... sc1), which the FP32 kernel's long unrolled
+// k-group loop schedules better (measured: 41 against 48 us per step at K =
+// M = 1024; the BF16 kernel is faster with XBuf).
+typedef const __attribute__((address_space(1))) unsigned long long gu64;
+__device__ __forceinline__ u4 ld_shared(gbyte *p) {
+    const gu64 *q = reinterpret_cast<const gu64 *>(p);
+    const unsigned long long lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return u4{(unsigned)lo, (unsigned)(lo >> 32), (unsigned)hi, (unsigned)(hi >> 32)};
+}
+
+template <bool SINGLE, int NCB>
+__device__ __forceinline__ void load_b(const XBuf &xg, int kb, unsigned loff, u4 (&bh)[NCB], u4 (&bl)[NCB]) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        gbyte *ph = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 0));
-        bh[cb] = *reinterpret_cast<gu4 *>(ph + loff);
-        if constexpr (!SINGLE) {
-            gbyte *pl = reinterpret_cast<gbyte *>(xg + frag_offset(kb, cb, 1));
-            bl[cb] = *reinterpret_cast<gu4 *>(pl + loff);
-        }
+    for (int cb = 0; cb < NCB; ++cb) {
+        bh[cb] = xg.ld(2u * (unsigned)frag_offset<NCB>(kb, cb, 0) + loff);
+        if constexpr (!SINGLE) bl[cb] = xg.ld(2u * (unsigned)frag_offset<NCB>(kb, cb, 1) + loff);
     }
 }
 
-template <int KB, bool SINGLE>
-__device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, int w, int lane,
-                                         f4 (&acc)[4][4]) {
+template <int KB, bool SINGLE, int NCB>
+__device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, unsigned xbytes, int w,
+                                         int lane, f4 (&acc)[4][NCB]) {
     constexpr int D = KB < kDepth ? KB : kDepth;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
     // The fragment addresses are the same every step; without this opaque
     // redefinition of the base the compiler hoists all of them out of the
     // time loop and spills them.
     uint64_t bits = reinterpret_cast<uint64_t>(x);
     asm volatile("" : "+s"(bits));
-    gbf16 *xg = reinterpret_cast<gbf16 *>(bits);
+    const XBuf xg(bits, xbytes);
     // this wave's k-blocks are w KB .. w KB + KB - 1 of the group's block
     const int kb0 = w * KB;
-    u4 rh[D][4], rl[D][4];
+    u4 rh[D][NCB], rl[D][NCB];
 #pragma unroll
-    for (int d = 0; d < D; ++d) load_b<SINGLE>(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
+    for (int d = 0; d < D; ++d) load_b<SINGLE, NCB>(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const int slot = kb % D;
-        u4 h[4], l[4];
+        u4 h[NCB], l[NCB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < NCB; ++cb) {
             h[cb] = rh[slot][cb];
             if constexpr (!SINGLE) l[cb] = rl[slot][cb];
         }
-        if (kb + D < KB) load_b<SINGLE>(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
+        if (kb + D < KB) load_b<SINGLE, NCB>(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
             const bf8 A = as_bf8(op[rb][kb]);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < NCB; ++cb) {
                 acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(h[cb]), acc[rb][cb], 0, 0, 0);
                 if constexpr (!SINGLE)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(l[cb]), acc[rb][cb], 0, 0, 0);
@@ -194,14 +226,20 @@ __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned s
     }
 }
 
-template <int KB, bool SINGLE>
+// NCB: 16-column blocks per group (NC = 16 NCB samples).  Finishing
+// threads: TPC = 256 / NC per column, each owning RPT = 4 NCB consecutive rows
+// of the tile, published in runs of 8 rows (one lane's B fragment) or 4 (half
+// of one).
+template <int KB, bool SINGLE, int NCB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_split_kernel(SplitArgs a) {
+    static_assert(NCB == 1 || NCB == 2 || NCB == 4, "16, 32 or 64 columns per group");
+    constexpr int NC = 16 * NCB, TPC = kThreads / NC, RPT = 4 * NCB;
     extern __shared__ __align__(16) unsigned char smem[];
     float *sth = reinterpret_cast<float *>(smem);          // [field][col][kLd] hi
-    float *stl = sth + 2 * kCols * kLd;                     // lo
-    float *part = stl + 2 * kCols * kLd;                    // [wave][col][kLd]
-    float *bl = part + kWaves * kCols * kLd;                // own rows of b
+    float *stl = sth + 2 * NC * kLd;                     // lo
+    float *part = stl + 2 * NC * kLd;                    // [wave][col][kLd]
+    float *bl = part + kWaves * NC * kLd;                // own rows of b
     float *cl = bl + kRows;                                 // own rows of c
     __shared__ int sh_slot;
 
@@ -221,7 +259,7 @@ void rank2_split_kernel(SplitArgs a) {
     const int r = s % R;                       // row tile
     const int g = (s / R) * 8 + xcc;           // group, interleaved over the XCDs
     if (g >= a.G) return;                      // idle workgroup (never counted)
-    const int col0 = g * kCols;
+    const int col0 = g * NC;
     unsigned *cnt = a.cnt + (size_t)g * kCntStride;
     unsigned phase = 0;
 
@@ -241,15 +279,15 @@ void rank2_split_kernel(SplitArgs a) {
 
     // ---- own tiles of V and S, b, c
     const int row0 = r * kRows;
-    for (int idx = tid; idx < 2 * kCols * kRows; idx += kThreads) {
-        const int f = idx / (kCols * kRows), rem = idx - f * kCols * kRows;
+    for (int idx = tid; idx < 2 * NC * kRows; idx += kThreads) {
+        const int f = idx / (NC * kRows), rem = idx - f * NC * kRows;
         const int j = rem / kRows, i = rem - j * kRows;
         const int m = col0 + j, row = row0 + i;
         const float *src = f == 0 ? a.V : a.S;
         float v = 0.f;
         if (m < a.M && row < a.kv) v = src[(size_t)m * a.kv + row];
-        sth[(f * kCols + j) * kLd + i] = v;
-        stl[(f * kCols + j) * kLd + i] = 0.f;
+        sth[(f * NC + j) * kLd + i] = v;
+        stl[(f * NC + j) * kLd + i] = 0.f;
     }
     for (int i = tid; i < kRows; i += kThreads) {
         const int row = row0 + i;
@@ -258,65 +296,75 @@ void rank2_split_kernel(SplitArgs a) {
     }
     __syncthreads();
 
-    // finishing thread: column fj, rows 16 fs .. 16 fs + 15
-    const int fj = tid >> 2, fs = tid & 3;
+    // finishing thread: column fj, rows RPT fs .. RPT fs + RPT - 1
+    const int fj = tid / TPC, fs = tid % TPC;
     const int fm = col0 + fj;
     const bool fok = fm < a.M;
     const double fmu = fok ? a.mu[fm] : 1.0;
 
     // publish rows of field f (hi words) as BF16 (hi, lo) into x, in the
-    // B-fragment order: rows row0 + 16 fs + 8 h + e (h = 0, 1) of column fj
-    // are terms e of lane 16 (((16 fs + 8 h) % 32) / 8) + fj % 16 of k-block
-    // (row0 + 16 fs) / 32, column block fj / 16
+    // B-fragment order: tile row o of column fj is term o % 8 of lane
+    // 16 ((o % 32) / 8) + fj % 16 of k-block (row0 + o) / 32, column block
+    // fj / 16 (row0 is a multiple of 32)
     auto publish = [&](int f, unsigned short *x) {
-        const float *h = sth + (f * kCols + fj) * kLd + 16 * fs;
-        unsigned short *xg = x + (size_t)g * kCols * 2 * kp;
-        const int kb = (row0 + 16 * fs) / 32, cb = fj / 16;
+        constexpr int CH = RPT < 8 ? RPT : 8;      // rows per store
+        const float *h = sth + (f * NC + fj) * kLd + RPT * fs;
+        unsigned short *xg = x + (size_t)g * NC * 2 * kp;
+        const int cb = fj / 16;
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            u4 ph, pl;
+        for (int c = 0; c < RPT / CH; ++c) {
+            unsigned ph[CH / 2], pl[CH / 2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < CH / 2; ++q) {
                 // hardware round-to-nearest-even, two values per instruction
-                const f2 v = {h[8 * half + 2 * q], h[8 * half + 2 * q + 1]};
+                const f2 v = {h[CH * c + 2 * q], h[CH * c + 2 * q + 1]};
                 const bf2 hi = __builtin_convertvector(v, bf2);
                 const f2 r = v - __builtin_convertvector(hi, f2);
                 const bf2 lo = __builtin_convertvector(r, bf2);
                 ph[q] = __builtin_bit_cast(unsigned, hi);
                 pl[q] = __builtin_bit_cast(unsigned, lo);
             }
-            const int ln = 16 * (((16 * fs + 8 * half) % 32) / 8) + (fj & 15);
-            *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 0) + 8 * ln) = ph;
-            if constexpr (!SINGLE) *reinterpret_cast<u4 *>(xg + frag_offset(kb, cb, 1) + 8 * ln) = pl;
+            const int o = RPT * fs + CH * c;
+            const int kb = (row0 + o) / 32, ln = 16 * ((o % 32) / 8) + (fj & 15);
+            unsigned short *dh = xg + frag_offset<NCB>(kb, cb, 0) + 8 * ln + o % 8;
+            unsigned short *dl = xg + frag_offset<NCB>(kb, cb, 1) + 8 * ln + o % 8;
+            if constexpr (CH == 8) {
+                *reinterpret_cast<u4 *>(dh) = u4{ph[0], ph[1], ph[2], ph[3]};
+                if constexpr (!SINGLE) *reinterpret_cast<u4 *>(dl) = u4{pl[0], pl[1], pl[2], pl[3]};
+            } else {
+                typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<u2 *>(dh) = u2{ph[0], ph[1]};
+                if constexpr (!SINGLE) *reinterpret_cast<u2 *>(dl) = u2{pl[0], pl[1]};
+            }
         }
     };
 
     // products -> LDS partials -> finished rows (FP64 update) -> published
     auto half_step = [&](int f, const u4 (&op)[4][KB], const unsigned short *xother, unsigned short *xmine,
                          double u, bool forced) -> double {
-        f4 acc[4][4];
-        products<KB, SINGLE>(op, xother + (size_t)g * kCols * 2 * kp, w, lane, acc);
-        float *pw = part + w * kCols * kLd;
+        f4 acc[4][NCB];
+        products<KB, SINGLE, NCB>(op, xother + (size_t)g * NC * 2 * kp, 2u * NC * 2 * kp, w, lane, acc);
+        float *pw = part + w * NC * kLd;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < NCB; ++cb)
                 *reinterpret_cast<f4 *>(pw + (16 * cb + (lane & 15)) * kLd + 16 * rb + 4 * (lane >> 4)) = acc[rb][cb];
         __syncthreads();
         double ypart = 0.0;
-        float *h = sth + (f * kCols + fj) * kLd + 16 * fs;
-        float *l = stl + (f * kCols + fj) * kLd + 16 * fs;
+        float *h = sth + (f * NC + fj) * kLd + RPT * fs;
+        float *l = stl + (f * NC + fj) * kLd + RPT * fs;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f4 p0 = *reinterpret_cast<const f4 *>(part + (0 * kCols + fj) * kLd + 16 * fs + 4 * q);
-            f4 p1 = *reinterpret_cast<const f4 *>(part + (1 * kCols + fj) * kLd + 16 * fs + 4 * q);
-            f4 p2 = *reinterpret_cast<const f4 *>(part + (2 * kCols + fj) * kLd + 16 * fs + 4 * q);
-            f4 p3 = *reinterpret_cast<const f4 *>(part + (3 * kCols + fj) * kLd + 16 * fs + 4 * q);
+        for (int q = 0; q < RPT / 4; ++q) {
+            f4 p0 = *reinterpret_cast<const f4 *>(part + (0 * NC + fj) * kLd + RPT * fs + 4 * q);
+            f4 p1 = *reinterpret_cast<const f4 *>(part + (1 * NC + fj) * kLd + RPT * fs + 4 * q);
+            f4 p2 = *reinterpret_cast<const f4 *>(part + (2 * NC + fj) * kLd + RPT * fs + 4 * q);
+            f4 p3 = *reinterpret_cast<const f4 *>(part + (3 * NC + fj) * kLd + RPT * fs + 4 * q);
             f4 hh = *reinterpret_cast<const f4 *>(h + 4 * q);
             f4 ll = *reinterpret_cast<const f4 *>(l + 4 * q);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int i = 16 * fs + 4 * q + e;
+                const int i = RPT * fs + 4 * q + e;
                 // the wave partials are FP32 chain sums; one more FP32 rounding is
                 // far below the BF16 state operand's
                 double inc = (double)((p0[e] + p1[e]) + (p2[e] + p3[e])) * (double)a.scale;
@@ -346,15 +394,16 @@ void rank2_split_kernel(SplitArgs a) {
         const double u = fok ? dev::forcing(a.source, t, fmu) : 0.0;
         double yp = half_step(0, opv, a.xs, a.xv, u, true);
         if (probe) {
-            // sum the 4 strips of column fj, then publish this tile's partial
-            yp += __shfl_xor(yp, 1, 64);
-            yp += __shfl_xor(yp, 2, 64);
-            if (fs == 0) a.yp[((size_t)g * R + r) * kCols + fj] = yp;
+            // sum the TPC strips of column fj, then publish this tile's partial
+#pragma unroll
+            for (int off = 1; off < TPC; off <<= 1) yp += __shfl_xor(yp, off, 64);
+            if (fs == 0) a.yp[((size_t)g * R + r) * NC + fj] = yp;
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
             double yv = 0.0;
-            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * kCols + fj];
+            for (int q = 0; q < R; ++q)
+                yv += __hip_atomic_load(&a.yp[((size_t)g * R + q) * NC + fj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             Jacc += a.dt * (yv * yv);
             if (a.y) a.y[(size_t)k * a.M + fm] = yv;
         }
@@ -363,13 +412,13 @@ void rank2_split_kernel(SplitArgs a) {
     }
 
     // ---- write back (hi + lo), J
-    for (int idx = tid; idx < 2 * kCols * kRows; idx += kThreads) {
-        const int f = idx / (kCols * kRows), rem = idx - f * kCols * kRows;
+    for (int idx = tid; idx < 2 * NC * kRows; idx += kThreads) {
+        const int f = idx / (NC * kRows), rem = idx - f * NC * kRows;
         const int j = rem / kRows, i = rem - j * kRows;
         const int m = col0 + j, row = row0 + i;
         if (m < a.M && row < a.kv) {
             float *dst = f == 0 ? a.V : a.S;
-            dst[(size_t)m * a.kv + row] = sth[(f * kCols + j) * kLd + i] + stl[(f * kCols + j) * kLd + i];
+            dst[(size_t)m * a.kv + row] = sth[(f * NC + j) * kLd + i] + stl[(f * NC + j) * kLd + i];
         }
     }
     if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
@@ -407,7 +456,7 @@ constexpr int kLdD = kRows + 2;    // LDS column stride of the FP64 partials (do
 typedef const __attribute__((address_space(1))) f4 gf4;
 
 template <int KG, int NCB>
-__device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, int w, int lane,
+__device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, unsigned xbytes, int w, int lane,
                                              double (&acc)[4][NCB][4]) {
     constexpr int D = KG < 2 ? KG : 2;
 #pragma unroll
@@ -421,12 +470,14 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, i
     asm volatile("" : "+s"(ob), "+s"(xb));
     const unsigned loff = 16u * (unsigned)lane;
     gbyte *opb = reinterpret_cast<gbyte *>(ob);
+    (void)xbytes;
     gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KG * NCB * 1024;   // this wave's k-groups
     auto load = [&](int kg, f4 (&a)[4], f4 (&b)[NCB]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
 #pragma unroll
-        for (int q = 0; q < NCB; ++q) b[q] = *reinterpret_cast<gf4 *>(xbb + (size_t)(kg * NCB + q) * 1024 + loff);
+        for (int q = 0; q < NCB; ++q)
+            b[q] = __builtin_bit_cast(f4, ld_shared(xbb + (size_t)(kg * NCB + q) * 1024 + loff));
     };
     f4 ra[D][4], rbx[D][NCB];
 #pragma unroll
@@ -581,7 +632,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, double u,
                          bool forced) -> double {
         double acc[4][NCB][4];
-        products_f32<KG, NCB>(opw, xother + (size_t)g * NC * kp, w, lane, acc);
+        products_f32<KG, NCB>(opw, xother + (size_t)g * NC * kp, 4u * NC * kp, w, lane, acc);
         double *pw = part + w * NC * kLdD;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
@@ -629,7 +680,8 @@ void rank2_split_f32_kernel(SplitArgs a) {
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
             double yv = 0.0;
-            for (int q = 0; q < R; ++q) yv += a.yp[((size_t)g * R + q) * NC + fj];
+            for (int q = 0; q < R; ++q)
+                yv += __hip_atomic_load(&a.yp[((size_t)g * R + q) * NC + fj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             Jacc += dt * (yv * yv);
             if (a.y) a.y[(size_t)k * M + fm] = yv;
         }
@@ -797,11 +849,24 @@ hipError_t launch_split_f32(int kp, int wi, void **args, hipStream_t st) {
     return hipLaunchCooperativeKernel(f, dim3(256), dim3(kThreads), args, rank2_split_f32_lds_bytes(), st);
 }
 
-// Low-precision kernels by (K = 256, 512, 1024) x (pair, single-pass).
-const void *const kSplitLpKernels[6] = {
-    (const void *)rank2_split_kernel<2, false>, (const void *)rank2_split_kernel<2, true>,
-    (const void *)rank2_split_kernel<4, false>, (const void *)rank2_split_kernel<4, true>,
-    (const void *)rank2_split_kernel<8, false>, (const void *)rank2_split_kernel<8, true>};
+// Low-precision kernels by (K = 256, 512, 1024) x (pair, single-pass) x
+// (group width 16, 32, 64 columns).
+#define ROM_LP_WIDTHS(KB, SG)                                                           \
+    (const void *)rank2_split_kernel<KB, SG, 1>, (const void *)rank2_split_kernel<KB, SG, 2>, \
+        (const void *)rank2_split_kernel<KB, SG, 4>
+const void *const kSplitLpKernels[18] = {ROM_LP_WIDTHS(2, false), ROM_LP_WIDTHS(2, true),
+                                         ROM_LP_WIDTHS(4, false), ROM_LP_WIDTHS(4, true),
+                                         ROM_LP_WIDTHS(8, false), ROM_LP_WIDTHS(8, true)};
+#undef ROM_LP_WIDTHS
+
+// Width index (group width 16 << wi columns) of the narrowest group whose
+// ceil(M / width) x R workgroups fit in 256; the caller's G x R <= 256 for
+// 64-column groups guarantees that one fits.
+int split_width_index(int M, int R) {
+    int wi = 0;
+    while (wi < 2 && (int64_t)((M + (16 << wi) - 1) / (16 << wi)) * R > 256) ++wi;
+    return wi;
+}
 
 }  // namespace
 
@@ -856,20 +921,17 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     hipError_t e = split_workspace(a, ws, G, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
-    if (f32) {
-        // the narrowest column group (16, 32 or 64 columns) whose workgroups
-        // all fit; the workspace, carved for G 64-column groups, covers it
-        // (ceil(M / nc) nc <= ceil(M / 64) 64)
-        int wi = 0;
-        while (wi < 2 && (int64_t)((a.M + (16 << wi) - 1) / (16 << wi)) * a.R > 256) ++wi;
-        a.G = (a.M + (16 << wi) - 1) / (16 << wi);
-        return launch_split_f32<false>(a.kp, wi, args, st);
-    }
+    // the narrowest column group (16, 32 or 64 columns) whose workgroups all
+    // fit; the workspace, carved for G 64-column groups, covers it
+    // (ceil(M / nc) nc <= ceil(M / 64) 64)
+    const int wi = split_width_index(a.M, a.R);
+    a.G = (a.M + (16 << wi) - 1) / (16 << wi);
+    if (f32) return launch_split_f32<false>(a.kp, wi, args, st);
     const size_t lds = rank2_split_lds_bytes();
     const int idx = a.kp == 256 ? 0 : (a.kp == 512 ? 1 : (a.kp == 1024 ? 2 : -1));
     if (idx < 0) return hipErrorInvalidValue;
-    return hipLaunchCooperativeKernel(kSplitLpKernels[2 * idx + (r2.single ? 1 : 0)], dim3(256), dim3(kThreads),
-                                      args, lds, st);
+    return hipLaunchCooperativeKernel(kSplitLpKernels[6 * idx + 3 * (r2.single ? 1 : 0) + wi], dim3(256),
+                                      dim3(kThreads), args, lds, st);
 }
 
 // The schedule needs all 256 workgroups resident at once, one per CU, 32 on

@@ -128,9 +128,11 @@ def test_rowsplit_f32_parity(K, M, N):
     assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
 
 
-@pytest.mark.parametrize("K,Ms", [(256, (1000, 2000, 4000)), (512, (500, 1000, 2000)), (1024, (250, 500, 1000))])
-def test_rowsplit_f32_group_width_bitwise(K, Ms):
-    """FP32 row-split runs take the narrowest column group (16, 32 or 64
+@pytest.mark.parametrize("ops,K,Ms", [("f32", 256, (1000, 2000, 4000)), ("f32", 512, (500, 1000, 2000)),
+                                      ("f32", 1024, (250, 500, 1000)), ("bf16", 512, (500, 1000, 2000)),
+                                      ("bf16", 1024, (250, 500, 1000))])
+def test_rowsplit_group_width_bitwise(ops, K, Ms):
+    """Row-split runs take the narrowest column group (16, 32 or 64
     samples) whose R = K / 64 workgroups per group all fit in 256; the Ms
     here select the three widths in turn.  A column's state arithmetic does
     not depend on the width, so the shared samples (a prefix of the same mu)
@@ -140,7 +142,7 @@ def test_rowsplit_f32_group_width_bitwise(K, Ms):
     from paper_2009_11742_amd import Rom
     inst = synth.round_to(synth.make_instance(K, K, max(Ms), seed=K + 5), "f32")
     N = 120
-    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule="rowsplit")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, schedule="rowsplit")
     c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
     outs = []
     for M in Ms:
@@ -160,11 +162,12 @@ def test_rowsplit_f32_group_width_bitwise(K, Ms):
     cols = np.array([0, m0 // 2, m0 - 1])
     A, B, _ = rom.operators()
     rom.close()
+    bar = F32_BAR if ops == "f32" else BAR
     for ci in cols:
         r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N, c=inst["c"])
         g = outs[0]
-        assert _relcol(g[0][ci:ci + 1].astype(np.float64).T, r["V"]) <= F32_BAR
-        assert abs(g[2][ci] - r["J"][0]) <= F32_BAR * r["J"][0]
+        assert _relcol(g[0][ci:ci + 1].astype(np.float64).T, r["V"]) <= bar
+        assert abs(g[2][ci] - r["J"][0]) <= bar * r["J"][0]
 
 
 def test_rowsplit_f32_k1024_m1024_sampled():
