@@ -50,6 +50,9 @@ def _run(inst, ops, N, schedule, probe=True, trace=False, n_split=None):
     return out
 
 
+# (256, 100): 16-sample groups whose exchange reads (32 KB per half-step)
+# fit in a CU's L1 -- the case that caught exchange lines served stale from
+# the L1 when the barrier's invalidate did not reach it.
 @pytest.mark.parametrize("ops", ["bf16", "fp8"])
 @pytest.mark.parametrize("K,M,N", [(256, 100, 1500), (512, 64, 800), (256, 200, 600)])
 def test_rowsplit_same_input_parity(ops, K, M, N):
