@@ -30,21 +30,39 @@ NSTEPS = 10000
 SEED = 0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
-# HBM bytes per launch of the rank-2 kernel at this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy
-# (factors 2.0 and 1.0); valid only for the kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha1": "fc1d167ba1c60b4cffde49fcd47937f7c17e8d02", "bytes": 5.516e6}
-KERNEL_SOURCES = ("paper_2009_11742_amd/csrc/k_rank2_f32.hip", "paper_2009_11742_amd/csrc/k_tile_f32.h",
-                  "paper_2009_11742_amd/csrc/k_common.h")
+# Kernel of each FP32 schedule (rom_last_schedule), its sources, and the HBM
+# bytes per launch at the bench workload from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a plain 256 MiB copy (factors 2.0 and
+# 1.0), valid only for the kernel sources they were taken on.
+SCHEDULE_KERNELS = {
+    "columns": ("rank2_f32_mfma_kernel", ("paper_2009_11742_amd/csrc/k_rank2_f32.hip",
+                                          "paper_2009_11742_amd/csrc/k_tile_f32.h",
+                                          "paper_2009_11742_amd/csrc/k_common.h")),
+    "columns8": ("rank2_f32_mfma_kernel", ("paper_2009_11742_amd/csrc/k_rank2_f32.hip",
+                                           "paper_2009_11742_amd/csrc/k_tile_f32.h",
+                                           "paper_2009_11742_amd/csrc/k_common.h")),
+    "rowsplit": ("rank2_split_f32_kernel", ("paper_2009_11742_amd/csrc/k_rank2_split.hip",
+                                            "paper_2009_11742_amd/csrc/k_common.h")),
+    "resident": ("rank2_resident_kernel", ("paper_2009_11742_amd/csrc/k_rank2_resident.hip",
+                                           "paper_2009_11742_amd/csrc/k_common.h")),
+}
+MEASURED_TRAFFIC = {"fc1d167ba1c60b4cffde49fcd47937f7c17e8d02": 5.516e6}
+FP32_VECTOR_PEAK_TFLOPS = 157.3          # with packed FP32; 78.6 without
+HBM_PEAK_GBS = 8000.0
 
 
-def _measured_traffic():
+def _sources_sha1(files):
     import hashlib
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return MEASURED_TRAFFIC["bytes"] if h.hexdigest() == MEASURED_TRAFFIC["sources_sha1"] else None
+    return h.hexdigest()
+
+
+def _measured_traffic(schedule):
+    files = SCHEDULE_KERNELS.get(schedule, (None, ()))[1]
+    return MEASURED_TRAFFIC.get(_sources_sha1(files)) if files else None
 
 
 def _err_cols(Xg, Xr):
@@ -60,6 +78,8 @@ def main():
     ap.add_argument("--fom-point", default=None,
                     help="fom workload: one point only, GRIDxM (e.g. 512x2048x48), timed over --steps runs")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the K = M = 1024 target record (FP32, BF16, FP8 runs and their oracle check)")
     ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline",
                              "forward512"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
@@ -82,6 +102,9 @@ def main():
     if args.workload != "rank2":
         print(json.dumps(OTHER[args.workload](args, torch, dev)))
         return
+    # the oracle references of the K = M = 1024 record run on host threads
+    # while the GPU is timed (they need nothing from it)
+    target_refs = None if args.no_target else start_target_refs()
     inst = synth.round_to(synth.make_instance(KV, KS, M, seed=SEED), "f32")
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
@@ -114,6 +137,19 @@ def main():
     kavg_s = float(np.median(kern_ms)) * 1e-3
     flops_per_launch = 4.0 * KV * KS * M * NSTEPS
     achieved = flops_per_launch / kavg_s / 1e12
+    schedule = rom.last_schedule
+    kernel = SCHEDULE_KERNELS.get(schedule, (schedule, ()))[0]
+    if schedule == "resident":
+        # FP32 FMAs on the vector ALUs; the chip's FP32 vector peak counts
+        # packed FP32 (this build issues none): 78.6 TFLOP/s without it
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "peak_without_packed_fp32": 78.6}
+    else:
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_MFMA_PEAK_TFLOPS}
+    roofline.update({"traffic": _measured_traffic(schedule), "kernel": kernel, "schedule": schedule,
+                     "kernel_ms": float(np.median(kern_ms)), "kernel_ms_runs": [float(x) for x in kern_ms],
+                     "flops_per_launch": flops_per_launch})
 
     Vg = V.cpu().numpy().astype(np.float64).T
     Sg = S.cpu().numpy().astype(np.float64).T
@@ -121,9 +157,15 @@ def main():
 
     # ---- rank-1 path on the same GPU: one sample per stream, each sample's
     # steps captured in a graph (2 kernel nodes per step), S concurrent streams
-    rank1 = None
+    rank1 = rank1b = None
     if not args.no_rank1:
         rank1 = rank1_rate(torch, rom, inst, 500)
+        rank1b = rank1_batch_rate(torch, rom, inst, 2000)
+
+    # ---- the K = M = 1024 record (FP32, BF16, FP8 operators)
+    target = None
+    if target_refs is not None:
+        target = workload_target(torch, dev, target_refs)
 
     # ---- CPU baseline: the FP64 oracle on a bounded column sample (all host
     # threads, plus its 1-thread rate), and a numpy/BLAS FP64 rank-2 loop as
@@ -166,15 +208,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rank-2 FP32 leapfrog, Kv=Ks=256, M=256 samples, 10000 steps per run",
                    "kv": KV, "ks": KS, "M": M, "nsteps": NSTEPS, "seed": SEED},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": _measured_traffic(),
-                     "kernel": "rank2_f32_mfma_kernel", "kernel_ms": float(np.median(kern_ms)),
-                     "kernel_ms_runs": [float(x) for x in kern_ms],
-                     "flops_per_launch": flops_per_launch},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "rank1": rank1,
         "rank2_over_rank1": (value / rank1["value"]) if rank1 else None,
+        "rank1_batch": rank1b,
+        "rank2_over_rank1_batch": (value / rank1b["value"]) if rank1b else None,
         "accuracy": errs,
+        "target_k1024_m1024": target,
     }
     print(json.dumps(out))
 
@@ -222,6 +263,106 @@ def rank1_rate(torch, rom, inst, nsteps, stream_counts=(1, 8, 32)):
             "graph_equals_eager": exact,
             "sample": "%d samples x %d steps, one graph per sample (2 kernels per step), best of S in %s"
                       % (best[1], nsteps, list(stream_counts))}
+
+
+def rank1_batch_rate(torch, rom, inst, nsteps):
+    """The chip-filling rank-1 reference: all M samples in one launch, one
+    workgroup per sample, each half-step a matrix-vector product that reads
+    the operator from device memory again (rom_run_rank1_batch).  Median of
+    3 event-timed runs; the operator bytes it reads per sample-step give its
+    achieved bandwidth (served from the L2s: both FP32 operators, 512 KB at
+    K = 256, fit in every XCD's 4 MB L2)."""
+    dev = torch.device("cuda:0")
+    kv, ks = inst["Avs"].shape
+    Mb = len(inst["mu"])
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    V, S = rom.zeros(Mb, device=dev)
+
+    def run():
+        V.zero_(); S.zero_()
+        rom.run_rank1_batch(mu, V, S, nsteps)
+    _, ms = _events_time(torch, run, 3, 1)
+    ksec = float(np.median(ms)) * 1e-3
+    rate = Mb * nsteps / ksec
+    op_bytes = 2.0 * kv * ks * 4
+    gbs = rate * op_bytes / 1e9
+    return {"value": rate, "unit": "sample-steps/s", "us_per_step": ksec / nsteps * 1e6,
+            "operator_bytes_per_sample_step": op_bytes, "operator_GB_per_s": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "sample": "%d samples x %d steps in one launch (rom_run_rank1_batch), median of 3" % (Mb, nsteps)}
+
+
+# ---- the K = M = 1024 record: FP32, BF16 and FP8 operators (with the state
+# operand as a BF16 pair and as one BF16 value), 5000 steps, one sampled
+# column checked against the same-input FP64 oracle over the whole run
+TARGET_K, TARGET_M, TARGET_N, TARGET_COL = 1024, 1024, 5000, 511
+TARGET_PEAKS = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+
+
+def _target_inst():
+    import synth
+    return synth.round_to(synth.make_instance(TARGET_K, TARGET_K, TARGET_M, seed=0), "f32")
+
+
+def start_target_refs():
+    """FP64 oracle runs of the sampled column with the FP32, BF16-rounded and
+    FP8-quantised operators (the oracle's own roundings), on host threads."""
+    import concurrent.futures as cf
+    import oracle
+    inst = _target_inst()
+    A, B = inst["Avs"], inst["Asv"]
+    amax = float(max(np.max(np.abs(A.astype(np.float32))), np.max(np.abs(B.astype(np.float32)))))
+    ops = {"f32": (A, B), "bf16": (oracle.round_bf16(A), oracle.round_bf16(B)),
+           "fp8": (oracle.quantize_e4m3(A, amax=amax)[0], oracle.quantize_e4m3(B, amax=amax)[0])}
+    ex = cf.ThreadPoolExecutor(max_workers=3)
+    mu = inst["mu"][TARGET_COL:TARGET_COL + 1]
+    futs = {k: ex.submit(oracle.run_rank2, a, b, inst["b"], inst["dt"], mu, TARGET_N, c=inst["c"])
+            for k, (a, b) in ops.items()}
+    return {"inst": inst, "futures": futs, "executor": ex, "t0": time.perf_counter()}
+
+
+def workload_target(torch, dev, refs):
+    from paper_2009_11742_amd import Rom
+    inst = refs["inst"]
+    K, Mt, N, col = TARGET_K, TARGET_M, TARGET_N, TARGET_COL
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
+    c = torch.tensor(inst["c"], dtype=torch.float32, device=dev)
+    runs, states = {}, {}
+    for ops, operand in (("f32", "pair"), ("bf16", "pair"), ("bf16", "single"), ("fp8", "pair"),
+                         ("fp8", "single")):
+        key = ops if operand == "pair" else ops + "_single"
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops=ops, state_operand=operand)
+        V, S = rom.zeros(Mt, device=dev)
+        J = torch.zeros(Mt, dtype=torch.float64, device=dev)
+
+        def run():
+            V.zero_(); S.zero_(); J.zero_()
+            rom.run_rank2(mu, V, S, N, c=c, J=J)
+        _, ms = _events_time(torch, run, 1, 1)
+        rom.check()
+        ksec = float(ms[0]) * 1e-3
+        tf = 4.0 * K * K * Mt * N / ksec / 1e12
+        runs[key] = {"us_per_step": ksec / N * 1e6, "value": Mt * N / ksec, "tflops": tf,
+                     "peak_tflops": TARGET_PEAKS[ops], "frac": tf / TARGET_PEAKS[ops],
+                     "schedule": rom.last_schedule,
+                     "products": {"f32": "FP32 MFMA (v_mfma_f32_16x16x4f32)",
+                                  "bf16": "BF16 MFMA (v_mfma_f32_16x16x32_bf16)",
+                                  "fp8": "FP8-E4M3 storage, BF16 MFMA (exact widening)"}[ops],
+                     "state_operand": "fp32" if ops == "f32" else ("bf16 pair" if operand == "pair" else "bf16")}
+        states[key] = (V[col].cpu().numpy().astype(np.float64), S[col].cpu().numpy().astype(np.float64),
+                       float(J[col].cpu()))
+        rom.close()
+    ref = {k: f.result() for k, f in refs["futures"].items()}
+    refs["executor"].shutdown()
+    for key, (v, s_, j) in states.items():
+        r = ref[key.split("_")[0]]
+        e = max(float(np.linalg.norm(v - r["V"][:, 0]) / np.linalg.norm(r["V"][:, 0])),
+                float(np.linalg.norm(s_ - r["S"][:, 0]) / np.linalg.norm(r["S"][:, 0])))
+        runs[key]["max_rel_state_err_vs_same_input_oracle"] = e
+        runs[key]["rel_qoi_err_vs_same_input_oracle"] = abs(j - r["J"][0]) / r["J"][0]
+    return {"workload": "Kv=Ks=1024, M=1024, 5000 steps; errors on column %d over all 5000 steps" % col,
+            "unit": "sample-steps/s", "runs": runs,
+            "oracle_wall_s": time.perf_counter() - refs["t0"]}
 
 
 def numpy_blas_rate(inst, ncols=16, nsteps=1000):

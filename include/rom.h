@@ -108,6 +108,11 @@ enum {
                                x = pi (mu t - 3); default: the Ricker wavelet
                                (1 - 2a) exp(-a), a = pi^2 (mu t - 1.5)^2.  The
                                adjoint's dJ/dmu differentiates the chosen one */,
+    ROM_SCHED_RESIDENT = 64u,/* FP32 operators and states, skew pairs
+                               (Asv == -Avs^T exactly) with Kv, Ks <= 256:
+                               the operator-resident kernel (one sample per
+                               workgroup, all of Avs in its registers); else
+                               4-column blocks                                */
     ROM_STATE_BF16 = 32u    /* BF16 / F8E4M3 operators with F32 states: the
                                state operand of every product is bf16(x)
                                alone (one MFMA pass, about 8 significant
@@ -198,10 +203,18 @@ rom_status rom_destroy(rom_ctx *ctx);
  *   ROM_SCHEDULE_COLUMNS8  as COLUMNS4 with 8 samples per workgroup (FP32
  *                          operators): half the operator bytes per flop,
  *                          half the workgroups.  Bitwise equal to COLUMNS4.
+ *   ROM_SCHEDULE_RESIDENT  skew pairs (Asv == -Avs^T exactly, the energy-
+ *                          conserving structure of Sec. 3.1) with FP32
+ *                          operators and Kv, Ks <= 256: one sample per
+ *                          workgroup, which keeps all of Avs in registers
+ *                          for the whole run and uses it for both half-
+ *                          steps (Asv V = -Avs^T V); no operator streaming,
+ *                          no exchange between workgroups.
  * Without a ROM_SCHED_* flag the first run of each shape (Kv_pad, Ks_pad, M
  * rounded up to 64, operator type) times every schedule that applies for 32
  * steps on scratch states and keeps the fastest for the process (that run
- * synchronises the stream), unless the process-wide tuning table already
+ * synchronises the stream; a row-split timing run whose group barrier timed
+ * out counts as not applicable, and its status is cleared), unless the process-wide tuning table already
  * holds the shape.  A stream being captured into a graph is never tuned and
  * never takes ROWSPLIT (whatever the flags or the table say): it runs the
  * table's column-block choice, else COLUMNS4.
@@ -228,9 +241,10 @@ rom_status rom_destroy(rom_ctx *ctx);
 typedef enum {
     ROM_SCHEDULE_COLUMNS4 = 0,
     ROM_SCHEDULE_ROWSPLIT = 1,
-    ROM_SCHEDULE_COLUMNS8 = 2
+    ROM_SCHEDULE_COLUMNS8 = 2,
+    ROM_SCHEDULE_RESIDENT = 3
 } rom_schedule;
-#define ROM_NSCHEDULES 3
+#define ROM_NSCHEDULES 4
 
 typedef struct {
     int32_t kv_pad, ks_pad; /* Kv, Ks rounded up to multiples of 64           */
@@ -256,6 +270,17 @@ void rom_tune_clear(void);
  * the condition.  ROM_OK otherwise.
  */
 rom_status rom_check(rom_ctx *ctx, void *stream);
+
+/*
+ * Test hook for the failure handling above (not for production use): with
+ * on != 0, every later row-split launch of this process waits at its first
+ * group barrier for one arrival more than the group has, with a short poll
+ * budget, so the wait runs out, ROM_E_TIMEOUT is recorded and every later
+ * wait of that launch returns at once; the kernel ends normally with
+ * invalid results.  on = 0 restores normal waits.  Process-wide; returns
+ * ROM_OK.
+ */
+rom_status rom_debug_force_timeout(int32_t on);
 
 /*
  * End-of-run health check: scans the states V (dev Kv x M) and S (dev Ks x
@@ -289,6 +314,21 @@ rom_status rom_step_rank1(rom_ctx *ctx, void *v, void *s, int64_t n, double mu,
  */
 rom_status rom_run_rank1(rom_ctx *ctx, void *v, void *s, double mu, int64_t n0, int64_t nsteps,
                          void *stream);
+
+/*
+ * Rank-1 formulation of M samples in one launch (Sec. 2.2 eq. (2.3); the
+ * rank-1 cost model of Sec. 2.3): workgroup m advances sample m through all
+ * steps, and every half-step is a matrix-vector product that reads the
+ * operator from device memory again, so no operator entry is reused within
+ * a step.  The whole chip is busy and there is no launch per step: the
+ * memory-bound baseline the rank-2 runs are compared with on this device.
+ * V (Kv x M), S (Ks x M), mu (M) as rom_run_rank2; per row the arithmetic
+ * of rom_step_rank1 without its split of the reduction over waves (the
+ * state is rounded once per half-step).  FP32 states and operators, Kv,
+ * Ks <= 1024.  Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_DEVICE.
+ */
+rom_status rom_run_rank1_batch(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
+                               void *V, void *S, void *stream);
 
 /*
  * Rank-2 run (Sec. 2.4 eq. (2.5) in the staggered form (3.3)): advance all M
@@ -334,7 +374,11 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  *   dmu           dev, M FP64: dJ/dmu_m (set)
  * Any of dAvs, dAsv, dmu may be NULL.  dt is held fixed.
  *
- * FP32 states and operators.  The recompute of the next segment and the
+ * FP32 states and operators.  The forward sweep runs on the schedule a
+ * rom_run_rank2 of the same shape takes; when that is ROWSPLIT the call
+ * synchronises `stream` after it and returns ROM_E_TIMEOUT (nothing of the
+ * reverse sweep enqueued) if one of its group barriers timed out.  The
+ * recompute of the next segment and the
  * gradient products of the last run on two internal streams beside the
  * reverse sweep on `stream`; the context keeps the workspace (checkpoints
  * unless ckpt_stride = -1, three sets of state and probe traces, two of W/Q

@@ -10,7 +10,9 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librom.so")
+# ROM_LIB overrides the library file (the sanitizer build of the host layer
+# is loaded this way by its CPU test)
+LIB_PATH = os.environ.get("ROM_LIB") or os.path.join(HERE, "librom.so")
 
 ROM_OK, ROM_E_ARG, ROM_E_NOMEM, ROM_E_DEVICE, ROM_E_UNSTABLE, ROM_E_UNSUPPORTED, \
     ROM_E_NONFINITE, ROM_E_TIMEOUT = range(8)
@@ -23,14 +25,15 @@ ROM_SCHED_ROWSPLIT = 4
 ROM_SCHED_COLUMNS8 = 8
 ROM_SOURCE_GAUSS1 = 16
 ROM_STATE_BF16 = 32
-ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8 = range(3)
-ROM_NSCHEDULES = 3
+ROM_SCHED_RESIDENT = 64
+ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8, ROM_SCHEDULE_RESIDENT = range(4)
+ROM_NSCHEDULES = 4
 
 # Every symbol include/rom.h declares.
-EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank2",
+EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_group_schedule", "rom_group_times", "rom_group_check",
-           "rom_get_operators", "rom_energy", "rom_check", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
+           "rom_get_operators", "rom_energy", "rom_check", "rom_debug_force_timeout", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
            "rom_fom_create", "rom_fom_run", "rom_fom_project", "rom_fom_destroy", "rom_pod",
@@ -82,6 +85,8 @@ def load():
         lib.rom_step_rank1.argtypes = [_vp, _vp, _vp, _i64, _d, _vp]
         lib.rom_run_rank1.restype = C.c_int
         lib.rom_run_rank1.argtypes = [_vp, _vp, _vp, _d, _i64, _i64, _vp]
+        lib.rom_run_rank1_batch.restype = C.c_int
+        lib.rom_run_rank1_batch.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp]
         lib.rom_run_rank2.restype = C.c_int
         lib.rom_run_rank2.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
         lib.rom_adjoint.restype = C.c_int
@@ -123,6 +128,8 @@ def load():
         lib.rom_energy.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
         lib.rom_check.restype = C.c_int
         lib.rom_check.argtypes = [_vp, _vp]
+        lib.rom_debug_force_timeout.restype = C.c_int
+        lib.rom_debug_force_timeout.argtypes = [_i32]
         lib.rom_last_schedule.restype = C.c_int32
         lib.rom_last_schedule.argtypes = [_vp]
         lib.rom_schedule_times.restype = C.c_int

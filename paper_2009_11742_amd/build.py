@@ -31,9 +31,16 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# sources (device code unchanged): the host validation layer is tested with
+# it on the CPU.  Loaded through ROM_LIB with the clang ASan runtime
+# preloaded (see tests/test_sanitizers.py).
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -57,6 +64,32 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print("built", LIB)
     return LIB
+
+
+def build_sanitized(out_dir: str) -> str:
+    """Build librom with host-side ASan + UBSan into out_dir; returns the
+    library path."""
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    extra = ["-g"] + SANITIZE_HOST
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda f: _compile(f, out_dir, extra), srcs))
+    lib = os.path.join(out_dir, "librom_sanitized.so")
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-shared-libsan"] + SANITIZE_HOST + ["-o", lib] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr)
+    return lib
+
+
+def asan_runtime() -> str:
+    """The clang ASan runtime the sanitized library needs preloaded."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+        path = hits[-1] if hits else ""
+    return path
 
 
 if __name__ == "__main__":

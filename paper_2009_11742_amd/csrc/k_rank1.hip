@@ -84,7 +84,101 @@ __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ 
     }
 }
 
+// Rank-1 formulation for many samples in one launch: workgroup m advances
+// sample m through all its steps, and every half-step is a matrix-vector
+// product that reads the operator from device memory again -- the rank-1
+// cost model of Sec. 2.3 (no reuse of an operator entry within a step),
+// with the whole chip busy and no launch per step.  Thread t owns rows t,
+// t + 256, ... of both fields (at most kRank1Rows each); the state hi words
+// pass through LDS to the other half-step.  The arithmetic per row is the
+// single-sample kernel's: compensated chunks of kChunk terms in increasing
+// k, then the double-float update.
+constexpr int kRank1Rows = 4;
+
+__device__ __forceinline__ void rank1_row(const float *__restrict__ A, int rows, int cols, int i,
+                                          const float *__restrict__ x, float &H, float &L) {
+    float hi = 0.f, lo = 0.f;
+    for (int c0 = 0; c0 < cols; c0 += kChunk) {
+        const int c1 = min(cols, c0 + kChunk);
+        float acc = 0.f;
+        for (int k = c0; k < c1; ++k) acc = fmaf(A[i + (size_t)k * rows], x[k], acc);
+        float s, e;
+        dev::two_sum(hi, acc, s, e);
+        hi = s;
+        lo += e;
+    }
+    H = hi;
+    L = lo;
+}
+
+__global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__ Avs, const float *__restrict__ Asv,
+                                                       const float *__restrict__ b, const double *__restrict__ mu,
+                                                       int kv, int ks, double dt, int64_t n0, int64_t nsteps,
+                                                       int src, float *__restrict__ V, float *__restrict__ S) {
+    extern __shared__ float xsh[];
+    float *xs = xsh, *xv = xsh + ks;           // S and V hi words
+    const int m = blockIdx.x, tid = threadIdx.x;
+    float vh[kRank1Rows], vl[kRank1Rows], sh[kRank1Rows], sl[kRank1Rows];
+#pragma unroll
+    for (int q = 0; q < kRank1Rows; ++q) {
+        const int iv = tid + 256 * q, is = tid + 256 * q;
+        vh[q] = iv < kv ? V[(size_t)m * kv + iv] : 0.f;
+        sh[q] = is < ks ? S[(size_t)m * ks + is] : 0.f;
+        vl[q] = sl[q] = 0.f;
+        if (is < ks) xs[is] = sh[q];
+    }
+    const double mum = mu[m];
+    __syncthreads();
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const double u = dev::forcing(src, (double)(n0 + k) * dt, mum);
+        const float uh = (float)u, ul = (float)(u - (double)uh);
+#pragma unroll
+        for (int q = 0; q < kRank1Rows; ++q) {
+            const int i = tid + 256 * q;
+            if (i < kv) {
+                float H, L;
+                rank1_row(Avs, kv, ks, i, xs, H, L);
+                const float F = b[i] * uh;
+                const float Fe = fmaf(b[i], uh, -F) + b[i] * ul;
+                dev::comp_update(vh[q], vl[q], H, L, F, Fe, (float)dt);
+                vh[q] = vh[q] + vl[q];      // rounded once per half-step, as the single-sample kernel
+                vl[q] = 0.f;
+                xv[i] = vh[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRank1Rows; ++q) {
+            const int i = tid + 256 * q;
+            if (i < ks) {
+                float H, L;
+                rank1_row(Asv, ks, kv, i, xv, H, L);
+                dev::comp_update(sh[q], sl[q], H, L, 0.f, 0.f, (float)dt);
+                sh[q] = sh[q] + sl[q];
+                sl[q] = 0.f;
+                xs[i] = sh[q];     // xs is read only by the velocity half-step
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kRank1Rows; ++q) {
+        const int i = tid + 256 * q;
+        if (i < kv) V[(size_t)m * kv + i] = vh[q];
+        if (i < ks) S[(size_t)m * ks + i] = sh[q];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_rank1_batch(const Rank2Args &a, hipStream_t st) {
+    if (a.kv > 256 * kRank1Rows || a.ks > 256 * kRank1Rows) return hipErrorInvalidValue;
+    const size_t lds = sizeof(float) * (size_t)(a.kv + a.ks);
+    hipLaunchKernelGGL(rank1_batch_f32, dim3(a.M), dim3(256), lds, st, static_cast<const float *>(a.avs),
+                       static_cast<const float *>(a.asv), static_cast<const float *>(a.b), a.mu, a.kv, a.ks, a.dt,
+                       a.n0, a.nsteps, a.source, static_cast<float *>(a.V), static_cast<float *>(a.S));
+    return hipGetLastError();
+}
 
 template <>
 hipError_t launch_rank1_step<float>(const void *avs_cm, const void *asv_cm, const void *b, int kv,

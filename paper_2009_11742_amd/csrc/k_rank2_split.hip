@@ -56,7 +56,7 @@ constexpr int kCols = 64;          // sample columns per group
 constexpr int kWaves = 4;
 constexpr int kThreads = 256;
 constexpr int kLd = kRows + 4;     // LDS column stride (floats)
-constexpr long kSpinMax = 1L << 20;
+constexpr long kSpinMax = 1L << 20;     // polls of one bounded wait
 constexpr int kCntStride = 64;     // counters 256 bytes apart
 
 __device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
@@ -82,6 +82,11 @@ struct SplitArgs {
     const SplitGroup *grp;      // grouped FP32 runs: per-group instance data, from grp[g0]
     int g0;
     int source;                 // source signal (dev::Source)
+    // bounded waits: poll budget (kSpinMax), and a bias added to every
+    // barrier target (0; 1 makes every first wait run out, the host-forced
+    // time-out of the failure-handling tests)
+    long spin_max;
+    unsigned wait_bias;
     int kv, kp, M, G, R;
     int64_t n0, nsteps;
     double dt;
@@ -97,10 +102,11 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         long spins = 0;
+        target += a.wait_bias;
         while (__hip_atomic_load(&a.status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
                __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinMax) {
+            if (++spins > a.spin_max) {
                 __hip_atomic_store(&a.status[1], (int)ROM_E_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&a.status[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
@@ -823,6 +829,8 @@ hipError_t split_workspace(SplitArgs &a, void *ws, int G, hipStream_t st) {
     a.yp = reinterpret_cast<double *>(x + 2 * xsz);
     a.cnt = reinterpret_cast<unsigned *>(a.yp + (size_t)G * a.R * kCols);
     a.slots = a.cnt + 256 * kCntStride;
+    a.spin_max = g_forced_timeout ? 256 : kSpinMax;
+    a.wait_bias = g_forced_timeout ? 1u : 0u;
     hipLaunchKernelGGL(split_zero_kernel, dim3(64), dim3(256), 0, st, a.cnt, 256 * kCntStride + 64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -40,6 +40,7 @@ rom_status hip_fail(hipError_t e, const char *where) {
 }  // namespace
 
 namespace rom {
+bool g_forced_timeout = false;
 rom_status api_fail(rom_status s, const std::string &msg) { return fail(s, msg); }
 rom_status api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
 }  // namespace rom
@@ -86,6 +87,23 @@ void hfree(void *p) {
     if (p) (void)hipFree(p);
 }
 
+// Read and clear the in-kernel wait words status[1] (ROM_E_TIMEOUT) and
+// status[2] (abort flag) once the work that may set them has completed
+// (the copies synchronise with the device).  `timed_out` tells whether a
+// bounded wait ran out.
+rom_status take_timeout(int *status, bool &timed_out, const char *who) {
+    int w[2] = {0, 0};
+    timed_out = false;
+    hipError_t e = hipMemcpy(w, status + 1, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (w[0] != 0 || w[1] != 0) {
+        e = hipMemset(status + 1, 0, sizeof(w));
+        if (e != hipSuccess) return hip_fail(e, who);
+        timed_out = w[0] == ROM_E_TIMEOUT;
+    }
+    return ROM_OK;
+}
+
 void free_ctx(rom_ctx *c) {
     if (!c) return;
     hfree(c->avs_cm);
@@ -101,6 +119,7 @@ void free_ctx(rom_ctx *c) {
     hfree(c->ws);
     hfree(c->avs_sp);
     hfree(c->asv_sp);
+    hfree(c->res_pk);
     hfree(c->sp_ws);
     hfree(c->status);
     for (hipStream_t &sd : c->side)
@@ -192,7 +211,10 @@ rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, int sched, int 
     hipError_t e;
     const bool lowp = ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3;
     a.single = (lowp && (ctx->flags & ROM_STATE_BF16)) ? 1 : 0;
-    if (sched == ROM_SCHEDULE_ROWSPLIT) {
+    if (sched == ROM_SCHEDULE_RESIDENT) {
+        a.avs = ctx->res_pk; a.asv = nullptr;
+        e = rom::launch_rank2_resident(a, st);
+    } else if (sched == ROM_SCHEDULE_ROWSPLIT) {
         rom_status rs = prepare_split(ctx, G, st);
         if (rs != ROM_OK) return rs;
         e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, lowp ? ctx->op_scale : 1.0f, ctx->sp_ws, G,
@@ -292,6 +314,13 @@ rom_status time_schedules(rom_ctx *ctx, const rom::Rank2Args &run, unsigned cand
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) rs = hip_fail(e, "schedule tuning");
     }
+    if (rs == ROM_OK && (cands >> ROM_SCHEDULE_ROWSPLIT & 1u)) {
+        // a row-split run whose barrier timed out is not applicable here,
+        // and its status must not be blamed on the caller's next run
+        bool to = false;
+        rs = take_timeout(ctx->status, to, "schedule tuning: status");
+        if (rs == ROM_OK && to) us[ROM_SCHEDULE_ROWSPLIT] = -1.f;
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     hfree(V);
@@ -300,11 +329,13 @@ rom_status time_schedules(rom_ctx *ctx, const rom::Rank2Args &run, unsigned cand
     return rs;
 }
 
-int fastest(const float (&us)[ROM_NSCHEDULES]) {
-    int best = ROM_SCHEDULE_COLUMNS4;
+// Fastest timed schedule among `cands` (bit per rom_schedule); COLUMNS4 if
+// none of them was timed.
+int fastest(const float (&us)[ROM_NSCHEDULES], unsigned cands = ~0u) {
+    int best = -1;
     for (int sc = 0; sc < ROM_NSCHEDULES; ++sc)
-        if (us[sc] >= 0.f && (us[best] < 0.f || us[sc] < us[best])) best = sc;
-    return best;
+        if ((cands >> sc & 1u) && us[sc] >= 0.f && (best < 0 || us[sc] < us[best])) best = sc;
+    return best < 0 ? ROM_SCHEDULE_COLUMNS4 : best;
 }
 
 // Schedule of an FP32-state rank-2 run (flags, table, or tuned now).
@@ -317,8 +348,13 @@ rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, 
     unsigned cands = 1u << ROM_SCHEDULE_COLUMNS4;
     if (G > 0) cands |= 1u << ROM_SCHEDULE_ROWSPLIT;
     if (cols8_ok(ctx)) cands |= 1u << ROM_SCHEDULE_COLUMNS8;
+    if (ctx->res_pk) cands |= 1u << ROM_SCHEDULE_RESIDENT;
     sched = ROM_SCHEDULE_COLUMNS4;
     if (ctx->flags & ROM_SCHED_COLUMNS) return ROM_OK;
+    if (ctx->flags & ROM_SCHED_RESIDENT) {
+        if (ctx->res_pk) sched = ROM_SCHEDULE_RESIDENT;
+        return ROM_OK;
+    }
     if (ctx->flags & ROM_SCHED_ROWSPLIT) {
         if (G > 0) sched = ROM_SCHEDULE_ROWSPLIT;
         return ROM_OK;
@@ -335,10 +371,12 @@ rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, 
         for (float &u : te.us) u = -1.f;
         rom_status rs = time_schedules(ctx, a, cands, G, kTuneSteps, st, te.us);
         if (rs != ROM_OK) return rs;
-        te.sched = fastest(te.us);
+        te.sched = fastest(te.us, cands);
         tune_store(key, te);
     }
-    if (cands >> te.sched & 1u) sched = te.sched;
+    // the table's choice where it applies to this context (a shape's entry
+    // is shared by skew and non-skew pairs), else the fastest that does
+    sched = (cands >> te.sched & 1u) ? te.sched : fastest(te.us, cands);
     return ROM_OK;
 }
 
@@ -398,11 +436,11 @@ rom_status check_config(const rom_config *cfg, const char *who) {
         return fail(ROM_E_UNSUPPORTED, w + ": supported (op, state) pairs are (F64, F64), "
                                           "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
     if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 |
-                                 ROM_SOURCE_GAUSS1 | ROM_STATE_BF16))
+                                 ROM_SCHED_RESIDENT | ROM_SOURCE_GAUSS1 | ROM_STATE_BF16))
         return fail(ROM_E_ARG, w + ": unknown flag bits");
     if ((cfg->flags & ROM_STATE_BF16) && !(lowp && cfg->state_type == ROM_F32))
         return fail(ROM_E_ARG, w + ": ROM_STATE_BF16 needs BF16 or F8E4M3 operators with F32 states");
-    const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8);
+    const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 | ROM_SCHED_RESIDENT);
     if (sf & (sf - 1)) return fail(ROM_E_ARG, w + ": at most one ROM_SCHED_* flag");
     return ROM_OK;
 }
@@ -494,6 +532,11 @@ rom_status build_ctx(const rom_config *cfg, bool skew, const double *sA, const d
         CHK(hipMalloc(&c->asv_pk, sizeof(float) * (size_t)c->kvp * c->ksp), ": device allocation");
         CHK(rom::launch_pack_f32(sA, kv, ks, c->kvp, c->ksp, c->avs_pk, st), ": pack");
         CHK(rom::launch_pack_f32(sB, ks, kv, c->ksp, c->kvp, c->asv_pk, st), ": pack");
+        if (skew && rom::rank2_resident_applies(c->kvp, c->ksp)) {
+            CHK(hipMalloc(&c->res_pk, rom::rank2_resident_pack_bytes(c->kvp, c->ksp)), ": device allocation");
+            CHK(rom::launch_resident_pack(static_cast<const float *>(c->avs_cm), kv, ks, c->kvp, c->ksp, c->res_pk,
+                                          st), ": pack");
+        }
     }
     CHK(hipStreamSynchronize(st), ": synchronize");
 #undef CHK
@@ -684,6 +727,11 @@ rom_status rom_destroy(rom_ctx *ctx) {
     return ROM_OK;
 }
 
+rom_status rom_debug_force_timeout(int32_t on) {
+    rom::g_forced_timeout = on != 0;
+    return ROM_OK;
+}
+
 int32_t rom_last_schedule(rom_ctx *ctx) { return ctx ? ctx->last_schedule : -1; }
 
 rom_status rom_schedule_times(rom_ctx *ctx, int32_t M, double us[ROM_NSCHEDULES]) {
@@ -723,7 +771,7 @@ rom_status rom_tune_put(const rom_tune_entry *e) {
         return fail(ROM_E_ARG, "rom_tune_put: bad op_type");
     if (e->schedule < 0 || e->schedule >= ROM_NSCHEDULES)
         return fail(ROM_E_ARG, "rom_tune_put: bad schedule");
-    if (e->m_pad == 0 && e->schedule == ROM_SCHEDULE_ROWSPLIT)
+    if (e->m_pad == 0 && e->schedule != ROM_SCHEDULE_COLUMNS4 && e->schedule != ROM_SCHEDULE_COLUMNS8)
         return fail(ROM_E_ARG, "rom_tune_put: a grouped tile entry names a column tile");
     TuneEntry te;
     te.sched = e->schedule;
@@ -742,15 +790,10 @@ rom_status rom_check(rom_ctx *ctx, void *stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "rom_check: synchronize");
-    int w[2] = {0, 0};
-    e = hipMemcpy(w, ctx->status + 1, sizeof(w), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "rom_check: read status");
-    if (w[0] != 0 || w[1] != 0) {
-        e = hipMemset(ctx->status + 1, 0, sizeof(w));
-        if (e != hipSuccess) return hip_fail(e, "rom_check: clear status");
-        if (w[0] == ROM_E_TIMEOUT)
-            return fail(ROM_E_TIMEOUT, "rom_check: a row-split group barrier timed out; the run's results are invalid");
-    }
+    bool to = false;
+    rom_status rs = take_timeout(ctx->status, to, "rom_check: status");
+    if (rs != ROM_OK) return rs;
+    if (to) return fail(ROM_E_TIMEOUT, "rom_check: a row-split group barrier timed out; the run's results are invalid");
     return ROM_OK;
 }
 
@@ -796,6 +839,25 @@ rom_status rom_run_rank1(rom_ctx *ctx, void *v, void *s, double mu, int64_t n0, 
         rom_status r = rom_step_rank1(ctx, v, s, n0 + k, mu, stream);
         if (r != ROM_OK) return r;
     }
+    return ROM_OK;
+}
+
+rom_status rom_run_rank1_batch(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps, void *V,
+                               void *S, void *stream) {
+    if (!ctx) return fail(ROM_E_ARG, "rom_run_rank1_batch: NULL context");
+    if (M < 1) return fail(ROM_E_ARG, "rom_run_rank1_batch: M must be >= 1");
+    if (!mu || !V || !S) return fail(ROM_E_ARG, "rom_run_rank1_batch: NULL mu, V or S");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_run_rank1_batch: n0 and nsteps must be >= 0");
+    if (ctx->state_type != ROM_F32 || ctx->op_type != ROM_F32)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_rank1_batch: FP32 states and operators only");
+    if (ctx->kv > 1024 || ctx->ks > 1024) return fail(ROM_E_UNSUPPORTED, "rom_run_rank1_batch: Kv, Ks <= 1024");
+    if (nsteps == 0) return ROM_OK;
+    rom::Rank2Args a;
+    a.avs = ctx->avs_cm; a.asv = ctx->asv_cm; a.b = ctx->b; a.mu = mu; a.V = V; a.S = S;
+    a.kv = ctx->kv; a.ks = ctx->ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M;
+    a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt; a.source = ctx_source(ctx);
+    hipError_t e = rom::launch_rank1_batch(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank1_batch: launch");
     return ROM_OK;
 }
 
@@ -955,6 +1017,16 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         a.V = curV; a.S = curS; a.J = J; a.n0 = nb; a.nsteps = len;
         rom_status rs = launch_fp32_state_run(ctx, a, fsched, fG, st);
         if (rs != ROM_OK) return rs;
+    }
+    if (fsched == ROM_SCHEDULE_ROWSPLIT) {
+        // the forward sweep ran on the row-split kernels: a group barrier
+        // that timed out leaves invalid checkpoints and J, so the reverse
+        // sweep is not started (this synchronises `stream`)
+        ACHK(hipStreamSynchronize(st), "rom_adjoint: synchronize");
+        bool to = false;
+        rom_status rs = take_timeout(ctx->status, to, "rom_adjoint: status");
+        if (rs != ROM_OK) return rs;
+        if (to) return fail(ROM_E_TIMEOUT, "rom_adjoint: a row-split group barrier of the forward sweep timed out");
     }
     // reverse sweep, segment by segment from the last.  Segment g's state
     // and probe traces (set g % kTr) are written by its recompute (side

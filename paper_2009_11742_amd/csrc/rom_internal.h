@@ -22,6 +22,12 @@ constexpr int kMaxPadSum = 4096;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Failure-handling test hook (rom_debug_force_timeout): when set, every
+// bounded in-kernel wait of the row-split kernels waits for one arrival too
+// many with a short poll budget, so it runs out and reports ROM_E_TIMEOUT
+// while the kernel still ends normally.
+extern bool g_forced_timeout;
+
 }  // namespace rom
 
 struct rom_ctx {
@@ -63,6 +69,9 @@ struct rom_ctx {
     void *sp_ws = nullptr;
     size_t sp_ws_bytes = 0;
     int sp_ok = -1;
+    // Operator-resident schedule (skew FP32 pairs, Kv, Ks <= 256): Avs in
+    // the per-thread tile order of its kernel, built by rom_create.
+    void *res_pk = nullptr;
     // Schedule of the last FP32-state rank-2 run (a rom_schedule, -1 none
     // yet).
     int last_schedule = -1;
@@ -113,6 +122,18 @@ struct Rank2Args {
     // alone (one MFMA pass), 0 = as the BF16 pair (x_hi, x_lo)
     int single = 0;
 };
+
+// Operator-resident kernel (skew pairs, FP32): whether padded sizes fit it,
+// the bytes of its operator pack, the pack from a column-major FP32 Avs, and
+// the run (a.avs = the pack).
+bool rank2_resident_applies(int kvp, int ksp);
+size_t rank2_resident_pack_bytes(int kvp, int ksp);
+hipError_t launch_resident_pack(const float *A, int kv, int ks, int kvp, int ksp, void *pk, hipStream_t st);
+hipError_t launch_rank2_resident(const Rank2Args &a, hipStream_t st);
+
+// Rank-1 formulation of M samples in one launch (a.avs / a.asv the
+// column-major FP32 operators, kv, ks <= 1024).
+hipError_t launch_rank1_batch(const Rank2Args &a, hipStream_t st);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_rank2_f32_mfma(const Rank2Args &a, int nset, hipStream_t st);

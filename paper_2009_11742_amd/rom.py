@@ -21,13 +21,14 @@ _DT = {"f64": (_lib.ROM_F64, torch.float64), "f32": (_lib.ROM_F32, torch.float32
 _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": _lib.ROM_F8E4M3}
 # FP32-state rank-2 schedule: "auto" (the autotuner's table), "columns"
 # (4-column blocks), "rowsplit" (row-split where it applies), "columns8"
-# (8-column blocks, FP32 operators)
+# (8-column blocks, FP32 operators), "resident" (skew FP32 pairs with Kv, Ks
+# <= 256: the whole operator in each workgroup's registers, one sample each)
 # source signal: the Ricker wavelet or the first derivative of a Gaussian
 _SOURCE = {"ricker": 0, "gauss1": _lib.ROM_SOURCE_GAUSS1}
 # state operand of the BF16 / FP8 products: the BF16 pair or bf16(x) alone
 _STATE_OPERAND = {"pair": 0, "single": _lib.ROM_STATE_BF16}
 _SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT,
-          "columns8": _lib.ROM_SCHED_COLUMNS8}
+          "columns8": _lib.ROM_SCHED_COLUMNS8, "resident": _lib.ROM_SCHED_RESIDENT}
 
 
 def _stream_handle(stream):
@@ -186,6 +187,17 @@ class Rom:
         check(_lib.load().rom_run_rank1(self._ctx, _ptr(v), _ptr(s), float(mu), int(n0), int(nsteps),
                                         _stream_handle(stream)))
 
+    def run_rank1_batch(self, mu, V, S, nsteps, n0=0, stream=None):
+        """The rank-1 formulation for all M samples in one launch (one
+        workgroup per sample, the operator re-read every half-step)."""
+        M = int(mu.numel())
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        check(_lib.load().rom_run_rank1_batch(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
+                                              _stream_handle(stream)))
+
     def run_rank2(self, mu, V, S, nsteps, n0=0, c=None, J=None, y=None, stream=None):
         """Advance all samples ``nsteps`` steps in place.
 
@@ -272,10 +284,25 @@ class RomQoI(torch.autograd.Function):
         dev = mu.device if mu.is_cuda else torch.device("cuda")
         mu_d = mu.detach().to(dev, torch.float64).contiguous()
         c_d = torch.as_tensor(c).detach().to(dev, torch.float32).contiguous()
-        out = rom.adjoint(mu_d, int(nsteps), c_d)
+        try:
+            if any(ctx.needs_input_grad[:3]):
+                # the adjoint's forward sweep gives J; the gradients are kept
+                # for backward
+                out = rom.adjoint(mu_d, int(nsteps), c_d)
+            else:
+                # no gradient wanted: the forward run alone
+                M = int(mu_d.numel())
+                V, S = rom.zeros(M, device=dev)
+                J = torch.zeros(M, dtype=torch.float64, device=dev)
+                rom.run_rank2(mu_d, V, S, int(nsteps), c=c_d, J=J)
+                out = {"J": J}
+            # a row-split group barrier that timed out invalidates J and the
+            # gradients: raise instead of returning them
+            rom.check()
+        finally:
+            rom.close()
         ctx.save_for_backward(Avs, Asv, mu)
         ctx.grads = out
-        rom.close()
         return out["J"].sum().to(mu.device)
 
     @staticmethod

@@ -77,7 +77,7 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     tuning.save(args.out, header="schedule tuning table: python -m paper_2009_11742_amd.tune\n"
                 "device: %s (%d CUs), %s\n"
-                "kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8"
+                "kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8 us_resident"
                 % (dev.name, dev.multi_processor_count, datetime.date.today().isoformat()))
     print("wrote %s (%d entries)" % (args.out, len(tuning.entries())))
 

@@ -129,7 +129,7 @@ def test_create_rejects_state_bf16_without_lowp_operators():
         cfg = _lib.RomConfig(8, 8, dt, op, st, _lib.ROM_STATE_BF16)
         assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
         assert "ROM_STATE_BF16" in _lib.load().rom_last_error().decode()
-    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_BF16, _lib.ROM_F32, 64)     # unknown bit
+    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_BF16, _lib.ROM_F32, 128)    # unknown bit
     assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
 
 
@@ -142,30 +142,36 @@ def test_tune_table_put_get_clear_and_file_round_trip(tmp_path):
     try:
         tuning.clear()
         assert lib.rom_tune_count() == 0
-        tuning.put(512, 512, 1024, "f32", "columns", [17.4, 27.2, -1.0])
-        tuning.put(256, 256, 256, "f32", "columns8", [4.9, 18.5, 4.1])
-        tuning.put(1024, 1024, 1024, "bf16", "rowsplit", [60.0, 11.0, -1.0])
-        tuning.put(768, 768, 0, "f32", "columns8", [40.0, -1.0, 45.0])
-        tuning.put(256, 256, 256, "f32", "columns", [4.9, 18.5, 5.5])      # replaces
+        tuning.put(512, 512, 1024, "f32", "columns", [17.4, 27.2, -1.0, -1.0])
+        tuning.put(256, 256, 256, "f32", "columns8", [4.9, 18.5, 4.1, 1.3])
+        tuning.put(1024, 1024, 1024, "bf16", "rowsplit", [60.0, 11.0, -1.0, -1.0])
+        tuning.put(768, 768, 0, "f32", "columns8", [40.0, -1.0, 45.0])       # last time missing: -1
+        tuning.put(256, 256, 256, "f32", "resident", [4.9, 18.5, 5.5, 1.2])  # replaces
         e = tuning.entries()
         assert [(d["kv_pad"], d["m_pad"]) for d in e] == [(256, 256), (512, 1024), (768, 0), (1024, 1024)]
-        assert e[0]["schedule"] == "columns" and e[0]["us"] == pytest.approx([4.9, 18.5, 5.5])
+        assert e[0]["schedule"] == "resident" and e[0]["us"] == pytest.approx([4.9, 18.5, 5.5, 1.2])
+        assert e[2]["us"] == pytest.approx([40.0, -1.0, 45.0, -1.0])
         assert e[3]["op"] == "bf16" and e[3]["schedule"] == "rowsplit"
         bad = [(100, 256, 64, "f32", "columns"), (256, 256, 65, "f32", "columns"),
-               (256, 256, 0, "f32", "rowsplit"), (0, 256, 64, "f32", "columns")]
+               (256, 256, 0, "f32", "rowsplit"), (256, 256, 0, "f32", "resident"), (0, 256, 64, "f32", "columns")]
         for kv, ks, m, op, sc in bad:
             with pytest.raises(_lib.RomError):
-                tuning.put(kv, ks, m, op, sc, [1.0, 1.0, 1.0])
-        ent = _lib.RomTuneEntry(256, 256, 64, _lib.ROM_F32, 3)
+                tuning.put(kv, ks, m, op, sc, [1.0, 1.0, 1.0, 1.0])
+        ent = _lib.RomTuneEntry(256, 256, 64, _lib.ROM_F32, 4)
         assert lib.rom_tune_put(ent) == _lib.ROM_E_ARG
         assert lib.rom_tune_get(99, _lib.RomTuneEntry()) == _lib.ROM_E_ARG
         p = tmp_path / "table.txt"
         tuning.save(str(p), header="test table")
         text = p.read_text()
-        assert text.startswith("# test table") and "512 512 1024 f32 columns 17.400 27.200 -1.000" in text
+        assert text.startswith("# test table") and "512 512 1024 f32 columns 17.400 27.200 -1.000 -1.000" in text
         tuning.clear()
         assert tuning.load(str(p)) == 4
         assert tuning.entries() == e
+        # a line of the earlier format (no resident time) still loads
+        p.write_text("256 256 64 f32 columns 1.0 2.0 3.0\n")
+        tuning.clear()
+        assert tuning.load(str(p)) == 1
+        assert tuning.entries()[0]["us"] == pytest.approx([1.0, 2.0, 3.0, -1.0])
         p.write_text("256 256 64 f32 columns 1.0\n")
         with pytest.raises(ValueError):
             tuning.load(str(p))
