@@ -353,6 +353,31 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
                          double *y, void *stream);
 
 /*
+ * Allocation-free rank-2 run, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc during a run): the
+ * rank-2 run of rom_run_rank2 on the
+ * ROWSPLIT schedule, arguments and results as there (bitwise the same as a
+ * rom_run_rank2 that takes ROWSPLIT), without allocating, tuning or
+ * synchronising.
+ *
+ * Its scratch (exchange rows, probe partials, barrier counters) lives in a
+ * static device array of 8448 KiB per GPU, held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (several
+ * streams, threads or contexts at once) race and give wrong results; calls
+ * in stream order are safe (each clears its counters before it runs).  The
+ * context's row-split operators are prepared by rom_create.  Requires FP32
+ * states (F32, BF16 or F8E4M3 operators), Kv == Ks in {256, 512, 1024},
+ * ceil(M / 64) * K / 64 <= 256 and a 256-CU gfx950: else ROM_E_UNSUPPORTED,
+ * as for a scratch need above the static size (nothing enqueued).  A group
+ * barrier that timed out is reported by rom_check.  The launch is
+ * cooperative and is not for graph capture.
+ * Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_DEVICE.
+ */
+rom_status rom_run_rank2_noalloc(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
+                                 int64_t nsteps, void *V, void *S, const void *c, double *J,
+                                 double *y, void *stream);
+
+/*
  * Discrete adjoint of a rank-2 run from step 0 for the probe QoI
  *   J = sum_m sum_{n=0}^{N-1} dt (c^T V_m^(n+1))^2
  * (differentiation of the leapfrog, the sensitivity use named in Sec. 5).

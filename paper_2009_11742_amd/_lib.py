@@ -30,7 +30,7 @@ ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8, ROM_SCHEDUL
 ROM_NSCHEDULES = 4
 
 # Every symbol include/rom.h declares.
-EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2",
+EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2", "rom_run_rank2_noalloc",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_group_schedule", "rom_group_times", "rom_group_check",
            "rom_get_operators", "rom_energy", "rom_check", "rom_debug_force_timeout", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
@@ -89,6 +89,8 @@ def load():
         lib.rom_run_rank1_batch.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp]
         lib.rom_run_rank2.restype = C.c_int
         lib.rom_run_rank2.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+        lib.rom_run_rank2_noalloc.restype = C.c_int
+        lib.rom_run_rank2_noalloc.argtypes = [_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
         lib.rom_adjoint.restype = C.c_int
         lib.rom_adjoint.argtypes = [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _i32, _vp]

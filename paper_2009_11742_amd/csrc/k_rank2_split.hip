@@ -37,6 +37,7 @@
 // FP32 partials meet in LDS, where each thread finishes 16 outputs: their
 // FP32 sum, then in FP64 the scale (FP8), forcing and the update of the
 // FP32 (hi, lo) state.
+#include <mutex>
 #include <string>
 
 #include "k_common.h"
@@ -876,7 +877,42 @@ int split_width_index(int M, int R) {
     return wi;
 }
 
+// Scratch of the allocation-free row-split run (rom_run_rank2_noalloc):
+// exchange rows, probe partials and barrier counters of the largest launch
+// the schedule makes (rank2_split_workspace_bytes over every eligible shape:
+// 8 MiB of exchange at G K = 256 x 64, 128 KiB of probe partials, 64 KiB of
+// counters).  One copy per GPU, held until the process ends; every call on a
+// GPU uses that GPU's copy.
+constexpr size_t kStaticScratchBytes = (size_t)8448 * 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 }  // namespace
+
+size_t rank2_split_static_bytes() { return kStaticScratchBytes; }
+
+// Device address of this GPU's static scratch, looked up once per device
+// with that device current (the array's host-side name is not a device
+// address).  Only the returned pointer is passed to kernels.
+hipError_t rank2_split_static_scratch(int device, void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 int rank2_split_groups_per_launch(int kvp) { return 256 / (kvp / kRows); }
 

@@ -538,6 +538,16 @@ rom_status build_ctx(const rom_config *cfg, bool skew, const double *sA, const d
                                           st), ": pack");
         }
     }
+    if (c->state_type == ROM_F32 && split_candidate(c, 1) > 0) {
+        // row-split operator packs up front (the allocation-free run needs
+        // them), and this device's static row-split scratch looked up once
+        // while the device is current (a failure is reported by the run that
+        // needs it)
+        rom_status rs = prepare_split_pack(c, st);
+        if (rs != ROM_OK) { free_ctx(c); return rs; }
+        void *scr = nullptr;
+        (void)rom::rank2_split_static_scratch(c->device, &scr);
+    }
     CHK(hipStreamSynchronize(st), ": synchronize");
 #undef CHK
     *out = c;
@@ -895,6 +905,41 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         e = rom::launch_rank2_valu<double>(a, st);
     }
     if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: launch");
+    return ROM_OK;
+}
+
+rom_status rom_run_rank2_noalloc(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, int64_t nsteps,
+                                 void *V, void *S, const void *c, double *J, double *y, void *stream) {
+    if (!ctx) return fail(ROM_E_ARG, "rom_run_rank2_noalloc: NULL context");
+    if (M < 1) return fail(ROM_E_ARG, "rom_run_rank2_noalloc: M must be >= 1");
+    if (!mu || !V || !S) return fail(ROM_E_ARG, "rom_run_rank2_noalloc: NULL mu, V or S");
+    if (n0 < 0 || nsteps < 0) return fail(ROM_E_ARG, "rom_run_rank2_noalloc: n0 and nsteps must be >= 0");
+    if ((J || y) && !c) return fail(ROM_E_ARG, "rom_run_rank2_noalloc: J and y require the probe c");
+    if (ctx->state_type != ROM_F32 || ctx->op_type == ROM_F64)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: FP32 states with F32, BF16 or F8E4M3 operators only");
+    const int G = split_candidate(ctx, M);
+    if (G == 0 || !ctx->avs_sp)
+        return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: the row-split schedule does not apply (Kv == Ks in "
+                                       "{256, 512, 1024}, ceil(M/64) * K/64 <= 256, a 256-CU gfx950)");
+    const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
+    if (need > rom::rank2_split_static_bytes())
+        return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: needs " + std::to_string(need) +
+                                           " bytes of scratch, above the static " +
+                                           std::to_string(rom::rank2_split_static_bytes()));
+    if (nsteps == 0) return ROM_OK;
+    void *scr = nullptr;
+    hipError_t e = rom::rank2_split_static_scratch(ctx->device, &scr);
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank2_noalloc: static scratch");
+    rom::Rank2Args a;
+    a.b = ctx->b; a.c = c; a.mu = mu; a.V = V; a.S = S; a.J = J; a.y = y;
+    a.kv = ctx->kv; a.ks = ctx->ks; a.kvp = ctx->kvp; a.ksp = ctx->ksp; a.M = M;
+    a.n0 = n0; a.nsteps = nsteps; a.dt = ctx->dt; a.source = ctx_source(ctx);
+    const bool lowp = ctx->op_type != ROM_F32;
+    a.single = (lowp && (ctx->flags & ROM_STATE_BF16)) ? 1 : 0;
+    e = rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, a, lowp ? ctx->op_scale : 1.0f, scr, G, ctx->status,
+                                !lowp, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank2_noalloc: launch");
+    ctx->last_schedule = ROM_SCHEDULE_ROWSPLIT;
     return ROM_OK;
 }
 

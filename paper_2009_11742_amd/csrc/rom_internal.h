@@ -171,6 +171,11 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
 size_t rank2_split_f32_lds_bytes();
 hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st);
 hipError_t rank2_split_configure();
+// Static scratch of the allocation-free row-split run: its size, and its
+// device address on `device` (which must be current at the first call for
+// that device; the lookup is done once per device).
+size_t rank2_split_static_bytes();
+hipError_t rank2_split_static_scratch(int device, void **ptr);
 // Receivers: Y and ensemble statistics of L steps from a chunk's state
 // traces (see k_receivers.hip).
 size_t receivers_lds_bytes(int kv, int M, int R);

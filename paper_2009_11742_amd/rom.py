@@ -219,6 +219,25 @@ class Rom:
         check(_lib.load().rom_run_rank2(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
                                         _ptr(c), _ptr(J), _ptr(y), _stream_handle(stream)))
 
+    def run_rank2_noalloc(self, mu, V, S, nsteps, n0=0, c=None, J=None, y=None, stream=None):
+        """run_rank2 on the row-split schedule without any device allocation
+        (the library's static per-GPU scratch; calls overlapping on one GPU
+        race).  Raises ROM_E_UNSUPPORTED where the row-split schedule does
+        not apply."""
+        M = int(mu.numel())
+        if mu.dtype != torch.float64 or not mu.is_cuda or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float64 CUDA tensor")
+        self._chk_state(V, self.kv, M, "V")
+        self._chk_state(S, self.ks, M, "S")
+        if c is not None:
+            self._chk_state(c.view(1, -1), self.kv, 1, "c")
+        if J is not None and (J.dtype != torch.float64 or J.numel() != M or not J.is_contiguous()):
+            raise ValueError("J must be a contiguous float64 tensor of M entries")
+        if y is not None and (y.dtype != torch.float64 or tuple(y.shape) != (int(nsteps), M) or not y.is_contiguous()):
+            raise ValueError("y must be a contiguous float64 tensor of shape (nsteps, M)")
+        check(_lib.load().rom_run_rank2_noalloc(self._ctx, M, _ptr(mu), int(n0), int(nsteps), _ptr(V), _ptr(S),
+                                                _ptr(c), _ptr(J), _ptr(y), _stream_handle(stream)))
+
     def energy(self, V, S, stream=None):
         """Per-sample modified energy |v|^2 + |s|^2 + dt v^T Avs s (float64 tensor)."""
         M = int(V.shape[0])
