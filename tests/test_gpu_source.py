@@ -2,13 +2,15 @@
 ROM_SOURCE_GAUSS1) on every stepping path, against the FP64 oracle run with
 the same source: FP32 column blocks (4 and 8 samples), FP32 and BF16
 row-split, the low-precision column blocks, the FP64 path, rank-1 steps,
-the adjoint's dJ/dmu, both grouped plans and the FOM.  Bars as for the
-Ricker runs: FP64 1e-12, FP32 1e-5, BF16 2e-3, adjoint 1e-4.  A Ricker run
-of the same inputs differs from these by far more than the bars.
+the adjoint's dJ/dmu, both grouped plans and the FOM, the operator-resident
+kernel.  Bars as for the Ricker runs: FP64 1e-12, FP32 1e-5, BF16
+lowp_bars.pair_bar(N), adjoint 1e-4.  A Ricker run of the same inputs
+differs from these by far more than the bars.
 """
 import numpy as np
 import pytest
 
+import lowp_bars
 import oracle
 import synth
 
@@ -41,11 +43,14 @@ def _run(rom, inst, N):
 
 @pytest.mark.parametrize("state,ops,schedule,K,M,bar", [
     ("f32", "f32", "columns", 128, 9, 1e-5), ("f32", "f32", "columns8", 96, 13, 1e-5),
-    ("f32", "f32", "rowsplit", 256, 70, 1e-5), ("f32", "bf16", "rowsplit", 256, 64, 2e-3),
-    ("f32", "bf16", "columns", 128, 6, 2e-3), ("f64", "f64", "auto", 64, 5, 1e-12)])
+    ("f32", "f32", "rowsplit", 256, 70, 1e-5), ("f32", "bf16", "rowsplit", 256, 64, "pair"),
+    ("f32", "bf16", "columns", 128, 6, "pair"), ("f64", "f64", "auto", 64, 5, 1e-12),
+    ("f32", "f32", "resident", 256, 11, 1e-5), ("f32", "f32", "resident", 96, 5, 1e-5)])
 def test_rank2_gauss1_matches_oracle(state, ops, schedule, K, M, bar):
     inst = synth.round_to(synth.make_instance(K, K, M, seed=K + M), state)
     N = 800
+    if bar == "pair":
+        bar = lowp_bars.pair_bar(N)
     rom = _rom(inst, state=state, ops=ops, schedule=schedule)
     V, S, J = _run(rom, inst, N)
     A, B, _ = rom.operators()
@@ -57,6 +62,8 @@ def test_rank2_gauss1_matches_oracle(state, ops, schedule, K, M, bar):
           % (state, ops, schedule, K, M, e, eJ, _relcol(V, rr["V"])))
     assert e <= bar and eJ <= bar
     assert _relcol(V, rr["V"]) > 100 * bar
+    if schedule != "auto":
+        assert rom.last_schedule == schedule
     rom.close()
 
 
