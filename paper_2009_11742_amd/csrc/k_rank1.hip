@@ -88,27 +88,114 @@ __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ 
 // sample m through all its steps, and every half-step is a matrix-vector
 // product that reads the operator from device memory again -- the rank-1
 // cost model of Sec. 2.3 (no reuse of an operator entry within a step),
-// with the whole chip busy and no launch per step.  Thread t owns rows t,
-// t + 256, ... of both fields (at most kRank1Rows each); the state hi words
-// pass through LDS to the other half-step.  The arithmetic per row is the
-// single-sample kernel's: compensated chunks of kChunk terms in increasing
-// k, then the double-float update.
-constexpr int kRank1Rows = 4;
+// with the whole chip busy and no launch per step.
+//
+// Per half-step the rows go in passes of four 64-row blocks; in a pass lane
+// l of every wave holds row l of each of the four blocks, and wave w sums
+// the reduction quarter w for all four, so each k step issues four
+// independent 256-byte loads (one per block) and the loads of a chunk are in
+// flight together.  The four quarter sums of block j meet in LDS and wave j
+// finishes them.  Per row this is exactly the single-sample kernel's
+// arithmetic (the same quarters, chunks of kChunk terms, two-sums, combine
+// order, forcing and double-float update, rounded once per half-step), so a
+// sample's trajectory equals rom_step_rank1's bit for bit.  The state hi
+// words pass through LDS to the other half-step.
+constexpr int kRank1Rows = 4;          // rows per lane and field (K <= 1024)
+constexpr int kBatch = 16;             // terms whose loads are in flight together
 
-__device__ __forceinline__ void rank1_row(const float *__restrict__ A, int rows, int cols, int i,
-                                          const float *__restrict__ x, float &H, float &L) {
-    float hi = 0.f, lo = 0.f;
-    for (int c0 = 0; c0 < cols; c0 += kChunk) {
-        const int c1 = min(cols, c0 + kChunk);
-        float acc = 0.f;
-        for (int k = c0; k < c1; ++k) acc = fmaf(A[i + (size_t)k * rows], x[k], acc);
-        float s, e;
-        dev::two_sum(hi, acc, s, e);
-        hi = s;
-        lo += e;
+// One half-step of the field with operator A (rows x cols): x (LDS, cols)
+// is the other field, xo (LDS, rows) receives this field's new hi words;
+// (h, l) are this lane's rows (one per pass).  FORCED adds b u.
+template <bool FORCED>
+__device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, int rows, int cols,
+                                                 const float *__restrict__ x, float *__restrict__ xo,
+                                                 const float *__restrict__ b, float uh, float ul, float dt,
+                                                 float (&h)[kRank1Rows], float (&pH)[4][4][64],
+                                                 float (&pL)[4][4][64]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = (cols + 3) / 4;
+    const int k0 = w * kq, k1 = min(cols, k0 + kq);
+    const int nblk = (rows + 63) / 64;
+    // rows a multiple of 4: a lane's four rows of a pass are 4 consecutive
+    // ones, one 16-byte load per term (1 KB per wave instruction); else one
+    // row from each of four 64-row blocks, 4-byte loads
+    const bool vec = (rows & 3) == 0;
+    for (int pass = 0; 4 * pass < nblk; ++pass) {
+        float hi[4], lo[4];
+        int rc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            hi[j] = lo[j] = 0.f;
+            // rows past the end read the last row(s) (in bounds) and are never finished
+            rc[j] = vec ? min(256 * pass + 4 * lane, rows - 4) + j : min((4 * pass + j) * 64 + lane, rows - 1);
+        }
+        for (int c0 = k0; c0 < k1; c0 += kChunk) {
+            const int c1 = min(k1, c0 + kChunk);
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            // batches of kBatch terms: all their loads are issued before the
+            // first multiply-add of the batch (the terms past c1 re-read the
+            // chunk's last column and are not used)
+            for (int kb = c0; kb < c1; kb += kBatch) {
+                const int kn = min(kBatch, c1 - kb);
+                float av[kBatch][4], xk[kBatch];
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    const int k = kb + min(t, kn - 1);
+                    const float *col = A + (size_t)k * rows;
+                    if (vec) {
+                        const dev::f4 v = *reinterpret_cast<const dev::f4 *>(col + rc[0]);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) av[t][j] = v[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) av[t][j] = col[rc[j]];
+                    }
+                    xk[t] = x[k];
+                }
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t)
+                    if (t < kn) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[j] = fmaf(av[t][j], xk[t], acc[j]);
+                    }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float s, e;
+                dev::two_sum(hi[j], acc[j], s, e);
+                hi[j] = s;
+                lo[j] += e;
+            }
+        }
+        // partial of pass row q (0..255) at pH[w][q / 64][q % 64]
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = vec ? 4 * lane + j : 64 * j + lane;
+            pH[w][q >> 6][q & 63] = hi[j];
+            pL[w][q >> 6][q & 63] = lo[j];
+        }
+        __syncthreads();
+        const int i = (4 * pass + w) * 64 + lane;       // wave w finishes block 4 pass + w
+        if (i < rows) {
+            float H = pH[0][w][lane], L = pL[0][w][lane];
+            for (int q = 1; q < 4; ++q) {
+                float s, e;
+                dev::two_sum(H, pH[q][w][lane], s, e);
+                H = s;
+                L += e + pL[q][w][lane];
+            }
+            float F = 0.f, Fe = 0.f;
+            if (FORCED) {
+                F = b[i] * uh;
+                Fe = fmaf(b[i], uh, -F) + b[i] * ul;
+            }
+            float hh = h[pass], ll = 0.f;
+            dev::comp_update(hh, ll, H, L, F, Fe, dt);
+            h[pass] = hh + ll;                  // rounded once per half-step
+            xo[i] = h[pass];
+        }
+        __syncthreads();                        // partials read before the next pass writes them
     }
-    H = hi;
-    L = lo;
 }
 
 __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__ Avs, const float *__restrict__ Asv,
@@ -116,54 +203,29 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
                                                        int kv, int ks, double dt, int64_t n0, int64_t nsteps,
                                                        int src, float *__restrict__ V, float *__restrict__ S) {
     extern __shared__ float xsh[];
+    __shared__ float pH[4][4][64], pL[4][4][64];
     float *xs = xsh, *xv = xsh + ks;           // S and V hi words
-    const int m = blockIdx.x, tid = threadIdx.x;
-    float vh[kRank1Rows], vl[kRank1Rows], sh[kRank1Rows], sl[kRank1Rows];
+    const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // lane's rows: (4 pass + w) * 64 + lane, pass = 0 .. kRank1Rows - 1
+    float vh[kRank1Rows], sh[kRank1Rows];
 #pragma unroll
     for (int q = 0; q < kRank1Rows; ++q) {
-        const int iv = tid + 256 * q, is = tid + 256 * q;
-        vh[q] = iv < kv ? V[(size_t)m * kv + iv] : 0.f;
-        sh[q] = is < ks ? S[(size_t)m * ks + is] : 0.f;
-        vl[q] = sl[q] = 0.f;
-        if (is < ks) xs[is] = sh[q];
+        const int i = (4 * q + w) * 64 + lane;
+        vh[q] = i < kv ? V[(size_t)m * kv + i] : 0.f;
+        sh[q] = i < ks ? S[(size_t)m * ks + i] : 0.f;
+        if (i < ks) xs[i] = sh[q];
     }
     const double mum = mu[m];
     __syncthreads();
     for (int64_t k = 0; k < nsteps; ++k) {
         const double u = dev::forcing(src, (double)(n0 + k) * dt, mum);
         const float uh = (float)u, ul = (float)(u - (double)uh);
-#pragma unroll
-        for (int q = 0; q < kRank1Rows; ++q) {
-            const int i = tid + 256 * q;
-            if (i < kv) {
-                float H, L;
-                rank1_row(Avs, kv, ks, i, xs, H, L);
-                const float F = b[i] * uh;
-                const float Fe = fmaf(b[i], uh, -F) + b[i] * ul;
-                dev::comp_update(vh[q], vl[q], H, L, F, Fe, (float)dt);
-                vh[q] = vh[q] + vl[q];      // rounded once per half-step, as the single-sample kernel
-                vl[q] = 0.f;
-                xv[i] = vh[q];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kRank1Rows; ++q) {
-            const int i = tid + 256 * q;
-            if (i < ks) {
-                float H, L;
-                rank1_row(Asv, ks, kv, i, xv, H, L);
-                dev::comp_update(sh[q], sl[q], H, L, 0.f, 0.f, (float)dt);
-                sh[q] = sh[q] + sl[q];
-                sl[q] = 0.f;
-                xs[i] = sh[q];     // xs is read only by the velocity half-step
-            }
-        }
-        __syncthreads();
+        rank1_batch_half<true>(Avs, kv, ks, xs, xv, b, uh, ul, (float)dt, vh, pH, pL);
+        rank1_batch_half<false>(Asv, ks, kv, xv, xs, nullptr, 0.f, 0.f, (float)dt, sh, pH, pL);
     }
 #pragma unroll
     for (int q = 0; q < kRank1Rows; ++q) {
-        const int i = tid + 256 * q;
+        const int i = (4 * q + w) * 64 + lane;
         if (i < kv) V[(size_t)m * kv + i] = vh[q];
         if (i < ks) S[(size_t)m * ks + i] = sh[q];
     }

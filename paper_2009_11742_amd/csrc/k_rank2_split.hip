@@ -125,6 +125,42 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
     // barrier.
 }
 
+// Sum of the probe partials of one column: the R row tiles' values at
+// p[q * stride], read with device-scope loads (other workgroups wrote them)
+// four at a time, all four in flight before the first is used (entries past
+// R re-read entry R - 1 and are not added; four keep the register pressure
+// of the kernels' time loop where it was), summed in the order q = 0 .. R-1.
+constexpr int kProbeBatch = 4;
+__device__ __forceinline__ double sum_partials(const double *p, int stride, int R) {
+    double y = 0.0;
+    for (int q0 = 0; q0 < R; q0 += kProbeBatch) {
+        double v[kProbeBatch];
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q)
+            v[q] = __hip_atomic_load(p + (size_t)min(q0 + q, R - 1) * stride, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q)
+            if (q0 + q < R) y += v[q];
+    }
+    return y;
+}
+
+// Forcing of a window of kUWin steps for the group's NC columns, in LDS:
+// u[s][j] = u(t_{n + s}; mu of column col0 + j) (zero past M), evaluated by
+// all threads together once per window, so each step reads its column's
+// value instead of evaluating the source (whose exp constants would
+// otherwise be held, and spilled, across the time loop).
+constexpr int kUWin = 16;
+template <int NC>
+__device__ __forceinline__ void forcing_window(double *u, int src, int64_t n, double dt, const double *mu, int col0,
+                                               int M) {
+    for (int idx = threadIdx.x; idx < kUWin * NC; idx += kThreads) {
+        const int s = idx / NC, j = idx - s * NC, m = col0 + j;
+        u[idx] = m < M ? dev::forcing(src, (double)(n + s) * dt, mu[m]) : 0.0;
+    }
+}
+
 // Products of one half-step for wave w: acc[rb][cb] (rows 16 rb.., columns
 // 16 cb..) = sum over this wave's KB k-blocks of op fragments x (x_hi + x_lo).
 // x points at the group's exchange block of the other field.  The B
@@ -249,6 +285,7 @@ void rank2_split_kernel(SplitArgs a) {
     float *bl = part + kWaves * NC * kLd;                // own rows of b
     float *cl = bl + kRows;                                 // own rows of c
     __shared__ int sh_slot;
+    __shared__ double uwin[kUWin * NC];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -307,7 +344,6 @@ void rank2_split_kernel(SplitArgs a) {
     const int fj = tid / TPC, fs = tid % TPC;
     const int fm = col0 + fj;
     const bool fok = fm < a.M;
-    const double fmu = fok ? a.mu[fm] : 1.0;
 
     // publish rows of field f (hi words) as BF16 (hi, lo) into x, in the
     // B-fragment order: tile row o of column fj is term o % 8 of lane
@@ -348,7 +384,7 @@ void rank2_split_kernel(SplitArgs a) {
 
     // products -> LDS partials -> finished rows (FP64 update) -> published
     auto half_step = [&](int f, const u4 (&op)[4][KB], const unsigned short *xother, unsigned short *xmine,
-                         double u, bool forced) -> double {
+                         const double *up, bool forced) -> double {
         f4 acc[4][NCB];
         products<KB, SINGLE, NCB>(op, xother + (size_t)g * NC * 2 * kp, 2u * NC * 2 * kp, w, lane, acc);
         float *pw = part + w * NC * kLd;
@@ -358,6 +394,7 @@ void rank2_split_kernel(SplitArgs a) {
             for (int cb = 0; cb < NCB; ++cb)
                 *reinterpret_cast<f4 *>(pw + (16 * cb + (lane & 15)) * kLd + 16 * rb + 4 * (lane >> 4)) = acc[rb][cb];
         __syncthreads();
+        const double u = forced ? *up : 0.0;
         double ypart = 0.0;
         float *h = sth + (f * NC + fj) * kLd + RPT * fs;
         float *l = stl + (f * NC + fj) * kLd + RPT * fs;
@@ -396,10 +433,9 @@ void rank2_split_kernel(SplitArgs a) {
     double Jacc = 0.0;
     const bool probe = a.c != nullptr;
     for (int64_t k = 0; k < a.nsteps; ++k) {
-        const int64_t n = a.n0 + k;
-        const double t = (double)n * a.dt;
-        const double u = fok ? dev::forcing(a.source, t, fmu) : 0.0;
-        double yp = half_step(0, opv, a.xs, a.xv, u, true);
+        if (k % kUWin == 0) forcing_window<NC>(uwin, a.source, a.n0 + k, a.dt, a.mu, col0, a.M);
+        // (read after the products' barrier inside half_step)
+        double yp = half_step(0, opv, a.xs, a.xv, uwin + (k % kUWin) * NC + fj, true);
         if (probe) {
             // sum the TPC strips of column fj, then publish this tile's partial
 #pragma unroll
@@ -408,13 +444,12 @@ void rank2_split_kernel(SplitArgs a) {
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
-            double yv = 0.0;
-            for (int q = 0; q < R; ++q)
-                yv += __hip_atomic_load(&a.yp[((size_t)g * R + q) * NC + fj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the R row-tile partials, all loads in flight together
+            const double yv = sum_partials(a.yp + (size_t)g * R * NC + fj, NC, R);
             Jacc += a.dt * (yv * yv);
             if (a.y) a.y[(size_t)k * a.M + fm] = yv;
         }
-        half_step(1, ops, a.xv, a.xs, 0.0, false);
+        half_step(1, ops, a.xv, a.xs, nullptr, false);
         group_barrier(a, cnt, (unsigned)R * ++phase);
     }
 
@@ -550,6 +585,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     float *bl = reinterpret_cast<float *>(part + kWaves * NC * kLdD);
     float *cl = bl + kRows;
     __shared__ int sh_slot;
+    __shared__ double uwin[kUWin * NC];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -605,7 +641,6 @@ void rank2_split_f32_kernel(SplitArgs a) {
     auto frow = [&](int e) { return 16 * kgl + 4 * (e / NCB) + q0 + e % NCB; };   // row within the tile
     const int fm = col0 + fj;
     const bool fok = fm < M;
-    const double fmu = fok ? mup[fm] : 1.0;
     float sh[2][RPT], sl[2][RPT];
 #pragma unroll
     for (int f = 0; f < 2; ++f)
@@ -636,7 +671,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
         }
     };
 
-    auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, double u,
+    auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, const double *up,
                          bool forced) -> double {
         double acc[4][NCB][4];
         products_f32<KG, NCB>(opw, xother + (size_t)g * NC * kp, 4u * NC * kp, w, lane, acc);
@@ -650,6 +685,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
                 for (int rr = 0; rr < 4; ++rr) d[rr] = acc[rb][cb][rr];
             }
         __syncthreads();
+        const double u = forced ? *up : 0.0;
         double ypart = 0.0;
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
@@ -674,10 +710,9 @@ void rank2_split_f32_kernel(SplitArgs a) {
     double Jacc = 0.0;
     const bool probe = csrc != nullptr;
     for (int64_t k = 0; k < a.nsteps; ++k) {
-        const int64_t n = a.n0 + k;
-        const double t = (double)n * dt;
-        const double u = fok ? dev::forcing(src, t, fmu) : 0.0;
-        double yp = half_step(0, opvw, xs, xv, u, true);
+        if (k % kUWin == 0) forcing_window<NC>(uwin, src, a.n0 + k, dt, mup, col0, M);
+        // (read after the products' barrier inside half_step)
+        double yp = half_step(0, opvw, xs, xv, uwin + (k % kUWin) * NC + fj, true);
         if (probe) {
             // sum over the TPC consecutive threads of column fj
 #pragma unroll
@@ -686,13 +721,11 @@ void rank2_split_f32_kernel(SplitArgs a) {
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
-            double yv = 0.0;
-            for (int q = 0; q < R; ++q)
-                yv += __hip_atomic_load(&a.yp[((size_t)g * R + q) * NC + fj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const double yv = sum_partials(a.yp + (size_t)g * R * NC + fj, NC, R);
             Jacc += dt * (yv * yv);
             if (a.y) a.y[(size_t)k * M + fm] = yv;
         }
-        half_step(1, opsw, xv, xs, 0.0, false);
+        half_step(1, opsw, xv, xs, nullptr, false);
         group_barrier(a, cnt, (unsigned)R * ++phase);
     }
 

@@ -1,8 +1,9 @@
 """Rank-1 formulation of many samples in one launch (rom_run_rank1_batch):
 one workgroup per sample, the operator re-read every half-step.  Parity
 against the FP64 oracle at the FP32 bar (1e-5) with the state rounded once
-per half-step, as the single-sample rank-1 step does; and against that step
-itself to the same bar."""
+per half-step, as the single-sample rank-1 step does; and, since it does
+each row's arithmetic in the same order as that step, bitwise equality
+with rom_run_rank1 on the first and last samples."""
 import numpy as np
 import pytest
 
@@ -33,12 +34,13 @@ def test_rank1_batch_parity(kv, ks, M, N, skew):
     ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
     Vg, Sg = V.cpu().numpy().astype(np.float64).T, S.cpu().numpy().astype(np.float64).T
     ev, es = _relcol(Vg, ref["V"]), _relcol(Sg, ref["S"])
-    # column 0 stepped by the single-sample rank-1 entry point
-    v = torch.zeros(kv, dtype=torch.float32, device="cuda")
-    s = torch.zeros(ks, dtype=torch.float32, device="cuda")
-    rom.run_rank1(v, s, float(inst["mu"][0]), N)
-    torch.cuda.synchronize()
-    e1 = float(np.linalg.norm(Vg[:, 0] - v.cpu().numpy()) / np.linalg.norm(ref["V"][:, 0]))
-    print("rank-1 batch K=(%d,%d) M=%d N=%d: V %.2e S %.2e vs step_rank1 %.2e" % (kv, ks, M, N, ev, es, e1))
-    assert max(ev, es, e1) <= BAR
+    print("rank-1 batch K=(%d,%d) M=%d N=%d: V %.2e S %.2e" % (kv, ks, M, N, ev, es))
+    assert max(ev, es) <= BAR
+    # the first and last samples stepped by the single-sample rank-1 entry point
+    for m in (0, M - 1):
+        v = torch.zeros(kv, dtype=torch.float32, device="cuda")
+        s = torch.zeros(ks, dtype=torch.float32, device="cuda")
+        rom.run_rank1(v, s, float(inst["mu"][m]), N)
+        torch.cuda.synchronize()
+        assert torch.equal(v, V[m]) and torch.equal(s, S[m]), m
     rom.close()
