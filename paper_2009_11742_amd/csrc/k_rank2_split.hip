@@ -224,10 +224,19 @@ __device__ __forceinline__ void load_b(const XBuf &xg, int kb, unsigned loff, u4
     }
 }
 
+// Ring depth in k-blocks: as deep as the registers left beside the resident
+// operator allow (the loads' latency, not the L2 bandwidth, bounds the
+// exchange reads: bytes in flight / latency).
+template <int KB, bool SINGLE, int NCB>
+constexpr int ring_depth() {
+    constexpr int d = SINGLE ? 4 : (NCB == 4 ? kDepth : 3);
+    return KB < d ? KB : d;
+}
+
 template <int KB, bool SINGLE, int NCB>
 __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned short *x, unsigned xbytes, int w,
                                          int lane, f4 (&acc)[4][NCB]) {
-    constexpr int D = KB < kDepth ? KB : kDepth;
+    constexpr int D = ring_depth<KB, SINGLE, NCB>();
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -240,32 +249,35 @@ __device__ __forceinline__ void products(const u4 (&op)[4][KB], const unsigned s
     const XBuf xg(bits, xbytes);
     // this wave's k-blocks are w KB .. w KB + KB - 1 of the group's block
     const int kb0 = w * KB;
+    const unsigned loff = 16u * (unsigned)lane;
     u4 rh[D][NCB], rl[D][NCB];
 #pragma unroll
-    for (int d = 0; d < D; ++d) load_b<SINGLE, NCB>(xg, kb0 + d, 16u * (unsigned)lane, rh[d], rl[d]);
+    for (int d = 0; d < D; ++d) load_b<SINGLE, NCB>(xg, kb0 + d, loff, rh[d], rl[d]);
     __builtin_amdgcn_sched_barrier(0);
+    // Column block by column block: the MFMAs of k-block kb that read a ring
+    // slot's column-block fragments are issued, then that column block's
+    // fragments of k-block kb + D are loaded into the same registers.  The
+    // ring needs no copies of the fragments in use, and each load still has
+    // the rest of this k-block and all of the next ahead of its use.
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const int slot = kb % D;
-        u4 h[NCB], l[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-            h[cb] = rh[slot][cb];
-            if constexpr (!SINGLE) l[cb] = rl[slot][cb];
-        }
-        if (kb + D < KB) load_b<SINGLE, NCB>(xg, kb0 + kb + D, 16u * (unsigned)lane, rh[slot], rl[slot]);
-        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-            const bf8 A = as_bf8(op[rb][kb]);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(h[cb]), acc[rb][cb], 0, 0, 0);
+            for (int rb = 0; rb < 4; ++rb) {
+                const bf8 A = as_bf8(op[rb][kb]);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(rh[slot][cb]), acc[rb][cb], 0, 0, 0);
                 if constexpr (!SINGLE)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(l[cb]), acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, as_bf8(rl[slot][cb]), acc[rb][cb], 0, 0, 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            if (kb + D < KB) {
+                rh[slot][cb] = xg.ld(2u * (unsigned)frag_offset<NCB>(kb0 + kb + D, cb, 0) + loff);
+                if constexpr (!SINGLE) rl[slot][cb] = xg.ld(2u * (unsigned)frag_offset<NCB>(kb0 + kb + D, cb, 1) + loff);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
