@@ -289,7 +289,8 @@ def rank1_batch_rate(torch, rom, inst, nsteps):
     gbs = rate * op_bytes / 1e9
     return {"value": rate, "unit": "sample-steps/s", "us_per_step": ksec / nsteps * 1e6,
             "operator_bytes_per_sample_step": op_bytes, "operator_GB_per_s": gbs,
-            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "served_from": "L2" if op_bytes <= 4 * 2 ** 20 else "HBM",
+            "ratio_to_hbm_peak": gbs / HBM_PEAK_GBS,
             "sample": "%d samples x %d steps in one launch (rom_run_rank1_batch), median of 3" % (Mb, nsteps)}
 
 
@@ -445,6 +446,8 @@ def workload_grouped(args, torch, dev):
         ss += M * N
     mus = [torch.tensor(inst["mu"], dtype=torch.float64, device=dev) for inst in insts]
 
+    info = {}
+
     def timed(schedule):
         roms, Vs, Ss = [], [], []
         for inst in insts:
@@ -452,6 +455,9 @@ def workload_grouped(args, torch, dev):
             V, S = rom.zeros(len(inst["mu"]), device=dev)
             roms.append(rom); Vs.append(V); Ss.append(S)
         plan = GroupPlan(roms, mus, Vs, Ss)
+        if schedule == "auto":
+            info["split_k"] = plan.split_k
+            info["plan_times_us_per_step"] = plan.times
         wall, ms = _events_time(torch, lambda: plan.run(N), 3, 1)
         plan.close()
         for r in roms:
@@ -473,6 +479,8 @@ def workload_grouped(args, torch, dev):
            "value": ss / ksec, "unit": "sample-steps/s", "tflops": flops / ksec / 1e12,
            "frac_fp32_mfma": flops / ksec / 1e12 / 157.3, "ms_per_run": ksec * 1e3,
            "ms_per_run_fixed_tile": fixed, "instances_on_8_column_tiles": n8,
+           "rowsplit_from_padded_k": info.get("split_k"),
+           "plan_times_us_per_step": info.get("plan_times_us_per_step"),
            "tile_table_us_per_workgroup_step": table}
     return out
 
@@ -511,7 +519,10 @@ def workload_copy(args, torch, dev):
 
 def workload_sweep(args, torch, dev):
     """Rank-2 vs rank-1 over K in {256, 512, 1024} x M in {1, 4, 16, 64, 256,
-    1024} (FP32 operators and states, median of 3 timed runs per point)."""
+    1024} (FP32 operators and states, median of 3 timed runs per point).
+    Rank-1 twice: the graph path (one sample per graph, two GEMV launches
+    per step, best of 8 / 32 streams) and the batch reference (all M samples
+    in one launch, rom_run_rank1_batch)."""
     import synth
     from paper_2009_11742_amd import Rom
     Ms = (1, 4, 16, 64, 256, 1024)
@@ -530,9 +541,17 @@ def workload_sweep(args, torch, dev):
                 rom.run_rank2(mu, V, S, N)
             wall, ms = _events_time(torch, run, 3, 1)
             ksec = float(np.median(ms)) * 1e-3
+
+            def run_b():
+                V.zero_(); S.zero_()
+                rom.run_rank1_batch(mu, V, S, N)
+            _, msb = _events_time(torch, run_b, 3, 1)
+            kb = float(np.median(msb)) * 1e-3
             pt = {"K": K, "M": M, "nsteps": N, "rank2": M * N / ksec,
                   "rank2_us_per_step": ksec / N * 1e6, "rank1": r1["value"],
                   "rank1_streams": r1["streams"], "ratio": M * N / ksec / r1["value"],
+                  "rank1_batch": M * N / kb, "rank1_batch_us_per_step": kb / N * 1e6,
+                  "ratio_batch": kb / ksec,
                   "tflops": 4.0 * K * K * M * N / ksec / 1e12, "schedule": rom.last_schedule}
             try:
                 pt["tuner_us_per_step"] = rom.schedule_times(M)

@@ -366,8 +366,10 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  * streams, threads or contexts at once) race and give wrong results; calls
  * in stream order are safe (each clears its counters before it runs).  The
  * context's row-split operators are prepared by rom_create.  Requires FP32
- * states (F32, BF16 or F8E4M3 operators), Kv == Ks in {256, 512, 1024},
- * ceil(M / 64) * K / 64 <= 256 and a 256-CU gfx950: else ROM_E_UNSUPPORTED,
+ * states, Kv == Ks, a padded K the row-split schedule takes (F32 operators:
+ * a multiple of 64 in [128, 2048]; BF16 or F8E4M3: 256, 512 or 1024), the
+ * ceil(M / 64) groups of 64 samples in one launch (at most 8 floor(32 /
+ * (K / 64))) and a 256-CU gfx950: else ROM_E_UNSUPPORTED,
  * as for a scratch need above the static size (nothing enqueued).  A group
  * barrier that timed out is reported by rom_check.  The launch is
  * cooperative and is not for graph capture.
@@ -484,32 +486,43 @@ rom_status rom_group_run(rom_group *g, int64_t n0, int64_t nsteps, void *stream)
 rom_status rom_group_destroy(rom_group *g);
 
 /*
- * Row-split grouped plan.  When every instance is square (Kv == Ks) with
- * the same padded K in {256, 512, 1024} and none is pinned to column blocks
- * (ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8), a plan can instead split each
- * instance's samples into groups of 64 and the operator rows of a group
- * over K / 64 workgroups, as the row-split schedule of rom_run_rank2 does
- * for one instance; 256 / (K / 64) groups run per cooperative launch, the
- * launches one after another.  Each instance's result is then bitwise
- * identical to its own rom_run_rank2 on the row-split schedule.  Which plan
- * runs: row-split if every context has ROM_SCHED_ROWSPLIT, else the faster
- * of the two, timed once per shape (padded K and the list of M) on scratch
- * states when the plan is made (rom_group_create: on the default stream;
- * rom_run_grouped: on `stream`) and remembered for the process.  A plan
- * keeps the column-block form too: a run enqueued on a stream that is being
- * captured into a graph uses it.  Making such a plan also packs each
- * context's row-split operators (2 K^2 floats per context, kept by it).
+ * Row-split grouped plan.  Instances that are square (Kv == Ks) with FP32
+ * operators and a padded K the row-split schedule takes (a multiple of 64
+ * in [128, 2048]), and that are not pinned to column blocks
+ * (ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8), can instead run as the
+ * row-split schedule of rom_run_rank2 runs one instance: samples in groups
+ * of 64, the operator rows of a group over K / 64 workgroups of one XCD.
+ * A plan puts the eligible instances from a padded-K threshold up on
+ * row-split: their groups, largest K first, fill cooperative launches (8
+ * XCDs x 32 workgroups each, groups of different K side by side), run one
+ * after another, followed by one column-block launch over the other
+ * instances.  Each instance's result is bitwise identical to its own
+ * rom_run_rank2 on the schedule it ran on.  Which threshold: the smallest
+ * eligible K if every context has ROM_SCHED_ROWSPLIT, else the fastest of
+ * "none" (column blocks only) and each eligible padded K, timed once per
+ * shape (the instances' padded K and M) on scratch states when the plan is
+ * made (rom_group_create: on the default stream; rom_run_grouped: on
+ * `stream`) and remembered for the process.  A plan keeps the all-column
+ * form too: a run enqueued on a stream that is being captured into a graph
+ * uses it.  Making such a plan also packs each eligible context's row-split
+ * operators (2 K^2 floats per context, kept by it).
  *
- * rom_group_schedule: ROM_SCHEDULE_ROWSPLIT or ROM_SCHEDULE_COLUMNS4 (the
- *   column-block plan, whatever tiles its instances take); -1 for NULL.
- * rom_group_times: per-step microseconds of the column-block (us[0]) and
- *   row-split (us[1]) plans if this plan timed them, else negative.
+ * rom_group_schedule: ROM_SCHEDULE_ROWSPLIT (a plan with a row-split
+ *   part) or ROM_SCHEDULE_COLUMNS4 (column blocks only, whatever tiles its
+ *   instances take); -1 for NULL.
+ * rom_group_times: per-step microseconds of the column-block plan (us[0])
+ *   and of the fastest plan with a row-split part (us[1]) if this plan
+ *   timed them, else negative.
+ * rom_group_split_k: the smallest padded K of the instances on the plan's
+ *   row-split part (every eligible instance with at least that padded K
+ *   runs there), 0 for a column-block plan, -1 for NULL.
  * rom_group_check: as rom_check, for the row-split plan's group barriers
  *   (synchronises `stream`).  rom_run_grouped synchronises `stream` after
  *   its run and returns ROM_E_TIMEOUT itself.
  */
 int32_t rom_group_schedule(const rom_group *g);
 rom_status rom_group_times(const rom_group *g, double us[2]);
+int32_t rom_group_split_k(const rom_group *g);
 rom_status rom_group_check(rom_group *g, void *stream);
 
 /*

@@ -32,7 +32,7 @@ ROM_NSCHEDULES = 4
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2", "rom_run_rank2_noalloc",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
-           "rom_group_schedule", "rom_group_times", "rom_group_check",
+           "rom_group_schedule", "rom_group_times", "rom_group_split_k", "rom_group_check",
            "rom_get_operators", "rom_energy", "rom_check", "rom_debug_force_timeout", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
@@ -120,6 +120,8 @@ def load():
         lib.rom_check_finite.argtypes = [_vp, _i32, _vp, _vp, _vp]
         lib.rom_group_schedule.restype = _i32
         lib.rom_group_schedule.argtypes = [_vp]
+        lib.rom_group_split_k.restype = _i32
+        lib.rom_group_split_k.argtypes = [_vp]
         lib.rom_group_times.restype = C.c_int
         lib.rom_group_times.argtypes = [_vp, _pd]
         lib.rom_group_check.restype = C.c_int

@@ -93,15 +93,19 @@ __global__ __launch_bounds__(256) void gemv_half_f64(const double *__restrict__ 
 // Per half-step the rows go in passes of four 64-row blocks; in a pass lane
 // l of every wave holds row l of each of the four blocks, and wave w sums
 // the reduction quarter w for all four, so each k step issues four
-// independent 256-byte loads (one per block) and the loads of a chunk are in
-// flight together.  The four quarter sums of block j meet in LDS and wave j
+// independent 256-byte loads (one per block); the loads of two batches of
+// kBatch terms are in flight at once.  The four quarter sums of block j meet in LDS and wave j
 // finishes them.  Per row this is exactly the single-sample kernel's
 // arithmetic (the same quarters, chunks of kChunk terms, two-sums, combine
 // order, forcing and double-float update, rounded once per half-step), so a
 // sample's trajectory equals rom_step_rank1's bit for bit.  The state hi
 // words pass through LDS to the other half-step.
 constexpr int kRank1Rows = 4;          // rows per lane and field (K <= 1024)
-constexpr int kBatch = 16;             // terms whose loads are in flight together
+typedef const __attribute__((address_space(1))) unsigned char gbyte;
+typedef const __attribute__((address_space(1))) dev::f4 gf4;
+typedef const __attribute__((address_space(1))) float gfloat;
+constexpr int kBatch = 16;             // terms per batch of loads (two batches in flight)
+static_assert(kChunk % kBatch == 0, "chunks are whole batches");
 
 // One half-step of the field with operator A (rows x cols): x (LDS, cols)
 // is the other field, xo (LDS, rows) receives this field's new hi words;
@@ -112,7 +116,7 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
                                                  const float *__restrict__ b, float uh, float ul, float dt,
                                                  float (&h)[kRank1Rows], float (&pH)[4][4][64],
                                                  float (&pL)[4][4][64]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int kq = (cols + 3) / 4;
     const int k0 = w * kq, k1 = min(cols, k0 + kq);
     const int nblk = (rows + 63) / 64;
@@ -129,42 +133,61 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
             // rows past the end read the last row(s) (in bounds) and are never finished
             rc[j] = vec ? min(256 * pass + 4 * lane, rows - 4) + j : min((4 * pass + j) * 64 + lane, rows - 1);
         }
-        for (int c0 = k0; c0 < k1; c0 += kChunk) {
-            const int c1 = min(k1, c0 + kChunk);
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            // batches of kBatch terms: all their loads are issued before the
-            // first multiply-add of the batch (the terms past c1 re-read the
-            // chunk's last column and are not used)
-            for (int kb = c0; kb < c1; kb += kBatch) {
-                const int kn = min(kBatch, c1 - kb);
-                float av[kBatch][4], xk[kBatch];
+        // the wave's terms k0 .. k1-1 in batches of kBatch (a chunk of kChunk
+        // terms is whole batches), two batches in flight: the loads of batch
+        // i + 1 are issued before the multiply-adds of batch i (the terms
+        // past k1 re-read the last column and are not used)
+        const int nb = k1 > k0 ? (k1 - k0 + kBatch - 1) / kBatch : 0;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        float av[2][kBatch][4], xk[2][kBatch];
+        // column k's address is wave-uniform (scalar base), the lane's rows a
+        // 32-bit byte offset: no 64-bit address registers per load
+        auto issue = [&](int bi, float (&a)[kBatch][4], float (&xx)[kBatch]) {
+            const int kb = k0 + bi * kBatch, kn = min(kBatch, k1 - kb);
 #pragma unroll
-                for (int t = 0; t < kBatch; ++t) {
-                    const int k = kb + min(t, kn - 1);
-                    const float *col = A + (size_t)k * rows;
-                    if (vec) {
-                        const dev::f4 v = *reinterpret_cast<const dev::f4 *>(col + rc[0]);
+            for (int t = 0; t < kBatch; ++t) {
+                const int k = kb + min(t, kn - 1);
+                gbyte *col = reinterpret_cast<gbyte *>(reinterpret_cast<uint64_t>(A + (size_t)k * rows));
+                if (vec) {
+                    const dev::f4 v = *reinterpret_cast<gf4 *>(col + 4u * (unsigned)rc[0]);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) av[t][j] = v[j];
-                    } else {
+                    for (int j = 0; j < 4; ++j) a[t][j] = v[j];
+                } else {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) av[t][j] = col[rc[j]];
-                    }
-                    xk[t] = x[k];
+                    for (int j = 0; j < 4; ++j) a[t][j] = *reinterpret_cast<gfloat *>(col + 4u * (unsigned)rc[j]);
                 }
-#pragma unroll
-                for (int t = 0; t < kBatch; ++t)
-                    if (t < kn) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[j] = fmaf(av[t][j], xk[t], acc[j]);
-                    }
+                xx[t] = x[k];
             }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto consume = [&](int bi, const float (&a)[kBatch][4], const float (&xx)[kBatch]) {
+            const int kb = k0 + bi * kBatch, kn = min(kBatch, k1 - kb);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float s, e;
-                dev::two_sum(hi[j], acc[j], s, e);
-                hi[j] = s;
-                lo[j] += e;
+            for (int t = 0; t < kBatch; ++t)
+                if (t < kn) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[j] = fmaf(a[t][j], xx[t], acc[j]);
+                }
+            // end of a chunk: fold its FP32 sum into (hi, lo)
+            if ((kb + kn - k0) % kChunk == 0 || kb + kn == k1) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float s, e;
+                    dev::two_sum(hi[j], acc[j], s, e);
+                    hi[j] = s;
+                    lo[j] += e;
+                    acc[j] = 0.f;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        if (nb > 0) issue(0, av[0], xk[0]);
+        for (int bi = 0; bi < nb; bi += 2) {
+            if (bi + 1 < nb) issue(bi + 1, av[1], xk[1]);
+            consume(bi, av[0], xk[0]);
+            if (bi + 1 < nb) {
+                if (bi + 2 < nb) issue(bi + 2, av[0], xk[0]);
+                consume(bi + 1, av[1], xk[1]);
             }
         }
         // partial of pass row q (0..255) at pH[w][q / 64][q % 64]

@@ -38,6 +38,7 @@
 // FP32 sum, then in FP64 the scale (FP8), forcing and the update of the
 // FP32 (hi, lo) state.
 #include <mutex>
+#include <type_traits>
 #include <string>
 
 #include "k_common.h"
@@ -59,6 +60,7 @@ constexpr int kThreads = 256;
 constexpr int kLd = kRows + 4;     // LDS column stride (floats)
 constexpr long kSpinMax = 1L << 20;     // polls of one bounded wait
 constexpr int kCntStride = 64;     // counters 256 bytes apart
+constexpr int kXcds = 8, kCusPerXcd = 32;
 
 __device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
@@ -81,6 +83,7 @@ struct SplitArgs {
     unsigned *slots;            // per-XCD slot counters (8)
     int *status;                // status[1] <- ROM_E_TIMEOUT
     const SplitGroup *grp;      // grouped FP32 runs: per-group instance data, from grp[g0]
+    const int *smap;            // grouped FP32 runs: slot map (see rank2_split_f32_kernel)
     int g0;
     int source;                 // source signal (dev::Source)
     // bounded waits: poll budget (kSpinMax), and a bias added to every
@@ -509,10 +512,15 @@ constexpr int kLdD = kRows + 2;    // LDS column stride of the FP64 partials (do
 
 typedef const __attribute__((address_space(1))) f4 gf4;
 
-template <int KG, int NCB>
-__device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, unsigned xbytes, int w, int lane,
+// KGT: k-groups per wave (K / 64) when fixed at compile time (fully
+// unrolled; K = 256, 512, 1024), 0 for any K that is a multiple of 64 (KG
+// taken at run time).  Both forms issue the same MFMAs in the same order
+// (FP32 chains of 4 k-groups, the last one shorter when KG % 4 != 0, each
+// folded into FP64 at its end), so they give the same sums.
+template <int KGT, int NCB>
+__device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, int KG, int w, int lane,
                                              double (&acc)[4][NCB][4]) {
-    constexpr int D = KG < 2 ? KG : 2;
+    constexpr int D = 2;     // ring depth in k-groups (K >= 128: KG >= 2)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -523,68 +531,112 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, u
     uint64_t ob = reinterpret_cast<uint64_t>(opw), xb = reinterpret_cast<uint64_t>(xgrp);
     asm volatile("" : "+s"(ob), "+s"(xb));
     const unsigned loff = 16u * (unsigned)lane;
-    gbyte *opb = reinterpret_cast<gbyte *>(ob);
-    (void)xbytes;
-    gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KG * NCB * 1024;   // this wave's k-groups
-    auto load = [&](int kg, f4 (&a)[4], f4 (&b)[NCB]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
-#pragma unroll
-        for (int q = 0; q < NCB; ++q)
-            b[q] = __builtin_bit_cast(f4, ld_shared(xbb + (size_t)(kg * NCB + q) * 1024 + loff));
-    };
     f4 ra[D][4], rbx[D][NCB];
+    // one FP32 chain of NQ k-groups from kg0, folded into the FP64 sums at
+    // its end; `load` refills ring slot kg % D with k-group kg + D
+    auto chain = [&](auto nq, int kg0, auto &&load) {
+        constexpr int NQ = decltype(nq)::value;
+        f4 c[4][NCB];
 #pragma unroll
-    for (int d = 0; d < D; ++d) load(d, ra[d], rbx[d]);
-    __builtin_amdgcn_sched_barrier(0);
-    f4 c[4][NCB];
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int kg = 0; kg < KG; ++kg) {
-        const int slot = kg % D;
-        f4 a[4], b[NCB];
+            for (int cb = 0; cb < NCB; ++cb) c[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = ra[slot][q];
+        for (int q = 0; q < NQ; ++q) {
+            const int kg = kg0 + q;
+            const int slot = q % D;   // kg0 is a multiple of kChainGroups, itself one of D
+            f4 a[4], b[NCB];
 #pragma unroll
-        for (int q = 0; q < NCB; ++q) b[q] = rbx[slot][q];
-        if (kg + D < KG) load(kg + D, ra[slot], rbx[slot]);
-        __builtin_amdgcn_sched_barrier(0);
-        if (kg % kChainGroups == 0) {
+            for (int i = 0; i < 4; ++i) a[i] = ra[slot][i];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int i = 0; i < NCB; ++i) b[i] = rbx[slot][i];
+            load(kg + D, ra[slot], rbx[slot]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) c[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j], c[rb][cb], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
-                    c[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], b[cb][j], c[rb][cb], 0, 0, 0);
-        if (kg % kChainGroups == kChainGroups - 1 || kg == KG - 1) {
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[rb][cb][r] += (double)c[rb][cb][r];
-        }
+                for (int r = 0; r < 4; ++r) acc[rb][cb][r] += (double)c[rb][cb][r];
         __builtin_amdgcn_sched_barrier(0);
+    };
+    using Q4 = std::integral_constant<int, kChainGroups>;
+    if constexpr (KGT > 0) {
+        gbyte *opb = reinterpret_cast<gbyte *>(ob);
+        gbyte *xbb = reinterpret_cast<gbyte *>(xb) + (size_t)w * KGT * NCB * 1024;   // this wave's k-groups
+        auto load = [&](int kg, f4 (&a)[4], f4 (&b)[NCB]) {
+            if (kg >= KGT) return;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<gf4 *>(opb + (size_t)(kg * 4 + q) * 1024 + loff);
+#pragma unroll
+            for (int q = 0; q < NCB; ++q)
+                b[q] = __builtin_bit_cast(f4, ld_shared(xbb + (size_t)(kg * NCB + q) * 1024 + loff));
+        };
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(d, ra[d], rbx[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        static_assert(KGT % kChainGroups == 0, "whole chains");
+#pragma unroll
+        for (int kg0 = 0; kg0 < KGT; kg0 += kChainGroups) chain(Q4{}, kg0, load);
+    } else {
+        // Run-time KG: buffer loads whose k-group offset is a scalar
+        // (soffset), so no per-load address arithmetic; a ring refill past
+        // the wave's last k-group re-reads that k-group (straight-line code:
+        // a branch around the refill would make the compiler wait for every
+        // load in flight).  Exchange loads take the device-scope policy.
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void *>(ob), (short)0, KG * 4 * 1024, kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void *>(xb), (short)0, 4 * KG * NCB * 1024, kRawBufferWord3);
+        const int xw = w * KG * NCB * 1024;
+        auto load = [&](int kg, f4 (&a)[4], f4 (&b)[NCB]) {
+            kg = min(kg, KG - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a[q] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(ro, loff, (kg * 4 + q) * 1024, 0));
+#pragma unroll
+            for (int q = 0; q < NCB; ++q)
+                b[q] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  rx, loff, xw + (kg * NCB + q) * 1024, kDeviceScope));
+        };
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(d, ra[d], rbx[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int full = KG - KG % kChainGroups;
+        for (int kg0 = 0; kg0 < full; kg0 += kChainGroups) chain(Q4{}, kg0, load);
+        switch (KG % kChainGroups) {
+        case 1: chain(std::integral_constant<int, 1>{}, full, load); break;
+        case 2: chain(std::integral_constant<int, 2>{}, full, load); break;
+        case 3: chain(std::integral_constant<int, 3>{}, full, load); break;
+        default: break;
+        }
     }
 }
 
-// GR: grouped run of many instances with the same padded K (64-column
-// groups).  Group g then takes its operators, source, mu, states, sizes,
-// first sample column and dt from a.grp[a.g0 + g] (the probe is off);
-// otherwise they come from the arguments and group g owns columns NC g ..
-// NC g + NC - 1.  The arithmetic of a column is the same either way.
+// GR: grouped run of many instances (64-column groups, each with its own
+// padded K).  A workgroup finds its group and row tile in the launch's slot
+// map (a.smap[32 xcc + slot]: 32 lg + r, or -1 for an idle slot); group lg
+// then takes its operators, source, mu, states, sizes, padded K, exchange
+// offset, first sample column and dt from a.grp[a.g0 + lg] (the probe is
+// off).  Otherwise they come from the arguments, the R = K / 64 row tiles of
+// group g are R consecutive slots of one XCD, and group g owns columns NC g
+// .. NC g + NC - 1.  The arithmetic of a column is the same either way.
 //
 // Finishing threads: TPC = 256 / NC threads per column; thread fs of column
 // fj owns the rows 16 kgl + 4 j + q0 + qq (j = 0..3, qq < NCB) of the row
 // tile, kgl = fs / (4 / NCB), q0 = NCB (fs % (4 / NCB)), as entry e = NCB j +
 // qq of its registers: with the exchange layout above, the entries of one qq
 // are the 4 terms of one lane's fragment, published as one float4.
-template <int KG, bool GR, int NCB>
+template <int KGT, bool GR, int NCB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void rank2_split_f32_kernel(SplitArgs a) {
     static_assert(NCB == 1 || NCB == 2 || NCB == 4, "16, 32 or 64 columns per group");
@@ -601,7 +653,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int kp = a.kp, R = a.R;
+    int kp = a.kp, R = a.R;
 
     if (tid == 0) {
         const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID
@@ -611,10 +663,19 @@ void rank2_split_f32_kernel(SplitArgs a) {
     __syncthreads();
     const int code = __builtin_amdgcn_readfirstlane(sh_slot);
     const int xcc = code & 7, s = code >> 3;
-    const int r = s % R;
-    const int g = (s / R) * 8 + xcc;
-    if (g >= a.G) return;
+    int r, g;
+    if constexpr (GR) {
+        const int e = s < 32 ? a.smap[32 * xcc + s] : -1;
+        if (e < 0) return;                     // idle workgroup (never counted)
+        g = __builtin_amdgcn_readfirstlane(e >> 5);
+        r = __builtin_amdgcn_readfirstlane(e & 31);
+    } else {
+        r = s % R;
+        g = (s / R) * 8 + xcc;
+        if (g >= a.G) return;
+    }
     int kv = a.kv, M = a.M, col0 = g * NC, src = a.source;
+    size_t xoff = (size_t)g * NC * kp;         // the group's exchange block (floats)
     double dt = a.dt;
     const float *bsrc = a.b, *csrc = a.c;
     const double *mup = a.mu;
@@ -625,6 +686,9 @@ void rank2_split_f32_kernel(SplitArgs a) {
         // fields in scalar registers (the operator bases must be scalar)
         const SplitGroup &q = a.grp[a.g0 + g];
         kv = __builtin_amdgcn_readfirstlane(q.kv);
+        kp = __builtin_amdgcn_readfirstlane(q.kp);
+        R = kp / kRows;
+        xoff = (size_t)uniform64((uint64_t)q.xoff);
         M = __builtin_amdgcn_readfirstlane(q.M);
         col0 = __builtin_amdgcn_readfirstlane(q.col0);
         src = __builtin_amdgcn_readfirstlane(q.source);
@@ -666,6 +730,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     __syncthreads();
 
     // this wave's operator panel (k-groups w KG .. of row tile r)
+    const int KG = KGT > 0 ? KGT : kp / 64;
     const f4 *opvw = reinterpret_cast<const f4 *>(opv) + (size_t)(r * kWaves + w) * KG * 4 * 64;
     const f4 *opsw = reinterpret_cast<const f4 *>(ops) + (size_t)(r * kWaves + w) * KG * 4 * 64;
     float *xv = reinterpret_cast<float *>(a.xv), *xs = reinterpret_cast<float *>(a.xs);
@@ -674,7 +739,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     // row row0 + 16 kgl + 4 j + q of column fj is term j of lane 16 q + fj % 16
     // in k-group (row0 + 16 kgl) / 16, column block fj / 16
     auto publish = [&](int f, float *x) {
-        float *xg = x + (size_t)g * NC * kp;
+        float *xg = x + xoff;
         const int kgg = (row0 + 16 * kgl) / 16, cb = fj / 16;
 #pragma unroll
         for (int qq = 0; qq < NCB; ++qq) {
@@ -686,7 +751,7 @@ void rank2_split_f32_kernel(SplitArgs a) {
     auto half_step = [&](int f, const f4 *opw, const float *xother, float *xmine, const double *up,
                          bool forced) -> double {
         double acc[4][NCB][4];
-        products_f32<KG, NCB>(opw, xother + (size_t)g * NC * kp, 4u * NC * kp, w, lane, acc);
+        products_f32<KGT, NCB>(opw, xother + xoff, KG, w, lane, acc);
         double *pw = part + w * NC * kLdD;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
@@ -817,23 +882,34 @@ size_t rank2_split_lds_bytes() {
     return sizeof(float) * ((size_t)2 * 2 * kCols * kLd + (size_t)kWaves * kCols * kLd + 2 * kRows);
 }
 
-// Supported shapes: Kv == Ks == K with K in {256, 512, 1024} (register-
-// resident fragments), and G x R <= 256 workgroups (one per CU, all
-// resident).  Returns the group count, or 0 if the row-split schedule does
-// not apply.
-int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M) {
-    if (kv != ks || kvp != ksp) return 0;
-    if (kvp != 256 && kvp != 512 && kvp != 1024) return 0;
-    const int R = kvp / kRows;
+bool rank2_split_k_ok(int kvp, bool f32) {
+    if (f32) return kvp % kRows == 0 && kvp >= 2 * kRows && kvp <= kMaxSplitK;
+    return kvp == 256 || kvp == 512 || kvp == 1024;
+}
+
+// Groups of R = kvp / 64 workgroups one launch holds: a group's workgroups
+// share an XCD, so each of the 8 XCDs (32 CUs) holds floor(32 / R) groups.
+int rank2_split_groups_per_launch(int kvp) { return kXcds * (kCusPerXcd / (kvp / kRows)); }
+
+// Supported shapes: Kv == Ks == K with K a multiple of 64 in [128, 2048]
+// for FP32 operators, K in {256, 512, 1024} for BF16 / FP8 ones (register-
+// resident fragments), and all 64-column groups in one launch (one
+// workgroup per CU, all resident).  Returns the group count, or 0 if the
+// row-split schedule does not apply.
+int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M, bool f32) {
+    if (kv != ks || kvp != ksp || !rank2_split_k_ok(kvp, f32)) return 0;
     const int G = (M + kCols - 1) / kCols;
-    if ((int64_t)G * R > 256) return 0;
+    if (G > rank2_split_groups_per_launch(kvp)) return 0;
     return G;
 }
 
 size_t rank2_split_workspace_bytes(int kvp, int G) {
-    const size_t R = kvp / kRows;
-    return sizeof(unsigned short) * 2 * (size_t)G * kCols * 2 * kvp   // xv, xs
-           + sizeof(double) * (size_t)G * R * kCols                    // yp
+    return rank2_split_ws_bytes((size_t)G * kCols * kvp, (size_t)G * (kvp / kRows) * kCols);
+}
+
+size_t rank2_split_ws_bytes(size_t xfloats, size_t ypd) {
+    return sizeof(float) * 2 * xfloats                                 // xv, xs
+           + sizeof(double) * ypd                                      // yp
            + sizeof(unsigned) * (256 * kCntStride + 64);               // counters, slots
 }
 
@@ -864,16 +940,17 @@ hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *d
 
 namespace {
 
-// Carve a workspace of rank2_split_workspace_bytes(kp, G) into the exchange
-// buffers, probe partials, group counters and XCD slot counters, and
-// enqueue the clearing of the counters and of the abort flag status[2].
-hipError_t split_workspace(SplitArgs &a, void *ws, int G, hipStream_t st) {
+// Carve a workspace of rank2_split_ws_bytes(xfloats, ypd) into the
+// exchange buffers (xfloats floats per field), probe partials (ypd
+// doubles), group counters and XCD slot counters, and enqueue the clearing
+// of the counters and of the abort flag status[2].
+hipError_t split_workspace(SplitArgs &a, void *ws, size_t xfloats, size_t ypd, hipStream_t st) {
     unsigned short *x = static_cast<unsigned short *>(ws);
-    const size_t xsz = (size_t)G * kCols * 2 * a.kp;
+    const size_t xsz = 2 * xfloats;    // in BF16 elements
     a.xv = x;
     a.xs = x + xsz;
     a.yp = reinterpret_cast<double *>(x + 2 * xsz);
-    a.cnt = reinterpret_cast<unsigned *>(a.yp + (size_t)G * a.R * kCols);
+    a.cnt = reinterpret_cast<unsigned *>(a.yp + ypd);
     a.slots = a.cnt + 256 * kCntStride;
     a.spin_max = g_forced_timeout ? 256 : kSpinMax;
     a.wait_bias = g_forced_timeout ? 1u : 0u;
@@ -884,22 +961,27 @@ hipError_t split_workspace(SplitArgs &a, void *ws, int G, hipStream_t st) {
     return hipGetLastError();
 }
 
-// FP32 kernels: single runs by (K = 256, 512, 1024) x (group width 16, 32,
-// 64 columns), then the grouped (64-column) kernels by K.
-const void *const kSplitF32Kernels[12] = {
+// FP32 kernels: single runs with 16- or 32-column groups at K = 256, 512,
+// 1024 take the compile-time k-group count; every other single run
+// (64-column groups, other K) and the grouped runs take the run-time one,
+// which measured faster with 64-column groups (38.7 against 40.3 us per
+// step at K = M = 1024) and slower with narrow ones (14.3 against 12.8 at
+// K = 1024, M = 256).  Table: (K = 256, 512, 1024) x (16, 32 columns), then
+// the run-time kernels for 16, 32, 64 columns, then the grouped one.
+const void *const kSplitF32Kernels[10] = {
     (const void *)rank2_split_f32_kernel<4, false, 1>,  (const void *)rank2_split_f32_kernel<4, false, 2>,
-    (const void *)rank2_split_f32_kernel<4, false, 4>,  (const void *)rank2_split_f32_kernel<8, false, 1>,
-    (const void *)rank2_split_f32_kernel<8, false, 2>,  (const void *)rank2_split_f32_kernel<8, false, 4>,
+    (const void *)rank2_split_f32_kernel<8, false, 1>,  (const void *)rank2_split_f32_kernel<8, false, 2>,
     (const void *)rank2_split_f32_kernel<16, false, 1>, (const void *)rank2_split_f32_kernel<16, false, 2>,
-    (const void *)rank2_split_f32_kernel<16, false, 4>, (const void *)rank2_split_f32_kernel<4, true, 4>,
-    (const void *)rank2_split_f32_kernel<8, true, 4>,   (const void *)rank2_split_f32_kernel<16, true, 4>};
+    (const void *)rank2_split_f32_kernel<0, false, 1>,  (const void *)rank2_split_f32_kernel<0, false, 2>,
+    (const void *)rank2_split_f32_kernel<0, false, 4>,  (const void *)rank2_split_f32_kernel<0, true, 4>};
 
 // wi: group width 16 << wi columns (single runs; grouped runs take 64).
 template <bool GR>
 hipError_t launch_split_f32(int kp, int wi, void **args, hipStream_t st) {
+    if (wi < 0 || wi > 2) return hipErrorInvalidValue;
     const int ki = kp == 256 ? 0 : (kp == 512 ? 1 : (kp == 1024 ? 2 : -1));
-    if (ki < 0 || wi < 0 || wi > 2) return hipErrorInvalidValue;
-    const void *f = GR ? kSplitF32Kernels[9 + ki] : kSplitF32Kernels[3 * ki + wi];
+    const void *f = GR ? kSplitF32Kernels[9] : (ki >= 0 && wi < 2 ? kSplitF32Kernels[2 * ki + wi]
+                                                                    : kSplitF32Kernels[6 + wi]);
     return hipLaunchCooperativeKernel(f, dim3(256), dim3(kThreads), args, rank2_split_f32_lds_bytes(), st);
 }
 
@@ -914,11 +996,12 @@ const void *const kSplitLpKernels[18] = {ROM_LP_WIDTHS(2, false), ROM_LP_WIDTHS(
 #undef ROM_LP_WIDTHS
 
 // Width index (group width 16 << wi columns) of the narrowest group whose
-// ceil(M / width) x R workgroups fit in 256; the caller's G x R <= 256 for
-// 64-column groups guarantees that one fits.
-int split_width_index(int M, int R) {
+// ceil(M / width) groups fit in one launch; the caller's check that the
+// 64-column groups fit guarantees that one does.
+int split_width_index(int M, int kvp) {
+    const int cap = rank2_split_groups_per_launch(kvp);
     int wi = 0;
-    while (wi < 2 && (int64_t)((M + (16 << wi) - 1) / (16 << wi)) * R > 256) ++wi;
+    while (wi < 2 && (M + (16 << wi) - 1) / (16 << wi) > cap) ++wi;
     return wi;
 }
 
@@ -959,27 +1042,23 @@ hipError_t rank2_split_static_scratch(int device, void **ptr) {
     return hipSuccess;
 }
 
-int rank2_split_groups_per_launch(int kvp) { return 256 / (kvp / kRows); }
-
-hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
-                                    int64_t n0, int64_t nsteps, hipStream_t st) {
+hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, const int *smap_dev, size_t xfloats,
+                                    void *ws, int *status, int64_t n0, int64_t nsteps, hipStream_t st) {
     if (G <= 0 || nsteps <= 0) return hipSuccess;
-    if ((kvp != 256 && kvp != 512 && kvp != 1024) || G > rank2_split_groups_per_launch(kvp))
-        return hipErrorInvalidValue;
+    if (G > kXcds * kCusPerXcd / 2) return hipErrorInvalidValue;
     SplitArgs a{};
     a.grp = grp_dev;
+    a.smap = smap_dev;
     a.g0 = g0;
-    a.kp = kvp;
     a.G = G;
-    a.R = kvp / kRows;
     a.n0 = n0;
     a.nsteps = nsteps;
     a.scale = 1.0f;
     a.status = status;
-    hipError_t e = split_workspace(a, ws, G, st);
+    hipError_t e = split_workspace(a, ws, xfloats, 0, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
-    return launch_split_f32<true>(kvp, 2, args, st);
+    return launch_split_f32<true>(0, 2, args, st);
 }
 
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
@@ -1006,14 +1085,16 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     a.scale = scale;
     a.status = status;
     a.grp = nullptr;
+    a.smap = nullptr;
     a.g0 = 0;
-    hipError_t e = split_workspace(a, ws, G, st);
+    if (!rank2_split_k_ok(a.kp, f32) || G > rank2_split_groups_per_launch(a.kp)) return hipErrorInvalidValue;
+    hipError_t e = split_workspace(a, ws, (size_t)G * kCols * a.kp, (size_t)G * a.R * kCols, st);
     if (e != hipSuccess) return e;
     void *args[] = {&a};
     // the narrowest column group (16, 32 or 64 columns) whose workgroups all
     // fit; the workspace, carved for G 64-column groups, covers it
     // (ceil(M / nc) nc <= ceil(M / 64) 64)
-    const int wi = split_width_index(a.M, a.R);
+    const int wi = split_width_index(a.M, a.kp);
     a.G = (a.M + (16 << wi) - 1) / (16 << wi);
     if (f32) return launch_split_f32<false>(a.kp, wi, args, st);
     const size_t lds = rank2_split_lds_bytes();

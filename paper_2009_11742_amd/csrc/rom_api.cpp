@@ -141,10 +141,11 @@ bool g_configured = false;
 int ctx_source(const rom_ctx *c) { return (c->flags & ROM_SOURCE_GAUSS1) ? 1 : 0; }
 
 // Row-split groups for a rank-2 run of M samples with FP32 states, or 0 if
-// the row-split kernels do not apply (Kv == Ks in {256, 512, 1024}, at most
-// 256 workgroups, a 256-CU gfx950).
+// the row-split kernels do not apply (Kv == Ks, padded K a multiple of 64 in
+// [128, 2048] with FP32 operators, in {256, 512, 1024} with BF16 / FP8 ones;
+// all groups in one launch; a 256-CU gfx950).
 int split_candidate(rom_ctx *ctx, int32_t M) {
-    const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M);
+    const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M, ctx->op_type == ROM_F32);
     if (G == 0) return 0;
     if (ctx->sp_ok < 0) ctx->sp_ok = rom::rank2_split_device_ok() ? 1 : 0;
     return ctx->sp_ok == 1 ? G : 0;
@@ -919,8 +920,9 @@ rom_status rom_run_rank2_noalloc(rom_ctx *ctx, int32_t M, const double *mu, int6
         return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: FP32 states with F32, BF16 or F8E4M3 operators only");
     const int G = split_candidate(ctx, M);
     if (G == 0 || !ctx->avs_sp)
-        return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: the row-split schedule does not apply (Kv == Ks in "
-                                       "{256, 512, 1024}, ceil(M/64) * K/64 <= 256, a 256-CU gfx950)");
+        return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: the row-split schedule does not apply (Kv == Ks, "
+                                       "padded K a multiple of 64 in [128, 2048] (F32) or in {256, 512, 1024} "
+                                       "(BF16, FP8), ceil(M/64) <= 8 floor(32 / (K/64)), a 256-CU gfx950)");
     const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
     if (need > rom::rank2_split_static_bytes())
         return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: needs " + std::to_string(need) +
@@ -1308,82 +1310,145 @@ rom_status build_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const d
     return ROM_OK;
 }
 
-// Row-split form of a grouped request, if it applies: every instance
-// square (Kv == Ks) with the same padded K in {256, 512, 1024}, FP32
-// operators, a device that runs the row-split kernels, and no instance
-// pinned to column blocks.  One descriptor per 64-sample group, instance
-// by instance.  Packs the instances' row-split operators on `st`.
-rom_status build_split_groups(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
-                              void *const *V, void *const *S, hipStream_t st, std::vector<rom::SplitGroup> &groups,
-                              std::vector<int> &owner, int &kvp, bool &forced) {
-    groups.clear();
-    owner.clear();
-    kvp = ctx[0]->kvp;
-    forced = true;
-    for (int i = 0; i < G; ++i) {
-        rom_ctx *c = ctx[i];
-        if (c->kv != c->ks || c->kvp != kvp || (c->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_COLUMNS8)))
-            return ROM_OK;
-        if (!(c->flags & ROM_SCHED_ROWSPLIT)) forced = false;
-        if (split_candidate(c, 64) == 0) return ROM_OK;
-    }
-    for (int i = 0; i < G; ++i) {
-        rom_status rs = prepare_split_pack(ctx[i], st);
-        if (rs != ROM_OK) return rs;
-        for (int c0 = 0; c0 < M[i]; c0 += 64) {
-            rom::SplitGroup q{};
-            q.opv = ctx[i]->avs_sp; q.ops = ctx[i]->asv_sp;
-            q.b = static_cast<const float *>(ctx[i]->b);
-            q.mu = mu[i];
-            q.V = static_cast<float *>(V[i]); q.S = static_cast<float *>(S[i]);
-            q.dt = ctx[i]->dt;
-            q.source = ctx_source(ctx[i]);
-            q.kv = ctx[i]->kv; q.M = M[i]; q.col0 = c0;
-            groups.push_back(q);
-            owner.push_back(i);
-        }
-    }
-    return ROM_OK;
+using rom::SplitPlan;
+using rom::SplitDev;
+
+// Whether instance i can run in a grouped row-split launch: square FP32,
+// padded K the row-split kernels take, a device that runs them, and not
+// pinned to column blocks.
+bool split_eligible(rom_ctx *c) {
+    if (c->kv != c->ks || (c->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_COLUMNS8))) return false;
+    return split_candidate(c, 64) > 0;
 }
 
-// Row-split launches of a grouped run: groups in launches of at most
-// rank2_split_groups_per_launch(kvp), one after another on `st`.
-hipError_t launch_split_groups(const rom::SplitGroup *dev, int ngroups, int kvp, void *ws, int *status, int64_t n0,
-                               int64_t nsteps, hipStream_t st) {
-    const int per = rom::rank2_split_groups_per_launch(kvp);
-    for (int g0 = 0; g0 < ngroups; g0 += per) {
-        hipError_t e = rom::launch_grouped_split_f32(dev, g0, std::min(per, ngroups - g0), kvp, ws, status, n0,
-                                                     nsteps, st);
+// Pack the groups of the instances with use[i] into launches.  Groups go in
+// order of decreasing K (then instance, then column), each into the first
+// launch with an XCD that has K / 64 free slots (of 32), on the XCD of that
+// launch with the most free slots; a launch's step takes as long as its
+// largest-K group's, so the smaller groups fill what the larger ones left.
+void plan_split(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu, void *const *V,
+                void *const *S, const std::vector<char> &use, SplitPlan &sp) {
+    struct Cand { int inst, col0, kp; };
+    std::vector<Cand> cand;
+    for (int i = 0; i < G; ++i)
+        if (use[i])
+            for (int c0 = 0; c0 < M[i]; c0 += 64) cand.push_back({i, c0, ctx[i]->kvp});
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) { return x.kp > y.kp; });
+    struct Launch { int freec[8]; std::vector<int> mem; std::vector<int> xcd; };
+    std::vector<Launch> ls;
+    for (int q = 0; q < (int)cand.size(); ++q) {
+        const int R = cand[q].kp / 64;
+        int li = -1, xb = -1;
+        for (int l = 0; l < (int)ls.size() && li < 0; ++l) {
+            for (int x = 0; x < 8; ++x)
+                if (ls[l].freec[x] >= R && (xb < 0 || ls[l].freec[x] > ls[l].freec[xb])) xb = x;
+            if (xb >= 0) li = l;
+        }
+        if (li < 0) {
+            Launch L;
+            for (int x = 0; x < 8; ++x) L.freec[x] = 32;
+            ls.push_back(L);
+            li = (int)ls.size() - 1;
+            xb = 0;
+        }
+        ls[li].freec[xb] -= R;
+        ls[li].mem.push_back(q);
+        ls[li].xcd.push_back(xb);
+    }
+    sp = SplitPlan();
+    sp.kmin = cand.empty() ? 0 : cand.back().kp;
+    for (const Launch &L : ls) {
+        const int g0 = (int)sp.groups.size();
+        int used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        std::vector<int> sm(256, -1);
+        int64_t xoff = 0;
+        for (size_t j = 0; j < L.mem.size(); ++j) {
+            const Cand &c = cand[L.mem[j]];
+            const int i = c.inst, x = L.xcd[j], R = c.kp / 64, lg = (int)j;
+            for (int r = 0; r < R; ++r) sm[32 * x + used[x] + r] = 32 * lg + r;
+            used[x] += R;
+            rom::SplitGroup g{};
+            g.opv = ctx[i]->avs_sp; g.ops = ctx[i]->asv_sp;
+            g.b = static_cast<const float *>(ctx[i]->b);
+            g.mu = mu[i];
+            g.V = static_cast<float *>(V[i]); g.S = static_cast<float *>(S[i]);
+            g.dt = ctx[i]->dt;
+            g.source = ctx_source(ctx[i]);
+            g.kv = ctx[i]->kv; g.kp = c.kp; g.M = M[i]; g.col0 = c.col0;
+            g.xoff = xoff;
+            xoff += 64 * (int64_t)c.kp;
+            sp.groups.push_back(g);
+            sp.owner.push_back(i);
+        }
+        sp.g0.push_back(g0);
+        sp.ng.push_back((int)L.mem.size());
+        sp.xfloats.push_back((size_t)xoff);
+        sp.smap.insert(sp.smap.end(), sm.begin(), sm.end());
+        sp.ws_bytes = std::max(sp.ws_bytes, rom::rank2_split_ws_bytes((size_t)xoff, 0));
+    }
+}
+
+void free_split_dev(SplitDev &d) {
+    hfree(d.groups); hfree(d.smap); hfree(d.ws); hfree(d.status);
+    d = SplitDev();
+}
+
+hipError_t upload_split(const SplitPlan &sp, SplitDev &d) {
+    hipError_t e = hipMalloc(&d.groups, sizeof(rom::SplitGroup) * sp.groups.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&d.smap), sizeof(int) * sp.smap.size());
+    if (e == hipSuccess) e = hipMalloc(&d.ws, sp.ws_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&d.status), sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMemset(d.status, 0, sizeof(int) * 4);
+    if (e == hipSuccess)
+        e = hipMemcpy(d.groups, sp.groups.data(), sizeof(rom::SplitGroup) * sp.groups.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.smap, sp.smap.data(), sizeof(int) * sp.smap.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+// Row-split launches of a grouped run, one after another on `st`.
+hipError_t launch_split_plan(const SplitPlan &sp, const SplitDev &d, int64_t n0, int64_t nsteps, hipStream_t st) {
+    for (size_t l = 0; l < sp.g0.size(); ++l) {
+        hipError_t e = rom::launch_grouped_split_f32(static_cast<const rom::SplitGroup *>(d.groups), sp.g0[l], sp.ng[l],
+                                                     d.smap + 256 * l, sp.xfloats[l], d.ws, d.status, n0, nsteps, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Which plan a grouped shape runs: timed once per shape (padded K and the
-// instances' sample counts) and remembered for the process.
+// Which plan a grouped shape runs: timed once per shape (the instances'
+// padded K and sample counts) and remembered for the process, as the
+// smallest padded K on row-split (0: column blocks only).
 std::mutex g_gsched_mu;
 std::map<std::vector<int>, int> g_gsched;
 
-// Time both plans of a grouped run (per step: best of two runs of
-// kTuneSteps steps after a 2-step warm-up) on scratch states; the caller's
-// mu arrays are read.  A row-split run whose barrier timed out is reported
-// as not applicable (t_split < 0) and its status cleared.
-rom_status time_group_plans(const std::vector<rom::Rank2Args> &inst, const std::vector<int2> &items, size_t lds,
-                            const std::vector<rom::SplitGroup> &groups, const std::vector<int> &owner, int kvp,
-                            void *ws, int *status, hipStream_t st, float &t_col, float &t_split) {
+// Column-block items of the instances with use[i] == 0.
+std::vector<int2> rest_items(const std::vector<int2> &items, const std::vector<char> &use) {
+    std::vector<int2> r;
+    for (const int2 &it : items)
+        if (!use[it.x]) r.push_back(it);
+    return r;
+}
+
+// Time a grouped plan (per step: best of two runs of kTuneSteps steps after
+// a 2-step warm-up) on scratch states: the row-split launches of sp (none
+// if it is empty), then column blocks over `items`.  The caller's mu arrays
+// are read.  A plan whose row-split barrier timed out is reported as not
+// applicable (us < 0).
+rom_status time_group_plan(const std::vector<rom::Rank2Args> &inst, const std::vector<int2> &items, size_t lds,
+                           const SplitPlan &sp, hipStream_t st, float &us) {
     const int G = (int)inst.size();
     std::vector<size_t> off(G + 1, 0);
     for (int i = 0; i < G; ++i) off[i + 1] = off[i] + (size_t)(inst[i].kv + inst[i].ks) * inst[i].M;
     std::vector<rom::Rank2Args> ic(inst);
-    std::vector<rom::SplitGroup> gc(groups);
+    SplitPlan sc(sp);
+    SplitDev sd;
     float *scr = nullptr;
     void *dev = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     rom_status rs = ROM_OK;
-    const size_t ib = sizeof(rom::Rank2Args) * ic.size(), tb = sizeof(int2) * items.size();
-    const size_t gb = sizeof(rom::SplitGroup) * gc.size();
+    const size_t ib = sizeof(rom::Rank2Args) * ic.size(), tb = sizeof(int2) * std::max<size_t>(1, items.size());
     hipError_t e = hipMalloc(&scr, sizeof(float) * off[G]);
-    if (e == hipSuccess) e = hipMalloc(&dev, ib + tb + gb);
+    if (e == hipSuccess) e = hipMalloc(&dev, ib + tb);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) {
@@ -1391,53 +1456,47 @@ rom_status time_group_plans(const std::vector<rom::Rank2Args> &inst, const std::
             ic[i].V = scr + off[i];
             ic[i].S = scr + off[i] + (size_t)inst[i].kv * inst[i].M;
         }
-        for (size_t q = 0; q < gc.size(); ++q) {
-            gc[q].V = static_cast<float *>(ic[owner[q]].V);
-            gc[q].S = static_cast<float *>(ic[owner[q]].S);
+        for (size_t q = 0; q < sc.groups.size(); ++q) {
+            sc.groups[q].V = static_cast<float *>(ic[sc.owner[q]].V);
+            sc.groups[q].S = static_cast<float *>(ic[sc.owner[q]].S);
         }
+        if (!sc.groups.empty()) e = upload_split(sc, sd);
         char *d = static_cast<char *>(dev);
-        e = hipMemsetAsync(scr, 0, sizeof(float) * off[G], st);
+        if (e == hipSuccess) e = hipMemsetAsync(scr, 0, sizeof(float) * off[G], st);
         if (e == hipSuccess) e = hipMemcpyAsync(d, ic.data(), ib, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(d + ib, items.data(), tb, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(d + ib + tb, gc.data(), gb, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !items.empty())
+            e = hipMemcpyAsync(d + ib, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     if (e != hipSuccess) rs = hip_fail(e, "grouped plan tuning: setup");
     const char *d = static_cast<const char *>(dev);
-    float best[2] = {1e30f, 1e30f};
-    for (int plan = 0; plan < 2 && rs == ROM_OK; ++plan) {
-        for (int rep = 0; rep < 3 && rs == ROM_OK; ++rep) {   // rep 0: warm-up
-            const int64_t n = rep == 0 ? 2 : kTuneSteps;
-            e = rep > 0 ? hipEventRecord(e0, st) : hipSuccess;
-            if (e == hipSuccess)
-                e = plan == 0 ? rom::launch_grouped_f32_mfma(reinterpret_cast<const rom::Rank2Args *>(d),
-                                                             reinterpret_cast<const int2 *>(d + ib), (int)items.size(),
-                                                             lds, 0, n, st)
-                              : launch_split_groups(reinterpret_cast<const rom::SplitGroup *>(d + ib + tb),
-                                                    (int)gc.size(), kvp, ws, status, 0, n, st);
-            if (e == hipSuccess && rep > 0) e = hipEventRecord(e1, st);
-            if (e == hipSuccess && rep > 0) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess && rep > 0) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { rs = hip_fail(e, "grouped plan tuning"); break; }
-            if (rep > 0) best[plan] = std::min(best[plan], ms * 1e3f / (float)n);
-        }
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && rs == ROM_OK; ++rep) {   // rep 0: warm-up
+        const int64_t n = rep == 0 ? 2 : kTuneSteps;
+        e = rep > 0 ? hipEventRecord(e0, st) : hipSuccess;
+        if (e == hipSuccess && !sc.groups.empty()) e = launch_split_plan(sc, sd, 0, n, st);
+        if (e == hipSuccess && !items.empty())
+            e = rom::launch_grouped_f32_mfma(reinterpret_cast<const rom::Rank2Args *>(d),
+                                             reinterpret_cast<const int2 *>(d + ib), (int)items.size(), lds, 0, n, st);
+        if (e == hipSuccess && rep > 0) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && rep > 0) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess && rep > 0) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { rs = hip_fail(e, "grouped plan tuning"); break; }
+        if (rep > 0) best = std::min(best, ms * 1e3f / (float)n);
     }
     if (rs == ROM_OK) e = hipStreamSynchronize(st);
     if (rs == ROM_OK && e != hipSuccess) rs = hip_fail(e, "grouped plan tuning");
-    if (rs == ROM_OK) {
+    if (rs == ROM_OK && sd.status) {
         int w[2] = {0, 0};
-        e = hipMemcpy(w, status + 1, sizeof(w), hipMemcpyDeviceToHost);
-        if (e == hipSuccess && (w[0] != 0 || w[1] != 0)) {
-            best[1] = -1.f;
-            e = hipMemset(status + 1, 0, sizeof(w));
-        }
+        e = hipMemcpy(w, sd.status + 1, sizeof(w), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && (w[0] != 0 || w[1] != 0)) best = -1.f;
         if (e != hipSuccess) rs = hip_fail(e, "grouped plan tuning: status");
     }
-    t_col = best[0];
-    t_split = best[1];
+    us = best;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    free_split_dev(sd);
     hfree(scr);
     hfree(dev);
     return rs;
@@ -1446,15 +1505,18 @@ rom_status time_group_plans(const std::vector<rom::Rank2Args> &inst, const std::
 // Free a plan's device memory (its work must have completed).
 void free_group(rom_group *g) {
     hfree(g->dev);
-    hfree(g->sp_dev);
-    hfree(g->sp_ws);
-    hfree(g->sp_status);
+    hfree(g->rest);
+    free_split_dev(g->sp);
     delete g;
 }
 
-// Build a plan: the column-block descriptor table always (graph capture runs
-// it), the row-split table and its workspace when that plan applies and is
-// forced or timed faster.  Tuning runs on `st` and synchronises it.
+// Build a plan: the column-block descriptor table of every instance always
+// (graph capture runs it); when the row-split kernels apply to some
+// instances and are forced or timed faster, the row-split launches for the
+// instances from a padded K threshold up and the column-block items of the
+// rest.  Candidate thresholds: each padded K of the eligible instances (all
+// of them on row-split when every instance asks for that schedule).  Tuning
+// runs on `st` and synchronises it.
 rom_status make_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu, void *const *V,
                       void *const *S, hipStream_t st, const char *who, rom_group **out) {
     std::string w(who);
@@ -1463,15 +1525,23 @@ rom_status make_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const do
     size_t lds = 0;
     rom_status r = build_group(ctx, G, M, mu, V, S, st, inst, items, lds);
     if (r != ROM_OK) return r;
-    std::vector<rom::SplitGroup> groups;
-    std::vector<int> owner;
-    int kvp = 0;
-    bool forced = false;
-    r = build_split_groups(ctx, G, M, mu, V, S, st, groups, owner, kvp, forced);
-    if (r != ROM_OK) return r;
-    if (!groups.empty() && !stream_capturing(st)) {
+    std::vector<char> elig(G, 0);
+    bool forced = true, any = false;
+    if (!stream_capturing(st)) {
+        for (int i = 0; i < G; ++i) {
+            elig[i] = split_eligible(ctx[i]) ? 1 : 0;
+            any = any || elig[i];
+            if (!elig[i] || !(ctx[i]->flags & ROM_SCHED_ROWSPLIT)) forced = false;
+        }
+    }
+    if (any) {
+        for (int i = 0; i < G; ++i)
+            if (elig[i]) {
+                r = prepare_split_pack(ctx[i], st);
+                if (r != ROM_OK) return r;
+            }
         hipError_t es = hipStreamSynchronize(st);   // the packs are complete before any plan runs
-        if (es != hipSuccess) return hip_fail(es, (std::string(who) + ": synchronize").c_str());
+        if (es != hipSuccess) return hip_fail(es, (w + ": synchronize").c_str());
     }
     rom_group *g = new (std::nothrow) rom_group();
     if (!g) return fail(ROM_E_NOMEM, w + ": host allocation failed");
@@ -1491,58 +1561,78 @@ rom_status make_group(rom_ctx *const *ctx, int32_t G, const int32_t *M, const do
     g->lds_bytes = lds;
     g->inst = static_cast<const rom::Rank2Args *>(g->dev);
     g->items = reinterpret_cast<const int2 *>(static_cast<char *>(g->dev) + ib);
-    if (!groups.empty() && !stream_capturing(st)) {
-        const int per = rom::rank2_split_groups_per_launch(kvp);
-        const size_t wsb = rom::rank2_split_workspace_bytes(kvp, std::min(per, (int)groups.size()));
-        e = hipMalloc(&g->sp_ws, wsb);
-        if (e == hipSuccess) e = hipMalloc(&g->sp_status, sizeof(int) * 4);
-        if (e == hipSuccess) e = hipMalloc(&g->sp_dev, sizeof(rom::SplitGroup) * groups.size());
-        if (e != hipSuccess) { free_group(g); return fail(ROM_E_NOMEM, w + ": device allocation failed"); }
-        e = hipMemset(g->sp_status, 0, sizeof(int) * 4);
-        if (e == hipSuccess)
-            e = hipMemcpy(g->sp_dev, groups.data(), sizeof(rom::SplitGroup) * groups.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) { free_group(g); return hip_fail(e, (w + ": upload").c_str()); }
-        g->kvp = kvp;
-        g->ngroups = (int)groups.size();
-        bool use = forced;
+    if (any) {
+        std::vector<int> ks;
+        for (int i = 0; i < G; ++i)
+            if (elig[i]) ks.push_back(ctx[i]->kvp);
+        std::sort(ks.begin(), ks.end());
+        ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+        auto use_from = [&](int t) {
+            std::vector<char> u(G, 0);
+            for (int i = 0; i < G; ++i) u[i] = (t > 0 && elig[i] && ctx[i]->kvp >= t) ? 1 : 0;
+            return u;
+        };
+        int t = forced ? ks.front() : -1;
         if (!forced) {
-            std::vector<int> key{kvp};
-            for (int i = 0; i < G; ++i) key.push_back(M[i]);
-            int dec = -1;
+            std::vector<int> key;
+            for (int i = 0; i < G; ++i) { key.push_back(elig[i] ? ctx[i]->kvp : -ctx[i]->kvp); key.push_back(M[i]); }
             {
                 std::lock_guard<std::mutex> lk(g_gsched_mu);
                 auto it = g_gsched.find(key);
-                if (it != g_gsched.end()) dec = it->second;
+                if (it != g_gsched.end()) t = it->second;
             }
-            if (dec < 0) {
-                float tc = -1.f, ts = -1.f;
-                r = time_group_plans(inst, items, lds, groups, owner, kvp, g->sp_ws, g->sp_status, st, tc, ts);
+            if (t < 0) {
+                float tc = -1.f;
+                SplitPlan none;
+                r = time_group_plan(inst, items, lds, none, st, tc);
                 if (r != ROM_OK) { free_group(g); return r; }
+                float tb = -1.f;
+                int best = 0;
+                for (int k : ks) {
+                    SplitPlan sp;
+                    const std::vector<char> u = use_from(k);
+                    plan_split(ctx, G, M, mu, V, S, u, sp);
+                    float ts = -1.f;
+                    r = time_group_plan(inst, rest_items(items, u), lds, sp, st, ts);
+                    if (r != ROM_OK) { free_group(g); return r; }
+                    if (ts >= 0.f && (tb < 0.f || ts < tb)) { tb = ts; best = k; }
+                }
                 g->us[0] = tc;
-                g->us[1] = ts;
-                dec = (ts >= 0.f && ts < tc) ? 1 : 0;
+                g->us[1] = tb;
+                t = (tb >= 0.f && tb < tc) ? best : 0;
                 std::lock_guard<std::mutex> lk(g_gsched_mu);
-                g_gsched[key] = dec;
+                g_gsched[key] = t;
             }
-            use = dec == 1;
         }
-        if (!use) {
-            hfree(g->sp_dev); hfree(g->sp_ws); hfree(g->sp_status);
-            g->sp_dev = g->sp_ws = nullptr;
-            g->sp_status = nullptr;
-            g->ngroups = 0;
+        if (t > 0) {
+            const std::vector<char> u = use_from(t);
+            plan_split(ctx, G, M, mu, V, S, u, g->plan);
+            e = upload_split(g->plan, g->sp);
+            const std::vector<int2> rest = rest_items(items, u);
+            if (e == hipSuccess && !rest.empty()) {
+                e = hipMalloc(&g->rest, sizeof(int2) * rest.size());
+                if (e == hipSuccess)
+                    e = hipMemcpy(g->rest, rest.data(), sizeof(int2) * rest.size(), hipMemcpyHostToDevice);
+            }
+            if (e != hipSuccess) { free_group(g); return hip_fail(e, (w + ": row-split plan upload").c_str()); }
+            g->nrest = (int)rest.size();
+            g->ngroups = (int)g->plan.groups.size();
         }
     }
     *out = g;
     return ROM_OK;
 }
 
-// Enqueue a plan's run: row-split launches when the plan has them and the
-// stream is not being captured, else the column-block launch.
+// Enqueue a plan's run: with a row-split part and a stream not being
+// captured, its launches and then column blocks over the other instances;
+// else column blocks over all instances.
 hipError_t run_group(rom_group *g, int64_t n0, int64_t nsteps, hipStream_t st) {
-    if (g->ngroups > 0 && !stream_capturing(st))
-        return launch_split_groups(static_cast<const rom::SplitGroup *>(g->sp_dev), g->ngroups, g->kvp, g->sp_ws,
-                                   g->sp_status, n0, nsteps, st);
+    if (g->ngroups > 0 && !stream_capturing(st)) {
+        hipError_t e = launch_split_plan(g->plan, g->sp, n0, nsteps, st);
+        if (e != hipSuccess || g->nrest == 0) return e;
+        return rom::launch_grouped_f32_mfma(g->inst, static_cast<const int2 *>(g->rest), g->nrest, g->lds_bytes, n0,
+                                            nsteps, st);
+    }
     return rom::launch_grouped_f32_mfma(g->inst, g->items, g->nitems, g->lds_bytes, n0, nsteps, st);
 }
 
@@ -1570,6 +1660,11 @@ int32_t rom_group_schedule(const rom_group *g) {
     return g->ngroups > 0 ? ROM_SCHEDULE_ROWSPLIT : ROM_SCHEDULE_COLUMNS4;
 }
 
+int32_t rom_group_split_k(const rom_group *g) {
+    if (!g) return -1;
+    return g->ngroups > 0 ? g->plan.kmin : 0;
+}
+
 rom_status rom_group_times(const rom_group *g, double us[2]) {
     if (!g || !us) return fail(ROM_E_ARG, "rom_group_times: NULL argument");
     us[0] = g->us[0];
@@ -1581,12 +1676,12 @@ rom_status rom_group_check(rom_group *g, void *stream) {
     if (!g) return fail(ROM_E_ARG, "rom_group_check: NULL plan");
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "rom_group_check: synchronize");
-    if (!g->sp_status) return ROM_OK;
+    if (!g->sp.status) return ROM_OK;
     int w[2] = {0, 0};
-    e = hipMemcpy(w, g->sp_status + 1, sizeof(w), hipMemcpyDeviceToHost);
+    e = hipMemcpy(w, g->sp.status + 1, sizeof(w), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "rom_group_check: read status");
     if (w[0] != 0 || w[1] != 0) {
-        e = hipMemset(g->sp_status + 1, 0, sizeof(w));
+        e = hipMemset(g->sp.status + 1, 0, sizeof(w));
         if (e != hipSuccess) return hip_fail(e, "rom_group_check: clear status");
         if (w[0] == ROM_E_TIMEOUT)
             return fail(ROM_E_TIMEOUT, "rom_group_check: a row-split group barrier timed out; the run's results are invalid");

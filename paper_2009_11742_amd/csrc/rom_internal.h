@@ -19,6 +19,9 @@ constexpr int kTileRows = 64;
 constexpr int kColBlock = 4;
 // Largest Kv_pad + Ks_pad the LDS-resident state of the rank-2 kernels holds.
 constexpr int kMaxPadSum = 4096;
+// Largest padded K of the FP32 row-split schedule: a group's K / 64
+// workgroups share one XCD (32 CUs).
+constexpr int kMaxSplitK = 2048;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -163,8 +166,12 @@ hipError_t launch_grouped_f32_mfma(const Rank2Args *inst_dev, const int2 *items_
 int gemm_nt_splits(int rows, int cols);
 // Row-split low-precision kernel.
 size_t rank2_split_lds_bytes();
-int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M);
+int rank2_split_groups(int kv, int ks, int kvp, int ksp, int M, bool f32);
+bool rank2_split_k_ok(int kvp, bool f32);
 size_t rank2_split_workspace_bytes(int kvp, int G);
+// Workspace of a launch with xfloats exchange floats per field and ypd
+// probe-partial doubles.
+size_t rank2_split_ws_bytes(size_t xfloats, size_t ypd);
 hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st);
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &a, float scale, void *ws,
                               int G, int *status, bool f32, hipStream_t st);
@@ -200,26 +207,31 @@ hipError_t launch_rank1_step(const void *avs_cm, const void *asv_cm, const void 
                              int ks, double dt, int64_t n, double mu, int source, void *v, void *s,
                              hipStream_t st);
 
-// Grouped row-split run (FP32 operators, Kv == Ks, one padded K for all
-// instances): one descriptor per 64-sample group.  opv / ops are the
+// Grouped row-split run (FP32 operators, Kv == Ks, each group with its own
+// padded K): one descriptor per 64-sample group.  opv / ops are the
 // instance's row-split FP32 operator packs, b its padded FP32 source, mu /
 // V / S its own arrays (ld kv); the group owns samples col0 .. col0 + 63
-// of the instance's M.
+// of the instance's M; xoff is the offset (floats) of its exchange block of
+// 64 kp floats within each field's exchange buffer of the launch.
 struct SplitGroup {
     const void *opv, *ops;
     const float *b;
     const double *mu;
     float *V, *S;
     double dt;
-    int kv, M, col0, source;
+    int64_t xoff;
+    int kv, kp, M, col0, source;
 };
-// Groups one cooperative launch holds at padded size kvp (256 / (kvp / 64)).
+// Groups one cooperative launch holds at padded size kvp: 8 floor(32 / (kvp / 64)).
 int rank2_split_groups_per_launch(int kvp);
 // Groups g0 .. g0 + G - 1 of the device table grp_dev, nsteps steps from
-// n0; ws holds rank2_split_workspace_bytes(kvp, G) bytes; status as for
-// launch_rank2_split.
-hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, int kvp, void *ws, int *status,
-                                    int64_t n0, int64_t nsteps, hipStream_t st);
+// n0.  smap_dev: the launch's slot map, 256 ints, entry 32 xcc + s = 32 lg
+// + r (group g0 + lg, row tile r) for the s-th workgroup on XCD xcc, or -1;
+// every group's kp / 64 row tiles on one XCD.  ws holds
+// rank2_split_ws_bytes(xfloats, 0) bytes (xfloats: the groups' 64 kp
+// summed); status as for launch_rank2_split.
+hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, const int *smap_dev, size_t xfloats,
+                                    void *ws, int *status, int64_t n0, int64_t nsteps, hipStream_t st);
 
 // Full-order side.  A sparse operator on the device: CSR, and when no row
 // holds more than 8 entries also a padded (ELL) copy of width W in {2, 4, 8}
@@ -272,6 +284,28 @@ hipError_t launch_pack_f32(const double *A, int rows, int cols, int rowsp, int c
 
 }  // namespace rom
 
+namespace rom {
+// Row-split part of a grouped plan: the 64-sample groups of the instances
+// it covers, ordered by launch, and per launch its first group, group
+// count, exchange floats per field and slot map (256 entries).
+struct SplitPlan {
+    std::vector<SplitGroup> groups;
+    std::vector<int> owner;                 // instance of each group
+    std::vector<int> g0, ng;                // per launch
+    std::vector<size_t> xfloats;            // per launch
+    std::vector<int> smap;                  // 256 per launch
+    size_t ws_bytes = 0;                    // the largest launch's workspace
+    int kmin = 0;                           // smallest padded K it covers
+};
+// Device copies of a row-split plan's tables.
+struct SplitDev {
+    void *groups = nullptr;    // SplitGroup [n]
+    int *smap = nullptr;       // 256 per launch
+    void *ws = nullptr;
+    int *status = nullptr;     // [4]: [1] ROM_E_TIMEOUT, [2] abort flag
+};
+}  // namespace rom
+
 struct rom_group {
     int device = 0;
     int G = 0, nitems = 0;
@@ -279,12 +313,13 @@ struct rom_group {
     void *dev = nullptr;          // [G] Rank2Args then [nitems] int2 items
     const rom::Rank2Args *inst = nullptr;
     const int2 *items = nullptr;
-    // row-split plan (used when ngroups > 0)
-    int ngroups = 0, kvp = 0;
-    void *sp_dev = nullptr;       // [ngroups] SplitGroup
-    void *sp_ws = nullptr;        // exchange workspace of one launch
-    int *sp_status = nullptr;     // [4]: [1] ROM_E_TIMEOUT, [2] abort flag
-    float us[2] = {-1.f, -1.f};   // timed per-step us of the two plans, if timed
+    // row-split part (used when ngroups > 0): its launches, then column
+    // blocks over the nrest items of the other instances
+    int ngroups = 0, nrest = 0;
+    rom::SplitPlan plan;
+    rom::SplitDev sp;
+    void *rest = nullptr;         // [nrest] int2 items
+    float us[2] = {-1.f, -1.f};   // timed per-step us: column blocks only, best plan with row-split
 };
 
 // Affine family of operator pairs (rank-3 direction): the Q terms of both

@@ -368,10 +368,14 @@ def run_grouped(roms, mus, Vs, Ss, nsteps, stream=None):
 class GroupPlan:
     """Uploaded descriptor table of a grouped run.  ``run`` enqueues the
     plan's launches (column blocks: one launch, which may be captured in a
-    HIP graph; row-split: one cooperative launch per 256 / (K / 64) groups,
-    and a captured run takes the column-block form).  ``schedule`` is
-    "rowsplit" or "columns"; ``times`` the timed per-step microseconds of
-    both plans, if this plan timed them.  Keeps references to its tensors."""
+    HIP graph; with a row-split part: its cooperative launches, groups of
+    different K side by side, then one column-block launch over the other
+    instances; a captured run takes the all-column form).  ``schedule`` is
+    "rowsplit" (a plan with a row-split part) or "columns"; ``split_k`` the
+    smallest padded K on the row-split part (0: none); ``times`` the timed
+    per-step microseconds of the column-block plan and of the fastest plan
+    with a row-split part, if this plan timed them.  Keeps references to its
+    tensors."""
 
     def __init__(self, roms, mus, Vs, Ss):
         ctxs, G, Ms, mup, Vp, Sp = _group_args(roms, mus, Vs, Ss)
@@ -387,6 +391,10 @@ class GroupPlan:
     def schedule(self):
         sc = _lib.load().rom_group_schedule(self._h)
         return "rowsplit" if sc == _lib.ROM_SCHEDULE_ROWSPLIT else "columns"
+
+    @property
+    def split_k(self):
+        return int(_lib.load().rom_group_split_k(self._h))
 
     @property
     def times(self):

@@ -1,9 +1,12 @@
-"""Grouped runs on the row-split plan: instances of one square padded K in
-{256, 512, 1024}, each split into 64-sample groups whose operator rows are
-spread over K / 64 workgroups, 256 / (K / 64) groups per cooperative launch.
+"""Grouped runs with a row-split part: square FP32 instances with a padded
+K that is a multiple of 64 in [128, 2048], each split into 64-sample groups
+whose operator rows are spread over K / 64 workgroups of one XCD; groups of
+different K share cooperative launches (8 XCDs x 32 workgroups), and the
+instances below the plan's K threshold run in one column-block launch
+after them.
 
-Each instance of such a run must equal its own rank-2 run on the row-split
-schedule bitwise (same per-column arithmetic), and the FP64 oracle to the
+Each instance of such a run must equal its own rank-2 run on the schedule
+it ran on bitwise (same per-column arithmetic), and the FP64 oracle to the
 FP32 bar (1e-5).  Every run is followed by the plan's barrier check.
 """
 import concurrent.futures as cf
@@ -188,4 +191,73 @@ def test_split_plan_graph_capture_uses_column_form():
         for (V, S), (Vr, Sr) in zip(zip(Vs, Ss), ref):
             assert torch.equal(V, Vr) and torch.equal(S, Sr), rep
     del g
+    _close(roms, plan)
+
+
+def test_mixed_k_split_plan_matches_standalone():
+    """Forced row-split over instances of seven padded K (128 .. 2048,
+    ragged Kv = 700) and ragged M: groups of different K side by side in
+    one launch, 18 groups of K = 704 (16 per launch) forcing a second
+    launch that the smaller groups fill.  Every instance bitwise equal to
+    its standalone row-split run; sampled columns against the oracle."""
+    from paper_2009_11742_amd import GroupPlan
+    specs = ([(700, 128, 60, 500 + i) for i in range(9)] + [(320, 64, 61, 520 + i) for i in range(6)] +
+             [(128, 200, 62, 540), (128, 7, 62, 541), (448, 90, 63, 542), (2048, 64, 64, 543),
+              (1024, 100, 65, 544), (192, 1, 66, 545)])
+    insts, roms, mus, Vs, Ss = _setup(specs, "rowsplit")
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    assert plan.schedule == "rowsplit" and plan.split_k == 128
+    N = 300
+    plan.run(N)
+    plan.check()
+    torch.cuda.synchronize()
+    for inst, mu, V, S in zip(insts, mus, Vs, Ss):
+        V1, S1 = _standalone(inst, mu, N, "rowsplit")
+        assert torch.equal(V, V1) and torch.equal(S, S1), inst["Avs"].shape
+    picks = [0, 9, 15, 16, 17, 18, 19, 20]
+
+    def check(i):
+        inst = insts[i]
+        col = len(inst["mu"]) - 1
+        r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][col:col + 1], N)
+        Vg = Vs[i].cpu().numpy().astype(np.float64).T[:, col:col + 1]
+        Sg = Ss[i].cpu().numpy().astype(np.float64).T[:, col:col + 1]
+        return max(_relcol(Vg, r["V"]), _relcol(Sg, r["S"]))
+
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        errs = list(ex.map(check, picks))
+    print("mixed-K split plan: sampled errors", ["%.2e" % e for e in errs])
+    assert max(errs) <= TOL
+    _close(roms, plan)
+
+
+def test_mixed_plan_auto_threshold():
+    """Unpinned contexts of several K: the plan times column blocks alone
+    and each K threshold, keeps the fastest; instances at or above the
+    threshold equal their standalone row-split runs bitwise, the others
+    their standalone column-block runs; a context pinned to column blocks
+    stays there."""
+    from paper_2009_11742_amd import GroupPlan, Rom
+    specs = [(128, 40, 70, 600), (320, 100, 71, 601), (704, 130, 72, 602), (768, 64, 73, 603),
+             (512, 300, 74, 604), (192, 17, 75, 605)]
+    insts, roms, mus, Vs, Ss = _setup(specs, "auto")
+    pinned = insts[5]
+    roms[5].close()
+    roms[5] = Rom(pinned["Avs"], pinned["Asv"], pinned["b"], pinned["dt"], state="f32", schedule="columns")
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    t, k = plan.times, plan.split_k
+    print("mixed auto plan: %s, split_k %d, times %s" % (plan.schedule, k, t))
+    assert t["columns"] is not None
+    assert (k > 0) == (plan.schedule == "rowsplit")
+    if t["rowsplit"] is not None and t["rowsplit"] < t["columns"]:
+        assert k > 0
+    N = 300
+    plan.run(N)
+    plan.check()
+    torch.cuda.synchronize()
+    for i, (inst, mu, V, S) in enumerate(zip(insts, mus, Vs, Ss)):
+        kp = -(-inst["Avs"].shape[0] // 64) * 64
+        sched = "rowsplit" if (k > 0 and kp >= k and i != 5) else "columns"
+        V1, S1 = _standalone(inst, mu, N, sched)
+        assert torch.equal(V, V1) and torch.equal(S, S1), (i, sched)
     _close(roms, plan)

@@ -237,9 +237,11 @@ def test_fp32_columns8_bitwise_equals_columns4(kv, ks, M, N):
 
 @pytest.mark.parametrize("schedule", ["auto", "columns8", "rowsplit"])
 def test_rank2_run_captured_in_graph_replays(schedule):
-    """rom_run_rank2 captured into a HIP graph (column-block schedules under
-    capture) replays three times, each replay bitwise equal to an eager run
-    of the same schedule, with eager work and synchronisation in between."""
+    """rom_run_rank2 captured into a HIP graph (non-cooperative schedules
+    under capture: column blocks, or the operator-resident kernel that
+    "auto" takes at this shape) replays three times, each replay bitwise
+    equal to an eager run of the same schedule, with eager work and
+    synchronisation in between."""
     from paper_2009_11742_amd import Rom
     inst = synth.round_to(synth.make_instance(256, 256, 24, seed=13), "f32")
     eager_sched = "columns" if schedule == "rowsplit" else schedule
@@ -270,5 +272,5 @@ def test_rank2_run_captured_in_graph_replays(schedule):
         Ve2, Se2 = rom_e.zeros(24)
         rom_e.run_rank2(mu, Ve2, Se2, 5)          # eager work between replays
         torch.cuda.synchronize()
-    assert rom.last_schedule in ("columns", "columns8")
+    assert rom.last_schedule in ("columns", "columns8", "resident")
     rom.close(); rom_e.close()

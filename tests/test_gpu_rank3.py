@@ -55,7 +55,7 @@ def test_affine_instance_operators_exact(kv, ks, Q, skew):
 
 
 def test_rank3_grouped_run_matches_standalone_and_oracle():
-    from paper_2009_11742_amd import AffineFamily, Rom, run_grouped
+    from paper_2009_11742_amd import AffineFamily, GroupPlan, Rom
     kv = ks = 128
     Q = 3
     A, B, b = _terms(kv, ks, Q, seed=3, skew=True)
@@ -74,13 +74,18 @@ def test_rank3_grouped_run_matches_standalone_and_oracle():
         mus.append(torch.tensor(rng.uniform(0.5, 1.0, M), dtype=torch.float64, device="cuda"))
         V, S = rom.zeros(M)
         Vs.append(V); Ss.append(S)
-    run_grouped(roms, mus, Vs, Ss, N)
+    plan = GroupPlan(roms, mus, Vs, Ss)
+    plan.run(N)
+    plan.check()
     torch.cuda.synchronize()
+    sched = plan.schedule          # one K: all instances on one schedule
+    plan.close()
     for p, M in enumerate(Ms):
         Ah = _assemble(A, ths[p]); Bh = _assemble(B, ths[p])
-        ref_rom = Rom(Ah, Bh, b32, dts[p], state="f32", schedule="columns")
+        ref_rom = Rom(Ah, Bh, b32, dts[p], state="f32", schedule=sched)
         V1, S1 = ref_rom.zeros(M)
         ref_rom.run_rank2(mus[p], V1, S1, N)
+        ref_rom.check()
         torch.cuda.synchronize()
         assert torch.equal(Vs[p], V1) and torch.equal(Ss[p], S1), p
         Ag, Bg, _ = roms[p].operators()

@@ -133,13 +133,52 @@ def test_rowsplit_f32_parity(K, M, N):
     assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
 
 
+# Any padded K that is a multiple of 64 from 128 to 2048 (the k-group count
+# of the FP32 kernel taken at run time; a group's K / 64 workgroups on one
+# XCD, so 8 floor(32 / (K / 64)) groups per launch): ragged K, R that does
+# not divide 32, and the largest K (one group per XCD).  Sampled columns
+# against the oracle where it would take long.
+@pytest.mark.parametrize("K,M,N,cols", [(128, 50, 800, None), (320, 70, 600, None), (700, 33, 500, None),
+                                        (1216, 20, 300, (0, 19)), (2048, 70, 300, (0, 69))])
+def test_rowsplit_f32_any_k_parity(K, M, N, cols):
+    inst = synth.round_to(synth.make_instance(K, K, M, seed=3 * K + M), "f32")
+    g = _run(inst, "f32", N, "rowsplit", trace=True)
+    sel = np.arange(M) if cols is None else np.array(cols)
+    ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][sel], N, c=inst["c"],
+                           trace=True)
+    e = max(_relcol(g["V"][:, sel], ref["V"]), _relcol(g["S"][:, sel], ref["S"]))
+    eJ = float(np.max(np.abs(g["J"][sel] - ref["J"]) / ref["J"]))
+    ey = float(np.max(np.abs(g["y"][:, sel] - ref["y"])) / np.max(np.abs(ref["y"])))
+    print("rowsplit f32 K=%d M=%d N=%d: state %.2e  J %.2e  y %.2e" % (K, M, N, e, eJ, ey))
+    assert e <= F32_BAR and eJ <= F32_BAR and ey <= F32_BAR
+
+
+def test_rowsplit_f32_any_k_schedule_and_limits():
+    """The autotuner may pick row-split at any eligible K; beyond one launch
+    (K = 2048: 8 groups of 64, so M > 512) or above K = 2048 the run takes
+    column blocks."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(2048, 2048, 600, seed=4), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule="rowsplit")
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    V, S = rom.zeros(600)
+    rom.run_rank2(mu, V, S, 3)
+    rom.check()
+    assert rom.last_schedule == "columns"
+    V, S = rom.zeros(512)
+    rom.run_rank2(mu[:512], V, S, 3)
+    rom.check()
+    assert rom.last_schedule == "rowsplit"
+    rom.close()
+
+
 @pytest.mark.parametrize("ops,K,Ms", [("f32", 256, (1000, 2000, 4000)), ("f32", 512, (500, 1000, 2000)),
-                                      ("f32", 1024, (250, 500, 1000)), ("bf16", 512, (500, 1000, 2000)),
-                                      ("bf16", 1024, (250, 500, 1000))])
+                                      ("f32", 1024, (250, 500, 1000)), ("f32", 320, (700, 1500, 3000)),
+                                      ("bf16", 512, (500, 1000, 2000)), ("bf16", 1024, (250, 500, 1000))])
 def test_rowsplit_group_width_bitwise(ops, K, Ms):
     """Row-split runs take the narrowest column group (16, 32 or 64
-    samples) whose R = K / 64 workgroups per group all fit in 256; the Ms
-    here select the three widths in turn.  A column's state arithmetic does
+    samples) whose groups all fit in one launch (8 floor(32 / (K / 64)));
+    the Ms here select the three widths in turn.  A column's state arithmetic does
     not depend on the width, so the shared samples (a prefix of the same mu)
     agree bitwise in V and S; the probe's FP64 row sum is spread over 4 NCB
     rows per thread and a shuffle tree over 16 / NCB threads, so J and the

@@ -48,7 +48,8 @@ def _both(inst, ops, nsteps, n0=0):
 def test_noalloc_equals_rowsplit_run_twice_second_smaller():
     big = synth.round_to(synth.make_instance(512, 512, 200, seed=21), "f32")
     small = synth.round_to(synth.make_instance(256, 256, 40, seed=22), "f32")
-    for inst, ops, N, n0 in ((big, "f32", 300, 0), (small, "bf16", 200, 7)):
+    odd = synth.round_to(synth.make_instance(330, 330, 30, seed=24), "f32")      # padded K 384, run-time K
+    for inst, ops, N, n0 in ((big, "f32", 300, 0), (small, "bf16", 200, 7), (odd, "f32", 150, 2)):
         out = _both(inst, ops, N, n0=n0)
         for a, b, name in zip(out["reference"], out["noalloc"], ("V", "S", "J", "y")):
             assert np.array_equal(a, b), (ops, name, float(np.max(np.abs(a - b))))
@@ -57,7 +58,7 @@ def test_noalloc_equals_rowsplit_run_twice_second_smaller():
 
 def test_noalloc_rejects_what_rowsplit_cannot_run():
     from paper_2009_11742_amd import Rom
-    inst = synth.round_to(synth.make_instance(320, 320, 8, seed=23), "f32")
+    inst = synth.round_to(synth.make_instance(320, 256, 8, seed=23, skew=False), "f32")   # Kv != Ks
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
     V, S = rom.zeros(8)
