@@ -105,95 +105,102 @@ typedef const __attribute__((address_space(1))) unsigned char gbyte;
 typedef const __attribute__((address_space(1))) dev::f4 gf4;
 typedef const __attribute__((address_space(1))) float gfloat;
 constexpr int kBatch = 16;             // terms per batch of loads (two batches in flight)
-static_assert(kChunk % kBatch == 0, "chunks are whole batches");
 
 // One half-step of the field with operator A (rows x cols): x (LDS, cols)
 // is the other field, xo (LDS, rows) receives this field's new hi words;
-// (h, l) are this lane's rows (one per pass).  FORCED adds b u.
-template <bool FORCED>
+// (h, l) are this lane's rows (one per pass).  FORCED adds b u.  VEC: rows a
+// multiple of 4, so a lane's four rows of a pass are 4 consecutive ones, one
+// 16-byte load per term (1 KB per wave instruction); else one row from each
+// of four 64-row blocks, 4-byte loads.
+template <bool FORCED, bool VEC>
 __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, int rows, int cols,
                                                  const float *__restrict__ x, float *__restrict__ xo,
-                                                 const float *__restrict__ b, float uh, float ul, float dt,
+                                                 const float (&bq)[kRank1Rows], float uh, float ul, float dt,
                                                  float (&h)[kRank1Rows], float (&pH)[4][4][64],
                                                  float (&pL)[4][4][64]) {
+    static_assert(kChunk == 2 * kBatch, "a chunk is two batches");
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int kq = (cols + 3) / 4;
     const int k0 = w * kq, k1 = min(cols, k0 + kq);
     const int nblk = (rows + 63) / 64;
-    // rows a multiple of 4: a lane's four rows of a pass are 4 consecutive
-    // ones, one 16-byte load per term (1 KB per wave instruction); else one
-    // row from each of four 64-row blocks, 4-byte loads
-    const bool vec = (rows & 3) == 0;
+    // chunks of this wave's terms k0 .. k1-1 (none if the range is empty)
+    const int nch = k1 > k0 ? (k1 - k0 + kChunk - 1) / kChunk : 0;
     for (int pass = 0; 4 * pass < nblk; ++pass) {
         float hi[4], lo[4];
-        int rc[4];
+        unsigned ro[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             hi[j] = lo[j] = 0.f;
             // rows past the end read the last row(s) (in bounds) and are never finished
-            rc[j] = vec ? min(256 * pass + 4 * lane, rows - 4) + j : min((4 * pass + j) * 64 + lane, rows - 1);
+            ro[j] = 4u * (unsigned)(VEC ? min(256 * pass + 4 * lane, rows - 4) + j
+                                        : min((4 * pass + j) * 64 + lane, rows - 1));
         }
-        // the wave's terms k0 .. k1-1 in batches of kBatch (a chunk of kChunk
-        // terms is whole batches), two batches in flight: the loads of batch
-        // i + 1 are issued before the multiply-adds of batch i (the terms
-        // past k1 re-read the last column and are not used)
-        const int nb = k1 > k0 ? (k1 - k0 + kBatch - 1) / kBatch : 0;
+        // Straight-line code, two batches of kBatch terms (one chunk) in
+        // flight: batch i + 1's loads are issued before batch i's
+        // multiply-adds.  A term past k1 loads column min(k, cols - 1) (in
+        // bounds) with multiplier 0, which adds an exact zero, so every
+        // batch takes the same instructions.
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
         float av[2][kBatch][4], xk[2][kBatch];
         // column k's address is wave-uniform (scalar base), the lane's rows a
         // 32-bit byte offset: no 64-bit address registers per load
         auto issue = [&](int bi, float (&a)[kBatch][4], float (&xx)[kBatch]) {
-            const int kb = k0 + bi * kBatch, kn = min(kBatch, k1 - kb);
+            const int kb = k0 + bi * kBatch;
 #pragma unroll
             for (int t = 0; t < kBatch; ++t) {
-                const int k = kb + min(t, kn - 1);
+                const int k = min(kb + t, cols - 1);
                 gbyte *col = reinterpret_cast<gbyte *>(reinterpret_cast<uint64_t>(A + (size_t)k * rows));
-                if (vec) {
-                    const dev::f4 v = *reinterpret_cast<gf4 *>(col + 4u * (unsigned)rc[0]);
+                if constexpr (VEC) {
+                    const dev::f4 v = *reinterpret_cast<gf4 *>(col + ro[0]);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) a[t][j] = v[j];
                 } else {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) a[t][j] = *reinterpret_cast<gfloat *>(col + 4u * (unsigned)rc[j]);
+                    for (int j = 0; j < 4; ++j) a[t][j] = *reinterpret_cast<gfloat *>(col + ro[j]);
                 }
-                xx[t] = x[k];
+                xx[t] = x[k] * (kb + t < k1 ? 1.f : 0.f);   // a product, not a branch around the load
             }
             __builtin_amdgcn_sched_barrier(0);
         };
-        auto consume = [&](int bi, const float (&a)[kBatch][4], const float (&xx)[kBatch]) {
-            const int kb = k0 + bi * kBatch, kn = min(kBatch, k1 - kb);
+        auto consume = [&](const float (&a)[kBatch][4], const float (&xx)[kBatch]) {
 #pragma unroll
             for (int t = 0; t < kBatch; ++t)
-                if (t < kn) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[j] = fmaf(a[t][j], xx[t], acc[j]);
-                }
-            // end of a chunk: fold its FP32 sum into (hi, lo)
-            if ((kb + kn - k0) % kChunk == 0 || kb + kn == k1) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float s, e;
-                    dev::two_sum(hi[j], acc[j], s, e);
-                    hi[j] = s;
-                    lo[j] += e;
-                    acc[j] = 0.f;
-                }
-            }
+                for (int j = 0; j < 4; ++j) acc[j] = fmaf(a[t][j], xx[t], acc[j]);
             __builtin_amdgcn_sched_barrier(0);
         };
-        if (nb > 0) issue(0, av[0], xk[0]);
-        for (int bi = 0; bi < nb; bi += 2) {
-            if (bi + 1 < nb) issue(bi + 1, av[1], xk[1]);
-            consume(bi, av[0], xk[0]);
-            if (bi + 1 < nb) {
-                if (bi + 2 < nb) issue(bi + 2, av[0], xk[0]);
-                consume(bi + 1, av[1], xk[1]);
+        // end of a chunk: fold its FP32 sum into (hi, lo)
+        auto fold = [&]() {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float s, e;
+                dev::two_sum(hi[j], acc[j], s, e);
+                hi[j] = s;
+                lo[j] += e;
+                acc[j] = 0.f;
             }
+        };
+        if (nch > 0) {
+            issue(0, av[0], xk[0]);
+            issue(1, av[1], xk[1]);
+            // every chunk but the last refills the ring with the next one;
+            // the last issues nothing (no loads left in flight past the
+            // products)
+            for (int c = 0; c < nch - 1; ++c) {
+                consume(av[0], xk[0]);
+                issue(2 * c + 2, av[0], xk[0]);
+                consume(av[1], xk[1]);
+                fold();
+                issue(2 * c + 3, av[1], xk[1]);
+            }
+            consume(av[0], xk[0]);
+            consume(av[1], xk[1]);
+            fold();
         }
         // partial of pass row q (0..255) at pH[w][q / 64][q % 64]
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int q = vec ? 4 * lane + j : 64 * j + lane;
+            const int q = VEC ? 4 * lane + j : 64 * j + lane;
             pH[w][q >> 6][q & 63] = hi[j];
             pL[w][q >> 6][q & 63] = lo[j];
         }
@@ -209,8 +216,9 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
             }
             float F = 0.f, Fe = 0.f;
             if (FORCED) {
-                F = b[i] * uh;
-                Fe = fmaf(b[i], uh, -F) + b[i] * ul;
+                const float bi = bq[pass];
+                F = bi * uh;
+                Fe = fmaf(bi, uh, -F) + bi * ul;
             }
             float hh = h[pass], ll = 0.f;
             dev::comp_update(hh, ll, H, L, F, Fe, dt);
@@ -221,6 +229,8 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
     }
 }
 
+// VV / VS: Kv / Ks a multiple of 4 (16-byte operator loads for that half-step).
+template <bool VV, bool VS>
 __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__ Avs, const float *__restrict__ Asv,
                                                        const float *__restrict__ b, const double *__restrict__ mu,
                                                        int kv, int ks, double dt, int64_t n0, int64_t nsteps,
@@ -230,10 +240,11 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
     float *xs = xsh, *xv = xsh + ks;           // S and V hi words
     const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // lane's rows: (4 pass + w) * 64 + lane, pass = 0 .. kRank1Rows - 1
-    float vh[kRank1Rows], sh[kRank1Rows];
+    float vh[kRank1Rows], sh[kRank1Rows], bq[kRank1Rows];
 #pragma unroll
     for (int q = 0; q < kRank1Rows; ++q) {
         const int i = (4 * q + w) * 64 + lane;
+        bq[q] = i < kv ? b[i] : 0.f;             // this lane's source rows, held for the run
         vh[q] = i < kv ? V[(size_t)m * kv + i] : 0.f;
         sh[q] = i < ks ? S[(size_t)m * ks + i] : 0.f;
         if (i < ks) xs[i] = sh[q];
@@ -243,8 +254,8 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
     for (int64_t k = 0; k < nsteps; ++k) {
         const double u = dev::forcing(src, (double)(n0 + k) * dt, mum);
         const float uh = (float)u, ul = (float)(u - (double)uh);
-        rank1_batch_half<true>(Avs, kv, ks, xs, xv, b, uh, ul, (float)dt, vh, pH, pL);
-        rank1_batch_half<false>(Asv, ks, kv, xv, xs, nullptr, 0.f, 0.f, (float)dt, sh, pH, pL);
+        rank1_batch_half<true, VV>(Avs, kv, ks, xs, xv, bq, uh, ul, (float)dt, vh, pH, pL);
+        rank1_batch_half<false, VS>(Asv, ks, kv, xv, xs, bq, 0.f, 0.f, (float)dt, sh, pH, pL);
     }
 #pragma unroll
     for (int q = 0; q < kRank1Rows; ++q) {
@@ -259,7 +270,9 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
 hipError_t launch_rank1_batch(const Rank2Args &a, hipStream_t st) {
     if (a.kv > 256 * kRank1Rows || a.ks > 256 * kRank1Rows) return hipErrorInvalidValue;
     const size_t lds = sizeof(float) * (size_t)(a.kv + a.ks);
-    hipLaunchKernelGGL(rank1_batch_f32, dim3(a.M), dim3(256), lds, st, static_cast<const float *>(a.avs),
+    auto f = (a.kv % 4 == 0) ? ((a.ks % 4 == 0) ? rank1_batch_f32<true, true> : rank1_batch_f32<true, false>)
+                             : ((a.ks % 4 == 0) ? rank1_batch_f32<false, true> : rank1_batch_f32<false, false>);
+    hipLaunchKernelGGL(f, dim3(a.M), dim3(256), lds, st, static_cast<const float *>(a.avs),
                        static_cast<const float *>(a.asv), static_cast<const float *>(a.b), a.mu, a.kv, a.ks, a.dt,
                        a.n0, a.nsteps, a.source, static_cast<float *>(a.V), static_cast<float *>(a.S));
     return hipGetLastError();
