@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--no-target", action="store_true",
                     help="skip the K = M = 1024 target record (FP32, BF16, FP8 runs and their oracle check)")
     ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline",
-                             "forward512"],
+                             "forward512", "rank1batch"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -517,6 +517,18 @@ def workload_copy(args, torch, dev):
             "GB_per_s": 2 * n * 4 / (float(np.mean(ms)) * 1e-3) / 1e9}
 
 
+def workload_rank1batch(args, torch, dev):
+    """The chip-filling rank-1 reference alone (K = M = 256, 2000 steps, three
+    launches): the run profiled for its L2 counters."""
+    import synth
+    from paper_2009_11742_amd import Rom
+    inst = synth.round_to(synth.make_instance(256, 256, 256, seed=0), "f32")
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    r = rank1_batch_rate(torch, rom, inst, 2000)
+    rom.close()
+    return dict(workload="rank-1 batch reference: Kv=Ks=256, M=256, 2000 steps", **r)
+
+
 def workload_sweep(args, torch, dev):
     """Rank-2 vs rank-1 over K in {256, 512, 1024} x M in {1, 4, 16, 64, 256,
     1024} (FP32 operators and states, median of 3 timed runs per point).
@@ -798,7 +810,7 @@ def workload_offline(args, torch, dev):
 
 
 OTHER = {"forward512": workload_forward512, "precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
-         "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain,
+         "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain, "rank1batch": workload_rank1batch,
          "receivers": workload_receivers, "rank3": workload_rank3, "fom": workload_fom,
          "offline": workload_offline}
 
