@@ -404,13 +404,18 @@ rom_status rom_run_rank2_noalloc(rom_ctx *ctx, int32_t M, const double *mu, int6
  * FP32 states and operators.  The forward sweep runs on the schedule a
  * rom_run_rank2 of the same shape takes; when that is ROWSPLIT the call
  * synchronises `stream` after it and returns ROM_E_TIMEOUT (nothing of the
- * reverse sweep enqueued) if one of its group barriers timed out.  The
- * recompute of the next segment and the
- * gradient products of the last run on two internal streams beside the
- * reverse sweep on `stream`; the context keeps the workspace (checkpoints
- * unless ckpt_stride = -1, three sets of state and probe traces, two of W/Q
- * traces: about 0.45 GB at Kv = Ks = 512, M = 256, N = 5000, 0.07 GB less
- * without checkpoints) until rom_destroy.
+ * reverse sweep enqueued) if one of its group barriers timed out.  With
+ * checkpoints and a ROWSPLIT forward sweep, the recompute and reverse sweep
+ * of every segment run on the row-split kernels as well, one after the
+ * other on `stream` (the context then also keeps row-split packs of Asv^T
+ * and Avs^T, 2 K^2 floats), the call synchronises `stream` at its end and
+ * returns ROM_E_TIMEOUT if a group barrier of those sweeps timed out.
+ * Otherwise the recompute of the next segment runs on an internal stream
+ * beside the reverse sweep on `stream`.  The gradient products of a
+ * reversed segment run on a second internal stream; the context keeps the
+ * workspace (checkpoints unless ckpt_stride = -1, three sets of state and
+ * probe traces, two of W/Q traces: about 0.45 GB at Kv = Ks = 512, M = 256,
+ * N = 5000, 0.07 GB less without checkpoints) until rom_destroy.
  */
 rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps,
                        const void *c, const void *V0, const void *S0, double *J,

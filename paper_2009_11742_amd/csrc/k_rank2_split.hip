@@ -82,6 +82,10 @@ struct SplitArgs {
     unsigned *cnt;              // group counters, kCntStride apart
     unsigned *slots;            // per-XCD slot counters (8)
     int *status;                // status[1] <- ROM_E_TIMEOUT
+    float *vtr, *str;           // FP32 traced runs: state traces (entry e, sample m, row: [e][m][row])
+    const double *ytr;          // adjoint runs: forward probe trace [step][m]
+    float *wtr, *qtr;           // adjoint runs: P after / Q before each step's P update
+    double *dmu;                // adjoint runs: += dt (b^T P) du/dmu
     const SplitGroup *grp;      // grouped FP32 runs: per-group instance data, from grp[g0]
     const int *smap;            // grouped FP32 runs: slot map (see rank2_split_f32_kernel)
     int g0;
@@ -161,6 +165,18 @@ __device__ __forceinline__ void forcing_window(double *u, int src, int64_t n, do
     for (int idx = threadIdx.x; idx < kUWin * NC; idx += kThreads) {
         const int s = idx / NC, j = idx - s * NC, m = col0 + j;
         u[idx] = m < M ? dev::forcing(src, (double)(n + s) * dt, mu[m]) : 0.0;
+    }
+}
+
+// Adjoint amplitude window: u[s][j] = 2 y(step r0 - s, column col0 + j)
+// for the kUWin iterations from r0 down (zero before the segment or past M):
+// the reverse sweep's source amplitude, from the forward probe trace.
+template <int NC>
+__device__ __forceinline__ void adjoint_window(double *u, const double *ytr, int64_t r0, int col0, int M) {
+    for (int idx = threadIdx.x; idx < kUWin * NC; idx += kThreads) {
+        const int s = idx / NC, j = idx - s * NC, m = col0 + j;
+        const int64_t r = r0 - s;
+        u[idx] = (m < M && r >= 0) ? 2.0 * ytr[(size_t)r * M + m] : 0.0;
     }
 }
 
@@ -636,11 +652,35 @@ __device__ __forceinline__ void products_f32(const f4 *opw, const float *xgrp, i
 // tile, kgl = fs / (4 / NCB), q0 = NCB (fs % (4 / NCB)), as entry e = NCB j +
 // qq of its registers: with the exchange layout above, the entries of one qq
 // are the 4 terms of one lane's fragment, published as one float4.
-template <int KGT, bool GR, int NCB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void rank2_split_f32_kernel(SplitArgs a) {
+// MODE: kSplitPlain, kSplitTraced (also writes the state after every step to
+// a.vtr / a.str, entry 0 the state given, and the probe trace to a.y), or
+// kSplitAdjoint: the discrete adjoint of the step run backwards, with the
+// fields (V, S) holding (P, Q), the operators packed as (Asv^T, Avs^T), the
+// host passing c as the source vector and b as the probe, the amplitude 2 y
+// read from a.ytr, iteration k taking step n = n0 + nsteps - 1 - k; it
+// writes a.qtr[n - n0] = Q before and a.wtr[n - n0] = P after the P update
+// and adds dt (b^T P) du/dmu(t_n) to a.dmu.
+enum SplitMode { kSplitPlain = 0, kSplitTraced = 1, kSplitAdjoint = 2 };
+
+// This workgroup's slot code (xcd + 8 * slot on that XCD), from the launch's
+// per-XCD slot counters.
+__device__ __forceinline__ int take_slot(unsigned *slots) {
+    __shared__ int sh_slot;
+    if (threadIdx.x == 0) {
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID
+        const unsigned s = __hip_atomic_fetch_add(&slots[xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh_slot = (int)(xcc + 8u * s);
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(sh_slot);
+}
+
+// The run of row tile r of group g (see the kernels below).
+template <int KGT, bool GR, int NCB, int MODE>
+__device__ __forceinline__ void split_f32_run(const SplitArgs &a, int g, int r, double *uwin) {
     static_assert(NCB == 1 || NCB == 2 || NCB == 4, "16, 32 or 64 columns per group");
     static_assert(!GR || NCB == 4, "grouped runs use 64-column groups");
+    static_assert(MODE == kSplitPlain || (!GR && KGT == 0), "traced and adjoint runs: single, run-time K");
     constexpr int NC = 16 * NCB;               // columns per group
     constexpr int TPC = kThreads / NC;         // finishing threads per column
     constexpr int RPT = 4 * NCB;               // rows per finishing thread and field
@@ -648,32 +688,10 @@ void rank2_split_f32_kernel(SplitArgs a) {
     double *part = reinterpret_cast<double *>(smem);        // [wave][col][kLdD]
     float *bl = reinterpret_cast<float *>(part + kWaves * NC * kLdD);
     float *cl = bl + kRows;
-    __shared__ int sh_slot;
-    __shared__ double uwin[kUWin * NC];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     int kp = a.kp, R = a.R;
-
-    if (tid == 0) {
-        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID
-        const unsigned s = __hip_atomic_fetch_add(&a.slots[xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sh_slot = (int)(xcc + 8u * s);
-    }
-    __syncthreads();
-    const int code = __builtin_amdgcn_readfirstlane(sh_slot);
-    const int xcc = code & 7, s = code >> 3;
-    int r, g;
-    if constexpr (GR) {
-        const int e = s < 32 ? a.smap[32 * xcc + s] : -1;
-        if (e < 0) return;                     // idle workgroup (never counted)
-        g = __builtin_amdgcn_readfirstlane(e >> 5);
-        r = __builtin_amdgcn_readfirstlane(e & 31);
-    } else {
-        r = s % R;
-        g = (s / R) * 8 + xcc;
-        if (g >= a.G) return;
-    }
     int kv = a.kv, M = a.M, col0 = g * NC, src = a.source;
     size_t xoff = (size_t)g * NC * kp;         // the group's exchange block (floats)
     double dt = a.dt;
@@ -781,15 +799,41 @@ void rank2_split_f32_kernel(SplitArgs a) {
         return ypart;
     };
 
+    // this thread's rows of field f (hi + lo) into trace matrix tr (M x kv
+    // per entry), entry e
+    auto trace = [&](float *tr, int f, int64_t e) {
+        float *d = tr + (size_t)e * M * kv + (size_t)fm * kv;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int row = row0 + frow(i);
+            if (fok && row < kv) d[row] = sh[f][i] + sl[f][i];
+        }
+    };
+
     publish(1, xs);
     group_barrier(a, cnt, (unsigned)R * ++phase);
+    if constexpr (MODE == kSplitTraced) {
+        trace(a.vtr, 0, 0);
+        trace(a.str, 1, 0);
+    }
 
     double Jacc = 0.0;
     const bool probe = csrc != nullptr;
+    const double muf = fok ? mup[fm] : 1.0;
     for (int64_t k = 0; k < a.nsteps; ++k) {
-        if (k % kUWin == 0) forcing_window<NC>(uwin, src, a.n0 + k, dt, mup, col0, M);
+        // step n of this iteration, its trace row
+        const int64_t n = MODE == kSplitAdjoint ? a.n0 + a.nsteps - 1 - k : a.n0 + k;
+        if (k % kUWin == 0) {
+            if constexpr (MODE == kSplitAdjoint)
+                adjoint_window<NC>(uwin, a.ytr, a.nsteps - 1 - k, col0, M);
+            else
+                forcing_window<NC>(uwin, src, a.n0 + k, dt, mup, col0, M);
+        }
+        if constexpr (MODE == kSplitAdjoint) trace(a.qtr, 1, n - a.n0);   // Q^{n+1}
         // (read after the products' barrier inside half_step)
         double yp = half_step(0, opvw, xs, xv, uwin + (k % kUWin) * NC + fj, true);
+        if constexpr (MODE == kSplitAdjoint) trace(a.wtr, 0, n - a.n0);   // w^n
+        if constexpr (MODE == kSplitTraced) trace(a.vtr, 0, k + 1);
         if (probe) {
             // sum over the TPC consecutive threads of column fj
 #pragma unroll
@@ -799,10 +843,15 @@ void rank2_split_f32_kernel(SplitArgs a) {
         group_barrier(a, cnt, (unsigned)R * ++phase);
         if (probe && r == 0 && fs == 0 && fok) {
             const double yv = sum_partials(a.yp + (size_t)g * R * NC + fj, NC, R);
-            Jacc += dt * (yv * yv);
-            if (a.y) a.y[(size_t)k * M + fm] = yv;
+            if constexpr (MODE == kSplitAdjoint) {
+                Jacc += dt * yv * dev::forcing_dmu(src, (double)n * dt, muf);
+            } else {
+                Jacc += dt * (yv * yv);
+                if (a.y) a.y[(size_t)k * M + fm] = yv;
+            }
         }
         half_step(1, opsw, xv, xs, nullptr, false);
+        if constexpr (MODE == kSplitTraced) trace(a.str, 1, k + 1);
         group_barrier(a, cnt, (unsigned)R * ++phase);
     }
 
@@ -814,12 +863,57 @@ void rank2_split_f32_kernel(SplitArgs a) {
             float *dst = f == 0 ? Vp : Sp;
             if (fok && row < kv) dst[(size_t)fm * kv + row] = sh[f][e] + sl[f][e];
         }
-    if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
+    if constexpr (MODE == kSplitAdjoint) {
+        if (probe && a.dmu && r == 0 && fs == 0 && fok) a.dmu[fm] += Jacc;
+    } else {
+        if (probe && a.J && r == 0 && fs == 0 && fok) a.J[fm] += Jacc;
+    }
 }
 
-// FP32 split-layout operator from a column-major FP32 matrix (rows x cols,
-// ld rows), zero padded: dst[t][w][kg][rb][lane][j] (see above).
-__global__ void split_pack_f32_kernel(const float *__restrict__ A, int rows, int cols, int T, int kp,
+template <int KGT, bool GR, int NCB, int MODE = kSplitPlain>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rank2_split_f32_kernel(SplitArgs a) {
+    __shared__ double uwin[kUWin * 16 * NCB];
+    const int code = take_slot(a.slots);
+    const int xcc = code & 7, s = code >> 3;
+    int r, g;
+    if constexpr (GR) {
+        const int e = s < 32 ? a.smap[32 * xcc + s] : -1;
+        if (e < 0) return;                     // idle workgroup (never counted)
+        g = __builtin_amdgcn_readfirstlane(e >> 5);
+        r = __builtin_amdgcn_readfirstlane(e & 31);
+    } else {
+        r = s % a.R;
+        g = (s / a.R) * 8 + xcc;
+        if (g >= a.G) return;
+    }
+    split_f32_run<KGT, GR, NCB, MODE>(a, g, r, uwin);
+}
+
+// Two runs of one shape side by side in one launch, on disjoint workgroups:
+// groups 0 .. G-1 run a0 traced (the adjoint's recompute of a segment),
+// groups G .. 2G-1 run a1 in adjoint mode (the reverse sweep of the next
+// segment).  Each run has its own workspace (exchange, counters); the slot
+// counters are a0's.
+template <int NCB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void rank2_split_f32_dual_kernel(SplitArgs a0, SplitArgs a1) {
+    __shared__ double uwin[kUWin * 16 * NCB];
+    const int code = take_slot(a0.slots);
+    const int xcc = code & 7, s = code >> 3;
+    const int r = s % a0.R, g = (s / a0.R) * 8 + xcc;
+    if (g >= 2 * a0.G) return;
+    if (g < a0.G)
+        split_f32_run<0, false, NCB, kSplitTraced>(a0, g, r, uwin);
+    else
+        split_f32_run<0, false, NCB, kSplitAdjoint>(a1, g - a0.G, r, uwin);
+}
+
+// FP32 split-layout operator (rows x cols) from a column-major FP32 matrix:
+// A itself (ld rows), or with `trans` the transpose of a column-major
+// cols x rows matrix (ld cols); zero padded: dst[t][w][kg][rb][lane][j]
+// (see above).
+__global__ void split_pack_f32_kernel(const float *__restrict__ A, int rows, int cols, int T, int kp, int trans,
                                       float *__restrict__ dst) {
     const int KG = kp / 64;
     const int64_t total = (int64_t)T * kWaves * KG * 4 * 64 * 4;
@@ -834,7 +928,7 @@ __global__ void split_pack_f32_kernel(const float *__restrict__ A, int rows, int
         const int t = (int)q;
         const int row = 64 * t + 16 * rb + (lane & 15);
         const int k = w * (kp / 4) + 16 * kg + 4 * j + (lane >> 4);
-        dst[idx] = (row < rows && k < cols) ? A[row + (int64_t)k * rows] : 0.f;
+        dst[idx] = (row < rows && k < cols) ? (trans ? A[k + (int64_t)row * cols] : A[row + (int64_t)k * rows]) : 0.f;
     }
 }
 
@@ -917,12 +1011,13 @@ size_t rank2_split_f32_lds_bytes() {
     return sizeof(double) * (size_t)kWaves * kCols * kLdD + sizeof(float) * 2 * kRows;
 }
 
-hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st) {
+hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st,
+                                 bool trans) {
     const int T = prow / kRows;
     const int64_t total = (int64_t)T * 64 * pcol;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(split_pack_f32_kernel, dim3(blocks), dim3(256), 0, st, A, rows, cols, T, pcol,
+    hipLaunchKernelGGL(split_pack_f32_kernel, dim3(blocks), dim3(256), 0, st, A, rows, cols, T, pcol, trans ? 1 : 0,
                        static_cast<float *>(dst));
     return hipGetLastError();
 }
@@ -974,6 +1069,19 @@ const void *const kSplitF32Kernels[10] = {
     (const void *)rank2_split_f32_kernel<16, false, 1>, (const void *)rank2_split_f32_kernel<16, false, 2>,
     (const void *)rank2_split_f32_kernel<0, false, 1>,  (const void *)rank2_split_f32_kernel<0, false, 2>,
     (const void *)rank2_split_f32_kernel<0, false, 4>,  (const void *)rank2_split_f32_kernel<0, true, 4>};
+
+// Traced and adjoint runs (run-time K) by group width.
+const void *const kSplitF32ModeKernels[2][3] = {
+    {(const void *)rank2_split_f32_kernel<0, false, 1, kSplitTraced>,
+     (const void *)rank2_split_f32_kernel<0, false, 2, kSplitTraced>,
+     (const void *)rank2_split_f32_kernel<0, false, 4, kSplitTraced>},
+    {(const void *)rank2_split_f32_kernel<0, false, 1, kSplitAdjoint>,
+     (const void *)rank2_split_f32_kernel<0, false, 2, kSplitAdjoint>,
+     (const void *)rank2_split_f32_kernel<0, false, 4, kSplitAdjoint>}};
+
+const void *const kSplitF32DualKernels[3] = {(const void *)rank2_split_f32_dual_kernel<1>,
+                                             (const void *)rank2_split_f32_dual_kernel<2>,
+                                             (const void *)rank2_split_f32_dual_kernel<4>};
 
 // wi: group width 16 << wi columns (single runs; grouped runs take 64).
 template <bool GR>
@@ -1062,8 +1170,8 @@ hipError_t launch_grouped_split_f32(const SplitGroup *grp_dev, int g0, int G, co
 }
 
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &r2, float scale, void *ws,
-                              int G, int *status, bool f32, hipStream_t st) {
-    SplitArgs a;
+                              int G, int *status, bool f32, hipStream_t st, int mode) {
+    SplitArgs a{};
     a.opv = static_cast<const u4 *>(opv);
     a.ops = static_cast<const u4 *>(ops);
     a.b = static_cast<const float *>(r2.b);
@@ -1096,12 +1204,83 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     // (ceil(M / nc) nc <= ceil(M / 64) 64)
     const int wi = split_width_index(a.M, a.kp);
     a.G = (a.M + (16 << wi) - 1) / (16 << wi);
+    if (mode != kSplitPlain) {
+        if (!f32 || (mode != kSplitTraced && mode != kSplitAdjoint)) return hipErrorInvalidValue;
+        a.vtr = static_cast<float *>(r2.vtr);
+        a.str = static_cast<float *>(r2.str);
+        a.ytr = r2.ytr;
+        a.wtr = static_cast<float *>(r2.wtr);
+        a.qtr = static_cast<float *>(r2.qtr);
+        a.dmu = r2.dmu;
+        return hipLaunchCooperativeKernel(kSplitF32ModeKernels[mode - 1][wi], dim3(256), dim3(kThreads), args,
+                                          rank2_split_f32_lds_bytes(), st);
+    }
     if (f32) return launch_split_f32<false>(a.kp, wi, args, st);
     const size_t lds = rank2_split_lds_bytes();
     const int idx = a.kp == 256 ? 0 : (a.kp == 512 ? 1 : (a.kp == 1024 ? 2 : -1));
     if (idx < 0) return hipErrorInvalidValue;
     return hipLaunchCooperativeKernel(kSplitLpKernels[6 * idx + 3 * (r2.single ? 1 : 0) + wi], dim3(256),
                                       dim3(kThreads), args, lds, st);
+}
+
+namespace {
+
+void fill_split_args(SplitArgs &a, const void *opv, const void *ops, const Rank2Args &r2, int *status) {
+    a = SplitArgs{};
+    a.opv = static_cast<const u4 *>(opv);
+    a.ops = static_cast<const u4 *>(ops);
+    a.b = static_cast<const float *>(r2.b);
+    a.c = static_cast<const float *>(r2.c);
+    a.mu = r2.mu;
+    a.V = static_cast<float *>(r2.V);
+    a.S = static_cast<float *>(r2.S);
+    a.J = r2.J;
+    a.y = r2.y;
+    a.kv = r2.kv;
+    a.kp = r2.kvp;
+    a.M = r2.M;
+    a.R = r2.kvp / kRows;
+    a.n0 = r2.n0;
+    a.nsteps = r2.nsteps;
+    a.dt = r2.dt;
+    a.source = r2.source;
+    a.scale = 1.0f;
+    a.status = status;
+    a.vtr = static_cast<float *>(r2.vtr);
+    a.str = static_cast<float *>(r2.str);
+    a.ytr = r2.ytr;
+    a.wtr = static_cast<float *>(r2.wtr);
+    a.qtr = static_cast<float *>(r2.qtr);
+    a.dmu = r2.dmu;
+}
+
+}  // namespace
+
+int rank2_split_dual_width(int kvp, int M) {
+    if (!rank2_split_k_ok(kvp, true)) return -1;
+    const int cap = rank2_split_groups_per_launch(kvp);
+    for (int wi = 0; wi < 3; ++wi)
+        if (2 * ((M + (16 << wi) - 1) / (16 << wi)) <= cap) return wi;
+    return -1;
+}
+
+hipError_t launch_rank2_split_dual(const void *opv0, const void *ops0, const Rank2Args &r0, void *ws0,
+                                   const void *opv1, const void *ops1, const Rank2Args &r1, void *ws1, int G,
+                                   int *status, hipStream_t st) {
+    const int wi = rank2_split_dual_width(r0.kvp, r0.M);
+    if (wi < 0 || r1.kvp != r0.kvp || r1.M != r0.M || r1.nsteps <= 0 || r0.nsteps <= 0) return hipErrorInvalidValue;
+    SplitArgs a0, a1;
+    fill_split_args(a0, opv0, ops0, r0, status);
+    fill_split_args(a1, opv1, ops1, r1, status);
+    const int R = r0.kvp / kRows;
+    // each run's workspace, carved for G 64-column groups
+    hipError_t e = split_workspace(a0, ws0, (size_t)G * kCols * a0.kp, (size_t)G * R * kCols, st);
+    if (e == hipSuccess) e = split_workspace(a1, ws1, (size_t)G * kCols * a1.kp, (size_t)G * R * kCols, st);
+    if (e != hipSuccess) return e;
+    a0.G = a1.G = (r0.M + (16 << wi) - 1) / (16 << wi);
+    void *args[] = {&a0, &a1};
+    return hipLaunchCooperativeKernel(kSplitF32DualKernels[wi], dim3(256), dim3(kThreads), args,
+                                      rank2_split_f32_lds_bytes(), st);
 }
 
 // The schedule needs all 256 workgroups resident at once, one per CU, 32 on
@@ -1127,6 +1306,20 @@ bool rank2_split_device_ok() {
             nb < 1)
             return false;
     }
+    for (const void *f : kSplitF32DualKernels) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, rank2_split_f32_lds_bytes()) != hipSuccess ||
+            nb < 1)
+            return false;
+    }
+    for (const auto &row : kSplitF32ModeKernels)
+        for (const void *f : row) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, rank2_split_f32_lds_bytes()) !=
+                    hipSuccess ||
+                nb < 1)
+                return false;
+        }
     return true;
 }
 
@@ -1141,6 +1334,15 @@ hipError_t rank2_split_configure() {
     }
     const int lf = (int)rank2_split_f32_lds_bytes();
     for (const void *f : kSplitF32Kernels) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+        if (e != hipSuccess) return e;
+    }
+    for (const auto &row : kSplitF32ModeKernels)
+        for (const void *f : row) {
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+            if (e != hipSuccess) return e;
+        }
+    for (const void *f : kSplitF32DualKernels) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf);
         if (e != hipSuccess) return e;
     }

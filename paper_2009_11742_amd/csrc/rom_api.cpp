@@ -119,6 +119,9 @@ void free_ctx(rom_ctx *c) {
     hfree(c->ws);
     hfree(c->avs_sp);
     hfree(c->asv_sp);
+    hfree(c->asvT_sp);
+    hfree(c->avsT_sp);
+    hfree(c->sp_ws2);
     hfree(c->res_pk);
     hfree(c->sp_ws);
     hfree(c->status);
@@ -1075,6 +1078,27 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         if (rs != ROM_OK) return rs;
         if (to) return fail(ROM_E_TIMEOUT, "rom_adjoint: a row-split group barrier of the forward sweep timed out");
     }
+    // With a checkpointed forward sweep on the row-split kernels, the
+    // recompute and reverse sweeps run on them too: the traced and adjoint
+    // row-split variants, one after the other on `stream` (cooperative
+    // launches may not share the chip), with the gradient products of each
+    // segment on side stream 1 beside the next segment's launches.
+    const bool split_adj = fsched == ROM_SCHEDULE_ROWSPLIT && !rev;
+    if (split_adj && !ctx->asvT_sp) {
+        const size_t pk = sizeof(float) * (size_t)ctx->kvp * ctx->ksp;
+        e = hipMalloc(&ctx->asvT_sp, pk);
+        if (e == hipSuccess) e = hipMalloc(&ctx->avsT_sp, pk);
+        if (e != hipSuccess) {
+            hfree(ctx->asvT_sp); hfree(ctx->avsT_sp);
+            ctx->asvT_sp = ctx->avsT_sp = nullptr;
+            return fail(ROM_E_NOMEM, "rom_adjoint: device allocation failed");
+        }
+        // Asv^T (Kv x Ks) from Asv (Ks x Kv), Avs^T (Ks x Kv) from Avs
+        ACHK(rom::launch_split_pack_f32(static_cast<const float *>(ctx->asv_cm), kv, ks, ctx->kvp, ctx->ksp,
+                                        ctx->asvT_sp, st, true), "rom_adjoint: split pack");
+        ACHK(rom::launch_split_pack_f32(static_cast<const float *>(ctx->avs_cm), ks, kv, ctx->ksp, ctx->kvp,
+                                        ctx->avsT_sp, st, true), "rom_adjoint: split pack");
+    }
     // reverse sweep, segment by segment from the last.  Segment g's state
     // and probe traces (set g % kTr) are written by its recompute (side
     // stream 0) and read by its reverse sweep (this stream) and its gradient
@@ -1121,8 +1145,96 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     ACHK(hipEventRecord(ev_fwd, st), "rom_adjoint: event");
     ACHK(hipStreamWaitEvent(s2, ev_fwd, 0), "rom_adjoint: event");
     ACHK(hipStreamWaitEvent(s3, ev_fwd, 0), "rom_adjoint: event");
-    ACHK(recompute(nseg - 1), "rom_adjoint: recompute");
-    for (int64_t g = nseg - 1; g >= 0; --g) {
+    // gradient products of a reversed segment (side stream 1), then its
+    // trace sets are free again
+    auto products = [&](int64_t g) -> hipError_t {
+        const int64_t len = (g * C + C <= nsteps) ? C : nsteps - g * C;
+        const int b = (int)(g % kTr), bw = (int)(g % kWq);
+        // dAvs += dt sum_n W^n (S^n)^T ;  dAsv += dt sum_n Q^{n+1} (V^{n+1})^T
+        hipError_t r = hipStreamWaitEvent(s3, ev_rev[bw], 0);
+        if (r == hipSuccess && dAvs) r = rom::launch_gemm_nt_acc64(wtrb[bw], strb[b], kv, ks, len * M, ctx->dt, dAvs64, part, s3);
+        if (r == hipSuccess && dAsv)
+            r = rom::launch_gemm_nt_acc64(qtrb[bw], vtrb[b] + v1, ks, kv, len * M, ctx->dt, dAsv64, part, s3);
+        if (r == hipSuccess) r = hipEventRecord(ev_tr_free[b], s3);
+        if (r == hipSuccess) r = hipEventRecord(ev_wq_free[bw], s3);
+        return r;
+    };
+    // row-split arguments of segment g's recompute (from its checkpoint,
+    // keeping every state and the probe trace) and reverse sweep (steps
+    // nb + len - 1 .. nb: source c, probe b)
+    auto split_rec = [&](int64_t g) {
+        const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
+        rom::Rank2Args fw = a;
+        fw.V = curV; fw.S = curS; fw.J = nullptr; fw.y = ytrb[g % kTr]; fw.n0 = nb; fw.nsteps = len;
+        fw.vtr = vtrb[g % kTr]; fw.str = strb[g % kTr];
+        return fw;
+    };
+    auto split_rev = [&](int64_t g) {
+        const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
+        rom::Rank2Args ad = a;
+        ad.b = c; ad.c = ctx->b; ad.V = P; ad.S = Q; ad.J = nullptr; ad.y = nullptr;
+        ad.n0 = nb; ad.nsteps = len; ad.ytr = ytrb[g % kTr]; ad.wtr = wtrb[g % kWq]; ad.qtr = qtrb[g % kWq];
+        ad.dmu = dmu;
+        return ad;
+    };
+    auto load_ckpt = [&](int64_t g) -> hipError_t {
+        const float *cg = ck + (size_t)g * (v1 + s1);
+        hipError_t r = hipMemcpyAsync(curV, cg, v1 * 4, hipMemcpyDeviceToDevice, st);
+        if (r == hipSuccess) r = hipMemcpyAsync(curS, cg + v1, s1 * 4, hipMemcpyDeviceToDevice, st);
+        return r;
+    };
+    // Side by side: where two runs of this shape fit one launch, segment g's
+    // reverse sweep and segment g - 1's recompute share a launch (disjoint
+    // workgroups, a second workspace); otherwise they run one after the
+    // other.
+    bool dual = split_adj && nseg > 1 && rom::rank2_split_dual_width(ctx->kvp, M) >= 0;
+    if (dual) {
+        const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, fG);
+        if (ctx->sp_ws2_bytes < need) {
+            ACHK(hipStreamSynchronize(st), "rom_adjoint: synchronize");
+            hfree(ctx->sp_ws2);
+            ctx->sp_ws2 = nullptr;
+            ctx->sp_ws2_bytes = 0;
+            e = hipMalloc(&ctx->sp_ws2, need);
+            if (e != hipSuccess) {
+                ctx->sp_ws2 = nullptr;
+                return fail(ROM_E_NOMEM, "rom_adjoint: workspace allocation failed");
+            }
+            ctx->sp_ws2_bytes = need;
+        }
+    }
+    if (split_adj) {
+        if (dual) {
+            ACHK(load_ckpt(nseg - 1), "rom_adjoint: copy");
+            ACHK(rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, split_rec(nseg - 1), 1.0f, ctx->sp_ws, fG,
+                                         ctx->status, true, st, 1), "rom_adjoint: recompute");
+        }
+        for (int64_t g = nseg - 1; g >= 0; --g) {
+            const int b = (int)(g % kTr), bw = (int)(g % kWq);
+            if (g + kWq < nseg) ACHK(hipStreamWaitEvent(st, ev_wq_free[bw], 0), "rom_adjoint: event");
+            if (dual && g >= 1) {
+                const int b1 = (int)((g - 1) % kTr);
+                if (g - 1 + kTr < nseg) ACHK(hipStreamWaitEvent(st, ev_tr_free[b1], 0), "rom_adjoint: event");
+                ACHK(load_ckpt(g - 1), "rom_adjoint: copy");
+                ACHK(rom::launch_rank2_split_dual(ctx->avs_sp, ctx->asv_sp, split_rec(g - 1), ctx->sp_ws,
+                                                  ctx->asvT_sp, ctx->avsT_sp, split_rev(g), ctx->sp_ws2, fG,
+                                                  ctx->status, st), "rom_adjoint: recompute + reverse launch");
+            } else {
+                if (!dual) {
+                    if (g + kTr < nseg) ACHK(hipStreamWaitEvent(st, ev_tr_free[b], 0), "rom_adjoint: event");
+                    ACHK(load_ckpt(g), "rom_adjoint: copy");
+                    ACHK(rom::launch_rank2_split(ctx->avs_sp, ctx->asv_sp, split_rec(g), 1.0f, ctx->sp_ws, fG,
+                                                 ctx->status, true, st, 1), "rom_adjoint: recompute");
+                }
+                ACHK(rom::launch_rank2_split(ctx->asvT_sp, ctx->avsT_sp, split_rev(g), 1.0f, ctx->sp_ws, fG,
+                                             ctx->status, true, st, 2), "rom_adjoint: reverse launch");
+            }
+            ACHK(hipEventRecord(ev_rev[bw], st), "rom_adjoint: event");
+            ACHK(products(g), "rom_adjoint: gradient product");
+        }
+    }
+    if (!split_adj) ACHK(recompute(nseg - 1), "rom_adjoint: recompute");
+    for (int64_t g = nseg - 1; g >= 0 && !split_adj; --g) {
         const int64_t nb = g * C, len = (nb + C <= nsteps) ? C : nsteps - nb;
         const int b = (int)(g % kTr), bw = (int)(g % kWq);
         if (g >= 1) ACHK(recompute(g - 1), "rom_adjoint: recompute");
@@ -1134,16 +1246,7 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
         ad.n0 = nb; ad.nsteps = len; ad.ytr = ytrb[b]; ad.wtr = wtrb[bw]; ad.qtr = qtrb[bw]; ad.dmu = dmu;
         ACHK(rom::launch_adjoint_f32_mfma(ad, st), "rom_adjoint: reverse launch");
         ACHK(hipEventRecord(ev_rev[bw], st), "rom_adjoint: event");
-        // dAvs += dt sum_n W^n (S^n)^T ;  dAsv += dt sum_n Q^{n+1} (V^{n+1})^T
-        ACHK(hipStreamWaitEvent(s3, ev_rev[bw], 0), "rom_adjoint: event");
-        if (dAvs)
-            ACHK(rom::launch_gemm_nt_acc64(wtrb[bw], strb[b], kv, ks, len * M, ctx->dt, dAvs64, part, s3),
-                 "rom_adjoint: gradient product");
-        if (dAsv)
-            ACHK(rom::launch_gemm_nt_acc64(qtrb[bw], vtrb[b] + v1, ks, kv, len * M, ctx->dt, dAsv64, part, s3),
-                 "rom_adjoint: gradient product");
-        ACHK(hipEventRecord(ev_tr_free[b], s3), "rom_adjoint: event");
-        ACHK(hipEventRecord(ev_wq_free[bw], s3), "rom_adjoint: event");
+        ACHK(products(g), "rom_adjoint: gradient product");
     }
     // join: nothing of this call stays on the side streams
     ACHK(hipEventRecord(ctx->ev[11], s2), "rom_adjoint: event");
@@ -1152,6 +1255,16 @@ rom_status rom_adjoint(rom_ctx *ctx, int32_t M, const double *mu, int64_t nsteps
     ACHK(hipStreamWaitEvent(st, ctx->ev[12], 0), "rom_adjoint: event");
     if (dAvs) ACHK(rom::launch_f64_to_f32(dAvs64, (float *)dAvs, (int64_t)kv * ks, st), "rom_adjoint: convert");
     if (dAsv) ACHK(rom::launch_f64_to_f32(dAsv64, (float *)dAsv, (int64_t)kv * ks, st), "rom_adjoint: convert");
+    if (split_adj) {
+        // the recompute and reverse sweeps ran on the row-split kernels: a
+        // timed-out group barrier makes the gradients invalid (this
+        // synchronises `stream`)
+        ACHK(hipStreamSynchronize(st), "rom_adjoint: synchronize");
+        bool to = false;
+        rom_status rs = take_timeout(ctx->status, to, "rom_adjoint: status");
+        if (rs != ROM_OK) return rs;
+        if (to) return fail(ROM_E_TIMEOUT, "rom_adjoint: a row-split group barrier of the reverse sweep timed out");
+    }
 #undef ACHK
     return ROM_OK;
 }

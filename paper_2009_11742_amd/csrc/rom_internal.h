@@ -69,6 +69,12 @@ struct rom_ctx {
     // (exchange rows, probe partials, barrier counters), and whether this
     // device can host it (-1 unknown, 0 no, 1 yes).
     void *avs_sp = nullptr, *asv_sp = nullptr;
+    // Row-split FP32 packs of Asv^T and Avs^T for the adjoint's reverse
+    // sweep on the row-split schedule (lazily).
+    void *asvT_sp = nullptr, *avsT_sp = nullptr;
+    // Second row-split workspace (the reverse sweep beside the recompute).
+    void *sp_ws2 = nullptr;
+    size_t sp_ws2_bytes = 0;
     void *sp_ws = nullptr;
     size_t sp_ws_bytes = 0;
     int sp_ok = -1;
@@ -173,10 +179,26 @@ size_t rank2_split_workspace_bytes(int kvp, int G);
 // probe-partial doubles.
 size_t rank2_split_ws_bytes(size_t xfloats, size_t ypd);
 hipError_t launch_split_pack(const void *lp, bool fp8, int kvp, int ksp, void *dst, hipStream_t st);
+// mode 0: plain run; FP32 only: 1, traced (a.vtr, a.str every step, probe
+// trace a.y), 2, adjoint (a.V, a.S hold P, Q; opv, ops the split packs of
+// Asv^T, Avs^T; a.b the probe c, a.c the source b; a.ytr, a.wtr, a.qtr,
+// a.dmu as for the column-block adjoint launch).
 hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args &a, float scale, void *ws,
-                              int G, int *status, bool f32, hipStream_t st);
+                              int G, int *status, bool f32, hipStream_t st, int mode = 0);
+// Width index (16 << wi columns) at which two FP32 runs of M samples at
+// padded K fit one launch side by side, or -1.
+int rank2_split_dual_width(int kvp, int M);
+// Run r0 traced (mode 1) and r1 in adjoint mode (mode 2) side by side in
+// one cooperative launch: same kvp and M, each with its own workspace of
+// rank2_split_workspace_bytes(kvp, G) bytes (G = ceil(M / 64)).
+hipError_t launch_rank2_split_dual(const void *opv0, const void *ops0, const Rank2Args &r0, void *ws0,
+                                   const void *opv1, const void *ops1, const Rank2Args &r1, void *ws1, int G,
+                                   int *status, hipStream_t st);
 size_t rank2_split_f32_lds_bytes();
-hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st);
+// Split-layout FP32 pack of a column-major rows x cols matrix, or with
+// `trans` of the transpose of a column-major cols x rows matrix.
+hipError_t launch_split_pack_f32(const float *A, int rows, int cols, int prow, int pcol, void *dst, hipStream_t st,
+                                 bool trans = false);
 hipError_t rank2_split_configure();
 // Static scratch of the allocation-free row-split run: its size, and its
 // device address on `device` (which must be current at the first call for
