@@ -186,7 +186,12 @@ rom_status rom_get_operators(rom_ctx *ctx, double *Avs, double *Asv, double *sca
  */
 rom_status rom_energy(rom_ctx *ctx, int32_t M, const void *V, const void *S, double *E, void *stream);
 
-/* Release every device buffer owned by the context.  NULL is accepted. */
+/*
+ * Release every device buffer and internal stream owned by the context
+ * (library housekeeping: no passage of the paper defines it).  Work the
+ * context enqueued must have completed.  NULL is accepted.  Errors: none
+ * (always ROM_OK).
+ */
 rom_status rom_destroy(rom_ctx *ctx);
 
 /*
@@ -637,7 +642,11 @@ rom_status rom_fom_destroy(rom_fom *F);
 rom_status rom_pod(int64_t n, int32_t ns, const double *X, double tol, int32_t kmax, double *phi,
                    double *sigma, int32_t *k, void *stream);
 
-/* Thread-local text describing the last non-OK status of this thread. */
+/*
+ * Thread-local text describing the last non-OK status of this thread
+ * (library housekeeping: no passage of the paper defines it).  The pointer
+ * stays valid until the thread's next library call; never NULL.
+ */
 const char *rom_last_error(void);
 
 /* Library version string. */

@@ -106,6 +106,9 @@ rom_status take_timeout(int *status, bool &timed_out, const char *who) {
 
 void free_ctx(rom_ctx *c) {
     if (!c) return;
+    // work still on the internal streams may read the buffers below
+    for (hipStream_t sd : c->side)
+        if (sd) (void)hipStreamSynchronize(sd);
     hfree(c->avs_cm);
     hfree(c->asv_cm);
     hfree(c->avs_pk);
@@ -126,10 +129,7 @@ void free_ctx(rom_ctx *c) {
     hfree(c->sp_ws);
     hfree(c->status);
     for (hipStream_t &sd : c->side)
-        if (sd) {
-            (void)hipStreamSynchronize(sd);
-            (void)hipStreamDestroy(sd);
-        }
+        if (sd) (void)hipStreamDestroy(sd);
     for (hipEvent_t &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t &ev : c->rc_ev)
