@@ -243,12 +243,13 @@ __device__ __forceinline__ void load_b(const XBuf &xg, int kb, unsigned loff, u4
     }
 }
 
-// Ring depth in k-blocks: as deep as the registers left beside the resident
-// operator allow (the loads' latency, not the L2 bandwidth, bounds the
-// exchange reads: bytes in flight / latency).
+// Ring depth in k-blocks (measured at K = 1024: the single-operand kernel
+// with 64-column groups takes 7.2 us per step at depth 2, 7.5 at 3 and 7.7
+// at 4; the pair 10.6 at 2 and 10.7 at 3 or 4), deeper only for the
+// narrower pair groups.
 template <int KB, bool SINGLE, int NCB>
 constexpr int ring_depth() {
-    constexpr int d = SINGLE ? 4 : (NCB == 4 ? kDepth : 3);
+    constexpr int d = (SINGLE || NCB == 4) ? kDepth : 3;
     return KB < d ? KB : d;
 }
 
