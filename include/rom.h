@@ -288,6 +288,20 @@ rom_status rom_check(rom_ctx *ctx, void *stream);
 rom_status rom_debug_force_timeout(int32_t on);
 
 /*
+ * Test hook for the grouped plans' row-split packing (host logic only; no
+ * device work): places n row-split groups of padded K kp[q] (multiples of
+ * 64 in [128, 2048]) into cooperative launches of 8 XCDs x 32 workgroups
+ * as rom_group_create does (largest K first, each group's K / 64 row tiles
+ * on one XCD, first launch with room).  Writes launch[q] and member[q] (the
+ * group's launch and its index lg within it) and, per launch l, the slot
+ * map slot_maps[256 l + 32 xcd + s] = 32 lg + r (row tile r of member lg
+ * in slot s of that XCD) or -1 for an idle slot.  Returns the number of
+ * launches, or -1 for an invalid argument or more than max_launches.
+ */
+int32_t rom_debug_pack_groups(const int32_t *kp, int32_t n, int32_t *launch, int32_t *member,
+                              int32_t *slot_maps, int32_t max_launches);
+
+/*
  * End-of-run health check: scans the states V (dev Kv x M) and S (dev Ks x
  * M, the context's state type) for NaN or infinite values (an unstable time
  * step, or non-finite inputs that reached the states) and returns

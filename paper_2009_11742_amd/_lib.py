@@ -33,7 +33,7 @@ ROM_NSCHEDULES = 4
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2", "rom_run_rank2_noalloc",
            "rom_adjoint", "rom_run_grouped", "rom_group_create", "rom_group_run", "rom_group_destroy",
            "rom_group_schedule", "rom_group_times", "rom_group_split_k", "rom_group_check",
-           "rom_get_operators", "rom_energy", "rom_check", "rom_debug_force_timeout", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
+           "rom_get_operators", "rom_energy", "rom_check", "rom_debug_force_timeout", "rom_debug_pack_groups", "rom_check_finite", "rom_last_schedule", "rom_schedule_times",
            "rom_tune_count", "rom_tune_get", "rom_tune_put", "rom_tune_clear", "rom_run_receivers",
            "rom_affine_create", "rom_affine_instance", "rom_affine_destroy",
            "rom_fom_create", "rom_fom_run", "rom_fom_project", "rom_fom_destroy", "rom_pod",
@@ -134,6 +134,9 @@ def load():
         lib.rom_check.argtypes = [_vp, _vp]
         lib.rom_debug_force_timeout.restype = C.c_int
         lib.rom_debug_force_timeout.argtypes = [_i32]
+        lib.rom_debug_pack_groups.restype = _i32
+        lib.rom_debug_pack_groups.argtypes = [C.POINTER(_i32), _i32, C.POINTER(_i32), C.POINTER(_i32),
+                                              C.POINTER(_i32), _i32]
         lib.rom_last_schedule.restype = C.c_int32
         lib.rom_last_schedule.argtypes = [_vp]
         lib.rom_schedule_times.restype = C.c_int

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
@@ -1434,52 +1435,79 @@ bool split_eligible(rom_ctx *c) {
     return split_candidate(c, 64) > 0;
 }
 
-// Pack the groups of the instances with use[i] into launches.  Groups go in
-// order of decreasing K (then instance, then column), each into the first
-// launch with an XCD that has K / 64 free slots (of 32), on the XCD of that
-// launch with the most free slots; a launch's step takes as long as its
-// largest-K group's, so the smaller groups fill what the larger ones left.
-void plan_split(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu, void *const *V,
-                void *const *S, const std::vector<char> &use, SplitPlan &sp) {
-    struct Cand { int inst, col0, kp; };
-    std::vector<Cand> cand;
-    for (int i = 0; i < G; ++i)
-        if (use[i])
-            for (int c0 = 0; c0 < M[i]; c0 += 64) cand.push_back({i, c0, ctx[i]->kvp});
-    std::stable_sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) { return x.kp > y.kp; });
-    struct Launch { int freec[8]; std::vector<int> mem; std::vector<int> xcd; };
-    std::vector<Launch> ls;
-    for (int q = 0; q < (int)cand.size(); ++q) {
-        const int R = cand[q].kp / 64;
+// Packing of row-split groups into cooperative launches (host logic only):
+// kp[q] is group q's padded K (K / 64 slots on one XCD of 32).  Groups go in
+// order of decreasing K (stable), each into the first launch with an XCD
+// that has K / 64 free slots, on the XCD of that launch with the most free
+// slots; a launch's step takes as long as its largest-K group's, so the
+// smaller groups fill what the larger ones left.  Returns per launch its
+// members (indices into kp, in placement order) and their XCDs.
+struct PackedLaunch {
+    std::vector<int> mem, xcd;
+};
+std::vector<PackedLaunch> pack_groups(const std::vector<int> &kp) {
+    std::vector<int> order(kp.size());
+    for (size_t q = 0; q < kp.size(); ++q) order[q] = (int)q;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return kp[x] > kp[y]; });
+    std::vector<PackedLaunch> ls;
+    std::vector<std::array<int, 8>> freec;
+    for (int q : order) {
+        const int R = kp[q] / 64;
         int li = -1, xb = -1;
         for (int l = 0; l < (int)ls.size() && li < 0; ++l) {
             for (int x = 0; x < 8; ++x)
-                if (ls[l].freec[x] >= R && (xb < 0 || ls[l].freec[x] > ls[l].freec[xb])) xb = x;
+                if (freec[l][x] >= R && (xb < 0 || freec[l][x] > freec[l][xb])) xb = x;
             if (xb >= 0) li = l;
         }
         if (li < 0) {
-            Launch L;
-            for (int x = 0; x < 8; ++x) L.freec[x] = 32;
-            ls.push_back(L);
+            ls.emplace_back();
+            freec.push_back({32, 32, 32, 32, 32, 32, 32, 32});
             li = (int)ls.size() - 1;
             xb = 0;
         }
-        ls[li].freec[xb] -= R;
+        freec[li][xb] -= R;
         ls[li].mem.push_back(q);
         ls[li].xcd.push_back(xb);
     }
+    return ls;
+}
+
+// Slot map of a packed launch: entry 32 xcd + s = 32 lg + r for row tile r
+// of the launch's lg-th member, the members' tiles in consecutive slots of
+// their XCD; -1 for idle slots.
+std::vector<int> launch_slot_map(const PackedLaunch &L, const std::vector<int> &kp) {
+    std::vector<int> sm(256, -1);
+    int used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t j = 0; j < L.mem.size(); ++j) {
+        const int x = L.xcd[j], R = kp[L.mem[j]] / 64;
+        for (int r = 0; r < R; ++r) sm[32 * x + used[x] + r] = 32 * (int)j + r;
+        used[x] += R;
+    }
+    return sm;
+}
+
+// Row-split part of a grouped plan for the instances with use[i]: their
+// 64-sample groups packed into launches (pack_groups).
+void plan_split(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu, void *const *V,
+                void *const *S, const std::vector<char> &use, SplitPlan &sp) {
+    struct Cand { int inst, col0; };
+    std::vector<Cand> cand;
+    std::vector<int> kp;
+    for (int i = 0; i < G; ++i)
+        if (use[i])
+            for (int c0 = 0; c0 < M[i]; c0 += 64) {
+                cand.push_back({i, c0});
+                kp.push_back(ctx[i]->kvp);
+            }
+    const std::vector<PackedLaunch> ls = pack_groups(kp);
     sp = SplitPlan();
-    sp.kmin = cand.empty() ? 0 : cand.back().kp;
-    for (const Launch &L : ls) {
+    sp.kmin = kp.empty() ? 0 : *std::min_element(kp.begin(), kp.end());
+    for (const PackedLaunch &L : ls) {
         const int g0 = (int)sp.groups.size();
-        int used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        std::vector<int> sm(256, -1);
         int64_t xoff = 0;
         for (size_t j = 0; j < L.mem.size(); ++j) {
             const Cand &c = cand[L.mem[j]];
-            const int i = c.inst, x = L.xcd[j], R = c.kp / 64, lg = (int)j;
-            for (int r = 0; r < R; ++r) sm[32 * x + used[x] + r] = 32 * lg + r;
-            used[x] += R;
+            const int i = c.inst;
             rom::SplitGroup g{};
             g.opv = ctx[i]->avs_sp; g.ops = ctx[i]->asv_sp;
             g.b = static_cast<const float *>(ctx[i]->b);
@@ -1487,12 +1515,13 @@ void plan_split(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *
             g.V = static_cast<float *>(V[i]); g.S = static_cast<float *>(S[i]);
             g.dt = ctx[i]->dt;
             g.source = ctx_source(ctx[i]);
-            g.kv = ctx[i]->kv; g.kp = c.kp; g.M = M[i]; g.col0 = c.col0;
+            g.kv = ctx[i]->kv; g.kp = kp[L.mem[j]]; g.M = M[i]; g.col0 = c.col0;
             g.xoff = xoff;
-            xoff += 64 * (int64_t)c.kp;
+            xoff += 64 * (int64_t)g.kp;
             sp.groups.push_back(g);
             sp.owner.push_back(i);
         }
+        const std::vector<int> sm = launch_slot_map(L, kp);
         sp.g0.push_back(g0);
         sp.ng.push_back((int)L.mem.size());
         sp.xfloats.push_back((size_t)xoff);
@@ -1752,6 +1781,25 @@ hipError_t run_group(rom_group *g, int64_t n0, int64_t nsteps, hipStream_t st) {
 }  // namespace
 
 extern "C" {
+
+int32_t rom_debug_pack_groups(const int32_t *kp, int32_t n, int32_t *launch, int32_t *member, int32_t *slot_maps,
+                              int32_t max_launches) {
+    if (!kp || n < 0 || !launch || !member || !slot_maps || max_launches < 1) return -1;
+    std::vector<int> k(kp, kp + n);
+    for (int v : k)
+        if (v < 128 || v > rom::kMaxSplitK || v % 64 != 0) return -1;
+    const std::vector<PackedLaunch> ls = pack_groups(k);
+    if ((int)ls.size() > max_launches) return -1;
+    for (size_t l = 0; l < ls.size(); ++l) {
+        for (size_t j = 0; j < ls[l].mem.size(); ++j) {
+            launch[ls[l].mem[j]] = (int32_t)l;
+            member[ls[l].mem[j]] = (int32_t)j;
+        }
+        const std::vector<int> sm = launch_slot_map(ls[l], k);
+        std::copy(sm.begin(), sm.end(), slot_maps + 256 * l);
+    }
+    return (int32_t)ls.size();
+}
 
 rom_status rom_group_create(rom_ctx *const *ctx, int32_t G, const int32_t *M, const double *const *mu,
                             void *const *V, void *const *S, rom_group **out) {
