@@ -9,6 +9,8 @@
 // contiguous bytes.  FP32 sums use the same compensated chunking as the
 // rank-2 kernel and a double-float increment, so the state is rounded once
 // per half-step.
+#include <type_traits>
+
 #include "k_common.h"
 #include "rom_internal.h"
 
@@ -106,63 +108,85 @@ typedef const __attribute__((address_space(1))) dev::f4 gf4;
 typedef const __attribute__((address_space(1))) float gfloat;
 constexpr int kBatch = 16;             // terms per batch of loads (two batches in flight)
 
-// One half-step of the field with operator A (rows x cols): x (LDS, cols)
-// is the other field, xo (LDS, rows) receives this field's new hi words;
-// (h, l) are this lane's rows (one per pass).  FORCED adds b u.  VEC: rows a
-// multiple of 4, so a lane's four rows of a pass are 4 consecutive ones, one
-// 16-byte load per term (1 KB per wave instruction); else one row from each
-// of four 64-row blocks, 4-byte loads.
-template <bool FORCED, bool VEC>
-__device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, int rows, int cols,
-                                                 const float *__restrict__ x, float *__restrict__ xo,
-                                                 const float (&bq)[kRank1Rows], float uh, float ul, float dt,
-                                                 float (&h)[kRank1Rows], float (&pH)[4][4][64],
-                                                 float (&pL)[4][4][64]) {
+// Operator loads of one batch: kBatch columns k0 + kBatch bi + t of the
+// lane's rows of pass `pass` of A (rows x cols), into a[t][0..3].  Columns
+// past the end load column cols - 1 (in bounds; their multiplier is 0).
+// Column k's address is wave-uniform (scalar base), the lane's rows a 32-bit
+// byte offset: no 64-bit address registers per load.  VEC: rows a multiple
+// of 4, so a lane's four rows of a pass are 4 consecutive ones, one 16-byte
+// load per term (1 KB per wave instruction); else one row from each of four
+// 64-row blocks, 4-byte loads.
+template <bool VEC>
+__device__ __forceinline__ void issue_ops(const float *__restrict__ A, int rows, int cols, int pass, int k0, int bi,
+                                          float (&a)[kBatch][4]) {
+    const int lane = threadIdx.x & 63;
+    unsigned ro[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)   // rows past the end read the last row(s) and are never finished
+        ro[j] = 4u * (unsigned)(VEC ? min(256 * pass + 4 * lane, rows - 4) + j
+                                    : min((4 * pass + j) * 64 + lane, rows - 1));
+    const int kb = k0 + bi * kBatch;
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const int k = min(kb + t, cols - 1);
+        gbyte *col = reinterpret_cast<gbyte *>(reinterpret_cast<uint64_t>(A + (size_t)k * rows));
+        if constexpr (VEC) {
+            const dev::f4 v = *reinterpret_cast<gf4 *>(col + ro[0]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[t][j] = v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[t][j] = *reinterpret_cast<gfloat *>(col + ro[j]);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// The operand a pass reads: operator A (rows x cols), layout VEC.
+struct R1Half {
+    const float *A;
+    int rows, cols;
+};
+
+// One half-step of the field with operator H.A: x (LDS, cols) is the other
+// field, xo (LDS, rows) receives this field's new hi words; h are this
+// lane's rows (one per pass).  FORCED adds b u.  ONE (both fields at most
+// 256 rows, one pass): the register ring av holds the first two batches on
+// entry (issued by the caller or the previous half-step), and while the last
+// chunk is multiplied the first two batches of the next half-step (operator
+// N.A, layout NVEC) are issued, so those loads are in flight across the
+// reduction and the update.  Otherwise each pass issues its own first two
+// batches.
+template <bool FORCED, bool VEC, bool NVEC, bool ONE>
+__device__ __forceinline__ void rank1_batch_half(const R1Half &H, const R1Half &N, const float *__restrict__ x,
+                                                 float *__restrict__ xo, const float (&bq)[kRank1Rows], float uh,
+                                                 float ul, float dt, float (&h)[kRank1Rows], float (&pH)[4][4][64],
+                                                 float (&pL)[4][4][64], float (&av)[2][kBatch][4]) {
     static_assert(kChunk == 2 * kBatch, "a chunk is two batches");
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rows = H.rows, cols = H.cols;
     const int kq = (cols + 3) / 4;
     const int k0 = w * kq, k1 = min(cols, k0 + kq);
     const int nblk = (rows + 63) / 64;
+    const int npass = ONE ? 1 : (nblk + 3) / 4;
     // chunks of this wave's terms k0 .. k1-1 (none if the range is empty)
     const int nch = k1 > k0 ? (k1 - k0 + kChunk - 1) / kChunk : 0;
-    for (int pass = 0; 4 * pass < nblk; ++pass) {
+    const int nk0 = w * ((N.cols + 3) / 4);   // the next half-step's first term of this wave
+    for (int pass = 0; pass < npass; ++pass) {
         float hi[4], lo[4];
-        unsigned ro[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            hi[j] = lo[j] = 0.f;
-            // rows past the end read the last row(s) (in bounds) and are never finished
-            ro[j] = 4u * (unsigned)(VEC ? min(256 * pass + 4 * lane, rows - 4) + j
-                                        : min((4 * pass + j) * 64 + lane, rows - 1));
-        }
+        for (int j = 0; j < 4; ++j) hi[j] = lo[j] = 0.f;
         // Straight-line code, two batches of kBatch terms (one chunk) in
         // flight: batch i + 1's loads are issued before batch i's
-        // multiply-adds.  A term past k1 loads column min(k, cols - 1) (in
-        // bounds) with multiplier 0, which adds an exact zero, so every
-        // batch takes the same instructions.
+        // multiply-adds.  A term past k1 has multiplier 0, which adds an
+        // exact zero, so every batch takes the same instructions.
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        float av[2][kBatch][4], xk[2][kBatch];
-        // column k's address is wave-uniform (scalar base), the lane's rows a
-        // 32-bit byte offset: no 64-bit address registers per load
-        auto issue = [&](int bi, float (&a)[kBatch][4], float (&xx)[kBatch]) {
+        auto consume = [&](int bi, const float (&a)[kBatch][4]) {
             const int kb = k0 + bi * kBatch;
+            float xx[kBatch];
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
-                const int k = min(kb + t, cols - 1);
-                gbyte *col = reinterpret_cast<gbyte *>(reinterpret_cast<uint64_t>(A + (size_t)k * rows));
-                if constexpr (VEC) {
-                    const dev::f4 v = *reinterpret_cast<gf4 *>(col + ro[0]);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) a[t][j] = v[j];
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) a[t][j] = *reinterpret_cast<gfloat *>(col + ro[j]);
-                }
-                xx[t] = x[k] * (kb + t < k1 ? 1.f : 0.f);   // a product, not a branch around the load
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        };
-        auto consume = [&](const float (&a)[kBatch][4], const float (&xx)[kBatch]) {
+            for (int t = 0; t < kBatch; ++t)   // a product, not a branch around the load
+                xx[t] = x[min(kb + t, cols - 1)] * (kb + t < k1 ? 1.f : 0.f);
 #pragma unroll
             for (int t = 0; t < kBatch; ++t)
 #pragma unroll
@@ -180,22 +204,32 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
                 acc[j] = 0.f;
             }
         };
-        if (nch > 0) {
-            issue(0, av[0], xk[0]);
-            issue(1, av[1], xk[1]);
-            // every chunk but the last refills the ring with the next one;
-            // the last issues nothing (no loads left in flight past the
-            // products)
-            for (int c = 0; c < nch - 1; ++c) {
-                consume(av[0], xk[0]);
-                issue(2 * c + 2, av[0], xk[0]);
-                consume(av[1], xk[1]);
-                fold();
-                issue(2 * c + 3, av[1], xk[1]);
+        // the first two batches of the next half-step
+        auto prefetch = [&](int bi) {
+            if constexpr (ONE) issue_ops<NVEC>(N.A, N.rows, N.cols, 0, nk0, bi, av[bi]);
+        };
+        if constexpr (!ONE) {
+            if (nch > 0) {
+                issue_ops<VEC>(H.A, rows, cols, pass, k0, 0, av[0]);
+                issue_ops<VEC>(H.A, rows, cols, pass, k0, 1, av[1]);
             }
-            consume(av[0], xk[0]);
-            consume(av[1], xk[1]);
+        }
+        for (int c = 0; c < nch - 1; ++c) {
+            consume(2 * c, av[0]);
+            issue_ops<VEC>(H.A, rows, cols, pass, k0, 2 * c + 2, av[0]);
+            consume(2 * c + 1, av[1]);
             fold();
+            issue_ops<VEC>(H.A, rows, cols, pass, k0, 2 * c + 3, av[1]);
+        }
+        if (nch > 0) {
+            consume(2 * nch - 2, av[0]);
+            prefetch(0);
+            consume(2 * nch - 1, av[1]);
+            fold();
+            prefetch(1);
+        } else {
+            prefetch(0);
+            prefetch(1);
         }
         // partial of pass row q (0..255) at pH[w][q / 64][q % 64]
 #pragma unroll
@@ -207,11 +241,11 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
         __syncthreads();
         const int i = (4 * pass + w) * 64 + lane;       // wave w finishes block 4 pass + w
         if (i < rows) {
-            float H = pH[0][w][lane], L = pL[0][w][lane];
+            float Hs = pH[0][w][lane], L = pL[0][w][lane];
             for (int q = 1; q < 4; ++q) {
                 float s, e;
-                dev::two_sum(H, pH[q][w][lane], s, e);
-                H = s;
+                dev::two_sum(Hs, pH[q][w][lane], s, e);
+                Hs = s;
                 L += e + pL[q][w][lane];
             }
             float F = 0.f, Fe = 0.f;
@@ -221,7 +255,7 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
                 Fe = fmaf(bi, uh, -F) + bi * ul;
             }
             float hh = h[pass], ll = 0.f;
-            dev::comp_update(hh, ll, H, L, F, Fe, dt);
+            dev::comp_update(hh, ll, Hs, L, F, Fe, dt);
             h[pass] = hh + ll;                  // rounded once per half-step
             xo[i] = h[pass];
         }
@@ -229,8 +263,9 @@ __device__ __forceinline__ void rank1_batch_half(const float *__restrict__ A, in
     }
 }
 
-// VV / VS: Kv / Ks a multiple of 4 (16-byte operator loads for that half-step).
-template <bool VV, bool VS>
+// VV / VS: Kv / Ks a multiple of 4 (16-byte operator loads for that
+// half-step); ONE: Kv, Ks <= 256 (one pass per half-step).
+template <bool VV, bool VS, bool ONE>
 __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__ Avs, const float *__restrict__ Asv,
                                                        const float *__restrict__ b, const double *__restrict__ mu,
                                                        int kv, int ks, double dt, int64_t n0, int64_t nsteps,
@@ -249,14 +284,23 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
         sh[q] = i < ks ? S[(size_t)m * ks + i] : 0.f;
         if (i < ks) xs[i] = sh[q];
     }
+    const R1Half hv = {Avs, kv, ks}, hs = {Asv, ks, kv};
+    // the ring: (one pass) the first two batches of the first velocity half-step
+    float av[2][kBatch][4];
+    if constexpr (ONE) {
+        const int wq = __builtin_amdgcn_readfirstlane(w) * ((ks + 3) / 4);
+        issue_ops<VV>(Avs, kv, ks, 0, wq, 0, av[0]);
+        issue_ops<VV>(Avs, kv, ks, 0, wq, 1, av[1]);
+    }
     const double mum = mu[m];
     __syncthreads();
     for (int64_t k = 0; k < nsteps; ++k) {
         const double u = dev::forcing(src, (double)(n0 + k) * dt, mum);
         const float uh = (float)u, ul = (float)(u - (double)uh);
-        rank1_batch_half<true, VV>(Avs, kv, ks, xs, xv, bq, uh, ul, (float)dt, vh, pH, pL);
-        rank1_batch_half<false, VS>(Asv, ks, kv, xv, xs, bq, 0.f, 0.f, (float)dt, sh, pH, pL);
+        rank1_batch_half<true, VV, VS, ONE>(hv, hs, xs, xv, bq, uh, ul, (float)dt, vh, pH, pL, av);
+        rank1_batch_half<false, VS, VV, ONE>(hs, hv, xv, xs, bq, 0.f, 0.f, (float)dt, sh, pH, pL, av);
     }
+    __builtin_amdgcn_s_waitcnt(0);   // the last prefetch (never used) has landed
 #pragma unroll
     for (int q = 0; q < kRank1Rows; ++q) {
         const int i = (4 * q + w) * 64 + lane;
@@ -270,8 +314,15 @@ __global__ __launch_bounds__(256) void rank1_batch_f32(const float *__restrict__
 hipError_t launch_rank1_batch(const Rank2Args &a, hipStream_t st) {
     if (a.kv > 256 * kRank1Rows || a.ks > 256 * kRank1Rows) return hipErrorInvalidValue;
     const size_t lds = sizeof(float) * (size_t)(a.kv + a.ks);
-    auto f = (a.kv % 4 == 0) ? ((a.ks % 4 == 0) ? rank1_batch_f32<true, true> : rank1_batch_f32<true, false>)
-                             : ((a.ks % 4 == 0) ? rank1_batch_f32<false, true> : rank1_batch_f32<false, false>);
+    const bool one = a.kv <= 256 && a.ks <= 256;
+    auto pick = [&](auto vv, auto vs) {
+        constexpr bool VV = decltype(vv)::value, VS = decltype(vs)::value;
+        return one ? rank1_batch_f32<VV, VS, true> : rank1_batch_f32<VV, VS, false>;
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    auto f = (a.kv % 4 == 0) ? ((a.ks % 4 == 0) ? pick(T{}, T{}) : pick(T{}, F{}))
+                             : ((a.ks % 4 == 0) ? pick(F{}, T{}) : pick(F{}, F{}));
     hipLaunchKernelGGL(f, dim3(a.M), dim3(256), lds, st, static_cast<const float *>(a.avs),
                        static_cast<const float *>(a.asv), static_cast<const float *>(a.b), a.mu, a.kv, a.ks, a.dt,
                        a.n0, a.nsteps, a.source, static_cast<float *>(a.V), static_cast<float *>(a.S));
