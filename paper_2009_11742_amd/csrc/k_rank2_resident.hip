@@ -184,7 +184,7 @@ void rank2_resident_kernel(Rank2Args a) {
     __shared__ __align__(16) float Ss[16 * (TC + 4)];  // S hi words, padded column blocks
     __shared__ __align__(16) float Vs[KVR];            // V hi words
     __shared__ __align__(16) float part[kWavesR][KSR]; // per-wave column partials of Avs^T V
-    __shared__ double ysum[kWavesR];                   // per-wave probe partials
+    __shared__ double yrow[KVR];                       // probe terms c_r V_r of the step
 
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -263,10 +263,9 @@ void rank2_resident_kernel(Rank2Args a) {
             const double yv = fma(dt, inc, (double)vh + (double)vl);
             vh = (float)yv;
             vl = (float)(yv - (double)vh);
-            if (vwriter) Vs[rv] = vh;
-            if (probe) {
-                const double cy = wave_sum64(vwriter ? cr * yv : 0.0);
-                if (l == 0) ysum[w] = cy;
+            if (vwriter) {
+                Vs[rv] = vh;
+                if (probe) yrow[rv] = cr * yv;
             }
         }
         __syncthreads();
@@ -292,12 +291,17 @@ void rank2_resident_kernel(Rank2Args a) {
             for (int j = 0; j < TC / 4; ++j) dst[j] = q[j];
         }
         __syncthreads();
-        if (probe && tid == 0) {
-            double yv = 0.0;
+        if (probe && w == 0) {
+            // one wave sums the probe terms (the other waves' VALUs stay on
+            // the products): lane l adds rows l, l + 64, .. then the wave tree
+            double t = 0.0;
 #pragma unroll
-            for (int v = 0; v < kWavesR; ++v) yv += ysum[v];
-            Jacc = fma(dt, yv * yv, Jacc);
-            if (a.y) a.y[(size_t)k * a.M + m] = yv;
+            for (int i = 0; i < KVR / 64; ++i) t += yrow[l + 64 * i];
+            const double yv = wave_sum64(t);
+            if (l == 0) {
+                Jacc = fma(dt, yv * yv, Jacc);
+                if (a.y) a.y[(size_t)k * a.M + m] = yv;
+            }
         }
         if (sown) {
             double Q = (double)part[4 * kh][ko];
