@@ -386,7 +386,8 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
  * in stream order are safe (each clears its counters before it runs).  The
  * context's row-split operators are prepared by rom_create.  Requires FP32
  * states, Kv == Ks, a padded K the row-split schedule takes (F32 operators:
- * a multiple of 64 in [128, 2048]; BF16 or F8E4M3: 256, 512 or 1024), the
+ * a multiple of 64 in [128, 2048]; BF16 or F8E4M3: a multiple of 128 in
+ * [128, 1024]), the
  * ceil(M / 64) groups of 64 samples in one launch (at most 8 floor(32 /
  * (K / 64))) and a 256-CU gfx950: else ROM_E_UNSUPPORTED,
  * as for a scratch need above the static size (nothing enqueued).  A group

@@ -979,7 +979,7 @@ size_t rank2_split_lds_bytes() {
 
 bool rank2_split_k_ok(int kvp, bool f32) {
     if (f32) return kvp % kRows == 0 && kvp >= 2 * kRows && kvp <= kMaxSplitK;
-    return kvp == 256 || kvp == 512 || kvp == 1024;
+    return kvp % 128 == 0 && kvp >= 128 && kvp <= 1024;   // whole 32-term k-blocks per wave
 }
 
 // Groups of R = kvp / 64 workgroups one launch holds: a group's workgroups
@@ -987,7 +987,7 @@ bool rank2_split_k_ok(int kvp, bool f32) {
 int rank2_split_groups_per_launch(int kvp) { return kXcds * (kCusPerXcd / (kvp / kRows)); }
 
 // Supported shapes: Kv == Ks == K with K a multiple of 64 in [128, 2048]
-// for FP32 operators, K in {256, 512, 1024} for BF16 / FP8 ones (register-
+// for FP32 operators, a multiple of 128 up to 1024 for BF16 / FP8 ones (register-
 // resident fragments), and all 64-column groups in one launch (one
 // workgroup per CU, all resident).  Returns the group count, or 0 if the
 // row-split schedule does not apply.
@@ -1094,14 +1094,16 @@ hipError_t launch_split_f32(int kp, int wi, void **args, hipStream_t st) {
     return hipLaunchCooperativeKernel(f, dim3(256), dim3(kThreads), args, rank2_split_f32_lds_bytes(), st);
 }
 
-// Low-precision kernels by (K = 256, 512, 1024) x (pair, single-pass) x
+// Low-precision kernels by (K = 128 KB, KB = 1 .. 8) x (pair, single-pass) x
 // (group width 16, 32, 64 columns).
 #define ROM_LP_WIDTHS(KB, SG)                                                           \
     (const void *)rank2_split_kernel<KB, SG, 1>, (const void *)rank2_split_kernel<KB, SG, 2>, \
         (const void *)rank2_split_kernel<KB, SG, 4>
-const void *const kSplitLpKernels[18] = {ROM_LP_WIDTHS(2, false), ROM_LP_WIDTHS(2, true),
-                                         ROM_LP_WIDTHS(4, false), ROM_LP_WIDTHS(4, true),
-                                         ROM_LP_WIDTHS(8, false), ROM_LP_WIDTHS(8, true)};
+const void *const kSplitLpKernels[48] = {
+    ROM_LP_WIDTHS(1, false), ROM_LP_WIDTHS(1, true), ROM_LP_WIDTHS(2, false), ROM_LP_WIDTHS(2, true),
+    ROM_LP_WIDTHS(3, false), ROM_LP_WIDTHS(3, true), ROM_LP_WIDTHS(4, false), ROM_LP_WIDTHS(4, true),
+    ROM_LP_WIDTHS(5, false), ROM_LP_WIDTHS(5, true), ROM_LP_WIDTHS(6, false), ROM_LP_WIDTHS(6, true),
+    ROM_LP_WIDTHS(7, false), ROM_LP_WIDTHS(7, true), ROM_LP_WIDTHS(8, false), ROM_LP_WIDTHS(8, true)};
 #undef ROM_LP_WIDTHS
 
 // Width index (group width 16 << wi columns) of the narrowest group whose
@@ -1218,8 +1220,7 @@ hipError_t launch_rank2_split(const void *opv, const void *ops, const Rank2Args 
     }
     if (f32) return launch_split_f32<false>(a.kp, wi, args, st);
     const size_t lds = rank2_split_lds_bytes();
-    const int idx = a.kp == 256 ? 0 : (a.kp == 512 ? 1 : (a.kp == 1024 ? 2 : -1));
-    if (idx < 0) return hipErrorInvalidValue;
+    const int idx = a.kp / 128 - 1;   // k-blocks per wave - 1 (K a multiple of 128, checked above)
     return hipLaunchCooperativeKernel(kSplitLpKernels[6 * idx + 3 * (r2.single ? 1 : 0) + wi], dim3(256),
                                       dim3(kThreads), args, lds, st);
 }

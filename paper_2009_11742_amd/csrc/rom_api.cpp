@@ -146,7 +146,7 @@ int ctx_source(const rom_ctx *c) { return (c->flags & ROM_SOURCE_GAUSS1) ? 1 : 0
 
 // Row-split groups for a rank-2 run of M samples with FP32 states, or 0 if
 // the row-split kernels do not apply (Kv == Ks, padded K a multiple of 64 in
-// [128, 2048] with FP32 operators, in {256, 512, 1024} with BF16 / FP8 ones;
+// [128, 2048] with FP32 operators, a multiple of 128 up to 1024 with BF16 / FP8 ones;
 // all groups in one launch; a 256-CU gfx950).
 int split_candidate(rom_ctx *ctx, int32_t M) {
     const int G = rom::rank2_split_groups(ctx->kv, ctx->ks, ctx->kvp, ctx->ksp, M, ctx->op_type == ROM_F32);
@@ -925,7 +925,7 @@ rom_status rom_run_rank2_noalloc(rom_ctx *ctx, int32_t M, const double *mu, int6
     const int G = split_candidate(ctx, M);
     if (G == 0 || !ctx->avs_sp)
         return fail(ROM_E_UNSUPPORTED, "rom_run_rank2_noalloc: the row-split schedule does not apply (Kv == Ks, "
-                                       "padded K a multiple of 64 in [128, 2048] (F32) or in {256, 512, 1024} "
+                                       "padded K a multiple of 64 in [128, 2048] (F32) or of 128 in [128, 1024] "
                                        "(BF16, FP8), ceil(M/64) <= 8 floor(32 / (K/64)), a 256-CU gfx950)");
     const size_t need = rom::rank2_split_workspace_bytes(ctx->kvp, G);
     if (need > rom::rank2_split_static_bytes())

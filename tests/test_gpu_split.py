@@ -47,7 +47,8 @@ def _run(inst, ops, N, schedule, probe=True, trace=False, n_split=None):
     rom.check()
     A, B, _ = rom.operators()
     out = {"V": V.cpu().numpy().astype(np.float64).T, "S": S.cpu().numpy().astype(np.float64).T,
-           "J": J.cpu().numpy() if probe else None, "y": y.cpu().numpy() if trace else None, "A": A, "B": B}
+           "J": J.cpu().numpy() if probe else None, "y": y.cpu().numpy() if trace else None, "A": A, "B": B,
+           "schedule": rom.last_schedule}
     rom.close()
     return out
 
@@ -55,11 +56,16 @@ def _run(inst, ops, N, schedule, probe=True, trace=False, n_split=None):
 # (256, 100): 16-sample groups whose exchange reads (32 KB per half-step)
 # fit in a CU's L1 -- the case that caught exchange lines served stale from
 # the L1 when the barrier's invalidate did not reach it.
+# K = 100, 330, 740: padded K 128, 384, 768 (one, three and six k-blocks of 32
+# terms per wave; 6 and 12 workgroups per group, so 2 to 8 CUs of each XCD
+# idle), with zero rows padding the operators.
 @pytest.mark.parametrize("ops", ["bf16", "fp8"])
-@pytest.mark.parametrize("K,M,N", [(256, 100, 1500), (512, 64, 800), (256, 200, 600)])
+@pytest.mark.parametrize("K,M,N", [(256, 100, 1500), (512, 64, 800), (256, 200, 600),
+                                   (100, 40, 900), (330, 90, 700), (740, 70, 500)])
 def test_rowsplit_same_input_parity(ops, K, M, N):
     inst = synth.round_to(synth.make_instance(K, K, M, seed=K + M), "f32")
     g = _run(inst, ops, N, "rowsplit", trace=True)
+    assert g["schedule"] == "rowsplit"
     ref = oracle.run_rank2(g["A"], g["B"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"], trace=True)
     e = max(_relcol(g["V"], ref["V"]), _relcol(g["S"], ref["S"]))
     eJ = float(np.max(np.abs(g["J"] - ref["J"]) / ref["J"]))
