@@ -35,13 +35,18 @@
 //    partner's H .. 2H-1, which then hold the same rows: no selects.  The
 //    sum of tile row s(p) ends in the 16 / TR lanes of equal s(p), which all
 //    update that row of V identically (a + b == b + a); one writes it out.
+//    The stress half-step multiplies the TR new V rows of the lane's own row
+//    block, all held in its DPP row: three more DPP patterns gather them into
+//    every lane, so V need not pass through LDS (two workgroup barriers per
+//    step, both for S; the largest tile keeps the LDS path, which measures
+//    faster there).
 //  * Stress half-step: each lane sums its TR rows for its TC columns; the
 //    four DPP rows of a wave combine with v_permlane16_swap and
 //    v_permlane32_swap (each lane keeps a quarter of its columns), the eight
 //    waves through LDS, where two lanes per column add four wave partials
 //    each in FP64 and meet with one more swap.
 // States: the FP32 (hi, lo) pair of each row of V and column of S stays in
-// its owners' registers and is updated in FP64; only the hi words pass
+// its owners' registers and is updated in FP64; only the hi words of S pass
 // through LDS to the lanes that multiply them.  The forcing u(t_n) of the
 // next 64 steps is evaluated once per wave, one step per lane.
 #include "k_common.h"
@@ -102,6 +107,30 @@ __device__ __forceinline__ void row_sum(float (&acc)[TR]) {
             acc[0] = acc[0] + level_partner<LEVEL>(acc[0]);
         }
         row_sum<TR, LEVEL + 1>(acc);
+    }
+}
+
+// The TR new V values of a lane's row block, in its register order:
+// vv[i] = V row TR rb + (i ^ s(p)), i.e. the value of a lane p' of the same
+// DPP row with s(p') = s(p) ^ i.  s is linear in the bits of p, so one
+// partner pattern per bit of i builds them all by doubling: TR = 8: bit 2 is
+// p ^ 8 (row_ror:8), bit 1 p ^ 7 (row_half_mirror), bit 0 p ^ 2 (quad_perm
+// xor 2); TR = 4: p ^ 8 and p ^ 7; TR = 2: p ^ 8.
+template <int TR>
+__device__ __forceinline__ void row_gather(float vh, float (&vv)[TR]) {
+    vv[0] = vh;
+    if constexpr (TR == 8) {
+        vv[4] = dpp_mov<kDppRor8>(vv[0]);
+        vv[2] = dpp_mov<kDppHalfMirror>(vv[0]);
+        vv[6] = dpp_mov<kDppHalfMirror>(vv[4]);
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) vv[i + 1] = dpp_mov<kDppXor2>(vv[i]);
+    } else if constexpr (TR == 4) {
+        vv[2] = dpp_mov<kDppRor8>(vv[0]);
+        vv[1] = dpp_mov<kDppHalfMirror>(vv[0]);
+        vv[3] = dpp_mov<kDppHalfMirror>(vv[2]);
+    } else {
+        vv[1] = dpp_mov<kDppRor8>(vv[0]);
     }
 }
 
@@ -181,8 +210,15 @@ __global__ __launch_bounds__(kThreadsR) __attribute__((amdgpu_waves_per_eu(2, 2)
 void rank2_resident_kernel(Rank2Args a) {
     constexpr int KVR = 32 * TR, KSR = 16 * TC;
     constexpr int DUP = 16 / TR - 1;                   // lanes of equal s(p) differ in these bits of p
+    // V gather for the stress half-step: in-row DPP moves and no workgroup
+    // barrier, except for the 8 x 16 tile (K = 256), which runs faster with
+    // the V rows through LDS behind a barrier (measured, M = 256, us per
+    // step: K = 64 0.60 -> 0.51, K = 128 0.79 -> 0.71, K = 192 1.16 -> 1.10;
+    // K = 256 1.28 with LDS and barrier, 1.35 with DPP moves or LDS without
+    // the barrier, 1.40 with both DPP moves and the barrier)
+    constexpr bool kDppGather = TC < 16;
     __shared__ __align__(16) float Ss[16 * (TC + 4)];  // S hi words, padded column blocks
-    __shared__ __align__(16) float Vs[KVR];            // V hi words
+    __shared__ __align__(16) float Vs[kDppGather ? 1 : KVR];   // V hi words (LDS gather)
     __shared__ __align__(16) float part[kWavesR][KSR]; // per-wave column partials of Avs^T V
     __shared__ double yrow[KVR];                       // probe terms c_r V_r of the step
 
@@ -264,18 +300,25 @@ void rank2_resident_kernel(Rank2Args a) {
             vh = (float)yv;
             vl = (float)(yv - (double)vh);
             if (vwriter) {
-                Vs[rv] = vh;
+                if constexpr (!kDppGather) Vs[rv] = vh;
                 if (probe) yrow[rv] = cr * yv;
             }
         }
-        __syncthreads();
 
-        // ---- stress half-step: column sums of Avs^T V, S -= dt (Avs^T V)
+        if constexpr (!kDppGather) __syncthreads();
+
+        // ---- stress half-step: column sums of Avs^T V, S -= dt (Avs^T V).
+        // The V rows a lane multiplies are those of its own row block, all
+        // updated within its DPP row.
         float q[TC];
         {
             float vv[TR];
+            if constexpr (kDppGather) {
+                row_gather<TR>(vh, vv);
+            } else {
 #pragma unroll
-            for (int i = 0; i < TR; ++i) vv[i] = Vs[TR * rb + (i ^ sx)];
+                for (int i = 0; i < TR; ++i) vv[i] = Vs[TR * rb + (i ^ sx)];
+            }
 #pragma unroll
             for (int j = 0; j < TC; ++j) {
                 float s = op[0][j] * vv[0];
