@@ -78,11 +78,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--fom-point", default=None,
                     help="fom workload: one point only, GRIDxM (e.g. 512x2048x48), timed over --steps runs")
+    ap.add_argument("--scaling-point", default=None,
+                    help="scaling workload: one point only, KxM (e.g. 4096x1024)")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
     ap.add_argument("--no-target", action="store_true",
                     help="skip the K = M = 1024 target record (FP32, BF16, FP8 runs and their oracle check)")
     ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline",
-                             "forward512", "rank1batch"],
+                             "forward512", "rank1batch", "scaling"],
                     help="rank2 (default, the reported line); the others print their own measurement line; "
                          "copy runs a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
@@ -574,6 +576,49 @@ def workload_sweep(args, torch, dev):
     return out
 
 
+def workload_scaling(args, torch, dev):
+    """The paper's ROM scaling range above the sweep (Sec. 4.2 goes to
+    K = 4096): FP32 rank-2 runs at K in {2048, 3072, 4096} x M in {64, 256,
+    1024} on the schedule the autotuner picks (the panel schedule above
+    Kv_pad + Ks_pad = 4096), median of 3 timed runs; at M = 1024 the error
+    of one sampled column against the oracle over the timed run length."""
+    import oracle
+    import synth
+    from paper_2009_11742_amd import Rom
+    Ks, Ms = (2048, 3072, 4096), (64, 256, 1024)
+    if args.scaling_point:
+        k, m = (int(v) for v in args.scaling_point.lower().split("x"))
+        Ks, Ms = (k,), (m,)
+    out = {"workload": "scaling: rank-2 FP32, K in %s x M in %s" % (list(Ks), list(Ms)),
+           "unit": "sample-steps/s", "points": []}
+    for K in Ks:
+        inst = synth.round_to(synth.make_instance(K, K, max(1024, max(Ms)), seed=0), "f32")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+        N = 50 if K <= 2048 else (30 if K <= 3072 else 20)
+        for M in Ms:
+            mu = torch.tensor(inst["mu"][:M], dtype=torch.float64, device=dev)
+            V, S = rom.zeros(M, device=dev)
+
+            def run():
+                V.zero_(); S.zero_()
+                rom.run_rank2(mu, V, S, N)
+            wall, ms = _events_time(torch, run, 3, 1)
+            rom.check()
+            ksec = float(np.median(ms)) * 1e-3
+            tf = 4.0 * K * K * M * N / ksec / 1e12
+            pt = {"K": K, "M": M, "nsteps": N, "value": M * N / ksec, "us_per_step": ksec / N * 1e6,
+                  "tflops": tf, "frac": tf / 157.3, "schedule": rom.last_schedule}
+            if M >= 1024:
+                ci = 517
+                r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N)
+                Vg = V.cpu().numpy().astype(np.float64).T[:, ci:ci + 1]
+                Sg = S.cpu().numpy().astype(np.float64).T[:, ci:ci + 1]
+                pt["max_rel_err_vs_oracle"] = max(_err_cols(Vg, r["V"]), _err_cols(Sg, r["S"]))
+            out["points"].append(pt)
+        rom.close()
+    return out
+
+
 def workload_forward512(args, torch, dev):
     """The forward run at the adjoint's shape: K = 512, M = 256, 5000 steps,
     FP32, on the schedule the tuning table gives (the row-split kernel with
@@ -812,7 +857,7 @@ def workload_offline(args, torch, dev):
 OTHER = {"forward512": workload_forward512, "precision": workload_precision, "grouped": workload_grouped, "adjoint": workload_adjoint,
          "copy": workload_copy, "sweep": workload_sweep, "plain": workload_plain, "rank1batch": workload_rank1batch,
          "receivers": workload_receivers, "rank3": workload_rank3, "fom": workload_fom,
-         "offline": workload_offline}
+         "offline": workload_offline, "scaling": workload_scaling}
 
 
 if __name__ == "__main__":

@@ -91,9 +91,11 @@ enum {
     ROM_SCHED_ROWSPLIT = 4u,/* FP32-state rank-2 runs: the row-split kernels
                                (operator rows split over the workgroups of a
                                sample group, exchanged every half-step)
-                               wherever they apply: Kv == Ks in {256, 512,
-                               1024}, ceil(M/64) * K/64 <= 256, a 256-CU
-                               gfx950; else 4-column blocks.  Groups of 64
+                               wherever they apply: Kv == Ks, padded K a
+                               multiple of 64 in [128, 2048] (FP32
+                               operators) or of 128 up to 1024 (BF16 / FP8),
+                               all groups in one launch, a 256-CU gfx950;
+                               else 4-column blocks.  Groups of 64
                                samples with BF16 / FP8 operators; with FP32
                                operators the narrowest of 16, 32, 64 whose
                                ceil(M/width) * K/64 workgroups fit in 256   */
@@ -113,6 +115,13 @@ enum {
                                the operator-resident kernel (one sample per
                                workgroup, all of Avs in its registers); else
                                4-column blocks                                */
+    ROM_SCHED_PANEL = 128u, /* FP32 operators and states: the panel
+                               schedule (one tiled matrix-product launch
+                               per half-step, nothing resident between
+                               them), which runs of any Kv, Ks take anyway
+                               where the column blocks' states do not fit
+                               in LDS (Kv_pad + Ks_pad > 4096); ignored
+                               with other operator or state types          */
     ROM_STATE_BF16 = 32u    /* BF16 / F8E4M3 operators with F32 states: the
                                state operand of every product is bf16(x)
                                alone (one MFMA pass, about 8 significant
@@ -215,6 +224,19 @@ rom_status rom_destroy(rom_ctx *ctx);
  *                          for the whole run and uses it for both half-
  *                          steps (Asv V = -Avs^T V); no operator streaming,
  *                          no exchange between workgroups.
+ *   ROM_SCHEDULE_PANEL     FP32 operators, any Kv, Ks: each half-step one
+ *                          launch of a tiled matrix product (128 operator
+ *                          rows x 64 samples per workgroup, FP32 matrix
+ *                          cores, FP64 compensated update in its epilogue);
+ *                          states and probe partials in a context
+ *                          workspace of about 8 (Kv + Ks) M bytes, operator
+ *                          copies of 4 Kv Ks bytes each, both allocated on
+ *                          the first such run (which must not be captured
+ *                          into a graph: ROM_E_UNSUPPORTED).  Always taken
+ *                          where Kv_pad + Ks_pad > 4096 or with
+ *                          ROM_SCHED_PANEL; the autotuner weighs it from
+ *                          Kv_pad + Ks_pad >= 2048 (under capture only
+ *                          once its workspace covers the run).
  * Without a ROM_SCHED_* flag the first run of each shape (Kv_pad, Ks_pad, M
  * rounded up to 64, operator type) times every schedule that applies for 32
  * steps on scratch states and keeps the fastest for the process (that run
@@ -247,9 +269,10 @@ typedef enum {
     ROM_SCHEDULE_COLUMNS4 = 0,
     ROM_SCHEDULE_ROWSPLIT = 1,
     ROM_SCHEDULE_COLUMNS8 = 2,
-    ROM_SCHEDULE_RESIDENT = 3
+    ROM_SCHEDULE_RESIDENT = 3,
+    ROM_SCHEDULE_PANEL = 4
 } rom_schedule;
-#define ROM_NSCHEDULES 4
+#define ROM_NSCHEDULES 5
 
 typedef struct {
     int32_t kv_pad, ks_pad; /* Kv, Ks rounded up to multiples of 64           */
@@ -365,7 +388,11 @@ rom_status rom_run_rank1_batch(rom_ctx *ctx, int32_t M, const double *mu, int64_
  * kernel keeps a compensation term per entry during the run (two-term
  * state) and rounds once when writing back, so splitting a run in two
  * differs from the whole run by at most a rounding of the state.
- * Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_DEVICE, ROM_E_TIMEOUT.
+ * Sizes: FP32 operators and states run at any Kv, Ks (above Kv_pad + Ks_pad
+ * = 4096 on the panel schedule); BF16 / FP8 operators and FP64 states
+ * within their kernels' LDS limits (ROM_E_UNSUPPORTED above).
+ * Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_NOMEM (panel workspace),
+ * ROM_E_DEVICE, ROM_E_TIMEOUT.
  */
 rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0,
                          int64_t nsteps, void *V, void *S, const void *c, double *J,

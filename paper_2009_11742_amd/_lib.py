@@ -26,8 +26,9 @@ ROM_SCHED_COLUMNS8 = 8
 ROM_SOURCE_GAUSS1 = 16
 ROM_STATE_BF16 = 32
 ROM_SCHED_RESIDENT = 64
-ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8, ROM_SCHEDULE_RESIDENT = range(4)
-ROM_NSCHEDULES = 4
+ROM_SCHED_PANEL = 128
+ROM_SCHEDULE_COLUMNS4, ROM_SCHEDULE_ROWSPLIT, ROM_SCHEDULE_COLUMNS8, ROM_SCHEDULE_RESIDENT, ROM_SCHEDULE_PANEL = range(5)
+ROM_NSCHEDULES = 5
 
 # Every symbol include/rom.h declares.
 EXPORTS = ["rom_create", "rom_destroy", "rom_step_rank1", "rom_run_rank1", "rom_run_rank1_batch", "rom_run_rank2", "rom_run_rank2_noalloc",

@@ -136,6 +136,9 @@ void free_ctx(rom_ctx *c) {
     for (hipEvent_t &ev : c->rc_ev)
         if (ev) (void)hipEventDestroy(ev);
     hfree(c->rc_ws);
+    hfree(c->avs_rm);
+    hfree(c->asv_rm);
+    hfree(c->pn_ws);
     delete c;
 }
 
@@ -212,11 +215,73 @@ bool cols8_ok(const rom_ctx *ctx) {
 
 // Launch one rank-2 run with FP32 states on schedule `sched` (a
 // rom_schedule that applies; G: row-split groups).
+// Panel schedule run (FP32 operators and states, any size).  The operator
+// copies and the workspace are allocated on first use; a stream being
+// captured cannot allocate, so a captured run needs an earlier uncaptured
+// run of at least as many samples on the context.
+bool stream_capturing(hipStream_t st);
+
+// Whether the autotuner weighs the panel schedule for a run: FP32
+// operators at Kv_pad + Ks_pad >= 2048 (below, its two launches per step
+// and its state traffic lose to every resident schedule), and under graph
+// capture only once its workspace covers the run.
+bool panel_candidate(const rom_ctx *ctx, int M, bool capturing) {
+    if (ctx->op_type != ROM_F32 || ctx->state_type != ROM_F32 || ctx->kvp + ctx->ksp < 2048) return false;
+    return !capturing || (ctx->avs_rm && ctx->pn_ws_bytes >= rom::panel_ws_bytes(ctx->kv, ctx->ks, M));
+}
+
+rom_status run_panel(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st) {
+    const bool capturing = stream_capturing(st);
+    const size_t need = rom::panel_ws_bytes(ctx->kv, ctx->ks, a.M);
+    if (!ctx->avs_rm || ctx->pn_ws_bytes < need) {
+        if (capturing)
+            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: the panel schedule allocates its workspace on first use; "
+                                           "run it once outside graph capture with at least this many samples");
+        hipError_t e = hipSuccess;
+        if (!ctx->avs_rm) {
+            const size_t ob = rom::panel_op_bytes(ctx->kv, ctx->ks);
+            e = hipMalloc(&ctx->avs_rm, ob);
+            if (e == hipSuccess) e = hipMalloc(&ctx->asv_rm, ob);
+            if (e == hipSuccess)
+                e = rom::launch_panel_pack(static_cast<const float *>(ctx->avs_cm), static_cast<const float *>(ctx->asv_cm),
+                                           ctx->kv, ctx->ks, static_cast<float *>(ctx->avs_rm),
+                                           static_cast<float *>(ctx->asv_rm), st);
+            if (e != hipSuccess) {
+                hfree(ctx->avs_rm); hfree(ctx->asv_rm);
+                ctx->avs_rm = ctx->asv_rm = nullptr;
+                return e == hipErrorOutOfMemory ? fail(ROM_E_NOMEM, "rom_run_rank2: panel operator allocation failed")
+                                                : hip_fail(e, "rom_run_rank2: panel pack");
+            }
+        }
+        if (ctx->pn_ws_bytes < need) {
+            // the previous workspace may still be read by queued work
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: synchronize");
+            hfree(ctx->pn_ws);
+            ctx->pn_ws = nullptr;
+            ctx->pn_ws_bytes = 0;
+            e = hipMalloc(&ctx->pn_ws, need);
+            if (e != hipSuccess) {
+                ctx->pn_ws = nullptr;
+                return fail(ROM_E_NOMEM, "rom_run_rank2: panel workspace allocation failed");
+            }
+            ctx->pn_ws_bytes = need;
+        }
+    }
+    hipError_t e = rom::launch_rank2_panel(static_cast<const float *>(ctx->avs_rm),
+                                           static_cast<const float *>(ctx->asv_rm), a, ctx->pn_ws, st);
+    if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: panel launch");
+    ctx->last_schedule = ROM_SCHEDULE_PANEL;
+    return ROM_OK;
+}
+
 rom_status launch_fp32_state_run(rom_ctx *ctx, rom::Rank2Args a, int sched, int G, hipStream_t st) {
     hipError_t e;
     const bool lowp = ctx->op_type == ROM_BF16 || ctx->op_type == ROM_F8E4M3;
     a.single = (lowp && (ctx->flags & ROM_STATE_BF16)) ? 1 : 0;
-    if (sched == ROM_SCHEDULE_RESIDENT) {
+    if (sched == ROM_SCHEDULE_PANEL) {
+        return run_panel(ctx, a, st);
+    } else if (sched == ROM_SCHEDULE_RESIDENT) {
         a.avs = ctx->res_pk; a.asv = nullptr;
         e = rom::launch_rank2_resident(a, st);
     } else if (sched == ROM_SCHEDULE_ROWSPLIT) {
@@ -354,6 +419,7 @@ rom_status pick_schedule(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st, 
     if (G > 0) cands |= 1u << ROM_SCHEDULE_ROWSPLIT;
     if (cols8_ok(ctx)) cands |= 1u << ROM_SCHEDULE_COLUMNS8;
     if (ctx->res_pk) cands |= 1u << ROM_SCHEDULE_RESIDENT;
+    if (panel_candidate(ctx, a.M, capturing)) cands |= 1u << ROM_SCHEDULE_PANEL;
     sched = ROM_SCHEDULE_COLUMNS4;
     if (ctx->flags & ROM_SCHED_COLUMNS) return ROM_OK;
     if (ctx->flags & ROM_SCHED_RESIDENT) {
@@ -441,11 +507,12 @@ rom_status check_config(const rom_config *cfg, const char *who) {
         return fail(ROM_E_UNSUPPORTED, w + ": supported (op, state) pairs are (F64, F64), "
                                           "(F32, F32), and (BF16 or F8E4M3, F32 or F64)");
     if (cfg->flags & ~(uint32_t)(ROM_SKEW_CHECK | ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 |
-                                 ROM_SCHED_RESIDENT | ROM_SOURCE_GAUSS1 | ROM_STATE_BF16))
+                                 ROM_SCHED_RESIDENT | ROM_SCHED_PANEL | ROM_SOURCE_GAUSS1 | ROM_STATE_BF16))
         return fail(ROM_E_ARG, w + ": unknown flag bits");
     if ((cfg->flags & ROM_STATE_BF16) && !(lowp && cfg->state_type == ROM_F32))
         return fail(ROM_E_ARG, w + ": ROM_STATE_BF16 needs BF16 or F8E4M3 operators with F32 states");
-    const uint32_t sf = cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 | ROM_SCHED_RESIDENT);
+    const uint32_t sf =
+        cfg->flags & (ROM_SCHED_COLUMNS | ROM_SCHED_ROWSPLIT | ROM_SCHED_COLUMNS8 | ROM_SCHED_RESIDENT | ROM_SCHED_PANEL);
     if (sf & (sf - 1)) return fail(ROM_E_ARG, w + ": at most one ROM_SCHED_* flag");
     return ROM_OK;
 }
@@ -895,9 +962,11 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         const bool lowp = ctx->op_type != ROM_F32;
         if (lowp && rom::rank2_lowp_lds_bytes(ctx->kvp, ctx->ksp) > 160 * 1024)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit");
-        if (!lowp && (ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
+        // FP32 operators: the panel schedule where the column blocks' states
+        // do not fit in LDS, or where the context pins it
+        if (!lowp && ((ctx->flags & ROM_SCHED_PANEL) || ctx->kvp + ctx->ksp > rom::kMaxPadSum ||
                       rom::rank2_f32_mfma_lds_bytes(ctx->kvp, ctx->ksp, 1) > 160 * 1024))
-            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: Kv + Ks above the LDS-resident limit (4096 padded)");
+            return run_panel(ctx, a, st);
         int sched = ROM_SCHEDULE_COLUMNS4, G = 0;
         rom_status rs = pick_schedule(ctx, a, st, sched, G);
         if (rs != ROM_OK) return rs;

@@ -99,6 +99,12 @@ struct rom_ctx {
     void *rc_ws = nullptr;
     size_t rc_ws_bytes = 0;
     hipEvent_t rc_ev[5] = {};
+    // Panel schedule (FP32, any size): row-major padded operator copies
+    // (built on first use) and the run workspace (states hi / lo, probe
+    // partials), grown on demand.
+    void *avs_rm = nullptr, *asv_rm = nullptr;
+    void *pn_ws = nullptr;
+    size_t pn_ws_bytes = 0;
 };
 
 namespace rom {
@@ -135,6 +141,17 @@ struct Rank2Args {
 // Operator-resident kernel (skew pairs, FP32): whether padded sizes fit it,
 // the bytes of its operator pack, the pack from a column-major FP32 Avs, and
 // the run (a.avs = the pack).
+// Panel schedule (FP32 operators and states, any Kv, Ks): one tiled MFMA
+// product launch per half-step.  Sizes padded to 128; operator copies of
+// panel_op_bytes each; run workspace of panel_ws_bytes.
+int panel_pad(int k);
+size_t panel_op_bytes(int kv, int ks);
+size_t panel_ws_bytes(int kv, int ks, int M);
+hipError_t launch_panel_pack(const float *avs_cm, const float *asv_cm, int kv, int ks, float *avs_rm,
+                             float *asv_rm, hipStream_t st);
+hipError_t launch_rank2_panel(const float *avs_rm, const float *asv_rm, const Rank2Args &a, void *ws,
+                              hipStream_t st);
+
 bool rank2_resident_applies(int kvp, int ksp);
 size_t rank2_resident_pack_bytes(int kvp, int ksp);
 hipError_t launch_resident_pack(const float *A, int kv, int ks, int kvp, int ksp, void *pk, hipStream_t st);

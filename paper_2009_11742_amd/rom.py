@@ -22,13 +22,14 @@ _OPS = {"f64": _lib.ROM_F64, "f32": _lib.ROM_F32, "bf16": _lib.ROM_BF16, "fp8": 
 # FP32-state rank-2 schedule: "auto" (the autotuner's table), "columns"
 # (4-column blocks), "rowsplit" (row-split where it applies), "columns8"
 # (8-column blocks, FP32 operators), "resident" (skew FP32 pairs with Kv, Ks
-# <= 256: the whole operator in each workgroup's registers, one sample each)
+# <= 256: the whole operator in each workgroup's registers, one sample each),
+# "panel" (FP32 operators, any size: one matrix-product launch per half-step)
 # source signal: the Ricker wavelet or the first derivative of a Gaussian
 _SOURCE = {"ricker": 0, "gauss1": _lib.ROM_SOURCE_GAUSS1}
 # state operand of the BF16 / FP8 products: the BF16 pair or bf16(x) alone
 _STATE_OPERAND = {"pair": 0, "single": _lib.ROM_STATE_BF16}
 _SCHED = {"auto": 0, "columns": _lib.ROM_SCHED_COLUMNS, "rowsplit": _lib.ROM_SCHED_ROWSPLIT,
-          "columns8": _lib.ROM_SCHED_COLUMNS8, "resident": _lib.ROM_SCHED_RESIDENT}
+          "columns8": _lib.ROM_SCHED_COLUMNS8, "resident": _lib.ROM_SCHED_RESIDENT, "panel": _lib.ROM_SCHED_PANEL}
 
 
 def _stream_handle(stream):

@@ -4,7 +4,8 @@
 
 Empties the process table, then runs the library's autotuner on the shapes
 of the standard workloads: FP32-state rank-2 runs for K in {256, 512, 1024}
-x M in {64, 256, 1024} (FP32 operators; BF16 and FP8 at K = M = 1024), and
+x M in {64, 256, 1024} and K = 2048 at M in {512, 1024} (FP32 operators; BF16
+and FP8 at K = M = 1024), and
 the grouped launch's per-workgroup tile times for K in {128, 192, ..., 768}.
 The operators are random skew pairs (timing does not depend on the values).
 Every entry is what the autotuner measured; nothing is edited by hand.
@@ -21,7 +22,7 @@ from . import tuning
 from .rom import GroupPlan, Rom
 
 RUN_SHAPES = [(K, M, "f32") for K in (256, 512, 1024) for M in (64, 256, 1024)] + \
-             [(1024, 1024, "bf16"), (1024, 1024, "fp8")]
+             [(2048, 512, "f32"), (2048, 1024, "f32"), (1024, 1024, "bf16"), (1024, 1024, "fp8")]
 TILE_K = list(range(128, 769, 64))
 
 
@@ -77,7 +78,7 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     tuning.save(args.out, header="schedule tuning table: python -m paper_2009_11742_amd.tune\n"
                 "device: %s (%d CUs), %s\n"
-                "kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8 us_resident"
+                "kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8 us_resident us_panel"
                 % (dev.name, dev.multi_processor_count, datetime.date.today().isoformat()))
     print("wrote %s (%d entries)" % (args.out, len(tuning.entries())))
 

@@ -4,12 +4,13 @@ The library's autotuner fills the table on the first run of each shape; a
 table measured earlier can be loaded instead, so runs of known shapes start
 without tuning launches.  The text format has one entry per line:
 
-    kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8 us_resident
+    kv_pad ks_pad m_pad op schedule us_columns us_rowsplit us_columns8 us_resident us_panel
 
 sizes padded to multiples of 64 (m_pad 0: the grouped launch's per-workgroup
 tile times), ``op`` one of f64 / f32 / bf16 / fp8, ``schedule`` one of
-columns / rowsplit / columns8 / resident, times in microseconds per step
-(negative: not applicable; a line without the last time has none).  ``#`` starts a comment.
+columns / rowsplit / columns8 / resident / panel, times in microseconds per step
+(negative: not applicable; lines of earlier formats, without the resident
+or panel times, have none).  ``#`` starts a comment.
 
 ``load_default()`` loads the table shipped beside this module
 (``tune_mi355x.txt``, written by ``python -m paper_2009_11742_amd.tune``) or
@@ -21,7 +22,7 @@ import os
 
 from . import _lib
 
-SCHEDULES = ("columns", "rowsplit", "columns8", "resident")
+SCHEDULES = ("columns", "rowsplit", "columns8", "resident", "panel")
 OPS = ("f64", "f32", "bf16", "fp8")
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_mi355x.txt")
 _loaded_default = False
@@ -74,8 +75,8 @@ def load(path):
             if not line:
                 continue
             p = line.split()
-            if len(p) not in (4 + _lib.ROM_NSCHEDULES, 5 + _lib.ROM_NSCHEDULES):
-                raise ValueError("%s:%d: expected %d fields" % (path, ln, 5 + _lib.ROM_NSCHEDULES))
+            if not 8 <= len(p) <= 5 + _lib.ROM_NSCHEDULES:
+                raise ValueError("%s:%d: expected 8 to %d fields" % (path, ln, 5 + _lib.ROM_NSCHEDULES))
             us = [float(u) for u in p[5:]]
             us += [-1.0] * (_lib.ROM_NSCHEDULES - len(us))
             put(int(p[0]), int(p[1]), int(p[2]), p[3], p[4], us)

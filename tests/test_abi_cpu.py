@@ -70,7 +70,9 @@ def test_create_rejects_bad_arguments():
     assert _create(_lib.RomConfig(8, 8, 0.0, _lib.ROM_F32, _lib.ROM_F32, 0), A, B, b)[0] == _lib.ROM_E_ARG
     assert _create(_lib.RomConfig(8, 8, float("nan"), _lib.ROM_F32, _lib.ROM_F32, 0), A, B, b)[0] == _lib.ROM_E_ARG
     assert _create(_lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_BF16, 0), A, B, b)[0] == _lib.ROM_E_ARG
-    assert _create(_lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_F32, 0x80), A, B, b)[0] == _lib.ROM_E_ARG
+    assert _create(_lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_F32, 0x100), A, B, b)[0] == _lib.ROM_E_ARG
+    two = _lib.ROM_SCHED_PANEL | _lib.ROM_SCHED_COLUMNS                   # at most one schedule flag
+    assert _create(_lib.RomConfig(8, 8, dt, _lib.ROM_F32, _lib.ROM_F32, two), A, B, b)[0] == _lib.ROM_E_ARG
     assert "rom_create" in _lib.load().rom_last_error().decode()
 
 
@@ -129,7 +131,7 @@ def test_create_rejects_state_bf16_without_lowp_operators():
         cfg = _lib.RomConfig(8, 8, dt, op, st, _lib.ROM_STATE_BF16)
         assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
         assert "ROM_STATE_BF16" in _lib.load().rom_last_error().decode()
-    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_BF16, _lib.ROM_F32, 128)    # unknown bit
+    cfg = _lib.RomConfig(8, 8, dt, _lib.ROM_BF16, _lib.ROM_F32, 256)    # unknown bit
     assert _create(cfg, A, B, b)[0] == _lib.ROM_E_ARG
 
 
@@ -149,15 +151,16 @@ def test_tune_table_put_get_clear_and_file_round_trip(tmp_path):
         tuning.put(256, 256, 256, "f32", "resident", [4.9, 18.5, 5.5, 1.2])  # replaces
         e = tuning.entries()
         assert [(d["kv_pad"], d["m_pad"]) for d in e] == [(256, 256), (512, 1024), (768, 0), (1024, 1024)]
-        assert e[0]["schedule"] == "resident" and e[0]["us"] == pytest.approx([4.9, 18.5, 5.5, 1.2])
-        assert e[2]["us"] == pytest.approx([40.0, -1.0, 45.0, -1.0])
+        assert e[0]["schedule"] == "resident" and e[0]["us"] == pytest.approx([4.9, 18.5, 5.5, 1.2, -1.0])
+        assert e[2]["us"] == pytest.approx([40.0, -1.0, 45.0, -1.0, -1.0])
         assert e[3]["op"] == "bf16" and e[3]["schedule"] == "rowsplit"
         bad = [(100, 256, 64, "f32", "columns"), (256, 256, 65, "f32", "columns"),
-               (256, 256, 0, "f32", "rowsplit"), (256, 256, 0, "f32", "resident"), (0, 256, 64, "f32", "columns")]
+               (256, 256, 0, "f32", "rowsplit"), (256, 256, 0, "f32", "resident"), (256, 256, 0, "f32", "panel"),
+               (0, 256, 64, "f32", "columns")]
         for kv, ks, m, op, sc in bad:
             with pytest.raises(_lib.RomError):
                 tuning.put(kv, ks, m, op, sc, [1.0, 1.0, 1.0, 1.0])
-        ent = _lib.RomTuneEntry(256, 256, 64, _lib.ROM_F32, 4)
+        ent = _lib.RomTuneEntry(256, 256, 64, _lib.ROM_F32, _lib.ROM_NSCHEDULES)
         assert lib.rom_tune_put(ent) == _lib.ROM_E_ARG
         assert lib.rom_tune_get(99, _lib.RomTuneEntry()) == _lib.ROM_E_ARG
         p = tmp_path / "table.txt"
@@ -167,11 +170,14 @@ def test_tune_table_put_get_clear_and_file_round_trip(tmp_path):
         tuning.clear()
         assert tuning.load(str(p)) == 4
         assert tuning.entries() == e
-        # a line of the earlier format (no resident time) still loads
-        p.write_text("256 256 64 f32 columns 1.0 2.0 3.0\n")
+        # lines of the earlier formats (no resident or panel time) still load
+        p.write_text("256 256 64 f32 columns 1.0 2.0 3.0\n512 512 64 f32 rowsplit 4.0 2.0 5.0 -1.0\n")
         tuning.clear()
-        assert tuning.load(str(p)) == 1
-        assert tuning.entries()[0]["us"] == pytest.approx([1.0, 2.0, 3.0, -1.0])
+        assert tuning.load(str(p)) == 2
+        assert tuning.entries()[0]["us"] == pytest.approx([1.0, 2.0, 3.0, -1.0, -1.0])
+        assert tuning.entries()[1]["us"] == pytest.approx([4.0, 2.0, 5.0, -1.0, -1.0])
+        tuning.put(2048, 2048, 1024, "f32", "panel", [286.0, -1.0, 400.0, -1.0, 198.0])
+        assert tuning.entries()[-1]["schedule"] == "panel"
         p.write_text("256 256 64 f32 columns 1.0\n")
         with pytest.raises(ValueError):
             tuning.load(str(p))

@@ -237,7 +237,7 @@ def test_rowsplit_f32_k1024_m1024_sampled():
     assert e <= F32_BAR and eJ <= F32_BAR
 
 
-@pytest.mark.parametrize("K,M,ops", [(1024, 1024, "f32"), (256, 256, "f32"), (512, 512, "bf16")])
+@pytest.mark.parametrize("K,M,ops", [(1024, 1024, "f32"), (256, 256, "f32"), (512, 512, "bf16"), (2048, 1024, "f32")])
 def test_schedule_autotuner(K, M, ops):
     """Without a schedule flag the first run of a shape times every schedule
     that applies and keeps the fastest (or takes the table's entry); the run
@@ -255,7 +255,12 @@ def test_schedule_autotuner(K, M, ops):
     print("autotuner K=%d M=%d %s: %s -> %s" % (K, M, ops, t, chosen))
     timed = {k: v for k, v in t.items() if v is not None}
     assert chosen == min(timed, key=timed.get)
-    assert (t["columns8"] is None) == (ops != "f32")
+    if K <= 1024:                  # the 8-column blocks' states fit in LDS
+        assert (t["columns8"] is None) == (ops != "f32")
+    if (K, M) == (2048, 1024):
+        # beyond one row-split launch: column blocks against the panel
+        # schedule, both timed
+        assert t["rowsplit"] is None and t["panel"] is not None and t["columns"] is not None
     A, B, _ = rom.operators()
     col = M // 3
     r = oracle.run_rank2(A, B, inst["b"], inst["dt"], inst["mu"][col:col + 1], N)
@@ -279,7 +284,8 @@ def test_online_tuning_and_table_entries_steer_the_schedule():
         rom.run_rank2(mu, V, S, N)
         rom.check()
         e = [d for d in tuning.entries() if d["m_pad"] == 128]
-        assert len(e) == 1 and all(u > 0 for u in e[0]["us"]), e
+        # every schedule timed but the panel one, not weighed below Kv_pad + Ks_pad = 2048
+        assert len(e) == 1 and all(u > 0 for u in e[0]["us"][:4]) and e[0]["us"][4] < 0, e
         ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
         outs = {}
         for sched in ("rowsplit", "columns8", "columns"):
