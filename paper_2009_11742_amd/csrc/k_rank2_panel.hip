@@ -59,6 +59,8 @@ struct PanelArgs {
     double *yp;                    // probe partials [rows / 128][Mq]
     const double *yp_in;           // stress launch: partials of the velocity half-step
     double *J, *y;                 // stress launch: J (M, +=) and trace row, or null
+    double *part;                  // split launches: FP64 partial products [nsplit][Mq][rows]
+    int nsplit;                    // k-range splits (1: products and update in one launch)
     int rows, kd, kreal, M, Mq;    // kreal: unpadded rows of this field (b, c guards)
     int64_t n;                     // step index (forcing at t_n = n dt)
     double dt;
@@ -77,29 +79,46 @@ __device__ __forceinline__ bool panel_tile(int bid, int ntr, int ntc, int &rt, i
     return true;
 }
 
-template <bool FORCED>
+// Stress launches (the update's or the finishing one): the probe of the
+// velocity half-step just completed, for the tile's columns: the FP64 sum
+// of the row-tile partials in tile order, J += dt y^2 and the trace entry.
+__device__ __forceinline__ void probe_reduce(const PanelArgs &a, int col0, int nrt, int tid) {
+    if (a.yp_in != nullptr && tid < kPN) {
+        const int m = col0 + tid;
+        if (m < a.M) {
+            double yv = 0.0;
+            for (int t = 0; t < nrt; ++t) yv += a.yp_in[(size_t)t * a.Mq + m];
+            if (a.J) a.J[m] += a.dt * (yv * yv);
+            if (a.y) a.y[m] = yv;
+        }
+    }
+}
+
+// SPLIT: workgroup (tile, s) sums the s-th of nsplit k-ranges and writes
+// its FP64 partials; panel_finish_kernel then does the update.
+template <bool FORCED, bool SPLIT>
 __global__ __launch_bounds__(kPThreads) void rank2_panel_kernel(PanelArgs a) {
     __shared__ __align__(16) float As[2][kPM * kPLd];
     __shared__ __align__(16) float Xs[2][kPN * kPLd];
     __shared__ double ysum[4][kPN];
 
-    int rt, ct;
-    if (!panel_tile(blockIdx.x, a.rows / kPM, a.Mq / kPN, rt, ct)) return;
+    int rt, ct, ks = 0;
+    if constexpr (SPLIT) {
+        // (row tile, split) pairs count as rows of the tile order: the
+        // column tiles of one operator segment share an XCD
+        int rs;
+        if (!panel_tile(blockIdx.x, a.rows / kPM * a.nsplit, a.Mq / kPN, rs, ct)) return;
+        rt = rs / a.nsplit;
+        ks = rs % a.nsplit;
+    } else {
+        if (!panel_tile(blockIdx.x, a.rows / kPM, a.Mq / kPN, rt, ct)) return;
+    }
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row0 = rt * kPM, col0 = ct * kPN;
 
-    // stress launch: the probe of the velocity half-step just completed
-    if constexpr (!FORCED) {
-        if (a.yp_in != nullptr && rt == 0 && tid < kPN) {
-            const int m = col0 + tid;
-            if (m < a.M) {
-                double yv = 0.0;
-                for (int t = 0; t < a.kd / kPM; ++t) yv += a.yp_in[(size_t)t * a.Mq + m];
-                if (a.J) a.J[m] += a.dt * (yv * yv);
-                if (a.y) a.y[m] = yv;
-            }
-        }
+    if constexpr (!FORCED && !SPLIT) {
+        if (rt == 0) probe_reduce(a, col0, a.kd / kPM, tid);
     }
 
     // staging: chunk k0 of the operator rows (4 float4 per thread) and of
@@ -145,7 +164,12 @@ __global__ __launch_bounds__(kPThreads) void rank2_panel_kernel(PanelArgs a) {
 
     // fragments: lane l reads terms 8 (l / 16) .. + 7 of row / column l % 16
     const int fr = l & 15, fk = (l >> 4) * 8;
-    const int nch = a.kd / kPK;
+    // this workgroup's chunks: [c0, c0 + nch) of the kd / 32
+    const int nall = a.kd / kPK;
+    const int c0 = SPLIT ? ks * nall / a.nsplit : 0;
+    const int nch = SPLIT ? (ks + 1) * nall / a.nsplit - c0 : nall;
+    Ag += (size_t)c0 * kPK;
+    Xg += (size_t)c0 * kPK;
     fetch(0);
     stage(0);
     __syncthreads();
@@ -179,6 +203,21 @@ __global__ __launch_bounds__(kPThreads) void rank2_panel_kernel(PanelArgs a) {
         __syncthreads();
     }
     if (nch & 1) fold();
+
+    if constexpr (SPLIT) {
+        // FP64 partials of 4 consecutive rows per (rb, cb)
+        double *pp = a.part + (size_t)ks * a.Mq * a.rows;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const int m = col0 + 16 * cb + fr, r = row0 + 32 * w + 16 * rb + 4 * (l >> 4);
+                double2 *d = reinterpret_cast<double2 *>(pp + (size_t)m * a.rows + r);
+                d[0] = double2{acc64[rb][cb][0], acc64[rb][cb][1]};
+                d[1] = double2{acc64[rb][cb][2], acc64[rb][cb][3]};
+            }
+        return;
+    }
 
     // ---- epilogue: compensated update of 4 consecutive rows per (rb, cb)
     const double dt = a.dt;
@@ -235,6 +274,66 @@ __global__ __launch_bounds__(kPThreads) void rank2_panel_kernel(PanelArgs a) {
     }
 }
 
+// Update of a split half-step: as the one-launch epilogue, with P the sum
+// of the nsplit FP64 partials in split order.  Workgroup b takes 8 columns
+// (8 (b % 8) .. of tile b / 8) of the tile's 128 rows; thread t rows
+// 4 (t % 32) .. + 3 of column t / 32 (each half-wave one column: coalesced
+// 16-byte accesses and a half-wave sum for the probe).  Eight workgroups
+// per tile, so a launch with few tiles still spreads its partial reads over
+// the chip.
+template <bool FORCED>
+__global__ __launch_bounds__(kPThreads) void panel_finish_kernel(PanelArgs a) {
+    const int ntc = a.Mq / kPN, tile = blockIdx.x / 8, jb = blockIdx.x % 8;
+    const int rt = tile / ntc, ct = tile % ntc;
+    const int tid = threadIdx.x, h = tid & 31;
+    const int row0 = rt * kPM, col0 = ct * kPN;
+    if constexpr (!FORCED) {
+        if (rt == 0 && jb == 0) probe_reduce(a, col0, a.kd / kPM, tid);
+    }
+    const double dt = a.dt;
+    const int r = row0 + 4 * h;
+    const size_t plane = (size_t)a.Mq * a.rows;
+    {
+        const int m = col0 + 8 * jb + (tid >> 5);
+        const size_t o = (size_t)m * a.rows + r;
+        double P[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < a.nsplit; ++q) {
+            const double2 *p = reinterpret_cast<const double2 *>(a.part + q * plane + o);
+            const double2 p0 = p[0], p1 = p[1];
+            P[0] += p0.x; P[1] += p0.y; P[2] += p1.x; P[3] += p1.y;
+        }
+        double u = 0.0;
+        if constexpr (FORCED) u = m < a.M ? dev::forcing(a.source, (double)a.n * dt, a.mu[m]) : 0.0;
+        f4 hh = *reinterpret_cast<const f4 *>(a.Yh + o);
+        f4 ll = *reinterpret_cast<const f4 *>(a.Yl + o);
+        double yp = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double inc = P[v];
+            if constexpr (FORCED) {
+                const double br = r + v < a.kreal ? (double)a.b[r + v] : 0.0;
+                inc = fma(br, u, inc);
+            }
+            const double yv = fma(dt, inc, (double)hh[v] + (double)ll[v]);
+            const float hv = (float)yv;
+            hh[v] = hv;
+            ll[v] = (float)(yv - (double)hv);
+            if constexpr (FORCED) {
+                if (a.c != nullptr && r + v < a.kreal) yp += (double)a.c[r + v] * yv;
+            }
+        }
+        *reinterpret_cast<f4 *>(a.Yh + o) = hh;
+        *reinterpret_cast<f4 *>(a.Yl + o) = ll;
+        if constexpr (FORCED) {
+            if (a.c != nullptr) {
+#pragma unroll
+                for (int off = 1; off < 32; off <<= 1) yp += __shfl_xor(yp, off, 64);
+                if (h == 0) a.yp[(size_t)rt * a.Mq + m] = yp;
+            }
+        }
+    }
+}
+
 // Pack a column-major FP32 matrix (rows x cols, ld rows) into the row-major
 // padded panel operator: dst[r * ldd + k] = src[k * rows + r], zero outside.
 __global__ void panel_pack_op_kernel(const float *__restrict__ src, int rows, int cols, int rowsq, int ldd,
@@ -274,12 +373,32 @@ int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); 
 
 int panel_pad(int k) { return round_up(k, kPM); }
 
+namespace {
+
+// k-range splits of a half-step with `rows` output rows and kd terms: below
+// 256 tiles (one workgroup per CU) the product is split until tiles x
+// splits reaches 256, with at least 8 chunks (256 terms) per split and at
+// most 16 splits; a power of two.  (Measured against splitting up to 512
+// work items: 108 against 141 us per step at K = 4096, M = 64, and 194
+// against 206 at K = 2048, M = 1024, which 256 tiles fill unsplit.)
+int panel_splits(int rows, int kd, int Mq) {
+    const int T = rows / kPM * (Mq / kPN);
+    int S = 1;
+    while (S < 16 && S * T < 256 && kd / kPK >= 8 * 2 * S) S *= 2;
+    return S;
+}
+
+}  // namespace
+
 size_t panel_op_bytes(int kv, int ks) { return sizeof(float) * (size_t)panel_pad(kv) * panel_pad(ks); }
 
 size_t panel_ws_bytes(int kv, int ks, int M) {
-    const size_t Mq = (size_t)round_up(M, kPN);
-    return sizeof(float) * 2 * Mq * ((size_t)panel_pad(kv) + panel_pad(ks))   // hi, lo of V and S
-           + sizeof(double) * (size_t)(panel_pad(kv) / kPM) * Mq;             // probe partials
+    const int kvq = panel_pad(kv), ksq = panel_pad(ks), Mq = round_up(M, kPN);
+    const size_t sv = panel_splits(kvq, ksq, Mq), ss = panel_splits(ksq, kvq, Mq);
+    const size_t part = std::max(sv > 1 ? sv * kvq : 0, ss > 1 ? ss * ksq : 0) * (size_t)Mq;
+    return sizeof(float) * 2 * (size_t)Mq * ((size_t)kvq + ksq)       // hi, lo of V and S
+           + sizeof(double) * (size_t)(kvq / kPM) * Mq                 // probe partials
+           + sizeof(double) * part;                                    // split partial products
 }
 
 hipError_t launch_panel_pack(const float *avs_cm, const float *asv_cm, int kv, int ks, float *avs_rm,
@@ -304,6 +423,7 @@ hipError_t launch_rank2_panel(const float *avs_rm, const float *asv_rm, const Ra
     float *Sh = Vl + (size_t)kvq * Mq;
     float *Sl = Sh + (size_t)ksq * Mq;
     double *yp = reinterpret_cast<double *>(Sl + (size_t)ksq * Mq);
+    double *part = yp + (size_t)(kvq / kPM) * Mq;
     hipError_t e;
     hipLaunchKernelGGL(panel_state_in_kernel, dim3(grid_for((int64_t)kvq * Mq)), dim3(256), 0, st,
                        static_cast<const float *>(r2.V), r2.kv, r2.M, kvq, Mq, Vh, Vl);
@@ -321,13 +441,28 @@ hipError_t launch_rank2_panel(const float *avs_rm, const float *asv_rm, const Ra
     s.A = asv_rm; s.X = Vh; s.Yh = Sh; s.Yl = Sl;
     s.yp_in = probe ? yp : nullptr; s.J = r2.J;
     s.rows = ksq; s.kd = kvq; s.kreal = r2.ks; s.M = r2.M; s.Mq = Mq; s.dt = r2.dt; s.source = r2.source;
-    const int gv = 8 * ((kvq / kPM * (Mq / kPN) + 7) / 8), gs = 8 * ((ksq / kPM * (Mq / kPN) + 7) / 8);
+    v.part = s.part = part;
+    v.nsplit = panel_splits(kvq, ksq, Mq);
+    s.nsplit = panel_splits(ksq, kvq, Mq);
+    // launch grids: 8 ceil(items / 8) (panel_tile deals items to XCDs)
+    auto grid = [](int items) { return dim3(8 * ((items + 7) / 8)); };
+    const int tv = kvq / kPM * (Mq / kPN), ts = ksq / kPM * (Mq / kPN);
     for (int64_t k = 0; k < r2.nsteps; ++k) {
         v.n = r2.n0 + k;
-        hipLaunchKernelGGL(rank2_panel_kernel<true>, dim3(gv), dim3(kPThreads), 0, st, v);
+        if (v.nsplit == 1) {
+            hipLaunchKernelGGL((rank2_panel_kernel<true, false>), grid(tv), dim3(kPThreads), 0, st, v);
+        } else {
+            hipLaunchKernelGGL((rank2_panel_kernel<true, true>), grid(tv * v.nsplit), dim3(kPThreads), 0, st, v);
+            hipLaunchKernelGGL(panel_finish_kernel<true>, dim3(8 * tv), dim3(kPThreads), 0, st, v);
+        }
         s.n = r2.n0 + k;
         s.y = r2.y ? r2.y + (size_t)k * r2.M : nullptr;
-        hipLaunchKernelGGL(rank2_panel_kernel<false>, dim3(gs), dim3(kPThreads), 0, st, s);
+        if (s.nsplit == 1) {
+            hipLaunchKernelGGL((rank2_panel_kernel<false, false>), grid(ts), dim3(kPThreads), 0, st, s);
+        } else {
+            hipLaunchKernelGGL((rank2_panel_kernel<false, true>), grid(ts * s.nsplit), dim3(kPThreads), 0, st, s);
+            hipLaunchKernelGGL(panel_finish_kernel<false>, dim3(8 * ts), dim3(kPThreads), 0, st, s);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(panel_state_out_kernel, dim3(grid_for((int64_t)r2.kv * r2.M)), dim3(256), 0, st, Vh, Vl,
