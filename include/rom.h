@@ -115,13 +115,17 @@ enum {
                                the operator-resident kernel (one sample per
                                workgroup, all of Avs in its registers); else
                                4-column blocks                                */
-    ROM_SCHED_PANEL = 128u, /* FP32 operators and states: the panel
-                               schedule (one tiled matrix-product launch
-                               per half-step, nothing resident between
-                               them), which runs of any Kv, Ks take anyway
-                               where the column blocks' states do not fit
-                               in LDS (Kv_pad + Ks_pad > 4096); ignored
-                               with other operator or state types          */
+    ROM_SCHED_PANEL = 128u, /* FP32 operators and states, or FP64 states:
+                               the panel schedule (one tiled matrix-product
+                               launch per half-step, nothing resident
+                               between them), which runs of any Kv, Ks take
+                               anyway where the column blocks' states do
+                               not fit in LDS (FP32: Kv_pad + Ks_pad >
+                               4096) and FP64 runs from Kv_pad + Ks_pad >=
+                               768 (ROM_SCHED_COLUMNS keeps FP64 runs on
+                               the vector-ALU column blocks where they fit);
+                               ignored with BF16 / FP8 operators and FP32
+                               states                                       */
     ROM_STATE_BF16 = 32u    /* BF16 / F8E4M3 operators with F32 states: the
                                state operand of every product is bf16(x)
                                alone (one MFMA pass, about 8 significant
@@ -254,7 +258,8 @@ rom_status rom_destroy(rom_ctx *ctx);
  * ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8 fixes the instance's tile.
  *
  * rom_last_schedule: the schedule of the context's last FP32-state rank-2
- * run; -1 if none.  rom_schedule_times: the table's per-step times
+ * run, ROM_SCHEDULE_PANEL after an FP64-state run on the panel schedule;
+ * -1 if none (or after an FP64-state run on the vector-ALU kernel).  rom_schedule_times: the table's per-step times
  * (microseconds) of each schedule for the context's shape at M samples,
  * negative where a schedule does not apply; ROM_E_ARG if that shape is not
  * in the table.
@@ -388,9 +393,10 @@ rom_status rom_run_rank1_batch(rom_ctx *ctx, int32_t M, const double *mu, int64_
  * kernel keeps a compensation term per entry during the run (two-term
  * state) and rounds once when writing back, so splitting a run in two
  * differs from the whole run by at most a rounding of the state.
- * Sizes: FP32 operators and states run at any Kv, Ks (above Kv_pad + Ks_pad
- * = 4096 on the panel schedule); BF16 / FP8 operators and FP64 states
- * within their kernels' LDS limits (ROM_E_UNSUPPORTED above).
+ * Sizes: FP32 operators and states, and FP64 states, run at any Kv, Ks
+ * (the panel schedule where the LDS-resident kernels stop); BF16 / FP8
+ * operators with FP32 states within their kernels' LDS limits
+ * (ROM_E_UNSUPPORTED above).
  * Errors: ROM_E_ARG, ROM_E_UNSUPPORTED, ROM_E_NOMEM (panel workspace),
  * ROM_E_DEVICE, ROM_E_TIMEOUT.
  */

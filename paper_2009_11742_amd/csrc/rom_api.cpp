@@ -227,25 +227,27 @@ bool stream_capturing(hipStream_t st);
 // capture only once its workspace covers the run.
 bool panel_candidate(const rom_ctx *ctx, int M, bool capturing) {
     if (ctx->op_type != ROM_F32 || ctx->state_type != ROM_F32 || ctx->kvp + ctx->ksp < 2048) return false;
-    return !capturing || (ctx->avs_rm && ctx->pn_ws_bytes >= rom::panel_ws_bytes(ctx->kv, ctx->ks, M));
+    return !capturing || (ctx->avs_rm && ctx->pn_ws_bytes >= rom::panel_ws_bytes(ctx->kv, ctx->ks, M, false));
 }
 
+// FP32 operators and states, or FP64 states (the operators as the FP64
+// path uses them).
 rom_status run_panel(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st) {
     const bool capturing = stream_capturing(st);
-    const size_t need = rom::panel_ws_bytes(ctx->kv, ctx->ks, a.M);
+    const bool f64 = ctx->state_type == ROM_F64;
+    const size_t need = rom::panel_ws_bytes(ctx->kv, ctx->ks, a.M, f64);
     if (!ctx->avs_rm || ctx->pn_ws_bytes < need) {
         if (capturing)
             return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: the panel schedule allocates its workspace on first use; "
                                            "run it once outside graph capture with at least this many samples");
         hipError_t e = hipSuccess;
         if (!ctx->avs_rm) {
-            const size_t ob = rom::panel_op_bytes(ctx->kv, ctx->ks);
+            const size_t ob = rom::panel_op_bytes(ctx->kv, ctx->ks, f64);
             e = hipMalloc(&ctx->avs_rm, ob);
             if (e == hipSuccess) e = hipMalloc(&ctx->asv_rm, ob);
             if (e == hipSuccess)
-                e = rom::launch_panel_pack(static_cast<const float *>(ctx->avs_cm), static_cast<const float *>(ctx->asv_cm),
-                                           ctx->kv, ctx->ks, static_cast<float *>(ctx->avs_rm),
-                                           static_cast<float *>(ctx->asv_rm), st);
+                e = rom::launch_panel_pack(ctx->avs_cm, ctx->asv_cm, ctx->kv, ctx->ks, f64, ctx->avs_rm, ctx->asv_rm,
+                                           st);
             if (e != hipSuccess) {
                 hfree(ctx->avs_rm); hfree(ctx->asv_rm);
                 ctx->avs_rm = ctx->asv_rm = nullptr;
@@ -268,8 +270,7 @@ rom_status run_panel(rom_ctx *ctx, const rom::Rank2Args &a, hipStream_t st) {
             ctx->pn_ws_bytes = need;
         }
     }
-    hipError_t e = rom::launch_rank2_panel(static_cast<const float *>(ctx->avs_rm),
-                                           static_cast<const float *>(ctx->asv_rm), a, ctx->pn_ws, st);
+    hipError_t e = rom::launch_rank2_panel(ctx->avs_rm, ctx->asv_rm, a, f64, ctx->pn_ws, st);
     if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: panel launch");
     ctx->last_schedule = ROM_SCHEDULE_PANEL;
     return ROM_OK;
@@ -973,10 +974,17 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         ctx->last_schedule = sched;
         return launch_fp32_state_run(ctx, a, sched, G, st);
     } else {
-        if (rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) > 150 * 1024)
-            return fail(ROM_E_UNSUPPORTED, "rom_run_rank2: FP64 states above the LDS-resident limit");
+        // FP64 states: the vector-ALU column blocks (pinned by
+        // ROM_SCHED_COLUMNS), else the panel schedule on the FP64 matrix
+        // cores where pinned, from Kv_pad + Ks_pad >= kPanelF64From, or where
+        // the column blocks' states do not fit in LDS (any size)
+        const bool fits = rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) <= 150 * 1024;
+        if (!fits || (ctx->flags & ROM_SCHED_PANEL) ||
+            (!(ctx->flags & ROM_SCHED_COLUMNS) && ctx->kvp + ctx->ksp >= rom::kPanelF64From))
+            return run_panel(ctx, a, st);
         a.avs = ctx->avs_cm; a.asv = ctx->asv_cm;
         e = rom::launch_rank2_valu<double>(a, st);
+        ctx->last_schedule = -1;
     }
     if (e != hipSuccess) return hip_fail(e, "rom_run_rank2: launch");
     return ROM_OK;

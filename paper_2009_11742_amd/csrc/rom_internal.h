@@ -141,15 +141,19 @@ struct Rank2Args {
 // Operator-resident kernel (skew pairs, FP32): whether padded sizes fit it,
 // the bytes of its operator pack, the pack from a column-major FP32 Avs, and
 // the run (a.avs = the pack).
-// Panel schedule (FP32 operators and states, any Kv, Ks): one tiled MFMA
-// product launch per half-step.  Sizes padded to 128; operator copies of
-// panel_op_bytes each; run workspace of panel_ws_bytes.
+// Panel schedule (FP32 operators and states, or FP64 states; any Kv, Ks):
+// one tiled MFMA product launch per half-step.  Sizes padded to 128;
+// operator copies of panel_op_bytes each; run workspace of panel_ws_bytes.
 int panel_pad(int k);
-size_t panel_op_bytes(int kv, int ks);
-size_t panel_ws_bytes(int kv, int ks, int M);
-hipError_t launch_panel_pack(const float *avs_cm, const float *asv_cm, int kv, int ks, float *avs_rm,
-                             float *asv_rm, hipStream_t st);
-hipError_t launch_rank2_panel(const float *avs_rm, const float *asv_rm, const Rank2Args &a, void *ws,
+// FP64 states take the panel schedule from Kv_pad + Ks_pad = kPanelF64From
+// (measured against the vector-ALU column blocks, us per step at M = 256:
+// K = 256 56.7 / 57.7, K = 384 171 / 79, K = 1024 1971 / 69)
+constexpr int kPanelF64From = 768;
+size_t panel_op_bytes(int kv, int ks, bool f64);
+size_t panel_ws_bytes(int kv, int ks, int M, bool f64);
+hipError_t launch_panel_pack(const void *avs_cm, const void *asv_cm, int kv, int ks, bool f64, void *avs_rm,
+                             void *asv_rm, hipStream_t st);
+hipError_t launch_rank2_panel(const void *avs_rm, const void *asv_rm, const Rank2Args &a, bool f64, void *ws,
                               hipStream_t st);
 
 bool rank2_resident_applies(int kvp, int ksp);

@@ -1,5 +1,6 @@
 """Edge cases of the GPU path: the largest LDS-resident FP32 state
-(Kv_pad + Ks_pad = 4096), the first size past it (ROM_E_UNSUPPORTED), the
+(Kv_pad + Ks_pad = 4096), the first size past it (the panel schedule with
+FP32 operators, ROM_E_UNSUPPORTED with BF16 ones), the
 8-column flag where 8 samples' state does not fit (falls back to 4), a
 single sample on every FP32 schedule, a one-step adjoint and a stride >= N
 adjoint, and a grouped run of one instance with one sample.  Bars as
@@ -48,15 +49,23 @@ def test_largest_lds_resident_state(kv, ks, M):
     assert np.max(np.abs(g["J"] - r["J"]) / r["J"]) <= 1e-5
 
 
-def test_past_the_lds_limit_is_unsupported():
+def test_past_the_lds_limit_takes_the_panel_schedule():
+    """FP32 runs past the column blocks' LDS limit (Kv_pad + Ks_pad > 4096)
+    run on the panel schedule; BF16 operators there are refused before
+    anything is written."""
     from paper_2009_11742_amd import Rom, RomError
     from paper_2009_11742_amd import _lib
     inst = synth.round_to(synth.make_instance(2049, 2048, 2, seed=1, skew=False), "f32")
-    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
+    N = 5
+    g = _run(inst, N, schedule="auto")
+    assert g["schedule"] == "panel"
+    r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"])
+    assert max(_relcol(g["V"], r["V"]), _relcol(g["S"], r["S"])) <= 1e-5
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", ops="bf16")
     mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
     V, S = rom.zeros(2)
     with pytest.raises(RomError) as ei:
-        rom.run_rank2(mu, V, S, 5)
+        rom.run_rank2(mu, V, S, N)
     assert ei.value.status == _lib.ROM_E_UNSUPPORTED
     assert torch.count_nonzero(V) == 0 and torch.count_nonzero(S) == 0     # nothing written
     rom.close()

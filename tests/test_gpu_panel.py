@@ -13,7 +13,13 @@ rectangular Kv != Ks pair above the limit (sampled columns).  Structural
 checks: a permutation of the samples permutes the results bitwise, a run
 split in two equals the whole run to a rounding of the state, graph replays
 equal the eager run bitwise, and a first run under capture is refused.
+
+FP64 states take the same schedule on the FP64 matrix cores (from
+Kv_pad + Ks_pad >= 768, or pinned): parity against the FP64 oracle at the
+FP64 bar (1e-12), pinned and automatic, split and unsplit, and agreement
+with the vector-ALU column blocks.
 """
+BAR64 = 1e-12
 import numpy as np
 import pytest
 
@@ -30,14 +36,14 @@ def _relcol(X, R):
     return float(np.max(np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)))
 
 
-def _run(inst, N, mu_np=None, schedule="panel", trace=True, n_split=None):
+def _run(inst, N, mu_np=None, schedule="panel", trace=True, n_split=None, state="f32"):
     from paper_2009_11742_amd import Rom
-    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32", schedule=schedule)
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state=state, schedule=schedule)
     mu_np = inst["mu"] if mu_np is None else mu_np
     M = len(mu_np)
     mu = torch.tensor(mu_np, dtype=torch.float64, device="cuda")
     V, S = rom.zeros(M)
-    c = torch.tensor(inst["c"], dtype=torch.float32, device="cuda")
+    c = torch.tensor(inst["c"], dtype=torch.float32 if state == "f32" else torch.float64, device="cuda")
     J = torch.zeros(M, dtype=torch.float64, device="cuda")
     y = torch.zeros((N, M), dtype=torch.float64, device="cuda") if trace else None
     if n_split is None:
@@ -159,3 +165,43 @@ def test_panel_graph_replay_bitwise_and_first_run_not_captured():
         rom.run_rank2(mu, V, S, 3, c=c, J=J)
         torch.cuda.synchronize()
     rom.close()
+
+
+@pytest.mark.parametrize("kv,ks,M,N,skew", [(256, 256, 100, 400, True), (200, 330, 70, 300, False),
+                                            (130, 70, 3, 300, False)])
+def test_panel_f64_parity_pinned(kv, ks, M, N, skew):
+    inst = synth.make_instance(kv, ks, M, seed=kv + 5 * ks + M, skew=skew)
+    g = _run(inst, N, state="f64")
+    assert g["sched"] == "panel"
+    ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"],
+                           trace=True)
+    e = _errors(g, ref)
+    print("panel f64 K=(%d,%d) M=%d N=%d: V %.2e S %.2e J %.2e y %.2e" % ((kv, ks, M, N) + e))
+    assert max(e) <= BAR64
+
+
+@pytest.mark.parametrize("kv,ks,M,N,cols", [(512, 512, 300, 200, [0, 150, 299]),
+                                            (2304, 2304, 96, 60, [0, 33, 95])])
+def test_panel_f64_auto_sampled(kv, ks, M, N, cols):
+    """FP64 runs from Kv_pad + Ks_pad = 768 take the panel schedule
+    unasked (K = 2304, M = 96: 8 k-range splits)."""
+    inst = synth.make_instance(kv, ks, M, seed=kv + M)
+    g = _run(inst, N, schedule="auto", state="f64")
+    assert g["sched"] == "panel"
+    cols = np.array(cols)
+    ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][cols], N, c=inst["c"],
+                           trace=True)
+    e = _errors(g, ref, cols)
+    print("panel f64 K=(%d,%d) M=%d N=%d sampled: V %.2e S %.2e J %.2e y %.2e" % ((kv, ks, M, N) + e))
+    assert max(e) <= BAR64
+
+
+def test_panel_f64_agrees_with_vector_alu_columns():
+    inst = synth.make_instance(384, 384, 40, seed=9)
+    a = _run(inst, 300, state="f64", schedule="panel")
+    b = _run(inst, 300, state="f64", schedule="columns")
+    assert a["sched"] == "panel" and b["sched"] is None
+    for key in ("V", "S"):
+        d = np.linalg.norm(a[key] - b[key], axis=0) / np.linalg.norm(b[key], axis=0)
+        assert float(np.max(d)) <= 1e-13, key
+    assert float(np.max(np.abs(a["J"] - b["J"]) / b["J"])) <= 1e-13
