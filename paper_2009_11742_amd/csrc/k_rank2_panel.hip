@@ -465,16 +465,27 @@ __global__ void panel_state_out_kernel(const T *__restrict__ hi, const float *__
 
 int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); }
 
-// k-range splits of a half-step with `rows` output rows and kd terms: below
-// 256 tiles (one workgroup per CU) the product is split until tiles x
-// splits reaches 256, with at least 256 terms per split and at most 16
-// splits; a power of two.  (Measured against splitting up to 512 work
-// items: 108 against 141 us per step at K = 4096, M = 64, and 194 against
-// 206 at K = 2048, M = 1024, which 256 tiles fill unsplit.)
+// k-range splits of a half-step with `rows` output rows and kd terms, a
+// power of two with at least 256 terms per split.  Below 256 tiles (one
+// workgroup per CU) the product is split until tiles x splits reaches 256,
+// at most 16 ways (measured against splitting up to 512 work items: 108
+// against 141 us per step at K = 4096, M = 64).  From 256 tiles on, S in
+// {1, 2, 4} minimising ceil(T S / 256) / S, the time of the busiest CU
+// when each takes its share of items of 1 / S the work (smaller S on ties):
+// 288 tiles (K = 2304, M = 1024) split 4 ways, 364 -> 283 us per step; 384
+// (K = 3072, M = 1024) 2 ways, 481 -> 410; 256 and 512 stay whole.
 int panel_splits(int rows, int kd, int Mq) {
     const int T = rows / kPM * (Mq / kPN);
     int S = 1;
-    while (S < 16 && S * T < 256 && kd >= 256 * 2 * S) S *= 2;
+    if (T < 256) {
+        while (S < 16 && S * T < 256 && kd >= 256 * 2 * S) S *= 2;
+        return S;
+    }
+    double best = 1e30;
+    for (int s = 1; s <= 4 && kd >= 256 * s; s *= 2) {
+        const double c = (double)((T * s + 255) / 256) / s;
+        if (c < best - 1e-9) { best = c; S = s; }
+    }
     return S;
 }
 
