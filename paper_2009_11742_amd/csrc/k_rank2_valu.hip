@@ -15,6 +15,7 @@ namespace {
 
 constexpr int NB = kColBlock;
 constexpr size_t kLdsBudget = 150 * 1024;
+static_assert(NB * 64 == 256, "one wave of the 256 threads per column (probe sums)");
 
 template <typename T>
 __device__ __forceinline__ T fma_t(T a, T b, T c);
@@ -72,6 +73,9 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
             T acc[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = T(0);
+            // unrolled so several operator loads (from L2 when the operators
+            // are not staged in LDS) are in flight at once
+#pragma unroll 8
             for (int q = 0; q < ks; ++q) {
                 T aq = A[i + (size_t)q * kv];
 #pragma unroll
@@ -85,17 +89,24 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
             }
         }
         __syncthreads();
-        if (cv != nullptr && tid < NB) {
+        if (cv != nullptr) {
+            // probe of column w (one wave per column): lane partials over
+            // rows lane, lane + 64, .., then the wave's tree
             double yv = 0.0;
-            for (int i = 0; i < kv; ++i) yv = fma((double)cv[i], (double)V[tid * kvp + i], yv);
-            Jacc += a.dt * (yv * yv);
-            if (a.y && col0 + tid < a.M) a.y[(size_t)k * a.M + col0 + tid] = yv;
+            for (int i = lane; i < kv; i += 64) yv = fma((double)cv[i], (double)V[w * kvp + i], yv);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) yv += __shfl_xor(yv, off, 64);
+            if (lane == 0) {
+                Jacc += a.dt * (yv * yv);
+                if (a.y && col0 + w < a.M) a.y[(size_t)k * a.M + col0 + w] = yv;
+            }
         }
         // ---- stress half-step
         for (int i = w * 64 + lane; i < ks; i += 256) {
             T acc[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = T(0);
+#pragma unroll 8
             for (int q = 0; q < kv; ++q) {
                 T bq = B[i + (size_t)q * ks];
 #pragma unroll
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
         int j = idx / ksp, i = idx - j * ksp, m = col0 + j;
         if (m < a.M && i < ks) Sout[(size_t)m * ks + i] = S[idx];
     }
-    if (cv != nullptr && a.J && tid < NB && col0 + tid < a.M) a.J[col0 + tid] += Jacc;
+    if (cv != nullptr && a.J && lane == 0 && col0 + w < a.M) a.J[col0 + w] += Jacc;
 }
 
 template <typename T>

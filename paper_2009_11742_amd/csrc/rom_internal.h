@@ -147,7 +147,7 @@ struct Rank2Args {
 int panel_pad(int k);
 // FP64 states take the panel schedule from Kv_pad + Ks_pad = kPanelF64From
 // (measured against the vector-ALU column blocks, us per step at M = 256:
-// K = 256 56.7 / 57.7, K = 384 171 / 79, K = 1024 1971 / 69)
+// K = 256 36.0 / 58.7, K = 384 104 / 80, K = 1024 1971 / 69)
 constexpr int kPanelF64From = 768;
 size_t panel_op_bytes(int kv, int ks, bool f64);
 size_t panel_ws_bytes(int kv, int ks, int M, bool f64);
