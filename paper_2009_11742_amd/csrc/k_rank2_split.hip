@@ -381,9 +381,11 @@ void rank2_split_kernel(SplitArgs a) {
     // B-fragment order: tile row o of column fj is term o % 8 of lane
     // 16 ((o % 32) / 8) + fj % 16 of k-block (row0 + o) / 32, column block
     // fj / 16 (row0 is a multiple of 32)
-    auto publish = [&](int f, unsigned short *x) {
+    // (value i of the thread's RPT rows from `hv`: the LDS tile, or the
+    // finishing loop's registers)
+    auto publish = [&](int f, unsigned short *x, auto hv) {
         constexpr int CH = RPT < 8 ? RPT : 8;      // rows per store
-        const float *h = sth + (f * NC + fj) * kLd + RPT * fs;
+        (void)f;
         unsigned short *xg = x + (size_t)g * NC * 2 * kp;
         const int cb = fj / 16;
 #pragma unroll
@@ -392,7 +394,7 @@ void rank2_split_kernel(SplitArgs a) {
 #pragma unroll
             for (int q = 0; q < CH / 2; ++q) {
                 // hardware round-to-nearest-even, two values per instruction
-                const f2 v = {h[CH * c + 2 * q], h[CH * c + 2 * q + 1]};
+                const f2 v = {hv(CH * c + 2 * q), hv(CH * c + 2 * q + 1)};
                 const bf2 hi = __builtin_convertvector(v, bf2);
                 const f2 r = v - __builtin_convertvector(hi, f2);
                 const bf2 lo = __builtin_convertvector(r, bf2);
@@ -430,6 +432,7 @@ void rank2_split_kernel(SplitArgs a) {
         double ypart = 0.0;
         float *h = sth + (f * NC + fj) * kLd + RPT * fs;
         float *l = stl + (f * NC + fj) * kLd + RPT * fs;
+        float hn[RPT];                             // the new hi words, published below
 #pragma unroll
         for (int q = 0; q < RPT / 4; ++q) {
             f4 p0 = *reinterpret_cast<const f4 *>(part + (0 * NC + fj) * kLd + RPT * fs + 4 * q);
@@ -453,13 +456,18 @@ void rank2_split_kernel(SplitArgs a) {
             }
             *reinterpret_cast<f4 *>(h + 4 * q) = hh;
             *reinterpret_cast<f4 *>(l + 4 * q) = ll;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) hn[4 * q + e] = hh[e];
         }
-        publish(f, xmine);
+        publish(f, xmine, [&](int i) { return hn[i]; });
         return ypart;
     };
 
     // ---- initial exchange: S rows (the first half-step reads S)
-    publish(1, a.xs);
+    {
+        const float *h0 = sth + (1 * NC + fj) * kLd + RPT * fs;
+        publish(1, a.xs, [&](int i) { return h0[i]; });
+    }
     group_barrier(a, cnt, (unsigned)R * ++phase);
 
     double Jacc = 0.0;

@@ -206,3 +206,23 @@ def test_panel_f64_agrees_with_vector_alu_columns():
         d = np.linalg.norm(a[key] - b[key], axis=0) / np.linalg.norm(b[key], axis=0)
         assert float(np.max(d)) <= 1e-13, key
     assert float(np.max(np.abs(a["J"] - b["J"]) / b["J"])) <= 1e-13
+
+
+def test_panel_f64_permutation_split_and_offset():
+    """FP64 panel runs: a sample permutation permutes the results bitwise;
+    a run split at step 91 (the second part with n0 = 91) equals the whole
+    run to FP64 rounding (the FP64 state carries no compensation term, so
+    only the order of the J sums differs)."""
+    inst = synth.make_instance(600, 600, 70, seed=13)        # Kv_pad + Ks_pad = 1280: automatic, 2 splits
+    N = 200
+    whole = _run(inst, N, state="f64", schedule="auto")
+    assert whole["sched"] == "panel"
+    perm = np.random.default_rng(4).permutation(70)
+    p = _run(inst, N, mu_np=inst["mu"][perm], state="f64", schedule="auto")
+    for key in ("V", "S"):
+        assert np.array_equal(p[key], whole[key][:, perm]), key
+    assert np.array_equal(p["J"], whole["J"][perm]) and np.array_equal(p["y"], whole["y"][:, perm])
+    split = _run(inst, N, trace=False, n_split=91, state="f64", schedule="auto")
+    for key in ("V", "S"):
+        assert np.array_equal(split[key], whole[key]), key
+    assert float(np.max(np.abs(split["J"] - whole["J"]) / whole["J"])) <= 1e-14
