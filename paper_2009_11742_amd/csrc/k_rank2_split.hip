@@ -132,24 +132,33 @@ __device__ __forceinline__ void group_barrier(const SplitArgs &a, unsigned *cnt,
     // barrier.
 }
 
-// Sum of the probe partials of one column: the R row tiles' values at
-// p[q * stride], read with device-scope loads (other workgroups wrote them)
-// four at a time, all four in flight before the first is used (entries past
-// R re-read entry R - 1 and are not added; four keep the register pressure
-// of the kernels' time loop where it was), summed in the order q = 0 .. R-1.
+// Probe partials of one column: the R row tiles' values at p[q * stride],
+// read with device-scope loads (other workgroups wrote them), kProbeBatch at
+// a time per thread, all in flight before the first is used (entries past R
+// re-read entry R - 1 and are not added; four keep the register pressure of
+// the kernels' time loop where it was).
 constexpr int kProbeBatch = 4;
-__device__ __forceinline__ double sum_partials(const double *p, int stride, int R) {
+
+// Their sum, spread over the TPC consecutive threads of the column: thread
+// fs reads the partials q = fs, fs + TPC, .. (four at a time, all in flight
+// together: one round trip to L2 for R <= 4 TPC instead of R / 4), sums
+// them in increasing q, and the TPC threads meet in a butterfly; every one
+// of them returns the column's total.  All TPC threads must call it.
+template <int TPC>
+__device__ __forceinline__ double sum_partials_spread(const double *p, int stride, int R, int fs) {
     double y = 0.0;
-    for (int q0 = 0; q0 < R; q0 += kProbeBatch) {
+    for (int q0 = fs; q0 < R; q0 += kProbeBatch * TPC) {
         double v[kProbeBatch];
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q)
-            v[q] = __hip_atomic_load(p + (size_t)min(q0 + q, R - 1) * stride, __ATOMIC_RELAXED,
+            v[q] = __hip_atomic_load(p + (size_t)min(q0 + q * TPC, R - 1) * stride, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q)
-            if (q0 + q < R) y += v[q];
+            if (q0 + q * TPC < R) y += v[q];
     }
+#pragma unroll
+    for (int off = 1; off < TPC; off <<= 1) y += __shfl_xor(y, off, 64);
     return y;
 }
 
@@ -483,11 +492,13 @@ void rank2_split_kernel(SplitArgs a) {
             if (fs == 0) a.yp[((size_t)g * R + r) * NC + fj] = yp;
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
-        if (probe && r == 0 && fs == 0 && fok) {
-            // the R row-tile partials, all loads in flight together
-            const double yv = sum_partials(a.yp + (size_t)g * R * NC + fj, NC, R);
-            Jacc += a.dt * (yv * yv);
-            if (a.y) a.y[(size_t)k * a.M + fm] = yv;
+        if (probe && r == 0 && fok) {
+            // the R row-tile partials, spread over the column's threads
+            const double yv = sum_partials_spread<TPC>(a.yp + (size_t)g * R * NC + fj, NC, R, fs);
+            if (fs == 0) {
+                Jacc += a.dt * (yv * yv);
+                if (a.y) a.y[(size_t)k * a.M + fm] = yv;
+            }
         }
         half_step(1, ops, a.xv, a.xs, nullptr, false);
         group_barrier(a, cnt, (unsigned)R * ++phase);
@@ -850,13 +861,15 @@ __device__ __forceinline__ void split_f32_run(const SplitArgs &a, int g, int r, 
             if (fs == 0) a.yp[((size_t)g * R + r) * NC + fj] = yp;
         }
         group_barrier(a, cnt, (unsigned)R * ++phase);
-        if (probe && r == 0 && fs == 0 && fok) {
-            const double yv = sum_partials(a.yp + (size_t)g * R * NC + fj, NC, R);
-            if constexpr (MODE == kSplitAdjoint) {
-                Jacc += dt * yv * dev::forcing_dmu(src, (double)n * dt, muf);
-            } else {
-                Jacc += dt * (yv * yv);
-                if (a.y) a.y[(size_t)k * M + fm] = yv;
+        if (probe && r == 0 && fok) {
+            const double yv = sum_partials_spread<TPC>(a.yp + (size_t)g * R * NC + fj, NC, R, fs);
+            if (fs == 0) {
+                if constexpr (MODE == kSplitAdjoint) {
+                    Jacc += dt * yv * dev::forcing_dmu(src, (double)n * dt, muf);
+                } else {
+                    Jacc += dt * (yv * yv);
+                    if (a.y) a.y[(size_t)k * M + fm] = yv;
+                }
             }
         }
         half_step(1, opsw, xv, xs, nullptr, false);

@@ -187,8 +187,9 @@ def test_rowsplit_group_width_bitwise(ops, K, Ms):
     the Ms here select the three widths in turn.  A column's state arithmetic does
     not depend on the width, so the shared samples (a prefix of the same mu)
     agree bitwise in V and S; the probe's FP64 row sum is spread over 4 NCB
-    rows per thread and a shuffle tree over 16 / NCB threads, so J and the
-    trace agree to FP64 reassociation (1e-14)."""
+    rows per thread and a shuffle tree over 16 / NCB threads, and so is the
+    sum of the row-tile partials, so J and the trace agree to FP64
+    reassociation (1e-14)."""
     from paper_2009_11742_amd import Rom
     inst = synth.round_to(synth.make_instance(K, K, max(Ms), seed=K + 5), "f32")
     N = 120
