@@ -15,6 +15,7 @@ namespace {
 
 constexpr int NB = kColBlock;
 constexpr size_t kLdsBudget = 150 * 1024;
+constexpr int kUWinV = 256 / NB;        // forcing window: one (step, column) value per thread
 static_assert(NB * 64 == 256, "one wave of the 256 threads per column (probe sums)");
 
 template <typename T>
@@ -24,14 +25,20 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 template <>
 __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return fmaf(a, b, c); }
 
-template <typename T>
+// RPL > 0 (Kv, Ks <= 64 RPL): wave w computes column w, each lane rows
+// lane + 64 r (r < RPL), so all four waves work at small K; RPL = 0: thread
+// (w, lane) computes rows 64 t + lane (t = w, w + 4, ..) of all 4 columns.
+// Both sum each entry's terms in increasing k with the same FMAs, so they
+// agree bitwise.  (Four interleaved FMA chains per entry measured no faster
+// at K = 64 and slower at K = 128.)
+template <typename T, int RPL>
 __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in_lds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int kv = a.kv, ks = a.ks, kvp = a.kvp, ksp = a.ksp;
     T *V = reinterpret_cast<T *>(smem);                // [NB][kvp]
     T *S = V + NB * kvp;                                // [NB][ksp]
-    double *ur = reinterpret_cast<double *>(S + NB * ksp);   // [NB] forcing of this step
-    T *opA = reinterpret_cast<T *>(ur + NB);            // Avs (kv x ks) if staged
+    double *uw = reinterpret_cast<double *>(S + NB * ksp);   // [kUWinV][NB] forcing window
+    T *opA = reinterpret_cast<T *>(uw + kUWinV * NB);   // Avs (kv x ks) if staged
     T *opB = opA + (size_t)kv * ks;                     // Asv (ks x kv) if staged
     const T *gA = static_cast<const T *>(a.avs);
     const T *gB = static_cast<const T *>(a.asv);
@@ -65,11 +72,33 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
     __syncthreads();
 
     for (int64_t k = 0; k < a.nsteps; ++k) {
-        const double t = (double)(a.n0 + k) * a.dt;
-        if (tid < NB) ur[tid] = (col0 + tid < a.M) ? dev::forcing(a.source, t, a.mu[col0 + tid]) : 0.0;
-        __syncthreads();
+        // the forcing of the next kUWinV steps, one value per thread, once
+        // per window (the previous step's last barrier protects the window)
+        if (k % kUWinV == 0) {
+            const int s = tid / NB, j = tid % NB;
+            uw[tid] = (col0 + j < a.M) ? dev::forcing(a.source, (double)(a.n0 + k + s) * a.dt, a.mu[col0 + j]) : 0.0;
+            __syncthreads();
+        }
+        const double *ur = uw + (k % kUWinV) * NB;
         // ---- velocity half-step
-        for (int i = w * 64 + lane; i < kv; i += 256) {
+        if constexpr (RPL > 0) {
+            T acc[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc[r] = T(0);
+#pragma unroll 8
+            for (int q = 0; q < ks; ++q) {
+                const T sq = S[w * ksp + q];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    acc[r] = fma_t<T>(A[min(lane + 64 * r, kv - 1) + (size_t)q * kv], sq, acc[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i < kv) V[w * kvp + i] = V[w * kvp + i] + dt * (acc[r] + bv[i] * (T)ur[w]);
+            }
+        }
+        for (int i = w * 64 + lane; RPL == 0 && i < kv; i += 256) {
             T acc[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = T(0);
@@ -102,7 +131,24 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
             }
         }
         // ---- stress half-step
-        for (int i = w * 64 + lane; i < ks; i += 256) {
+        if constexpr (RPL > 0) {
+            T acc[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc[r] = T(0);
+#pragma unroll 8
+            for (int q = 0; q < kv; ++q) {
+                const T vq = V[w * kvp + q];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    acc[r] = fma_t<T>(B[min(lane + 64 * r, ks - 1) + (size_t)q * ks], vq, acc[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i < ks) S[w * ksp + i] = S[w * ksp + i] + dt * acc[r];
+            }
+        }
+        for (int i = w * 64 + lane; RPL == 0 && i < ks; i += 256) {
             T acc[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = T(0);
@@ -133,7 +179,7 @@ __global__ __launch_bounds__(256) void rank2_valu_kernel(Rank2Args a, int ops_in
 
 template <typename T>
 size_t valu_lds(int kv, int ks, int kvp, int ksp, bool ops) {
-    size_t base = sizeof(T) * (size_t)NB * (kvp + ksp) + sizeof(double) * NB;
+    size_t base = sizeof(T) * (size_t)NB * (kvp + ksp) + sizeof(double) * kUWinV * NB;
     base = (base + 15) / 16 * 16;
     return ops ? base + 2 * sizeof(T) * (size_t)kv * ks : base;
 }
@@ -146,7 +192,13 @@ hipError_t launch_rank2_valu(const Rank2Args &a, hipStream_t st) {
     bool ops = valu_lds<T>(a.kv, a.ks, a.kvp, a.ksp, true) <= kLdsBudget;
     size_t lds = valu_lds<T>(a.kv, a.ks, a.kvp, a.ksp, ops);
     if (lds > kLdsBudget) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rank2_valu_kernel<T>, dim3(blocks), dim3(256), lds, st, a, ops ? 1 : 0);
+    const int kmax = a.kv > a.ks ? a.kv : a.ks;
+    if (kmax <= 64)
+        hipLaunchKernelGGL((rank2_valu_kernel<T, 1>), dim3(blocks), dim3(256), lds, st, a, ops ? 1 : 0);
+    else if (kmax <= 128)
+        hipLaunchKernelGGL((rank2_valu_kernel<T, 2>), dim3(blocks), dim3(256), lds, st, a, ops ? 1 : 0);
+    else
+        hipLaunchKernelGGL((rank2_valu_kernel<T, 0>), dim3(blocks), dim3(256), lds, st, a, ops ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -159,11 +211,14 @@ size_t rank2_valu_lds_bytes(rom_dtype st, int kv, int ks, int kvp, int ksp) {
 }
 
 hipError_t rank2_valu_configure() {
-    hipError_t e = hipFuncSetAttribute((const void *)rank2_valu_kernel<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)rank2_valu_kernel<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *fns[] = {(const void *)rank2_valu_kernel<double, 0>, (const void *)rank2_valu_kernel<double, 1>,
+                         (const void *)rank2_valu_kernel<double, 2>, (const void *)rank2_valu_kernel<float, 0>,
+                         (const void *)rank2_valu_kernel<float, 1>, (const void *)rank2_valu_kernel<float, 2>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rom
