@@ -581,7 +581,10 @@ def workload_scaling(args, torch, dev):
     K = 4096): FP32 rank-2 runs at K in {2048, 3072, 4096} x M in {64, 256,
     1024} on the schedule the autotuner picks (the panel schedule above
     Kv_pad + Ks_pad = 4096), median of 3 timed runs; at M = 1024 the error
-    of one sampled column against the oracle over the timed run length."""
+    of one sampled column against the oracle over the timed run length.
+    Per K the rank-1 formulation as launched work (graphs of two GEMV
+    launches per step, best of 8 / 32 streams) and the rank-2 / rank-1
+    ratio of each point."""
     import oracle
     import synth
     from paper_2009_11742_amd import Rom
@@ -595,6 +598,9 @@ def workload_scaling(args, torch, dev):
         inst = synth.round_to(synth.make_instance(K, K, max(1024, max(Ms)), seed=0), "f32")
         rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f32")
         N = 50 if K <= 2048 else (30 if K <= 3072 else 20)
+        r1 = rank1_rate(torch, rom, inst, N, stream_counts=(8, 32))
+        out.setdefault("rank1", {})[str(K)] = {"value": r1["value"], "streams": r1["streams"],
+                                               "graph_equals_eager": r1["graph_equals_eager"]}
         for M in Ms:
             mu = torch.tensor(inst["mu"][:M], dtype=torch.float64, device=dev)
             V, S = rom.zeros(M, device=dev)
@@ -607,7 +613,8 @@ def workload_scaling(args, torch, dev):
             ksec = float(np.median(ms)) * 1e-3
             tf = 4.0 * K * K * M * N / ksec / 1e12
             pt = {"K": K, "M": M, "nsteps": N, "value": M * N / ksec, "us_per_step": ksec / N * 1e6,
-                  "tflops": tf, "frac": tf / 157.3, "schedule": rom.last_schedule}
+                  "tflops": tf, "frac": tf / 157.3, "schedule": rom.last_schedule,
+                  "rank2_over_rank1": M * N / ksec / r1["value"]}
             if M >= 1024:
                 ci = 517
                 r = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"][ci:ci + 1], N)
