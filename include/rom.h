@@ -123,7 +123,9 @@ enum {
                                not fit in LDS (FP32: Kv_pad + Ks_pad >
                                4096) and FP64 runs from Kv_pad + Ks_pad >=
                                768 (ROM_SCHED_COLUMNS keeps FP64 runs on
-                               the vector-ALU column blocks where they fit);
+                               the vector-ALU column blocks where they fit,
+                               and so does a stream under graph capture
+                               before the panel workspace exists);
                                ignored with BF16 / FP8 operators and FP32
                                states                                       */
     ROM_STATE_BF16 = 32u    /* BF16 / F8E4M3 operators with F32 states: the

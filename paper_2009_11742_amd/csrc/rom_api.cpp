@@ -979,8 +979,13 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         // cores where pinned, from Kv_pad + Ks_pad >= kPanelF64From, or where
         // the column blocks' states do not fit in LDS (any size)
         const bool fits = rom::rank2_valu_lds_bytes(ctx->state_type, ctx->kv, ctx->ks, ctx->kvp, ctx->ksp) <= 150 * 1024;
-        if (!fits || (ctx->flags & ROM_SCHED_PANEL) ||
-            (!(ctx->flags & ROM_SCHED_COLUMNS) && ctx->kvp + ctx->ksp >= rom::kPanelF64From))
+        // a stream being captured cannot allocate the panel workspace: an
+        // unpinned run that fits the column blocks stays on them until an
+        // uncaptured panel run has set the workspace up
+        const bool panel_ready = ctx->avs_rm && ctx->pn_ws_bytes >= rom::panel_ws_bytes(ctx->kv, ctx->ks, M, true);
+        const bool auto_panel = !(ctx->flags & ROM_SCHED_COLUMNS) && ctx->kvp + ctx->ksp >= rom::kPanelF64From &&
+                                (panel_ready || !stream_capturing(st));
+        if (!fits || (ctx->flags & ROM_SCHED_PANEL) || auto_panel)
             return run_panel(ctx, a, st);
         a.avs = ctx->avs_cm; a.asv = ctx->asv_cm;
         e = rom::launch_rank2_valu<double>(a, st);

@@ -226,3 +226,50 @@ def test_panel_f64_permutation_split_and_offset():
     for key in ("V", "S"):
         assert np.array_equal(split[key], whole[key]), key
     assert float(np.max(np.abs(split["J"] - whole["J"]) / whole["J"])) <= 1e-14
+
+
+def test_panel_f64_capture_before_and_after_the_workspace():
+    """An FP64 run that would take the panel schedule, captured into a graph
+    before any panel run of the context, stays on the vector-ALU column
+    blocks (it cannot allocate under capture), bitwise equal to an eager
+    run pinned there; after an eager panel run the captured run takes the
+    panel schedule, bitwise equal to its eager run."""
+    from paper_2009_11742_amd import Rom
+    inst = synth.make_instance(400, 400, 12, seed=14)
+    M, N = 12, 50
+    mu = torch.tensor(inst["mu"], dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+
+    def eager(schedule):
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64", schedule=schedule)
+        V, S = rom.zeros(M)
+        V.fill_(1e-3)
+        rom.run_rank2(mu, V, S, N)
+        torch.cuda.synchronize()
+        out = (V.clone(), S.clone(), rom.last_schedule)
+        rom.close()
+        return out
+
+    ref_cols, ref_panel = eager("columns"), eager("auto")
+    assert ref_cols[2] is None and ref_panel[2] == "panel"
+    rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64")
+    V, S = rom.zeros(M)
+    for want, ref in ((None, ref_cols), ("panel", ref_panel)):
+        g = torch.cuda.CUDAGraph()
+        V.fill_(1e-3); S.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            rom.run_rank2(mu, V, S, N)
+        assert rom.last_schedule == want
+        for rep in range(2):
+            V.fill_(1e-3); S.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(V, ref[0]) and torch.equal(S, ref[1]), (want, rep)
+        if want is None:
+            V.fill_(1e-3); S.zero_()
+            rom.run_rank2(mu, V, S, N)          # eager: sets the panel workspace up
+            torch.cuda.synchronize()
+            assert rom.last_schedule == "panel"
+    rom.close()
