@@ -664,7 +664,8 @@ def workload_forward512(args, torch, dev):
 def workload_plain(args, torch, dev):
     """The plain-method workload: K = 64, M in {1, 8}, 2000 steps, FP64
     states and operators (latency bound: two dependent half-steps per step,
-    no roofline).  Error against the FP64 oracle on every column."""
+    no roofline), and the rank-1 formulation of sample 0 (two GEMV launches
+    per step).  Error against the FP64 oracle on every column."""
     import oracle
     import synth
     from paper_2009_11742_amd import Rom
@@ -683,9 +684,23 @@ def workload_plain(args, torch, dev):
         ksec = float(np.median(ms)) * 1e-3
         ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
         err = max(_err_cols(V.cpu().numpy().T, ref["V"]), _err_cols(S.cpu().numpy().T, ref["S"]))
-        out["runs"]["M%d" % M] = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6,
-                                  "max_rel_err_vs_oracle": err}
+        rec = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "max_rel_err_vs_oracle": err}
+        if M == 1:
+            # the rank-1 formulation of the same sample: two GEMV launches per
+            # step (eager, one stream), error against the oracle likewise
+            v = torch.zeros(64, dtype=torch.float64, device=dev)
+            s = torch.zeros(64, dtype=torch.float64, device=dev)
+
+            def run1():
+                v.zero_(); s.zero_()
+                rom.run_rank1(v, s, float(inst["mu"][0]), N)
+            _, ms1 = _events_time(torch, run1, 5, 1)
+            k1 = float(np.median(ms1)) * 1e-3
+            e1 = max(_err_cols(v.cpu().numpy()[:, None], ref["V"]), _err_cols(s.cpu().numpy()[:, None], ref["S"]))
+            out["rank1"] = {"value": N / k1, "us_per_step": k1 / N * 1e6, "max_rel_err_vs_oracle": e1}
+        out["runs"]["M%d" % M] = rec
         rom.close()
+    out["rank2_M8_over_rank1"] = out["runs"]["M8"]["value"] / out["rank1"]["value"]
     return out
 
 
