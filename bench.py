@@ -664,16 +664,18 @@ def workload_forward512(args, torch, dev):
 def workload_plain(args, torch, dev):
     """The plain-method workload: K = 64, M in {1, 8}, 2000 steps, FP64
     states and operators (latency bound: two dependent half-steps per step,
-    no roofline), and the rank-1 formulation of sample 0 (two GEMV launches
-    per step).  Error against the FP64 oracle on every column."""
+    no roofline; the operator-resident kernel, and at M = 8 also the vector-
+    ALU column blocks for comparison), and the rank-1 formulation of sample 0
+    (two GEMV launches per step).  Error against the FP64 oracle on every
+    column."""
     import oracle
     import synth
     from paper_2009_11742_amd import Rom
     N = 2000
     out = {"workload": "plain: Kv=Ks=64, M in {1, 8}, 2000 steps, FP64", "unit": "sample-steps/s", "runs": {}}
-    for M in (1, 8):
+    for M, sched in ((1, "auto"), (8, "auto"), (8, "columns")):
         inst = synth.make_instance(64, 64, M, seed=0)
-        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64")
+        rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64", schedule=sched)
         mu = torch.tensor(inst["mu"], dtype=torch.float64, device=dev)
         V, S = rom.zeros(M, device=dev)
 
@@ -684,7 +686,8 @@ def workload_plain(args, torch, dev):
         ksec = float(np.median(ms)) * 1e-3
         ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N)
         err = max(_err_cols(V.cpu().numpy().T, ref["V"]), _err_cols(S.cpu().numpy().T, ref["S"]))
-        rec = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "max_rel_err_vs_oracle": err}
+        rec = {"value": M * N / ksec, "us_per_step": ksec / N * 1e6, "max_rel_err_vs_oracle": err,
+               "schedule": rom.last_schedule or "columns"}
         if M == 1:
             # the rank-1 formulation of the same sample: two GEMV launches per
             # step (eager, one stream), error against the oracle likewise
@@ -698,7 +701,7 @@ def workload_plain(args, torch, dev):
             k1 = float(np.median(ms1)) * 1e-3
             e1 = max(_err_cols(v.cpu().numpy()[:, None], ref["V"]), _err_cols(s.cpu().numpy()[:, None], ref["S"]))
             out["rank1"] = {"value": N / k1, "us_per_step": k1 / N * 1e6, "max_rel_err_vs_oracle": e1}
-        out["runs"]["M%d" % M] = rec
+        out["runs"]["M%d" % M + ("" if sched == "auto" else "_" + sched)] = rec
         rom.close()
     out["rank2_M8_over_rank1"] = out["runs"]["M8"]["value"] / out["rank1"]["value"]
     return out

@@ -212,7 +212,8 @@ def _canaries_intact(buf, n, pad=320):
 @pytest.mark.parametrize("kv,ks,M,state,ops,schedule", [
     (70, 45, 13, "f32", "f32", "columns"), (70, 45, 13, "f32", "f32", "columns8"),
     (256, 256, 70, "f32", "f32", "rowsplit"), (256, 256, 70, "f32", "bf16", "rowsplit"),
-    (70, 45, 13, "f32", "bf16", "columns"), (33, 50, 5, "f64", "f64", "auto")])
+    (70, 45, 13, "f32", "bf16", "columns"), (33, 50, 5, "f64", "f64", "auto"),
+    (100, 100, 5, "f64", "f64", "auto")])
 def test_no_writes_outside_the_outputs(kv, ks, M, state, ops, schedule):
     """Canary-padded states, QoI and trace buffers on ragged K and M: every
     kernel path writes only inside the arrays it is given."""
