@@ -114,7 +114,9 @@ enum {
                                (Asv == -Avs^T exactly) with Kv, Ks <= 256:
                                the operator-resident kernel (one sample per
                                workgroup, all of Avs in its registers); else
-                               4-column blocks                                */
+                               4-column blocks.  (FP64-state runs of skew
+                               pairs with Kv_pad, Ks_pad <= 128 take the
+                               FP64 resident kernel with or without it.)     */
     ROM_SCHED_PANEL = 128u, /* FP32 operators and states, or FP64 states:
                                the panel schedule (one tiled matrix-product
                                launch per half-step, nothing resident
@@ -229,7 +231,13 @@ rom_status rom_destroy(rom_ctx *ctx);
  *                          workgroup, which keeps all of Avs in registers
  *                          for the whole run and uses it for both half-
  *                          steps (Asv V = -Avs^T V); no operator streaming,
- *                          no exchange between workgroups.
+ *                          no exchange between workgroups.  FP64 states
+ *                          (FP64 operators, or BF16 / FP8 ones, which stay
+ *                          skew when rounded) have an FP64 form of it for
+ *                          Kv_pad, Ks_pad <= 128 (padded to 64), taken by
+ *                          every such run of a skew pair unless
+ *                          ROM_SCHED_COLUMNS pins the vector-ALU column
+ *                          blocks.
  *   ROM_SCHEDULE_PANEL     FP32 operators, any Kv, Ks: each half-step one
  *                          launch of a tiled matrix product (128 operator
  *                          rows x 64 samples per workgroup, FP32 matrix
@@ -260,8 +268,9 @@ rom_status rom_destroy(rom_ctx *ctx);
  * ROM_SCHED_COLUMNS / ROM_SCHED_COLUMNS8 fixes the instance's tile.
  *
  * rom_last_schedule: the schedule of the context's last FP32-state rank-2
- * run, ROM_SCHEDULE_PANEL after an FP64-state run on the panel schedule;
- * -1 if none (or after an FP64-state run on the vector-ALU kernel).  rom_schedule_times: the table's per-step times
+ * run; after an FP64-state run ROM_SCHEDULE_PANEL (panel schedule),
+ * ROM_SCHEDULE_RESIDENT (FP64 resident kernel) or -1 (vector-ALU column
+ * blocks); -1 if none.  rom_schedule_times: the table's per-step times
  * (microseconds) of each schedule for the context's shape at M samples,
  * negative where a schedule does not apply; ROM_E_ARG if that shape is not
  * in the table.
