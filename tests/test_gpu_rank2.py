@@ -69,9 +69,10 @@ def _ref(inst, nsteps, cols=None, probe=False, trace=False, n0=0, V0=None, S0=No
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("M", [1, 8])
-def test_fp64_plain_workload(M):
+@pytest.mark.parametrize("schedule", ["auto", "columns"])       # FP64 resident kernel, vector-ALU column blocks
+def test_fp64_plain_workload(M, schedule):
     inst = synth.round_to(synth.make_instance(64, 64, M, seed=0), "f64")
-    g = _gpu_run(inst, "f64", 2000, probe=True, trace=True)
+    g = _gpu_run(inst, "f64", 2000, probe=True, trace=True, schedule=schedule)
     r = _ref(inst, 2000, probe=True, trace=True)
     assert _relcol(g["V"], r["V"]) <= TOL["f64"]
     assert _relcol(g["S"], r["S"]) <= TOL["f64"]
@@ -121,11 +122,12 @@ def test_fp64_nonzero_start_and_offset():
     assert _relcol(g["V"], r["V"]) <= TOL["f64"] and _relcol(g["S"], r["S"]) <= TOL["f64"]
 
 
-def test_fp64_run_split_bitwise():
+@pytest.mark.parametrize("schedule", ["auto", "columns"])
+def test_fp64_run_split_bitwise(schedule):
     inst = synth.make_instance(48, 48, 5, seed=2)
-    whole = _gpu_run(inst, "f64", 400)
-    p1 = _gpu_run(inst, "f64", 150)
-    p2 = _gpu_run(inst, "f64", 250, n0=150, V0=p1["V"], S0=p1["S"])
+    whole = _gpu_run(inst, "f64", 400, schedule=schedule)
+    p1 = _gpu_run(inst, "f64", 150, schedule=schedule)
+    p2 = _gpu_run(inst, "f64", 250, n0=150, V0=p1["V"], S0=p1["S"], schedule=schedule)
     assert np.array_equal(whole["V"], p2["V"]) and np.array_equal(whole["S"], p2["S"])
 
 
