@@ -8,7 +8,9 @@ one full rank-2 run.  Inputs are resident on the GPU before timing starts.
 Prints ONE JSON line: sample-steps/s of the rank-2 path (whole job), the
 rank-1 path's rate on the same GPU, the roofline of the rank-2 kernel, the
 error against the FP64 oracle on sampled columns, and the oracle's own rate
-on the host (cpu_baseline).
+on the host (cpu_baseline); beside them the K = M = 1024 record (FP32, BF16,
+FP8 operators) and the plain FP64 record (K = 64, M in {1, 8}, 2000 steps,
+with its rank-1 formulation).
 """
 from __future__ import annotations
 
@@ -81,6 +83,8 @@ def main():
     ap.add_argument("--scaling-point", default=None,
                     help="scaling workload: one point only, KxM (e.g. 4096x1024)")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 comparison")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain FP64 record (K = 64, M in {1, 8}, 2000 steps, with its rank-1 run)")
     ap.add_argument("--no-target", action="store_true",
                     help="skip the K = M = 1024 target record (FP32, BF16, FP8 runs and their oracle check)")
     ap.add_argument("--workload", default="rank2", choices=["rank2", "precision", "grouped", "adjoint", "copy", "sweep", "plain", "receivers", "rank3", "fom", "offline",
@@ -170,6 +174,10 @@ def main():
     if target_refs is not None:
         target = workload_target(torch, dev, target_refs)
 
+    # ---- the plain FP64 record (K = 64, M in {1, 8}, 2000 steps) and its
+    # rank-1 formulation, error against the oracle on every column
+    plain = None if args.no_plain else workload_plain(args, torch, dev)
+
     # ---- CPU baseline: the FP64 oracle on a bounded column sample (all host
     # threads, plus its 1-thread rate), and a numpy/BLAS FP64 rank-2 loop as
     # the CPU + BLAS context
@@ -219,6 +227,7 @@ def main():
         "rank2_over_rank1_batch": (value / rank1b["value"]) if rank1b else None,
         "accuracy": errs,
         "target_k1024_m1024": target,
+        "plain_fp64": plain,
     }
     print(json.dumps(out))
 
