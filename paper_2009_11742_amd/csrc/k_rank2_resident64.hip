@@ -1,17 +1,21 @@
-// Rank-2 leapfrog stepper for skew operator pairs (Asv = -Avs^T exactly)
-// with FP64 states and Kv, Ks <= 128: the operator-resident schedule in FP64.
+// Rank-2 leapfrog stepper with FP64 states at small K: the operator-resident
+// schedule in FP64, for skew operator pairs (Asv = -Avs^T exactly) with
+// Kv, Ks <= 128 and for other pairs with Kv_pad Ks_pad <= 8192.
 //
 // Method: Sec. 2.4 eq. (2.5) for the staggered system of Sec. 3.1 eq. (3.3),
-//     V <- V + dt (Avs S + b u(t_n; mu))      then      S <- S - dt Avs^T V
-// (for a skew pair Asv V = -Avs^T V: the energy-conserving structure of
-// Sec. 3.1), with the probe QoI J += dt (c^T V)^2 on the new V of each step.
+//     V <- V + dt (Avs S + b u(t_n; mu))      then      S <- S + dt Asv V
+// (for a skew pair Asv V = -Avs^T V, the energy-conserving structure of
+// Sec. 3.1, so one operator serves both half-steps), with the probe QoI
+// J += dt (c^T V)^2 on the new V of each step.
 //
 // At these sizes a step is a few thousand FP64 multiply-adds per sample, so
 // every schedule that moves operators or states through memory per step is
 // bound by latency.  Here one workgroup of four waves steps one sample and
-// keeps all of Avs (at most 128 KB in FP64) in its registers for the whole
+// keeps its operators (at most 128 KB in FP64) in registers for the whole
 // run; nothing but two column partials per wave passes through LDS, and one
-// workgroup barrier per step is the only wait.
+// workgroup barrier per step is the only wait.  A non-skew pair holds Asv^T
+// in a second tile of the same layout (twice the registers: hence the
+// smaller size limit).
 //
 // Layout.  Thread t holds the TR x TC tile of Avs at row block rb = t / 16
 // and column block cb = t % 16 (columns TC cb + j): the 16 lanes of a row
@@ -22,7 +26,8 @@
 //    p ^ 1) leave each lane the full sum of row TR rb + s(p), which it
 //    updates in FP64 (the 16 / TR lanes of a row compute bitwise equal
 //    values); the TR new rows of the block come back by DPP moves.
-//  * Stress: each lane sums its TR rows for its TC columns; two permlane
+//  * Stress: each lane sums its TR rows for its TC columns (of Avs, negated
+//    in the update, or of Asv^T); two permlane
 //    swap levels between the wave's 16-lane rows leave each lane a quarter
 //    of its columns' wave sums, the four waves meet in LDS (double-buffered
 //    by step parity, so the barrier of step n + 1 separates the reads of step
@@ -171,7 +176,7 @@ __device__ __forceinline__ double read_lane64(double x, int i) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-template <int TR, int TC>
+template <int TR, int TC, bool SKEW>
 __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args a) {
     constexpr int KSR = 16 * TC;
     constexpr int QW = TC / 4;                          // wave sums each lane holds
@@ -189,6 +194,7 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
     const int kv = a.kv, ks = a.ks;
     const double dt = a.dt;
     const double *Ag = static_cast<const double *>(a.avs);   // column-major kv x ks
+    const double *Bg = static_cast<const double *>(a.asv);   // column-major ks x kv (non-skew pairs)
     double *Vg = static_cast<double *>(a.V) + (size_t)m * kv;
     double *Sg = static_cast<double *>(a.S) + (size_t)m * ks;
     const double *bg = static_cast<const double *>(a.b);
@@ -196,7 +202,8 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
     const bool probe = cg != nullptr;
     const double mu = a.mu[m];
 
-    double op[TR][TC], cr[TR], s[TC];
+    // op: the Avs tile; opT: the Asv^T tile of a non-skew pair
+    double op[TR][TC], opT[SKEW ? 1 : TR][SKEW ? 1 : TC], cr[TR], s[TC];
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
         const int r = TR * rb + (i ^ sx);
@@ -205,6 +212,7 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
         for (int j = 0; j < TC; ++j) {
             const int c = TC * cb + j;
             op[i][j] = (ok && c < ks) ? Ag[(size_t)c * kv + r] : 0.0;
+            if constexpr (!SKEW) opT[i][j] = (ok && c < ks) ? Bg[(size_t)r * ks + c] : 0.0;
         }
         cr[i] = (ok && probe) ? cg[r] : 0.0;
     }
@@ -237,15 +245,18 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
         row_sum64<TR>(acc);
         v = v + dt * (acc[0] + br * u);
 
-        // ---- stress half-step: S -= dt Avs^T V
+        // ---- stress half-step: S += dt Asv V (S -= dt Avs^T V for a skew pair)
         double vv[TR];
         row_gather64<TR>(v, vv);
         double q[TC];
 #pragma unroll
         for (int j = 0; j < TC; ++j) {
-            double t = op[0][j] * vv[0];
+            const auto &B = [&]() -> const double(&)[TR][TC] {
+                if constexpr (SKEW) return op; else return opT;
+            }();
+            double t = B[0][j] * vv[0];
 #pragma unroll
-            for (int i = 1; i < TR; ++i) t = fma(op[i][j], vv[i], t);
+            for (int i = 1; i < TR; ++i) t = fma(B[i][j], vv[i], t);
             q[j] = t;
         }
         col_sum_rows64<TC>(q);
@@ -263,7 +274,7 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
         for (int j = 0; j < TC; ++j) {
             const int c = TC * cb + j;
             const double Q = (part[par][0][c] + part[par][1][c]) + (part[par][2][c] + part[par][3][c]);
-            s[j] = s[j] - dt * Q;
+            s[j] = SKEW ? s[j] - dt * Q : s[j] + dt * Q;
         }
         if (probe && tid == 0) {
             const double y = (ypart[par][0] + ypart[par][1]) + (ypart[par][2] + ypart[par][3]);
@@ -283,22 +294,31 @@ __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args
 
 }  // namespace
 
-bool rank2_resident64_applies(int kvp, int ksp) { return kvp <= 128 && ksp <= 128; }
+bool rank2_resident64_applies(int kvp, int ksp, bool skew) {
+    return kvp <= 128 && ksp <= 128 && (skew || kvp * ksp <= 8192);
+}
 
-// a.avs: the context's column-major FP64 Avs (a.asv unused); a.kvp, a.ksp
-// the sizes padded to 64.
-hipError_t launch_rank2_resident64(const Rank2Args &a, hipStream_t st) {
-    if (!rank2_resident64_applies(a.kvp, a.ksp) || a.kvp % 64 || a.ksp % 64 || a.kvp < 64 || a.ksp < 64)
+// a.avs, a.asv: the context's column-major FP64 Avs and Asv (Asv read for
+// non-skew pairs only); a.kvp, a.ksp the sizes padded to 64.
+hipError_t launch_rank2_resident64(const Rank2Args &a, bool skew, hipStream_t st) {
+    if (!rank2_resident64_applies(a.kvp, a.ksp, skew) || a.kvp % 64 || a.ksp % 64 || a.kvp < 64 || a.ksp < 64)
         return hipErrorInvalidValue;
     const dim3 g(a.M), b(kR64Threads);
-    if (a.kvp == 64 && a.ksp == 64)
-        hipLaunchKernelGGL((rank2_resident64_kernel<4, 4>), g, b, 0, st, a);
-    else if (a.kvp == 64)
-        hipLaunchKernelGGL((rank2_resident64_kernel<4, 8>), g, b, 0, st, a);
-    else if (a.ksp == 64)
-        hipLaunchKernelGGL((rank2_resident64_kernel<8, 4>), g, b, 0, st, a);
-    else
-        hipLaunchKernelGGL((rank2_resident64_kernel<8, 8>), g, b, 0, st, a);
+    const int shape = (a.kvp == 128) * 2 + (a.ksp == 128);
+    if (skew) {
+        switch (shape) {
+        case 0: hipLaunchKernelGGL((rank2_resident64_kernel<4, 4, true>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((rank2_resident64_kernel<4, 8, true>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((rank2_resident64_kernel<8, 4, true>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((rank2_resident64_kernel<8, 8, true>), g, b, 0, st, a); break;
+        }
+    } else {
+        switch (shape) {
+        case 0: hipLaunchKernelGGL((rank2_resident64_kernel<4, 4, false>), g, b, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((rank2_resident64_kernel<4, 8, false>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((rank2_resident64_kernel<8, 4, false>), g, b, 0, st, a); break;
+        }
+    }
     return hipGetLastError();
 }
 

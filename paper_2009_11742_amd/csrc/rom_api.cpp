@@ -988,10 +988,11 @@ rom_status rom_run_rank2(rom_ctx *ctx, int32_t M, const double *mu, int64_t n0, 
         if (!fits || (ctx->flags & ROM_SCHED_PANEL) || auto_panel)
             return run_panel(ctx, a, st);
         a.avs = ctx->avs_cm; a.asv = ctx->asv_cm;
-        // skew pairs with Kv_pad, Ks_pad <= 128: the operator-resident
-        // kernel unless the context pins the column blocks
-        if (ctx->skew && !(ctx->flags & ROM_SCHED_COLUMNS) && rom::rank2_resident64_applies(ctx->kvp, ctx->ksp)) {
-            e = rom::launch_rank2_resident64(a, st);
+        // small K (skew pairs: Kv_pad, Ks_pad <= 128; others: Kv_pad Ks_pad
+        // <= 8192): the operator-resident kernel unless the context pins
+        // the column blocks
+        if (!(ctx->flags & ROM_SCHED_COLUMNS) && rom::rank2_resident64_applies(ctx->kvp, ctx->ksp, ctx->skew)) {
+            e = rom::launch_rank2_resident64(a, ctx->skew, st);
             ctx->last_schedule = ROM_SCHEDULE_RESIDENT;
         } else {
             e = rom::launch_rank2_valu<double>(a, st);

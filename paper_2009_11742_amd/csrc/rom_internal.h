@@ -160,10 +160,11 @@ bool rank2_resident_applies(int kvp, int ksp);
 size_t rank2_resident_pack_bytes(int kvp, int ksp);
 hipError_t launch_resident_pack(const float *A, int kv, int ks, int kvp, int ksp, void *pk, hipStream_t st);
 hipError_t launch_rank2_resident(const Rank2Args &a, hipStream_t st);
-// FP64 states, skew pairs with Kv_pad, Ks_pad <= 128: the operator-resident
-// schedule in FP64 (a.avs = the column-major FP64 Avs).
-bool rank2_resident64_applies(int kvp, int ksp);
-hipError_t launch_rank2_resident64(const Rank2Args &a, hipStream_t st);
+// FP64 states: the operator-resident schedule in FP64 for skew pairs with
+// Kv_pad, Ks_pad <= 128 and other pairs with Kv_pad Ks_pad <= 8192 (a.avs,
+// a.asv = the column-major FP64 operators).
+bool rank2_resident64_applies(int kvp, int ksp, bool skew);
+hipError_t launch_rank2_resident64(const Rank2Args &a, bool skew, hipStream_t st);
 
 // Rank-1 formulation of M samples in one launch (a.avs / a.asv the
 // column-major FP32 operators, kv, ks <= 1024).

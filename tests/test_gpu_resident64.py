@@ -1,16 +1,19 @@
-"""Operator-resident schedule with FP64 states (skew pairs, Kv, Ks <= 128):
-one sample per workgroup with all of Avs in its registers in FP64, used for
-both half-steps (Asv V = -Avs^T V), states held redundantly in registers.
+"""Operator-resident schedule with FP64 states (skew pairs with Kv, Ks <=
+128; other pairs with Kv_pad Ks_pad <= 8192): one sample per workgroup with
+its operators in registers in FP64 (Avs alone for a skew pair, used for both
+half-steps as Asv V = -Avs^T V; Avs and Asv^T otherwise), states held
+redundantly in registers.
 
 Parity against the FP64 oracle at the FP64 bar (1e-12, per-sample relative
 l2 error of the final states; the probe QoI J and trace y relative): the
 plain-method workload (K = 64, M = 8, 2000 steps) and every tile shape
 (padded Kv, Ks in {64, 128}, square and rectangular), ragged sizes, one
-sample.  Structural checks: agreement with the vector-ALU column blocks
-(ROM_SCHED_COLUMNS), a permutation of the samples permutes the results
-bitwise, a run split in two (the second part with n0 > 0) equals the whole
-run bitwise in V and S, graph replays equal the eager run bitwise, a
-non-skew pair and a pair above the size limit keep the column blocks, and
+sample; non-skew pairs (weighted transposes and an independent random Asv)
+at the three tiles they take.  Structural checks: agreement with the
+vector-ALU column blocks (ROM_SCHED_COLUMNS), a permutation of the samples
+permutes the results bitwise, a run split in two (the second part with
+n0 > 0) equals the whole run bitwise in V and S, graph replays equal the
+eager run bitwise, pairs above the size limits keep the column blocks, and
 BF16 operators with FP64 states (skew after rounding) agree with the column
 blocks on the same rounded operators.
 """
@@ -31,6 +34,7 @@ def _relcol(X, R):
 
 
 def _run(inst, N, mu_np=None, schedule="auto", trace=True, n_split=None, ops=None):
+    """Run on FP64 states; returns states (K x M), J, y and the schedule."""
     from paper_2009_11742_amd import Rom
     rom = Rom(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], state="f64", ops=ops, schedule=schedule)
     mu_np = inst["mu"] if mu_np is None else mu_np
@@ -77,8 +81,25 @@ def test_resident64_parity(kv, ks, M, N):
     assert max(e) <= BAR64
 
 
-def test_resident64_agrees_with_vector_alu_columns():
-    inst = synth.make_instance(96, 96, 12, seed=21)
+# non-skew pairs: weighted transposes (the form of staggered finite-difference
+# operators) and an independent random Asv, at the (64, 64), (128, 64) and
+# (64, 128) tiles
+@pytest.mark.parametrize("kv,ks,M,N,kind", [(64, 64, 8, 1500, "weighted"), (100, 60, 3, 500, "weighted"),
+                                            (40, 128, 5, 400, "weighted"), (60, 50, 4, 60, "random")])
+def test_resident64_non_skew_parity(kv, ks, M, N, kind):
+    inst = synth.make_instance(kv, ks, M, seed=kv + ks + 5 * M, skew=False, random_asv=(kind == "random"))
+    g = _run(inst, N)
+    assert g["sched"] == "resident"
+    ref = oracle.run_rank2(inst["Avs"], inst["Asv"], inst["b"], inst["dt"], inst["mu"], N, c=inst["c"],
+                           trace=True)
+    e = _errors(g, ref)
+    print("resident f64 %s K=(%d,%d) M=%d N=%d: V %.2e S %.2e J %.2e y %.2e" % ((kind, kv, ks, M, N) + e))
+    assert max(e) <= BAR64
+
+
+@pytest.mark.parametrize("skew", [True, False])
+def test_resident64_agrees_with_vector_alu_columns(skew):
+    inst = synth.make_instance(96, 60, 12, seed=21, skew=skew)
     a = _run(inst, 800)
     b = _run(inst, 800, schedule="columns")
     assert a["sched"] == "resident" and b["sched"] is None
@@ -133,7 +154,7 @@ def test_resident64_graph_replay_bitwise():
     rom.close()
 
 
-@pytest.mark.parametrize("kv,ks,skew", [(64, 64, False), (130, 130, True)])
+@pytest.mark.parametrize("kv,ks,skew", [(128, 128, False), (70, 100, False), (130, 130, True), (64, 129, True)])
 def test_resident64_not_applicable_keeps_the_column_blocks(kv, ks, skew):
     inst = synth.make_instance(kv, ks, 4, seed=51, skew=skew)
     g = _run(inst, 300, trace=False)
