@@ -115,8 +115,9 @@ enum {
                                the operator-resident kernel (one sample per
                                workgroup, all of Avs in its registers); else
                                4-column blocks.  (FP64-state runs of skew
-                               pairs with Kv_pad, Ks_pad <= 128 take the
-                               FP64 resident kernel with or without it.)     */
+                               pairs with Kv_pad, Ks_pad <= 128, and of
+                               other pairs with Kv_pad Ks_pad <= 8192, take
+                               the FP64 resident kernel with or without it.)*/
     ROM_SCHED_PANEL = 128u, /* FP32 operators and states, or FP64 states:
                                the panel schedule (one tiled matrix-product
                                launch per half-step, nothing resident
@@ -232,12 +233,13 @@ rom_status rom_destroy(rom_ctx *ctx);
  *                          for the whole run and uses it for both half-
  *                          steps (Asv V = -Avs^T V); no operator streaming,
  *                          no exchange between workgroups.  FP64 states
- *                          (FP64 operators, or BF16 / FP8 ones, which stay
- *                          skew when rounded) have an FP64 form of it for
- *                          Kv_pad, Ks_pad <= 128 (padded to 64), taken by
- *                          every such run of a skew pair unless
- *                          ROM_SCHED_COLUMNS pins the vector-ALU column
- *                          blocks.
+ *                          (FP64 operators, or BF16 / FP8 ones) have an
+ *                          FP64 form of it, for skew pairs (which stay
+ *                          skew when rounded) with Kv_pad, Ks_pad <= 128
+ *                          and for other pairs, holding Asv as well, with
+ *                          Kv_pad Ks_pad <= 8192 (sizes padded to 64): every
+ *                          such run takes it unless ROM_SCHED_COLUMNS pins
+ *                          the vector-ALU column blocks.
  *   ROM_SCHEDULE_PANEL     FP32 operators, any Kv, Ks: each half-step one
  *                          launch of a tiled matrix product (128 operator
  *                          rows x 64 samples per workgroup, FP32 matrix
