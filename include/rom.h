@@ -87,7 +87,9 @@ enum {
     ROM_SCHED_COLUMNS = 2u, /* FP32-state rank-2 runs (FP32, BF16, FP8
                                operators): always the 4-column column-block
                                kernels (each workgroup owns 4 samples and
-                               streams the whole operator)                    */
+                               streams the whole operator); FP64-state runs:
+                               the vector-ALU column blocks where their
+                               states fit in LDS                              */
     ROM_SCHED_ROWSPLIT = 4u,/* FP32-state rank-2 runs: the row-split kernels
                                (operator rows split over the workgroups of a
                                sample group, exchanged every half-step)
