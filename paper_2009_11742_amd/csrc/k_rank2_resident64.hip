@@ -27,9 +27,9 @@
 //    updates in FP64 (the 16 / TR lanes of a row compute bitwise equal
 //    values); the TR new rows of the block come back by DPP moves.
 //  * Stress: each lane sums its TR rows for its TC columns (of Avs, negated
-//    in the update, or of Asv^T); two permlane
-//    swap levels between the wave's 16-lane rows leave each lane a quarter
-//    of its columns' wave sums, the four waves meet in LDS (double-buffered
+//    in the update, or of Asv^T); two permlane swap levels between the
+//    wave's 16-lane rows leave each lane a quarter of its columns' wave
+//    sums, the four waves meet in LDS (double-buffered
 //    by step parity, so the barrier of step n + 1 separates the reads of step
 //    n from the writes of step n + 2), and every lane reads the four wave
 //    sums of its TC columns and updates its own copy of them: S is held
