@@ -40,6 +40,7 @@
 //  * Forcing: each wave evaluates u(t_n) for the next 64 steps, one step per
 //    lane, and reads the step's value from its lane.
 #include "k_common.h"
+#include "k_lane.h"
 #include "rom_internal.h"
 
 namespace rom {
@@ -47,134 +48,7 @@ namespace {
 
 constexpr int kR64Threads = 256;
 
-// DPP controls (gfx9 encoding)
-constexpr int kDppRor8 = 0x128;            // row_ror:8        (p ^ 8)
-constexpr int kDppHalfMirror = 0x141;      // row_half_mirror  (p ^ 7)
-constexpr int kDppXor2 = 0x4E;             // quad_perm [2,3,0,1]
-constexpr int kDppXor1 = 0xB1;             // quad_perm [1,0,3,2]
-
-// Every lane of these patterns has a source lane (bound_ctrl, zero "old").
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov64(double x) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Register order of a lane's tile rows: register i holds tile row i ^ s(p).
-// With b3 b2 b1 the bits of p: TR = 8: s = 4 b3 + 2 b2 + (b1 ^ b2); TR = 4:
-// s = 2 b3 + b2.  Halving level k's partner changes s by exactly
-// TR >> (k + 1) while 2 (TR >> (k + 1)) registers are live, and leaves it
-// unchanged at the levels after the halving (which then add equal rows).
-__device__ __forceinline__ int row_xor(int TR, int p) {
-    const int b3 = (p >> 3) & 1, b2 = (p >> 2) & 1, b1 = (p >> 1) & 1;
-    return TR == 8 ? 4 * b3 + 2 * b2 + (b1 ^ b2) : 2 * b3 + b2;
-}
-
-template <int LEVEL>
-__device__ __forceinline__ double level_partner64(double x) {
-    if constexpr (LEVEL == 0) return dpp_mov64<kDppRor8>(x);
-    else if constexpr (LEVEL == 1) return dpp_mov64<kDppHalfMirror>(x);
-    else if constexpr (LEVEL == 2) return dpp_mov64<kDppXor2>(x);
-    else return dpp_mov64<kDppXor1>(x);
-}
-
-// Sum over the 16 lanes of the DPP row of the row partials acc[0 .. TR):
-// afterwards acc[0] holds the sum for tile row s(p).
-template <int TR, int LEVEL = 0>
-__device__ __forceinline__ void row_sum64(double (&acc)[TR]) {
-    if constexpr (LEVEL < 4) {
-        constexpr int H = TR >> (LEVEL + 1);
-        if constexpr (H >= 1) {
-#pragma unroll
-            for (int t = 0; t < H; ++t) acc[t] = acc[t] + level_partner64<LEVEL>(acc[t + H]);
-        } else {
-            acc[0] = acc[0] + level_partner64<LEVEL>(acc[0]);
-        }
-        row_sum64<TR, LEVEL + 1>(acc);
-    }
-}
-
-// The TR rows of a lane's row block in its register order: vv[i] = row
-// TR rb + (i ^ s(p)), the value of a lane p' of the same DPP row with
-// s(p') = s(p) ^ i; one partner pattern per bit of i (TR = 8: p ^ 8, p ^ 7,
-// p ^ 2; TR = 4: p ^ 8, p ^ 7).
-template <int TR>
-__device__ __forceinline__ void row_gather64(double x, double (&vv)[TR]) {
-    vv[0] = x;
-    if constexpr (TR == 8) {
-        vv[4] = dpp_mov64<kDppRor8>(vv[0]);
-        vv[2] = dpp_mov64<kDppHalfMirror>(vv[0]);
-        vv[6] = dpp_mov64<kDppHalfMirror>(vv[4]);
-#pragma unroll
-        for (int i = 0; i < 8; i += 2) vv[i + 1] = dpp_mov64<kDppXor2>(vv[i]);
-    } else {
-        vv[2] = dpp_mov64<kDppRor8>(vv[0]);
-        vv[1] = dpp_mov64<kDppHalfMirror>(vv[0]);
-        vv[3] = dpp_mov64<kDppHalfMirror>(vv[2]);
-    }
-}
-
-__device__ __forceinline__ unsigned lo32(double x) { return (unsigned)__builtin_bit_cast(uint64_t, x); }
-__device__ __forceinline__ unsigned hi32(double x) { return (unsigned)(__builtin_bit_cast(uint64_t, x) >> 32); }
-__device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Sum over the four 16-lane rows of a wave of the column partials q[0 ..
-// TC): afterwards q[0 .. TC/4) of a lane in row rho hold the wave's sums for
-// columns TC p + col_off(rho) + j.  v_permlane16_swap exchanges the second
-// operand of even rows with the first operand of the odd row above it,
-// v_permlane32_swap does the same between the two halves of the wave; the
-// low and high words of each double take the same exchange.
-template <int TC>
-__device__ __forceinline__ void col_sum_rows64(double (&q)[TC]) {
-    constexpr int H1 = TC / 2, H2 = TC / 4;
-#pragma unroll
-    for (int j = 0; j < H1; ++j) {
-        const auto rl = __builtin_amdgcn_permlane16_swap(lo32(q[j]), lo32(q[j + H1]), false, false);
-        const auto rh = __builtin_amdgcn_permlane16_swap(hi32(q[j]), hi32(q[j + H1]), false, false);
-        q[j] = mk64(rl[0], rh[0]) + mk64(rl[1], rh[1]);
-    }
-#pragma unroll
-    for (int j = 0; j < H2; ++j) {
-        const auto rl = __builtin_amdgcn_permlane32_swap(lo32(q[j]), lo32(q[j + H2]), false, false);
-        const auto rh = __builtin_amdgcn_permlane32_swap(hi32(q[j]), hi32(q[j + H2]), false, false);
-        q[j] = mk64(rl[0], rh[0]) + mk64(rl[1], rh[1]);
-    }
-}
-
-__device__ __forceinline__ int col_off(int TC, int rho) { return (rho & 1) * (TC / 2) + (rho >> 1) * (TC / 4); }
-
-// x + (the value of lane l ^ 16 (W32 false) or l ^ 32 (W32 true)), bitwise
-// equal in both lanes.  With both operands of a permlane swap equal to x a
-// lane receives its own x and its partner's, in an order that depends on its
-// half; a + b == b + a.
-template <bool W32>
-__device__ __forceinline__ double swap_sum64(double x) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
-    unsigned l0, l1, h0, h1;
-    if constexpr (W32) {
-        const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
-    } else {
-        const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
-    }
-    return __builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0) + __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1);
-}
-
-// The value of lane i (wave-uniform i) in every lane.
-__device__ __forceinline__ double read_lane64(double x, int i) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, i);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), i);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
+using namespace lane;
 
 template <int TR, int TC, bool SKEW>
 __global__ __launch_bounds__(kR64Threads) void rank2_resident64_kernel(Rank2Args a) {
